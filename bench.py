@@ -1,0 +1,139 @@
+"""Benchmark: cell-updates per second of the FP32 finite-volume step.
+
+Workload (one GPU): shallow water on a 1024 x 1024 grid, FP32, reflective
+walls, bed = 8 seeded Gaussians, free surface = 1 + 16 seeded Gaussian bumps,
+zero velocity, HLLE flux, MINMOD reconstruction, Heun stages, CFL 0.4 with
+the global wave-speed reduction every step.  A "step" is one full time step
+(both stages and the Delta t reduction).  Inputs are resident in HBM before
+the timed region.  Prints one JSON line.
+
+Also measured (reported inside the line, not as `value`): the four-quadrant
+Euler workload at 1024^2 (FP32, walls, 500 steps) and the oracle on the host
+cores over a bounded sample of the shallow-water workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_CELL_UPDATE = {"swe_bathy": 28, "euler": 32}  # read q (+b), write q, FP32
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=1000)
+    p.add_argument("--warmup", type=int, default=100)
+    p.add_argument("--n", type=int, default=1024, help="grid side")
+    p.add_argument("--no-cpu-baseline", action="store_true")
+    p.add_argument("--no-euler", action="store_true")
+    p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time for the baseline")
+    return p.parse_args()
+
+
+def timed_run(solver, steps, warmup, torch):
+    """Warm up, then time exactly `steps` steps with HIP events recorded on the
+    solver's stream, bracketed by device synchronisation."""
+    solver.run(warmup)
+    torch.cuda.synchronize()
+    st = solver.stream
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(st)
+    solver.run(steps)
+    e1.record(st)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return e0.elapsed_time(e1) / 1e3, wall
+
+
+def cpu_baseline(n, target_s):
+    import oracle
+    from paper_2602_08670_amd import inputs
+
+    threads = min(16, os.cpu_count() or 1)
+    q0, b = inputs.swe_bathy(n, seed=0)
+    cfg = oracle.Config(nx=n, ny=n, bc_x=oracle.WALL, bc_y=oracle.WALL, nthreads=threads)
+    t0 = time.perf_counter()
+    q1, *_ = oracle.run(cfg, q0, b, 1)
+    one = time.perf_counter() - t0
+    steps = max(1, min(200, int(target_s / max(one, 1e-3))))
+    t0 = time.perf_counter()
+    oracle.run(cfg, q1, b, steps)
+    el = time.perf_counter() - t0
+    return {"value": round(n * n * steps / el / 1e6, 3), "unit": "Mcell-updates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{steps} steps of the {n}^2 FP64 shallow-water bed workload (after 1 untimed step), "
+                      f"{el:.1f} s, OpenMP rows"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is described in DESIGN.md, not implemented", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2602_08670_amd import fv, inputs
+
+    n = args.n
+    dev = torch.device("cuda:0")
+    q0, b = inputs.swe_bathy(n, seed=0)
+    s = fv.Solver(q0, b, prec=fv.FV_F32, bc_x=fv.FV_BC_WALL, bc_y=fv.FV_BC_WALL, device=dev)
+    gpu_s, wall_s = timed_run(s, args.steps, args.warmup, torch)
+    t_sim, nsteps = s.time()
+    s.close()
+    cells = n * n * args.steps
+    mcups = cells / gpu_s / 1e6
+    launches = 2 * args.steps
+    per_launch_s = gpu_s / launches
+    bytes_per_launch = BYTES_PER_CELL_UPDATE["swe_bathy"] * n * n / 2  # two stage launches per cell-update
+    achieved = bytes_per_launch / per_launch_s / 1e9
+
+    extra = {"wall_s": round(wall_s, 6), "sim_time": t_sim, "stage_launch_us": round(per_launch_s * 1e6, 3)}
+    if not args.no_euler:
+        qe = inputs.euler_quadrants(n, seed=0)
+        se = fv.Solver(qe, prec=fv.FV_F32, bc_x=fv.FV_BC_WALL, bc_y=fv.FV_BC_WALL, device=dev)
+        esteps = max(1, args.steps // 2)
+        eg, _ = timed_run(se, esteps, max(1, args.warmup // 2), torch)
+        se.close()
+        extra["euler_1024_fp32_mcups"] = round(n * n * esteps / eg / 1e6, 1)
+        extra["euler_hbm_frac"] = round(BYTES_PER_CELL_UPDATE["euler"] * n * n * esteps / eg / 1e9 / HBM_PEAK_GBS, 4)
+
+    line = {
+        "metric": "Mcell-updates/s FP32 SWE 1024^2 + % HBM roofline; p50/p99 solve latency",
+        "value": round(mcups, 1),
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(gpu_s / args.steps * 1e3, 6),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded Gaussian bed and surface bumps)",
+        "config": {"workload": f"swe_bathy_{n}x{n}_fp32_walls_hlle_minmod_heun_cfl0.4", "nx": n, "ny": n,
+                   "steps": args.steps, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "extra": extra,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

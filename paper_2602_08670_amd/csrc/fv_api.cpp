@@ -1,0 +1,339 @@
+// C-ABI host side of libfv: configuration checks, workspace layout, step
+// sequencing and the documented sync points.  All device work is enqueued on
+// the caller's stream; Delta t stays on the device (three rotating rate slots:
+// step n reads slot n%3, its last stage reduces into (n+1)%3 and clears
+// (n+2)%3, so one launch per stage suffices and no memset is recorded).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "../../include/fv.h"
+#include "fv_internal.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+fv_status fail(fv_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+fv_status fail(fv_status code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+fv_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(FV_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+    size_t ctl, totals_out, partials, s1, s2, total;
+};
+
+int nvar_of(const fv_config *c) { return c->eqn == FV_EULER ? 4 : 3; }
+
+fv_status validate(const fv_config *c)
+{
+    if (!c) return fail(FV_E_INVALID, "config is NULL");
+    if (c->struct_size != sizeof(fv_config))
+        return fail(FV_E_INVALID, "struct_size %u != sizeof(fv_config) %zu", c->struct_size, sizeof(fv_config));
+    if (c->eqn != FV_SWE && c->eqn != FV_EULER) return fail(FV_E_INVALID, "eqn %d", c->eqn);
+    if (c->prec != FV_F32 && c->prec != FV_F64) return fail(FV_E_INVALID, "prec %d", c->prec);
+    if (c->nx < 4 || c->ny < 4) return fail(FV_E_INVALID, "grid %dx%d: each side must be >= 4", c->nx, c->ny);
+    if ((int64_t)c->nx * c->ny > (int64_t)1 << 30) return fail(FV_E_INVALID, "grid too large");
+    for (int bc : {c->bc_x, c->bc_y})
+        if (bc != FV_BC_PERIODIC && bc != FV_BC_WALL) return fail(FV_E_INVALID, "boundary %d", bc);
+    if (c->flux < FV_FLUX_HLLE || c->flux > FV_FLUX_ROE) return fail(FV_E_INVALID, "flux %d", c->flux);
+    if (c->recon != FV_RECON_MINMOD && c->recon != FV_RECON_FIRST) return fail(FV_E_INVALID, "recon %d", c->recon);
+    if (c->rk_stages < 1 || c->rk_stages > 3) return fail(FV_E_INVALID, "rk_stages %d", c->rk_stages);
+    if (c->reserved0 != 0) return fail(FV_E_INVALID, "reserved0 must be 0");
+    if (!(c->lx > 0) || !(c->ly > 0)) return fail(FV_E_INVALID, "domain size");
+    if (!(c->dt_fixed > 0) && !(c->cfl > 0 && c->cfl <= 1)) return fail(FV_E_INVALID, "cfl %g not in (0,1]", c->cfl);
+    if (c->eqn == FV_SWE && !(c->g > 0)) return fail(FV_E_INVALID, "g %g", c->g);
+    if (c->eqn == FV_EULER && !(c->gamma > 1)) return fail(FV_E_INVALID, "gamma %g", c->gamma);
+    if (!(c->h_ref >= 0)) return fail(FV_E_INVALID, "h_ref %g < 0", c->h_ref);
+    return FV_OK;
+}
+
+Layout layout_of(const fv_config *c)
+{
+    Layout L;
+    size_t es = c->prec == FV_F64 ? 8 : 4;
+    size_t st = align256((size_t)nvar_of(c) * c->nx * c->ny * es);
+    L.ctl = 0;
+    L.totals_out = 256;
+    L.partials = 512;
+    L.s1 = L.partials + align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * sizeof(double));
+    L.s2 = L.s1 + st;
+    L.total = L.s2 + (c->rk_stages == 3 ? st : 0);
+    return L;
+}
+
+}  // namespace
+
+struct fv_solver {
+    fv_config cfg;
+    fvk::StageDesc d;
+    void *q;
+    const void *bed;
+    char *ws;
+    Layout L;
+    hipStream_t stream;
+    int64_t enq;  // steps enqueued since the last rate initialisation
+    size_t state_bytes;
+    fvk::Ctl *ctl() { return (fvk::Ctl *)(ws + L.ctl); }
+};
+
+namespace {
+
+fv_status init_rate(fv_solver *s)
+{
+    // rate slots, time and flags are reset by a host->device copy of a fresh
+    // control block (ordered on the stream before any kernel that reads it)
+    s->enq = 0;
+    int slot = 0;
+    hipError_t e = fvk::launch_rate(s->d, s->q, s->ctl(), slot, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "rate kernel");
+    return FV_OK;
+}
+
+fv_status sync_and_check(fv_solver *s)
+{
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    int bad = 0;
+    e = hipMemcpy(&bad, &s->ctl()->bad, sizeof(int), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read flag");
+    if (bad) return fail(FV_E_INADMISSIBLE, "a cell became inadmissible (h<=0, rho<=0, p<=0 or non-finite)");
+    return FV_OK;
+}
+
+fv_status enqueue_step(fv_solver *s)
+{
+    const int n = (int)(s->enq % 3);
+    const bool cfl = !(s->cfg.dt_fixed > 0);
+    const int ri = n, ro = cfl ? (n + 1) % 3 : -1, rc = cfl ? (n + 2) % 3 : -1;
+    char *S1 = s->ws + s->L.s1, *S2 = s->ws + s->L.s2;
+    hipError_t e = hipSuccess;
+    fvk::Ctl *ctl = s->ctl();
+    switch (s->cfg.rk_stages) {
+    case 1:
+        e = fvk::launch_stage(s->d, s->q, s->q, S1, s->bed, 0.0, 1.0, ctl, ri, ro, rc, 1, s->stream);
+        if (e == hipSuccess) e = hipMemcpyAsync(s->q, S1, s->state_bytes, hipMemcpyDeviceToDevice, s->stream);
+        break;
+    case 2:
+        e = fvk::launch_stage(s->d, s->q, s->q, S1, s->bed, 0.0, 1.0, ctl, ri, -1, -1, 0, s->stream);
+        if (e == hipSuccess)
+            e = fvk::launch_stage(s->d, S1, s->q, s->q, s->bed, 0.5, 0.5, ctl, ri, ro, rc, 1, s->stream);
+        break;
+    default:
+        e = fvk::launch_stage(s->d, s->q, s->q, S1, s->bed, 0.0, 1.0, ctl, ri, -1, -1, 0, s->stream);
+        if (e == hipSuccess)
+            e = fvk::launch_stage(s->d, S1, s->q, S2, s->bed, 0.75, 0.25, ctl, ri, -1, -1, 0, s->stream);
+        if (e == hipSuccess)
+            e = fvk::launch_stage(s->d, S2, s->q, s->q, s->bed, 1.0 / 3.0, 2.0 / 3.0, ctl, ri, ro, rc, 1, s->stream);
+        break;
+    }
+    if (e != hipSuccess) return hip_fail(e, "stage launch");
+    s->enq++;
+    return FV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fv_nvar(const fv_config *cfg) { return cfg ? nvar_of(cfg) : 0; }
+
+size_t fv_workspace_bytes(const fv_config *cfg)
+{
+    if (validate(cfg) != FV_OK) return 0;
+    return layout_of(cfg).total;
+}
+
+fv_status fv_init(const fv_config *cfg, void *q, const void *bathy, void *workspace, size_t workspace_bytes,
+                  void *stream, fv_solver **out)
+{
+    if (!out) return fail(FV_E_INVALID, "out is NULL");
+    *out = nullptr;
+    fv_status rc = validate(cfg);
+    if (rc != FV_OK) return rc;
+    if (!q || !workspace) return fail(FV_E_INVALID, "state or workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(FV_E_INVALID, "workspace must be 256-byte aligned");
+    if (bathy && cfg->eqn != FV_SWE) return fail(FV_E_INVALID, "a bed is only defined for the shallow-water equations");
+    Layout L = layout_of(cfg);
+    if (workspace_bytes < L.total)
+        return fail(FV_E_NOMEM, "workspace %zu bytes < required %zu", workspace_bytes, L.total);
+
+    fv_solver *s = new fv_solver();
+    s->cfg = *cfg;
+    s->q = q;
+    s->bed = bathy;
+    s->ws = (char *)workspace;
+    s->L = L;
+    s->stream = (hipStream_t)stream;
+    s->enq = 0;
+    s->state_bytes = (size_t)nvar_of(cfg) * cfg->nx * cfg->ny * (cfg->prec == FV_F64 ? 8 : 4);
+    fvk::StageDesc &d = s->d;
+    d.prec = cfg->prec;
+    d.eqn = cfg->eqn;
+    d.bathy = bathy ? 1 : 0;
+    d.flux = cfg->flux;
+    d.recon = cfg->recon;
+    d.nx = cfg->nx;
+    d.ny = cfg->ny;
+    d.bc_x = cfg->bc_x;
+    d.bc_y = cfg->bc_y;
+    d.rdx = cfg->nx / cfg->lx;
+    d.rdy = cfg->ny / cfg->ly;
+    d.g = cfg->g;
+    d.gamma = cfg->gamma;
+    d.cfl = cfg->cfl;
+    d.dt_fixed = cfg->dt_fixed;
+    d.h0 = 0.0;
+
+    fvk::Ctl fresh;
+    std::memset(&fresh, 0, sizeof fresh);
+    hipError_t e = hipMemcpyAsync(s->ctl(), &fresh, sizeof fresh, hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) {
+        delete s;
+        return hip_fail(e, "control block upload");
+    }
+    rc = init_rate(s);
+    if (rc == FV_OK) rc = sync_and_check(s);
+    if (rc == FV_OK && cfg->eqn == FV_SWE && cfg->h_ref > 0) {
+        s->d.h0 = cfg->h_ref;
+    } else if (rc == FV_OK && cfg->eqn == FV_SWE) {
+        // reference depth of the pressure term: mean initial depth
+        double tot[5];
+        rc = fv_totals(s, tot);
+        if (rc == FV_OK) s->d.h0 = tot[0] / (cfg->lx * cfg->ly);
+    }
+    if (rc != FV_OK) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return FV_OK;
+}
+
+fv_status fv_step(fv_solver *s)
+{
+    if (!s) return fail(FV_E_INVALID, "solver is NULL");
+    return enqueue_step(s);
+}
+
+fv_status fv_run(fv_solver *s, int64_t nsteps)
+{
+    if (!s) return fail(FV_E_INVALID, "solver is NULL");
+    if (nsteps < 0) return fail(FV_E_INVALID, "nsteps %lld < 0", (long long)nsteps);
+    for (int64_t k = 0; k < nsteps; k++) {
+        fv_status rc = enqueue_step(s);
+        if (rc != FV_OK) return rc;
+    }
+    return FV_OK;
+}
+
+fv_status fv_time(fv_solver *s, double *t, int64_t *step)
+{
+    if (!s) return fail(FV_E_INVALID, "solver is NULL");
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    fvk::Ctl c;
+    e = hipMemcpy(&c, s->ctl(), sizeof c, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read control block");
+    if (t) *t = c.t;
+    if (step) *step = c.step;
+    if (c.bad) return fail(FV_E_INADMISSIBLE, "a cell became inadmissible at step %lld", (long long)c.step);
+    return FV_OK;
+}
+
+fv_status fv_totals(fv_solver *s, double *out)
+{
+    if (!s || !out) return fail(FV_E_INVALID, "NULL argument");
+    double *dev_out = (double *)(s->ws + s->L.totals_out);
+    double *partials = (double *)(s->ws + s->L.partials);
+    hipError_t e = fvk::launch_totals(s->d, s->q, partials, fvk::TOTALS_MAX_BLOCKS, dev_out, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "totals launch");
+    e = hipMemcpyAsync(out, dev_out, (nvar_of(&s->cfg) + 1) * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "totals copy");
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return FV_OK;
+}
+
+fv_status fv_get_state(fv_solver *s, void *dst, int dst_is_host)
+{
+    if (!s || !dst) return fail(FV_E_INVALID, "NULL argument");
+    hipError_t e = hipMemcpyAsync(dst, s->q, s->state_bytes,
+                                  dst_is_host ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "state copy");
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return FV_OK;
+}
+
+fv_status fv_set_state(fv_solver *s, const void *src, int src_is_host)
+{
+    if (!s || !src) return fail(FV_E_INVALID, "NULL argument");
+    hipError_t e = hipMemcpyAsync(s->q, src, s->state_bytes,
+                                  src_is_host ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "state copy");
+    fvk::Ctl c;
+    e = hipStreamSynchronize(s->stream);
+    if (e == hipSuccess) e = hipMemcpy(&c, s->ctl(), sizeof c, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "read control block");
+    c.bad = 0;
+    c.rate[0] = c.rate[1] = c.rate[2] = 0;
+    e = hipMemcpyAsync(s->ctl(), &c, sizeof c, hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "control block upload");
+    fv_status rc = init_rate(s);
+    if (rc != FV_OK) return rc;
+    return sync_and_check(s);
+}
+
+void *fv_state_ptr(fv_solver *s) { return s ? s->q : nullptr; }
+
+double fv_reference_depth(const fv_solver *s) { return s ? s->d.h0 : 0.0; }
+
+fv_status fv_set_stream(fv_solver *s, void *stream)
+{
+    if (!s) return fail(FV_E_INVALID, "solver is NULL");
+    hipError_t e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    s->stream = (hipStream_t)stream;
+    return FV_OK;
+}
+
+fv_status fv_face_fluxes(fv_solver *s, void *fx, void *fy)
+{
+    if (!s || !fx || !fy) return fail(FV_E_INVALID, "NULL argument");
+    if (s->bed) return fail(FV_E_UNSUPPORTED, "face export is defined for flat-bottom configurations");
+    hipError_t e = fvk::launch_face_fluxes(s->d, s->q, fx, fy, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "face kernel");
+    e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return FV_OK;
+}
+
+void fv_destroy(fv_solver *s)
+{
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    delete s;
+}
+
+const char *fv_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

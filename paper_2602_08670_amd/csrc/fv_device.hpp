@@ -1,0 +1,311 @@
+// Device-side physics of the finite-volume step: face-state reconstruction,
+// normal-frame numerical fluxes and the hydrostatic bed treatment.
+//
+// Thesis "A Machine Learning accelerated geophysical fluid solver":
+//   shallow-water flux, eq 2.3; Euler flux with the ideal-gas law, eq 2.4 and
+//   section 4.2; MINMOD face states, eq 2.18; HLLE, eq 2.16; Rusanov, eq 2.12;
+//   Roe, eq 2.13/2.14; axis-aligned rotation into the face frame, eq 2.24.
+// The bed source follows the hydrostatic reconstruction of Audusse et al.
+// (2004), the reading taken where the thesis leaves the discretisation open.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace fvk {
+
+enum { SWE = 0, EULER = 1 };
+enum { HLLE = 0, RUSANOV = 1, ROE = 2 };
+enum { MINMOD = 0, FIRST = 1 };
+
+// ---------------------------------------------------------------- arithmetic
+// Single precision uses the hardware reciprocal and square root (about 1 ulp);
+// double precision keeps IEEE division and square root.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ double fsqrt(double x) { return __builtin_sqrt(x); }
+template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
+template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
+template <typename T> __device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
+
+// MINMOD(a, b): 0 unless a and b share a sign, else the one of smaller magnitude.
+template <typename T> __device__ __forceinline__ T minmod(T a, T b)
+{
+    bool same = (a > T(0) && b > T(0)) || (a < T(0) && b < T(0));
+    T m = tabs(a) <= tabs(b) ? a : b;
+    return same ? m : T(0);
+}
+
+// Velocity m/h; a dry state (h == 0, produced only by the hydrostatic step)
+// has zero velocity.
+template <typename T> __device__ __forceinline__ T vel(T m, T h) { return h > T(0) ? m * rcp(h) : T(0); }
+
+template <typename T> struct Phys {
+    T g;      // gravity
+    T gamma;  // ratio of specific heats
+    T h0;     // reference depth: the SWE pressure is carried as g (h - h0)(h + h0) / 2
+};
+
+// ------------------------------------------------------------ shallow water
+// Normal-frame state (h, m, t): m momentum normal to the face, t tangential.
+template <typename T> struct SweS { T h, m, t; };
+
+// Physical flux.  The pressure g h^2/2 is carried relative to the constant
+// g h0^2/2: every numerical flux below is affine in (F_L, F_R) with weights
+// summing to one, so the constant shifts all face fluxes equally and cancels
+// in the divergence of every cell, while the rounding error of the momentum
+// flux scales with |h - h0| instead of h.
+template <typename T> __device__ __forceinline__ void swe_phys(const SweS<T> &s, T g, T h0, T u, T f[3])
+{
+    f[0] = s.m;
+    f[1] = s.m * u + T(0.5) * g * (s.h - h0) * (s.h + h0);
+    f[2] = s.t * u;
+}
+
+template <typename T, int FLUX>
+__device__ __forceinline__ void swe_numflux(const SweS<T> &L, const SweS<T> &R, T g, T h0, T F[3])
+{
+    T ul = vel(L.m, L.h), ur = vel(R.m, R.h);
+    T fl[3], fr[3];
+    swe_phys(L, g, h0, ul, fl);
+    swe_phys(R, g, h0, ur, fr);
+    T cl = fsqrt(g * L.h), cr = fsqrt(g * R.h);
+    T dq[3] = {R.h - L.h, R.m - L.m, R.t - L.t};
+    if (FLUX == RUSANOV) {
+        T a = tmax(tabs(ul) + cl, tabs(ur) + cr);
+#pragma unroll
+        for (int k = 0; k < 3; k++) F[k] = T(0.5) * (fl[k] + fr[k]) - T(0.5) * a * dq[k];
+        return;
+    }
+    // Roe averages: sqrt(h)-weighted velocities, c~ = sqrt(g (hL + hR) / 2)
+    T wl = fsqrt(L.h), wr = fsqrt(R.h);
+    T iw = rcp(wl + wr);
+    T ua = (wl * ul + wr * ur) * iw;
+    T ca = fsqrt(g * T(0.5) * (L.h + R.h));
+    if (FLUX == HLLE) {
+        T sL = tmin(tmin(ul - cl, ua - ca), T(0));
+        T sR = tmax(tmax(ur + cr, ua + ca), T(0));
+        T den = sR - sL;
+        if (den == T(0)) {
+#pragma unroll
+            for (int k = 0; k < 3; k++) F[k] = T(0.5) * (fl[k] + fr[k]);
+            return;
+        }
+        T id = rcp(den), ss = sL * sR;
+#pragma unroll
+        for (int k = 0; k < 3; k++) F[k] = (sR * fl[k] - sL * fr[k] + ss * dq[k]) * id;
+        return;
+    }
+    // Roe: three waves u-c, u (shear), u+c
+    T tl = vel(L.t, L.h), tr = vel(R.t, R.h);
+    T va = (wl * tl + wr * tr) * iw;
+    T i2c = rcp(T(2) * ca);
+    T a1 = ((ua + ca) * dq[0] - dq[1]) * i2c;
+    T a3 = (dq[1] - (ua - ca) * dq[0]) * i2c;
+    T a2 = dq[2] - va * dq[0];
+    T l1 = tabs(ua - ca) * a1, l2 = tabs(ua) * a2, l3 = tabs(ua + ca) * a3;
+    F[0] = T(0.5) * (fl[0] + fr[0]) - T(0.5) * (l1 + l3);
+    F[1] = T(0.5) * (fl[1] + fr[1]) - T(0.5) * (l1 * (ua - ca) + l3 * (ua + ca));
+    F[2] = T(0.5) * (fl[2] + fr[2]) - T(0.5) * (l1 * va + l2 + l3 * va);
+}
+
+// ----------------------------------------------------------------- Euler
+template <typename T> struct EulS { T r, m, t, E; };
+
+template <typename T> __device__ __forceinline__ T eul_p(const EulS<T> &s, T gamma)
+{
+    return (gamma - T(1)) * (s.E - T(0.5) * (s.m * s.m + s.t * s.t) * rcp(s.r));
+}
+
+template <typename T, int FLUX>
+__device__ __forceinline__ void eul_numflux(const EulS<T> &L, const EulS<T> &R, T gamma, T F[4])
+{
+    T irl = rcp(L.r), irr = rcp(R.r);
+    T ul = L.m * irl, ur = R.m * irr;
+    T pl = eul_p(L, gamma), pr = eul_p(R, gamma);
+    T fl[4] = {L.m, L.m * ul + pl, L.t * ul, ul * (L.E + pl)};
+    T fr[4] = {R.m, R.m * ur + pr, R.t * ur, ur * (R.E + pr)};
+    T dq[4] = {R.r - L.r, R.m - L.m, R.t - L.t, R.E - L.E};
+    T cl = fsqrt(gamma * pl * irl), cr = fsqrt(gamma * pr * irr);
+    if (FLUX == RUSANOV) {
+        T a = tmax(tabs(ul) + cl, tabs(ur) + cr);
+#pragma unroll
+        for (int k = 0; k < 4; k++) F[k] = T(0.5) * (fl[k] + fr[k]) - T(0.5) * a * dq[k];
+        return;
+    }
+    T wl = fsqrt(L.r), wr = fsqrt(R.r);
+    T iw = rcp(wl + wr);
+    T vl = L.t * irl, vr = R.t * irr;
+    T ua = (wl * ul + wr * ur) * iw;
+    T va = (wl * vl + wr * vr) * iw;
+    T Ha = (wl * ((L.E + pl) * irl) + wr * ((R.E + pr) * irr)) * iw;
+    T c2 = (gamma - T(1)) * (Ha - T(0.5) * (ua * ua + va * va));
+    T ca = fsqrt(tmax(c2, T(0)));
+    if (FLUX == HLLE) {
+        T sL = tmin(tmin(ul - cl, ua - ca), T(0));
+        T sR = tmax(tmax(ur + cr, ua + ca), T(0));
+        T den = sR - sL;
+        if (den == T(0)) {
+#pragma unroll
+            for (int k = 0; k < 4; k++) F[k] = T(0.5) * (fl[k] + fr[k]);
+            return;
+        }
+        T id = rcp(den), ss = sL * sR;
+#pragma unroll
+        for (int k = 0; k < 4; k++) F[k] = (sR * fl[k] - sL * fr[k] + ss * dq[k]) * id;
+        return;
+    }
+    // Roe: acoustic u-c, entropy u, shear u, acoustic u+c (normal frame)
+    T gm1 = gamma - T(1);
+    T a3 = dq[2] - va * dq[0];
+    T d5 = dq[3] - a3 * va;
+    T a2 = gm1 * rcp(ca * ca) * (dq[0] * (Ha - ua * ua) + ua * dq[1] - d5);
+    T a1 = (dq[0] * (ua + ca) - dq[1] - ca * a2) * rcp(T(2) * ca);
+    T a4 = dq[0] - (a1 + a2);
+    T w1 = tabs(ua - ca) * a1, w2 = tabs(ua) * a2, w3 = tabs(ua) * a3, w4 = tabs(ua + ca) * a4;
+    F[0] = T(0.5) * (fl[0] + fr[0]) - T(0.5) * (w1 + w2 + w4);
+    F[1] = T(0.5) * (fl[1] + fr[1]) - T(0.5) * (w1 * (ua - ca) + w2 * ua + w4 * (ua + ca));
+    F[2] = T(0.5) * (fl[2] + fr[2]) - T(0.5) * (w1 * va + w2 * va + w3 + w4 * va);
+    F[3] = T(0.5) * (fl[3] + fr[3]) -
+           T(0.5) * (w1 * (Ha - ua * ca) + w2 * T(0.5) * (ua * ua + va * va) + w3 * va + w4 * (Ha + ua * ca));
+}
+
+// --------------------------------------------------------- face states
+
+// Face states on both sides of face i+1/2 from the four cells i-1, i, i+1, i+2
+// along the face normal, for one scalar: MINMOD (eq 2.18, right state taken
+// towards the face) or first order.
+template <typename T, int RECON>
+__device__ __forceinline__ void recon_pair(T m1, T c0, T c1, T p2, T &ql, T &qr)
+{
+    if (RECON == FIRST) {
+        ql = c0;
+        qr = c1;
+    } else {
+        ql = c0 + T(0.5) * minmod(c0 - m1, c1 - c0);
+        qr = c1 - T(0.5) * minmod(c1 - c0, p2 - c1);
+    }
+}
+
+template <typename T> __device__ __forceinline__ bool eul_admissible(T r, T m, T t, T E, T gamma)
+{
+    if (!(r > T(0))) return false;
+    T p = (gamma - T(1)) * (E - T(0.5) * (m * m + t * t) * rcp(r));
+    return p > T(0);
+}
+
+// Cell-state admissibility (also rejects NaN).
+template <typename T, int EQN> __device__ __forceinline__ bool cell_ok(const T *s, T gamma)
+{
+    if (EQN == SWE) return s[0] > T(0) && s[0] < T(1e30);
+    return eul_admissible(s[0], s[1], s[2], s[3], gamma) && s[3] < T(1e300);
+}
+
+// Largest characteristic rate (|u|+c)/dx + (|v|+c)/dy of a cell state.
+template <typename T, int EQN> __device__ __forceinline__ T cell_rate(const T *s, Phys<T> ph, T rdx, T rdy)
+{
+    T ir = rcp(s[0]);
+    T u = s[1] * ir, v = s[2] * ir;
+    T c;
+    if (EQN == SWE) {
+        c = fsqrt(ph.g * s[0]);
+    } else {
+        T p = (ph.gamma - T(1)) * (s[3] - T(0.5) * (s[1] * s[1] + s[2] * s[2]) * ir);
+        c = fsqrt(ph.gamma * p * ir);
+    }
+    return (tabs(u) + c) * rdx + (tabs(v) + c) * rdy;
+}
+
+// Full face computation.  Inputs: the four cells along the normal for each
+// variable, in Cartesian order (v = 0..NV-1, plus the free surface eta = h + b
+// as the last entry when BATHY).  Output: flux seen by the cell on the left
+// (FlC, NV values, Cartesian order) and the normal-momentum flux seen by the
+// cell on the right (frn) -- they differ only by the hydrostatic correction.
+// AXIS 0: x face (normal momentum is variable 1), AXIS 1: y face (variable 2).
+template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int AXIS>
+__device__ __forceinline__ void face_flux(const T (*st)[4], Phys<T> ph, T *FlC, T &frn)
+{
+    constexpr int NV = EQN == SWE ? 3 : 4;
+    constexpr int NR = NV + (BATHY ? 1 : 0);
+    constexpr int NM = AXIS == 0 ? 1 : 2, TM = AXIS == 0 ? 2 : 1;
+    T QL[NR], QR[NR];
+#pragma unroll
+    for (int v = 0; v < NR; v++) recon_pair<T, RECON>(st[v][0], st[v][1], st[v][2], st[v][3], QL[v], QR[v]);
+    // face states that are not admissible fall back to the cell average
+    bool okl, okr;
+    if (EQN == SWE) {
+        okl = QL[0] > T(0);
+        okr = QR[0] > T(0);
+    } else {
+        okl = eul_admissible(QL[0], QL[1], QL[2], QL[3], ph.gamma);
+        okr = eul_admissible(QR[0], QR[1], QR[2], QR[3], ph.gamma);
+    }
+    if (!okl) {
+#pragma unroll
+        for (int v = 0; v < NR; v++) QL[v] = st[v][1];
+    }
+    if (!okr) {
+#pragma unroll
+        for (int v = 0; v < NR; v++) QR[v] = st[v][2];
+    }
+    if (EQN == EULER) {
+        EulS<T> L{QL[0], QL[NM], QL[TM], QL[3]}, R{QR[0], QR[NM], QR[TM], QR[3]};
+        T F[4];
+        eul_numflux<T, FLUX>(L, R, ph.gamma, F);
+        FlC[0] = F[0];
+        FlC[NM] = F[1];
+        FlC[TM] = F[2];
+        FlC[3] = F[3];
+        frn = F[1];
+        return;
+    }
+    if (!BATHY) {
+        SweS<T> L{QL[0], QL[NM], QL[TM]}, R{QR[0], QR[NM], QR[TM]};
+        T F[3];
+        swe_numflux<T, FLUX>(L, R, ph.g, ph.h0, F);
+        FlC[0] = F[0];
+        FlC[NM] = F[1];
+        FlC[TM] = F[2];
+        frn = F[1];
+        return;
+    }
+    // hydrostatic reconstruction: bed at the face = max of the two sides,
+    // depths re-evaluated against it, velocities kept
+    T hl = QL[0], hr = QR[0];
+    T el = QL[NV], er = QR[NV];
+    T zf = tmax(el - hl, er - hr);
+    T hls = tmax(T(0), el - zf), hrs = tmax(T(0), er - zf);
+    T il = rcp(hl), ir = rcp(hr);
+    SweS<T> L{hls, hls * (QL[NM] * il), hls * (QL[TM] * il)};
+    SweS<T> R{hrs, hrs * (QR[NM] * ir), hrs * (QR[TM] * ir)};
+    T F[3] = {T(0), T(0), T(0)};
+    if (hls > T(0) || hrs > T(0)) swe_numflux<T, FLUX>(L, R, ph.g, ph.h0, F);
+    FlC[0] = F[0];
+    FlC[NM] = F[1] + T(0.5) * ph.g * (hl - hls) * (hl + hls);
+    FlC[TM] = F[2];
+    frn = F[1] + T(0.5) * ph.g * (hr - hrs) * (hr + hrs);
+}
+
+// Bed source of one cell along one axis, from the cell's own face states:
+// -g (h_{i-1/2+} + h_{i+1/2-})/2 (z_{i+1/2-} - z_{i-1/2+}) / dx.
+// Inputs: depth and free surface of cells i-1, i, i+1 along the axis.
+template <typename T, int RECON>
+__device__ __forceinline__ T bed_source(T hm, T h0, T hp, T em, T e0, T ep, T g, T rdx)
+{
+    T hR, hL, eR, eL;  // hR: state at face i+1/2 from the left; hL: at i-1/2 from the right
+    if (RECON == FIRST) {
+        hR = hL = h0;
+        eR = eL = e0;
+    } else {
+        T sh = minmod(h0 - hm, hp - h0), se = minmod(e0 - em, ep - e0);
+        hR = h0 + T(0.5) * sh;
+        hL = h0 - T(0.5) * sh;
+        eR = e0 + T(0.5) * se;
+        eL = e0 - T(0.5) * se;
+        if (!(hR > T(0))) { hR = h0; eR = e0; }
+        if (!(hL > T(0))) { hL = h0; eL = e0; }
+    }
+    return -g * T(0.5) * (hL + hR) * ((eR - hR) - (eL - hL)) * rdx;
+}
+
+}  // namespace fvk

@@ -1,0 +1,55 @@
+// Internal interface between the C-ABI host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+namespace fvk {
+
+// Device control block of one solve (lives in the caller's workspace).
+// rate[k] holds the bits of a non-negative double: the largest CFL rate of a
+// state, reduced with atomicMax on the bit pattern (monotone for x >= 0).
+struct Ctl {
+    unsigned long long rate[3];
+    double t;             // simulated time
+    long long step;       // completed steps
+    int bad;              // a step produced an inadmissible cell
+    int pad0;
+    unsigned long long pad1[2];
+};
+static_assert(sizeof(Ctl) == 64, "control block layout");
+
+struct StageDesc {
+    int prec;   // 0 float, 1 double
+    int eqn;    // 0 SWE, 1 Euler
+    int bathy;  // bed present
+    int flux;
+    int recon;
+    int nx, ny, bc_x, bc_y;
+    double rdx, rdy, g, gamma;
+    double h0;  // SWE reference depth of the pressure term (mean initial depth)
+    double cfl, dt_fixed;
+};
+
+// One RK stage: out = a0*q0 + a1*(qs + dt*L(qs)); q0 is read only at the
+// updated cell, so out may alias q0.  On the last stage the CFL rate of out
+// is reduced into ctl->rate[rate_out] (rate_out >= 0), rate_clear is zeroed,
+// admissibility is checked and time/step advance.
+hipError_t launch_stage(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed,
+                        double a0, double a1, Ctl *ctl, int rate_in, int rate_out, int rate_clear, int last,
+                        hipStream_t st);
+
+// Reduce the CFL rate of q into ctl->rate[slot] and flag inadmissible cells.
+hipError_t launch_rate(const StageDesc &d, const void *q, Ctl *ctl, int slot, hipStream_t st);
+
+// Deterministic double-precision totals (nvar sums + energy) into out_dev.
+hipError_t launch_totals(const StageDesc &d, const void *q, double *partials, int max_blocks, double *out_dev,
+                         hipStream_t st);
+
+// Face fluxes of q (flat bottom): fx [nv][ny][nx+1], fy [nv][ny+1][nx].
+hipError_t launch_face_fluxes(const StageDesc &d, const void *q, void *fx, void *fy, hipStream_t st);
+
+constexpr int TOTALS_MAX_BLOCKS = 1024;
+
+}  // namespace fvk

@@ -1,0 +1,455 @@
+// Finite-volume stage kernels for gfx950 (MI355X).
+//
+// One workgroup of 256 threads (four wave64) owns a TX x TY tile of cells.
+//  1. The tile plus a two-cell halo of every variable (and eta = h + b with a
+//     bed) is staged into LDS with coalesced row loads; ghost cells are
+//     synthesised during the load (periodic wrap or wall mirror with the
+//     normal momentum negated).
+//  2. Every x face and y face of the tile is evaluated exactly once
+//     (reconstruction, hydrostatic step, numerical flux) and kept in LDS.
+//  3. Each cell forms the flux divergence (eq 2.9 / eq 2.23), adds the bed
+//     source, combines the Runge-Kutta stage (eq 2.19 / eq 2.20) and writes
+//     its new value.  On the last stage the CFL rate of the new state is
+//     reduced with a wave64 shuffle max, across waves in LDS, then one
+//     atomicMax per workgroup into the device slot read by the next step, so
+//     Delta t never travels through the host.
+#include "fv_device.hpp"
+#include "fv_internal.hpp"
+
+namespace fvk {
+
+__device__ __forceinline__ int map_index(int i, int n, int bc, bool &flip)
+{
+    if (i >= 0 && i < n) return i;
+    if (bc == 0) return ((i % n) + n) % n;
+    flip = true;
+    int m = i < 0 ? -1 - i : 2 * n - 1 - i;
+    return m < 0 ? 0 : (m >= n ? n - 1 : m);  // cells past the ghost layer are never used
+}
+
+template <typename T> struct StageArgs {
+    const T *qs;
+    const T *q0;
+    T *out;
+    const T *bed;
+    int nx, ny, bc_x, bc_y;
+    T rdx, rdy;
+    Phys<T> ph;
+    T a0, a1;
+    double cfl, dt_fixed;
+    Ctl *ctl;
+    int rate_in, rate_out, rate_clear, last;
+};
+
+template <typename T> __device__ __forceinline__ T wave_max(T v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = tmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+template <typename T, int EQN>
+__device__ __forceinline__ bool cell_finite_ok(const T *s, T gamma)
+{
+    constexpr int NV = EQN == SWE ? 3 : 4;
+    bool fin = true;
+#pragma unroll
+    for (int v = 0; v < NV; v++) fin = fin && __builtin_isfinite(s[v]);
+    if (!fin) return false;
+    if (EQN == SWE) return s[0] > T(0);
+    return eul_admissible(s[0], s[1], s[2], s[3], gamma);
+}
+
+// Block-wide max of v (threads 0..255) -> returned in thread 0.
+template <typename T> __device__ __forceinline__ T block_max256(T v, T *red)
+{
+    v = wave_max(v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    T m = red[0];
+#pragma unroll
+    for (int w = 1; w < 4; w++) m = tmax(m, red[w]);
+    return m;
+}
+
+template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int TX, int TY>
+__global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
+{
+    constexpr int NV = EQN == SWE ? 3 : 4;
+    constexpr int NL = NV + (BATHY ? 1 : 0);
+    constexpr int NF = NV + (BATHY ? 1 : 0);
+    constexpr int HX = TX + 4, HY = TY + 4;
+    __shared__ T s_q[NL][HY][HX];
+    __shared__ T s_fx[NF][TY][TX + 1];
+    __shared__ T s_fy[NF][TY + 1][TX];
+    __shared__ T s_red[4];
+
+    if (a.ctl->bad) return;  // an earlier step failed: the state is frozen
+    const int tid = threadIdx.x;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const int nx = a.nx, ny = a.ny;
+    const size_t plane = (size_t)nx * ny;
+
+    const double dtd = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl / __longlong_as_double(a.ctl->rate[a.rate_in]);
+    const T dt = (T)dtd;
+
+    // 1. halo tile -> LDS with ghost synthesis
+    for (int k = tid; k < HY * HX; k += 256) {
+        int ly = k / HX, lx = k - ly * HX;
+        bool fx = false, fy = false;
+        int ix = map_index(x0 - 2 + lx, nx, a.bc_x, fx);
+        int iy = map_index(y0 - 2 + ly, ny, a.bc_y, fy);
+        size_t idx = (size_t)iy * nx + ix;
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            T val = a.qs[v * plane + idx];
+            if ((v == 1 && fx) || (v == 2 && fy)) val = -val;
+            s_q[v][ly][lx] = val;
+        }
+        if (BATHY) s_q[NV][ly][lx] = s_q[0][ly][lx] + a.bed[idx];
+    }
+    __syncthreads();
+
+    // 2a. x faces: face fi of row fj lies between halo cells fi+1 and fi+2
+    for (int f = tid; f < TY * (TX + 1); f += 256) {
+        int fj = f / (TX + 1), fi = f - fj * (TX + 1);
+        T st[NL][4];
+#pragma unroll
+        for (int v = 0; v < NL; v++)
+#pragma unroll
+            for (int k = 0; k < 4; k++) st[v][k] = s_q[v][fj + 2][fi + k];
+        T Fl[NV], frn;
+        face_flux<T, EQN, BATHY, FLUX, RECON, 0>(st, a.ph, Fl, frn);
+#pragma unroll
+        for (int v = 0; v < NV; v++) s_fx[v][fj][fi] = Fl[v];
+        if (BATHY) s_fx[NV][fj][fi] = frn;
+    }
+    // 2b. y faces: face fj of column fi lies between halo rows fj+1 and fj+2
+    for (int f = tid; f < (TY + 1) * TX; f += 256) {
+        int fj = f / TX, fi = f - fj * TX;
+        T st[NL][4];
+#pragma unroll
+        for (int v = 0; v < NL; v++)
+#pragma unroll
+            for (int k = 0; k < 4; k++) st[v][k] = s_q[v][fj + k][fi + 2];
+        T Fl[NV], frn;
+        face_flux<T, EQN, BATHY, FLUX, RECON, 1>(st, a.ph, Fl, frn);
+#pragma unroll
+        for (int v = 0; v < NV; v++) s_fy[v][fj][fi] = Fl[v];
+        if (BATHY) s_fy[NV][fj][fi] = frn;
+    }
+    __syncthreads();
+
+    // 3. divergence + source + RK combine
+    T lmax = T(0);
+    bool bad = false;
+    for (int k = tid; k < TX * TY; k += 256) {
+        int cy = k / TX, cx = k - cy * TX;
+        int gx = x0 + cx, gy = y0 + cy;
+        if (gx >= nx || gy >= ny) continue;
+        size_t idx = (size_t)gy * nx + gx;
+        T Lv[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            T fxm = (BATHY && v == 1) ? s_fx[NV][cy][cx] : s_fx[v][cy][cx];
+            T fym = (BATHY && v == 2) ? s_fy[NV][cy][cx] : s_fy[v][cy][cx];
+            T lxv = -(s_fx[v][cy][cx + 1] - fxm) * a.rdx;
+            T lyv = -(s_fy[v][cy + 1][cx] - fym) * a.rdy;
+            Lv[v] = lxv + lyv;
+        }
+        if (BATHY) {
+            const int hx = cx + 2, hy = cy + 2;
+            Lv[1] += bed_source<T, RECON>(s_q[0][hy][hx - 1], s_q[0][hy][hx], s_q[0][hy][hx + 1],
+                                          s_q[NV][hy][hx - 1], s_q[NV][hy][hx], s_q[NV][hy][hx + 1], a.ph.g,
+                                          a.rdx);
+            Lv[2] += bed_source<T, RECON>(s_q[0][hy - 1][hx], s_q[0][hy][hx], s_q[0][hy + 1][hx],
+                                          s_q[NV][hy - 1][hx], s_q[NV][hy][hx], s_q[NV][hy + 1][hx], a.ph.g,
+                                          a.rdy);
+        }
+        T qn[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) {
+            T o = a.a1 * (s_q[v][cy + 2][cx + 2] + dt * Lv[v]);
+            if (a.a0 != T(0)) o = a.a0 * a.q0[v * plane + idx] + o;
+            a.out[v * plane + idx] = o;
+            qn[v] = o;
+        }
+        if (a.last) {
+            if (!cell_finite_ok<T, EQN>(qn, a.ph.gamma)) bad = true;
+            else if (a.rate_out >= 0) lmax = tmax(lmax, cell_rate<T, EQN>(qn, a.ph, a.rdx, a.rdy));
+        }
+    }
+    if (!a.last) return;
+    if (bad) atomicExch(&a.ctl->bad, 1);
+    if (a.rate_out >= 0) {
+        T m = block_max256(lmax, s_red);
+        if (tid == 0) atomicMax(&a.ctl->rate[a.rate_out], (unsigned long long)__double_as_longlong((double)m));
+    }
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+        a.ctl->t += dtd;
+        a.ctl->step += 1;
+        if (a.rate_clear >= 0) a.ctl->rate[a.rate_clear] = 0ull;
+    }
+}
+
+// ------------------------------------------------------------ CFL rate of q
+template <typename T, int EQN>
+__global__ __launch_bounds__(256) void rate_kernel(const T *q, int n, T rdx, T rdy, Phys<T> ph, Ctl *ctl, int slot)
+{
+    __shared__ T s_red[4];
+    constexpr int NV = EQN == SWE ? 3 : 4;
+    T lmax = T(0);
+    bool bad = false;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        T s[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) s[v] = q[(size_t)v * n + k];
+        if (!cell_finite_ok<T, EQN>(s, ph.gamma)) bad = true;
+        else lmax = tmax(lmax, cell_rate<T, EQN>(s, ph, rdx, rdy));
+    }
+    if (bad) atomicExch(&ctl->bad, 1);
+    T m = block_max256(lmax, s_red);
+    if (threadIdx.x == 0) atomicMax(&ctl->rate[slot], (unsigned long long)__double_as_longlong((double)m));
+}
+
+// ----------------------------------------------------------------- totals
+// Block b sums a fixed set of cells in a fixed order, then a fixed-order tree;
+// a single block then adds the block partials in index order.
+template <typename T, int EQN>
+__global__ __launch_bounds__(256) void totals_partial_kernel(const T *q, int n, double dA, double g, double *partials)
+{
+    constexpr int NV = EQN == SWE ? 3 : 4;
+    __shared__ double s[NV + 1][256];
+    double acc[NV + 1];
+#pragma unroll
+    for (int v = 0; v <= NV; v++) acc[v] = 0.0;
+    for (int k = blockIdx.x * 256 + threadIdx.x; k < n; k += gridDim.x * 256) {
+        double c[NV];
+#pragma unroll
+        for (int v = 0; v < NV; v++) c[v] = (double)q[(size_t)v * n + k];
+#pragma unroll
+        for (int v = 0; v < NV; v++) acc[v] += c[v] * dA;
+        double kin = 0.5 * (c[1] * c[1] + c[2] * c[2]) / c[0];
+        acc[NV] += (EQN == SWE ? 0.5 * g * c[0] * c[0] + kin : kin) * dA;
+    }
+#pragma unroll
+    for (int v = 0; v <= NV; v++) s[v][threadIdx.x] = acc[v];
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w)
+#pragma unroll
+            for (int v = 0; v <= NV; v++) s[v][threadIdx.x] += s[v][threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int v = 0; v <= NV; v++) partials[blockIdx.x * (NV + 1) + v] = s[v][0];
+}
+
+__global__ void totals_final_kernel(const double *partials, int nblocks, int nout, double *out)
+{
+    if (threadIdx.x >= nout) return;
+    double acc = 0.0;
+    for (int b = 0; b < nblocks; b++) acc += partials[b * nout + threadIdx.x];
+    out[threadIdx.x] = acc;
+}
+
+// --------------------------------------------------------------- face export
+template <typename T, int EQN, int FLUX, int RECON>
+__global__ void face_kernel(const T *q, int nx, int ny, int bc_x, int bc_y, Phys<T> ph, T *fx, T *fy)
+{
+    constexpr int NV = EQN == SWE ? 3 : 4;
+    const size_t plane = (size_t)nx * ny;
+    const int nfx = (nx + 1) * ny, nfy = nx * (ny + 1);
+    int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= nfx + nfy) return;
+    int axis = f < nfx ? 0 : 1;
+    int i, j;
+    if (axis == 0) {
+        j = f / (nx + 1);
+        i = f - j * (nx + 1) - 1;  // face between cells i and i+1
+    } else {
+        int g = f - nfx;
+        j = g / nx - 1;            // face between rows j and j+1
+        i = g - (j + 1) * nx;
+    }
+    T st[NV][4];
+    for (int k = 0; k < 4; k++) {
+        int ci = axis == 0 ? i - 1 + k : i, cj = axis == 0 ? j : j - 1 + k;
+        bool flx = false, fly = false;
+        int ix = map_index(ci, nx, bc_x, flx), iy = map_index(cj, ny, bc_y, fly);
+        for (int v = 0; v < NV; v++) {
+            T val = q[v * plane + (size_t)iy * nx + ix];
+            if ((v == 1 && flx) || (v == 2 && fly)) val = -val;
+            st[v][k] = val;
+        }
+    }
+    T Fl[NV], frn;
+    if (axis == 0) {
+        face_flux<T, EQN, false, FLUX, RECON, 0>(st, ph, Fl, frn);
+        for (int v = 0; v < NV; v++) fx[(size_t)v * nfx + (size_t)j * (nx + 1) + i + 1] = Fl[v];
+    } else {
+        face_flux<T, EQN, false, FLUX, RECON, 1>(st, ph, Fl, frn);
+        for (int v = 0; v < NV; v++) fy[(size_t)v * nfy + (size_t)(j + 1) * nx + i] = Fl[v];
+    }
+}
+
+// ----------------------------------------------------------------- dispatch
+template <typename T> struct Tile;
+template <> struct Tile<float> { static constexpr int X = 64, Y = 16; };
+template <> struct Tile<double> { static constexpr int X = 64, Y = 8; };
+
+template <typename T, int EQN, bool BATHY, int FLUX, int RECON>
+static hipError_t stage_t(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed, double a0,
+                          double a1, Ctl *ctl, int ri, int ro, int rc, int last, hipStream_t st)
+{
+    StageArgs<T> a;
+    a.qs = (const T *)qs;
+    a.q0 = (const T *)q0;
+    a.out = (T *)out;
+    a.bed = (const T *)bed;
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.bc_x = d.bc_x;
+    a.bc_y = d.bc_y;
+    a.rdx = (T)d.rdx;
+    a.rdy = (T)d.rdy;
+    a.ph.g = (T)d.g;
+    a.ph.gamma = (T)d.gamma;
+    a.ph.h0 = (T)d.h0;
+    a.a0 = (T)a0;
+    a.a1 = (T)a1;
+    a.cfl = d.cfl;
+    a.dt_fixed = d.dt_fixed;
+    a.ctl = ctl;
+    a.rate_in = ri;
+    a.rate_out = ro;
+    a.rate_clear = rc;
+    a.last = last;
+    constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;
+    dim3 grid((d.nx + TX - 1) / TX, (d.ny + TY - 1) / TY);
+    hipLaunchKernelGGL((stage_kernel<T, EQN, BATHY, FLUX, RECON, TX, TY>), grid, dim3(256), 0, st, a);
+    return hipGetLastError();
+}
+
+template <typename T, int EQN, bool BATHY, int FLUX>
+static hipError_t stage_r(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed, double a0,
+                          double a1, Ctl *ctl, int ri, int ro, int rc, int last, hipStream_t st)
+{
+    if (d.recon == FIRST)
+        return stage_t<T, EQN, BATHY, FLUX, FIRST>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
+    return stage_t<T, EQN, BATHY, FLUX, MINMOD>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
+}
+
+template <typename T, int EQN, bool BATHY>
+static hipError_t stage_f(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed, double a0,
+                          double a1, Ctl *ctl, int ri, int ro, int rc, int last, hipStream_t st)
+{
+    switch (d.flux) {
+    case RUSANOV: return stage_r<T, EQN, BATHY, RUSANOV>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
+    case ROE: return stage_r<T, EQN, BATHY, ROE>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
+    default: return stage_r<T, EQN, BATHY, HLLE>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
+    }
+}
+
+template <typename T>
+static hipError_t stage_p(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed, double a0,
+                          double a1, Ctl *ctl, int ri, int ro, int rc, int last, hipStream_t st)
+{
+    if (d.eqn == EULER) return stage_f<T, EULER, false>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
+    if (d.bathy) return stage_f<T, SWE, true>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
+    return stage_f<T, SWE, false>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
+}
+
+hipError_t launch_stage(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed, double a0,
+                        double a1, Ctl *ctl, int rate_in, int rate_out, int rate_clear, int last, hipStream_t st)
+{
+    if (d.prec == 1)
+        return stage_p<double>(d, qs, q0, out, bed, a0, a1, ctl, rate_in, rate_out, rate_clear, last, st);
+    return stage_p<float>(d, qs, q0, out, bed, a0, a1, ctl, rate_in, rate_out, rate_clear, last, st);
+}
+
+template <typename T>
+static hipError_t rate_t(const StageDesc &d, const void *q, Ctl *ctl, int slot, hipStream_t st)
+{
+    int n = d.nx * d.ny;
+    int blocks = (n + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    Phys<T> ph{(T)d.g, (T)d.gamma, T(0)};
+    if (d.eqn == EULER)
+        hipLaunchKernelGGL((rate_kernel<T, EULER>), dim3(blocks), dim3(256), 0, st, (const T *)q, n, (T)d.rdx,
+                           (T)d.rdy, ph, ctl, slot);
+    else
+        hipLaunchKernelGGL((rate_kernel<T, SWE>), dim3(blocks), dim3(256), 0, st, (const T *)q, n, (T)d.rdx,
+                           (T)d.rdy, ph, ctl, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_rate(const StageDesc &d, const void *q, Ctl *ctl, int slot, hipStream_t st)
+{
+    return d.prec == 1 ? rate_t<double>(d, q, ctl, slot, st) : rate_t<float>(d, q, ctl, slot, st);
+}
+
+template <typename T>
+static hipError_t totals_t(const StageDesc &d, const void *q, double *partials, int max_blocks, double *out,
+                           hipStream_t st)
+{
+    int n = d.nx * d.ny;
+    int blocks = (n + 255) / 256;
+    if (blocks > max_blocks) blocks = max_blocks;
+    double dA = 1.0 / (d.rdx * d.rdy);
+    int nv = d.eqn == EULER ? 4 : 3;
+    if (d.eqn == EULER)
+        hipLaunchKernelGGL((totals_partial_kernel<T, EULER>), dim3(blocks), dim3(256), 0, st, (const T *)q, n, dA,
+                           d.g, partials);
+    else
+        hipLaunchKernelGGL((totals_partial_kernel<T, SWE>), dim3(blocks), dim3(256), 0, st, (const T *)q, n, dA,
+                           d.g, partials);
+    hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(64), 0, st, partials, blocks, nv + 1, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_totals(const StageDesc &d, const void *q, double *partials, int max_blocks, double *out_dev,
+                         hipStream_t st)
+{
+    return d.prec == 1 ? totals_t<double>(d, q, partials, max_blocks, out_dev, st)
+                       : totals_t<float>(d, q, partials, max_blocks, out_dev, st);
+}
+
+template <typename T, int EQN, int FLUX>
+static hipError_t face_r(const StageDesc &d, const void *q, void *fx, void *fy, hipStream_t st)
+{
+    int nf = (d.nx + 1) * d.ny + d.nx * (d.ny + 1);
+    Phys<T> ph{(T)d.g, (T)d.gamma, T(0)};  // exported fluxes carry the full pressure
+    dim3 grid((nf + 255) / 256);
+    if (d.recon == FIRST)
+        hipLaunchKernelGGL((face_kernel<T, EQN, FLUX, FIRST>), grid, dim3(256), 0, st, (const T *)q, d.nx, d.ny,
+                           d.bc_x, d.bc_y, ph, (T *)fx, (T *)fy);
+    else
+        hipLaunchKernelGGL((face_kernel<T, EQN, FLUX, MINMOD>), grid, dim3(256), 0, st, (const T *)q, d.nx, d.ny,
+                           d.bc_x, d.bc_y, ph, (T *)fx, (T *)fy);
+    return hipGetLastError();
+}
+
+template <typename T, int EQN>
+static hipError_t face_f(const StageDesc &d, const void *q, void *fx, void *fy, hipStream_t st)
+{
+    switch (d.flux) {
+    case RUSANOV: return face_r<T, EQN, RUSANOV>(d, q, fx, fy, st);
+    case ROE: return face_r<T, EQN, ROE>(d, q, fx, fy, st);
+    default: return face_r<T, EQN, HLLE>(d, q, fx, fy, st);
+    }
+}
+
+template <typename T>
+static hipError_t face_p(const StageDesc &d, const void *q, void *fx, void *fy, hipStream_t st)
+{
+    return d.eqn == EULER ? face_f<T, EULER>(d, q, fx, fy, st) : face_f<T, SWE>(d, q, fx, fy, st);
+}
+
+hipError_t launch_face_fluxes(const StageDesc &d, const void *q, void *fx, void *fy, hipStream_t st)
+{
+    return d.prec == 1 ? face_p<double>(d, q, fx, fy, st) : face_p<float>(d, q, fx, fy, st);
+}
+
+}  // namespace fvk

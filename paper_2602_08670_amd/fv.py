@@ -1,0 +1,223 @@
+"""Thin Python binding of libfv (include/fv.h): argument marshalling only.
+
+Every entry point keeps the C name (fv_init, fv_step, fv_run, ...).  Device
+memory and streams come from PyTorch; all computation runs in the HIP
+kernels of libfv.so.  If the library is not built the import of this module
+raises immediately -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfv.so")
+
+FV_OK, FV_E_INVALID, FV_E_NOMEM, FV_E_HIP, FV_E_INADMISSIBLE, FV_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5
+FV_SWE, FV_EULER = 0, 1
+FV_F32, FV_F64 = 0, 1
+FV_BC_PERIODIC, FV_BC_WALL = 0, 1
+FV_FLUX_HLLE, FV_FLUX_RUSANOV, FV_FLUX_ROE = 0, 1, 2
+FV_RECON_MINMOD, FV_RECON_FIRST = 0, 1
+
+
+class FvError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fv status {code}: {msg}")
+        self.code = code
+
+
+class fv_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("eqn", ctypes.c_int32), ("prec", ctypes.c_int32),
+                ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("bc_x", ctypes.c_int32),
+                ("bc_y", ctypes.c_int32), ("flux", ctypes.c_int32), ("recon", ctypes.c_int32),
+                ("rk_stages", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("lx", ctypes.c_double),
+                ("ly", ctypes.c_double), ("cfl", ctypes.c_double), ("dt_fixed", ctypes.c_double),
+                ("g", ctypes.c_double), ("gamma", ctypes.c_double), ("h_ref", ctypes.c_double)]
+
+
+def make_config(eqn=FV_SWE, prec=FV_F32, nx=64, ny=64, bc_x=FV_BC_PERIODIC, bc_y=FV_BC_PERIODIC,
+                flux=FV_FLUX_HLLE, recon=FV_RECON_MINMOD, rk_stages=2, lx=1.0, ly=1.0, cfl=0.4,
+                dt_fixed=0.0, g=9.81, gamma=1.4, h_ref=0.0) -> fv_config:
+    return fv_config(ctypes.sizeof(fv_config), eqn, prec, nx, ny, bc_x, bc_y, flux, recon, rk_stages, 0,
+                     lx, ly, cfl, dt_fixed, g, gamma, h_ref)
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, st = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int
+    cp = ctypes.POINTER(fv_config)
+    sig = {
+        "fv_nvar": ([cp], ctypes.c_int),
+        "fv_workspace_bytes": ([cp], ctypes.c_size_t),
+        "fv_init": ([cp, vp, vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], st),
+        "fv_step": ([vp], st),
+        "fv_run": ([vp, i64], st),
+        "fv_time": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)], st),
+        "fv_totals": ([vp, ctypes.POINTER(ctypes.c_double)], st),
+        "fv_get_state": ([vp, vp, ctypes.c_int], st),
+        "fv_set_state": ([vp, vp, ctypes.c_int], st),
+        "fv_state_ptr": ([vp], vp),
+        "fv_reference_depth": ([vp], ctypes.c_double),
+        "fv_set_stream": ([vp, vp], st),
+        "fv_face_fluxes": ([vp, vp, vp], st),
+        "fv_destroy": ([vp], None),
+        "fv_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    return lib
+
+
+lib = _load()
+
+
+def _check(rc: int):
+    if rc != FV_OK:
+        raise FvError(rc, lib.fv_last_error().decode())
+
+
+# --------------------------------------------------------------- C-ABI names
+
+def fv_nvar(cfg: fv_config) -> int:
+    return lib.fv_nvar(ctypes.byref(cfg))
+
+
+def fv_workspace_bytes(cfg: fv_config) -> int:
+    n = lib.fv_workspace_bytes(ctypes.byref(cfg))
+    if n == 0:
+        raise FvError(FV_E_INVALID, lib.fv_last_error().decode())
+    return n
+
+
+def fv_init(cfg: fv_config, q_ptr: int, bathy_ptr: int | None, ws_ptr: int, ws_bytes: int, stream: int = 0):
+    h = ctypes.c_void_p()
+    _check(lib.fv_init(ctypes.byref(cfg), q_ptr, bathy_ptr, ws_ptr, ws_bytes, stream, ctypes.byref(h)))
+    return h
+
+
+def fv_step(h):
+    _check(lib.fv_step(h))
+
+
+def fv_run(h, nsteps: int):
+    _check(lib.fv_run(h, int(nsteps)))
+
+
+def fv_time(h):
+    t, s = ctypes.c_double(), ctypes.c_int64()
+    _check(lib.fv_time(h, ctypes.byref(t), ctypes.byref(s)))
+    return t.value, s.value
+
+
+def fv_totals(h, nvar: int) -> np.ndarray:
+    out = np.zeros(nvar + 1)
+    _check(lib.fv_totals(h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+    return out
+
+
+def fv_get_state(h, dst_ptr: int, dst_is_host: int):
+    _check(lib.fv_get_state(h, dst_ptr, dst_is_host))
+
+
+def fv_set_state(h, src_ptr: int, src_is_host: int):
+    _check(lib.fv_set_state(h, src_ptr, src_is_host))
+
+
+def fv_state_ptr(h) -> int:
+    return lib.fv_state_ptr(h)
+
+
+def fv_reference_depth(h) -> float:
+    return lib.fv_reference_depth(h)
+
+
+def fv_set_stream(h, stream: int):
+    _check(lib.fv_set_stream(h, stream))
+
+
+def fv_face_fluxes(h, fx_ptr: int, fy_ptr: int):
+    _check(lib.fv_face_fluxes(h, fx_ptr, fy_ptr))
+
+
+def fv_destroy(h):
+    lib.fv_destroy(h)
+
+
+def fv_last_error() -> str:
+    return lib.fv_last_error().decode()
+
+
+# ------------------------------------------------------ torch-backed handle
+
+class Solver:
+    """A solve whose state, bed and workspace are torch CUDA tensors."""
+
+    def __init__(self, q0, bathy=None, device="cuda", stream=None, **cfg_kw):
+        import torch
+
+        q0 = np.asarray(q0)
+        nvar, ny, nx = q0.shape
+        cfg_kw.setdefault("eqn", FV_SWE if nvar == 3 else FV_EULER)
+        self.cfg = make_config(nx=nx, ny=ny, **cfg_kw)
+        self.dtype = torch.float64 if self.cfg.prec == FV_F64 else torch.float32
+        self.nvar = nvar
+        self.device = torch.device(device)
+        self.q = torch.tensor(q0, dtype=self.dtype, device=self.device).contiguous()
+        self.bed = None if bathy is None else torch.tensor(np.asarray(bathy), dtype=self.dtype,
+                                                           device=self.device).contiguous()
+        nbytes = fv_workspace_bytes(self.cfg)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = fv_init(self.cfg, self.q.data_ptr(), None if self.bed is None else self.bed.data_ptr(),
+                         self.ws.data_ptr(), nbytes, self.stream.cuda_stream)
+
+    def step(self):
+        fv_step(self.h)
+
+    def run(self, nsteps: int):
+        fv_run(self.h, nsteps)
+
+    def time(self):
+        return fv_time(self.h)
+
+    def totals(self) -> np.ndarray:
+        return fv_totals(self.h, self.nvar)
+
+    def state(self) -> np.ndarray:
+        out = np.empty((self.nvar, self.cfg.ny, self.cfg.nx),
+                       dtype=np.float64 if self.cfg.prec == FV_F64 else np.float32)
+        fv_get_state(self.h, out.ctypes.data, 1)
+        return out.astype(np.float64)
+
+    def set_state(self, q):
+        src = np.ascontiguousarray(q, dtype=np.float64 if self.cfg.prec == FV_F64 else np.float32)
+        fv_set_state(self.h, src.ctypes.data, 1)
+
+    def reference_depth(self) -> float:
+        return fv_reference_depth(self.h)
+
+    def face_fluxes(self):
+        import torch
+
+        fx = torch.empty((self.nvar, self.cfg.ny, self.cfg.nx + 1), dtype=self.dtype, device=self.device)
+        fy = torch.empty((self.nvar, self.cfg.ny + 1, self.cfg.nx), dtype=self.dtype, device=self.device)
+        fv_face_fluxes(self.h, fx.data_ptr(), fy.data_ptr())
+        return fx.double().cpu().numpy(), fy.double().cpu().numpy()
+
+    def close(self):
+        if self.h is not None:
+            fv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

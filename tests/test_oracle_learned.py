@@ -1,0 +1,203 @@
+"""Pins of the learned-path oracle (oracle/learned.py): projection invariants,
+exactness on linear data, special cases that reduce to the (separately
+pinned) classic oracle, brute-force convolution, bfloat16 rounding, the
+fallback wiring, and autograd gradients against central finite differences."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+from paper_2602_08670_amd import inputs as I
+
+F64 = torch.float64
+
+
+@pytest.fixture(scope="module")
+def L():
+    from oracle import learned
+
+    return learned
+
+
+def test_projection_invariants(L):
+    A = L.moment_matrix(1)
+    P = L.projector(1)
+    assert torch.allclose(P @ P, P, atol=1e-15)
+    assert torch.allclose(P, P.T, atol=1e-15)
+    assert int(torch.linalg.matrix_rank(P)) == 4
+    assert torch.abs(A @ P).max() < 1e-15
+    e0 = torch.tensor([1.0, 0.0], dtype=F64)
+    for side in range(2):
+        assert torch.abs(A @ L.ALPHA_BASE[side] - e0).max() < 1e-15
+    g = torch.Generator().manual_seed(0)
+    z = torch.randn(4, 72, 5, 6, generator=g, dtype=F64) * 3
+    a = L.coefficients(z, P)
+    res = torch.einsum("pk,baswkhx->baswphx", A, a) - e0[None, None, None, None, :, None, None]
+    assert res.abs().max() < 1e-14
+    a0 = L.coefficients(torch.zeros(1, 72, 2, 2, dtype=F64), P)
+    assert torch.equal(a0[0, 1, 0, 2, :, 1, 1], L.ALPHA_BASE[0])
+
+
+def test_moment_matrix_matches_cell_average_integrals(L):
+    """Row 1 is the cell centre (cell average of x); row 2 adds 1/12."""
+    A = L.moment_matrix(2)
+    assert torch.allclose(A[0], torch.ones(6, dtype=F64))
+    assert torch.allclose(A[1], L.OFFSETS)
+    assert torch.allclose(A[2], L.OFFSETS ** 2 + 1.0 / 12.0)
+
+
+def test_constrained_faces_exact_on_linear_data(L):
+    """Any alpha = alpha_base + P z reproduces the face value of a linear field
+    from its cell averages (interior faces, away from the periodic seam)."""
+    n = 24
+    x = torch.arange(n, dtype=F64)  # cell centres in cell units
+    q = torch.zeros(1, 3, n, n, dtype=F64)
+    q[0, 0] = 2.0 + 0.03 * x[None, :] - 0.01 * x[:, None]
+    q[0, 1] = 0.5 - 0.02 * x[None, :]
+    q[0, 2] = 0.1 + 0.04 * x[:, None]
+    g = torch.Generator().manual_seed(1)
+    a = L.coefficients(torch.randn(1, 72, n, n, generator=g, dtype=F64), L.projector(1))
+    QL, QR = L.learned_faces(q, a, axis=0)
+    face = lambda f: f  # noqa: E731
+    for v, (c0, cx, cy) in enumerate([(2.0, 0.03, -0.01), (0.5, -0.02, 0.0), (0.1, 0.0, 0.04)]):
+        exact = c0 + cx * (x[None, :] + 0.5) + cy * x[:, None]  # value at face i+1/2
+        sl = (slice(None), slice(3, n - 3))
+        assert torch.abs(QL[0, v][sl] - exact[sl]).max() < 1e-12
+        assert torch.abs(QR[0, v][sl] - exact[sl]).max() < 1e-12
+    QL, QR = L.learned_faces(q, a, axis=1)
+    exact = 2.0 + 0.03 * x[None, :] - 0.01 * (x[:, None] + 0.5)
+    assert torch.abs(QL[0, 0][3:n - 3] - exact[3:n - 3]).max() < 1e-12
+
+
+@pytest.mark.parametrize("flux,cflux", [("hlle", 0), ("rusanov", 1)])
+def test_one_hot_alpha_equals_first_order_classic(L, orc, flux, cflux):
+    """alpha_L = e(cell i), alpha_R = e(cell i+1) is the first-order scheme:
+    the learned operator equals the classic oracle with recon=FIRST."""
+    q0, _ = I.swe_bathy(32, seed=3)
+    q0[1] = 0.05 * np.sin(2 * np.pi * np.arange(32) / 32)[None, :]
+    q0[2] = -0.04 * np.cos(2 * np.pi * np.arange(32) / 32)[:, None]
+    q = torch.tensor(q0)[None]
+    a = torch.zeros(1, 2, 2, 3, 6, 32, 32, dtype=F64)
+    a[:, :, 0, :, 2] = 1.0
+    a[:, :, 1, :, 3] = 1.0
+    Lq, nfb = L.rhs(q, a, 1 / 32, 1 / 32, flux=flux)
+    ref = orc.rhs(orc.Config(nx=32, ny=32, recon=orc.FIRST, flux=cflux), q0)
+    assert nfb == 0
+    assert np.abs(Lq[0].numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("flux,cflux", [("hlle", 0), ("rusanov", 1)])
+def test_plain_minmod_equals_classic(L, orc, flux, cflux):
+    q0, _ = I.swe_bathy(32, seed=4)
+    q0[1] = 0.05 * np.sin(2 * np.pi * np.arange(32) / 32)[None, :]
+    q = torch.tensor(q0)[None]
+    Lq, _ = L.rhs(q, None, 1 / 32, 1 / 32, flux=flux)
+    ref = orc.rhs(orc.Config(nx=32, ny=32, flux=cflux), q0)
+    assert np.abs(Lq[0].numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    qs = L.plain_step(q, 1e-3, 1 / 32, 1 / 32, flux=flux)
+    ref, *_ = orc.run(orc.Config(nx=32, ny=32, flux=cflux, dt_fixed=1e-3), q0, None, 1)
+    assert np.abs(qs[0].numpy() - ref).max() <= 1e-13
+
+
+def test_all_faces_fall_back_gives_plain_scheme(L):
+    """Coefficients that make every learned depth negative send every face
+    side to the MINMOD state: the operator equals the plain one exactly."""
+    q0 = I.random_smooth_swe(16, seed=2)
+    q = torch.tensor(q0)[None]
+    a = torch.zeros(1, 2, 2, 3, 6, 16, 16, dtype=F64)
+    a[:, :, :, :, 2] = -1.0
+    Lq, nfb = L.rhs(q, a, 1 / 16, 1 / 16)
+    ref, _ = L.rhs(q, None, 1 / 16, 1 / 16)
+    assert nfb == 2 * 2 * 16 * 16
+    assert torch.equal(Lq, ref)
+
+
+def test_conv_bruteforce_and_library(L):
+    g = torch.Generator().manual_seed(5)
+    x = torch.randn(2, 2, 5, 4, generator=g, dtype=F64)
+    w = torch.randn(3, 2, 3, 3, generator=g, dtype=F64)
+    b = torch.randn(3, generator=g, dtype=F64)
+    out = L.conv3x3_periodic(x, w, b)
+    ref = torch.zeros(2, 3, 5, 4, dtype=F64)
+    for n, o, y, xx, c, ky, kx in itertools.product(range(2), range(3), range(5), range(4), range(2), range(3),
+                                                     range(3)):
+        ref[n, o, y, xx] += w[o, c, ky, kx] * x[n, c, (y + ky - 1) % 5, (xx + kx - 1) % 4]
+    ref += b[None, :, None, None]
+    assert torch.allclose(out, ref, atol=1e-13)
+    lib = torch.nn.functional.conv2d(torch.nn.functional.pad(x, (1, 1, 1, 1), mode="circular"), w, b)
+    assert torch.allclose(out, lib, atol=1e-13)
+
+
+def test_bf16_round_to_nearest_even(L):
+    v = torch.tensor([1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -8 + 2.0 ** -20, -3.0 - 2.0 ** -7],
+                     dtype=F64)
+    r = L.bf16(v, ste=False)
+    assert r.tolist() == [1.0, 1.0 + 2.0 ** -6, 1.0 + 2.0 ** -7, -3.0]
+
+
+def test_zero_last_layer_gives_fromm(L):
+    """With z = 0 every face uses Fromm's stencils."""
+    p = L.init_params(0, hidden=8, layers=[(3, 8), (8, 8), (8, 72)])
+    q = torch.tensor(I.random_smooth_swe(12, seed=1))[None]
+    z = L.cnn(p, q)
+    assert torch.equal(z, torch.zeros_like(z))
+
+
+def test_rollout_loss_zero_on_own_rollout(L):
+    p = L.init_params(3, hidden=8, scale_last=0.05, layers=[(3, 8), (8, 8), (8, 72)])
+    q = torch.tensor(I.random_smooth_swe(16, seed=6))[None]
+    dt = 5e-4
+    tg = []
+    qq = q
+    for _ in range(3):
+        qq, _ = L.learned_step(p, qq, dt, 1 / 16, 1 / 16)
+        tg.append(qq)
+    tg = torch.stack(tg, 1).detach()
+    assert float(L.rollout_loss(p, q, tg, dt, 1 / 16, 1 / 16, [0.1, 0.1, 0.1])) < 1e-28
+
+
+@pytest.mark.slow
+def test_autograd_matches_central_differences(L):
+    """d loss / d theta and d loss / d q0 from automatic differentiation agree
+    with central finite differences (h = 1e-6) on a small network and grid
+    (bfloat16 rounding off so the loss is smooth)."""
+    p = L.init_params(4, hidden=4, scale_last=0.2, layers=[(3, 4), (4, 4), (4, 72)])
+    p["b"][0] = torch.full((4,), 0.3, dtype=F64)
+    q0 = torch.tensor(I.random_smooth_swe(8, seed=7, humps=2))[None]
+    q0[:, 1] = 0.02
+    dt = 2e-3
+    with torch.no_grad():
+        tg = []
+        qq = q0 + 0.001
+        for _ in range(2):
+            qq = L.plain_step(qq, dt, 1 / 8, 1 / 8)
+            tg.append(qq)
+        tg = torch.stack(tg, 1)
+    leaves = p["w"] + p["b"]
+    for t in leaves:
+        t.requires_grad_(True)
+    qv = q0.clone().requires_grad_(True)
+    loss = L.rollout_loss(p, qv, tg, dt, 1 / 8, 1 / 8, [0.1, 0.05, 0.05], round_bf16=False)
+    grads = torch.autograd.grad(loss, leaves + [qv])
+    g = torch.Generator().manual_seed(11)
+    h = 1e-6
+    checked = 0
+    for t, gr in zip(leaves + [qv], grads):
+        flat = t.detach().view(-1)
+        for _ in range(3):
+            k = int(torch.randint(0, flat.numel(), (1,), generator=g))
+            with torch.no_grad():
+                old = flat[k].item()
+                flat[k] = old + h
+                lp = L.rollout_loss(p, qv.detach() if t is not qv else qv, tg, dt, 1 / 8, 1 / 8, [0.1, 0.05, 0.05],
+                                    round_bf16=False)
+                flat[k] = old - h
+                lm = L.rollout_loss(p, qv.detach() if t is not qv else qv, tg, dt, 1 / 8, 1 / 8, [0.1, 0.05, 0.05],
+                                    round_bf16=False)
+                flat[k] = old
+            fd = (lp - lm).item() / (2 * h)
+            an = gr.view(-1)[k].item()
+            assert abs(fd - an) <= 1e-6 * abs(fd) + 1e-10, (fd, an)
+            checked += 1
+    assert checked == 3 * len(leaves + [qv])
