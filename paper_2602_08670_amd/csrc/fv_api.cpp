@@ -38,7 +38,7 @@ fv_status hip_fail(hipError_t e, const char *what)
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t ctl, totals_out, partials, s1, s2, total;
+    size_t ctl, rates, totals_out, partials, s1, s2, total;
 };
 
 int nvar_of(const fv_config *c) { return c->eqn == FV_EULER ? 4 : 3; }
@@ -72,8 +72,9 @@ Layout layout_of(const fv_config *c)
     size_t es = c->prec == FV_F64 ? 8 : 4;
     size_t st = align256((size_t)nvar_of(c) * c->nx * c->ny * es);
     L.ctl = 0;
-    L.totals_out = 256;
-    L.partials = 512;
+    L.rates = fvk::CTL_BYTES;
+    L.totals_out = L.rates + fvk::RATE_BYTES;
+    L.partials = L.totals_out + 256;
     L.s1 = L.partials + align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * sizeof(double));
     L.s2 = L.s1 + st;
     L.total = L.s2 + (c->rk_stages == 3 ? st : 0);
@@ -93,6 +94,7 @@ struct fv_solver {
     int64_t enq;  // steps enqueued since the last rate initialisation
     size_t state_bytes;
     fvk::Ctl *ctl() { return (fvk::Ctl *)(ws + L.ctl); }
+    unsigned long long *rates() { return (unsigned long long *)(ws + L.rates); }
 };
 
 namespace {
@@ -103,7 +105,8 @@ fv_status init_rate(fv_solver *s)
     // control block (ordered on the stream before any kernel that reads it)
     s->enq = 0;
     int slot = 0;
-    hipError_t e = fvk::launch_rate(s->d, s->q, s->ctl(), slot, s->stream);
+    hipError_t e = hipMemsetAsync(s->rates(), 0, fvk::RATE_BYTES, s->stream);
+    if (e == hipSuccess) e = fvk::launch_rate(s->d, s->q, s->ctl(), s->rates(), slot, s->stream);
     if (e != hipSuccess) return hip_fail(e, "rate kernel");
     return FV_OK;
 }
@@ -129,20 +132,20 @@ fv_status enqueue_step(fv_solver *s)
     fvk::Ctl *ctl = s->ctl();
     switch (s->cfg.rk_stages) {
     case 1:
-        e = fvk::launch_stage(s->d, s->q, s->q, S1, s->bed, 0.0, 1.0, ctl, ri, ro, rc, 1, s->stream);
+        e = fvk::launch_stage(s->d, s->q, s->q, S1, s->bed, 0.0, 1.0, ctl, s->rates(), ri, ro, rc, 1, s->stream);
         if (e == hipSuccess) e = hipMemcpyAsync(s->q, S1, s->state_bytes, hipMemcpyDeviceToDevice, s->stream);
         break;
     case 2:
-        e = fvk::launch_stage(s->d, s->q, s->q, S1, s->bed, 0.0, 1.0, ctl, ri, -1, -1, 0, s->stream);
+        e = fvk::launch_stage(s->d, s->q, s->q, S1, s->bed, 0.0, 1.0, ctl, s->rates(), ri, -1, -1, 0, s->stream);
         if (e == hipSuccess)
-            e = fvk::launch_stage(s->d, S1, s->q, s->q, s->bed, 0.5, 0.5, ctl, ri, ro, rc, 1, s->stream);
+            e = fvk::launch_stage(s->d, S1, s->q, s->q, s->bed, 0.5, 0.5, ctl, s->rates(), ri, ro, rc, 1, s->stream);
         break;
     default:
-        e = fvk::launch_stage(s->d, s->q, s->q, S1, s->bed, 0.0, 1.0, ctl, ri, -1, -1, 0, s->stream);
+        e = fvk::launch_stage(s->d, s->q, s->q, S1, s->bed, 0.0, 1.0, ctl, s->rates(), ri, -1, -1, 0, s->stream);
         if (e == hipSuccess)
-            e = fvk::launch_stage(s->d, S1, s->q, S2, s->bed, 0.75, 0.25, ctl, ri, -1, -1, 0, s->stream);
+            e = fvk::launch_stage(s->d, S1, s->q, S2, s->bed, 0.75, 0.25, ctl, s->rates(), ri, -1, -1, 0, s->stream);
         if (e == hipSuccess)
-            e = fvk::launch_stage(s->d, S2, s->q, s->q, s->bed, 1.0 / 3.0, 2.0 / 3.0, ctl, ri, ro, rc, 1, s->stream);
+            e = fvk::launch_stage(s->d, S2, s->q, s->q, s->bed, 1.0 / 3.0, 2.0 / 3.0, ctl, s->rates(), ri, ro, rc, 1, s->stream);
         break;
     }
     if (e != hipSuccess) return hip_fail(e, "stage launch");
@@ -295,7 +298,6 @@ fv_status fv_set_state(fv_solver *s, const void *src, int src_is_host)
     if (e == hipSuccess) e = hipMemcpy(&c, s->ctl(), sizeof c, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "read control block");
     c.bad = 0;
-    c.rate[0] = c.rate[1] = c.rate[2] = 0;
     e = hipMemcpyAsync(s->ctl(), &c, sizeof c, hipMemcpyHostToDevice, s->stream);
     if (e != hipSuccess) return hip_fail(e, "control block upload");
     fv_status rc = init_rate(s);

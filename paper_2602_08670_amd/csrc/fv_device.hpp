@@ -7,6 +7,12 @@
 //   Roe, eq 2.13/2.14; axis-aligned rotation into the face frame, eq 2.24.
 // The bed source follows the hydrostatic reconstruction of Audusse et al.
 // (2004), the reading taken where the thesis leaves the discretisation open.
+//
+// The step is bound by vector-ALU issue, so the code is written branch-free:
+// min/max/abs map to single instructions (v_min3/v_max3, |x| source
+// modifiers), MINMOD is one v_med3_f32, guards are selects, and every face
+// evaluates one reciprocal per side, one for the Roe weight and one for the
+// HLLE denominator, plus three square roots.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -24,82 +30,77 @@ __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x);
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
 __device__ __forceinline__ float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
 __device__ __forceinline__ double fsqrt(double x) { return __builtin_sqrt(x); }
-template <typename T> __device__ __forceinline__ T tmin(T a, T b) { return a < b ? a : b; }
-template <typename T> __device__ __forceinline__ T tmax(T a, T b) { return a > b ? a : b; }
-template <typename T> __device__ __forceinline__ T tabs(T a) { return a < T(0) ? -a : a; }
+__device__ __forceinline__ float tmin(float a, float b) { return __builtin_fminf(a, b); }
+__device__ __forceinline__ double tmin(double a, double b) { return __builtin_fmin(a, b); }
+__device__ __forceinline__ float tmax(float a, float b) { return __builtin_fmaxf(a, b); }
+__device__ __forceinline__ double tmax(double a, double b) { return __builtin_fmax(a, b); }
+__device__ __forceinline__ float tabs(float a) { return __builtin_fabsf(a); }
+__device__ __forceinline__ double tabs(double a) { return __builtin_fabs(a); }
 
-// MINMOD(a, b): 0 unless a and b share a sign, else the one of smaller magnitude.
-template <typename T> __device__ __forceinline__ T minmod(T a, T b)
+// MINMOD(a, b): 0 unless a and b share a sign, else the one of smaller
+// magnitude -- which is the median of (a, b, 0).
+__device__ __forceinline__ float minmod(float a, float b) { return __builtin_amdgcn_fmed3f(a, b, 0.0f); }
+__device__ __forceinline__ double minmod(double a, double b)
 {
-    bool same = (a > T(0) && b > T(0)) || (a < T(0) && b < T(0));
-    T m = tabs(a) <= tabs(b) ? a : b;
-    return same ? m : T(0);
+    return __builtin_fmax(__builtin_fmin(a, b), __builtin_fmin(__builtin_fmax(a, b), 0.0));
 }
 
-// Velocity m/h; a dry state (h == 0, produced only by the hydrostatic step)
-// has zero velocity.
-template <typename T> __device__ __forceinline__ T vel(T m, T h) { return h > T(0) ? m * rcp(h) : T(0); }
+// 1/x for x > 0, else 0 (a dry state has zero velocity).
+template <typename T> __device__ __forceinline__ T rcp_pos(T x) { return x > T(0) ? rcp(x) : T(0); }
 
 template <typename T> struct Phys {
     T g;      // gravity
+    T sqg;    // sqrt(g)
     T gamma;  // ratio of specific heats
     T h0;     // reference depth: the SWE pressure is carried as g (h - h0)(h + h0) / 2
 };
 
 // ------------------------------------------------------------ shallow water
-// Normal-frame state (h, m, t): m momentum normal to the face, t tangential.
-template <typename T> struct SweS { T h, m, t; };
+// Normal-frame state given by depth and velocities: (h, u normal, v tangential).
+template <typename T> struct SweV { T h, u, v; };
 
-// Physical flux.  The pressure g h^2/2 is carried relative to the constant
-// g h0^2/2: every numerical flux below is affine in (F_L, F_R) with weights
-// summing to one, so the constant shifts all face fluxes equally and cancels
-// in the divergence of every cell, while the rounding error of the momentum
-// flux scales with |h - h0| instead of h.
-template <typename T> __device__ __forceinline__ void swe_phys(const SweS<T> &s, T g, T h0, T u, T f[3])
-{
-    f[0] = s.m;
-    f[1] = s.m * u + T(0.5) * g * (s.h - h0) * (s.h + h0);
-    f[2] = s.t * u;
-}
-
+// Numerical flux of two normal-frame shallow-water states.  The pressure
+// g h^2/2 is carried relative to the constant g h0^2/2: every flux below is
+// affine in (F_L, F_R) with weights summing to one (and equal to (F_L+F_R)/2
+// when both sides are dry), so the constant shifts all face fluxes equally
+// and cancels in every cell's divergence, while the rounding error of the
+// momentum flux scales with |h - h0| instead of h.
 template <typename T, int FLUX>
-__device__ __forceinline__ void swe_numflux(const SweS<T> &L, const SweS<T> &R, T g, T h0, T F[3])
+__device__ __forceinline__ void swe_numflux(const SweV<T> &L, const SweV<T> &R, const Phys<T> &ph, T F[3])
 {
-    T ul = vel(L.m, L.h), ur = vel(R.m, R.h);
-    T fl[3], fr[3];
-    swe_phys(L, g, h0, ul, fl);
-    swe_phys(R, g, h0, ur, fr);
-    T cl = fsqrt(g * L.h), cr = fsqrt(g * R.h);
-    T dq[3] = {R.h - L.h, R.m - L.m, R.t - L.t};
+    const T hg = T(0.5) * ph.g;
+    T ml = L.h * L.u, mr = R.h * R.u;
+    T fl[3] = {ml, ml * L.u + hg * (L.h - ph.h0) * (L.h + ph.h0), ml * L.v};
+    T fr[3] = {mr, mr * R.u + hg * (R.h - ph.h0) * (R.h + ph.h0), mr * R.v};
+    T dq[3] = {R.h - L.h, mr - ml, R.h * R.v - L.h * L.v};
+    T wl = fsqrt(L.h), wr = fsqrt(R.h);
+    T cl = ph.sqg * wl, cr = ph.sqg * wr;
     if (FLUX == RUSANOV) {
-        T a = tmax(tabs(ul) + cl, tabs(ur) + cr);
+        T a = tmax(tabs(L.u) + cl, tabs(R.u) + cr);
 #pragma unroll
         for (int k = 0; k < 3; k++) F[k] = T(0.5) * (fl[k] + fr[k]) - T(0.5) * a * dq[k];
         return;
     }
     // Roe averages: sqrt(h)-weighted velocities, c~ = sqrt(g (hL + hR) / 2)
-    T wl = fsqrt(L.h), wr = fsqrt(R.h);
-    T iw = rcp(wl + wr);
-    T ua = (wl * ul + wr * ur) * iw;
-    T ca = fsqrt(g * T(0.5) * (L.h + R.h));
+    T iw = rcp_pos(wl + wr);
+    T ua = (wl * L.u + wr * R.u) * iw;
+    T ca = fsqrt(hg * (L.h + R.h));
     if (FLUX == HLLE) {
-        T sL = tmin(tmin(ul - cl, ua - ca), T(0));
-        T sR = tmax(tmax(ur + cr, ua + ca), T(0));
+        T sL = tmin(tmin(L.u - cl, ua - ca), T(0));
+        T sR = tmax(tmax(R.u + cr, ua + ca), T(0));
         T den = sR - sL;
-        if (den == T(0)) {
+        T id = rcp_pos(den), ss = sL * sR;
+        bool wet = den > T(0);
 #pragma unroll
-            for (int k = 0; k < 3; k++) F[k] = T(0.5) * (fl[k] + fr[k]);
-            return;
+        for (int k = 0; k < 3; k++) {
+            T hll = (sR * fl[k] - sL * fr[k] + ss * dq[k]) * id;
+            F[k] = wet ? hll : T(0.5) * (fl[k] + fr[k]);
         }
-        T id = rcp(den), ss = sL * sR;
-#pragma unroll
-        for (int k = 0; k < 3; k++) F[k] = (sR * fl[k] - sL * fr[k] + ss * dq[k]) * id;
         return;
     }
     // Roe: three waves u-c, u (shear), u+c
-    T tl = vel(L.t, L.h), tr = vel(R.t, R.h);
-    T va = (wl * tl + wr * tr) * iw;
-    T i2c = rcp(T(2) * ca);
+    T va = (wl * L.v + wr * R.v) * iw;
+    T i2c = rcp_pos(T(2) * ca);
     T a1 = ((ua + ca) * dq[0] - dq[1]) * i2c;
     T a3 = (dq[1] - (ua - ca) * dq[0]) * i2c;
     T a2 = dq[2] - va * dq[0];
@@ -122,7 +123,9 @@ __device__ __forceinline__ void eul_numflux(const EulS<T> &L, const EulS<T> &R, 
 {
     T irl = rcp(L.r), irr = rcp(R.r);
     T ul = L.m * irl, ur = R.m * irr;
-    T pl = eul_p(L, gamma), pr = eul_p(R, gamma);
+    T vl = L.t * irl, vr = R.t * irr;
+    T pl = (gamma - T(1)) * (L.E - T(0.5) * (L.m * ul + L.t * vl));
+    T pr = (gamma - T(1)) * (R.E - T(0.5) * (R.m * ur + R.t * vr));
     T fl[4] = {L.m, L.m * ul + pl, L.t * ul, ul * (L.E + pl)};
     T fr[4] = {R.m, R.m * ur + pr, R.t * ur, ur * (R.E + pr)};
     T dq[4] = {R.r - L.r, R.m - L.m, R.t - L.t, R.E - L.E};
@@ -135,7 +138,6 @@ __device__ __forceinline__ void eul_numflux(const EulS<T> &L, const EulS<T> &R, 
     }
     T wl = fsqrt(L.r), wr = fsqrt(R.r);
     T iw = rcp(wl + wr);
-    T vl = L.t * irl, vr = R.t * irr;
     T ua = (wl * ul + wr * ur) * iw;
     T va = (wl * vl + wr * vr) * iw;
     T Ha = (wl * ((L.E + pl) * irl) + wr * ((R.E + pr) * irr)) * iw;
@@ -144,13 +146,7 @@ __device__ __forceinline__ void eul_numflux(const EulS<T> &L, const EulS<T> &R, 
     if (FLUX == HLLE) {
         T sL = tmin(tmin(ul - cl, ua - ca), T(0));
         T sR = tmax(tmax(ur + cr, ua + ca), T(0));
-        T den = sR - sL;
-        if (den == T(0)) {
-#pragma unroll
-            for (int k = 0; k < 4; k++) F[k] = T(0.5) * (fl[k] + fr[k]);
-            return;
-        }
-        T id = rcp(den), ss = sL * sR;
+        T id = rcp(sR - sL), ss = sL * sR;  // sR - sL >= c~ > 0 for admissible states
 #pragma unroll
         for (int k = 0; k < 4; k++) F[k] = (sR * fl[k] - sL * fr[k] + ss * dq[k]) * id;
         return;
@@ -189,28 +185,20 @@ __device__ __forceinline__ void recon_pair(T m1, T c0, T c1, T p2, T &ql, T &qr)
 
 template <typename T> __device__ __forceinline__ bool eul_admissible(T r, T m, T t, T E, T gamma)
 {
-    if (!(r > T(0))) return false;
     T p = (gamma - T(1)) * (E - T(0.5) * (m * m + t * t) * rcp(r));
-    return p > T(0);
-}
-
-// Cell-state admissibility (also rejects NaN).
-template <typename T, int EQN> __device__ __forceinline__ bool cell_ok(const T *s, T gamma)
-{
-    if (EQN == SWE) return s[0] > T(0) && s[0] < T(1e30);
-    return eul_admissible(s[0], s[1], s[2], s[3], gamma) && s[3] < T(1e300);
+    return r > T(0) && p > T(0);
 }
 
 // Largest characteristic rate (|u|+c)/dx + (|v|+c)/dy of a cell state.
-template <typename T, int EQN> __device__ __forceinline__ T cell_rate(const T *s, Phys<T> ph, T rdx, T rdy)
+template <typename T, int EQN> __device__ __forceinline__ T cell_rate(const T *s, const Phys<T> &ph, T rdx, T rdy)
 {
     T ir = rcp(s[0]);
     T u = s[1] * ir, v = s[2] * ir;
     T c;
     if (EQN == SWE) {
-        c = fsqrt(ph.g * s[0]);
+        c = ph.sqg * fsqrt(s[0]);
     } else {
-        T p = (ph.gamma - T(1)) * (s[3] - T(0.5) * (s[1] * s[1] + s[2] * s[2]) * ir);
+        T p = (ph.gamma - T(1)) * (s[3] - T(0.5) * (s[1] * u + s[2] * v));
         c = fsqrt(ph.gamma * p * ir);
     }
     return (tabs(u) + c) * rdx + (tabs(v) + c) * rdy;
@@ -223,7 +211,7 @@ template <typename T, int EQN> __device__ __forceinline__ T cell_rate(const T *s
 // cell on the right (frn) -- they differ only by the hydrostatic correction.
 // AXIS 0: x face (normal momentum is variable 1), AXIS 1: y face (variable 2).
 template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int AXIS>
-__device__ __forceinline__ void face_flux(const T (*st)[4], Phys<T> ph, T *FlC, T &frn)
+__device__ __forceinline__ void face_flux(const T (*st)[4], const Phys<T> &ph, T *FlC, T &frn)
 {
     constexpr int NV = EQN == SWE ? 3 : 4;
     constexpr int NR = NV + (BATHY ? 1 : 0);
@@ -240,13 +228,10 @@ __device__ __forceinline__ void face_flux(const T (*st)[4], Phys<T> ph, T *FlC, 
         okl = eul_admissible(QL[0], QL[1], QL[2], QL[3], ph.gamma);
         okr = eul_admissible(QR[0], QR[1], QR[2], QR[3], ph.gamma);
     }
-    if (!okl) {
 #pragma unroll
-        for (int v = 0; v < NR; v++) QL[v] = st[v][1];
-    }
-    if (!okr) {
-#pragma unroll
-        for (int v = 0; v < NR; v++) QR[v] = st[v][2];
+    for (int v = 0; v < NR; v++) {
+        QL[v] = okl ? QL[v] : st[v][1];
+        QR[v] = okr ? QR[v] : st[v][2];
     }
     if (EQN == EULER) {
         EulS<T> L{QL[0], QL[NM], QL[TM], QL[3]}, R{QR[0], QR[NM], QR[TM], QR[3]};
@@ -259,10 +244,11 @@ __device__ __forceinline__ void face_flux(const T (*st)[4], Phys<T> ph, T *FlC, 
         frn = F[1];
         return;
     }
+    T il = rcp(QL[0]), ir = rcp(QR[0]);  // face depths are positive here
     if (!BATHY) {
-        SweS<T> L{QL[0], QL[NM], QL[TM]}, R{QR[0], QR[NM], QR[TM]};
+        SweV<T> L{QL[0], QL[NM] * il, QL[TM] * il}, R{QR[0], QR[NM] * ir, QR[TM] * ir};
         T F[3];
-        swe_numflux<T, FLUX>(L, R, ph.g, ph.h0, F);
+        swe_numflux<T, FLUX>(L, R, ph, F);
         FlC[0] = F[0];
         FlC[NM] = F[1];
         FlC[TM] = F[2];
@@ -275,15 +261,14 @@ __device__ __forceinline__ void face_flux(const T (*st)[4], Phys<T> ph, T *FlC, 
     T el = QL[NV], er = QR[NV];
     T zf = tmax(el - hl, er - hr);
     T hls = tmax(T(0), el - zf), hrs = tmax(T(0), er - zf);
-    T il = rcp(hl), ir = rcp(hr);
-    SweS<T> L{hls, hls * (QL[NM] * il), hls * (QL[TM] * il)};
-    SweS<T> R{hrs, hrs * (QR[NM] * ir), hrs * (QR[TM] * ir)};
-    T F[3] = {T(0), T(0), T(0)};
-    if (hls > T(0) || hrs > T(0)) swe_numflux<T, FLUX>(L, R, ph.g, ph.h0, F);
+    SweV<T> L{hls, QL[NM] * il, QL[TM] * il}, R{hrs, QR[NM] * ir, QR[TM] * ir};
+    T F[3];
+    swe_numflux<T, FLUX>(L, R, ph, F);
+    const T hg = T(0.5) * ph.g;
     FlC[0] = F[0];
-    FlC[NM] = F[1] + T(0.5) * ph.g * (hl - hls) * (hl + hls);
+    FlC[NM] = F[1] + hg * (hl - hls) * (hl + hls);
     FlC[TM] = F[2];
-    frn = F[1] + T(0.5) * ph.g * (hr - hrs) * (hr + hrs);
+    frn = F[1] + hg * (hr - hrs) * (hr + hrs);
 }
 
 // Bed source of one cell along one axis, from the cell's own face states:
@@ -302,8 +287,11 @@ __device__ __forceinline__ T bed_source(T hm, T h0, T hp, T em, T e0, T ep, T g,
         hL = h0 - T(0.5) * sh;
         eR = e0 + T(0.5) * se;
         eL = e0 - T(0.5) * se;
-        if (!(hR > T(0))) { hR = h0; eR = e0; }
-        if (!(hL > T(0))) { hL = h0; eL = e0; }
+        bool okR = hR > T(0), okL = hL > T(0);
+        eR = okR ? eR : e0;
+        hR = okR ? hR : h0;
+        eL = okL ? eL : e0;
+        hL = okL ? hL : h0;
     }
     return -g * T(0.5) * (hL + hR) * ((eR - hR) - (eL - hL)) * rdx;
 }

@@ -8,17 +8,28 @@
 namespace fvk {
 
 // Device control block of one solve (lives in the caller's workspace).
-// rate[k] holds the bits of a non-negative double: the largest CFL rate of a
-// state, reduced with atomicMax on the bit pattern (monotone for x >= 0).
 struct Ctl {
-    unsigned long long rate[3];
     double t;             // simulated time
     long long step;       // completed steps
     int bad;              // a step produced an inadmissible cell
     int pad0;
-    unsigned long long pad1[2];
+    unsigned long long pad1[5];
 };
 static_assert(sizeof(Ctl) == 64, "control block layout");
+
+// CFL rate slots.  Slot k holds RATE_SUB sub-slots, each the bits of a
+// non-negative double reduced with atomicMax on the bit pattern (monotone for
+// x >= 0).  Workgroups spread their atomics over the sub-slots, which sit
+// RATE_STRIDE bytes apart so concurrent atomics land on different memory
+// channels; readers load one sub-slot per lane and take a wave max.
+constexpr int RATE_SUB = 64;
+constexpr int RATE_STRIDE = 256;
+constexpr size_t RATE_BYTES = 3 * RATE_SUB * RATE_STRIDE;
+__host__ __device__ inline unsigned long long *rate_slot(unsigned long long *base, int k, int s)
+{
+    return base + ((size_t)(k * RATE_SUB + s) * RATE_STRIDE) / sizeof(unsigned long long);
+}
+constexpr size_t CTL_BYTES = 256;
 
 struct StageDesc {
     int prec;   // 0 float, 1 double
@@ -37,11 +48,12 @@ struct StageDesc {
 // is reduced into ctl->rate[rate_out] (rate_out >= 0), rate_clear is zeroed,
 // admissibility is checked and time/step advance.
 hipError_t launch_stage(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed,
-                        double a0, double a1, Ctl *ctl, int rate_in, int rate_out, int rate_clear, int last,
-                        hipStream_t st);
+                        double a0, double a1, Ctl *ctl, unsigned long long *rates, int rate_in, int rate_out,
+                        int rate_clear, int last, hipStream_t st);
 
 // Reduce the CFL rate of q into ctl->rate[slot] and flag inadmissible cells.
-hipError_t launch_rate(const StageDesc &d, const void *q, Ctl *ctl, int slot, hipStream_t st);
+hipError_t launch_rate(const StageDesc &d, const void *q, Ctl *ctl, unsigned long long *rates, int slot,
+                       hipStream_t st);
 
 // Deterministic double-precision totals (nvar sums + energy) into out_dev.
 hipError_t launch_totals(const StageDesc &d, const void *q, double *partials, int max_blocks, double *out_dev,

@@ -38,6 +38,7 @@ template <typename T> struct StageArgs {
     T a0, a1;
     double cfl, dt_fixed;
     Ctl *ctl;
+    unsigned long long *rates;
     int rate_in, rate_out, rate_clear, last;
 };
 
@@ -46,6 +47,18 @@ template <typename T> __device__ __forceinline__ T wave_max(T v)
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v = tmax(v, __shfl_xor(v, off, 64));
     return v;
+}
+
+// Largest CFL rate stored in slot k (max over its sub-slots), wave-uniform.
+static_assert(RATE_SUB == 64, "one sub-slot per lane");
+__device__ __forceinline__ double read_rate(unsigned long long *rates, int k)
+{
+    return wave_max(__longlong_as_double(*rate_slot(rates, k, threadIdx.x & 63)));
+}
+
+__device__ __forceinline__ void push_rate(unsigned long long *rates, int k, double m, int block_linear)
+{
+    atomicMax(rate_slot(rates, k, block_linear & (RATE_SUB - 1)), (unsigned long long)__double_as_longlong(m));
 }
 
 template <typename T, int EQN>
@@ -90,23 +103,60 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
     const int nx = a.nx, ny = a.ny;
     const size_t plane = (size_t)nx * ny;
 
-    const double dtd = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl / __longlong_as_double(a.ctl->rate[a.rate_in]);
+    const double dtd = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl / read_rate(a.rates, a.rate_in);
     const T dt = (T)dtd;
 
-    // 1. halo tile -> LDS with ghost synthesis
-    for (int k = tid; k < HY * HX; k += 256) {
-        int ly = k / HX, lx = k - ly * HX;
-        bool fx = false, fy = false;
-        int ix = map_index(x0 - 2 + lx, nx, a.bc_x, fx);
-        int iy = map_index(y0 - 2 + ly, ny, a.bc_y, fy);
-        size_t idx = (size_t)iy * nx + ix;
+    // q0 is needed only in the final combine: load it now so its latency
+    // hides behind the face work
+    constexpr int CPT = (TX * TY + 255) / 256;  // cells per thread
+    T q0r[CPT][NV];
+    if (a.a0 != T(0)) {
 #pragma unroll
-        for (int v = 0; v < NV; v++) {
-            T val = a.qs[v * plane + idx];
-            if ((v == 1 && fx) || (v == 2 && fy)) val = -val;
-            s_q[v][ly][lx] = val;
+        for (int c = 0; c < CPT; c++) {
+            int k = tid + c * 256;
+            int cy = k / TX, cx = k - cy * TX;
+            int gx = x0 + cx, gy = y0 + cy;
+            bool in = k < TX * TY && gx < nx && gy < ny;
+            size_t idx = in ? (size_t)gy * nx + gx : 0;
+#pragma unroll
+            for (int v = 0; v < NV; v++) q0r[c][v] = a.q0[v * plane + idx];
         }
-        if (BATHY) s_q[NV][ly][lx] = s_q[0][ly][lx] + a.bed[idx];
+    }
+
+    // 1. halo tile -> LDS with ghost synthesis.  Tiles whose halo lies inside
+    //    the grid (all but the border tiles) index directly.
+    const bool inner = x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= nx && y0 + TY + 2 <= ny;
+    if (inner) {
+        const T *base = a.qs + (size_t)(y0 - 2) * nx + (x0 - 2);
+        const T *bbase = BATHY ? a.bed + (size_t)(y0 - 2) * nx + (x0 - 2) : nullptr;
+        int ly = tid / HX, lx = tid - ly * HX;
+        for (int k = tid; k < HY * HX; k += 256) {
+            size_t off = (size_t)ly * nx + lx;
+#pragma unroll
+            for (int v = 0; v < NV; v++) s_q[v][ly][lx] = base[v * plane + off];
+            if (BATHY) s_q[NV][ly][lx] = s_q[0][ly][lx] + bbase[off];
+            lx += 256 % HX;
+            ly += 256 / HX;
+            if (lx >= HX) {
+                lx -= HX;
+                ly += 1;
+            }
+        }
+    } else {
+        for (int k = tid; k < HY * HX; k += 256) {
+            int ly = k / HX, lx = k - ly * HX;
+            bool fx = false, fy = false;
+            int ix = map_index(x0 - 2 + lx, nx, a.bc_x, fx);
+            int iy = map_index(y0 - 2 + ly, ny, a.bc_y, fy);
+            size_t idx = (size_t)iy * nx + ix;
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                T val = a.qs[v * plane + idx];
+                if ((v == 1 && fx) || (v == 2 && fy)) val = -val;
+                s_q[v][ly][lx] = val;
+            }
+            if (BATHY) s_q[NV][ly][lx] = s_q[0][ly][lx] + a.bed[idx];
+        }
     }
     __syncthreads();
 
@@ -143,10 +193,12 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
     // 3. divergence + source + RK combine
     T lmax = T(0);
     bool bad = false;
-    for (int k = tid; k < TX * TY; k += 256) {
+#pragma unroll
+    for (int c = 0; c < CPT; c++) {
+        int k = tid + c * 256;
         int cy = k / TX, cx = k - cy * TX;
         int gx = x0 + cx, gy = y0 + cy;
-        if (gx >= nx || gy >= ny) continue;
+        if (k >= TX * TY || gx >= nx || gy >= ny) continue;
         size_t idx = (size_t)gy * nx + gx;
         T Lv[NV];
 #pragma unroll
@@ -170,7 +222,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
 #pragma unroll
         for (int v = 0; v < NV; v++) {
             T o = a.a1 * (s_q[v][cy + 2][cx + 2] + dt * Lv[v]);
-            if (a.a0 != T(0)) o = a.a0 * a.q0[v * plane + idx] + o;
+            if (a.a0 != T(0)) o = a.a0 * q0r[c][v] + o;
             a.out[v * plane + idx] = o;
             qn[v] = o;
         }
@@ -183,18 +235,21 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
     if (bad) atomicExch(&a.ctl->bad, 1);
     if (a.rate_out >= 0) {
         T m = block_max256(lmax, s_red);
-        if (tid == 0) atomicMax(&a.ctl->rate[a.rate_out], (unsigned long long)__double_as_longlong((double)m));
+        if (tid == 0) push_rate(a.rates, a.rate_out, (double)m, blockIdx.x + blockIdx.y * gridDim.x);
     }
-    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
-        a.ctl->t += dtd;
-        a.ctl->step += 1;
-        if (a.rate_clear >= 0) a.ctl->rate[a.rate_clear] = 0ull;
+    if (blockIdx.x == 0 && blockIdx.y == 0) {
+        if (tid == 0) {
+            a.ctl->t += dtd;
+            a.ctl->step += 1;
+        }
+        if (a.rate_clear >= 0 && tid < RATE_SUB) *rate_slot(a.rates, a.rate_clear, tid) = 0ull;
     }
 }
 
 // ------------------------------------------------------------ CFL rate of q
 template <typename T, int EQN>
-__global__ __launch_bounds__(256) void rate_kernel(const T *q, int n, T rdx, T rdy, Phys<T> ph, Ctl *ctl, int slot)
+__global__ __launch_bounds__(256) void rate_kernel(const T *q, int n, T rdx, T rdy, Phys<T> ph, Ctl *ctl,
+                                                   unsigned long long *rates, int slot)
 {
     __shared__ T s_red[4];
     constexpr int NV = EQN == SWE ? 3 : 4;
@@ -209,7 +264,7 @@ __global__ __launch_bounds__(256) void rate_kernel(const T *q, int n, T rdx, T r
     }
     if (bad) atomicExch(&ctl->bad, 1);
     T m = block_max256(lmax, s_red);
-    if (threadIdx.x == 0) atomicMax(&ctl->rate[slot], (unsigned long long)__double_as_longlong((double)m));
+    if (threadIdx.x == 0) push_rate(rates, slot, (double)m, blockIdx.x);
 }
 
 // ----------------------------------------------------------------- totals
@@ -246,12 +301,21 @@ __global__ __launch_bounds__(256) void totals_partial_kernel(const T *q, int n, 
         for (int v = 0; v <= NV; v++) partials[blockIdx.x * (NV + 1) + v] = s[v][0];
 }
 
-__global__ void totals_final_kernel(const double *partials, int nblocks, int nout, double *out)
+// One workgroup per output: thread t adds partials t, t+256, ... in order,
+// then a fixed-order tree over the 256 threads.
+__global__ __launch_bounds__(256) void totals_final_kernel(const double *partials, int nblocks, int nout, double *out)
 {
-    if (threadIdx.x >= nout) return;
+    __shared__ double s[256];
+    const int o = blockIdx.x;
     double acc = 0.0;
-    for (int b = 0; b < nblocks; b++) acc += partials[b * nout + threadIdx.x];
-    out[threadIdx.x] = acc;
+    for (int b = threadIdx.x; b < nblocks; b += 256) acc += partials[b * nout + o];
+    s[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[o] = s[0];
 }
 
 // --------------------------------------------------------------- face export
@@ -296,12 +360,13 @@ __global__ void face_kernel(const T *q, int nx, int ny, int bc_x, int bc_y, Phys
 
 // ----------------------------------------------------------------- dispatch
 template <typename T> struct Tile;
-template <> struct Tile<float> { static constexpr int X = 64, Y = 16; };
+template <> struct Tile<float> { static constexpr int X = 64, Y = 8; };
 template <> struct Tile<double> { static constexpr int X = 64, Y = 8; };
 
 template <typename T, int EQN, bool BATHY, int FLUX, int RECON>
 static hipError_t stage_t(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed, double a0,
-                          double a1, Ctl *ctl, int ri, int ro, int rc, int last, hipStream_t st)
+                          double a1, Ctl *ctl, unsigned long long *rates, int ri, int ro, int rc, int last,
+                          hipStream_t st)
 {
     StageArgs<T> a;
     a.qs = (const T *)qs;
@@ -315,6 +380,7 @@ static hipError_t stage_t(const StageDesc &d, const void *qs, const void *q0, vo
     a.rdx = (T)d.rdx;
     a.rdy = (T)d.rdy;
     a.ph.g = (T)d.g;
+    a.ph.sqg = (T)__builtin_sqrt(d.g);
     a.ph.gamma = (T)d.gamma;
     a.ph.h0 = (T)d.h0;
     a.a0 = (T)a0;
@@ -322,6 +388,7 @@ static hipError_t stage_t(const StageDesc &d, const void *qs, const void *q0, vo
     a.cfl = d.cfl;
     a.dt_fixed = d.dt_fixed;
     a.ctl = ctl;
+    a.rates = rates;
     a.rate_in = ri;
     a.rate_out = ro;
     a.rate_clear = rc;
@@ -334,60 +401,66 @@ static hipError_t stage_t(const StageDesc &d, const void *qs, const void *q0, vo
 
 template <typename T, int EQN, bool BATHY, int FLUX>
 static hipError_t stage_r(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed, double a0,
-                          double a1, Ctl *ctl, int ri, int ro, int rc, int last, hipStream_t st)
+                          double a1, Ctl *ctl, unsigned long long *rates, int ri, int ro, int rc, int last,
+                          hipStream_t st)
 {
     if (d.recon == FIRST)
-        return stage_t<T, EQN, BATHY, FLUX, FIRST>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
-    return stage_t<T, EQN, BATHY, FLUX, MINMOD>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
+        return stage_t<T, EQN, BATHY, FLUX, FIRST>(d, qs, q0, out, bed, a0, a1, ctl, rates, ri, ro, rc, last, st);
+    return stage_t<T, EQN, BATHY, FLUX, MINMOD>(d, qs, q0, out, bed, a0, a1, ctl, rates, ri, ro, rc, last, st);
 }
 
 template <typename T, int EQN, bool BATHY>
 static hipError_t stage_f(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed, double a0,
-                          double a1, Ctl *ctl, int ri, int ro, int rc, int last, hipStream_t st)
+                          double a1, Ctl *ctl, unsigned long long *rates, int ri, int ro, int rc, int last,
+                          hipStream_t st)
 {
     switch (d.flux) {
-    case RUSANOV: return stage_r<T, EQN, BATHY, RUSANOV>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
-    case ROE: return stage_r<T, EQN, BATHY, ROE>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
-    default: return stage_r<T, EQN, BATHY, HLLE>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
+    case RUSANOV: return stage_r<T, EQN, BATHY, RUSANOV>(d, qs, q0, out, bed, a0, a1, ctl, rates, ri, ro, rc, last, st);
+    case ROE: return stage_r<T, EQN, BATHY, ROE>(d, qs, q0, out, bed, a0, a1, ctl, rates, ri, ro, rc, last, st);
+    default: return stage_r<T, EQN, BATHY, HLLE>(d, qs, q0, out, bed, a0, a1, ctl, rates, ri, ro, rc, last, st);
     }
 }
 
 template <typename T>
 static hipError_t stage_p(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed, double a0,
-                          double a1, Ctl *ctl, int ri, int ro, int rc, int last, hipStream_t st)
+                          double a1, Ctl *ctl, unsigned long long *rates, int ri, int ro, int rc, int last,
+                          hipStream_t st)
 {
-    if (d.eqn == EULER) return stage_f<T, EULER, false>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
-    if (d.bathy) return stage_f<T, SWE, true>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
-    return stage_f<T, SWE, false>(d, qs, q0, out, bed, a0, a1, ctl, ri, ro, rc, last, st);
+    if (d.eqn == EULER) return stage_f<T, EULER, false>(d, qs, q0, out, bed, a0, a1, ctl, rates, ri, ro, rc, last, st);
+    if (d.bathy) return stage_f<T, SWE, true>(d, qs, q0, out, bed, a0, a1, ctl, rates, ri, ro, rc, last, st);
+    return stage_f<T, SWE, false>(d, qs, q0, out, bed, a0, a1, ctl, rates, ri, ro, rc, last, st);
 }
 
 hipError_t launch_stage(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed, double a0,
-                        double a1, Ctl *ctl, int rate_in, int rate_out, int rate_clear, int last, hipStream_t st)
+                        double a1, Ctl *ctl, unsigned long long *rates, int rate_in, int rate_out, int rate_clear,
+                        int last, hipStream_t st)
 {
     if (d.prec == 1)
-        return stage_p<double>(d, qs, q0, out, bed, a0, a1, ctl, rate_in, rate_out, rate_clear, last, st);
-    return stage_p<float>(d, qs, q0, out, bed, a0, a1, ctl, rate_in, rate_out, rate_clear, last, st);
+        return stage_p<double>(d, qs, q0, out, bed, a0, a1, ctl, rates, rate_in, rate_out, rate_clear, last, st);
+    return stage_p<float>(d, qs, q0, out, bed, a0, a1, ctl, rates, rate_in, rate_out, rate_clear, last, st);
 }
 
 template <typename T>
-static hipError_t rate_t(const StageDesc &d, const void *q, Ctl *ctl, int slot, hipStream_t st)
+static hipError_t rate_t(const StageDesc &d, const void *q, Ctl *ctl, unsigned long long *rates, int slot,
+                         hipStream_t st)
 {
     int n = d.nx * d.ny;
     int blocks = (n + 255) / 256;
     if (blocks > 2048) blocks = 2048;
-    Phys<T> ph{(T)d.g, (T)d.gamma, T(0)};
+    Phys<T> ph{(T)d.g, (T)__builtin_sqrt(d.g), (T)d.gamma, T(0)};
     if (d.eqn == EULER)
         hipLaunchKernelGGL((rate_kernel<T, EULER>), dim3(blocks), dim3(256), 0, st, (const T *)q, n, (T)d.rdx,
-                           (T)d.rdy, ph, ctl, slot);
+                           (T)d.rdy, ph, ctl, rates, slot);
     else
         hipLaunchKernelGGL((rate_kernel<T, SWE>), dim3(blocks), dim3(256), 0, st, (const T *)q, n, (T)d.rdx,
-                           (T)d.rdy, ph, ctl, slot);
+                           (T)d.rdy, ph, ctl, rates, slot);
     return hipGetLastError();
 }
 
-hipError_t launch_rate(const StageDesc &d, const void *q, Ctl *ctl, int slot, hipStream_t st)
+hipError_t launch_rate(const StageDesc &d, const void *q, Ctl *ctl, unsigned long long *rates, int slot,
+                       hipStream_t st)
 {
-    return d.prec == 1 ? rate_t<double>(d, q, ctl, slot, st) : rate_t<float>(d, q, ctl, slot, st);
+    return d.prec == 1 ? rate_t<double>(d, q, ctl, rates, slot, st) : rate_t<float>(d, q, ctl, rates, slot, st);
 }
 
 template <typename T>
@@ -405,7 +478,7 @@ static hipError_t totals_t(const StageDesc &d, const void *q, double *partials, 
     else
         hipLaunchKernelGGL((totals_partial_kernel<T, SWE>), dim3(blocks), dim3(256), 0, st, (const T *)q, n, dA,
                            d.g, partials);
-    hipLaunchKernelGGL(totals_final_kernel, dim3(1), dim3(64), 0, st, partials, blocks, nv + 1, out);
+    hipLaunchKernelGGL(totals_final_kernel, dim3(nv + 1), dim3(256), 0, st, partials, blocks, nv + 1, out);
     return hipGetLastError();
 }
 
@@ -420,7 +493,7 @@ template <typename T, int EQN, int FLUX>
 static hipError_t face_r(const StageDesc &d, const void *q, void *fx, void *fy, hipStream_t st)
 {
     int nf = (d.nx + 1) * d.ny + d.nx * (d.ny + 1);
-    Phys<T> ph{(T)d.g, (T)d.gamma, T(0)};  // exported fluxes carry the full pressure
+    Phys<T> ph{(T)d.g, (T)__builtin_sqrt(d.g), (T)d.gamma, T(0)};  // exported fluxes carry the full pressure
     dim3 grid((nf + 255) / 256);
     if (d.recon == FIRST)
         hipLaunchKernelGGL((face_kernel<T, EQN, FLUX, FIRST>), grid, dim3(256), 0, st, (const T *)q, d.nx, d.ny,
