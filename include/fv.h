@@ -67,7 +67,7 @@ typedef struct {
     int32_t flux;         /* FV_FLUX_* */
     int32_t recon;        /* FV_RECON_MINMOD | FV_RECON_FIRST */
     int32_t rk_stages;    /* 1 forward Euler, 2 Heun, 3 three-stage SSP */
-    int32_t reserved0;    /* must be 0 */
+    int32_t learned;      /* 1: the workspace also holds the buffers of fv_learned_step */
     double lx, ly;        /* domain [0,lx] x [0,ly], > 0 */
     double cfl;           /* Courant number in (0, 1] */
     double dt_fixed;      /* > 0: fixed Delta t, the CFL reduction is skipped */
@@ -147,6 +147,80 @@ fv_status fv_face_fluxes(fv_solver *s, void *fx, void *fy);
 
 /* Release the handle (not the caller's buffers).  Waits for queued work. */
 void fv_destroy(fv_solver *s);
+
+/* ------------------------------------------------------------------------
+ * Learned stencil coefficients (thesis section 2.5.3, fourth approach:
+ * a CNN outputs constrained reconstruction coefficients per conserved
+ * variable; eq 2.26-2.27 for the pseudo-linear stencil).
+ *
+ * Network: five 3x3 convolutions 3 -> 32 -> 32 -> 32 -> 32 -> 72, ReLU
+ * between layers, periodic padding, input (h, hu, hv) normalised per channel
+ * as (q - mean) * inv_std.  BF16 weights and activations, FP32 accumulation
+ * on MFMA; the 72 outputs of a cell are raw coefficients z for its +x and +y
+ * faces, channel ((axis*2 + side)*3 + var)*6 + k, side 0 = left state, 1 =
+ * right state, k over the six cells i-2..i+3 around the face.  They are
+ * mapped onto the constraint set alpha = alpha_base + P z, where P projects
+ * onto the null space of the moment conditions (the face value is exact for
+ * cell averages of polynomials of degree <= order) and alpha_base are
+ * Fromm's stencils; the face state is sum_k alpha_k q(i-2+k).  A face side
+ * whose learned depth is <= 0 uses the plain MINMOD state; a step that leaves
+ * a cell with h <= 0 is redone with the plain scheme.
+ *
+ * Master parameters: FP32 device vector of fv_model_param_count() floats,
+ * layer by layer W_l[co][ci][ky][kx] followed by b_l[co].
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t struct_size; /* sizeof(fv_model_desc) */
+    int32_t hidden;       /* hidden channels: 32 */
+    int32_t order;        /* constraint order 0 or 1 (1: exact for linear data) */
+    int32_t reserved0;    /* must be 0 */
+    float mean[3];        /* input normalisation */
+    float inv_std[3];
+} fv_model_desc;
+
+typedef struct fv_model fv_model;
+
+typedef struct {
+    int64_t fallback_faces; /* face sides that used the MINMOD state, cumulative */
+    int64_t redone_steps;   /* steps redone with the plain scheme, cumulative */
+} fv_learned_stats;
+
+/* Number of FP32 master parameters (49448). */
+size_t fv_model_param_count(void);
+
+/* Device bytes a model needs for its packed BF16 weights. */
+size_t fv_model_workspace_bytes(const fv_model_desc *desc);
+
+/* Create a model over caller-owned device memory: params (FP32 master
+ * vector, read now and by fv_model_update) and workspace (packed weights,
+ * 256-byte aligned).  Packing is enqueued on stream. */
+fv_status fv_model_create(const fv_model_desc *desc, const float *params, void *workspace, size_t workspace_bytes,
+                          void *stream, fv_model **out);
+
+/* Re-pack the weights after the master parameters changed (async). */
+fv_status fv_model_update(fv_model *m);
+
+void fv_model_destroy(fv_model *m);
+
+/* Scratch bytes fv_model_forward needs for B solves of ny x nx cells. */
+size_t fv_model_forward_scratch_bytes(int B, int nx, int ny);
+
+/* Batched network inference on the model's stream (async):
+ *   q       device [B][3][ny][nx] FP32 states (periodic, nx % 16 == 0,
+ *           nx*ny % 64 == 0);
+ *   z       device [B][ny][nx][72] FP32 raw coefficients (output);
+ *   scratch device, >= fv_model_forward_scratch_bytes(B, nx, ny), 256-byte
+ *           aligned (BF16 activations). */
+fv_status fv_model_forward(const fv_model *m, const float *q, int B, int nx, int ny, float *z, void *scratch,
+                           size_t scratch_bytes);
+
+/* Enqueue nsteps learned Heun steps at the fixed step cfg.dt_fixed.
+ * Requires a shallow-water FP32 solver with periodic boundaries, no bed,
+ * rk_stages = 2, dt_fixed > 0, learned = 1, nx % 16 == 0 and
+ * nx*ny % 64 == 0 (FV_E_UNSUPPORTED otherwise).  When stats is not NULL the
+ * call synchronises and fills the cumulative counters.  Inadmissible results
+ * of the plain redo are reported by fv_time as FV_E_INADMISSIBLE. */
+fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *fv_last_error(void);

@@ -96,12 +96,24 @@ def conv3x3_periodic(x: torch.Tensor, w: torch.Tensor, b: torch.Tensor) -> torch
     return out
 
 
-def cnn(params: dict, q: torch.Tensor, round_bf16: bool = True) -> torch.Tensor:
-    """Raw coefficients z (B, 72, H, W) of states q (B, 3, H, W)."""
+def cnn(params: dict, q: torch.Tensor, round_bf16: bool = True, shadow_f32: bool = False) -> torch.Tensor:
+    """Raw coefficients z (B, 72, H, W) of states q (B, 3, H, W).
+
+    shadow_f32: diagnostic only -- normalise and accumulate every convolution
+    in float32 (as the GPU does) instead of float64; the distance between
+    this and the double-precision result bounds what float32 accumulation
+    alone changes through the bfloat16 rounding decisions."""
     rnd = bf16 if round_bf16 else (lambda t: t)
+    W, bias = params["w"], params["b"]
+    if shadow_f32:
+        x = ((q.float() - params["mean"].float()[None, :, None, None])
+             * params["inv_std"].float()[None, :, None, None]).double()
+        x = rnd(x).float()
+        for l in range(len(W) - 1):
+            x = rnd(torch.relu(conv3x3_periodic(x, W[l].float(), bias[l].float())).double()).float()
+        return conv3x3_periodic(x, W[-1].float(), bias[-1].float()).double()
     x = (q - params["mean"][None, :, None, None]) * params["inv_std"][None, :, None, None]
     x = rnd(x)
-    W, bias = params["w"], params["b"]
     for l in range(len(W) - 1):
         x = rnd(torch.relu(conv3x3_periodic(x, W[l], bias[l])))
     return conv3x3_periodic(x, W[-1], bias[-1])
@@ -190,11 +202,11 @@ FLUXES = {"hlle": hlle, "rusanov": rusanov}
 
 def rhs(q: torch.Tensor, alpha, dx: float, dy: float, g: float = 9.81, flux: str = "hlle"):
     """Spatial operator L(q) with learned face states (alpha given) or the
-    plain MINMOD states (alpha None).  Returns (L, number of face sides that
-    fell back to MINMOD)."""
+    plain MINMOD states (alpha None).  Returns (L, per-solve number of face
+    sides that fell back to MINMOD)."""
     fn = FLUXES[flux]
     L = torch.zeros_like(q)
-    nfb = 0
+    nfb = torch.zeros(q.shape[0], dtype=torch.int64)
     for axis, (dim, d) in enumerate(((3, dx), (2, dy))):
         ML, MR = minmod_faces(q, dim)
         if alpha is None:
@@ -202,7 +214,7 @@ def rhs(q: torch.Tensor, alpha, dx: float, dy: float, g: float = 9.81, flux: str
         else:
             QL, QR = learned_faces(q, alpha, axis)
             okl, okr = QL[:, :1] > 0, QR[:, :1] > 0
-            nfb += int((~okl).sum() + (~okr).sum())
+            nfb = nfb + (~okl).flatten(1).sum(1) + (~okr).flatten(1).sum(1)
             QL = torch.where(okl, QL, ML)
             QR = torch.where(okr, QR, MR)
         nm, tm = (1, 2) if axis == 0 else (2, 1)
@@ -225,7 +237,9 @@ def plain_step(q, dt, dx, dy, g=9.81, flux="hlle"):
 def learned_step(params, q, dt, dx, dy, g=9.81, flux="hlle", order=1, round_bf16=True):
     """One Heun step of the learned scheme.  The network runs on the input of
     each stage.  Returns (q_next, stats) with stats = dict(fallback_faces,
-    redone = per-solve flags of steps redone with the plain scheme)."""
+    redone = per-solve flags of steps redone with the plain scheme).  Face
+    sides of the second stage are not counted for a solve whose first stage
+    was already inadmissible (its step is redone either way)."""
     P = projector(order)
     a0 = coefficients(cnn(params, q, round_bf16), P)
     L0, f0 = rhs(q, a0, dx, dy, g, flux)
@@ -241,7 +255,8 @@ def learned_step(params, q, dt, dx, dy, g=9.81, flux="hlle", order=1, round_bf16
     if bool(bad.any()):
         qp = plain_step(q, dt, dx, dy, g, flux)
         q2 = torch.where(bad[:, None, None, None], qp, q2)
-    return q2, {"fallback_faces": f0 + f1, "redone": bad}
+    nfb = f0 + torch.where(bad1, torch.zeros_like(f1), f1)
+    return q2, {"fallback_faces": int(nfb.sum()), "redone": bad}
 
 
 def rollout_loss(params, q0, targets, dt, dx, dy, scale, g=9.81, flux="hlle", round_bf16=True):

@@ -64,4 +64,56 @@ hipError_t launch_pack(const float *master, void *packed, hipStream_t st);
 hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny,
                           void *const acts[4], float *z, hipStream_t st);
 
+struct LearnedArgs;
+
+// Launch wrappers of the learned stage (learned_kernels.hip).
+struct StageBatch {
+    const float *qs, *q0;
+    float *out;
+    const float *z;
+    int B, nx, ny;
+    float rdx, rdy, g, h0;
+    float a0, a1;
+    const float *dt;
+    int *bad;                // per-solve flag bits: 1 = stage 1 failed, 2 = stage 2 failed
+    int flagbit;             // bit this stage sets; stage 2 (flagbit 2) skips counting when bit 1 is set
+    unsigned long long *nfb;
+    int *fatal;
+    Proj pr;
+};
+hipError_t learned_stage(int mode, int flux, const StageBatch &sb, hipStream_t st);
+hipError_t launch_commit(float *q, const float *s2, const int *bad, size_t per_solve, int B, hipStream_t st);
+hipError_t launch_finish(int *bad, unsigned long long *redone, int B, const float *dt, double *t, long long *steps,
+                         hipStream_t st);
+
+// Reverse pass of one learned stage (adjoint_kernels.hip): writes
+// gqs = (accumulate ? gqs : 0) + a1*gout + (FV part of the adjoint), and gz,
+// the adjoint of the raw coefficients z of this stage.
+struct AdjStage {
+    const float *qs, *z, *gout;
+    float a1, dt;
+    int B, nx, ny;
+    float rdx, rdy, g, h0;
+    Proj pr;
+    const int *plain;  // per solve: the step ran the plain scheme (or NULL)
+    float *contrib;    // scratch [2][B][ny][nx][18]
+    float *gz;         // [B][ny][nx][72]
+    float *gqs;
+    int accumulate;
+};
+hipError_t launch_adjoint(int flux, const AdjStage &s, hipStream_t st);
+
+// Backward of the network for B solves: adds d loss / d theta into grads
+// (master layout, FP32) and d loss / d q into dq ([B][3][ny][nx], FP32),
+// given gz = d loss / d z and the activations saved by the forward.
+size_t backward_scratch_bytes(int B, int nx, int ny);
+hipError_t launch_backward(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny,
+                           void *const acts[4], const float *gz, float *dq, float *grads, void *scratch,
+                           hipStream_t st);
+
+// Projector onto the null space of the moment conditions of the given order
+// (exactness for cell averages of polynomials of degree <= order) and Fromm's
+// base stencils.
+Proj make_projection(int order);
+
 }  // namespace cnn

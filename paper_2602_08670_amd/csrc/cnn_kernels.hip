@@ -234,3 +234,291 @@ hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, i
 }
 
 }  // namespace cnn
+
+// ================================================================ backward
+namespace cnn {
+
+// gz [p][72] FP32 -> dz [p][96] BF16 (zero padded K for the 3 K blocks of
+// the layer-4 input-gradient convolution).
+__global__ void dz_prep_kernel(const float *gz, bf16 *dz, long npix)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < npix * 96; i += (long)gridDim.x * blockDim.x) {
+        long p = i / 96;
+        int c = (int)(i - p * 96);
+        dz[i] = (bf16)(c < 72 ? gz[p * 72 + c] : 0.0f);
+    }
+}
+
+// Network input as the forward rounds it: x0 = bf16((q - mean) * inv_std),
+// NHWC with 16 channels (3 used) for the layer-0 weight gradient.
+__global__ void x0_kernel(const float *q, bf16 *x0, int B, int H, int W, Norm nrm)
+{
+    const long hw = (long)H * W, npix = (long)B * hw;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < npix * 16; i += (long)gridDim.x * blockDim.x) {
+        long p = i / 16;
+        int c = (int)(i - p * 16);
+        long b = p / hw, r = p - b * hw;
+        float v = c < 3 ? (q[(b * 3 + c) * hw + r] - nrm.mean[c]) * nrm.inv_std[c] : 0.0f;
+        x0[i] = (bf16)v;
+    }
+}
+
+// Input gradient of a convolution: dIn[p] = sum_t Wt[t] G[p + d_t] with the
+// transposed, tap-flipped weights (same implicit-GEMM layout as the forward).
+// EPI 0: hidden layer, multiply by the ReLU mask of the previous activation
+//        (act > 0 <=> pre-activation > 0) and store BF16 [p][32];
+// EPI 1: network input, add dq[c] += dx0[c] * inv_std[c] into the FP32
+//        planar state gradient.
+template <int KB, int NT, int EPI>
+__global__ __launch_bounds__(256) void conv_dgrad_kernel(const bf16 *G, const bf16 *wt, const bf16 *act_prev,
+                                                         bf16 *out, float *dq, int B, int H, int W, Norm nrm)
+{
+    constexpr int CG = KB * 32;
+    constexpr int WEL = 9 * NT * 16 * CG;
+    __shared__ bf16x8 s_w[WEL / 8];
+    const bf16x8 *gw = (const bf16x8 *)wt;
+    for (int i = threadIdx.x; i < WEL / 8; i += 256) s_w[i] = gw[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, px = lane & 15;
+    const long npix = (long)B * H * W;
+    const long p0 = ((long)blockIdx.x * 4 + wave) * 16;
+    if (p0 >= npix) return;
+    const long p = p0 + px;
+    const int hw = H * W;
+    const int b = (int)(p / hw);
+    const int rem = (int)(p - (long)b * hw);
+    const int y = rem / W, x = rem - y * W;
+    floatx4 acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bf16 *gb = G + (size_t)b * hw * CG;
+#pragma unroll
+    for (int tap = 0; tap < 9; tap++) {
+        int yy = wrap(y + tap / 3 - 1, H), xx = wrap(x + tap % 3 - 1, W);
+        const bf16 *src = gb + (size_t)(yy * W + xx) * CG;
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            bf16x8 bx = *(const bf16x8 *)(src + kb * 32 + 8 * g);
+#pragma unroll
+            for (int t = 0; t < NT; t++)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * (CG / 8) + kb * 4 + g],
+                                                                 bx, acc[t], 0, 0, 0);
+        }
+    }
+    if (EPI == 0) {
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            const int c0 = 16 * t + 4 * g;
+            bf16x4 m = *(const bf16x4 *)(act_prev + (size_t)p * 32 + c0);
+            bf16x4 o;
+#pragma unroll
+            for (int i = 0; i < 4; i++) o[i] = (bf16)((float)m[i] > 0.0f ? acc[t][i] : 0.0f);
+            *(bf16x4 *)(out + (size_t)p * 32 + c0) = o;
+        }
+    } else if (g == 0) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) dq[((size_t)b * 3 + c) * hw + rem] += acc[0][c] * nrm.inv_std[c];
+    }
+}
+
+// Weight and bias gradient of a convolution over a chunk of pixels:
+//   dW[t][co][ci] += sum_p G[p][co] In[p + d_t][ci],  db[co] += sum_p G[p][co].
+// MFMA with K = pixels: both operands are staged transposed in LDS per 64
+// pixels (rows = channels, 64 pixels contiguous), so a fragment is one
+// 16-byte LDS read.  Each block writes its partial sums; a fixed-order
+// reduction adds the partials of all blocks.
+template <int CG, int CO_T, int CI>
+__global__ __launch_bounds__(256) void wgrad_kernel(const bf16 *G, const bf16 *In, int B, int H, int W, int ppb,
+                                                    float *partial)
+{
+    constexpr int CI_T = CI / 16;
+    constexpr int NCO = CO_T * 16;
+    constexpr int NTILE = CO_T * CI_T;
+    constexpr int TPW = (NTILE + 3) / 4;
+    constexpr int LD = 72;  // row stride in BF16 (64 pixels + pad, 16-byte multiple)
+    __shared__ bf16 sG[NCO * LD];
+    __shared__ bf16 sI[CI * LD];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    const long npix = (long)B * H * W;
+    const int hw = H * W;
+    floatx4 acc[TPW][9];
+#pragma unroll
+    for (int j = 0; j < TPW; j++)
+#pragma unroll
+        for (int t = 0; t < 9; t++) acc[j][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+    float bacc = 0.0f;
+    const long pbeg = (long)blockIdx.x * ppb;
+    for (int sub = 0; sub < ppb; sub += 64) {
+        const long base = pbeg + sub;
+        if (base >= npix) break;
+        __syncthreads();
+        // G chunk, transposed: sG[co][px]
+        for (int i = tid; i < 64 * (NCO / 8); i += 256) {
+            int pxl = i / (NCO / 8), c8 = i - pxl * (NCO / 8);
+            long p = base + pxl;
+            bf16x8 v;
+            if (p < npix) v = *(const bf16x8 *)(G + (size_t)p * CG + c8 * 8);
+            else
+                for (int e = 0; e < 8; e++) v[e] = (bf16)0.0f;
+#pragma unroll
+            for (int e = 0; e < 8; e++) sG[(c8 * 8 + e) * LD + pxl] = v[e];
+        }
+        __syncthreads();
+        if (tid < NCO) {
+            float s = 0.0f;
+            for (int k = 0; k < 64; k++) s += (float)sG[tid * LD + k];
+            bacc += s;
+        }
+        for (int tap = 0; tap < 9; tap++) {
+            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+            __syncthreads();
+            for (int i = tid; i < 64 * (CI / 8); i += 256) {
+                int pxl = i / (CI / 8), c8 = i - pxl * (CI / 8);
+                long p = base + pxl;
+                bf16x8 v;
+                if (p < npix) {
+                    int b = (int)(p / hw), rem = (int)(p - (long)b * hw);
+                    int y = rem / W, x = rem - y * W;
+                    int yy = wrap(y + dy, H), xx = wrap(x + dx, W);
+                    v = *(const bf16x8 *)(In + ((size_t)b * hw + yy * W + xx) * CI + c8 * 8);
+                } else {
+                    for (int e = 0; e < 8; e++) v[e] = (bf16)0.0f;
+                }
+#pragma unroll
+                for (int e = 0; e < 8; e++) sI[(c8 * 8 + e) * LD + pxl] = v[e];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int j = 0; j < TPW; j++) {
+                const int id = wave + 4 * j;
+                if (id < NTILE) {
+                    const int cot = id / CI_T, cit = id - cot * CI_T;
+#pragma unroll
+                    for (int ks = 0; ks < 2; ks++) {
+                        bf16x8 af = *(const bf16x8 *)(sG + (cot * 16 + r16) * LD + ks * 32 + 8 * g);
+                        bf16x8 bf = *(const bf16x8 *)(sI + (cit * 16 + r16) * LD + ks * 32 + 8 * g);
+                        acc[j][tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[j][tap], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    // partial layout: [9][NCO][CI] then [NCO] bias
+    float *pp = partial + (size_t)blockIdx.x * (9 * NCO * CI + NCO);
+#pragma unroll
+    for (int j = 0; j < TPW; j++) {
+        const int id = wave + 4 * j;
+        if (id < NTILE) {
+            const int cot = id / CI_T, cit = id - cot * CI_T;
+#pragma unroll
+            for (int tap = 0; tap < 9; tap++)
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    pp[((size_t)tap * NCO + cot * 16 + 4 * g + i) * CI + cit * 16 + r16] = acc[j][tap][i];
+        }
+    }
+    if (tid < NCO) pp[9 * NCO * CI + tid] = bacc;
+}
+
+// grads[W_l, b_l] += sum over blocks (in block order) of the partials.
+__global__ void wgrad_reduce_kernel(const float *partial, int nblocks, int NCO, int CI, int co_real, int ci_real,
+                                    int woff, int boff, float *grads)
+{
+    const int per = 9 * NCO * CI + NCO;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < per; e += gridDim.x * blockDim.x) {
+        int co, ci = 0, tap = 0;
+        bool isb = e >= 9 * NCO * CI;
+        if (isb) {
+            co = e - 9 * NCO * CI;
+        } else {
+            tap = e / (NCO * CI);
+            int r = e - tap * NCO * CI;
+            co = r / CI;
+            ci = r - co * CI;
+        }
+        if (co >= co_real || ci >= ci_real) continue;
+        float s = 0.0f;
+        for (int k = 0; k < nblocks; k++) s += partial[(size_t)k * per + e];
+        if (isb) grads[boff + co] += s;
+        else grads[woff + (co * ci_real + ci) * 9 + tap] += s;
+    }
+}
+
+static int ppb_for(long npix)
+{
+    long ppb = (npix + 255) / 256;
+    ppb = (ppb + 63) / 64 * 64;
+    return (int)(ppb < 64 ? 64 : ppb);
+}
+
+size_t backward_scratch_bytes(int B, int nx, int ny)
+{
+    long npix = (long)B * nx * ny;
+    int ppb = ppb_for(npix);
+    long nblocks = (npix + ppb - 1) / ppb;
+    size_t part = (size_t)nblocks * (9 * 80 * 32 + 80) * 4;
+    return al256(npix * 96 * 2) + 2 * al256(npix * 32 * 2) + al256(npix * 16 * 2) + al256(part);
+}
+
+template <int CG, int CO_T, int CI>
+static void wgrad(const bf16 *G, const bf16 *In, int B, int H, int W, float *partial, int co_real, int ci_real,
+                  int woff, int boff, float *grads, hipStream_t st)
+{
+    long npix = (long)B * H * W;
+    int ppb = ppb_for(npix);
+    int nblocks = (int)((npix + ppb - 1) / ppb);
+    hipLaunchKernelGGL((wgrad_kernel<CG, CO_T, CI>), dim3(nblocks), dim3(256), 0, st, G, In, B, H, W, ppb, partial);
+    int per = 9 * CO_T * 16 * CI + CO_T * 16;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((per + 255) / 256), dim3(256), 0, st, (const float *)partial, nblocks,
+                       CO_T * 16, CI, co_real, ci_real, woff, boff, grads);
+}
+
+hipError_t launch_backward(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny,
+                           void *const acts[4], const float *gz, float *dq, float *grads, void *scratch,
+                           hipStream_t st)
+{
+    const Packed pk = packed_layout();
+    const MasterLayout ml = master_layout();
+    const char *P = (const char *)packed;
+    const long npix = (long)B * nx * ny;
+    char *sc = (char *)scratch;
+    bf16 *dz = (bf16 *)sc;
+    sc += al256(npix * 96 * 2);
+    bf16 *dA = (bf16 *)sc;
+    sc += al256(npix * 32 * 2);
+    bf16 *dB = (bf16 *)sc;
+    sc += al256(npix * 32 * 2);
+    bf16 *x0 = (bf16 *)sc;
+    sc += al256(npix * 16 * 2);
+    float *partial = (float *)sc;
+    const bf16 *a[4] = {(const bf16 *)acts[0], (const bf16 *)acts[1], (const bf16 *)acts[2], (const bf16 *)acts[3]};
+    unsigned eg = (unsigned)((npix * 96 + 255) / 256);
+    if (eg > 8192) eg = 8192;
+    dim3 cg((unsigned)((npix + 63) / 64)), blk(256);
+
+    hipLaunchKernelGGL(dz_prep_kernel, dim3(eg), blk, 0, st, gz, dz, npix);
+    // layer 4: 32 -> 72
+    wgrad<96, 5, 32>(dz, a[3], B, ny, nx, partial, 72, 32, ml.w[4], ml.b[4], grads, st);
+    hipLaunchKernelGGL((conv_dgrad_kernel<3, 2, 0>), cg, blk, 0, st, (const bf16 *)dz,
+                       (const bf16 *)(P + pk.wt[4]), a[3], dA, (float *)nullptr, B, ny, nx, nrm);
+    // layers 3, 2, 1: 32 -> 32
+    bf16 *cur = dA, *nxt = dB;
+    for (int l = 3; l >= 1; l--) {
+        wgrad<32, 2, 32>(cur, a[l - 1], B, ny, nx, partial, 32, 32, ml.w[l], ml.b[l], grads, st);
+        hipLaunchKernelGGL((conv_dgrad_kernel<1, 2, 0>), cg, blk, 0, st, (const bf16 *)cur,
+                           (const bf16 *)(P + pk.wt[l]), a[l - 1], nxt, (float *)nullptr, B, ny, nx, nrm);
+        bf16 *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    // layer 0: 3 -> 32 (input rebuilt as the forward rounds it)
+    hipLaunchKernelGGL(x0_kernel, dim3(eg), blk, 0, st, q, x0, B, ny, nx, nrm);
+    wgrad<32, 2, 16>(cur, x0, B, ny, nx, partial, 32, 3, ml.w[0], ml.b[0], grads, st);
+    hipLaunchKernelGGL((conv_dgrad_kernel<1, 1, 1>), cg, blk, 0, st, (const bf16 *)cur,
+                       (const bf16 *)(P + pk.wt[0]), (const bf16 *)nullptr, (bf16 *)nullptr, dq, B, ny, nx, nrm);
+    return hipGetLastError();
+}
+
+}  // namespace cnn

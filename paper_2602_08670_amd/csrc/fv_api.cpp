@@ -12,6 +12,7 @@
 #include <string>
 
 #include "../../include/fv.h"
+#include "cnn_internal.hpp"
 #include "fv_internal.hpp"
 
 namespace {
@@ -38,7 +39,10 @@ fv_status hip_fail(hipError_t e, const char *what)
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
-    size_t ctl, rates, totals_out, partials, s1, s2, total;
+    size_t ctl, rates, totals_out, partials, s1, s2;
+    // buffers of the learned step (cfg.learned == 1)
+    size_t act0, act1, z, s2l, small;
+    size_t total;
 };
 
 int nvar_of(const fv_config *c) { return c->eqn == FV_EULER ? 4 : 3; }
@@ -57,7 +61,7 @@ fv_status validate(const fv_config *c)
     if (c->flux < FV_FLUX_HLLE || c->flux > FV_FLUX_ROE) return fail(FV_E_INVALID, "flux %d", c->flux);
     if (c->recon != FV_RECON_MINMOD && c->recon != FV_RECON_FIRST) return fail(FV_E_INVALID, "recon %d", c->recon);
     if (c->rk_stages < 1 || c->rk_stages > 3) return fail(FV_E_INVALID, "rk_stages %d", c->rk_stages);
-    if (c->reserved0 != 0) return fail(FV_E_INVALID, "reserved0 must be 0");
+    if (c->learned != 0 && c->learned != 1) return fail(FV_E_INVALID, "learned %d", c->learned);
     if (!(c->lx > 0) || !(c->ly > 0)) return fail(FV_E_INVALID, "domain size");
     if (!(c->dt_fixed > 0) && !(c->cfl > 0 && c->cfl <= 1)) return fail(FV_E_INVALID, "cfl %g not in (0,1]", c->cfl);
     if (c->eqn == FV_SWE && !(c->g > 0)) return fail(FV_E_INVALID, "g %g", c->g);
@@ -77,7 +81,19 @@ Layout layout_of(const fv_config *c)
     L.partials = L.totals_out + 256;
     L.s1 = L.partials + align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * sizeof(double));
     L.s2 = L.s1 + st;
-    L.total = L.s2 + (c->rk_stages == 3 ? st : 0);
+    size_t end = L.s2 + (c->rk_stages == 3 ? st : 0);
+    if (c->learned) {
+        size_t npix = (size_t)c->nx * c->ny;
+        L.act0 = end;
+        L.act1 = L.act0 + align256(npix * cnn::CH * 2);
+        L.z = L.act1 + align256(npix * cnn::CH * 2);
+        L.s2l = L.z + align256(npix * cnn::COUT * 4);
+        L.small = L.s2l + st;
+        end = L.small + 256;
+    } else {
+        L.act0 = L.act1 = L.z = L.s2l = L.small = 0;
+    }
+    L.total = end;
     return L;
 }
 
@@ -213,6 +229,18 @@ fv_status fv_init(const fv_config *cfg, void *q, const void *bathy, void *worksp
         delete s;
         return hip_fail(e, "control block upload");
     }
+    if (cfg->learned) {
+        // learned-step counters: dt (float), bad, pad, nfb, redone
+        char small[256];
+        std::memset(small, 0, sizeof small);
+        float dtf = (float)cfg->dt_fixed;
+        std::memcpy(small, &dtf, sizeof dtf);
+        e = hipMemcpyAsync(s->ws + L.small, small, sizeof small, hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) {
+            delete s;
+            return hip_fail(e, "learned counters upload");
+        }
+    }
     rc = init_rate(s);
     if (rc == FV_OK) rc = sync_and_check(s);
     if (rc == FV_OK && cfg->eqn == FV_SWE && cfg->h_ref > 0) {
@@ -337,5 +365,163 @@ void fv_destroy(fv_solver *s)
 }
 
 const char *fv_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"
+
+// ------------------------------------------------------------ learned path
+
+struct fv_model {
+    fv_model_desc desc;
+    const float *params;
+    void *packed;
+    hipStream_t stream;
+    cnn::Norm nrm;
+    cnn::Proj pr;
+};
+
+namespace {
+
+// offsets inside the 256-byte block of learned counters
+constexpr size_t SM_DT = 0, SM_BAD = 8, SM_NFB = 16, SM_REDONE = 24;
+
+}  // namespace
+
+extern "C" {
+
+size_t fv_model_param_count(void) { return cnn::NPARAM; }
+
+size_t fv_model_workspace_bytes(const fv_model_desc *desc)
+{
+    if (!desc || desc->struct_size != sizeof(fv_model_desc) || desc->hidden != 32) return 0;
+    return cnn::packed_layout().bytes;
+}
+
+fv_status fv_model_create(const fv_model_desc *desc, const float *params, void *workspace, size_t workspace_bytes,
+                          void *stream, fv_model **out)
+{
+    if (!out) return fail(FV_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!desc || desc->struct_size != sizeof(fv_model_desc)) return fail(FV_E_INVALID, "model desc struct_size");
+    if (desc->hidden != 32) return fail(FV_E_UNSUPPORTED, "hidden width %d (this build: 32)", desc->hidden);
+    if (desc->order < 0 || desc->order > 1) return fail(FV_E_INVALID, "constraint order %d", desc->order);
+    if (desc->reserved0 != 0) return fail(FV_E_INVALID, "reserved0 must be 0");
+    if (!params || !workspace) return fail(FV_E_INVALID, "params or workspace is NULL");
+    if (((uintptr_t)workspace & 255) != 0) return fail(FV_E_INVALID, "workspace must be 256-byte aligned");
+    if (workspace_bytes < cnn::packed_layout().bytes)
+        return fail(FV_E_NOMEM, "model workspace %zu < %zu", workspace_bytes, cnn::packed_layout().bytes);
+    fv_model *m = new fv_model();
+    m->desc = *desc;
+    m->params = params;
+    m->packed = workspace;
+    m->stream = (hipStream_t)stream;
+    for (int c = 0; c < 3; c++) {
+        m->nrm.mean[c] = desc->mean[c];
+        m->nrm.inv_std[c] = desc->inv_std[c];
+    }
+    m->pr = cnn::make_projection(desc->order);
+    hipError_t e = cnn::launch_pack(params, workspace, m->stream);
+    if (e != hipSuccess) {
+        delete m;
+        return hip_fail(e, "pack kernel");
+    }
+    *out = m;
+    return FV_OK;
+}
+
+fv_status fv_model_update(fv_model *m)
+{
+    if (!m) return fail(FV_E_INVALID, "model is NULL");
+    hipError_t e = cnn::launch_pack(m->params, m->packed, m->stream);
+    return e == hipSuccess ? FV_OK : hip_fail(e, "pack kernel");
+}
+
+void fv_model_destroy(fv_model *m) { delete m; }
+
+size_t fv_model_forward_scratch_bytes(int B, int nx, int ny)
+{
+    if (B <= 0 || nx <= 0 || ny <= 0) return 0;
+    return 2 * align256((size_t)B * nx * ny * cnn::CH * 2);
+}
+
+fv_status fv_model_forward(const fv_model *m, const float *q, int B, int nx, int ny, float *z, void *scratch,
+                           size_t scratch_bytes)
+{
+    if (!m || !q || !z || !scratch) return fail(FV_E_INVALID, "NULL argument");
+    if (B <= 0 || nx < 16 || ny < 2 || nx % 16 || ((int64_t)nx * ny) % 64)
+        return fail(FV_E_UNSUPPORTED, "network grids need nx %% 16 == 0 and nx*ny %% 64 == 0 (got %dx%d)", nx, ny);
+    if (((uintptr_t)scratch & 255) != 0) return fail(FV_E_INVALID, "scratch must be 256-byte aligned");
+    size_t need = fv_model_forward_scratch_bytes(B, nx, ny);
+    if (scratch_bytes < need) return fail(FV_E_NOMEM, "scratch %zu < %zu", scratch_bytes, need);
+    char *sc = (char *)scratch;
+    size_t half = need / 2;
+    void *acts[4] = {sc, sc + half, sc, sc + half};
+    hipError_t e = cnn::launch_forward(m->packed, m->nrm, q, B, nx, ny, acts, z, m->stream);
+    return e == hipSuccess ? FV_OK : hip_fail(e, "network launch");
+}
+
+fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats)
+{
+    if (!s || !m) return fail(FV_E_INVALID, "NULL argument");
+    const fv_config &c = s->cfg;
+    if (c.eqn != FV_SWE || c.prec != FV_F32 || c.bc_x != FV_BC_PERIODIC || c.bc_y != FV_BC_PERIODIC || s->bed ||
+        c.rk_stages != 2 || !(c.dt_fixed > 0) || !c.learned || c.nx % 16 || ((int64_t)c.nx * c.ny) % 64 ||
+        (c.flux != FV_FLUX_HLLE && c.flux != FV_FLUX_RUSANOV))
+        return fail(FV_E_UNSUPPORTED,
+                    "learned steps need SWE, FP32, periodic, flat bed, Heun, dt_fixed > 0, learned = 1, "
+                    "HLLE or Rusanov, nx %% 16 == 0 and nx*ny %% 64 == 0");
+    if (nsteps < 0) return fail(FV_E_INVALID, "nsteps < 0");
+    char *ws = s->ws;
+    const Layout &L = s->L;
+    float *q = (float *)s->q;
+    float *S1 = (float *)(ws + L.s1), *S2 = (float *)(ws + L.s2l), *z = (float *)(ws + L.z);
+    char *sm = ws + L.small;
+    void *acts[4] = {ws + L.act0, ws + L.act1, ws + L.act0, ws + L.act1};
+    cnn::StageBatch sb;
+    sb.B = 1;
+    sb.nx = c.nx;
+    sb.ny = c.ny;
+    sb.rdx = (float)s->d.rdx;
+    sb.rdy = (float)s->d.rdy;
+    sb.g = (float)c.g;
+    sb.h0 = (float)s->d.h0;
+    sb.dt = (const float *)(sm + SM_DT);
+    sb.bad = (int *)(sm + SM_BAD);
+    sb.nfb = (unsigned long long *)(sm + SM_NFB);
+    sb.fatal = &s->ctl()->bad;
+    sb.pr = m->pr;
+    sb.z = z;
+    const int fl = c.flux == FV_FLUX_RUSANOV ? 1 : 0;  // kernel flux ids: 0 HLLE, 1 Rusanov
+    const size_t per = (size_t)3 * c.nx * c.ny;
+    hipError_t e = hipSuccess;
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; k++) {
+        // stage 1: coefficients of q, q1 = q + dt L(q)
+        e = cnn::launch_forward(m->packed, m->nrm, q, 1, c.nx, c.ny, acts, z, s->stream);
+        sb.qs = q; sb.q0 = q; sb.out = S1; sb.a0 = 0.f; sb.a1 = 1.f; sb.flagbit = 1;
+        if (e == hipSuccess) e = cnn::learned_stage(0, fl, sb, s->stream);
+        // stage 2: coefficients of q1, q2 = q/2 + (q1 + dt L(q1))/2
+        if (e == hipSuccess) e = cnn::launch_forward(m->packed, m->nrm, S1, 1, c.nx, c.ny, acts, z, s->stream);
+        sb.qs = S1; sb.q0 = q; sb.out = S2; sb.a0 = 0.5f; sb.a1 = 0.5f; sb.flagbit = 2;
+        if (e == hipSuccess) e = cnn::learned_stage(0, fl, sb, s->stream);
+        // admissible: take the learned result; otherwise redo with the plain scheme
+        if (e == hipSuccess) e = cnn::launch_commit(q, S2, sb.bad, per, 1, s->stream);
+        sb.qs = q; sb.q0 = q; sb.out = S1; sb.a0 = 0.f; sb.a1 = 1.f;
+        if (e == hipSuccess) e = cnn::learned_stage(1, fl, sb, s->stream);
+        sb.qs = S1; sb.q0 = q; sb.out = q; sb.a0 = 0.5f; sb.a1 = 0.5f;
+        if (e == hipSuccess) e = cnn::learned_stage(1, fl, sb, s->stream);
+        if (e == hipSuccess)
+            e = cnn::launch_finish(sb.bad, (unsigned long long *)(sm + SM_REDONE), 1, sb.dt, &s->ctl()->t,
+                                   &s->ctl()->step, s->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "learned step launch");
+    if (stats) {
+        e = hipStreamSynchronize(s->stream);
+        unsigned long long cnt[2];
+        if (e == hipSuccess) e = hipMemcpy(cnt, sm + SM_NFB, sizeof cnt, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "read learned counters");
+        stats->fallback_faces = (int64_t)cnt[0];
+        stats->redone_steps = (int64_t)cnt[1];
+    }
+    return FV_OK;
+}
 
 }  // extern "C"

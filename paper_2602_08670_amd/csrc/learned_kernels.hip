@@ -1,0 +1,328 @@
+// Learned-coefficient finite-volume stage for batches of periodic
+// shallow-water solves (FP32), thesis section 2.5.3, fourth approach.
+//
+// Every cell owns its +x and +y face.  For a face the kernel reads the
+// owner's 36 raw coefficients z (one axis: 2 sides x 3 variables x 6), maps
+// them onto the constraint set, alpha = alpha_base + P z (P: orthogonal
+// projector onto the null space of the moment conditions), and forms the two
+// face states as sum_k alpha_k q(i-2+k) over the six cells around the face.
+// A side whose learned depth is not positive uses its MINMOD state instead
+// (counted).  Fluxes, divergence and the Runge-Kutta combine follow the
+// classic stage kernel.  MODE 1 runs the plain MINMOD scheme only for the
+// solves whose learned step produced an inadmissible cell (the step is redone).
+#include "cnn_internal.hpp"
+#include "fv_device.hpp"
+
+namespace cnn {
+
+using fvk::Phys;
+using fvk::SweV;
+
+struct LearnedArgs {
+    const float *qs;  // stage input [B][3][ny][nx]
+    const float *q0;  // q^n, read only at the updated cell
+    float *out;
+    const float *z;   // [B][ny][nx][72]
+    int B, nx, ny;
+    float rdx, rdy;
+    Phys<float> ph;
+    float a0, a1;
+    const float *dt;         // per solve
+    int *bad;                // per solve flag bits
+    int flagbit;
+    unsigned long long *nfb; // per solve fallback face sides
+    int *fatal;              // per solve: the plain redo itself failed
+    Proj pr;
+};
+
+__device__ __forceinline__ int pwrap(int i, int n) { return ((i % n) + n) % n; }
+
+// Face states of one face from the six stencil values st[v][0..5] (cells
+// i-2..i+3 along the normal).  MODE 0: learned with fallback; MODE 1: MINMOD.
+template <int MODE>
+__device__ __forceinline__ int face_states(const float (*st)[6], const float *zc, const Proj &pr, float *QL,
+                                           float *QR)
+{
+    float ML[3], MR[3];
+#pragma unroll
+    for (int v = 0; v < 3; v++) fvk::recon_pair<float, fvk::MINMOD>(st[v][1], st[v][2], st[v][3], st[v][4], ML[v], MR[v]);
+    bool okl = ML[0] > 0.0f, okr = MR[0] > 0.0f;
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        ML[v] = okl ? ML[v] : st[v][2];
+        MR[v] = okr ? MR[v] : st[v][3];
+    }
+    if (MODE == 1) {
+#pragma unroll
+        for (int v = 0; v < 3; v++) {
+            QL[v] = ML[v];
+            QR[v] = MR[v];
+        }
+        return 0;
+    }
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+#pragma unroll
+        for (int v = 0; v < 3; v++) {
+            const float *zz = zc + (s * 3 + v) * 6;
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                float al = pr.base[s * 6 + k];
+#pragma unroll
+                for (int j = 0; j < 6; j++) al += pr.P[k * 6 + j] * zz[j];
+                acc += al * st[v][k];
+            }
+            (s == 0 ? QL : QR)[v] = acc;
+        }
+    }
+    bool ll = QL[0] > 0.0f, lr = QR[0] > 0.0f;
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        QL[v] = ll ? QL[v] : ML[v];
+        QR[v] = lr ? QR[v] : MR[v];
+    }
+    return (ll ? 0 : 1) + (lr ? 0 : 1);
+}
+
+template <int FLUX, int AXIS>
+__device__ __forceinline__ void flux3(const float *QL, const float *QR, const Phys<float> &ph, float *F)
+{
+    constexpr int NM = AXIS == 0 ? 1 : 2, TM = AXIS == 0 ? 2 : 1;
+    float il = fvk::rcp(QL[0]), ir = fvk::rcp(QR[0]);
+    SweV<float> L{QL[0], QL[NM] * il, QL[TM] * il}, R{QR[0], QR[NM] * ir, QR[TM] * ir};
+    float G[3];
+    fvk::swe_numflux<float, FLUX>(L, R, ph, G);
+    F[0] = G[0];
+    F[NM] = G[1];
+    F[TM] = G[2];
+}
+
+template <int MODE, int FLUX>
+__global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
+{
+    constexpr int TX = 64, TY = 8, HX = TX + 6, HY = TY + 6;
+    __shared__ float s_q[3][HY][HX];
+    __shared__ float s_fx[3][TY][TX + 1];
+    __shared__ float s_fy[3][TY + 1][TX];
+    __shared__ int s_cnt;
+    __shared__ int s_bad;
+
+    const int b = blockIdx.z;
+    if (MODE == 1 && a.bad[b] == 0) return;
+    const int tid = threadIdx.x;
+    const int nx = a.nx, ny = a.ny;
+    const size_t plane = (size_t)nx * ny;
+    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    const float *qs = a.qs + (size_t)b * 3 * plane;
+    const float dt = a.dt[b];
+    // stage 2 of a solve whose stage 1 failed is evaluated (its result is
+    // discarded by the redo) but its fallback faces are not counted
+    const bool count = MODE == 0 && !(a.flagbit == 2 && (a.bad[b] & 1));
+    if (tid == 0) {
+        s_cnt = 0;
+        s_bad = 0;
+    }
+    for (int k = tid; k < HY * HX; k += 256) {
+        int ly = k / HX, lx = k - ly * HX;
+        size_t idx = (size_t)pwrap(y0 - 3 + ly, ny) * nx + pwrap(x0 - 3 + lx, nx);
+#pragma unroll
+        for (int v = 0; v < 3; v++) s_q[v][ly][lx] = qs[v * plane + idx];
+    }
+    __syncthreads();
+
+    int nfb = 0;
+    // x faces: owner cell (x0 - 1 + fi, y0 + fj) <-> halo column fi + 2
+    for (int f = tid; f < TY * (TX + 1); f += 256) {
+        int fj = f / (TX + 1), fi = f - fj * (TX + 1);
+        float st[3][6];
+#pragma unroll
+        for (int v = 0; v < 3; v++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) st[v][k] = s_q[v][fj + 3][fi + k];
+        int gy = y0 + fj < ny ? y0 + fj : ny - 1;
+        const float *zc = a.z + (((size_t)b * ny + gy) * nx + pwrap(x0 - 1 + fi, nx)) * 72;
+        float QL[3], QR[3], F[3];
+        int c = face_states<MODE>(st, zc, a.pr, QL, QR);
+        // each face is counted once: as the left face of a cell of this tile
+        if (fi < TX && x0 + fi < nx && y0 + fj < ny) nfb += c;
+        flux3<FLUX, 0>(QL, QR, a.ph, F);
+#pragma unroll
+        for (int v = 0; v < 3; v++) s_fx[v][fj][fi] = F[v];
+    }
+    // y faces: owner cell (x0 + fi, y0 - 1 + fj) <-> halo row fj + 2
+    for (int f = tid; f < (TY + 1) * TX; f += 256) {
+        int fj = f / TX, fi = f - fj * TX;
+        float st[3][6];
+#pragma unroll
+        for (int v = 0; v < 3; v++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) st[v][k] = s_q[v][fj + k][fi + 3];
+        int gx = x0 + fi < nx ? x0 + fi : nx - 1;
+        const float *zc = a.z + (((size_t)b * ny + pwrap(y0 - 1 + fj, ny)) * nx + gx) * 72 + 36;
+        float QL[3], QR[3], F[3];
+        int c = face_states<MODE>(st, zc, a.pr, QL, QR);
+        if (fj < TY && y0 + fj < ny && x0 + fi < nx) nfb += c;
+        flux3<FLUX, 1>(QL, QR, a.ph, F);
+#pragma unroll
+        for (int v = 0; v < 3; v++) s_fy[v][fj][fi] = F[v];
+    }
+    __syncthreads();
+
+    bool bad = false;
+    for (int k = tid; k < TX * TY; k += 256) {
+        int cy = k / TX, cx = k - cy * TX;
+        int gx = x0 + cx, gy = y0 + cy;
+        if (gx >= nx || gy >= ny) continue;
+        size_t idx = (size_t)b * 3 * plane + (size_t)gy * nx + gx;
+        float qn[3];
+#pragma unroll
+        for (int v = 0; v < 3; v++) {
+            float L = -(s_fx[v][cy][cx + 1] - s_fx[v][cy][cx]) * a.rdx - (s_fy[v][cy + 1][cx] - s_fy[v][cy][cx]) * a.rdy;
+            float o = a.a1 * (s_q[v][cy + 3][cx + 3] + dt * L);
+            if (a.a0 != 0.0f) o = a.a0 * a.q0[idx + v * plane] + o;
+            a.out[idx + v * plane] = o;
+            qn[v] = o;
+        }
+        bool ok = qn[0] > 0.0f && __builtin_isfinite(qn[0]) && __builtin_isfinite(qn[1]) && __builtin_isfinite(qn[2]);
+        bad = bad || !ok;
+    }
+    if (count && nfb) atomicAdd(&s_cnt, nfb);
+    if (bad) s_bad = 1;
+    __syncthreads();
+    if (tid == 0) {
+        if (MODE == 0 && s_cnt) atomicAdd(&a.nfb[b], (unsigned long long)s_cnt);
+        if (s_bad) {
+            if (MODE == 0) atomicOr(&a.bad[b], a.flagbit);
+            else atomicExch(&a.fatal[b], 1);
+        }
+    }
+}
+
+// q[b] <- S2[b] for the solves whose learned step was admissible.
+__global__ void commit_kernel(float *q, const float *s2, const int *bad, size_t per_solve, int B)
+{
+    size_t n = per_solve * B;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        int b = (int)(i / per_solve);
+        if (!bad[b]) q[i] = s2[i];
+    }
+}
+
+// End of step: count redone steps, clear the per-step flags, advance time.
+__global__ void finish_kernel(int *bad, unsigned long long *redone, int B, const float *dt, double *t,
+                              long long *steps)
+{
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < B) {
+        if (bad[b]) redone[b] += 1;
+        bad[b] = 0;
+    }
+    if (b == 0 && t) {
+        *t += (double)dt[0];
+        *steps += 1;
+    }
+}
+
+hipError_t learned_stage(int mode, int flux, const StageBatch &sb, hipStream_t st)
+{
+    LearnedArgs a;
+    a.qs = sb.qs;
+    a.q0 = sb.q0;
+    a.out = sb.out;
+    a.z = sb.z;
+    a.B = sb.B;
+    a.nx = sb.nx;
+    a.ny = sb.ny;
+    a.rdx = sb.rdx;
+    a.rdy = sb.rdy;
+    a.ph.g = sb.g;
+    a.ph.sqg = __builtin_sqrtf(sb.g);
+    a.ph.gamma = 1.4f;
+    a.ph.h0 = sb.h0;
+    a.a0 = sb.a0;
+    a.a1 = sb.a1;
+    a.dt = sb.dt;
+    a.bad = sb.bad;
+    a.flagbit = sb.flagbit;
+    a.nfb = sb.nfb;
+    a.fatal = sb.fatal;
+    a.pr = sb.pr;
+    dim3 grid((a.nx + 63) / 64, (a.ny + 7) / 8, a.B), blk(256);
+    if (mode == 0) {
+        if (flux == fvk::RUSANOV) hipLaunchKernelGGL((learned_stage_kernel<0, fvk::RUSANOV>), grid, blk, 0, st, a);
+        else hipLaunchKernelGGL((learned_stage_kernel<0, fvk::HLLE>), grid, blk, 0, st, a);
+    } else {
+        if (flux == fvk::RUSANOV) hipLaunchKernelGGL((learned_stage_kernel<1, fvk::RUSANOV>), grid, blk, 0, st, a);
+        else hipLaunchKernelGGL((learned_stage_kernel<1, fvk::HLLE>), grid, blk, 0, st, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_commit(float *q, const float *s2, const int *bad, size_t per_solve, int B, hipStream_t st)
+{
+    size_t n = per_solve * B;
+    unsigned blocks = (unsigned)((n + 255) / 256);
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(commit_kernel, dim3(blocks), dim3(256), 0, st, q, s2, bad, per_solve, B);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(int *bad, unsigned long long *redone, int B, const float *dt, double *t, long long *steps,
+                         hipStream_t st)
+{
+    hipLaunchKernelGGL(finish_kernel, dim3((B + 255) / 256), dim3(256), 0, st, bad, redone, B, dt, t, steps);
+    return hipGetLastError();
+}
+
+Proj make_projection(int order)
+{
+    // moment matrix A (order+1) x 6: cell averages of x^p over unit cells
+    // centred at -2.5 .. 2.5 (the six cells around the face)
+    const int m = order + 1;
+    double A[3][6];
+    for (int p = 0; p < m; p++)
+        for (int k = 0; k < 6; k++) {
+            double xc = -2.5 + k;
+            A[p][k] = (__builtin_pow(xc + 0.5, p + 1) - __builtin_pow(xc - 0.5, p + 1)) / (p + 1);
+        }
+    // X = (A A^T)^-1 A by Gauss-Jordan on [A A^T | A]
+    double M[3][9];
+    for (int i = 0; i < m; i++) {
+        for (int j = 0; j < m; j++) {
+            double s = 0;
+            for (int k = 0; k < 6; k++) s += A[i][k] * A[j][k];
+            M[i][j] = s;
+        }
+        for (int k = 0; k < 6; k++) M[i][m + k] = A[i][k];
+    }
+    for (int c = 0; c < m; c++) {
+        int piv = c;
+        for (int r = c + 1; r < m; r++)
+            if (__builtin_fabs(M[r][c]) > __builtin_fabs(M[piv][c])) piv = r;
+        for (int j = 0; j < m + 6; j++) {
+            double t = M[c][j];
+            M[c][j] = M[piv][j];
+            M[piv][j] = t;
+        }
+        double d = M[c][c];
+        for (int j = 0; j < m + 6; j++) M[c][j] /= d;
+        for (int r = 0; r < m; r++)
+            if (r != c) {
+                double f = M[r][c];
+                for (int j = 0; j < m + 6; j++) M[r][j] -= f * M[c][j];
+            }
+    }
+    Proj pr;
+    for (int i = 0; i < 6; i++)
+        for (int j = 0; j < 6; j++) {
+            double s = (i == j) ? 1.0 : 0.0;
+            for (int p = 0; p < m; p++) s -= A[p][i] * M[p][m + j];
+            pr.P[i * 6 + j] = (float)s;
+        }
+    const float fromm[12] = {0.f, -0.25f, 1.f, 0.25f, 0.f, 0.f, 0.f, 0.f, 0.25f, 1.f, -0.25f, 0.f};
+    for (int i = 0; i < 12; i++) pr.base[i] = fromm[i];
+    return pr;
+}
+
+}  // namespace cnn

@@ -33,16 +33,37 @@ class fv_config(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("eqn", ctypes.c_int32), ("prec", ctypes.c_int32),
                 ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("bc_x", ctypes.c_int32),
                 ("bc_y", ctypes.c_int32), ("flux", ctypes.c_int32), ("recon", ctypes.c_int32),
-                ("rk_stages", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("lx", ctypes.c_double),
+                ("rk_stages", ctypes.c_int32), ("learned", ctypes.c_int32), ("lx", ctypes.c_double),
                 ("ly", ctypes.c_double), ("cfl", ctypes.c_double), ("dt_fixed", ctypes.c_double),
                 ("g", ctypes.c_double), ("gamma", ctypes.c_double), ("h_ref", ctypes.c_double)]
 
 
 def make_config(eqn=FV_SWE, prec=FV_F32, nx=64, ny=64, bc_x=FV_BC_PERIODIC, bc_y=FV_BC_PERIODIC,
                 flux=FV_FLUX_HLLE, recon=FV_RECON_MINMOD, rk_stages=2, lx=1.0, ly=1.0, cfl=0.4,
-                dt_fixed=0.0, g=9.81, gamma=1.4, h_ref=0.0) -> fv_config:
-    return fv_config(ctypes.sizeof(fv_config), eqn, prec, nx, ny, bc_x, bc_y, flux, recon, rk_stages, 0,
+                dt_fixed=0.0, g=9.81, gamma=1.4, h_ref=0.0, learned=0) -> fv_config:
+    return fv_config(ctypes.sizeof(fv_config), eqn, prec, nx, ny, bc_x, bc_y, flux, recon, rk_stages, learned,
                      lx, ly, cfl, dt_fixed, g, gamma, h_ref)
+
+
+class fv_model_desc(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("hidden", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("mean", ctypes.c_float * 3), ("inv_std", ctypes.c_float * 3)]
+
+
+class fv_learned_stats(ctypes.Structure):
+    _fields_ = [("fallback_faces", ctypes.c_int64), ("redone_steps", ctypes.c_int64)]
+
+
+def make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0), order=1, hidden=32) -> fv_model_desc:
+    d = fv_model_desc()
+    d.struct_size = ctypes.sizeof(fv_model_desc)
+    d.hidden = hidden
+    d.order = order
+    d.reserved0 = 0
+    for i in range(3):
+        d.mean[i] = mean[i]
+        d.inv_std[i] = inv_std[i]
+    return d
 
 
 def _load():
@@ -66,6 +87,14 @@ def _load():
         "fv_set_stream": ([vp, vp], st),
         "fv_face_fluxes": ([vp, vp, vp], st),
         "fv_destroy": ([vp], None),
+        "fv_model_param_count": ([], ctypes.c_size_t),
+        "fv_model_workspace_bytes": ([ctypes.POINTER(fv_model_desc)], ctypes.c_size_t),
+        "fv_model_create": ([ctypes.POINTER(fv_model_desc), vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], st),
+        "fv_model_update": ([vp], st),
+        "fv_model_destroy": ([vp], None),
+        "fv_model_forward_scratch_bytes": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
+        "fv_model_forward": ([vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_size_t], st),
+        "fv_learned_step": ([vp, vp, i64, ctypes.POINTER(fv_learned_stats)], st),
         "fv_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -154,6 +183,98 @@ def fv_last_error() -> str:
     return lib.fv_last_error().decode()
 
 
+def fv_model_param_count() -> int:
+    return lib.fv_model_param_count()
+
+
+def fv_model_workspace_bytes(desc: fv_model_desc) -> int:
+    n = lib.fv_model_workspace_bytes(ctypes.byref(desc))
+    if n == 0:
+        raise FvError(FV_E_INVALID, "invalid model description")
+    return n
+
+
+def fv_model_create(desc: fv_model_desc, params_ptr: int, ws_ptr: int, ws_bytes: int, stream: int = 0):
+    h = ctypes.c_void_p()
+    _check(lib.fv_model_create(ctypes.byref(desc), params_ptr, ws_ptr, ws_bytes, stream, ctypes.byref(h)))
+    return h
+
+
+def fv_model_update(m):
+    _check(lib.fv_model_update(m))
+
+
+def fv_model_destroy(m):
+    lib.fv_model_destroy(m)
+
+
+def fv_model_forward_scratch_bytes(B: int, nx: int, ny: int) -> int:
+    return lib.fv_model_forward_scratch_bytes(B, nx, ny)
+
+
+def fv_model_forward(m, q_ptr: int, B: int, nx: int, ny: int, z_ptr: int, scratch_ptr: int, scratch_bytes: int):
+    _check(lib.fv_model_forward(m, q_ptr, B, nx, ny, z_ptr, scratch_ptr, scratch_bytes))
+
+
+def fv_learned_step(h, m, nsteps: int, want_stats: bool = True):
+    st = fv_learned_stats()
+    _check(lib.fv_learned_step(h, m, int(nsteps), ctypes.byref(st) if want_stats else None))
+    return (st.fallback_faces, st.redone_steps) if want_stats else None
+
+
+def params_to_vector(weights, biases) -> np.ndarray:
+    """Master parameter vector from per-layer W (co, ci, 3, 3) and b (co)."""
+    parts = []
+    for w, b in zip(weights, biases):
+        parts.append(np.asarray(w, dtype=np.float32).ravel())
+        parts.append(np.asarray(b, dtype=np.float32).ravel())
+    return np.concatenate(parts)
+
+
+class Model:
+    """Network parameters (torch FP32 master vector on the device) and the
+    packed weights of libfv."""
+
+    def __init__(self, params, desc: fv_model_desc | None = None, device="cuda", stream=None):
+        import torch
+
+        self.desc = desc if desc is not None else make_model_desc()
+        self.device = torch.device(device)
+        p = torch.as_tensor(np.asarray(params, dtype=np.float32), device=self.device).contiguous()
+        if p.numel() != fv_model_param_count():
+            raise ValueError(f"expected {fv_model_param_count()} parameters, got {p.numel()}")
+        self.params = p
+        n = fv_model_workspace_bytes(self.desc)
+        self.ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = fv_model_create(self.desc, self.params.data_ptr(), self.ws.data_ptr(), n, self.stream.cuda_stream)
+
+    def update(self):
+        fv_model_update(self.h)
+
+    def forward(self, q):
+        """z [B, ny, nx, 72] for states q [B, 3, ny, nx] (torch CUDA float32)."""
+        import torch
+
+        B, _, ny, nx = q.shape
+        z = torch.empty((B, ny, nx, 72), dtype=torch.float32, device=self.device)
+        nb = fv_model_forward_scratch_bytes(B, nx, ny)
+        sc = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        fv_model_forward(self.h, q.data_ptr(), B, nx, ny, z.data_ptr(), sc.data_ptr(), nb)
+        return z
+
+    def close(self):
+        if self.h is not None:
+            fv_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 # ------------------------------------------------------ torch-backed handle
 
 class Solver:
@@ -202,6 +323,9 @@ class Solver:
 
     def reference_depth(self) -> float:
         return fv_reference_depth(self.h)
+
+    def learned_step(self, model: "Model", nsteps: int, want_stats: bool = True):
+        return fv_learned_step(self.h, model.h, nsteps, want_stats)
 
     def face_fluxes(self):
         import torch
