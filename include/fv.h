@@ -225,6 +225,70 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
 /* Message of the last failing call on this thread ("" if none). */
 const char *fv_last_error(void);
 
+/* ------------------------------------------------------------------------
+ * Training of the coefficient network (thesis eq 2.28, section 2.5.3):
+ * Loss = sum_{t=1..T} MSE(Q_ref(t), Q_pred(t)) over T learned Heun steps at
+ * a fixed step from the coarse initial states, the MSE averaged over cells
+ * and variables with variable v divided by scale[v].  The forward keeps
+ * every stage's input, activations and coefficients; the reverse pass runs
+ * the Heun adjoint, the finite-volume adjoint (flux Jacobians of the branch
+ * taken, MINMOD derivative on fallback faces, plain-scheme adjoint for
+ * redone steps) and the network's BF16 MFMA backward with FP32 accumulation.
+ * Gradient reductions are in a fixed order (run-to-run identical).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t struct_size; /* sizeof(fv_train_config) */
+    int32_t B;            /* windows per batch */
+    int32_t nx, ny;       /* periodic coarse grid (nx % 16 == 0, nx*ny % 64 == 0) */
+    int32_t T;            /* largest number of unrolled steps */
+    int32_t flux;         /* FV_FLUX_HLLE | FV_FLUX_RUSANOV */
+    double lx, ly;        /* domain size */
+    double dt;            /* fixed step */
+    double g;             /* gravity */
+    double h_ref;         /* reference depth of the pressure term, > 0 */
+    float scale[3];       /* loss scale of h, hu, hv */
+    float lr, beta1, beta2, eps; /* Adam */
+} fv_train_config;
+
+typedef struct fv_trainer fv_trainer;
+
+/* Device workspace of a trainer (saved states, activations, coefficients,
+ * adjoints); 0 if the configuration is invalid. */
+size_t fv_train_workspace_bytes(const fv_train_config *cfg);
+
+/* Create a trainer for model m (its stream is used).  grads, adam_m, adam_v:
+ * caller-owned device FP32 vectors of fv_model_param_count() elements
+ * (grads is overwritten by each fv_train_step; the Adam moments must start
+ * at zero).  workspace: >= fv_train_workspace_bytes, 256-byte aligned. */
+fv_status fv_train_create(const fv_train_config *cfg, fv_model *m, float *grads, float *adam_m, float *adam_v,
+                          void *workspace, size_t workspace_bytes, fv_trainer **out);
+
+/* One loss/gradient evaluation.  q0: device [B][3][ny][nx] FP32 initial
+ * states; targets: device [T][B][3][ny][nx] reference states after steps
+ * 1..T (1 <= T <= cfg.T).  Writes d loss / d theta into grads.  Sync point:
+ * *loss (host) receives the loss; stats (nullable) the fallback faces and
+ * redone steps of the rollout. */
+fv_status fv_train_step(fv_trainer *tr, const float *q0, const float *targets, int T, double *loss,
+                        fv_learned_stats *stats);
+
+/* d loss / d q0 of the last fv_train_step, copied to dst (device,
+ * [B][3][ny][nx]). */
+fv_status fv_train_input_grad(fv_trainer *tr, float *dst);
+
+/* State after step t (0..T) of the last fv_train_step's rollout (device). */
+fv_status fv_train_state(fv_trainer *tr, int t, float *dst);
+
+/* Adam update of the model's master parameters from grads, then re-pack
+ * the model's weights (async on the model's stream). */
+fv_status fv_adam_step(fv_trainer *tr);
+
+void fv_train_destroy(fv_trainer *tr);
+
+/* Block-average coarsening (exact cell averages): coarse[v][J][I] = mean of
+ * the factor x factor block of fine[v] (FP32 device arrays, nx and ny
+ * multiples of factor), FP64 accumulation.  Async on stream. */
+fv_status fv_coarsen(const float *fine, int nvar, int nx, int ny, int factor, float *coarse, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

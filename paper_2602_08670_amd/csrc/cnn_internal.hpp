@@ -83,8 +83,19 @@ struct StageBatch {
 };
 hipError_t learned_stage(int mode, int flux, const StageBatch &sb, hipStream_t st);
 hipError_t launch_commit(float *q, const float *s2, const int *bad, size_t per_solve, int B, hipStream_t st);
-hipError_t launch_finish(int *bad, unsigned long long *redone, int B, const float *dt, double *t, long long *steps,
-                         hipStream_t st);
+hipError_t launch_finish(int *bad, unsigned long long *redone, int *record, int B, const float *dt, double *t,
+                         long long *steps, hipStream_t st);
+
+// Training helpers (train_kernels.hip).
+// loss_acc += sum((pred - tgt)/s_v)^2 / N over the batch (N = B*3*ny*nx,
+// FP64 fixed-order reduction) and G += 2 (pred - tgt) / (s_v^2 N).
+hipError_t launch_loss(const float *pred, const float *tgt, const float *scale3, int B, int nx, int ny, float *G,
+                       double *partials, int max_blocks, double *loss_acc, hipStream_t st);
+hipError_t launch_scale(float *out, const float *in, float a, size_t n, hipStream_t st);
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, size_t n, float lr, float b1, float b2,
+                       float eps, float bc1, float bc2, hipStream_t st);
+hipError_t launch_flags_or(const int *flags, int B, int *any, hipStream_t st);
+hipError_t launch_coarsen(const float *fine, int nvar, int nx, int ny, int f, float *coarse, hipStream_t st);
 
 // Reverse pass of one learned stage (adjoint_kernels.hip): writes
 // gqs = (accumulate ? gqs : 0) + a1*gout + (FV part of the adjoint), and gz,

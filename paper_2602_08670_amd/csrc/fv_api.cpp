@@ -11,15 +11,13 @@
 #include <cstring>
 #include <string>
 
-#include "../../include/fv.h"
-#include "cnn_internal.hpp"
+#include "api_common.hpp"
 #include "fv_internal.hpp"
 
-namespace {
+namespace fvapi {
 
 thread_local std::string g_err;
 
-fv_status fail(fv_status code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 fv_status fail(fv_status code, const char *fmt, ...)
 {
     char buf[512];
@@ -36,7 +34,15 @@ fv_status hip_fail(hipError_t e, const char *what)
     return fail(FV_E_HIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+const char *last_error() { return g_err.c_str(); }
+
+}  // namespace fvapi
+
+using fvapi::align256;
+using fvapi::fail;
+using fvapi::hip_fail;
+
+namespace {
 
 struct Layout {
     size_t ctl, rates, totals_out, partials, s1, s2;
@@ -364,20 +370,11 @@ void fv_destroy(fv_solver *s)
     delete s;
 }
 
-const char *fv_last_error(void) { return g_err.c_str(); }
+const char *fv_last_error(void) { return fvapi::last_error(); }
 
 }  // extern "C"
 
 // ------------------------------------------------------------ learned path
-
-struct fv_model {
-    fv_model_desc desc;
-    const float *params;
-    void *packed;
-    hipStream_t stream;
-    cnn::Norm nrm;
-    cnn::Proj pr;
-};
 
 namespace {
 
@@ -509,7 +506,7 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
         sb.qs = S1; sb.q0 = q; sb.out = q; sb.a0 = 0.5f; sb.a1 = 0.5f;
         if (e == hipSuccess) e = cnn::learned_stage(1, fl, sb, s->stream);
         if (e == hipSuccess)
-            e = cnn::launch_finish(sb.bad, (unsigned long long *)(sm + SM_REDONE), 1, sb.dt, &s->ctl()->t,
+            e = cnn::launch_finish(sb.bad, (unsigned long long *)(sm + SM_REDONE), nullptr, 1, sb.dt, &s->ctl()->t,
                                    &s->ctl()->step, s->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "learned step launch");

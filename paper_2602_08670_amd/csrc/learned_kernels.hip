@@ -209,13 +209,15 @@ __global__ void commit_kernel(float *q, const float *s2, const int *bad, size_t 
     }
 }
 
-// End of step: count redone steps, clear the per-step flags, advance time.
-__global__ void finish_kernel(int *bad, unsigned long long *redone, int B, const float *dt, double *t,
+// End of step: count redone steps (and record which solves were redone),
+// clear the per-step flags, advance time.
+__global__ void finish_kernel(int *bad, unsigned long long *redone, int *record, int B, const float *dt, double *t,
                               long long *steps)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < B) {
-        if (bad[b]) redone[b] += 1;
+        if (bad[b] && redone) redone[b] += 1;
+        if (record) record[b] = bad[b] != 0;
         bad[b] = 0;
     }
     if (b == 0 && t) {
@@ -268,10 +270,10 @@ hipError_t launch_commit(float *q, const float *s2, const int *bad, size_t per_s
     return hipGetLastError();
 }
 
-hipError_t launch_finish(int *bad, unsigned long long *redone, int B, const float *dt, double *t, long long *steps,
-                         hipStream_t st)
+hipError_t launch_finish(int *bad, unsigned long long *redone, int *record, int B, const float *dt, double *t,
+                         long long *steps, hipStream_t st)
 {
-    hipLaunchKernelGGL(finish_kernel, dim3((B + 255) / 256), dim3(256), 0, st, bad, redone, B, dt, t, steps);
+    hipLaunchKernelGGL(finish_kernel, dim3((B + 255) / 256), dim3(256), 0, st, bad, redone, record, B, dt, t, steps);
     return hipGetLastError();
 }
 

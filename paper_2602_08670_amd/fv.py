@@ -54,6 +54,14 @@ class fv_learned_stats(ctypes.Structure):
     _fields_ = [("fallback_faces", ctypes.c_int64), ("redone_steps", ctypes.c_int64)]
 
 
+class fv_train_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("B", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("T", ctypes.c_int32), ("flux", ctypes.c_int32), ("lx", ctypes.c_double),
+                ("ly", ctypes.c_double), ("dt", ctypes.c_double), ("g", ctypes.c_double), ("h_ref", ctypes.c_double),
+                ("scale", ctypes.c_float * 3), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
 def make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0), order=1, hidden=32) -> fv_model_desc:
     d = fv_model_desc()
     d.struct_size = ctypes.sizeof(fv_model_desc)
@@ -95,6 +103,16 @@ def _load():
         "fv_model_forward_scratch_bytes": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
         "fv_model_forward": ([vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_size_t], st),
         "fv_learned_step": ([vp, vp, i64, ctypes.POINTER(fv_learned_stats)], st),
+        "fv_train_workspace_bytes": ([ctypes.POINTER(fv_train_config)], ctypes.c_size_t),
+        "fv_train_create": ([ctypes.POINTER(fv_train_config), vp, vp, vp, vp, vp, ctypes.c_size_t,
+                             ctypes.POINTER(vp)], st),
+        "fv_train_step": ([vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                           ctypes.POINTER(fv_learned_stats)], st),
+        "fv_train_input_grad": ([vp, vp], st),
+        "fv_train_state": ([vp, ctypes.c_int, vp], st),
+        "fv_adam_step": ([vp], st),
+        "fv_train_destroy": ([vp], None),
+        "fv_coarsen": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp], st),
         "fv_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -220,6 +238,125 @@ def fv_learned_step(h, m, nsteps: int, want_stats: bool = True):
     st = fv_learned_stats()
     _check(lib.fv_learned_step(h, m, int(nsteps), ctypes.byref(st) if want_stats else None))
     return (st.fallback_faces, st.redone_steps) if want_stats else None
+
+
+def fv_train_workspace_bytes(cfg: fv_train_config) -> int:
+    n = lib.fv_train_workspace_bytes(ctypes.byref(cfg))
+    if n == 0:
+        raise FvError(FV_E_INVALID, lib.fv_last_error().decode())
+    return n
+
+
+def fv_train_create(cfg, model_h, grads_ptr, m_ptr, v_ptr, ws_ptr, ws_bytes):
+    h = ctypes.c_void_p()
+    _check(lib.fv_train_create(ctypes.byref(cfg), model_h, grads_ptr, m_ptr, v_ptr, ws_ptr, ws_bytes,
+                               ctypes.byref(h)))
+    return h
+
+
+def fv_train_step(h, q0_ptr, tgt_ptr, T):
+    loss = ctypes.c_double()
+    st = fv_learned_stats()
+    _check(lib.fv_train_step(h, q0_ptr, tgt_ptr, int(T), ctypes.byref(loss), ctypes.byref(st)))
+    return loss.value, (st.fallback_faces, st.redone_steps)
+
+
+def fv_train_input_grad(h, dst_ptr):
+    _check(lib.fv_train_input_grad(h, dst_ptr))
+
+
+def fv_train_state(h, t, dst_ptr):
+    _check(lib.fv_train_state(h, int(t), dst_ptr))
+
+
+def fv_adam_step(h):
+    _check(lib.fv_adam_step(h))
+
+
+def fv_train_destroy(h):
+    lib.fv_train_destroy(h)
+
+
+def fv_coarsen(fine_ptr, nvar, nx, ny, factor, coarse_ptr, stream=0):
+    _check(lib.fv_coarsen(fine_ptr, nvar, nx, ny, factor, coarse_ptr, stream))
+
+
+def make_train_config(B, nx, ny, T, dt, lx=1.0, ly=1.0, g=9.81, h_ref=1.0, flux=FV_FLUX_HLLE,
+                      scale=(0.05, 0.05, 0.05), lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8) -> fv_train_config:
+    c = fv_train_config()
+    c.struct_size = ctypes.sizeof(fv_train_config)
+    c.B, c.nx, c.ny, c.T, c.flux = B, nx, ny, T, flux
+    c.lx, c.ly, c.dt, c.g, c.h_ref = lx, ly, dt, g, h_ref
+    for i in range(3):
+        c.scale[i] = scale[i]
+    c.lr, c.beta1, c.beta2, c.eps = lr, beta1, beta2, eps
+    return c
+
+
+class Trainer:
+    """Unrolled-loss training of a Model on batches of coarse windows."""
+
+    def __init__(self, model: "Model", cfg: fv_train_config):
+        import torch
+
+        self.model = model
+        self.cfg = cfg
+        n = fv_model_param_count()
+        dev = model.device
+        self.grads = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.m = torch.zeros(n, dtype=torch.float32, device=dev)
+        self.v = torch.zeros(n, dtype=torch.float32, device=dev)
+        nb = fv_train_workspace_bytes(cfg)
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=dev)
+        self.h = fv_train_create(cfg, model.h, self.grads.data_ptr(), self.m.data_ptr(), self.v.data_ptr(),
+                                 self.ws.data_ptr(), nb)
+
+    def step(self, q0, targets):
+        """q0 [B,3,ny,nx], targets [T,B,3,ny,nx] (torch CUDA float32)."""
+        q0 = q0.contiguous()
+        targets = targets.contiguous()
+        return fv_train_step(self.h, q0.data_ptr(), targets.data_ptr(), targets.shape[0])
+
+    def input_grad(self):
+        import torch
+
+        c = self.cfg
+        out = torch.empty((c.B, 3, c.ny, c.nx), dtype=torch.float32, device=self.model.device)
+        fv_train_input_grad(self.h, out.data_ptr())
+        return out
+
+    def state(self, t):
+        import torch
+
+        c = self.cfg
+        out = torch.empty((c.B, 3, c.ny, c.nx), dtype=torch.float32, device=self.model.device)
+        fv_train_state(self.h, t, out.data_ptr())
+        return out
+
+    def adam(self):
+        fv_adam_step(self.h)
+
+    def close(self):
+        if self.h is not None:
+            fv_train_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def coarsen(fine, factor):
+    """Block average of a torch CUDA float32 state [nvar, ny, nx] by factor."""
+    import torch
+
+    nvar, ny, nx = fine.shape
+    out = torch.empty((nvar, ny // factor, nx // factor), dtype=torch.float32, device=fine.device)
+    fv_coarsen(fine.contiguous().data_ptr(), nvar, nx, ny, factor, out.data_ptr(),
+               torch.cuda.current_stream(fine.device).cuda_stream)
+    return out
 
 
 def params_to_vector(weights, biases) -> np.ndarray:
