@@ -289,6 +289,78 @@ void fv_train_destroy(fv_trainer *tr);
  * multiples of factor), FP64 accumulation.  Async on stream. */
 fv_status fv_coarsen(const float *fine, int nvar, int nx, int ny, int factor, float *coarse, void *stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of independent FP32 solves (shallow water
+ * over a bed, or Euler; HLLE, MINMOD, Heun, CFL time step; square grids on
+ * the unit square).  Requests wait in a FIFO queue; at each round boundary
+ * those whose device footprint (fv_request_bytes) fits the free part of the
+ * caller's memory pool are admitted (a later request may pass one that does
+ * not fit).  A round advances every active solve by up to steps_per_round
+ * steps, each stage of each step being one batched launch over the tiles of
+ * all active solves of an equation type; finished solves are copied back
+ * and their memory returns to the pool.  The per-cell arithmetic is the
+ * single-solve kernel's, so a solve's result is bit-identical alone (fv_run)
+ * and in any mix.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t struct_size;    /* sizeof(fv_server_config) */
+    int32_t max_solves;      /* solve slots */
+    int32_t steps_per_round; /* K: steps between admission/retirement points */
+    int32_t reserved0;       /* must be 0 */
+    uint64_t max_items;      /* most tiles (workgroups) one batched launch may hold */
+} fv_server_config;
+
+typedef struct {
+    uint32_t struct_size;    /* sizeof(fv_request) */
+    int32_t eqn;             /* FV_SWE (with the given bed, or a zero bed) | FV_EULER */
+    int32_t n;               /* cells per side, >= 8 */
+    int32_t bc;              /* FV_BC_PERIODIC | FV_BC_WALL on both axes */
+    int64_t steps;           /* time steps to run */
+    double cfl, g, gamma;
+    double h_ref;            /* SWE pressure reference depth, 0 = mean initial depth */
+    const float *q0;         /* host [nvar][n][n]; copied by fv_server_submit */
+    const float *bed;        /* host [n][n] (SWE, nullable); copied */
+} fv_request;
+
+typedef struct {
+    int32_t state;           /* 0 queued, 1 running, 2 done, 3 failed (inadmissible) */
+    int32_t pad;
+    int64_t steps_done;
+    double t_submit, t_admit, t_done; /* seconds since fv_server_create */
+    double sim_time;         /* simulated time reached (done requests) */
+} fv_request_info;
+
+typedef struct fv_server fv_server;
+
+/* Pool bytes taken by the server's tables (solve table, work-lists). */
+size_t fv_server_pool_overhead(const fv_server_config *cfg);
+
+/* Device bytes one request occupies while admitted; 0 if invalid. */
+size_t fv_request_bytes(const fv_request *r);
+
+/* Create a server over a caller-owned device pool (256-byte aligned); its
+ * work is enqueued on stream. */
+fv_status fv_server_create(const fv_server_config *cfg, void *pool, size_t pool_bytes, void *stream,
+                           fv_server **out);
+
+/* Queue a request (inputs are copied); *id identifies it. */
+fv_status fv_server_submit(fv_server *s, const fv_request *r, int64_t *id);
+
+/* Admit what fits, run one round, retire finished solves.  Sync point.
+ * Reports the running and queued request counts after the round. */
+fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued);
+
+fv_status fv_server_info(fv_server *s, int64_t id, fv_request_info *info);
+
+/* Copy a finished request's final state to dst (host, [nvar][n][n]);
+ * FV_E_INADMISSIBLE if it failed (dst then holds the failing state). */
+fv_status fv_server_result(fv_server *s, int64_t id, float *dst);
+
+/* Forget a finished request (frees its host copy). */
+fv_status fv_server_release(fv_server *s, int64_t id);
+
+void fv_server_destroy(fv_server *s);
+
 #ifdef __cplusplus
 }
 #endif

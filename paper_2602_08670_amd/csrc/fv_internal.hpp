@@ -51,6 +51,26 @@ hipError_t launch_stage(const StageDesc &d, const void *qs, const void *q0, void
                         double a0, double a1, Ctl *ctl, unsigned long long *rates, int rate_in, int rate_out,
                         int rate_clear, int last, hipStream_t st);
 
+// Batched FP32 Heun stages over many solves (serving).  BatchSolve is one
+// solve's device descriptor; WorkItem one solve of a step's list: where its
+// workgroups start in the launch and its CFL slots at that step.
+struct BatchSolve {
+    void *q, *s1;
+    const void *bed;
+    void *ctl, *rates;
+    int nx, ny, bc_x, bc_y;
+    double rdx, rdy, g, sqg, gamma, h0, cfl, dt_fixed;
+};
+struct WorkItem {
+    int solve;
+    int tile_begin;  // index of the solve's first workgroup in the launch (prefix sum of tiles)
+    int tiles_x;     // tiles per row of the solve; tile = workgroup - tile_begin, row-major
+    unsigned char ri, ro, rc, pad;
+};
+constexpr int TILE_X = 64, TILE_Y = 8;  // FP32 tile of the stage kernels
+hipError_t launch_batch_stage(int eqn, int bathy, int stage, const BatchSolve *solves, const WorkItem *items,
+                              const int *nitems, int grid, hipStream_t st);
+
 // Reduce the CFL rate of q into ctl->rate[slot] and flag inadmissible cells.
 hipError_t launch_rate(const StageDesc &d, const void *q, Ctl *ctl, unsigned long long *rates, int slot,
                        hipStream_t st);

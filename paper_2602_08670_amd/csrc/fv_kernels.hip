@@ -27,6 +27,10 @@ __device__ __forceinline__ int map_index(int i, int n, int bc, bool &flip)
     return m < 0 ? 0 : (m >= n ? n - 1 : m);  // cells past the ghost layer are never used
 }
 
+template <typename T> struct Tile;
+template <> struct Tile<float> { static constexpr int X = 64, Y = 8; };
+template <> struct Tile<double> { static constexpr int X = 64, Y = 8; };
+
 template <typename T> struct StageArgs {
     const T *qs;
     const T *q0;
@@ -85,8 +89,12 @@ template <typename T> __device__ __forceinline__ T block_max256(T v, T *red)
     return m;
 }
 
+// One RK stage on the TX x TY tile at (x0, y0).  `tile_linear` is the tile's
+// index within its solve; the tile with index 0 does the per-step
+// bookkeeping of the solve.  Shared by the single-solve kernel and the
+// batched kernel, so a solve computes bit-identical results in both.
 template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int TX, int TY>
-__global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
+__device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, const int y0, const int tile_linear)
 {
     constexpr int NV = EQN == SWE ? 3 : 4;
     constexpr int NL = NV + (BATHY ? 1 : 0);
@@ -99,7 +107,6 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
 
     if (a.ctl->bad) return;  // an earlier step failed: the state is frozen
     const int tid = threadIdx.x;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
     const int nx = a.nx, ny = a.ny;
     const size_t plane = (size_t)nx * ny;
 
@@ -235,15 +242,71 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
     if (bad) atomicExch(&a.ctl->bad, 1);
     if (a.rate_out >= 0) {
         T m = block_max256(lmax, s_red);
-        if (tid == 0) push_rate(a.rates, a.rate_out, (double)m, blockIdx.x + blockIdx.y * gridDim.x);
+        if (tid == 0) push_rate(a.rates, a.rate_out, (double)m, tile_linear);
     }
-    if (blockIdx.x == 0 && blockIdx.y == 0) {
+    if (tile_linear == 0) {
         if (tid == 0) {
             a.ctl->t += dtd;
             a.ctl->step += 1;
         }
         if (a.rate_clear >= 0 && tid < RATE_SUB) *rate_slot(a.rates, a.rate_clear, tid) = 0ull;
     }
+}
+
+template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int TX, int TY>
+__global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
+{
+    stage_tile<T, EQN, BATHY, FLUX, RECON, TX, TY>(a, blockIdx.x * TX, blockIdx.y * TY,
+                                                   blockIdx.x + blockIdx.y * gridDim.x);
+}
+
+// Batched stage over many solves: the step's list holds one item per solve
+// (sorted by tile_begin); workgroup w binary-searches the solve whose tile
+// range contains w.  STAGE 1: S1 = q + dt L(q); STAGE 2: q = q/2 + (S1 + dt
+// L(S1))/2 (Heun).
+template <typename T, int EQN, bool BATHY, int STAGE>
+__global__ __launch_bounds__(256) void batch_stage_kernel(const BatchSolve *solves, const WorkItem *items,
+                                                          const int *nitems)
+{
+    constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;
+    const int n = *nitems;
+    const int w = blockIdx.x;
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (items[mid].tile_begin <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    const WorkItem it = items[lo];
+    const int tile = w - it.tile_begin;
+    const BatchSolve &d = solves[it.solve];
+    StageArgs<T> a;
+    a.qs = (const T *)(STAGE == 1 ? d.q : d.s1);
+    a.q0 = (const T *)d.q;
+    a.out = (T *)(STAGE == 1 ? d.s1 : d.q);
+    a.bed = (const T *)d.bed;
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.bc_x = d.bc_x;
+    a.bc_y = d.bc_y;
+    a.rdx = (T)d.rdx;
+    a.rdy = (T)d.rdy;
+    a.ph.g = (T)d.g;
+    a.ph.sqg = (T)d.sqg;
+    a.ph.gamma = (T)d.gamma;
+    a.ph.h0 = (T)d.h0;
+    a.a0 = STAGE == 1 ? T(0) : T(0.5);
+    a.a1 = STAGE == 1 ? T(1) : T(0.5);
+    a.cfl = d.cfl;
+    a.dt_fixed = d.dt_fixed;
+    a.ctl = (Ctl *)d.ctl;
+    a.rates = (unsigned long long *)d.rates;
+    a.rate_in = it.ri;
+    a.rate_out = STAGE == 1 ? -1 : it.ro;
+    a.rate_clear = STAGE == 1 ? -1 : it.rc;
+    a.last = STAGE == 2;
+    const int ty = tile / it.tiles_x, tx = tile - ty * it.tiles_x;
+    stage_tile<T, EQN, BATHY, HLLE, MINMOD, TX, TY>(a, tx * TX, ty * TY, tile);
 }
 
 // ------------------------------------------------------------ CFL rate of q
@@ -359,9 +422,6 @@ __global__ void face_kernel(const T *q, int nx, int ny, int bc_x, int bc_y, Phys
 }
 
 // ----------------------------------------------------------------- dispatch
-template <typename T> struct Tile;
-template <> struct Tile<float> { static constexpr int X = 64, Y = 8; };
-template <> struct Tile<double> { static constexpr int X = 64, Y = 8; };
 
 template <typename T, int EQN, bool BATHY, int FLUX, int RECON>
 static hipError_t stage_t(const StageDesc &d, const void *qs, const void *q0, void *out, const void *bed, double a0,
@@ -454,6 +514,24 @@ static hipError_t rate_t(const StageDesc &d, const void *q, Ctl *ctl, unsigned l
     else
         hipLaunchKernelGGL((rate_kernel<T, SWE>), dim3(blocks), dim3(256), 0, st, (const T *)q, n, (T)d.rdx,
                            (T)d.rdy, ph, ctl, rates, slot);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_stage(int eqn, int bathy, int stage, const BatchSolve *solves, const WorkItem *items,
+                              const int *nitems, int grid, hipStream_t st)
+{
+    if (grid <= 0) return hipSuccess;
+    dim3 g(grid), b(256);
+    if (eqn == EULER) {
+        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, 1>), g, b, 0, st, solves, items, nitems);
+        else hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, 2>), g, b, 0, st, solves, items, nitems);
+    } else if (bathy) {
+        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, 1>), g, b, 0, st, solves, items, nitems);
+        else hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, 2>), g, b, 0, st, solves, items, nitems);
+    } else {
+        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, 1>), g, b, 0, st, solves, items, nitems);
+        else hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, 2>), g, b, 0, st, solves, items, nitems);
+    }
     return hipGetLastError();
 }
 

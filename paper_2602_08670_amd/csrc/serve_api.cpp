@@ -1,0 +1,446 @@
+// Serving: continuous batching of many independent solves on one GPU.
+//
+// Requests (shallow water over a bed, or Euler; square grids; their own step
+// counts) wait in a FIFO queue.  At every round boundary the server admits
+// queued requests whose device footprint fits the free part of the memory
+// pool (first fit, later requests may pass one that does not fit), uploads
+// their state and computes their first CFL rate.  A round then advances all
+// active solves by up to K steps: for every step the host builds a list of
+// the solves still running at that step per equation type (where their
+// workgroups start in the launch, and their CFL slots at that step) -- a
+// solve with fewer remaining steps simply drops out of the later lists --
+// and each stage of each step is one batched launch over all tiles of the
+// listed solves.  Shallow-water requests always run the bed kernel (a zero
+// bed when none is given).  After the round, finished solves are copied back and their memory
+// returns to the pool, so the next round can admit newly arrived requests
+// while the long-running ones continue.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <unordered_map>
+#include <vector>
+
+#include "api_common.hpp"
+#include "fv_internal.hpp"
+
+using fvapi::align256;
+using fvapi::fail;
+using fvapi::hip_fail;
+
+namespace {
+
+struct Req {
+    int64_t id;
+    fv_request r;
+    std::vector<float> q0, bed, result;
+    int state = 0;  // 0 queued, 1 active, 2 done, 3 failed
+    double t_submit = 0, t_admit = 0, t_done = 0;
+    size_t off = 0, bytes = 0;
+    int slot = -1;
+    int64_t done_steps = 0;
+    int tiles_x = 0, tiles = 0;
+    double sim_time = 0;
+    size_t q_off, s1_off, bed_off, ctl_off, rates_off;
+    int nvar() const { return r.eqn == FV_EULER ? 4 : 3; }
+};
+
+size_t req_bytes(const fv_request *r)
+{
+    size_t n2 = (size_t)r->n * r->n;
+    int nvar = r->eqn == FV_EULER ? 4 : 3;
+    size_t b = 2 * align256(nvar * n2 * 4) + fvk::CTL_BYTES + fvk::RATE_BYTES;
+    if (r->eqn == FV_SWE) b += align256(n2 * 4);
+    return b;
+}
+
+}  // namespace
+
+struct fv_server {
+    fv_server_config cfg;
+    char *pool;
+    size_t pool_bytes;
+    hipStream_t stream;
+    std::chrono::steady_clock::time_point t0;
+    // pool regions
+    size_t tab_off, items_off, nitems_off, scratch_off, heap_off;
+    std::map<size_t, size_t> free_list;  // offset -> size
+    // host side
+    std::deque<Req *> queue;
+    std::vector<Req *> active;
+    std::vector<int> free_slots;
+    std::unordered_map<int64_t, std::unique_ptr<Req>> reqs;
+    int64_t next_id = 1;
+    fvk::WorkItem *h_items = nullptr;  // pinned
+    int *h_nitems = nullptr;
+    std::vector<fvk::BatchSolve> h_tab;
+
+    double now() const
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    bool alloc(size_t bytes, size_t *off)
+    {
+        for (auto it = free_list.begin(); it != free_list.end(); ++it) {
+            if (it->second >= bytes) {
+                *off = it->first;
+                size_t rest = it->second - bytes;
+                size_t noff = it->first + bytes;
+                free_list.erase(it);
+                if (rest) free_list[noff] = rest;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(size_t off, size_t bytes)
+    {
+        auto it = free_list.emplace(off, bytes).first;
+        auto nx = std::next(it);
+        if (nx != free_list.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_list.erase(nx);
+        }
+        if (it != free_list.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_list.erase(it);
+            }
+        }
+    }
+};
+
+namespace {
+
+// one list per step and equation type, one item per active solve
+size_t items_capacity(const fv_server_config *c) { return (size_t)c->steps_per_round * 2 * c->max_solves; }
+
+fv_status validate(const fv_server_config *c)
+{
+    if (!c || c->struct_size != sizeof(fv_server_config)) return fail(FV_E_INVALID, "server config struct_size");
+    if (c->max_solves < 1 || c->steps_per_round < 1 || c->max_items < 1)
+        return fail(FV_E_INVALID, "max_solves, steps_per_round and max_items must be >= 1");
+    if (c->max_items > (uint64_t)1 << 31) return fail(FV_E_INVALID, "max_items above 2^31");
+    if (c->reserved0 != 0) return fail(FV_E_INVALID, "reserved0 must be 0");
+    return FV_OK;
+}
+
+size_t overhead(const fv_server_config *c)
+{
+    size_t o = align256(sizeof(fvk::BatchSolve) * c->max_solves);
+    o += align256(items_capacity(c) * sizeof(fvk::WorkItem));
+    o += align256((size_t)c->steps_per_round * 2 * sizeof(int));
+    o += align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * 8 + 256);
+    return o;
+}
+
+fv_status validate_req(const fv_request *r)
+{
+    if (!r || r->struct_size != sizeof(fv_request)) return fail(FV_E_INVALID, "request struct_size");
+    if (r->eqn != FV_SWE && r->eqn != FV_EULER) return fail(FV_E_INVALID, "eqn %d", r->eqn);
+    if (r->n < 8) return fail(FV_E_INVALID, "grid side %d < 8", r->n);
+    if (r->bc != FV_BC_PERIODIC && r->bc != FV_BC_WALL) return fail(FV_E_INVALID, "bc %d", r->bc);
+    if (r->steps < 0) return fail(FV_E_INVALID, "steps < 0");
+    if (!(r->cfl > 0 && r->cfl <= 1)) return fail(FV_E_INVALID, "cfl");
+    if (!r->q0) return fail(FV_E_INVALID, "initial state is NULL");
+    if (r->eqn == FV_EULER && r->bed) return fail(FV_E_INVALID, "a bed is only defined for shallow water");
+    return FV_OK;
+}
+
+// Upload an admitted request and compute its first CFL rate (and reference
+// depth for shallow water) exactly as fv_init does for a single solve.
+fv_status admit(fv_server *s, Req *q, std::vector<Req *> &need_h0)
+{
+    const fv_request &r = q->r;
+    size_t n2 = (size_t)r.n * r.n;
+    int nvar = q->nvar();
+    q->q_off = q->off;
+    q->s1_off = q->q_off + align256(nvar * n2 * 4);
+    size_t o = q->s1_off + align256(nvar * n2 * 4);
+    q->bed_off = 0;
+    if (r.eqn == FV_SWE) {
+        q->bed_off = o;
+        o += align256(n2 * 4);
+    }
+    q->ctl_off = o;
+    q->rates_off = o + fvk::CTL_BYTES;
+    char *P = s->pool;
+    hipError_t e = hipMemcpyAsync(P + q->q_off, q->q0.data(), nvar * n2 * 4, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess && r.eqn == FV_SWE) {
+        if (q->bed.empty()) e = hipMemsetAsync(P + q->bed_off, 0, n2 * 4, s->stream);
+        else e = hipMemcpyAsync(P + q->bed_off, q->bed.data(), n2 * 4, hipMemcpyHostToDevice, s->stream);
+    }
+    if (e == hipSuccess) e = hipMemsetAsync(P + q->ctl_off, 0, fvk::CTL_BYTES + fvk::RATE_BYTES, s->stream);
+    if (e != hipSuccess) return hip_fail(e, "admission upload");
+    fvk::BatchSolve &d = s->h_tab[q->slot];
+    d.q = P + q->q_off;
+    d.s1 = P + q->s1_off;
+    d.bed = r.eqn == FV_SWE ? P + q->bed_off : nullptr;
+    d.ctl = P + q->ctl_off;
+    d.rates = P + q->rates_off;
+    d.nx = d.ny = r.n;
+    d.bc_x = d.bc_y = r.bc;
+    d.rdx = d.rdy = (double)r.n;  // unit square
+    d.g = r.g;
+    d.sqg = std::sqrt(r.g);
+    d.gamma = r.gamma;
+    d.h0 = r.eqn == FV_SWE ? r.h_ref : 0.0;
+    d.cfl = r.cfl;
+    d.dt_fixed = 0.0;
+    fvk::StageDesc sd{};
+    sd.prec = 0;
+    sd.eqn = r.eqn;
+    sd.bathy = r.eqn == FV_SWE;
+    sd.nx = sd.ny = r.n;
+    sd.bc_x = sd.bc_y = r.bc;
+    sd.rdx = sd.rdy = r.n;
+    sd.g = r.g;
+    sd.gamma = r.gamma;
+    e = fvk::launch_rate(sd, P + q->q_off, (fvk::Ctl *)(P + q->ctl_off), (unsigned long long *)(P + q->rates_off), 0,
+                         s->stream);
+    if (e != hipSuccess) return hip_fail(e, "admission rate kernel");
+    if (r.eqn == FV_SWE && !(r.h_ref > 0)) need_h0.push_back(q);
+    q->tiles_x = (r.n + fvk::TILE_X - 1) / fvk::TILE_X;
+    q->tiles = q->tiles_x * ((r.n + fvk::TILE_Y - 1) / fvk::TILE_Y);
+    return FV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fv_server_pool_overhead(const fv_server_config *cfg) { return validate(cfg) == FV_OK ? overhead(cfg) : 0; }
+
+size_t fv_request_bytes(const fv_request *r) { return validate_req(r) == FV_OK ? req_bytes(r) : 0; }
+
+fv_status fv_server_create(const fv_server_config *cfg, void *pool, size_t pool_bytes, void *stream,
+                           fv_server **out)
+{
+    if (!out) return fail(FV_E_INVALID, "out is NULL");
+    *out = nullptr;
+    fv_status rc = validate(cfg);
+    if (rc != FV_OK) return rc;
+    if (!pool || ((uintptr_t)pool & 255)) return fail(FV_E_INVALID, "pool must be a 256-byte aligned device buffer");
+    size_t ov = overhead(cfg);
+    if (pool_bytes < ov + 65536) return fail(FV_E_NOMEM, "pool %zu bytes < tables %zu + 64 KiB", pool_bytes, ov);
+    auto s = std::make_unique<fv_server>();
+    s->cfg = *cfg;
+    s->pool = (char *)pool;
+    s->pool_bytes = pool_bytes;
+    s->stream = (hipStream_t)stream;
+    s->t0 = std::chrono::steady_clock::now();
+    s->tab_off = 0;
+    s->items_off = align256(sizeof(fvk::BatchSolve) * cfg->max_solves);
+    s->nitems_off = s->items_off + align256(items_capacity(cfg) * sizeof(fvk::WorkItem));
+    s->scratch_off = s->nitems_off + align256((size_t)cfg->steps_per_round * 2 * sizeof(int));
+    s->heap_off = ov;
+    s->free_list[s->heap_off] = pool_bytes - s->heap_off;
+    s->h_tab.assign(cfg->max_solves, fvk::BatchSolve{});
+    for (int i = cfg->max_solves - 1; i >= 0; i--) s->free_slots.push_back(i);
+    hipError_t e = hipHostMalloc((void **)&s->h_items, items_capacity(cfg) * sizeof(fvk::WorkItem), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_nitems, (size_t)cfg->steps_per_round * 2 * sizeof(int), 0);
+    if (e != hipSuccess) {
+        if (s->h_items) (void)hipHostFree(s->h_items);
+        return hip_fail(e, "pinned work-list buffers");
+    }
+    *out = s.release();
+    return FV_OK;
+}
+
+fv_status fv_server_submit(fv_server *s, const fv_request *r, int64_t *id)
+{
+    if (!s || !id) return fail(FV_E_INVALID, "NULL argument");
+    fv_status rc = validate_req(r);
+    if (rc != FV_OK) return rc;
+    if (req_bytes(r) > s->pool_bytes - s->heap_off)
+        return fail(FV_E_NOMEM, "request needs %zu bytes, the pool holds %zu", req_bytes(r), s->pool_bytes - s->heap_off);
+    auto q = std::make_unique<Req>();
+    q->id = s->next_id++;
+    q->r = *r;
+    size_t n2 = (size_t)r->n * r->n;
+    q->q0.assign(r->q0, r->q0 + (size_t)q->nvar() * n2);
+    if (r->bed) q->bed.assign(r->bed, r->bed + n2);
+    q->r.q0 = nullptr;
+    q->r.bed = nullptr;
+    q->bytes = req_bytes(r);
+    q->t_submit = s->now();
+    *id = q->id;
+    s->queue.push_back(q.get());
+    s->reqs[q->id] = std::move(q);
+    return FV_OK;
+}
+
+fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
+{
+    if (!s) return fail(FV_E_INVALID, "server is NULL");
+    const int K = s->cfg.steps_per_round;
+    char *P = s->pool;
+    // ---- admission (FIFO, later requests may pass one that does not fit)
+    std::vector<Req *> admitted, need_h0;
+    for (auto it = s->queue.begin(); it != s->queue.end();) {
+        Req *q = *it;
+        size_t off;
+        if (!s->free_slots.empty() && s->alloc(q->bytes, &off)) {
+            q->off = off;
+            q->slot = s->free_slots.back();
+            s->free_slots.pop_back();
+            fv_status rc = admit(s, q, need_h0);
+            if (rc != FV_OK) return rc;
+            q->state = 1;
+            q->t_admit = s->now();
+            admitted.push_back(q);
+            s->active.push_back(q);
+            it = s->queue.erase(it);
+        } else {
+            ++it;
+        }
+    }
+    hipError_t e = hipSuccess;
+    if (!need_h0.empty()) {
+        // reference depth = mean initial depth, as fv_init computes it
+        double *out = (double *)(P + s->scratch_off);
+        double *partials = out + 8;
+        for (Req *q : need_h0) {
+            fvk::StageDesc sd{};
+            sd.prec = 0;
+            sd.eqn = FV_SWE;
+            sd.nx = sd.ny = q->r.n;
+            sd.rdx = sd.rdy = q->r.n;
+            sd.g = q->r.g;
+            e = fvk::launch_totals(sd, P + q->q_off, partials, fvk::TOTALS_MAX_BLOCKS, out, s->stream);
+            double tot[4];
+            if (e == hipSuccess) e = hipMemcpyAsync(tot, out, sizeof tot, hipMemcpyDeviceToHost, s->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+            if (e != hipSuccess) return hip_fail(e, "reference depth");
+            s->h_tab[q->slot].h0 = tot[0];  // unit square: mean depth = mass
+        }
+    }
+    if (!admitted.empty()) {
+        e = hipMemcpyAsync(P + s->tab_off, s->h_tab.data(), sizeof(fvk::BatchSolve) * s->cfg.max_solves,
+                           hipMemcpyHostToDevice, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "solve table upload");
+    }
+    // ---- work-lists of the round: one list per [step][type] (type 0 = SWE,
+    // 1 = Euler) of the solves still running at that step, packed back to
+    // back; tiles per launch are capped by max_items
+    const size_t ncap = (size_t)s->cfg.max_solves;
+    std::vector<int> counts((size_t)K * 2, 0), grids((size_t)K * 2, 0);
+    for (int k = 0; k < K; k++)
+        for (Req *q : s->active) {
+            if (q->r.steps - q->done_steps <= k) continue;
+            int type = q->r.eqn == FV_EULER ? 1 : 0;
+            size_t li = (size_t)k * 2 + type;
+            if ((uint64_t)grids[li] + q->tiles > s->cfg.max_items)
+                return fail(FV_E_NOMEM, "more than max_items = %llu tiles in one launch",
+                            (unsigned long long)s->cfg.max_items);
+            fvk::WorkItem &w = s->h_items[li * ncap + counts[li]];
+            int64_t st = q->done_steps + k;
+            w.solve = q->slot;
+            w.tile_begin = grids[li];
+            w.tiles_x = q->tiles_x;
+            w.ri = (unsigned char)(st % 3);
+            w.ro = (unsigned char)((st + 1) % 3);
+            w.rc = (unsigned char)((st + 2) % 3);
+            w.pad = 0;
+            counts[li]++;
+            grids[li] += q->tiles;
+        }
+    for (size_t i = 0; i < counts.size(); i++) s->h_nitems[i] = counts[i];
+    fvk::WorkItem *d_items = (fvk::WorkItem *)(P + s->items_off);
+    int *d_nitems = (int *)(P + s->nitems_off);
+    size_t used = 0;  // the lists are uploaded up to the last non-empty one
+    for (size_t li = 0; li < counts.size(); li++)
+        if (counts[li]) used = li * ncap + counts[li];
+    e = hipMemcpyAsync(d_items, s->h_items, used * sizeof(fvk::WorkItem), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_nitems, s->h_nitems, (size_t)K * 2 * sizeof(int), hipMemcpyHostToDevice, s->stream);
+    const fvk::BatchSolve *tab = (const fvk::BatchSolve *)(P + s->tab_off);
+    for (int k = 0; k < K && e == hipSuccess; k++)
+        for (int stage = 1; stage <= 2 && e == hipSuccess; stage++)
+            for (int type = 0; type < 2 && e == hipSuccess; type++) {
+                size_t li = (size_t)k * 2 + type;
+                e = fvk::launch_batch_stage(type == 1 ? FV_EULER : FV_SWE, type == 0, stage, tab, d_items + li * ncap,
+                                            d_nitems + li, grids[li], s->stream);
+            }
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+    if (e != hipSuccess) return hip_fail(e, "round");
+    // ---- retire finished solves
+    double tnow = s->now();
+    for (auto it = s->active.begin(); it != s->active.end();) {
+        Req *q = *it;
+        int64_t adv = q->r.steps - q->done_steps < K ? q->r.steps - q->done_steps : K;
+        q->done_steps += adv;
+        if (q->done_steps < q->r.steps) {
+            ++it;
+            continue;
+        }
+        size_t n = (size_t)q->nvar() * q->r.n * q->r.n;
+        q->result.resize(n);
+        fvk::Ctl c;
+        e = hipMemcpy(q->result.data(), P + q->q_off, n * 4, hipMemcpyDeviceToHost);
+        if (e == hipSuccess) e = hipMemcpy(&c, P + q->ctl_off, sizeof c, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "result copy");
+        q->sim_time = c.t;
+        q->state = c.bad ? 3 : 2;
+        q->t_done = tnow;
+        s->release(q->off, q->bytes);
+        s->free_slots.push_back(q->slot);
+        q->slot = -1;
+        it = s->active.erase(it);
+    }
+    if (n_active) *n_active = (int32_t)s->active.size();
+    if (n_queued) *n_queued = (int32_t)s->queue.size();
+    return FV_OK;
+}
+
+fv_status fv_server_info(fv_server *s, int64_t id, fv_request_info *info)
+{
+    if (!s || !info) return fail(FV_E_INVALID, "NULL argument");
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(FV_E_INVALID, "unknown request %lld", (long long)id);
+    const Req &q = *it->second;
+    info->state = q.state;
+    info->pad = 0;
+    info->steps_done = q.done_steps;
+    info->t_submit = q.t_submit;
+    info->t_admit = q.t_admit;
+    info->t_done = q.t_done;
+    info->sim_time = q.sim_time;
+    return FV_OK;
+}
+
+fv_status fv_server_result(fv_server *s, int64_t id, float *dst)
+{
+    if (!s || !dst) return fail(FV_E_INVALID, "NULL argument");
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end()) return fail(FV_E_INVALID, "unknown request %lld", (long long)id);
+    const Req &q = *it->second;
+    if (q.state < 2) return fail(FV_E_INVALID, "request %lld is not finished", (long long)id);
+    std::memcpy(dst, q.result.data(), q.result.size() * 4);
+    return q.state == 3 ? fail(FV_E_INADMISSIBLE, "request %lld became inadmissible", (long long)id) : FV_OK;
+}
+
+fv_status fv_server_release(fv_server *s, int64_t id)
+{
+    if (!s) return fail(FV_E_INVALID, "server is NULL");
+    auto it = s->reqs.find(id);
+    if (it == s->reqs.end() || it->second->state < 2) return fail(FV_E_INVALID, "request is not finished");
+    s->reqs.erase(it);
+    return FV_OK;
+}
+
+void fv_server_destroy(fv_server *s)
+{
+    if (!s) return;
+    (void)hipStreamSynchronize(s->stream);
+    if (s->h_items) (void)hipHostFree(s->h_items);
+    if (s->h_nitems) (void)hipHostFree(s->h_nitems);
+    delete s;
+}
+
+}  // extern "C"

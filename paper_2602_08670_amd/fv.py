@@ -62,6 +62,24 @@ class fv_train_config(ctypes.Structure):
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
+class fv_server_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("max_solves", ctypes.c_int32),
+                ("steps_per_round", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("max_items", ctypes.c_uint64)]
+
+
+class fv_request(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("eqn", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("bc", ctypes.c_int32), ("steps", ctypes.c_int64), ("cfl", ctypes.c_double), ("g", ctypes.c_double),
+                ("gamma", ctypes.c_double), ("h_ref", ctypes.c_double), ("q0", ctypes.c_void_p),
+                ("bed", ctypes.c_void_p)]
+
+
+class fv_request_info(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("pad", ctypes.c_int32), ("steps_done", ctypes.c_int64),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
+                ("sim_time", ctypes.c_double)]
+
+
 def make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0), order=1, hidden=32) -> fv_model_desc:
     d = fv_model_desc()
     d.struct_size = ctypes.sizeof(fv_model_desc)
@@ -75,6 +93,11 @@ def make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0), order=1, h
 
 
 def _load():
+    # libfv must bind to the HIP runtime instance that owns the device memory
+    # and streams it is handed: PyTorch ships its own libamdhip64 (same
+    # soname), so it is loaded first and the library's dependency resolves to it.
+    import torch  # noqa: F401
+
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built: run __graft_entry__.build() (hipcc, gfx950)")
     lib = ctypes.CDLL(LIB_PATH)
@@ -113,6 +136,15 @@ def _load():
         "fv_adam_step": ([vp], st),
         "fv_train_destroy": ([vp], None),
         "fv_coarsen": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp], st),
+        "fv_server_pool_overhead": ([ctypes.POINTER(fv_server_config)], ctypes.c_size_t),
+        "fv_request_bytes": ([ctypes.POINTER(fv_request)], ctypes.c_size_t),
+        "fv_server_create": ([ctypes.POINTER(fv_server_config), vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], st),
+        "fv_server_submit": ([vp, ctypes.POINTER(fv_request), ctypes.POINTER(i64)], st),
+        "fv_server_round": ([vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], st),
+        "fv_server_info": ([vp, i64, ctypes.POINTER(fv_request_info)], st),
+        "fv_server_result": ([vp, i64, vp], st),
+        "fv_server_release": ([vp, i64], st),
+        "fv_server_destroy": ([vp], None),
         "fv_last_error": ([], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -357,6 +389,74 @@ def coarsen(fine, factor):
     fv_coarsen(fine.contiguous().data_ptr(), nvar, nx, ny, factor, out.data_ptr(),
                torch.cuda.current_stream(fine.device).cuda_stream)
     return out
+
+
+def make_request(q0, steps, bed=None, bc=FV_BC_WALL, cfl=0.4, g=9.81, gamma=1.4, h_ref=0.0):
+    """Request over host arrays (kept referenced by the returned tuple until
+    fv_server_submit copied them)."""
+    q0 = np.ascontiguousarray(q0, dtype=np.float32)
+    nvar, n, n2 = q0.shape
+    assert n == n2
+    b = None if bed is None else np.ascontiguousarray(bed, dtype=np.float32)
+    r = fv_request(ctypes.sizeof(fv_request), FV_SWE if nvar == 3 else FV_EULER, n, bc, int(steps), cfl, g, gamma,
+                   h_ref, q0.ctypes.data, None if b is None else b.ctypes.data)
+    return r, (q0, b)
+
+
+class Server:
+    """Continuous-batching server over a torch-allocated device pool."""
+
+    def __init__(self, pool_bytes: int, max_solves: int = 1024, steps_per_round: int = 24,
+                 max_items: int = 1 << 18, device="cuda", stream=None):
+        import torch
+
+        self.cfg = fv_server_config(ctypes.sizeof(fv_server_config), max_solves, steps_per_round, 0, max_items)
+        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
+        h = ctypes.c_void_p()
+        _check(lib.fv_server_create(ctypes.byref(self.cfg), self.pool.data_ptr(), pool_bytes,
+                                    self.stream.cuda_stream, ctypes.byref(h)))
+        self.h = h
+
+    @staticmethod
+    def request_bytes(req: fv_request) -> int:
+        return lib.fv_request_bytes(ctypes.byref(req))
+
+    def submit(self, q0, steps, bed=None, **kw) -> int:
+        r, keep = make_request(q0, steps, bed, **kw)
+        rid = ctypes.c_int64()
+        _check(lib.fv_server_submit(self.h, ctypes.byref(r), ctypes.byref(rid)))
+        del keep
+        return rid.value
+
+    def round(self):
+        a, q = ctypes.c_int32(), ctypes.c_int32()
+        _check(lib.fv_server_round(self.h, ctypes.byref(a), ctypes.byref(q)))
+        return a.value, q.value
+
+    def info(self, rid: int) -> fv_request_info:
+        inf = fv_request_info()
+        _check(lib.fv_server_info(self.h, rid, ctypes.byref(inf)))
+        return inf
+
+    def result(self, rid: int, shape):
+        out = np.empty(shape, dtype=np.float32)
+        _check(lib.fv_server_result(self.h, rid, out.ctypes.data))
+        return out
+
+    def release(self, rid: int):
+        _check(lib.fv_server_release(self.h, rid))
+
+    def close(self):
+        if self.h is not None:
+            lib.fv_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def params_to_vector(weights, biases) -> np.ndarray:

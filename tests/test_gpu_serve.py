@@ -1,0 +1,106 @@
+"""Serving: continuous batching of mixed shallow-water / Euler solves.
+
+Each request's result is bit-identical to the same solve run alone through
+fv_run (the batched launch executes the single-solve kernel's per-cell code
+and each solve keeps its own CFL reduction), requests are admitted as memory
+frees up, and late arrivals overlap with running solves."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2602_08670_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fv():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2602_08670_amd import fv as F
+
+    return F
+
+
+def make_req(kind, n, seed):
+    if kind == "swe":
+        q, b = I.swe_bathy(n, seed=seed)
+        return q.astype(np.float32), b.astype(np.float32)
+    return I.euler_quadrants(n, seed=seed).astype(np.float32), None
+
+
+def alone(fv, q, b, steps):
+    s = fv.Solver(q, b, prec=fv.FV_F32, bc_x=fv.FV_BC_WALL, bc_y=fv.FV_BC_WALL)
+    s.run(steps)
+    out = s.state().astype(np.float32)
+    t, _ = s.time()
+    s.close()
+    return out, t
+
+
+def test_mix_bitwise_equals_alone(fv):
+    specs = [("swe", 64, 1, 37), ("euler", 128, 2, 50), ("swe", 200, 3, 24), ("euler", 64, 4, 61),
+             ("swe", 128, 5, 5), ("euler", 96, 6, 48)]
+    srv = fv.Server(64 << 20, max_solves=16, steps_per_round=12, max_items=1 << 14)
+    ids = []
+    for kind, n, seed, steps in specs:
+        q, b = make_req(kind, n, seed)
+        ids.append(srv.submit(q, steps, bed=b))
+    rounds = 0
+    while True:
+        a, qd = srv.round()
+        rounds += 1
+        if a == 0 and qd == 0:
+            break
+        assert rounds < 100
+    for rid, (kind, n, seed, steps) in zip(ids, specs):
+        q, b = make_req(kind, n, seed)
+        got = srv.result(rid, q.shape)
+        ref, t = alone(fv, q, b, steps)
+        inf = srv.info(rid)
+        print(f"[serve] {kind} {n}^2 {steps} steps: t={inf.sim_time:.6f} alone t={t:.6f}", flush=True)
+        assert inf.state == 2 and inf.steps_done == steps
+        assert np.array_equal(got, ref), (kind, n, steps)
+        assert inf.sim_time == t
+    srv.close()
+
+
+def test_admission_by_memory_and_late_arrivals(fv):
+    """A pool that holds only two 256^2 solves: the third waits until one
+    finishes; a request submitted while others run joins at the next round."""
+    q, b = make_req("swe", 256, 9)
+    req_bytes = fv.Server.request_bytes(fv.make_request(q, 10, bed=b)[0])
+    import ctypes
+
+    cfg_ov = fv.lib.fv_server_pool_overhead(fv.fv_server_config(ctypes.sizeof(fv.fv_server_config), 8, 10, 0,
+                                                               1 << 14))
+    assert cfg_ov > 0
+    pool = cfg_ov + 2 * req_bytes + 300 * 1024  # room for two 256^2 solves and a small one
+    srv = fv.Server(pool, max_solves=8, steps_per_round=10, max_items=1 << 14)
+    r1 = srv.submit(q, 30, bed=b)
+    r2 = srv.submit(q, 10, bed=b)
+    r3 = srv.submit(q, 10, bed=b)
+    a, qd = srv.round()
+    assert (a, qd) == (1, 1)  # r2 finished in round 1, r3 still queued (memory)
+    assert srv.info(r1).state == 1
+    assert srv.info(r3).state == 0 and srv.info(r2).state == 2
+    r4 = srv.submit(*make_req("euler", 64, 3)[:1], 20)  # late arrival, small
+    a, qd = srv.round()
+    assert srv.info(r3).state == 2 and srv.info(r4).state in (1, 2)
+    while srv.round() != (0, 0):
+        pass
+    for rid in (r1, r2, r3, r4):
+        assert srv.info(rid).state == 2
+    assert srv.info(r4).t_admit > srv.info(r1).t_admit
+    ref, _ = alone(fv, q, b, 30)
+    assert np.array_equal(srv.result(r1, q.shape), ref)
+    srv.close()
+
+
+def test_request_larger_than_pool_rejected(fv):
+    q, b = make_req("swe", 512, 1)
+    srv = fv.Server(4 << 20, max_solves=4, steps_per_round=4, max_items=1 << 12)
+    with pytest.raises(fv.FvError) as e:
+        srv.submit(q, 10, bed=b)
+    assert e.value.code == fv.FV_E_NOMEM
+    srv.close()
