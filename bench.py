@@ -37,6 +37,9 @@ def parse():
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-euler", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time for the baseline")
+    p.add_argument("--calib-copy-mb", type=int, default=0,
+                   help="before the run, copy this many MiB device-to-device once (a known-size kernel for "
+                        "calibrating hardware traffic counters)")
     return p.parse_args()
 
 
@@ -89,6 +92,12 @@ def main():
 
     n = args.n
     dev = torch.device("cuda:0")
+    if args.calib_copy_mb:
+        src = torch.ones(args.calib_copy_mb << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     q0, b = inputs.swe_bathy(n, seed=0)
     s = fv.Solver(q0, b, prec=fv.FV_F32, bc_x=fv.FV_BC_WALL, bc_y=fv.FV_BC_WALL, device=dev)
     gpu_s, wall_s = timed_run(s, args.steps, args.warmup, torch)

@@ -45,13 +45,28 @@ using fvapi::hip_fail;
 namespace {
 
 struct Layout {
-    size_t ctl, rates, totals_out, partials, s1, s2;
+    size_t ctl, rates, totals_out, partials, batch, s1, s2;
     // buffers of the learned step (cfg.learned == 1)
     size_t act0, act1, z, s2l, small;
     size_t total;
 };
 
 int nvar_of(const fv_config *c) { return c->eqn == FV_EULER ? 4 : 3; }
+
+// A solve in the configuration the server runs (FP32, HLLE, MINMOD, Heun,
+// CFL-controlled Delta t) steps through the server's batched stage kernels as
+// a batch of one, so it computes bit-identical results alone and in a mix.
+// Its device descriptor and the three per-step lists (one per rotation of
+// the CFL slots) sit in the workspace.
+constexpr size_t BATCH_TAB = 0, BATCH_ITEMS = 256, BATCH_N = 320, BATCH_BYTES = 512;
+static_assert(sizeof(fvk::BatchSolve) <= BATCH_ITEMS && BATCH_ITEMS + 3 * sizeof(fvk::WorkItem) <= BATCH_N,
+              "batch-of-one layout");
+
+bool runs_batched(const fv_config *c)
+{
+    return c->prec == FV_F32 && c->flux == FV_FLUX_HLLE && c->recon == FV_RECON_MINMOD && c->rk_stages == 2 &&
+           !(c->dt_fixed > 0) && !c->learned;
+}
 
 fv_status validate(const fv_config *c)
 {
@@ -85,7 +100,8 @@ Layout layout_of(const fv_config *c)
     L.rates = fvk::CTL_BYTES;
     L.totals_out = L.rates + fvk::RATE_BYTES;
     L.partials = L.totals_out + 256;
-    L.s1 = L.partials + align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * sizeof(double));
+    L.batch = L.partials + align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * sizeof(double));
+    L.s1 = L.batch + BATCH_BYTES;
     L.s2 = L.s1 + st;
     size_t end = L.s2 + (c->rk_stages == 3 ? st : 0);
     if (c->learned) {
@@ -115,6 +131,7 @@ struct fv_solver {
     hipStream_t stream;
     int64_t enq;  // steps enqueued since the last rate initialisation
     size_t state_bytes;
+    bool batched;
     fvk::Ctl *ctl() { return (fvk::Ctl *)(ws + L.ctl); }
     unsigned long long *rates() { return (unsigned long long *)(ws + L.rates); }
 };
@@ -152,6 +169,18 @@ fv_status enqueue_step(fv_solver *s)
     char *S1 = s->ws + s->L.s1, *S2 = s->ws + s->L.s2;
     hipError_t e = hipSuccess;
     fvk::Ctl *ctl = s->ctl();
+    if (s->batched) {
+        const char *B = s->ws + s->L.batch;
+        const auto *tab = (const fvk::BatchSolve *)(B + BATCH_TAB);
+        const auto *items = (const fvk::WorkItem *)(B + BATCH_ITEMS) + n;
+        const int *nitems = (const int *)(B + BATCH_N);
+        const int tiles = ((s->cfg.nx + fvk::TILE_X - 1) / fvk::TILE_X) * ((s->cfg.ny + fvk::TILE_Y - 1) / fvk::TILE_Y);
+        e = fvk::launch_batch_stage(s->d.eqn, s->d.bathy, 1, tab, items, nitems, tiles, s->stream);
+        if (e == hipSuccess) e = fvk::launch_batch_stage(s->d.eqn, s->d.bathy, 2, tab, items, nitems, tiles, s->stream);
+        if (e != hipSuccess) return hip_fail(e, "stage launch");
+        s->enq++;
+        return FV_OK;
+    }
     switch (s->cfg.rk_stages) {
     case 1:
         e = fvk::launch_stage(s->d, s->q, s->q, S1, s->bed, 0.0, 1.0, ctl, s->rates(), ri, ro, rc, 1, s->stream);
@@ -172,6 +201,48 @@ fv_status enqueue_step(fv_solver *s)
     }
     if (e != hipSuccess) return hip_fail(e, "stage launch");
     s->enq++;
+    return FV_OK;
+}
+
+// Descriptor and step lists of the batch-of-one path (see runs_batched).
+fv_status upload_batch(fv_solver *s)
+{
+    alignas(16) char buf[BATCH_BYTES];
+    std::memset(buf, 0, sizeof buf);
+    fvk::BatchSolve d{};
+    d.q = s->q;
+    d.s1 = s->ws + s->L.s1;
+    d.bed = s->bed;
+    d.ctl = s->ctl();
+    d.rates = s->rates();
+    d.nx = s->cfg.nx;
+    d.ny = s->cfg.ny;
+    d.bc_x = s->cfg.bc_x;
+    d.bc_y = s->cfg.bc_y;
+    d.rdx = s->d.rdx;
+    d.rdy = s->d.rdy;
+    d.g = s->cfg.g;
+    d.sqg = std::sqrt(s->cfg.g);
+    d.gamma = s->cfg.gamma;
+    d.h0 = s->d.h0;
+    d.cfl = s->cfg.cfl;
+    d.dt_fixed = 0.0;
+    std::memcpy(buf + BATCH_TAB, &d, sizeof d);
+    for (int k = 0; k < 3; k++) {
+        fvk::WorkItem it{};
+        it.solve = 0;
+        it.tile_begin = 0;
+        it.tiles_x = (s->cfg.nx + fvk::TILE_X - 1) / fvk::TILE_X;
+        it.ri = (unsigned char)k;
+        it.ro = (unsigned char)((k + 1) % 3);
+        it.rc = (unsigned char)((k + 2) % 3);
+        std::memcpy(buf + BATCH_ITEMS + k * sizeof it, &it, sizeof it);
+    }
+    const int one = 1;
+    std::memcpy(buf + BATCH_N, &one, sizeof one);
+    hipError_t e = hipMemcpyAsync(s->ws + s->L.batch, buf, sizeof buf, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // buf is on this stack frame
+    if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
     return FV_OK;
 }
 
@@ -257,6 +328,8 @@ fv_status fv_init(const fv_config *cfg, void *q, const void *bathy, void *worksp
         rc = fv_totals(s, tot);
         if (rc == FV_OK) s->d.h0 = tot[0] / (cfg->lx * cfg->ly);
     }
+    s->batched = runs_batched(cfg);
+    if (rc == FV_OK && s->batched) rc = upload_batch(s);
     if (rc != FV_OK) {
         delete s;
         return rc;

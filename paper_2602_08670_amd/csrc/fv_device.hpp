@@ -209,9 +209,12 @@ template <typename T, int EQN> __device__ __forceinline__ T cell_rate(const T *s
 // as the last entry when BATHY).  Output: flux seen by the cell on the left
 // (FlC, NV values, Cartesian order) and the normal-momentum flux seen by the
 // cell on the right (frn) -- they differ only by the hydrostatic correction.
+// With a bed, `sd` receives the two face states the centred bed source needs:
+// {h, z} of the left state and {h, z} of the right state (z = eta - h), after
+// the positivity fallback.
 // AXIS 0: x face (normal momentum is variable 1), AXIS 1: y face (variable 2).
 template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int AXIS>
-__device__ __forceinline__ void face_flux(const T (*st)[4], const Phys<T> &ph, T *FlC, T &frn)
+__device__ __forceinline__ void face_flux(const T (*st)[4], const Phys<T> &ph, T *FlC, T &frn, T *sd)
 {
     constexpr int NV = EQN == SWE ? 3 : 4;
     constexpr int NR = NV + (BATHY ? 1 : 0);
@@ -269,31 +272,53 @@ __device__ __forceinline__ void face_flux(const T (*st)[4], const Phys<T> &ph, T
     FlC[NM] = F[1] + hg * (hl - hls) * (hl + hls);
     FlC[TM] = F[2];
     frn = F[1] + hg * (hr - hrs) * (hr + hrs);
+    sd[0] = hl;
+    sd[1] = el - hl;
+    sd[2] = hr;
+    sd[3] = er - hr;
 }
 
-// Bed source of one cell along one axis, from the cell's own face states:
-// -g (h_{i-1/2+} + h_{i+1/2-})/2 (z_{i+1/2-} - z_{i-1/2+}) / dx.
-// Inputs: depth and free surface of cells i-1, i, i+1 along the axis.
-template <typename T, int RECON>
-__device__ __forceinline__ T bed_source(T hm, T h0, T hp, T em, T e0, T ep, T g, T rdx)
+template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int AXIS>
+__device__ __forceinline__ void face_flux(const T (*st)[4], const Phys<T> &ph, T *FlC, T &frn)
 {
-    T hR, hL, eR, eL;  // hR: state at face i+1/2 from the left; hL: at i-1/2 from the right
-    if (RECON == FIRST) {
-        hR = hL = h0;
-        eR = eL = e0;
-    } else {
-        T sh = minmod(h0 - hm, hp - h0), se = minmod(e0 - em, ep - e0);
-        hR = h0 + T(0.5) * sh;
-        hL = h0 - T(0.5) * sh;
-        eR = e0 + T(0.5) * se;
-        eL = e0 - T(0.5) * se;
-        bool okR = hR > T(0), okL = hL > T(0);
-        eR = okR ? eR : e0;
-        hR = okR ? hR : h0;
-        eL = okL ? eL : e0;
-        hL = okL ? hL : h0;
+    T sd[4];
+    face_flux<T, EQN, BATHY, FLUX, RECON, AXIS>(st, ph, FlC, frn, sd);
+}
+
+// What one face hands to its two cells, for kernels that pass face results
+// between lanes: TL to the cell on the left (below), TR to the cell on the
+// right (above).  Entries 0..NV-1: the flux that cell sees (the two differ
+// only in the normal momentum, by the hydrostatic correction); with a bed,
+// entries NV and NV+1: depth and bed height of the face state on that side.
+template <typename T, int EQN, bool BATHY> struct FaceSide {
+    static constexpr int NV = EQN == SWE ? 3 : 4;
+    static constexpr int N = NV + (BATHY ? 2 : 0);
+};
+
+template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int AXIS>
+__device__ __forceinline__ void face_eval(const T (*st)[4], const Phys<T> &ph, T *TL, T *TR)
+{
+    constexpr int NV = FaceSide<T, EQN, BATHY>::NV;
+    constexpr int NM = AXIS == 0 ? 1 : 2;
+    T F[NV], frn, sd[4];
+    face_flux<T, EQN, BATHY, FLUX, RECON, AXIS>(st, ph, F, frn, sd);
+#pragma unroll
+    for (int v = 0; v < NV; v++) TL[v] = TR[v] = F[v];
+    TR[NM] = frn;
+    if (BATHY) {
+        TL[NV] = sd[0];
+        TL[NV + 1] = sd[1];
+        TR[NV] = sd[2];
+        TR[NV + 1] = sd[3];
     }
-    return -g * T(0.5) * (hL + hR) * ((eR - hR) - (eL - hL)) * rdx;
+}
+
+// Centred bed source of one cell along one axis (hydrostatic reconstruction):
+// -g (h_{i-1/2+} + h_{i+1/2-})/2 (z_{i+1/2-} - z_{i-1/2+}) / dx, from the
+// face state at the cell's low face (hL, zL) and at its high face (hR, zR).
+template <typename T> __device__ __forceinline__ T bed_centred(T hL, T zL, T hR, T zR, T g, T rdx)
+{
+    return -g * T(0.5) * (hL + hR) * (zR - zL) * rdx;
 }
 
 }  // namespace fvk

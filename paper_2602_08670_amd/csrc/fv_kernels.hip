@@ -46,6 +46,14 @@ template <typename T> struct StageArgs {
     int rate_in, rate_out, rate_clear, last;
 };
 
+// Global-memory view of a pointer.  The batched kernels read their array
+// pointers from a device descriptor, where the compiler cannot see that they
+// address global memory; it would then emit flat accesses, which may alias
+// LDS and so are ordered behind every LDS store.
+template <typename T> using gmem = __attribute__((address_space(1))) T;
+template <typename T> __device__ __forceinline__ const gmem<T> *gload(const T *p) { return (const gmem<T> *)p; }
+template <typename T> __device__ __forceinline__ gmem<T> *gstore(T *p) { return (gmem<T> *)p; }
+
 template <typename T> __device__ __forceinline__ T wave_max(T v)
 {
 #pragma unroll
@@ -57,7 +65,7 @@ template <typename T> __device__ __forceinline__ T wave_max(T v)
 static_assert(RATE_SUB == 64, "one sub-slot per lane");
 __device__ __forceinline__ double read_rate(unsigned long long *rates, int k)
 {
-    return wave_max(__longlong_as_double(*rate_slot(rates, k, threadIdx.x & 63)));
+    return wave_max(__longlong_as_double(*gload(rate_slot(rates, k, threadIdx.x & 63))));
 }
 
 __device__ __forceinline__ void push_rate(unsigned long long *rates, int k, double m, int block_linear)
@@ -89,44 +97,73 @@ template <typename T> __device__ __forceinline__ T block_max256(T v, T *red)
     return m;
 }
 
+// Lane l receives v from lane l + 1 of its wave (DPP wave shift); lane 63
+// receives `edge`.  Every lane of the wave must be active.
+__device__ __forceinline__ float from_right(float v, float edge)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xf, 0xf, false));
+}
+__device__ __forceinline__ double from_right(double v, double edge)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const unsigned long long e = (unsigned long long)__double_as_longlong(edge);
+    const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)e, (int)(unsigned)b, 0x130, 0xf, 0xf, false);
+    const unsigned hi =
+        (unsigned)__builtin_amdgcn_update_dpp((int)(unsigned)(e >> 32), (int)(unsigned)(b >> 32), 0x130, 0xf, 0xf, false);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // One RK stage on the TX x TY tile at (x0, y0).  `tile_linear` is the tile's
 // index within its solve; the tile with index 0 does the per-step
 // bookkeeping of the solve.  Shared by the single-solve kernel and the
 // batched kernel, so a solve computes bit-identical results in both.
+//
+// Work split: lane = column, wave w owns tile rows [w*RPW, (w+1)*RPW).  Each
+// lane evaluates the low x face and the low y face of each of its cells, so
+// face results stay in registers: the high x face arrives from lane + 1 by a
+// DPP shift, the high y face from the same lane's next row.  Faces with no
+// owner inside the wave are the tile's right column (one lane per row, wave
+// 0, through LDS), the tile's top row (last wave) and the low face of each
+// wave's first row, which the wave below reads through LDS.
 template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int TX, int TY>
 __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, const int y0, const int tile_linear)
 {
+    static_assert(TX == 64, "a tile row is one wave64");
+    static_assert(TY % 4 == 0 && TY <= 64, "four waves, whole rows each");
+    constexpr int NW = 4, RPW = TY / NW;
     constexpr int NV = EQN == SWE ? 3 : 4;
-    constexpr int NL = NV + (BATHY ? 1 : 0);
-    constexpr int NF = NV + (BATHY ? 1 : 0);
+    constexpr int NL = NV + (BATHY ? 1 : 0);  // LDS planes: variables (+ eta)
+    constexpr int NT = FaceSide<T, EQN, BATHY>::N;
     constexpr int HX = TX + 4, HY = TY + 4;
     __shared__ T s_q[NL][HY][HX];
-    __shared__ T s_fx[NF][TY][TX + 1];
-    __shared__ T s_fy[NF][TY + 1][TX];
-    __shared__ T s_red[4];
+    __shared__ T s_edge[NT][TY];         // right face of column TX-1, handed to that cell
+    __shared__ T s_low[NW - 1][NT][TX];  // low y face of wave w+1's first row, handed to wave w
+    __shared__ T s_red[NW];
+    __shared__ double s_dt;
 
-    if (a.ctl->bad) return;  // an earlier step failed: the state is frozen
-    const int tid = threadIdx.x;
+    if (gload(a.ctl)->bad) return;  // an earlier step failed: the state is frozen
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int r0 = wave * RPW;
     const int nx = a.nx, ny = a.ny;
     const size_t plane = (size_t)nx * ny;
+    const size_t tbase = (size_t)y0 * nx + x0;
 
-    const double dtd = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl / read_rate(a.rates, a.rate_in);
-    const T dt = (T)dtd;
+    if (wave == 1) {
+        const double d = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl / read_rate(a.rates, a.rate_in);
+        if (lane == 0) s_dt = d;
+    }
 
     // q0 is needed only in the final combine: load it now so its latency
     // hides behind the face work
-    constexpr int CPT = (TX * TY + 255) / 256;  // cells per thread
-    T q0r[CPT][NV];
+    T q0r[RPW][NV];
     if (a.a0 != T(0)) {
 #pragma unroll
-        for (int c = 0; c < CPT; c++) {
-            int k = tid + c * 256;
-            int cy = k / TX, cx = k - cy * TX;
-            int gx = x0 + cx, gy = y0 + cy;
-            bool in = k < TX * TY && gx < nx && gy < ny;
-            size_t idx = in ? (size_t)gy * nx + gx : 0;
+        for (int j = 0; j < RPW; j++) {
+            const int cy = r0 + j;
+            const bool in = x0 + lane < nx && y0 + cy < ny;
+            const unsigned off = in ? (unsigned)(cy * nx + lane) : 0u;
 #pragma unroll
-            for (int v = 0; v < NV; v++) q0r[c][v] = a.q0[v * plane + idx];
+            for (int v = 0; v < NV; v++) q0r[j][v] = gload(a.q0 + v * plane + tbase)[off];
         }
     }
 
@@ -134,19 +171,29 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
     //    the grid (all but the border tiles) index directly.
     const bool inner = x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= nx && y0 + TY + 2 <= ny;
     if (inner) {
-        const T *base = a.qs + (size_t)(y0 - 2) * nx + (x0 - 2);
-        const T *bbase = BATHY ? a.bed + (size_t)(y0 - 2) * nx + (x0 - 2) : nullptr;
-        int ly = tid / HX, lx = tid - ly * HX;
-        for (int k = tid; k < HY * HX; k += 256) {
-            size_t off = (size_t)ly * nx + lx;
+        // every load is issued before the first LDS store; the last pass
+        // re-reads the tile's first halo element on lanes past the end
+        constexpr int NIT = (HY * HX + 255) / 256;
+        const size_t hb = tbase - 2 * (size_t)nx - 2;
+        T val[NIT][NL];
 #pragma unroll
-            for (int v = 0; v < NV; v++) s_q[v][ly][lx] = base[v * plane + off];
-            if (BATHY) s_q[NV][ly][lx] = s_q[0][ly][lx] + bbase[off];
-            lx += 256 % HX;
-            ly += 256 / HX;
-            if (lx >= HX) {
-                lx -= HX;
-                ly += 1;
+        for (int it = 0; it < NIT; it++) {
+            const int e = tid + it * 256;
+            const int ec = e < HY * HX ? e : 0;
+            const int ly = ec / HX, lx = ec - ly * HX;
+            const unsigned off = (unsigned)(ly * nx + lx);
+#pragma unroll
+            for (int v = 0; v < NV; v++) val[it][v] = gload(a.qs + v * plane + hb)[off];
+            if (BATHY) val[it][NV] = gload(a.bed + hb)[off];
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int e = tid + it * 256;
+            if (e < HY * HX) {
+                const int ly = e / HX, lx = e - ly * HX;
+#pragma unroll
+                for (int v = 0; v < NV; v++) s_q[v][ly][lx] = val[it][v];
+                if (BATHY) s_q[NV][ly][lx] = val[it][0] + val[it][NV];
             }
         }
     } else {
@@ -156,86 +203,122 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
             int ix = map_index(x0 - 2 + lx, nx, a.bc_x, fx);
             int iy = map_index(y0 - 2 + ly, ny, a.bc_y, fy);
             size_t idx = (size_t)iy * nx + ix;
+            T val[NV];
 #pragma unroll
-            for (int v = 0; v < NV; v++) {
-                T val = a.qs[v * plane + idx];
-                if ((v == 1 && fx) || (v == 2 && fy)) val = -val;
-                s_q[v][ly][lx] = val;
-            }
-            if (BATHY) s_q[NV][ly][lx] = s_q[0][ly][lx] + a.bed[idx];
+            for (int v = 0; v < NV; v++) val[v] = gload(a.qs)[v * plane + idx];
+            const T b = BATHY ? gload(a.bed)[idx] : T(0);
+#pragma unroll
+            for (int v = 0; v < NV; v++) s_q[v][ly][lx] = ((v == 1 && fx) || (v == 2 && fy)) ? -val[v] : val[v];
+            if (BATHY) s_q[NV][ly][lx] = val[0] + b;
         }
     }
     __syncthreads();
+    const T dt = (T)s_dt;
 
-    // 2a. x faces: face fi of row fj lies between halo cells fi+1 and fi+2
-    for (int f = tid; f < TY * (TX + 1); f += 256) {
-        int fj = f / (TX + 1), fi = f - fj * (TX + 1);
+    // 2. faces with no owner lane: the tile's right column and top row
+    if (wave == 0 && lane < TY) {
         T st[NL][4];
 #pragma unroll
         for (int v = 0; v < NL; v++)
 #pragma unroll
-            for (int k = 0; k < 4; k++) st[v][k] = s_q[v][fj + 2][fi + k];
-        T Fl[NV], frn;
-        face_flux<T, EQN, BATHY, FLUX, RECON, 0>(st, a.ph, Fl, frn);
+            for (int k = 0; k < 4; k++) st[v][k] = s_q[v][lane + 2][TX + k];
+        T tl[NT], tr[NT];
+        face_eval<T, EQN, BATHY, FLUX, RECON, 0>(st, a.ph, tl, tr);
 #pragma unroll
-        for (int v = 0; v < NV; v++) s_fx[v][fj][fi] = Fl[v];
-        if (BATHY) s_fx[NV][fj][fi] = frn;
+        for (int k = 0; k < NT; k++) s_edge[k][lane] = tl[k];
     }
-    // 2b. y faces: face fj of column fi lies between halo rows fj+1 and fj+2
-    for (int f = tid; f < (TY + 1) * TX; f += 256) {
-        int fj = f / TX, fi = f - fj * TX;
+    T top[NT];  // low-side values of the y face above this wave's last row
+    if (wave == NW - 1) {
         T st[NL][4];
 #pragma unroll
         for (int v = 0; v < NL; v++)
 #pragma unroll
-            for (int k = 0; k < 4; k++) st[v][k] = s_q[v][fj + k][fi + 2];
-        T Fl[NV], frn;
-        face_flux<T, EQN, BATHY, FLUX, RECON, 1>(st, a.ph, Fl, frn);
+            for (int k = 0; k < 4; k++) st[v][k] = s_q[v][TY + k][lane + 2];
+        T tr[NT];
+        face_eval<T, EQN, BATHY, FLUX, RECON, 1>(st, a.ph, top, tr);
+    }
+
+    // 3. y faces: the low face of every own row, evaluated from the last row
+    //    down so that each row's y divergence can be formed at once
+    T Ly[RPW][NV];
+    T lowR[NT];  // high-side values of the low face of the wave's first row
 #pragma unroll
-        for (int v = 0; v < NV; v++) s_fy[v][fj][fi] = Fl[v];
-        if (BATHY) s_fy[NV][fj][fi] = frn;
+    for (int j = RPW - 1; j >= 0; j--) {
+        const int cy = r0 + j;
+        T st[NL][4];
+#pragma unroll
+        for (int v = 0; v < NL; v++)
+#pragma unroll
+            for (int k = 0; k < 4; k++) st[v][k] = s_q[v][cy + k][lane + 2];
+        T tl[NT], tr[NT];
+        face_eval<T, EQN, BATHY, FLUX, RECON, 1>(st, a.ph, tl, tr);
+        if (j == RPW - 1) {
+            if (wave == NW - 1) {
+#pragma unroll
+                for (int v = 0; v < NV; v++) Ly[j][v] = -(top[v] - tr[v]) * a.rdy;
+                if (BATHY) Ly[j][2] += bed_centred(tr[NV], tr[NV + 1], top[NV], top[NV + 1], a.ph.g, a.rdy);
+            } else {
+#pragma unroll
+                for (int k = 0; k < NT; k++) lowR[k] = tr[k];  // finished after the exchange
+            }
+        } else {
+#pragma unroll
+            for (int v = 0; v < NV; v++) Ly[j][v] = -(top[v] - tr[v]) * a.rdy;
+            if (BATHY) Ly[j][2] += bed_centred(tr[NV], tr[NV + 1], top[NV], top[NV + 1], a.ph.g, a.rdy);
+        }
+        if (j == 0 && wave > 0) {
+#pragma unroll
+            for (int k = 0; k < NT; k++) s_low[wave - 1][k][lane] = tl[k];
+        }
+#pragma unroll
+        for (int k = 0; k < NT; k++) top[k] = tl[k];
     }
     __syncthreads();
+    if (wave < NW - 1) {
+        T up[NT];
+#pragma unroll
+        for (int k = 0; k < NT; k++) up[k] = s_low[wave][k][lane];
+#pragma unroll
+        for (int v = 0; v < NV; v++) Ly[RPW - 1][v] = -(up[v] - lowR[v]) * a.rdy;
+        if (BATHY) Ly[RPW - 1][2] += bed_centred(lowR[NV], lowR[NV + 1], up[NV], up[NV + 1], a.ph.g, a.rdy);
+    }
 
-    // 3. divergence + source + RK combine
+    // 4. x faces, divergence, bed source, RK combine
     T lmax = T(0);
     bool bad = false;
 #pragma unroll
-    for (int c = 0; c < CPT; c++) {
-        int k = tid + c * 256;
-        int cy = k / TX, cx = k - cy * TX;
-        int gx = x0 + cx, gy = y0 + cy;
-        if (k >= TX * TY || gx >= nx || gy >= ny) continue;
-        size_t idx = (size_t)gy * nx + gx;
+    for (int j = 0; j < RPW; j++) {
+        const int cy = r0 + j;
+        T st[NL][4];
+#pragma unroll
+        for (int v = 0; v < NL; v++)
+#pragma unroll
+            for (int k = 0; k < 4; k++) st[v][k] = s_q[v][cy + 2][lane + k];
+        T tl[NT], tr[NT], rt[NT];
+        face_eval<T, EQN, BATHY, FLUX, RECON, 0>(st, a.ph, tl, tr);
+#pragma unroll
+        for (int k = 0; k < NT; k++) rt[k] = from_right(tl[k], s_edge[k][cy]);
         T Lv[NV];
 #pragma unroll
-        for (int v = 0; v < NV; v++) {
-            T fxm = (BATHY && v == 1) ? s_fx[NV][cy][cx] : s_fx[v][cy][cx];
-            T fym = (BATHY && v == 2) ? s_fy[NV][cy][cx] : s_fy[v][cy][cx];
-            T lxv = -(s_fx[v][cy][cx + 1] - fxm) * a.rdx;
-            T lyv = -(s_fy[v][cy + 1][cx] - fym) * a.rdy;
-            Lv[v] = lxv + lyv;
-        }
-        if (BATHY) {
-            const int hx = cx + 2, hy = cy + 2;
-            Lv[1] += bed_source<T, RECON>(s_q[0][hy][hx - 1], s_q[0][hy][hx], s_q[0][hy][hx + 1],
-                                          s_q[NV][hy][hx - 1], s_q[NV][hy][hx], s_q[NV][hy][hx + 1], a.ph.g,
-                                          a.rdx);
-            Lv[2] += bed_source<T, RECON>(s_q[0][hy - 1][hx], s_q[0][hy][hx], s_q[0][hy + 1][hx],
-                                          s_q[NV][hy - 1][hx], s_q[NV][hy][hx], s_q[NV][hy + 1][hx], a.ph.g,
-                                          a.rdy);
-        }
-        T qn[NV];
+        for (int v = 0; v < NV; v++) Lv[v] = -(rt[v] - tr[v]) * a.rdx;
+        if (BATHY) Lv[1] += bed_centred(tr[NV], tr[NV + 1], rt[NV], rt[NV + 1], a.ph.g, a.rdx);
 #pragma unroll
-        for (int v = 0; v < NV; v++) {
-            T o = a.a1 * (s_q[v][cy + 2][cx + 2] + dt * Lv[v]);
-            if (a.a0 != T(0)) o = a.a0 * q0r[c][v] + o;
-            a.out[v * plane + idx] = o;
-            qn[v] = o;
-        }
-        if (a.last) {
-            if (!cell_finite_ok<T, EQN>(qn, a.ph.gamma)) bad = true;
-            else if (a.rate_out >= 0) lmax = tmax(lmax, cell_rate<T, EQN>(qn, a.ph, a.rdx, a.rdy));
+        for (int v = 0; v < NV; v++) Lv[v] = Lv[v] + Ly[j][v];  // each axis complete, then summed
+        const bool in = x0 + lane < nx && y0 + cy < ny;
+        if (in) {
+            const unsigned off = (unsigned)(cy * nx + lane);
+            T qn[NV];
+#pragma unroll
+            for (int v = 0; v < NV; v++) {
+                T o = a.a1 * (st[v][2] + dt * Lv[v]);
+                if (a.a0 != T(0)) o = a.a0 * q0r[j][v] + o;
+                gstore(a.out + v * plane + tbase)[off] = o;
+                qn[v] = o;
+            }
+            if (a.last) {
+                if (!cell_finite_ok<T, EQN>(qn, a.ph.gamma)) bad = true;
+                else if (a.rate_out >= 0) lmax = tmax(lmax, cell_rate<T, EQN>(qn, a.ph, a.rdx, a.rdy));
+            }
         }
     }
     if (!a.last) return;
@@ -246,7 +329,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
     }
     if (tile_linear == 0) {
         if (tid == 0) {
-            a.ctl->t += dtd;
+            a.ctl->t += (double)s_dt;
             a.ctl->step += 1;
         }
         if (a.rate_clear >= 0 && tid < RATE_SUB) *rate_slot(a.rates, a.rate_clear, tid) = 0ull;
