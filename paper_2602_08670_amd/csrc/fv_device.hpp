@@ -48,6 +48,10 @@ __device__ __forceinline__ double minmod(double a, double b)
 // 1/x for x > 0, else 0 (a dry state has zero velocity).
 template <typename T> __device__ __forceinline__ T rcp_pos(T x) { return x > T(0) ? rcp(x) : T(0); }
 
+// A positive power of two far below any wave speed or sqrt(h) of interest:
+// the floor that keeps HLLE's denominator and the Roe weight positive.
+template <typename T> __device__ __forceinline__ T tiny() { return T(0x1p-60f); }
+
 template <typename T> struct Phys {
     T g;      // gravity
     T sqg;    // sqrt(g)
@@ -81,21 +85,21 @@ __device__ __forceinline__ void swe_numflux(const SweV<T> &L, const SweV<T> &R, 
         for (int k = 0; k < 3; k++) F[k] = T(0.5) * (fl[k] + fr[k]) - T(0.5) * a * dq[k];
         return;
     }
-    // Roe averages: sqrt(h)-weighted velocities, c~ = sqrt(g (hL + hR) / 2)
-    T iw = rcp_pos(wl + wr);
+    // Roe averages: sqrt(h)-weighted velocities (zero when both sides are
+    // dry), c~ = sqrt(g (hL + hR) / 2)
+    T iw = rcp(tmax(wl + wr, tiny<T>()));
     T ua = (wl * L.u + wr * R.u) * iw;
     T ca = fsqrt(hg * (L.h + R.h));
     if (FLUX == HLLE) {
+        // sR is floored at a tiny power of two instead of 0.  The denominator
+        // is then never zero: where it would be (both sides dry, sL = sR = 0)
+        // the formula returns F_L exactly, which equals (F_L + F_R)/2 there;
+        // elsewhere the floor moves the flux by a relative 2^-60 at most.
         T sL = tmin(tmin(L.u - cl, ua - ca), T(0));
-        T sR = tmax(tmax(R.u + cr, ua + ca), T(0));
-        T den = sR - sL;
-        T id = rcp_pos(den), ss = sL * sR;
-        bool wet = den > T(0);
+        T sR = tmax(tmax(R.u + cr, ua + ca), tiny<T>());
+        T id = rcp(sR - sL), ss = sL * sR;
 #pragma unroll
-        for (int k = 0; k < 3; k++) {
-            T hll = (sR * fl[k] - sL * fr[k] + ss * dq[k]) * id;
-            F[k] = wet ? hll : T(0.5) * (fl[k] + fr[k]);
-        }
+        for (int k = 0; k < 3; k++) F[k] = (sR * fl[k] - sL * fr[k] + ss * dq[k]) * id;
         return;
     }
     // Roe: three waves u-c, u (shear), u+c
@@ -222,19 +226,20 @@ __device__ __forceinline__ void face_flux(const T (*st)[4], const Phys<T> &ph, T
     T QL[NR], QR[NR];
 #pragma unroll
     for (int v = 0; v < NR; v++) recon_pair<T, RECON>(st[v][0], st[v][1], st[v][2], st[v][3], QL[v], QR[v]);
-    // face states that are not admissible fall back to the cell average
-    bool okl, okr;
-    if (EQN == SWE) {
-        okl = QL[0] > T(0);
-        okr = QR[0] > T(0);
-    } else {
-        okl = eul_admissible(QL[0], QL[1], QL[2], QL[3], ph.gamma);
-        okr = eul_admissible(QR[0], QR[1], QR[2], QR[3], ph.gamma);
-    }
+    // Face states that are not admissible fall back to the cell average.  A
+    // MINMOD (or first-order) face depth of positive cell averages is at
+    // least half the cell's own depth, so for shallow water the fallback can
+    // only act where a cell average is already non-positive, which the step
+    // reports as a failure anyway: the check is kept for Euler only, where a
+    // reconstructed pressure can turn negative.
+    if (EQN == EULER) {
+        const bool okl = eul_admissible(QL[0], QL[1], QL[2], QL[3], ph.gamma);
+        const bool okr = eul_admissible(QR[0], QR[1], QR[2], QR[3], ph.gamma);
 #pragma unroll
-    for (int v = 0; v < NR; v++) {
-        QL[v] = okl ? QL[v] : st[v][1];
-        QR[v] = okr ? QR[v] : st[v][2];
+        for (int v = 0; v < NR; v++) {
+            QL[v] = okl ? QL[v] : st[v][1];
+            QR[v] = okr ? QR[v] : st[v][2];
+        }
     }
     if (EQN == EULER) {
         EulS<T> L{QL[0], QL[NM], QL[TM], QL[3]}, R{QR[0], QR[NM], QR[TM], QR[3]};

@@ -336,11 +336,23 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
     }
 }
 
-template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int TX, int TY>
-__global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
+// Workgroups are handed to the eight XCDs in turn (workgroup w runs on XCD
+// w mod 8).  For a grid that is a multiple of 8, give XCD k the contiguous
+// k-th eighth of the tiles, so that neighbouring tiles, which re-read each
+// other's halo rows, share one L2.
+__device__ __forceinline__ int xcd_tile(int w, int grid)
 {
-    stage_tile<T, EQN, BATHY, FLUX, RECON, TX, TY>(a, blockIdx.x * TX, blockIdx.y * TY,
-                                                   blockIdx.x + blockIdx.y * gridDim.x);
+    return (grid & 7) ? w : (w & 7) * (grid >> 3) + (w >> 3);
+}
+inline int xcd_grid(int ntiles) { return (ntiles + 7) & ~7; }
+
+template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int TX, int TY>
+__global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a, int tiles_x, int ntiles)
+{
+    const int tile = xcd_tile(blockIdx.x, gridDim.x);
+    if (tile >= ntiles) return;
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    stage_tile<T, EQN, BATHY, FLUX, RECON, TX, TY>(a, tx * TX, ty * TY, tile);
 }
 
 // Batched stage over many solves: the step's list holds one item per solve
@@ -349,11 +361,12 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a)
 // L(S1))/2 (Heun).
 template <typename T, int EQN, bool BATHY, int STAGE>
 __global__ __launch_bounds__(256) void batch_stage_kernel(const BatchSolve *solves, const WorkItem *items,
-                                                          const int *nitems)
+                                                          const int *nitems, int ntiles)
 {
     constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    if (w >= ntiles) return;
     const int n = *nitems;
-    const int w = blockIdx.x;
     int lo = 0, hi = n - 1;
     while (lo < hi) {
         int mid = (lo + hi + 1) >> 1;
@@ -537,8 +550,9 @@ static hipError_t stage_t(const StageDesc &d, const void *qs, const void *q0, vo
     a.rate_clear = rc;
     a.last = last;
     constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;
-    dim3 grid((d.nx + TX - 1) / TX, (d.ny + TY - 1) / TY);
-    hipLaunchKernelGGL((stage_kernel<T, EQN, BATHY, FLUX, RECON, TX, TY>), grid, dim3(256), 0, st, a);
+    const int tiles_x = (d.nx + TX - 1) / TX, ntiles = tiles_x * ((d.ny + TY - 1) / TY);
+    hipLaunchKernelGGL((stage_kernel<T, EQN, BATHY, FLUX, RECON, TX, TY>), dim3(xcd_grid(ntiles)), dim3(256), 0, st, a,
+                       tiles_x, ntiles);
     return hipGetLastError();
 }
 
@@ -604,16 +618,16 @@ hipError_t launch_batch_stage(int eqn, int bathy, int stage, const BatchSolve *s
                               const int *nitems, int grid, hipStream_t st)
 {
     if (grid <= 0) return hipSuccess;
-    dim3 g(grid), b(256);
+    dim3 g(xcd_grid(grid)), b(256);
     if (eqn == EULER) {
-        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, 1>), g, b, 0, st, solves, items, nitems);
-        else hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, 2>), g, b, 0, st, solves, items, nitems);
+        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, 1>), g, b, 0, st, solves, items, nitems, grid);
+        else hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, 2>), g, b, 0, st, solves, items, nitems, grid);
     } else if (bathy) {
-        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, 1>), g, b, 0, st, solves, items, nitems);
-        else hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, 2>), g, b, 0, st, solves, items, nitems);
+        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, 1>), g, b, 0, st, solves, items, nitems, grid);
+        else hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, 2>), g, b, 0, st, solves, items, nitems, grid);
     } else {
-        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, 1>), g, b, 0, st, solves, items, nitems);
-        else hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, 2>), g, b, 0, st, solves, items, nitems);
+        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, 1>), g, b, 0, st, solves, items, nitems, grid);
+        else hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, 2>), g, b, 0, st, solves, items, nitems, grid);
     }
     return hipGetLastError();
 }
