@@ -175,8 +175,8 @@ fv_status enqueue_step(fv_solver *s)
         const auto *items = (const fvk::WorkItem *)(B + BATCH_ITEMS) + n;
         const int *nitems = (const int *)(B + BATCH_N);
         const int tiles = ((s->cfg.nx + fvk::TILE_X - 1) / fvk::TILE_X) * ((s->cfg.ny + fvk::TILE_Y - 1) / fvk::TILE_Y);
-        e = fvk::launch_batch_stage(s->d.eqn, s->d.bathy, 1, tab, items, nitems, tiles, s->stream);
-        if (e == hipSuccess) e = fvk::launch_batch_stage(s->d.eqn, s->d.bathy, 2, tab, items, nitems, tiles, s->stream);
+        e = fvk::launch_batch_stage(s->d.eqn, s->d.bathy, 1, tab, items, nitems, tiles, s->stream, 1);
+        if (e == hipSuccess) e = fvk::launch_batch_stage(s->d.eqn, s->d.bathy, 2, tab, items, nitems, tiles, s->stream, 1);
         if (e != hipSuccess) return hip_fail(e, "stage launch");
         s->enq++;
         return FV_OK;

@@ -67,9 +67,13 @@ struct WorkItem {
     int tiles_x;     // tiles per row of the solve; tile = workgroup - tile_begin, row-major
     unsigned char ri, ro, rc, pad;
 };
-constexpr int TILE_X = 64, TILE_Y = 8;  // FP32 tile of the stage kernels
+#ifndef FV_TILE_Y
+#define FV_TILE_Y 8
+#endif
+constexpr int TILE_X = 64, TILE_Y = FV_TILE_Y;  // FP32 tile of the stage kernels
+// one != 0 declares that the list holds exactly one solve, solves[0].
 hipError_t launch_batch_stage(int eqn, int bathy, int stage, const BatchSolve *solves, const WorkItem *items,
-                              const int *nitems, int grid, hipStream_t st);
+                              const int *nitems, int grid, hipStream_t st, int one = 0);
 
 // Reduce the CFL rate of q into ctl->rate[slot] and flag inadmissible cells.
 hipError_t launch_rate(const StageDesc &d, const void *q, Ctl *ctl, unsigned long long *rates, int slot,

@@ -28,7 +28,8 @@ __device__ __forceinline__ int map_index(int i, int n, int bc, bool &flip)
 }
 
 template <typename T> struct Tile;
-template <> struct Tile<float> { static constexpr int X = 64, Y = 8; };
+template <> struct Tile<float> { static constexpr int X = TILE_X, Y = TILE_Y; };
+static_assert(TILE_X == 64, "a tile row is one wave64");
 template <> struct Tile<double> { static constexpr int X = 64, Y = 8; };
 
 template <typename T> struct StageArgs {
@@ -141,7 +142,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
     __shared__ T s_red[NW];
     __shared__ double s_dt;
 
-    if (gload(a.ctl)->bad) return;  // an earlier step failed: the state is frozen
+    // An earlier step failed: the state is frozen.  The flag is checked only
+    // where something would be written, so its load is off the critical path.
+    const bool frozen = gload(a.ctl)->bad != 0;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int r0 = wave * RPW;
     const int nx = a.nx, ny = a.ny;
@@ -153,8 +156,29 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
         if (lane == 0) s_dt = d;
     }
 
-    // q0 is needed only in the final combine: load it now so its latency
-    // hides behind the face work
+    // 1. halo tile -> LDS with ghost synthesis.  Tiles whose halo lies inside
+    //    the grid (all but the border tiles) index directly.
+    const bool inner = x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= nx && y0 + TY + 2 <= ny;
+    // every halo load is issued before the first LDS store, and before the
+    // q0 loads; the last pass re-reads the tile's first halo element on lanes
+    // past the end
+    constexpr int NIT = (HY * HX + 255) / 256;
+    T val[NIT][NL];
+    if (inner) {
+        const size_t hb = tbase - 2 * (size_t)nx - 2;
+#pragma unroll
+        for (int it = 0; it < NIT; it++) {
+            const int e = tid + it * 256;
+            const int ec = e < HY * HX ? e : 0;
+            const int ly = ec / HX, lx = ec - ly * HX;
+            const unsigned off = (unsigned)(ly * nx + lx);
+#pragma unroll
+            for (int v = 0; v < NV; v++) val[it][v] = gload(a.qs + v * plane + hb)[off];
+            if (BATHY) val[it][NV] = gload(a.bed + hb)[off];
+        }
+    }
+    // q0 is needed only in the final combine: load it after the halo so its
+    // latency hides behind the face work
     T q0r[RPW][NV];
     if (a.a0 != T(0)) {
 #pragma unroll
@@ -167,25 +191,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
         }
     }
 
-    // 1. halo tile -> LDS with ghost synthesis.  Tiles whose halo lies inside
-    //    the grid (all but the border tiles) index directly.
-    const bool inner = x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= nx && y0 + TY + 2 <= ny;
     if (inner) {
-        // every load is issued before the first LDS store; the last pass
-        // re-reads the tile's first halo element on lanes past the end
-        constexpr int NIT = (HY * HX + 255) / 256;
-        const size_t hb = tbase - 2 * (size_t)nx - 2;
-        T val[NIT][NL];
-#pragma unroll
-        for (int it = 0; it < NIT; it++) {
-            const int e = tid + it * 256;
-            const int ec = e < HY * HX ? e : 0;
-            const int ly = ec / HX, lx = ec - ly * HX;
-            const unsigned off = (unsigned)(ly * nx + lx);
-#pragma unroll
-            for (int v = 0; v < NV; v++) val[it][v] = gload(a.qs + v * plane + hb)[off];
-            if (BATHY) val[it][NV] = gload(a.bed + hb)[off];
-        }
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
             const int e = tid + it * 256;
@@ -304,7 +310,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
         if (BATHY) Lv[1] += bed_centred(tr[NV], tr[NV + 1], rt[NV], rt[NV + 1], a.ph.g, a.rdx);
 #pragma unroll
         for (int v = 0; v < NV; v++) Lv[v] = Lv[v] + Ly[j][v];  // each axis complete, then summed
-        const bool in = x0 + lane < nx && y0 + cy < ny;
+        const bool in = x0 + lane < nx && y0 + cy < ny && !frozen;
         if (in) {
             const unsigned off = (unsigned)(cy * nx + lane);
             T qn[NV];
@@ -312,7 +318,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
             for (int v = 0; v < NV; v++) {
                 T o = a.a1 * (st[v][2] + dt * Lv[v]);
                 if (a.a0 != T(0)) o = a.a0 * q0r[j][v] + o;
-                gstore(a.out + v * plane + tbase)[off] = o;
+                __builtin_nontemporal_store(o, gstore(a.out + v * plane + tbase) + off);
                 qn[v] = o;
             }
             if (a.last) {
@@ -321,7 +327,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
             }
         }
     }
-    if (!a.last) return;
+    if (!a.last || frozen) return;
     if (bad) atomicExch(&a.ctl->bad, 1);
     if (a.rate_out >= 0) {
         T m = block_max256(lmax, s_red);
@@ -361,21 +367,32 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a, int tiles_x,
 // L(S1))/2 (Heun).
 template <typename T, int EQN, bool BATHY, int STAGE>
 __global__ __launch_bounds__(256) void batch_stage_kernel(const BatchSolve *solves, const WorkItem *items,
-                                                          const int *nitems, int ntiles)
+                                                          const int *nitems, int ntiles, int one)
 {
     constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;
     const int w = xcd_tile(blockIdx.x, gridDim.x);
     if (w >= ntiles) return;
-    const int n = *nitems;
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-        int mid = (lo + hi + 1) >> 1;
-        if (items[mid].tile_begin <= w) lo = mid;
-        else hi = mid - 1;
+    // one != 0: the list is known to hold one solve, solves[0] (a single
+    // solve stepping through this kernel); its descriptor and list entry are
+    // then fetched together instead of one after the other
+    WorkItem it;
+    const BatchSolve *dp;
+    if (one) {
+        it = items[0];
+        dp = solves;
+    } else {
+        const int n = *nitems;
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (items[mid].tile_begin <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        it = items[lo];
+        dp = solves + it.solve;
     }
-    const WorkItem it = items[lo];
     const int tile = w - it.tile_begin;
-    const BatchSolve &d = solves[it.solve];
+    const BatchSolve &d = *dp;
     StageArgs<T> a;
     a.qs = (const T *)(STAGE == 1 ? d.q : d.s1);
     a.q0 = (const T *)d.q;
@@ -615,19 +632,19 @@ static hipError_t rate_t(const StageDesc &d, const void *q, Ctl *ctl, unsigned l
 }
 
 hipError_t launch_batch_stage(int eqn, int bathy, int stage, const BatchSolve *solves, const WorkItem *items,
-                              const int *nitems, int grid, hipStream_t st)
+                              const int *nitems, int grid, hipStream_t st, int one)
 {
     if (grid <= 0) return hipSuccess;
     dim3 g(xcd_grid(grid)), b(256);
     if (eqn == EULER) {
-        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, 1>), g, b, 0, st, solves, items, nitems, grid);
-        else hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, 2>), g, b, 0, st, solves, items, nitems, grid);
+        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, 1>), g, b, 0, st, solves, items, nitems, grid, one);
+        else hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, 2>), g, b, 0, st, solves, items, nitems, grid, one);
     } else if (bathy) {
-        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, 1>), g, b, 0, st, solves, items, nitems, grid);
-        else hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, 2>), g, b, 0, st, solves, items, nitems, grid);
+        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, 1>), g, b, 0, st, solves, items, nitems, grid, one);
+        else hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, 2>), g, b, 0, st, solves, items, nitems, grid, one);
     } else {
-        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, 1>), g, b, 0, st, solves, items, nitems, grid);
-        else hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, 2>), g, b, 0, st, solves, items, nitems, grid);
+        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, 1>), g, b, 0, st, solves, items, nitems, grid, one);
+        else hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, 2>), g, b, 0, st, solves, items, nitems, grid, one);
     }
     return hipGetLastError();
 }
