@@ -193,19 +193,28 @@ template <typename T> __device__ __forceinline__ bool eul_admissible(T r, T m, T
     return r > T(0) && p > T(0);
 }
 
-// Largest characteristic rate (|u|+c)/dx + (|v|+c)/dy of a cell state.
-template <typename T, int EQN> __device__ __forceinline__ T cell_rate(const T *s, const Phys<T> &ph, T rdx, T rdy)
+// CFL rate (|u|+c)/dx + (|v|+c)/dy of a cell and whether the cell is
+// admissible (finite, h > 0; or rho > 0 and p > 0).  A non-finite or
+// non-positive depth, or a non-finite momentum or energy, makes the rate NaN
+// or infinite, so one comparison of the rate covers finiteness; the
+// comparison is false for NaN.  (A positive depth so small that the rate
+// overflows is reported inadmissible too: it would stall Delta t at 0.)
+template <typename T, int EQN>
+__device__ __forceinline__ bool cell_rate_ok(const T *s, const Phys<T> &ph, T rdx, T rdy, T &rate)
 {
-    T ir = rcp(s[0]);
-    T u = s[1] * ir, v = s[2] * ir;
+    const T ir = rcp(s[0]);
+    const T u = s[1] * ir, v = s[2] * ir;
     T c;
+    bool pos = true;
     if (EQN == SWE) {
         c = ph.sqg * fsqrt(s[0]);
     } else {
-        T p = (ph.gamma - T(1)) * (s[3] - T(0.5) * (s[1] * u + s[2] * v));
+        const T p = (ph.gamma - T(1)) * (s[3] - T(0.5) * (s[1] * u + s[2] * v));
         c = fsqrt(ph.gamma * p * ir);
+        pos = s[0] > T(0) && p > T(0);
     }
-    return (tabs(u) + c) * rdx + (tabs(v) + c) * rdy;
+    rate = (tabs(u) + c) * rdx + (tabs(v) + c) * rdy;
+    return pos && rate < T(__builtin_inf());
 }
 
 // Full face computation.  Inputs: the four cells along the normal for each

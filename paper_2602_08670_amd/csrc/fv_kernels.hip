@@ -74,17 +74,26 @@ __device__ __forceinline__ void push_rate(unsigned long long *rates, int k, doub
     atomicMax(rate_slot(rates, k, block_linear & (RATE_SUB - 1)), (unsigned long long)__double_as_longlong(m));
 }
 
-template <typename T, int EQN>
-__device__ __forceinline__ bool cell_finite_ok(const T *s, T gamma)
+// Max over a wave of non-negative values, in every lane.  Non-negative
+// floats order like their bit patterns, so the float path reduces unsigned
+// integers with DPP row shifts (lane 15 of each 16-lane row ends with its
+// row's max) and combines the four rows with lane reads.
+template <int CTRL> __device__ __forceinline__ unsigned dpp_u(unsigned x)
 {
-    constexpr int NV = EQN == SWE ? 3 : 4;
-    bool fin = true;
-#pragma unroll
-    for (int v = 0; v < NV; v++) fin = fin && __builtin_isfinite(s[v]);
-    if (!fin) return false;
-    if (EQN == SWE) return s[0] > T(0);
-    return eul_admissible(s[0], s[1], s[2], s[3], gamma);
+    return (unsigned)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, 0xf, 0xf, false);  // lanes with no source read 0
 }
+__device__ __forceinline__ float wave_max_nonneg(float v)
+{
+    unsigned x = __float_as_uint(v);
+    x = max(x, dpp_u<0x111>(x));  // row_shr:1
+    x = max(x, dpp_u<0x112>(x));  // row_shr:2
+    x = max(x, dpp_u<0x114>(x));  // row_shr:4
+    x = max(x, dpp_u<0x118>(x));  // row_shr:8
+    const unsigned a = max((unsigned)__builtin_amdgcn_readlane((int)x, 15), (unsigned)__builtin_amdgcn_readlane((int)x, 31));
+    const unsigned b = max((unsigned)__builtin_amdgcn_readlane((int)x, 47), (unsigned)__builtin_amdgcn_readlane((int)x, 63));
+    return __uint_as_float(max(a, b));
+}
+__device__ __forceinline__ double wave_max_nonneg(double v) { return wave_max(v); }
 
 // Block-wide max of v (threads 0..255) -> returned in thread 0.
 template <typename T> __device__ __forceinline__ T block_max256(T v, T *red)
@@ -139,7 +148,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
     __shared__ T s_q[NL][HY][HX];
     __shared__ T s_edge[NT][TY];         // right face of column TX-1, handed to that cell
     __shared__ T s_low[NW - 1][NT][TX];  // low y face of wave w+1's first row, handed to wave w
-    __shared__ T s_red[NW];
     __shared__ double s_dt;
 
     // An earlier step failed: the state is frozen.  The flag is checked only
@@ -322,16 +330,18 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
                 qn[v] = o;
             }
             if (a.last) {
-                if (!cell_finite_ok<T, EQN>(qn, a.ph.gamma)) bad = true;
-                else if (a.rate_out >= 0) lmax = tmax(lmax, cell_rate<T, EQN>(qn, a.ph, a.rdx, a.rdy));
+                T r;
+                if (cell_rate_ok<T, EQN>(qn, a.ph, a.rdx, a.rdy, r)) lmax = tmax(lmax, r);
+                else bad = true;
             }
         }
     }
     if (!a.last || frozen) return;
     if (bad) atomicExch(&a.ctl->bad, 1);
     if (a.rate_out >= 0) {
-        T m = block_max256(lmax, s_red);
-        if (tid == 0) push_rate(a.rates, a.rate_out, (double)m, tile_linear);
+        // one atomic per wave: no block-wide reduction, no further barrier
+        const T m = wave_max_nonneg(lmax);
+        if (lane == 0) push_rate(a.rates, a.rate_out, (double)m, tile_linear * NW + wave);
     }
     if (tile_linear == 0) {
         if (tid == 0) {
@@ -435,8 +445,9 @@ __global__ __launch_bounds__(256) void rate_kernel(const T *q, int n, T rdx, T r
         T s[NV];
 #pragma unroll
         for (int v = 0; v < NV; v++) s[v] = q[(size_t)v * n + k];
-        if (!cell_finite_ok<T, EQN>(s, ph.gamma)) bad = true;
-        else lmax = tmax(lmax, cell_rate<T, EQN>(s, ph, rdx, rdy));
+        T r;
+        if (cell_rate_ok<T, EQN>(s, ph, rdx, rdy, r)) lmax = tmax(lmax, r);
+        else bad = true;
     }
     if (bad) atomicExch(&ctl->bad, 1);
     T m = block_max256(lmax, s_red);
