@@ -8,8 +8,16 @@ the global wave-speed reduction every step.  A "step" is one full time step
 the timed region.  Prints one JSON line.
 
 Also measured (reported inside the line, not as `value`): the four-quadrant
-Euler workload at 1024^2 (FP32, walls, 500 steps) and the oracle on the host
+Euler workload at 1024^2 (FP32, walls, 500 steps), a sample of the serving
+stream (p50/p99 latency from arrival to completion) and the oracle on the host
 cores over a bounded sample of the shallow-water workload.
+
+The roofline object describes the stage kernel, which is bound by vector-ALU
+issue: achieved = algorithmic FP32 operations per launch / mean launch time
+(HIP events on the solver's stream over the timed steps), peak = the FP32
+vector rate without packed math.  `traffic` is the measured HBM bytes per
+launch from the committed counter summary, null once the kernel sources
+differ from the ones the counters were taken on.
 """
 from __future__ import annotations
 
@@ -26,6 +34,16 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_CELL_UPDATE = {"swe_bathy": 28, "euler": 32}  # read q (+b), write q, FP32
+# Algorithmic FP32 operations of one cell-update of the shallow-water-over-a-
+# bed step (MINMOD on h, hu, hv, eta; hydrostatic reconstruction; HLLE; bed
+# source; Heun; CFL rate), counted from the formulas with an FMA as two
+# operations: 114 per face and two faces per cell per stage, plus divergence,
+# bed source and stage combine: 261 for stage 1, 270 for stage 2, and 12 for
+# the CFL rate of the new state.
+FLOP_PER_CELL_UPDATE = {"swe_bathy": 543}
+# FP32 vector peak without packed math: 256 CUs x 64 lanes x 2 (FMA) x 2.4 GHz.
+ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kernel_swe_bathy_1024_fp32.json")
 
 
 def parse():
@@ -36,6 +54,8 @@ def parse():
     p.add_argument("--n", type=int, default=1024, help="grid side")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-euler", action="store_true")
+    p.add_argument("--serving-requests", type=int, default=64,
+                   help="requests in the serving sample (0: skip); p50/p99 at 0.8 of the saturated rate")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time for the baseline")
     p.add_argument("--calib-copy-mb", type=int, default=0,
                    help="before the run, copy this many MiB device-to-device once (a known-size kernel for "
@@ -58,6 +78,38 @@ def timed_run(solver, steps, warmup, torch):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     return e0.elapsed_time(e1) / 1e3, wall
+
+
+def measured_traffic():
+    """Bytes per stage launch from the committed counter summary, or None
+    when the kernel sources changed since the counters were taken."""
+    from paper_2602_08670_amd import pmc_traffic
+
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if rec.get("kernel_sources_sha256") != pmc_traffic.kernel_sources_sha256():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def serving_sample(n_req):
+    """The mixed SWE/Euler request stream (sizes 64..1024, 100..2000 steps)
+    through the continuous-batching server: once with every request at t=0,
+    then with Poisson arrivals at 0.8 of that saturated rate."""
+    from paper_2602_08670_amd import serve_bench as sb
+
+    stream = sb.request_stream(n_req, seed=0)
+    ics = sb.ICCache()
+    for kind, n, steps, sd in stream:
+        ics.get(kind, n, sd)
+    sat = sb.run_server_latency(stream, ics, np.zeros(n_req))
+    rate = 0.8 * n_req / sat["wall_s"]
+    poi = sb.run_server_latency(stream, ics, sb.arrivals(n_req, rate, 0))
+    return {"requests": n_req, "saturated_mcups": round(sat["mcups"], 1), "poisson_rate_per_s": round(rate, 2),
+            "p50_s": round(poi["p50_s"], 4), "p99_s": round(poi["p99_s"], 4), "poisson_mcups": round(poi["mcups"], 1)}
 
 
 def cpu_baseline(n, target_s):
@@ -107,10 +159,14 @@ def main():
     mcups = cells / gpu_s / 1e6
     launches = 2 * args.steps
     per_launch_s = gpu_s / launches
-    bytes_per_launch = BYTES_PER_CELL_UPDATE["swe_bathy"] * n * n / 2  # two stage launches per cell-update
-    achieved = bytes_per_launch / per_launch_s / 1e9
+    # two stage launches per cell-update; per launch: half a cell-update per cell
+    flop_per_launch = FLOP_PER_CELL_UPDATE["swe_bathy"] * n * n / 2
+    achieved = flop_per_launch / per_launch_s / 1e12
+    hbm_gbs = BYTES_PER_CELL_UPDATE["swe_bathy"] * n * n / 2 / per_launch_s / 1e9
+    traffic = measured_traffic() if n == 1024 else None
 
-    extra = {"wall_s": round(wall_s, 6), "sim_time": t_sim, "stage_launch_us": round(per_launch_s * 1e6, 3)}
+    extra = {"wall_s": round(wall_s, 6), "sim_time": t_sim, "stage_launch_us": round(per_launch_s * 1e6, 3),
+             "hbm_gbs_algorithmic": round(hbm_gbs, 1), "hbm_frac": round(hbm_gbs / HBM_PEAK_GBS, 4)}
     if not args.no_euler:
         qe = inputs.euler_quadrants(n, seed=0)
         se = fv.Solver(qe, prec=fv.FV_F32, bc_x=fv.FV_BC_WALL, bc_y=fv.FV_BC_WALL, device=dev)
@@ -119,6 +175,9 @@ def main():
         se.close()
         extra["euler_1024_fp32_mcups"] = round(n * n * esteps / eg / 1e6, 1)
         extra["euler_hbm_frac"] = round(BYTES_PER_CELL_UPDATE["euler"] * n * n * esteps / eg / 1e9 / HBM_PEAK_GBS, 4)
+
+    if args.serving_requests > 0:
+        extra["serving"] = serving_sample(args.serving_requests)
 
     line = {
         "metric": "Mcell-updates/s FP32 SWE 1024^2 + % HBM roofline; p50/p99 solve latency",
@@ -135,8 +194,8 @@ def main():
         "data": "synthetic (seeded Gaussian bed and surface bumps)",
         "config": {"workload": f"swe_bathy_{n}x{n}_fp32_walls_hlle_minmod_heun_cfl0.4", "nx": n, "ny": n,
                    "steps": args.steps, "parallelism": "single-gpu"},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2), "peak": round(ALU_PEAK_TFLOPS, 1),
+                     "unit": "TFLOP/s", "frac": round(achieved / ALU_PEAK_TFLOPS, 4), "traffic": traffic},
         "extra": extra,
     }
     if not args.no_cpu_baseline:
