@@ -214,6 +214,16 @@ size_t fv_model_forward_scratch_bytes(int B, int nx, int ny);
 fv_status fv_model_forward(const fv_model *m, const float *q, int B, int nx, int ny, float *z, void *scratch,
                            size_t scratch_bytes);
 
+/* The same network pass in one launch, without scratch: each workgroup runs
+ * all five layers on an 8x8 tile of pixels, recomputing the halo the 3x3
+ * stack needs (thesis section 2.5.3, fourth approach: the network of
+ * fv_model_forward).  For small grids, where a launch per layer would
+ * dominate.  z is bit-identical to fv_model_forward's.
+ *   q  device [B][3][ny][nx] FP32 (periodic, nx % 8 == 0, ny % 8 == 0);
+ *   z  device [B][ny][nx][72] FP32 (output).
+ * Enqueued on the model's stream; FV_E_UNSUPPORTED for other grid sizes. */
+fv_status fv_model_forward_tiled(const fv_model *m, const float *q, int B, int nx, int ny, float *z);
+
 /* Enqueue nsteps learned Heun steps at the fixed step cfg.dt_fixed.
  * Requires a shallow-water FP32 solver with periodic boundaries, no bed,
  * rk_stages = 2, dt_fixed > 0, learned = 1, nx % 16 == 0 and

@@ -64,13 +64,22 @@ hipError_t launch_pack(const float *master, void *packed, hipStream_t st);
 hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny,
                           void *const acts[4], float *z, hipStream_t st);
 
+// The same forward in one launch, without keeping activations: every
+// workgroup runs all five layers on an 8x8 tile of pixels (nx % 8 == 0,
+// ny % 8 == 0); z is bit-identical to launch_forward's.  With alpha != NULL
+// the output is the constrained coefficients base + P z per group of six
+// instead of z.
+hipError_t launch_forward_fused(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny, float *z,
+                                hipStream_t st, const Proj *alpha = nullptr);
+
 struct LearnedArgs;
 
 // Launch wrappers of the learned stage (learned_kernels.hip).
 struct StageBatch {
     const float *qs, *q0;
     float *out;
-    const float *z;
+    const float *z;          // raw coefficients, or (alpha != 0) constrained ones, [B][ny][nx][72]
+    int alpha;
     int B, nx, ny;
     float rdx, rdy, g, h0;
     float a0, a1;
@@ -80,7 +89,20 @@ struct StageBatch {
     unsigned long long *nfb;
     int *fatal;
     Proj pr;
+    // modes 2 and 3 (the end of a step in two launches instead of four):
+    const float *commit_src;     // mode 2: S2, copied to commit_dst for admissible solves
+    float *commit_dst;
+    int *bad_next;               // mode 3: the next step's flags, cleared
+    unsigned long long *redone;  // mode 3: per solve, +1 when the step was redone (or NULL)
+    double *t;                   // mode 3: solve 0's time and step count advance (or NULL)
+    long long *steps;
 };
+// mode 0: learned stage with fallback (sets bad bits);
+// mode 1: plain MINMOD stage, only for solves with bad != 0;
+// mode 2: solves with bad == 0 commit S2 -> q, the others run the plain
+//         first stage (redo);
+// mode 3: plain second stage for solves with bad != 0, and the step's
+//         bookkeeping (redone count, next flags cleared, time).
 hipError_t learned_stage(int mode, int flux, const StageBatch &sb, hipStream_t st);
 hipError_t launch_commit(float *q, const float *s2, const int *bad, size_t per_solve, int B, hipStream_t st);
 hipError_t launch_finish(int *bad, unsigned long long *redone, int *record, int B, const float *dt, double *t,

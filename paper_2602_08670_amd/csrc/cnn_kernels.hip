@@ -233,6 +233,234 @@ hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, i
     return hipGetLastError();
 }
 
+// ------------------------------------------------------- fused inference
+// All five layers for one FT x FT tile of output pixels in one workgroup.
+// Layer l's output is computed on the (FT + 2(4 - l))^2 region around the
+// tile, so the next layer finds its 3x3 neighbourhood inside the block: the
+// input region (FT + 10)^2 is read once with periodic wrap, activations stay
+// in LDS (two ping-pong buffers), and each layer's packed weights are staged
+// into one LDS buffer in turn.  Each output pixel accumulates its MFMAs in
+// the same order as conv_fwd_kernel (taps 0..8, K slices within a tap), with
+// the same bias, ReLU and BF16 rounding, so z is bit-identical to the
+// layer-by-layer pass; only the halo pixels are computed more than once.
+constexpr int FT = 8;            // output tile side
+constexpr int FR0 = FT + 8;      // side of layer 0's output region
+constexpr int FRI = FT + 10;     // side of the input region
+constexpr int FW_EL = 9 * 5 * 16 * 32;  // largest packed weight block (layer 4), bf16 elements
+
+// Hidden layer NT = 2 co tiles: each wave loads the layer's A fragments
+// (9 taps x 2 tiles, 16 bytes per lane each) from LDS into registers once and
+// reuses them for all its pixel groups; only B is read per group and tap.
+constexpr int FNW = 8;  // waves per workgroup of the fused pass
+
+__device__ __forceinline__ void fused_hidden(const bf16x8 *in, int rin, bf16 *out, const bf16x8 *w, const float *bias,
+                                             int wave, int lane)
+{
+    constexpr int NT = 2;
+    const int g = lane >> 4, px = lane & 15;
+    const int rout = rin - 2, npx = rout * rout, ngrp = (npx + 15) >> 4;
+    bf16x8 A[9][NT];
+#pragma unroll
+    for (int tap = 0; tap < 9; tap++)
+#pragma unroll
+        for (int t = 0; t < NT; t++) A[tap][t] = w[((tap * NT + t) * 16 + px) * 4 + g];
+    float bs[NT][4];
+#pragma unroll
+    for (int t = 0; t < NT; t++)
+#pragma unroll
+        for (int i = 0; i < 4; i++) bs[t][i] = bias[16 * t + 4 * g + i];
+    for (int gi = wave; gi < ngrp; gi += FNW) {
+        const int p = gi * 16 + px;
+        const bool valid = p < npx;
+        const int pc = valid ? p : 0;
+        const int py = pc / rout, pxx = pc - py * rout;
+        floatx4 acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int tap = 0; tap < 9; tap++) {
+            const bf16x8 bx = in[((py + tap / 3) * rin + pxx + tap % 3) * 4 + g];
+#pragma unroll
+            for (int t = 0; t < NT; t++) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[tap][t], bx, acc[t], 0, 0, 0);
+        }
+        if (valid) {
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const int co0 = 16 * t + 4 * g;
+                bf16x4 o;
+#pragma unroll
+                for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[t][i] + bs[t][i], 0.0f);
+                *(bf16x4 *)(out + (size_t)p * 32 + co0) = o;
+            }
+        }
+    }
+}
+
+__device__ __forceinline__ void stage_weights(bf16x8 *s_w, const char *P, size_t off, int nel)
+{
+    const bf16x8 *gw = (const bf16x8 *)(P + off);
+    for (int i = threadIdx.x; i < nel / 8; i += blockDim.x) s_w[i] = gw[i];
+}
+
+// ALPHA: instead of z, write the constrained coefficients alpha = base + P z
+// of every group of six (same operation order as the learned stage's own
+// projection, so alpha is bit-identical to projecting this kernel's z).
+template <bool ALPHA>
+__global__ __launch_bounds__(FNW * 64) void conv_fused_kernel(const float *q, const char *P, Packed pk, Norm nrm, float *z,
+                                                         int B, int H, int W, Proj pr)
+{
+    __shared__ bf16 s_in[3][FRI * FRI];
+    __shared__ bf16x8 s_a0[FR0 * FR0 * 4];                  // 32 channels = 4 x bf16x8 per pixel
+    __shared__ bf16x8 s_a1[(FR0 - 2) * (FR0 - 2) * 4];
+    // all five layers' packed weights, loaded together at the start
+    constexpr int W0 = 32 * 32 / 8, WH = 9 * 32 * 32 / 8, W4 = FW_EL / 8;
+    __shared__ bf16x8 s_wall[W0 + 3 * WH + W4];
+
+    const int tx_n = W / FT, ty_n = H / FT;
+    const int tile = blockIdx.x;
+    const int b = tile / (tx_n * ty_n);
+    const int r = tile - b * tx_n * ty_n;
+    const int y0 = (r / tx_n) * FT, x0 = (r % tx_n) * FT;
+    // the wave index as a scalar: MFMAs under `gi == wave` must sit behind a
+    // real branch (an MFMA does not honour a partial EXEC mask)
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = lane >> 4, px = lane & 15;
+    const size_t hw = (size_t)H * W;
+    const float *qb = q + (size_t)b * 3 * hw;
+
+    // input region, normalised and rounded to BF16 as the first layer reads it
+    for (int i = threadIdx.x; i < 3 * FRI * FRI; i += FNW * 64) {
+        const int ci = i / (FRI * FRI), k = i - ci * FRI * FRI;
+        const int ry = k / FRI, rx = k - ry * FRI;
+        const int yy = wrap(y0 - 5 + ry, H), xx = wrap(x0 - 5 + rx, W);
+        s_in[ci][k] = (bf16)((qb[(size_t)ci * hw + (size_t)yy * W + xx] - nrm.mean[ci]) * nrm.inv_std[ci]);
+    }
+    stage_weights(s_wall, P, pk.w[0], 32 * 32);
+#pragma unroll
+    for (int l = 1; l < 4; l++) stage_weights(s_wall + W0 + (l - 1) * WH, P, pk.w[l], 9 * 32 * 32);
+    stage_weights(s_wall + W0 + 3 * WH, P, pk.w[4], FW_EL);
+    __syncthreads();
+
+    // layer 0 on the FR0 x FR0 region (one row of 16 pixels per group)
+    {
+        const float *bias = (const float *)(P + pk.b[0]);
+        const bf16x8 A0 = s_wall[px * 4 + g], A1 = s_wall[(16 + px) * 4 + g];
+        for (int gi = wave; gi < FR0; gi += FNW) {
+            const int py = gi, pxx = px;
+            bf16x8 bx;
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int k = 8 * g + e;
+                bf16 v = (bf16)0.0f;
+                if (k < 27) {
+                    const int tap = k / 3, ci = k - 3 * tap;
+                    v = s_in[ci][(py + tap / 3) * FRI + pxx + tap % 3];
+                }
+                bx[e] = v;
+            }
+            floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
+            acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, bx, acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, bx, acc[1], 0, 0, 0);
+            const int p = py * FR0 + pxx;
+#pragma unroll
+            for (int t = 0; t < 2; t++) {
+                const int co0 = 16 * t + 4 * g;
+                bf16x4 o;
+#pragma unroll
+                for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[t][i] + bias[co0 + i], 0.0f);
+                *(bf16x4 *)((bf16 *)s_a0 + (size_t)p * 32 + co0) = o;
+            }
+        }
+    }
+    // hidden layers 1..3: s_a0 -> s_a1 -> s_a0 -> s_a1
+    for (int l = 1; l < 4; l++) {
+        __syncthreads();  // previous layer's output written
+        const int rin = FR0 - 2 * (l - 1);
+        const bf16x8 *in = (l & 1) ? s_a0 : s_a1;
+        bf16 *out = (bf16 *)((l & 1) ? s_a1 : s_a0);
+        fused_hidden(in, rin, out, s_wall + W0 + (l - 1) * WH, (const float *)(P + pk.b[l]), wave, lane);
+    }
+    __syncthreads();
+    // layer 4: s_a1 (FT + 2)^2 -> z on the FT x FT tile: 4 pixel groups x 5
+    // co tiles = 20 accumulation chains of 9 taps, chain c = (group c % 4,
+    // co tile c / 4), dealt to the waves in turn
+    const bf16x8 *s_w = s_wall + W0 + 3 * WH;
+    float *s_z = (float *)(s_wall + W0);  // [FT*FT][72] over the hidden layers' weights (ALPHA only)
+    {
+        constexpr int NT = 5, RIN = FT + 2, NG = FT * FT / 16, NCH = NG * NT;
+        constexpr int CPW = (NCH + FNW - 1) / FNW;  // chains per wave
+        const float *bias = (const float *)(P + pk.b[4]);
+        floatx4 acc[CPW];
+#pragma unroll
+        for (int j = 0; j < CPW; j++) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int j = 0; j < CPW; j++) {
+            const int c = wave + j * FNW;
+            if (c < NCH) {  // wave-uniform
+                const int gi = c % NG, t = c / NG;
+                const int p = gi * 16 + px;
+                const int py = p / FT, pxx = p - py * FT;
+#pragma unroll
+                for (int tap = 0; tap < 9; tap++) {
+                    const bf16x8 bx = s_a1[((py + tap / 3) * RIN + pxx + tap % 3) * 4 + g];
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * 4 + g], bx,
+                                                                     acc[j], 0, 0, 0);
+                }
+            }
+        }
+        if (ALPHA) __syncthreads();  // every wave past the hidden layers' weights before they hold z
+#pragma unroll
+        for (int j = 0; j < CPW; j++) {
+            const int c = wave + j * FNW;
+            if (c < NCH) {
+                const int gi = c % NG, t = c / NG;
+                const int co0 = 16 * t + 4 * g;
+                if (co0 < 72) {
+                    const int p = gi * 16 + px;
+                    const int py = p / FT, pxx = p - py * FT;
+                    floatx4 o;
+#pragma unroll
+                    for (int i = 0; i < 4; i++) o[i] = acc[j][i] + bias[co0 + i];
+                    if (ALPHA) *(floatx4 *)(s_z + p * 72 + co0) = o;
+                    else *(floatx4 *)(z + ((size_t)b * hw + (size_t)(y0 + py) * W + x0 + pxx) * 72 + co0) = o;
+                }
+            }
+        }
+    }
+    if (ALPHA) {
+        __syncthreads();
+        // 64 pixels x 12 groups of six: (axis*2 + side)*3 + var
+        for (int task = threadIdx.x; task < FT * FT * 12; task += FNW * 64) {
+            const int p = task / 12, grp = task - p * 12;
+            const int side = (grp / 3) & 1;
+            const float *zz = s_z + p * 72 + grp * 6;
+            const int py = p / FT, pxx = p - py * FT;
+            float *dst = z + ((size_t)b * hw + (size_t)(y0 + py) * W + x0 + pxx) * 72 + grp * 6;
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                float al = pr.base[side * 6 + k];
+#pragma unroll
+                for (int j = 0; j < 6; j++) al += pr.P[k * 6 + j] * zz[j];
+                dst[k] = al;
+            }
+        }
+    }
+}
+
+hipError_t launch_forward_fused(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny, float *z,
+                                hipStream_t st, const Proj *alpha)
+{
+    if (nx % FT || ny % FT) return hipErrorInvalidValue;
+    const int tiles = B * (nx / FT) * (ny / FT);
+    if (alpha)
+        hipLaunchKernelGGL(conv_fused_kernel<true>, dim3(tiles), dim3(FNW * 64), 0, st, q, (const char *)packed,
+                           packed_layout(), nrm, z, B, ny, nx, *alpha);
+    else
+        hipLaunchKernelGGL(conv_fused_kernel<false>, dim3(tiles), dim3(FNW * 64), 0, st, q, (const char *)packed,
+                           packed_layout(), nrm, z, B, ny, nx, Proj{});
+    return hipGetLastError();
+}
+
 }  // namespace cnn
 
 // ================================================================ backward

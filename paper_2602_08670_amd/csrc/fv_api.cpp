@@ -130,6 +130,7 @@ struct fv_solver {
     Layout L;
     hipStream_t stream;
     int64_t enq;  // steps enqueued since the last rate initialisation
+    int64_t lsteps;  // learned steps enqueued (picks the slot of the step's flags)
     size_t state_bytes;
     bool batched;
     fvk::Ctl *ctl() { return (fvk::Ctl *)(ws + L.ctl); }
@@ -529,6 +530,15 @@ fv_status fv_model_forward(const fv_model *m, const float *q, int B, int nx, int
     return e == hipSuccess ? FV_OK : hip_fail(e, "network launch");
 }
 
+fv_status fv_model_forward_tiled(const fv_model *m, const float *q, int B, int nx, int ny, float *z)
+{
+    if (!m || !q || !z) return fail(FV_E_INVALID, "NULL argument");
+    if (B <= 0 || nx < 8 || ny < 8 || nx % 8 || ny % 8)
+        return fail(FV_E_UNSUPPORTED, "the tiled network pass needs nx %% 8 == 0 and ny %% 8 == 0 (got %dx%d)", nx, ny);
+    hipError_t e = cnn::launch_forward_fused(m->packed, m->nrm, q, B, nx, ny, z, m->stream);
+    return e == hipSuccess ? FV_OK : hip_fail(e, "network launch");
+}
+
 fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats)
 {
     if (!s || !m) return fail(FV_E_INVALID, "NULL argument");
@@ -546,7 +556,7 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
     float *S1 = (float *)(ws + L.s1), *S2 = (float *)(ws + L.s2l), *z = (float *)(ws + L.z);
     char *sm = ws + L.small;
     void *acts[4] = {ws + L.act0, ws + L.act1, ws + L.act0, ws + L.act1};
-    cnn::StageBatch sb;
+    cnn::StageBatch sb{};
     sb.B = 1;
     sb.nx = c.nx;
     sb.ny = c.ny;
@@ -561,26 +571,35 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
     sb.pr = m->pr;
     sb.z = z;
     const int fl = c.flux == FV_FLUX_RUSANOV ? 1 : 0;  // kernel flux ids: 0 HLLE, 1 Rusanov
-    const size_t per = (size_t)3 * c.nx * c.ny;
+    const bool fused = c.ny % 8 == 0;  // whole network in one launch per evaluation
+    int *flags = (int *)(sm + SM_BAD);  // two slots: this step's and the next step's
+    sb.redone = (unsigned long long *)(sm + SM_REDONE);
+    sb.t = &s->ctl()->t;
+    sb.steps = &s->ctl()->step;
+    // the tiled network pass also applies the projection: z then holds alpha
+    sb.alpha = fused ? 1 : 0;
+    auto forward = [&](const float *in) {
+        return fused ? cnn::launch_forward_fused(m->packed, m->nrm, in, 1, c.nx, c.ny, z, s->stream, &m->pr)
+                     : cnn::launch_forward(m->packed, m->nrm, in, 1, c.nx, c.ny, acts, z, s->stream);
+    };
     hipError_t e = hipSuccess;
-    for (int64_t k = 0; k < nsteps && e == hipSuccess; k++) {
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; k++, s->lsteps++) {
+        sb.bad = flags + (s->lsteps & 1);
+        sb.bad_next = flags + ((s->lsteps + 1) & 1);
         // stage 1: coefficients of q, q1 = q + dt L(q)
-        e = cnn::launch_forward(m->packed, m->nrm, q, 1, c.nx, c.ny, acts, z, s->stream);
+        e = forward(q);
         sb.qs = q; sb.q0 = q; sb.out = S1; sb.a0 = 0.f; sb.a1 = 1.f; sb.flagbit = 1;
         if (e == hipSuccess) e = cnn::learned_stage(0, fl, sb, s->stream);
         // stage 2: coefficients of q1, q2 = q/2 + (q1 + dt L(q1))/2
-        if (e == hipSuccess) e = cnn::launch_forward(m->packed, m->nrm, S1, 1, c.nx, c.ny, acts, z, s->stream);
+        if (e == hipSuccess) e = forward(S1);
         sb.qs = S1; sb.q0 = q; sb.out = S2; sb.a0 = 0.5f; sb.a1 = 0.5f; sb.flagbit = 2;
         if (e == hipSuccess) e = cnn::learned_stage(0, fl, sb, s->stream);
-        // admissible: take the learned result; otherwise redo with the plain scheme
-        if (e == hipSuccess) e = cnn::launch_commit(q, S2, sb.bad, per, 1, s->stream);
+        // admissible: q <- S2; otherwise redo the step with the plain scheme
         sb.qs = q; sb.q0 = q; sb.out = S1; sb.a0 = 0.f; sb.a1 = 1.f;
-        if (e == hipSuccess) e = cnn::learned_stage(1, fl, sb, s->stream);
+        sb.commit_src = S2; sb.commit_dst = q;
+        if (e == hipSuccess) e = cnn::learned_stage(2, fl, sb, s->stream);
         sb.qs = S1; sb.q0 = q; sb.out = q; sb.a0 = 0.5f; sb.a1 = 0.5f;
-        if (e == hipSuccess) e = cnn::learned_stage(1, fl, sb, s->stream);
-        if (e == hipSuccess)
-            e = cnn::launch_finish(sb.bad, (unsigned long long *)(sm + SM_REDONE), nullptr, 1, sb.dt, &s->ctl()->t,
-                                   &s->ctl()->step, s->stream);
+        if (e == hipSuccess) e = cnn::learned_stage(3, fl, sb, s->stream);
     }
     if (e != hipSuccess) return hip_fail(e, "learned step launch");
     if (stats) {

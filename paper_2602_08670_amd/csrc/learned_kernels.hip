@@ -10,6 +10,10 @@
 // (counted).  Fluxes, divergence and the Runge-Kutta combine follow the
 // classic stage kernel.  MODE 1 runs the plain MINMOD scheme only for the
 // solves whose learned step produced an inadmissible cell (the step is redone).
+// MODE 2 and 3 end a step in two launches: MODE 2 commits the learned result
+// of the admissible solves and runs the plain first stage for the others;
+// MODE 3 runs the plain second stage for those and does the step's
+// bookkeeping.
 #include "cnn_internal.hpp"
 #include "fv_device.hpp"
 
@@ -33,13 +37,20 @@ struct LearnedArgs {
     unsigned long long *nfb; // per solve fallback face sides
     int *fatal;              // per solve: the plain redo itself failed
     Proj pr;
+    const float *commit_src;
+    float *commit_dst;
+    int *bad_next;
+    unsigned long long *redone;
+    double *t;
+    long long *steps;
 };
 
 __device__ __forceinline__ int pwrap(int i, int n) { return ((i % n) + n) % n; }
 
 // Face states of one face from the six stencil values st[v][0..5] (cells
 // i-2..i+3 along the normal).  MODE 0: learned with fallback; MODE 1: MINMOD.
-template <int MODE>
+// AL: zc already holds alpha = base + P z (projected by the network pass).
+template <int MODE, bool AL = false>
 __device__ __forceinline__ int face_states(const float (*st)[6], const float *zc, const Proj &pr, float *QL,
                                            float *QR)
 {
@@ -68,9 +79,14 @@ __device__ __forceinline__ int face_states(const float (*st)[6], const float *zc
             float acc = 0.0f;
 #pragma unroll
             for (int k = 0; k < 6; k++) {
-                float al = pr.base[s * 6 + k];
+                float al;
+                if (AL) {
+                    al = zz[k];
+                } else {
+                    al = pr.base[s * 6 + k];
 #pragma unroll
-                for (int j = 0; j < 6; j++) al += pr.P[k * 6 + j] * zz[j];
+                    for (int j = 0; j < 6; j++) al += pr.P[k * 6 + j] * zz[j];
+                }
                 acc += al * st[v][k];
             }
             (s == 0 ? QL : QR)[v] = acc;
@@ -98,7 +114,7 @@ __device__ __forceinline__ void flux3(const float *QL, const float *QR, const Ph
     F[TM] = G[2];
 }
 
-template <int MODE, int FLUX>
+template <int MODE, int FLUX, bool AL = false>
 __global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
 {
     constexpr int TX = 64, TY = 8, HX = TX + 6, HY = TY + 6;
@@ -108,12 +124,35 @@ __global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
     __shared__ int s_cnt;
     __shared__ int s_bad;
 
+    constexpr int FS = MODE == 0 ? 0 : 1;  // face states: learned or plain MINMOD
     const int b = blockIdx.z;
-    if (MODE == 1 && a.bad[b] == 0) return;
     const int tid = threadIdx.x;
     const int nx = a.nx, ny = a.ny;
     const size_t plane = (size_t)nx * ny;
     const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
+    if (MODE == 3 && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+        // this step's flags are only read in this launch; the next step's
+        // flags are not read before the next step
+        const int flag = a.bad[b];
+        if (flag && a.redone) a.redone[b] += 1;
+        a.bad_next[b] = 0;
+        if (b == 0 && a.t) {
+            *a.t += (double)a.dt[0];
+            *a.steps += 1;
+        }
+    }
+    if (MODE == 2 && a.bad[b] == 0) {
+        // admissible learned step: q <- S2 on this tile
+        for (int k = tid; k < TX * TY; k += 256) {
+            const int cy = k / TX, cx = k - cy * TX;
+            if (x0 + cx >= nx || y0 + cy >= ny) continue;
+            const size_t idx = (size_t)b * 3 * plane + (size_t)(y0 + cy) * nx + x0 + cx;
+#pragma unroll
+            for (int v = 0; v < 3; v++) a.commit_dst[idx + v * plane] = a.commit_src[idx + v * plane];
+        }
+        return;
+    }
+    if ((MODE == 1 || MODE == 3) && a.bad[b] == 0) return;
     const float *qs = a.qs + (size_t)b * 3 * plane;
     const float dt = a.dt[b];
     // stage 2 of a solve whose stage 1 failed is evaluated (its result is
@@ -143,7 +182,7 @@ __global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
         int gy = y0 + fj < ny ? y0 + fj : ny - 1;
         const float *zc = a.z + (((size_t)b * ny + gy) * nx + pwrap(x0 - 1 + fi, nx)) * 72;
         float QL[3], QR[3], F[3];
-        int c = face_states<MODE>(st, zc, a.pr, QL, QR);
+        int c = face_states<FS, AL>(st, zc, a.pr, QL, QR);
         // each face is counted once: as the left face of a cell of this tile
         if (fi < TX && x0 + fi < nx && y0 + fj < ny) nfb += c;
         flux3<FLUX, 0>(QL, QR, a.ph, F);
@@ -161,7 +200,7 @@ __global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
         int gx = x0 + fi < nx ? x0 + fi : nx - 1;
         const float *zc = a.z + (((size_t)b * ny + pwrap(y0 - 1 + fj, ny)) * nx + gx) * 72 + 36;
         float QL[3], QR[3], F[3];
-        int c = face_states<MODE>(st, zc, a.pr, QL, QR);
+        int c = face_states<FS, AL>(st, zc, a.pr, QL, QR);
         if (fj < TY && y0 + fj < ny && x0 + fi < nx) nfb += c;
         flux3<FLUX, 1>(QL, QR, a.ph, F);
 #pragma unroll
@@ -250,13 +289,39 @@ hipError_t learned_stage(int mode, int flux, const StageBatch &sb, hipStream_t s
     a.nfb = sb.nfb;
     a.fatal = sb.fatal;
     a.pr = sb.pr;
+    a.commit_src = sb.commit_src;
+    a.commit_dst = sb.commit_dst;
+    a.bad_next = sb.bad_next;
+    a.redone = sb.redone;
+    a.t = sb.t;
+    a.steps = sb.steps;
+    if ((mode == 2 && (!a.commit_src || !a.commit_dst)) || (mode == 3 && !a.bad_next)) return hipErrorInvalidValue;
     dim3 grid((a.nx + 63) / 64, (a.ny + 7) / 8, a.B), blk(256);
-    if (mode == 0) {
-        if (flux == fvk::RUSANOV) hipLaunchKernelGGL((learned_stage_kernel<0, fvk::RUSANOV>), grid, blk, 0, st, a);
-        else hipLaunchKernelGGL((learned_stage_kernel<0, fvk::HLLE>), grid, blk, 0, st, a);
-    } else {
-        if (flux == fvk::RUSANOV) hipLaunchKernelGGL((learned_stage_kernel<1, fvk::RUSANOV>), grid, blk, 0, st, a);
+    const bool rus = flux == fvk::RUSANOV;
+    switch (mode) {
+    case 0:
+        if (sb.alpha) {
+            if (rus) hipLaunchKernelGGL((learned_stage_kernel<0, fvk::RUSANOV, true>), grid, blk, 0, st, a);
+            else hipLaunchKernelGGL((learned_stage_kernel<0, fvk::HLLE, true>), grid, blk, 0, st, a);
+        } else {
+            if (rus) hipLaunchKernelGGL((learned_stage_kernel<0, fvk::RUSANOV>), grid, blk, 0, st, a);
+            else hipLaunchKernelGGL((learned_stage_kernel<0, fvk::HLLE>), grid, blk, 0, st, a);
+        }
+        break;
+    case 1:
+        if (rus) hipLaunchKernelGGL((learned_stage_kernel<1, fvk::RUSANOV>), grid, blk, 0, st, a);
         else hipLaunchKernelGGL((learned_stage_kernel<1, fvk::HLLE>), grid, blk, 0, st, a);
+        break;
+    case 2:
+        if (rus) hipLaunchKernelGGL((learned_stage_kernel<2, fvk::RUSANOV>), grid, blk, 0, st, a);
+        else hipLaunchKernelGGL((learned_stage_kernel<2, fvk::HLLE>), grid, blk, 0, st, a);
+        break;
+    case 3:
+        if (rus) hipLaunchKernelGGL((learned_stage_kernel<3, fvk::RUSANOV>), grid, blk, 0, st, a);
+        else hipLaunchKernelGGL((learned_stage_kernel<3, fvk::HLLE>), grid, blk, 0, st, a);
+        break;
+    default:
+        return hipErrorInvalidValue;
     }
     return hipGetLastError();
 }

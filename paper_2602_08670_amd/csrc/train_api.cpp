@@ -164,7 +164,7 @@ fv_status fv_train_step(fv_trainer *tr, const float *q0, const float *targets, i
     if (e == hipSuccess) e = hipMemsetAsync(ws + L.nfb, 0, align256(B * 8) * 2, st);
     if (e == hipSuccess) e = hipMemsetAsync(ws + L.fatal, 0, align256(B * 4), st);
 
-    cnn::StageBatch sb;
+    cnn::StageBatch sb{};
     sb.B = B;
     sb.nx = nx;
     sb.ny = ny;

@@ -125,6 +125,7 @@ def _load():
         "fv_model_destroy": ([vp], None),
         "fv_model_forward_scratch_bytes": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_size_t),
         "fv_model_forward": ([vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp, ctypes.c_size_t], st),
+        "fv_model_forward_tiled": ([vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp], st),
         "fv_learned_step": ([vp, vp, i64, ctypes.POINTER(fv_learned_stats)], st),
         "fv_train_workspace_bytes": ([ctypes.POINTER(fv_train_config)], ctypes.c_size_t),
         "fv_train_create": ([ctypes.POINTER(fv_train_config), vp, vp, vp, vp, vp, ctypes.c_size_t,
@@ -264,6 +265,10 @@ def fv_model_forward_scratch_bytes(B: int, nx: int, ny: int) -> int:
 
 def fv_model_forward(m, q_ptr: int, B: int, nx: int, ny: int, z_ptr: int, scratch_ptr: int, scratch_bytes: int):
     _check(lib.fv_model_forward(m, q_ptr, B, nx, ny, z_ptr, scratch_ptr, scratch_bytes))
+
+
+def fv_model_forward_tiled(m, q_ptr: int, B: int, nx: int, ny: int, z_ptr: int):
+    _check(lib.fv_model_forward_tiled(m, q_ptr, B, nx, ny, z_ptr))
 
 
 def fv_learned_step(h, m, nsteps: int, want_stats: bool = True):
@@ -498,6 +503,15 @@ class Model:
         nb = fv_model_forward_scratch_bytes(B, nx, ny)
         sc = torch.empty(nb, dtype=torch.uint8, device=self.device)
         fv_model_forward(self.h, q.data_ptr(), B, nx, ny, z.data_ptr(), sc.data_ptr(), nb)
+        return z
+
+    def forward_tiled(self, q):
+        """The same z from the one-launch tiled pass (nx, ny multiples of 8)."""
+        import torch
+
+        B, _, ny, nx = q.shape
+        z = torch.empty((B, ny, nx, 72), dtype=torch.float32, device=self.device)
+        fv_model_forward_tiled(self.h, q.data_ptr(), B, nx, ny, z.data_ptr())
         return z
 
     def close(self):

@@ -139,7 +139,7 @@ def graph_replay(launch, total: int, chunk: int, stream):
     return time.perf_counter() - t0
 
 
-def evaluate(model, seeds, n_fine, factor, n_coarse_steps, plain_sizes=(64, 128, 256), chunk=50):
+def evaluate(model, seeds, n_fine, factor, n_coarse_steps, plain_sizes=(64, 128, 256, 512), chunk=50):
     """Errors at the final time of the learned coarse solver and of the plain
     scheme at plain_sizes against the fine reference (block-averaged), and
     graph-replayed time-to-solution of each."""
@@ -197,15 +197,20 @@ def main():
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval-seeds", type=int, default=4)
     ap.add_argument("--eval-steps", type=int, default=1000)
+    ap.add_argument("--plain-sizes", default="64,128,256,512",
+                    help="grid sides of the plain-scheme comparison runs (multiples of the coarse side)")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
+    plain_sizes = tuple(int(v) for v in a.plain_sizes.split(",") if v)
     t0 = time.perf_counter()
     data = dataset(range(1000, 1000 + a.train_seeds), a.n_fine, a.factor, a.traj_steps)
     tdata = time.perf_counter() - t0
     print(f"[data] {tuple(data.shape)} in {tdata:.1f} s", flush=True)
     model, hist, wall = train(data, a.iters, a.batch, a.T, a.lr, log_every=100, n_fine=a.n_fine, factor=a.factor)
     print(f"[train] {a.iters} iterations in {wall:.1f} s, loss {hist[0][2]:.3e} -> {hist[-1][2]:.3e}", flush=True)
-    res = evaluate(model, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps)
+    res = evaluate(model, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps, plain_sizes=plain_sizes)
+    print(f"[eval] " + ", ".join(f"{k}: rel L2(h) {v['rel_l2_h']:.3e} in {v['time_to_solution_s'] * 1e3:.1f} ms"
+                                 for k, v in res["cases"].items()), flush=True)
     untrained = fv.Model(init_params(0), model.desc)
     res["untrained"] = evaluate(untrained, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps,
                                 plain_sizes=())["cases"]["learned"]

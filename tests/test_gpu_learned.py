@@ -91,6 +91,24 @@ def test_network_ragged_batch_and_sizes(fv, L):
     m.close()
 
 
+def test_tiled_forward_bitwise_equals_layer_by_layer(fv, L):
+    """The one-launch tiled pass recomputes each tile's halo in LDS but keeps
+    every output's MFMA order, bias, ReLU and BF16 rounding: z must be
+    bit-identical to the layer-by-layer pass (several tiles, periodic wrap
+    across tile and grid edges, batches)."""
+    p = oracle_params(L, 3, scale_last=0.3)
+    m = gpu_model(fv, p)
+    for ny, nx, B in ((64, 64, 3), (32, 32, 5), (8, 16, 1), (24, 48, 2)):
+        q = (1.0 + 0.1 * np.random.default_rng(7 * ny + nx + B).standard_normal((B, 3, ny, nx))).astype(np.float32)
+        qt = torch.tensor(q, device="cuda")
+        z1 = m.forward(qt).cpu().numpy()
+        z2 = m.forward_tiled(qt).cpu().numpy()
+        ndiff = int(np.sum(z1 != z2))
+        print(f"[tiled] {ny}x{nx} B={B}: {ndiff} differing of {z1.size}", flush=True)
+        assert ndiff == 0
+    m.close()
+
+
 def run_learned(fv, L, p, q0, dt, nsteps, flux="hlle"):
     fl = fv.FV_FLUX_HLLE if flux == "hlle" else fv.FV_FLUX_RUSANOV
     n = q0.shape[-1]
