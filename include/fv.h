@@ -292,6 +292,10 @@ fv_status fv_train_state(fv_trainer *tr, int t, float *dst);
  * the model's weights (async on the model's stream). */
 fv_status fv_adam_step(fv_trainer *tr);
 
+/* Learning rate of the following fv_adam_step calls (a schedule is the
+ * caller's; the loss of eq 2.28 is minimised with Adam).  lr must be > 0. */
+fv_status fv_train_set_lr(fv_trainer *tr, float lr);
+
 void fv_train_destroy(fv_trainer *tr);
 
 /* Block-average coarsening (exact cell averages): coarse[v][J][I] = mean of

@@ -300,6 +300,14 @@ fv_status fv_adam_step(fv_trainer *tr)
     return e == hipSuccess ? FV_OK : hip_fail(e, "adam step");
 }
 
+fv_status fv_train_set_lr(fv_trainer *tr, float lr)
+{
+    if (!tr) return fail(FV_E_INVALID, "trainer is NULL");
+    if (!(lr > 0.0f)) return fail(FV_E_INVALID, "learning rate %g <= 0", (double)lr);
+    tr->cfg.lr = lr;
+    return FV_OK;
+}
+
 void fv_train_destroy(fv_trainer *tr)
 {
     if (!tr) return;

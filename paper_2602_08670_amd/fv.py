@@ -135,6 +135,7 @@ def _load():
         "fv_train_input_grad": ([vp, vp], st),
         "fv_train_state": ([vp, ctypes.c_int, vp], st),
         "fv_adam_step": ([vp], st),
+        "fv_train_set_lr": ([vp, ctypes.c_float], st),
         "fv_train_destroy": ([vp], None),
         "fv_coarsen": ([vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, vp], st),
         "fv_server_pool_overhead": ([ctypes.POINTER(fv_server_config)], ctypes.c_size_t),
@@ -310,6 +311,10 @@ def fv_adam_step(h):
     _check(lib.fv_adam_step(h))
 
 
+def fv_train_set_lr(h, lr: float):
+    _check(lib.fv_train_set_lr(h, float(lr)))
+
+
 def fv_train_destroy(h):
     lib.fv_train_destroy(h)
 
@@ -372,6 +377,9 @@ class Trainer:
 
     def adam(self):
         fv_adam_step(self.h)
+
+    def set_lr(self, lr: float):
+        fv_train_set_lr(self.h, lr)
 
     def close(self):
         if self.h is not None:

@@ -78,9 +78,11 @@ def init_params(seed: int) -> np.ndarray:
 
 
 def train(data, iters: int, B: int = 16, T_max: int = 8, lr: float = 1e-3, seed: int = 0, log_every: int = 0,
-          model=None, dt_c: float | None = None, n_fine: int | None = None, factor: int | None = None):
+          model=None, dt_c: float | None = None, n_fine: int | None = None, factor: int | None = None,
+          lr_final: float | None = None):
     """Curriculum training on windows of the coarse trajectories data
-    [n_traj, S+1, 3, n, n].  T grows 1 -> T_max over the first half."""
+    [n_traj, S+1, 3, n, n].  T grows 1 -> T_max over the first half; with
+    lr_final the learning rate follows a cosine from lr to lr_final."""
     import torch
 
     n_traj, S1, _, n, _ = data.shape
@@ -101,6 +103,8 @@ def train(data, iters: int, B: int = 16, T_max: int = 8, lr: float = 1e-3, seed:
         q0 = torch.stack([data[a, k] for a, k in zip(ti, ki)])
         tg = torch.stack([torch.stack([data[a, k + 1 + t] for a, k in zip(ti, ki)]) for t in range(T)])
         loss, stats = tr.step(q0, tg)
+        if lr_final is not None:
+            tr.set_lr(lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * it / max(1, iters - 1))))
         tr.adam()
         hist.append((it, T, loss))
         if log_every and it % log_every == 0:
@@ -191,10 +195,11 @@ def main():
     ap.add_argument("--factor", type=int, default=32)
     ap.add_argument("--train-seeds", type=int, default=40)
     ap.add_argument("--traj-steps", type=int, default=512)
-    ap.add_argument("--iters", type=int, default=1500)
+    ap.add_argument("--iters", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--T", type=int, default=8)
+    ap.add_argument("--T", type=int, default=16)
     ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr-final", type=float, default=2e-5, help="end of the cosine schedule (<= 0: constant)")
     ap.add_argument("--eval-seeds", type=int, default=4)
     ap.add_argument("--eval-steps", type=int, default=1000)
     ap.add_argument("--plain-sizes", default="64,128,256,512",
@@ -206,7 +211,8 @@ def main():
     data = dataset(range(1000, 1000 + a.train_seeds), a.n_fine, a.factor, a.traj_steps)
     tdata = time.perf_counter() - t0
     print(f"[data] {tuple(data.shape)} in {tdata:.1f} s", flush=True)
-    model, hist, wall = train(data, a.iters, a.batch, a.T, a.lr, log_every=100, n_fine=a.n_fine, factor=a.factor)
+    model, hist, wall = train(data, a.iters, a.batch, a.T, a.lr, log_every=100, n_fine=a.n_fine, factor=a.factor,
+                              lr_final=a.lr_final if a.lr_final > 0 else None)
     print(f"[train] {a.iters} iterations in {wall:.1f} s, loss {hist[0][2]:.3e} -> {hist[-1][2]:.3e}", flush=True)
     res = evaluate(model, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps, plain_sizes=plain_sizes)
     print(f"[eval] " + ", ".join(f"{k}: rel L2(h) {v['rel_l2_h']:.3e} in {v['time_to_solution_s'] * 1e3:.1f} ms"
