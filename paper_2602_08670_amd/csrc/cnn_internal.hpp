@@ -64,6 +64,41 @@ hipError_t launch_pack(const float *master, void *packed, hipStream_t st);
 hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny,
                           void *const acts[4], float *z, hipStream_t st);
 
+// Device descriptor of one learned solve (periodic nx x ny shallow water,
+// flat bed, fixed Delta t) for the work-list kernels.
+struct LSolve {
+    float *q, *s1, *s2;      // state and stage buffers [3][n][n]
+    float *z;                // constrained coefficients [n][n][72]
+    const float *dt;         // fixed step (device)
+    int *flags;              // two per-step flag slots
+    unsigned long long *nfb, *redone;
+    int *fatal;              // the plain redo failed: the solve is frozen
+    double *t;               // simulated time and step count
+    long long *steps;
+    int nx, ny;
+    float rdx, rdy, g, sqg, h0;  // 1/dx, 1/dy, gravity, sqrt(g), pressure reference depth
+    float pad;
+};
+// One solve of a step's list: its first workgroup in the network-pass and in
+// the stage launches (prefix sums over the list), and which flag slot the
+// step uses.
+struct LItem {
+    int solve, tb_cnn, tb_st, parity;
+};
+constexpr int LTILE_CNN = 8;            // network pass tile side
+constexpr int LTILE_X = 64, LTILE_Y = 8;  // stage tile
+inline int ltiles_cnn(int nx, int ny) { return (nx / LTILE_CNN) * (ny / LTILE_CNN); }
+inline int ltiles_st(int nx, int ny) { return ((nx + LTILE_X - 1) / LTILE_X) * ((ny + LTILE_Y - 1) / LTILE_Y); }
+
+// Work-list launches over the listed solves (one != 0: exactly one solve,
+// tab[items[0].solve]).  Network pass: stage 1 reads q, stage 2 reads S1,
+// both write alpha to z.  Learned stage: mode 0 with stage 1 or 2, mode 2, 3
+// (as learned_stage), HLLE.
+hipError_t launch_forward_batch(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve *tab,
+                                const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one = 0);
+hipError_t launch_learned_batch(int mode, int stage, const LSolve *tab, const LItem *items, const int *nitems,
+                                int ntiles, const Proj &pr, hipStream_t st, int one = 0);
+
 // The same forward in one launch, without keeping activations: every
 // workgroup runs all five layers on an 8x8 tile of pixels (nx % 8 == 0,
 // ny % 8 == 0); z is bit-identical to launch_forward's.  With alpha != NULL

@@ -244,6 +244,7 @@ hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, i
 // the same bias, ReLU and BF16 rounding, so z is bit-identical to the
 // layer-by-layer pass; only the halo pixels are computed more than once.
 constexpr int FT = 8;            // output tile side
+static_assert(FT == LTILE_CNN, "network pass tile of the work lists");
 constexpr int FR0 = FT + 8;      // side of layer 0's output region
 constexpr int FRI = FT + 10;     // side of the input region
 constexpr int FW_EL = 9 * 5 * 16 * 32;  // largest packed weight block (layer 4), bf16 elements
@@ -306,8 +307,53 @@ __device__ __forceinline__ void stage_weights(bf16x8 *s_w, const char *P, size_t
 // of every group of six (same operation order as the learned stage's own
 // projection, so alpha is bit-identical to projecting this kernel's z).
 template <bool ALPHA>
+__device__ __forceinline__ void fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
+                                           int H, int W, int y0, int x0, const Proj &pr);
+
+template <bool ALPHA>
 __global__ __launch_bounds__(FNW * 64) void conv_fused_kernel(const float *q, const char *P, Packed pk, Norm nrm, float *z,
-                                                         int B, int H, int W, Proj pr)
+                                                              int B, int H, int W, Proj pr)
+{
+    const int tx_n = W / FT, ty_n = H / FT;
+    const int tile = blockIdx.x;
+    const int b = tile / (tx_n * ty_n);
+    const int r = tile - b * tx_n * ty_n;
+    const size_t hw = (size_t)H * W;
+    fused_tile<ALPHA>(q + (size_t)b * 3 * hw, P, pk, nrm, z + (size_t)b * hw * 72, H, W, (r / tx_n) * FT,
+                      (r % tx_n) * FT, pr);
+}
+
+// Work-list form: workgroup w finds its solve by binary search over the
+// items' first network tile.  STAGE 1 reads q, STAGE 2 reads S1.
+template <int STAGE>
+__global__ __launch_bounds__(FNW * 64) void conv_fused_batch_kernel(const LSolve *tab, const LItem *items,
+                                                                    const int *nitems, int ntiles, int one,
+                                                                    const char *P, Packed pk, Norm nrm, Proj pr)
+{
+    const int w = blockIdx.x;
+    if (w >= ntiles) return;
+    LItem it;
+    if (one) {
+        it = items[0];
+    } else {
+        const int n = *nitems;
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].tb_cnn <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        it = items[lo];
+    }
+    const LSolve &d = tab[it.solve];
+    const int tile = w - it.tb_cnn, tx_n = d.nx / FT;
+    const int ty = tile / tx_n, tx = tile - ty * tx_n;
+    fused_tile<true>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, d.z, d.ny, d.nx, ty * FT, tx * FT, pr);
+}
+
+template <bool ALPHA>
+__device__ __forceinline__ void fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
+                                           int H, int W, int y0, int x0, const Proj &pr)
 {
     __shared__ bf16 s_in[3][FRI * FRI];
     __shared__ bf16x8 s_a0[FR0 * FR0 * 4];                  // 32 channels = 4 x bf16x8 per pixel
@@ -316,17 +362,11 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_kernel(const float *q, co
     constexpr int W0 = 32 * 32 / 8, WH = 9 * 32 * 32 / 8, W4 = FW_EL / 8;
     __shared__ bf16x8 s_wall[W0 + 3 * WH + W4];
 
-    const int tx_n = W / FT, ty_n = H / FT;
-    const int tile = blockIdx.x;
-    const int b = tile / (tx_n * ty_n);
-    const int r = tile - b * tx_n * ty_n;
-    const int y0 = (r / tx_n) * FT, x0 = (r % tx_n) * FT;
-    // the wave index as a scalar: MFMAs under `gi == wave` must sit behind a
-    // real branch (an MFMA does not honour a partial EXEC mask)
+    // the wave index as a scalar: MFMAs under a wave-dependent condition
+    // must sit behind a real branch (an MFMA does not honour a partial EXEC)
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, px = lane & 15;
     const size_t hw = (size_t)H * W;
-    const float *qb = q + (size_t)b * 3 * hw;
 
     // input region, normalised and rounded to BF16 as the first layer reads it
     for (int i = threadIdx.x; i < 3 * FRI * FRI; i += FNW * 64) {
@@ -422,7 +462,7 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_kernel(const float *q, co
 #pragma unroll
                     for (int i = 0; i < 4; i++) o[i] = acc[j][i] + bias[co0 + i];
                     if (ALPHA) *(floatx4 *)(s_z + p * 72 + co0) = o;
-                    else *(floatx4 *)(z + ((size_t)b * hw + (size_t)(y0 + py) * W + x0 + pxx) * 72 + co0) = o;
+                    else *(floatx4 *)(zb + ((size_t)(y0 + py) * W + x0 + pxx) * 72 + co0) = o;
                 }
             }
         }
@@ -435,7 +475,7 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_kernel(const float *q, co
             const int side = (grp / 3) & 1;
             const float *zz = s_z + p * 72 + grp * 6;
             const int py = p / FT, pxx = p - py * FT;
-            float *dst = z + ((size_t)b * hw + (size_t)(y0 + py) * W + x0 + pxx) * 72 + grp * 6;
+            float *dst = zb + ((size_t)(y0 + py) * W + x0 + pxx) * 72 + grp * 6;
 #pragma unroll
             for (int k = 0; k < 6; k++) {
                 float al = pr.base[side * 6 + k];
@@ -445,6 +485,20 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_kernel(const float *q, co
             }
         }
     }
+}
+
+hipError_t launch_forward_batch(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve *tab,
+                                const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const Packed pk = packed_layout();
+    if (stage == 1)
+        hipLaunchKernelGGL(conv_fused_batch_kernel<1>, dim3(ntiles), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
+                           one, (const char *)packed, pk, nrm, pr);
+    else
+        hipLaunchKernelGGL(conv_fused_batch_kernel<2>, dim3(ntiles), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
+                           one, (const char *)packed, pk, nrm, pr);
+    return hipGetLastError();
 }
 
 hipError_t launch_forward_fused(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny, float *z,

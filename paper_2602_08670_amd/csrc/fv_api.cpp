@@ -47,7 +47,7 @@ namespace {
 struct Layout {
     size_t ctl, rates, totals_out, partials, batch, s1, s2;
     // buffers of the learned step (cfg.learned == 1)
-    size_t act0, act1, z, s2l, small;
+    size_t act0, act1, z, s2l, small, lbatch;
     size_t total;
 };
 
@@ -61,6 +61,11 @@ int nvar_of(const fv_config *c) { return c->eqn == FV_EULER ? 4 : 3; }
 constexpr size_t BATCH_TAB = 0, BATCH_ITEMS = 256, BATCH_N = 320, BATCH_BYTES = 512;
 static_assert(sizeof(fvk::BatchSolve) <= BATCH_ITEMS && BATCH_ITEMS + 3 * sizeof(fvk::WorkItem) <= BATCH_N,
               "batch-of-one layout");
+
+// The learned step's descriptor and its two one-item lists (flag slot 0
+// and 1) for the work-list kernels, as the server uses them.
+constexpr size_t LB_TAB = 0, LB_ITEMS = 128, LB_N = 192, LBATCH_BYTES = 256;
+static_assert(sizeof(cnn::LSolve) <= LB_ITEMS && LB_ITEMS + 2 * sizeof(cnn::LItem) <= LB_N, "learned batch layout");
 
 bool runs_batched(const fv_config *c)
 {
@@ -111,9 +116,10 @@ Layout layout_of(const fv_config *c)
         L.z = L.act1 + align256(npix * cnn::CH * 2);
         L.s2l = L.z + align256(npix * cnn::COUT * 4);
         L.small = L.s2l + st;
-        end = L.small + 256;
+        L.lbatch = L.small + 256;
+        end = L.lbatch + LBATCH_BYTES;
     } else {
-        L.act0 = L.act1 = L.z = L.s2l = L.small = 0;
+        L.act0 = L.act1 = L.z = L.s2l = L.small = L.lbatch = 0;
     }
     L.total = end;
     return L;
@@ -202,6 +208,46 @@ fv_status enqueue_step(fv_solver *s)
     }
     if (e != hipSuccess) return hip_fail(e, "stage launch");
     s->enq++;
+    return FV_OK;
+}
+
+// offsets inside the 256-byte block of learned counters
+constexpr size_t SM_DT = 0, SM_BAD = 8, SM_NFB = 16, SM_REDONE = 24;
+
+fv_status upload_lbatch(fv_solver *s)
+{
+    alignas(16) char buf[LBATCH_BYTES];
+    std::memset(buf, 0, sizeof buf);
+    char *ws = s->ws, *sm = ws + s->L.small;
+    cnn::LSolve d{};
+    d.q = (float *)s->q;
+    d.s1 = (float *)(ws + s->L.s1);
+    d.s2 = (float *)(ws + s->L.s2l);
+    d.z = (float *)(ws + s->L.z);
+    d.dt = (const float *)(sm + SM_DT);
+    d.flags = (int *)(sm + SM_BAD);
+    d.nfb = (unsigned long long *)(sm + SM_NFB);
+    d.redone = (unsigned long long *)(sm + SM_REDONE);
+    d.fatal = &s->ctl()->bad;
+    d.t = &s->ctl()->t;
+    d.steps = &s->ctl()->step;
+    d.nx = s->cfg.nx;
+    d.ny = s->cfg.ny;
+    d.rdx = (float)s->d.rdx;
+    d.rdy = (float)s->d.rdy;
+    d.g = (float)s->cfg.g;
+    d.sqg = std::sqrt((float)s->cfg.g);
+    d.h0 = (float)s->d.h0;
+    std::memcpy(buf + LB_TAB, &d, sizeof d);
+    for (int p = 0; p < 2; p++) {
+        cnn::LItem it{0, 0, 0, p};
+        std::memcpy(buf + LB_ITEMS + p * sizeof it, &it, sizeof it);
+    }
+    const int one = 1;
+    std::memcpy(buf + LB_N, &one, sizeof one);
+    hipError_t e = hipMemcpyAsync(ws + s->L.lbatch, buf, sizeof buf, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // buf is on this stack frame
+    if (e != hipSuccess) return hip_fail(e, "learned descriptor upload");
     return FV_OK;
 }
 
@@ -331,6 +377,7 @@ fv_status fv_init(const fv_config *cfg, void *q, const void *bathy, void *worksp
     }
     s->batched = runs_batched(cfg);
     if (rc == FV_OK && s->batched) rc = upload_batch(s);
+    if (rc == FV_OK && cfg->learned) rc = upload_lbatch(s);
     if (rc != FV_OK) {
         delete s;
         return rc;
@@ -450,13 +497,6 @@ const char *fv_last_error(void) { return fvapi::last_error(); }
 
 // ------------------------------------------------------------ learned path
 
-namespace {
-
-// offsets inside the 256-byte block of learned counters
-constexpr size_t SM_DT = 0, SM_BAD = 8, SM_NFB = 16, SM_REDONE = 24;
-
-}  // namespace
-
 extern "C" {
 
 size_t fv_model_param_count(void) { return cnn::NPARAM; }
@@ -571,6 +611,27 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
     sb.pr = m->pr;
     sb.z = z;
     const int fl = c.flux == FV_FLUX_RUSANOV ? 1 : 0;  // kernel flux ids: 0 HLLE, 1 Rusanov
+    hipError_t e = hipSuccess;
+    if (fl == 0 && c.nx % 8 == 0 && c.ny % 8 == 0) {
+        // the server's work-list kernels as a batch of one: six launches per
+        // step (network pass and learned stage twice, commit-or-redo, redo
+        // and bookkeeping), bit-identical to the same solve in a served mix
+        const char *B = ws + L.lbatch;
+        const auto *tab = (const cnn::LSolve *)(B + LB_TAB);
+        const auto *items0 = (const cnn::LItem *)(B + LB_ITEMS);
+        const int *nit = (const int *)(B + LB_N);
+        const int tc = cnn::ltiles_cnn(c.nx, c.ny), ts = cnn::ltiles_st(c.nx, c.ny);
+        for (int64_t k = 0; k < nsteps && e == hipSuccess; k++, s->lsteps++) {
+            const cnn::LItem *it = items0 + (s->lsteps & 1);
+            e = cnn::launch_forward_batch(1, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
+            if (e == hipSuccess) e = cnn::launch_learned_batch(0, 1, tab, it, nit, ts, m->pr, s->stream, 1);
+            if (e == hipSuccess) e = cnn::launch_forward_batch(2, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
+            if (e == hipSuccess) e = cnn::launch_learned_batch(0, 2, tab, it, nit, ts, m->pr, s->stream, 1);
+            if (e == hipSuccess) e = cnn::launch_learned_batch(2, 0, tab, it, nit, ts, m->pr, s->stream, 1);
+            if (e == hipSuccess) e = cnn::launch_learned_batch(3, 0, tab, it, nit, ts, m->pr, s->stream, 1);
+        }
+        nsteps = 0;  // done; fall through to the statistics
+    }
     const bool fused = c.ny % 8 == 0;  // whole network in one launch per evaluation
     int *flags = (int *)(sm + SM_BAD);  // two slots: this step's and the next step's
     sb.redone = (unsigned long long *)(sm + SM_REDONE);
@@ -582,7 +643,6 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
         return fused ? cnn::launch_forward_fused(m->packed, m->nrm, in, 1, c.nx, c.ny, z, s->stream, &m->pr)
                      : cnn::launch_forward(m->packed, m->nrm, in, 1, c.nx, c.ny, acts, z, s->stream);
     };
-    hipError_t e = hipSuccess;
     for (int64_t k = 0; k < nsteps && e == hipSuccess; k++, s->lsteps++) {
         sb.bad = flags + (s->lsteps & 1);
         sb.bad_next = flags + ((s->lsteps + 1) & 1);

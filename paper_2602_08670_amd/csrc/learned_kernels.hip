@@ -114,8 +114,11 @@ __device__ __forceinline__ void flux3(const float *QL, const float *QR, const Ph
     F[TM] = G[2];
 }
 
-template <int MODE, int FLUX, bool AL = false>
-__global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
+// One 64 x 8 tile of solve b at (x0, y0); `first` marks the solve's tile
+// that does the per-step bookkeeping of MODE 3.
+template <int MODE, int FLUX, bool AL>
+__device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, const int x0, const int y0,
+                                             const bool first)
 {
     constexpr int TX = 64, TY = 8, HX = TX + 6, HY = TY + 6;
     __shared__ float s_q[3][HY][HX];
@@ -125,12 +128,10 @@ __global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
     __shared__ int s_bad;
 
     constexpr int FS = MODE == 0 ? 0 : 1;  // face states: learned or plain MINMOD
-    const int b = blockIdx.z;
     const int tid = threadIdx.x;
     const int nx = a.nx, ny = a.ny;
     const size_t plane = (size_t)nx * ny;
-    const int x0 = blockIdx.x * TX, y0 = blockIdx.y * TY;
-    if (MODE == 3 && blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) {
+    if (MODE == 3 && first && tid == 0) {
         // this step's flags are only read in this launch; the next step's
         // flags are not read before the next step
         const int flag = a.bad[b];
@@ -236,6 +237,84 @@ __global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
             else atomicExch(&a.fatal[b], 1);
         }
     }
+}
+
+template <int MODE, int FLUX, bool AL = false>
+__global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
+{
+    learned_tile<MODE, FLUX, AL>(a, blockIdx.z, blockIdx.x * 64, blockIdx.y * 8, blockIdx.x == 0 && blockIdx.y == 0);
+}
+
+// Work-list form over a table of solves of any size (serving, and single
+// solves as a batch of one): workgroup w finds its solve by binary search
+// over the items' first stage tile.  MODE 0 with STAGE 1 or 2, MODE 2, 3.
+template <int MODE, int STAGE>
+__global__ __launch_bounds__(256) void learned_batch_kernel(const LSolve *tab, const LItem *items, const int *nitems,
+                                                            int ntiles, int one, Proj pr)
+{
+    const int w = blockIdx.x;
+    if (w >= ntiles) return;
+    LItem it;
+    if (one) {
+        it = items[0];
+    } else {
+        const int n = *nitems;
+        int lo = 0, hi = n - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].tb_st <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        it = items[lo];
+    }
+    const LSolve &d = tab[it.solve];
+    LearnedArgs a;
+    a.B = 1;
+    a.nx = d.nx;
+    a.ny = d.ny;
+    a.rdx = d.rdx;
+    a.rdy = d.rdy;
+    a.ph.g = d.g;
+    a.ph.sqg = d.sqg;
+    a.ph.gamma = 1.4f;
+    a.ph.h0 = d.h0;
+    a.z = d.z;
+    a.dt = d.dt;
+    a.bad = d.flags + it.parity;
+    a.bad_next = d.flags + (it.parity ^ 1);
+    a.flagbit = STAGE;
+    a.nfb = d.nfb;
+    a.fatal = d.fatal;
+    a.redone = d.redone;
+    a.t = d.t;
+    a.steps = d.steps;
+    a.pr = pr;
+    a.commit_src = d.s2;
+    a.commit_dst = d.q;
+    if (MODE == 0 && STAGE == 2) {
+        a.qs = d.s1; a.q0 = d.q; a.out = d.s2; a.a0 = 0.5f; a.a1 = 0.5f;
+    } else if (MODE == 3) {
+        a.qs = d.s1; a.q0 = d.q; a.out = d.q; a.a0 = 0.5f; a.a1 = 0.5f;
+    } else {  // MODE 0 stage 1, MODE 2: q -> S1
+        a.qs = d.q; a.q0 = d.q; a.out = d.s1; a.a0 = 0.0f; a.a1 = 1.0f;
+    }
+    const int tile = w - it.tb_st;
+    const int tiles_x = (d.nx + LTILE_X - 1) / LTILE_X;
+    const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
+    learned_tile<MODE, fvk::HLLE, true>(a, 0, tx * LTILE_X, ty * LTILE_Y, tile == 0);
+}
+
+hipError_t launch_learned_batch(int mode, int stage, const LSolve *tab, const LItem *items, const int *nitems,
+                                int ntiles, const Proj &pr, hipStream_t st, int one)
+{
+    if (ntiles <= 0) return hipSuccess;
+    dim3 g(ntiles), b(256);
+    if (mode == 0 && stage == 1) hipLaunchKernelGGL((learned_batch_kernel<0, 1>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
+    else if (mode == 0 && stage == 2) hipLaunchKernelGGL((learned_batch_kernel<0, 2>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
+    else if (mode == 2) hipLaunchKernelGGL((learned_batch_kernel<2, 0>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
+    else if (mode == 3) hipLaunchKernelGGL((learned_batch_kernel<3, 0>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
+    else return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 // q[b] <- S2[b] for the solves whose learned step was admissible.
