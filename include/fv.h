@@ -306,15 +306,21 @@ fv_status fv_coarsen(const float *fine, int nvar, int nx, int ny, int factor, fl
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of independent FP32 solves (shallow water
  * over a bed, or Euler; HLLE, MINMOD, Heun, CFL time step; square grids on
- * the unit square).  Requests wait in a FIFO queue; at each round boundary
+ * the unit square), and of learned shallow-water solves (the network of the
+ * thesis's section 2.5.3 with the server's model, periodic, flat bed, fixed
+ * Delta t, Heun; the plain scheme redoes inadmissible steps).  Requests wait
+ * in a FIFO queue; at each round boundary
  * those whose device footprint (fv_request_bytes) fits the free part of the
  * caller's memory pool are admitted (a later request may pass one that does
  * not fit).  A round advances every active solve by up to steps_per_round
  * steps, each stage of each step being one batched launch over the tiles of
- * all active solves of an equation type; finished solves are copied back
- * and their memory returns to the pool.  The per-cell arithmetic is the
- * single-solve kernel's, so a solve's result is bit-identical alone (fv_run)
- * and in any mix.
+ * all active solves of an equation type; for the learned solves each step
+ * is six batched launches (the network pass of every learned solve in one
+ * BF16 MFMA launch, the learned stage, both twice, then commit-or-redo and
+ * redo).  Finished solves are copied back and their memory returns to the
+ * pool.  The single-solve calls (fv_run, fv_learned_step) run the same
+ * kernels as a batch of one, so a solve's result is bit-identical alone and
+ * in any mix.
  * ------------------------------------------------------------------------ */
 typedef struct {
     uint32_t struct_size;    /* sizeof(fv_server_config) */
@@ -322,6 +328,8 @@ typedef struct {
     int32_t steps_per_round; /* K: steps between admission/retirement points */
     int32_t reserved0;       /* must be 0 */
     uint64_t max_items;      /* most tiles (workgroups) one batched launch may hold */
+    const fv_model *model;   /* network of the learned requests (NULL: none accepted); its
+                                packed weights must be ready (its stream synchronised) */
 } fv_server_config;
 
 typedef struct {
@@ -334,6 +342,9 @@ typedef struct {
     double h_ref;            /* SWE pressure reference depth, 0 = mean initial depth */
     const float *q0;         /* host [nvar][n][n]; copied by fv_server_submit */
     const float *bed;        /* host [n][n] (SWE, nullable); copied */
+    int32_t learned;         /* 1: learned solve (SWE, periodic, no bed, n % 16 == 0) */
+    int32_t reserved1;       /* must be 0 */
+    double dt_fixed;         /* learned: the fixed time step (> 0); `steps` learned steps */
 } fv_request;
 
 typedef struct {
@@ -342,6 +353,8 @@ typedef struct {
     int64_t steps_done;
     double t_submit, t_admit, t_done; /* seconds since fv_server_create */
     double sim_time;         /* simulated time reached (done requests) */
+    int64_t fallback_faces;  /* learned: face sides that fell back to MINMOD */
+    int64_t redone_steps;    /* learned: steps redone with the plain scheme */
 } fv_request_info;
 
 typedef struct fv_server fv_server;

@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "api_common.hpp"
+#include "cnn_internal.hpp"
 #include "fv_internal.hpp"
 
 using fvapi::align256;
@@ -46,12 +47,21 @@ struct Req {
     int tiles_x = 0, tiles = 0;
     double sim_time = 0;
     size_t q_off, s1_off, bed_off, ctl_off, rates_off;
+    size_t s2_off, z_off, small_off;  // learned requests
+    int64_t fallback_faces = 0, redone_steps = 0;
     int nvar() const { return r.eqn == FV_EULER ? 4 : 3; }
+    bool learned() const { return r.learned != 0; }
 };
+
+// learned counters block: dt (float) at 0, two flag slots at 8, fallback
+// faces at 16, redone steps at 24
+constexpr size_t LS_DT = 0, LS_FLAGS = 8, LS_NFB = 16, LS_REDONE = 24, LS_BYTES = 256;
 
 size_t req_bytes(const fv_request *r)
 {
     size_t n2 = (size_t)r->n * r->n;
+    if (r->learned)  // q, S1, S2, alpha, control block, counters
+        return 3 * align256(3 * n2 * 4) + align256(n2 * cnn::COUT * 4) + fvk::CTL_BYTES + LS_BYTES;
     int nvar = r->eqn == FV_EULER ? 4 : 3;
     size_t b = 2 * align256(nvar * n2 * 4) + fvk::CTL_BYTES + fvk::RATE_BYTES;
     if (r->eqn == FV_SWE) b += align256(n2 * 4);
@@ -67,7 +77,7 @@ struct fv_server {
     hipStream_t stream;
     std::chrono::steady_clock::time_point t0;
     // pool regions
-    size_t tab_off, items_off, nitems_off, scratch_off, heap_off;
+    size_t tab_off, items_off, nitems_off, scratch_off, ltab_off, litems_off, lnitems_off, heap_off;
     std::map<size_t, size_t> free_list;  // offset -> size
     // host side
     std::deque<Req *> queue;
@@ -78,6 +88,9 @@ struct fv_server {
     fvk::WorkItem *h_items = nullptr;  // pinned
     int *h_nitems = nullptr;
     std::vector<fvk::BatchSolve> h_tab;
+    cnn::LItem *h_litems = nullptr;    // pinned
+    int *h_lnitems = nullptr;
+    std::vector<cnn::LSolve> h_ltab;
 
     double now() const
     {
@@ -130,12 +143,18 @@ fv_status validate(const fv_server_config *c)
     return FV_OK;
 }
 
+// learned solves: one list per step, one item per active learned solve
+size_t litems_capacity(const fv_server_config *c) { return (size_t)c->steps_per_round * c->max_solves; }
+
 size_t overhead(const fv_server_config *c)
 {
     size_t o = align256(sizeof(fvk::BatchSolve) * c->max_solves);
     o += align256(items_capacity(c) * sizeof(fvk::WorkItem));
     o += align256((size_t)c->steps_per_round * 2 * sizeof(int));
     o += align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * 8 + 256);
+    o += align256(sizeof(cnn::LSolve) * c->max_solves);
+    o += align256(litems_capacity(c) * sizeof(cnn::LItem));
+    o += align256((size_t)c->steps_per_round * sizeof(int));
     return o;
 }
 
@@ -146,6 +165,14 @@ fv_status validate_req(const fv_request *r)
     if (r->n < 8) return fail(FV_E_INVALID, "grid side %d < 8", r->n);
     if (r->bc != FV_BC_PERIODIC && r->bc != FV_BC_WALL) return fail(FV_E_INVALID, "bc %d", r->bc);
     if (r->steps < 0) return fail(FV_E_INVALID, "steps < 0");
+    if (r->reserved1 != 0 || (r->learned != 0 && r->learned != 1)) return fail(FV_E_INVALID, "learned / reserved1");
+    if (r->learned) {
+        if (r->eqn != FV_SWE || r->bc != FV_BC_PERIODIC || r->bed || r->n % 16 || !(r->dt_fixed > 0) || !(r->g > 0))
+            return fail(FV_E_INVALID, "learned requests: SWE, periodic, no bed, n %% 16 == 0, dt_fixed > 0, g > 0");
+        if (!(r->h_ref >= 0)) return fail(FV_E_INVALID, "h_ref < 0");
+        if (!r->q0) return fail(FV_E_INVALID, "initial state is NULL");
+        return FV_OK;
+    }
     if (!(r->cfl > 0 && r->cfl <= 1)) return fail(FV_E_INVALID, "cfl");
     if (!r->q0) return fail(FV_E_INVALID, "initial state is NULL");
     if (r->eqn == FV_EULER && r->bed) return fail(FV_E_INVALID, "a bed is only defined for shallow water");
@@ -154,8 +181,52 @@ fv_status validate_req(const fv_request *r)
 
 // Upload an admitted request and compute its first CFL rate (and reference
 // depth for shallow water) exactly as fv_init does for a single solve.
+fv_status admit_learned(fv_server *s, Req *q, std::vector<Req *> &need_h0)
+{
+    const fv_request &r = q->r;
+    const size_t n2 = (size_t)r.n * r.n, st = align256(3 * n2 * 4);
+    q->q_off = q->off;
+    q->s1_off = q->q_off + st;
+    q->s2_off = q->s1_off + st;
+    q->z_off = q->s2_off + st;
+    q->ctl_off = q->z_off + align256(n2 * cnn::COUT * 4);
+    q->small_off = q->ctl_off + fvk::CTL_BYTES;
+    char *P = s->pool;
+    char small[LS_BYTES];
+    std::memset(small, 0, sizeof small);
+    const float dtf = (float)r.dt_fixed;
+    std::memcpy(small + LS_DT, &dtf, sizeof dtf);
+    hipError_t e = hipMemcpyAsync(P + q->q_off, q->q0.data(), 3 * n2 * 4, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(P + q->ctl_off, 0, fvk::CTL_BYTES, s->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(P + q->small_off, small, sizeof small, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // `small` is on this stack frame
+    if (e != hipSuccess) return hip_fail(e, "admission upload");
+    cnn::LSolve &d = s->h_ltab[q->slot];
+    d = cnn::LSolve{};
+    d.q = (float *)(P + q->q_off);
+    d.s1 = (float *)(P + q->s1_off);
+    d.s2 = (float *)(P + q->s2_off);
+    d.z = (float *)(P + q->z_off);
+    d.dt = (const float *)(P + q->small_off + LS_DT);
+    d.flags = (int *)(P + q->small_off + LS_FLAGS);
+    d.nfb = (unsigned long long *)(P + q->small_off + LS_NFB);
+    d.redone = (unsigned long long *)(P + q->small_off + LS_REDONE);
+    fvk::Ctl *ctl = (fvk::Ctl *)(P + q->ctl_off);
+    d.fatal = &ctl->bad;
+    d.t = &ctl->t;
+    d.steps = &ctl->step;
+    d.nx = d.ny = r.n;
+    d.rdx = d.rdy = (float)(double)r.n;  // unit square
+    d.g = (float)r.g;
+    d.sqg = std::sqrt((float)r.g);
+    d.h0 = (float)r.h_ref;
+    if (!(r.h_ref > 0)) need_h0.push_back(q);
+    return FV_OK;
+}
+
 fv_status admit(fv_server *s, Req *q, std::vector<Req *> &need_h0)
 {
+    if (q->learned()) return admit_learned(s, q, need_h0);
     const fv_request &r = q->r;
     size_t n2 = (size_t)r.n * r.n;
     int nvar = q->nvar();
@@ -238,14 +309,22 @@ fv_status fv_server_create(const fv_server_config *cfg, void *pool, size_t pool_
     s->items_off = align256(sizeof(fvk::BatchSolve) * cfg->max_solves);
     s->nitems_off = s->items_off + align256(items_capacity(cfg) * sizeof(fvk::WorkItem));
     s->scratch_off = s->nitems_off + align256((size_t)cfg->steps_per_round * 2 * sizeof(int));
+    s->ltab_off = s->scratch_off + align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * 8 + 256);
+    s->litems_off = s->ltab_off + align256(sizeof(cnn::LSolve) * cfg->max_solves);
+    s->lnitems_off = s->litems_off + align256(litems_capacity(cfg) * sizeof(cnn::LItem));
     s->heap_off = ov;
     s->free_list[s->heap_off] = pool_bytes - s->heap_off;
     s->h_tab.assign(cfg->max_solves, fvk::BatchSolve{});
+    s->h_ltab.assign(cfg->max_solves, cnn::LSolve{});
     for (int i = cfg->max_solves - 1; i >= 0; i--) s->free_slots.push_back(i);
     hipError_t e = hipHostMalloc((void **)&s->h_items, items_capacity(cfg) * sizeof(fvk::WorkItem), 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_nitems, (size_t)cfg->steps_per_round * 2 * sizeof(int), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_litems, litems_capacity(cfg) * sizeof(cnn::LItem), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_lnitems, (size_t)cfg->steps_per_round * sizeof(int), 0);
     if (e != hipSuccess) {
         if (s->h_items) (void)hipHostFree(s->h_items);
+        if (s->h_nitems) (void)hipHostFree(s->h_nitems);
+        if (s->h_litems) (void)hipHostFree(s->h_litems);
         return hip_fail(e, "pinned work-list buffers");
     }
     *out = s.release();
@@ -257,6 +336,7 @@ fv_status fv_server_submit(fv_server *s, const fv_request *r, int64_t *id)
     if (!s || !id) return fail(FV_E_INVALID, "NULL argument");
     fv_status rc = validate_req(r);
     if (rc != FV_OK) return rc;
+    if (r->learned && !s->cfg.model) return fail(FV_E_INVALID, "a learned request needs a server model");
     if (req_bytes(r) > s->pool_bytes - s->heap_off)
         return fail(FV_E_NOMEM, "request needs %zu bytes, the pool holds %zu", req_bytes(r), s->pool_bytes - s->heap_off);
     auto q = std::make_unique<Req>();
@@ -317,12 +397,16 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
             if (e == hipSuccess) e = hipMemcpyAsync(tot, out, sizeof tot, hipMemcpyDeviceToHost, s->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
             if (e != hipSuccess) return hip_fail(e, "reference depth");
-            s->h_tab[q->slot].h0 = tot[0];  // unit square: mean depth = mass
+            if (q->learned()) s->h_ltab[q->slot].h0 = (float)tot[0];
+            else s->h_tab[q->slot].h0 = tot[0];  // unit square: mean depth = mass
         }
     }
     if (!admitted.empty()) {
         e = hipMemcpyAsync(P + s->tab_off, s->h_tab.data(), sizeof(fvk::BatchSolve) * s->cfg.max_solves,
                            hipMemcpyHostToDevice, s->stream);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(P + s->ltab_off, s->h_ltab.data(), sizeof(cnn::LSolve) * s->cfg.max_solves,
+                               hipMemcpyHostToDevice, s->stream);
         if (e != hipSuccess) return hip_fail(e, "solve table upload");
     }
     // ---- work-lists of the round: one list per [step][type] (type 0 = SWE,
@@ -330,9 +414,25 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
     // back; tiles per launch are capped by max_items
     const size_t ncap = (size_t)s->cfg.max_solves;
     std::vector<int> counts((size_t)K * 2, 0), grids((size_t)K * 2, 0);
+    std::vector<int> lcounts((size_t)K, 0), lgrid_cnn((size_t)K, 0), lgrid_st((size_t)K, 0);
     for (int k = 0; k < K; k++)
         for (Req *q : s->active) {
             if (q->r.steps - q->done_steps <= k) continue;
+            if (q->learned()) {
+                const int tc = cnn::ltiles_cnn(q->r.n, q->r.n), ts = cnn::ltiles_st(q->r.n, q->r.n);
+                if ((uint64_t)lgrid_cnn[k] + tc > s->cfg.max_items || (uint64_t)lgrid_st[k] + ts > s->cfg.max_items)
+                    return fail(FV_E_NOMEM, "more than max_items = %llu tiles in one launch",
+                                (unsigned long long)s->cfg.max_items);
+                cnn::LItem &w = s->h_litems[(size_t)k * ncap + lcounts[k]];
+                w.solve = q->slot;
+                w.tb_cnn = lgrid_cnn[k];
+                w.tb_st = lgrid_st[k];
+                w.parity = (int)((q->done_steps + k) & 1);
+                lcounts[k]++;
+                lgrid_cnn[k] += tc;
+                lgrid_st[k] += ts;
+                continue;
+            }
             int type = q->r.eqn == FV_EULER ? 1 : 0;
             size_t li = (size_t)k * 2 + type;
             if ((uint64_t)grids[li] + q->tiles > s->cfg.max_items)
@@ -359,14 +459,39 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
     e = hipMemcpyAsync(d_items, s->h_items, used * sizeof(fvk::WorkItem), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(d_nitems, s->h_nitems, (size_t)K * 2 * sizeof(int), hipMemcpyHostToDevice, s->stream);
+    // learned lists
+    cnn::LItem *d_litems = (cnn::LItem *)(P + s->litems_off);
+    int *d_lnitems = (int *)(P + s->lnitems_off);
+    size_t lused = 0;
+    for (int k = 0; k < K; k++) {
+        s->h_lnitems[k] = lcounts[k];
+        if (lcounts[k]) lused = (size_t)k * ncap + lcounts[k];
+    }
+    if (e == hipSuccess && lused)
+        e = hipMemcpyAsync(d_litems, s->h_litems, lused * sizeof(cnn::LItem), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess && lused)
+        e = hipMemcpyAsync(d_lnitems, s->h_lnitems, (size_t)K * sizeof(int), hipMemcpyHostToDevice, s->stream);
     const fvk::BatchSolve *tab = (const fvk::BatchSolve *)(P + s->tab_off);
-    for (int k = 0; k < K && e == hipSuccess; k++)
+    const cnn::LSolve *ltab = (const cnn::LSolve *)(P + s->ltab_off);
+    const fv_model *m = s->cfg.model;
+    for (int k = 0; k < K && e == hipSuccess; k++) {
         for (int stage = 1; stage <= 2 && e == hipSuccess; stage++)
             for (int type = 0; type < 2 && e == hipSuccess; type++) {
                 size_t li = (size_t)k * 2 + type;
                 e = fvk::launch_batch_stage(type == 1 ? FV_EULER : FV_SWE, type == 0, stage, tab, d_items + li * ncap,
                                             d_nitems + li, grids[li], s->stream);
             }
+        if (!lcounts[k] || e != hipSuccess) continue;
+        // learned solves: every network pass of the step in one launch
+        const cnn::LItem *it = d_litems + (size_t)k * ncap;
+        const int *nit = d_lnitems + k;
+        e = cnn::launch_forward_batch(1, m->packed, m->nrm, m->pr, ltab, it, nit, lgrid_cnn[k], s->stream);
+        if (e == hipSuccess) e = cnn::launch_learned_batch(0, 1, ltab, it, nit, lgrid_st[k], m->pr, s->stream);
+        if (e == hipSuccess) e = cnn::launch_forward_batch(2, m->packed, m->nrm, m->pr, ltab, it, nit, lgrid_cnn[k], s->stream);
+        if (e == hipSuccess) e = cnn::launch_learned_batch(0, 2, ltab, it, nit, lgrid_st[k], m->pr, s->stream);
+        if (e == hipSuccess) e = cnn::launch_learned_batch(2, 0, ltab, it, nit, lgrid_st[k], m->pr, s->stream);
+        if (e == hipSuccess) e = cnn::launch_learned_batch(3, 0, ltab, it, nit, lgrid_st[k], m->pr, s->stream);
+    }
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_fail(e, "round");
     // ---- retire finished solves
@@ -384,6 +509,12 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
         fvk::Ctl c;
         e = hipMemcpy(q->result.data(), P + q->q_off, n * 4, hipMemcpyDeviceToHost);
         if (e == hipSuccess) e = hipMemcpy(&c, P + q->ctl_off, sizeof c, hipMemcpyDeviceToHost);
+        if (e == hipSuccess && q->learned()) {
+            unsigned long long cnt[2];
+            e = hipMemcpy(cnt, P + q->small_off + LS_NFB, sizeof cnt, hipMemcpyDeviceToHost);
+            q->fallback_faces = (int64_t)cnt[0];
+            q->redone_steps = (int64_t)cnt[1];
+        }
         if (e != hipSuccess) return hip_fail(e, "result copy");
         q->sim_time = c.t;
         q->state = c.bad ? 3 : 2;
@@ -411,6 +542,8 @@ fv_status fv_server_info(fv_server *s, int64_t id, fv_request_info *info)
     info->t_admit = q.t_admit;
     info->t_done = q.t_done;
     info->sim_time = q.sim_time;
+    info->fallback_faces = q.fallback_faces;
+    info->redone_steps = q.redone_steps;
     return FV_OK;
 }
 
@@ -440,6 +573,8 @@ void fv_server_destroy(fv_server *s)
     (void)hipStreamSynchronize(s->stream);
     if (s->h_items) (void)hipHostFree(s->h_items);
     if (s->h_nitems) (void)hipHostFree(s->h_nitems);
+    if (s->h_litems) (void)hipHostFree(s->h_litems);
+    if (s->h_lnitems) (void)hipHostFree(s->h_lnitems);
     delete s;
 }
 

@@ -64,20 +64,22 @@ class fv_train_config(ctypes.Structure):
 
 class fv_server_config(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_solves", ctypes.c_int32),
-                ("steps_per_round", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("max_items", ctypes.c_uint64)]
+                ("steps_per_round", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("max_items", ctypes.c_uint64),
+                ("model", ctypes.c_void_p)]
 
 
 class fv_request(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("eqn", ctypes.c_int32), ("n", ctypes.c_int32),
                 ("bc", ctypes.c_int32), ("steps", ctypes.c_int64), ("cfl", ctypes.c_double), ("g", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("h_ref", ctypes.c_double), ("q0", ctypes.c_void_p),
-                ("bed", ctypes.c_void_p)]
+                ("bed", ctypes.c_void_p), ("learned", ctypes.c_int32), ("reserved1", ctypes.c_int32),
+                ("dt_fixed", ctypes.c_double)]
 
 
 class fv_request_info(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("pad", ctypes.c_int32), ("steps_done", ctypes.c_int64),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
-                ("sim_time", ctypes.c_double)]
+                ("sim_time", ctypes.c_double), ("fallback_faces", ctypes.c_int64), ("redone_steps", ctypes.c_int64)]
 
 
 def make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0), order=1, hidden=32) -> fv_model_desc:
@@ -404,15 +406,20 @@ def coarsen(fine, factor):
     return out
 
 
-def make_request(q0, steps, bed=None, bc=FV_BC_WALL, cfl=0.4, g=9.81, gamma=1.4, h_ref=0.0):
+def make_request(q0, steps, bed=None, bc=FV_BC_WALL, cfl=0.4, g=9.81, gamma=1.4, h_ref=0.0, learned=False,
+                 dt_fixed=0.0):
     """Request over host arrays (kept referenced by the returned tuple until
-    fv_server_submit copied them)."""
+    fv_server_submit copied them).  learned=True: a learned solve (periodic,
+    no bed) of `steps` steps of dt_fixed with the server's model."""
     q0 = np.ascontiguousarray(q0, dtype=np.float32)
     nvar, n, n2 = q0.shape
     assert n == n2
     b = None if bed is None else np.ascontiguousarray(bed, dtype=np.float32)
+    if learned:
+        bc = FV_BC_PERIODIC
     r = fv_request(ctypes.sizeof(fv_request), FV_SWE if nvar == 3 else FV_EULER, n, bc, int(steps), cfl, g, gamma,
-                   h_ref, q0.ctypes.data, None if b is None else b.ctypes.data)
+                   h_ref, q0.ctypes.data, None if b is None else b.ctypes.data, 1 if learned else 0, 0,
+                   float(dt_fixed))
     return r, (q0, b)
 
 
@@ -420,10 +427,14 @@ class Server:
     """Continuous-batching server over a torch-allocated device pool."""
 
     def __init__(self, pool_bytes: int, max_solves: int = 1024, steps_per_round: int = 24,
-                 max_items: int = 1 << 18, device="cuda", stream=None):
+                 max_items: int = 1 << 18, device="cuda", stream=None, model=None):
         import torch
 
-        self.cfg = fv_server_config(ctypes.sizeof(fv_server_config), max_solves, steps_per_round, 0, max_items)
+        self.model = model  # kept alive while the server runs
+        if model is not None:
+            torch.cuda.synchronize()  # the model's packed weights are ready
+        self.cfg = fv_server_config(ctypes.sizeof(fv_server_config), max_solves, steps_per_round, 0, max_items,
+                                    None if model is None else model.h)
         self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
         h = ctypes.c_void_p()

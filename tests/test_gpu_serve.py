@@ -104,3 +104,69 @@ def test_request_larger_than_pool_rejected(fv):
         srv.submit(q, 10, bed=b)
     assert e.value.code == fv.FV_E_NOMEM
     srv.close()
+
+
+def small_model(fv, seed, scale=0.02, bias_last=0.0):
+    """A network with small seeded weights (and an optional constant bias on
+    the raw coefficients of the last layer)."""
+    rng = np.random.default_rng(seed)
+    vec = (rng.standard_normal(49448) * scale).astype(np.float32)
+    vec[-72:] += bias_last
+    return fv.Model(vec, fv.make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0)))
+
+
+def test_learned_mix_bitwise_equals_alone(fv):
+    """Learned requests of several sizes served together with plain ones: each
+    learned result (state, time, fallback and redo counts) is bit-identical to
+    fv_learned_step on the same solve alone -- both run the work-list kernels,
+    the single solve as a batch of one."""
+    from paper_2602_08670_amd import learned_solver as LS
+
+    m = small_model(fv, 11, scale=0.03, bias_last=0.5)
+    dt = LS.fine_dt(2048) * 32
+    learned_specs = [(32, 1, 37), (64, 2, 25), (48, 3, 31), (128, 4, 12)]
+    plain_specs = [("swe", 64, 5, 20), ("euler", 96, 6, 30)]
+    srv = fv.Server(256 << 20, max_solves=16, steps_per_round=10, max_items=1 << 14, model=m)
+    lids, pids = [], []
+    for n, seed, steps in learned_specs:
+        q = I.random_smooth_swe(n, seed=seed).astype(np.float32)
+        lids.append(srv.submit(q, steps, learned=True, dt_fixed=dt))
+    for kind, n, seed, steps in plain_specs:
+        q, b = make_req(kind, n, seed)
+        pids.append(srv.submit(q, steps, bed=b))
+    rounds = 0
+    while True:
+        a, qd = srv.round()
+        rounds += 1
+        if a == 0 and qd == 0:
+            break
+        assert rounds < 100
+    for rid, (n, seed, steps) in zip(lids, learned_specs):
+        q = I.random_smooth_swe(n, seed=seed).astype(np.float32)
+        got = srv.result(rid, q.shape)
+        inf = srv.info(rid)
+        s = fv.Solver(q, prec=fv.FV_F32, dt_fixed=dt, learned=1)
+        fb, red = s.learned_step(m, steps)
+        ref = s.state().astype(np.float32)
+        t, k = s.time()
+        s.close()
+        print(f"[serve learned] {n}^2 {steps} steps: t={inf.sim_time:.6f} alone t={t:.6f}, fallback "
+              f"{inf.fallback_faces}/{fb}, redone {inf.redone_steps}/{red}", flush=True)
+        assert inf.state == 2 and inf.steps_done == steps
+        assert np.array_equal(got, ref), (n, steps)
+        assert inf.sim_time == t
+        assert (inf.fallback_faces, inf.redone_steps) == (fb, red)
+    for rid, (kind, n, seed, steps) in zip(pids, plain_specs):
+        q, b = make_req(kind, n, seed)
+        ref, t = alone(fv, q, b, steps)
+        assert np.array_equal(srv.result(rid, q.shape), ref), (kind, n)
+    srv.close()
+    m.close()
+
+
+def test_learned_request_needs_model(fv):
+    srv = fv.Server(64 << 20, max_solves=4, steps_per_round=4, max_items=1 << 12)
+    q = I.random_smooth_swe(32, seed=0).astype(np.float32)
+    with pytest.raises(fv.FvError):
+        srv.submit(q, 5, learned=True, dt_fixed=1e-3)
+    srv.close()
