@@ -306,7 +306,7 @@ fv_status fv_coarsen(const float *fine, int nvar, int nx, int ny, int factor, fl
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of independent FP32 solves (shallow water
  * over a bed, or Euler; HLLE, MINMOD, Heun, CFL time step; square grids on
- * the unit square), and of learned shallow-water solves (the network of the
+ * a square domain), and of learned shallow-water solves (the network of the
  * thesis's section 2.5.3 with the server's model, periodic, flat bed, fixed
  * Delta t, Heun; the plain scheme redoes inadmissible steps).  Requests wait
  * in a FIFO queue; at each round boundary
@@ -327,7 +327,8 @@ typedef struct {
     int32_t max_solves;      /* solve slots */
     int32_t steps_per_round; /* K: steps between admission/retirement points */
     int32_t reserved0;       /* must be 0 */
-    uint64_t max_items;      /* most tiles (workgroups) one batched launch may hold */
+    uint64_t max_items;      /* most tiles (workgroups) one batched launch may hold: admission keeps
+                                every launch within it; a request that alone needs more is rejected */
     const fv_model *model;   /* network of the learned requests (NULL: none accepted); its
                                 packed weights must be ready (its stream synchronised) */
 } fv_server_config;
@@ -345,6 +346,7 @@ typedef struct {
     int32_t learned;         /* 1: learned solve (SWE, periodic, no bed, n % 16 == 0) */
     int32_t reserved1;       /* must be 0 */
     double dt_fixed;         /* learned: the fixed time step (> 0); `steps` learned steps */
+    double lx;               /* side of the square domain (0: the unit square) */
 } fv_request;
 
 typedef struct {

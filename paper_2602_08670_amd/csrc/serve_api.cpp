@@ -53,6 +53,8 @@ struct Req {
     bool learned() const { return r.learned != 0; }
 };
 
+double side(const fv_request &r) { return r.lx > 0 ? r.lx : 1.0; }
+
 // learned counters block: dt (float) at 0, two flag slots at 8, fallback
 // faces at 16, redone steps at 24
 constexpr size_t LS_DT = 0, LS_FLAGS = 8, LS_NFB = 16, LS_REDONE = 24, LS_BYTES = 256;
@@ -166,6 +168,7 @@ fv_status validate_req(const fv_request *r)
     if (r->bc != FV_BC_PERIODIC && r->bc != FV_BC_WALL) return fail(FV_E_INVALID, "bc %d", r->bc);
     if (r->steps < 0) return fail(FV_E_INVALID, "steps < 0");
     if (r->reserved1 != 0 || (r->learned != 0 && r->learned != 1)) return fail(FV_E_INVALID, "learned / reserved1");
+    if (!(r->lx >= 0)) return fail(FV_E_INVALID, "domain side lx < 0");
     if (r->learned) {
         if (r->eqn != FV_SWE || r->bc != FV_BC_PERIODIC || r->bed || r->n % 16 || !(r->dt_fixed > 0) || !(r->g > 0))
             return fail(FV_E_INVALID, "learned requests: SWE, periodic, no bed, n %% 16 == 0, dt_fixed > 0, g > 0");
@@ -216,7 +219,7 @@ fv_status admit_learned(fv_server *s, Req *q, std::vector<Req *> &need_h0)
     d.t = &ctl->t;
     d.steps = &ctl->step;
     d.nx = d.ny = r.n;
-    d.rdx = d.rdy = (float)(double)r.n;  // unit square
+    d.rdx = d.rdy = (float)(r.n / side(r));
     d.g = (float)r.g;
     d.sqg = std::sqrt((float)r.g);
     d.h0 = (float)r.h_ref;
@@ -256,7 +259,7 @@ fv_status admit(fv_server *s, Req *q, std::vector<Req *> &need_h0)
     d.rates = P + q->rates_off;
     d.nx = d.ny = r.n;
     d.bc_x = d.bc_y = r.bc;
-    d.rdx = d.rdy = (double)r.n;  // unit square
+    d.rdx = d.rdy = r.n / side(r);
     d.g = r.g;
     d.sqg = std::sqrt(r.g);
     d.gamma = r.gamma;
@@ -269,7 +272,7 @@ fv_status admit(fv_server *s, Req *q, std::vector<Req *> &need_h0)
     sd.bathy = r.eqn == FV_SWE;
     sd.nx = sd.ny = r.n;
     sd.bc_x = sd.bc_y = r.bc;
-    sd.rdx = sd.rdy = r.n;
+    sd.rdx = sd.rdy = r.n / side(r);
     sd.g = r.g;
     sd.gamma = r.gamma;
     e = fvk::launch_rate(sd, P + q->q_off, (fvk::Ctl *)(P + q->ctl_off), (unsigned long long *)(P + q->rates_off), 0,
@@ -337,6 +340,15 @@ fv_status fv_server_submit(fv_server *s, const fv_request *r, int64_t *id)
     fv_status rc = validate_req(r);
     if (rc != FV_OK) return rc;
     if (r->learned && !s->cfg.model) return fail(FV_E_INVALID, "a learned request needs a server model");
+    {
+        const uint64_t n = (uint64_t)r->n;
+        const uint64_t own = r->learned ? (uint64_t)cnn::ltiles_st(r->n, r->n)
+                                        : ((n + fvk::TILE_X - 1) / fvk::TILE_X) * ((n + fvk::TILE_Y - 1) / fvk::TILE_Y);
+        const uint64_t own_cnn = r->learned ? (uint64_t)cnn::ltiles_cnn(r->n, r->n) : 0;
+        if (own > s->cfg.max_items || own_cnn > s->cfg.max_items)
+            return fail(FV_E_NOMEM, "request needs more than max_items = %llu tiles in one launch",
+                        (unsigned long long)s->cfg.max_items);
+    }
     if (req_bytes(r) > s->pool_bytes - s->heap_off)
         return fail(FV_E_NOMEM, "request needs %zu bytes, the pool holds %zu", req_bytes(r), s->pool_bytes - s->heap_off);
     auto q = std::make_unique<Req>();
@@ -362,10 +374,30 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
     char *P = s->pool;
     // ---- admission (FIFO, later requests may pass one that does not fit)
     std::vector<Req *> admitted, need_h0;
+    // tiles per launch of each kind (plain SWE, Euler, learned network pass,
+    // learned stage): a request is admitted only while its launches stay
+    // within max_items
+    uint64_t tiles[4] = {0, 0, 0, 0};
+    auto kind_tiles = [](const Req *q, uint64_t t[4]) {
+        const int n = q->r.n;
+        if (q->learned()) {
+            t[2] += (uint64_t)cnn::ltiles_cnn(n, n);
+            t[3] += (uint64_t)cnn::ltiles_st(n, n);
+        } else {
+            t[q->r.eqn == FV_EULER ? 1 : 0] +=
+                (uint64_t)((n + fvk::TILE_X - 1) / fvk::TILE_X) * ((n + fvk::TILE_Y - 1) / fvk::TILE_Y);
+        }
+    };
+    for (Req *q : s->active) kind_tiles(q, tiles);
     for (auto it = s->queue.begin(); it != s->queue.end();) {
         Req *q = *it;
         size_t off;
-        if (!s->free_slots.empty() && s->alloc(q->bytes, &off)) {
+        uint64_t after[4] = {tiles[0], tiles[1], tiles[2], tiles[3]};
+        kind_tiles(q, after);
+        bool fits = true;
+        for (int k = 0; k < 4; k++) fits = fits && after[k] <= s->cfg.max_items;
+        if (fits && !s->free_slots.empty() && s->alloc(q->bytes, &off)) {
+            for (int k = 0; k < 4; k++) tiles[k] = after[k];
             q->off = off;
             q->slot = s->free_slots.back();
             s->free_slots.pop_back();
@@ -390,15 +422,16 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
             sd.prec = 0;
             sd.eqn = FV_SWE;
             sd.nx = sd.ny = q->r.n;
-            sd.rdx = sd.rdy = q->r.n;
+            sd.rdx = sd.rdy = q->r.n / side(q->r);
             sd.g = q->r.g;
             e = fvk::launch_totals(sd, P + q->q_off, partials, fvk::TOTALS_MAX_BLOCKS, out, s->stream);
             double tot[4];
             if (e == hipSuccess) e = hipMemcpyAsync(tot, out, sizeof tot, hipMemcpyDeviceToHost, s->stream);
             if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
             if (e != hipSuccess) return hip_fail(e, "reference depth");
-            if (q->learned()) s->h_ltab[q->slot].h0 = (float)tot[0];
-            else s->h_tab[q->slot].h0 = tot[0];  // unit square: mean depth = mass
+            const double h0 = tot[0] / (side(q->r) * side(q->r));  // mean depth = mass / area
+            if (q->learned()) s->h_ltab[q->slot].h0 = (float)h0;
+            else s->h_tab[q->slot].h0 = h0;
         }
     }
     if (!admitted.empty()) {

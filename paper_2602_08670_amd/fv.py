@@ -73,7 +73,7 @@ class fv_request(ctypes.Structure):
                 ("bc", ctypes.c_int32), ("steps", ctypes.c_int64), ("cfl", ctypes.c_double), ("g", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("h_ref", ctypes.c_double), ("q0", ctypes.c_void_p),
                 ("bed", ctypes.c_void_p), ("learned", ctypes.c_int32), ("reserved1", ctypes.c_int32),
-                ("dt_fixed", ctypes.c_double)]
+                ("dt_fixed", ctypes.c_double), ("lx", ctypes.c_double)]
 
 
 class fv_request_info(ctypes.Structure):
@@ -407,7 +407,7 @@ def coarsen(fine, factor):
 
 
 def make_request(q0, steps, bed=None, bc=FV_BC_WALL, cfl=0.4, g=9.81, gamma=1.4, h_ref=0.0, learned=False,
-                 dt_fixed=0.0):
+                 dt_fixed=0.0, lx=0.0):
     """Request over host arrays (kept referenced by the returned tuple until
     fv_server_submit copied them).  learned=True: a learned solve (periodic,
     no bed) of `steps` steps of dt_fixed with the server's model."""
@@ -419,7 +419,7 @@ def make_request(q0, steps, bed=None, bc=FV_BC_WALL, cfl=0.4, g=9.81, gamma=1.4,
         bc = FV_BC_PERIODIC
     r = fv_request(ctypes.sizeof(fv_request), FV_SWE if nvar == 3 else FV_EULER, n, bc, int(steps), cfl, g, gamma,
                    h_ref, q0.ctypes.data, None if b is None else b.ctypes.data, 1 if learned else 0, 0,
-                   float(dt_fixed))
+                   float(dt_fixed), float(lx))
     return r, (q0, b)
 
 
