@@ -135,8 +135,8 @@ def cpu_baseline(n, target_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
-              "multi-GPU sharding is described in DESIGN.md, not implemented", file=sys.stderr)
+        print(f"bench.py: runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU domain "
+              "decomposition is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
 

@@ -54,6 +54,26 @@ template <typename T> struct StageArgs {
 template <typename T> using gmem = __attribute__((address_space(1))) T;
 template <typename T> __device__ __forceinline__ const gmem<T> *gload(const T *p) { return (const gmem<T> *)p; }
 template <typename T> __device__ __forceinline__ gmem<T> *gstore(T *p) { return (gmem<T> *)p; }
+// base[i] for a wave-uniform base and a byte offset that fits in 32 bits:
+// the address is then an SGPR pair plus a 32-bit VGPR offset, with no 64-bit
+// arithmetic per element.
+// The base goes through readfirstlane so that the compiler keeps it in
+// SGPRs instead of folding a uniform offset into every lane's address.
+template <typename T> __device__ __forceinline__ T *sbase(T *p)
+{
+    const unsigned long long u = (unsigned long long)p;
+    const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)u);
+    const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(u >> 32));
+    return (T *)(((unsigned long long)hi << 32) | lo);
+}
+template <typename T> __device__ __forceinline__ T ld_off(const T *base, unsigned i)
+{
+    return *(const gmem<T> *)((const char *)sbase(base) + i * (unsigned)sizeof(T));
+}
+template <typename T> __device__ __forceinline__ gmem<T> *st_off(T *base, unsigned i)
+{
+    return (gmem<T> *)((char *)sbase(base) + i * (unsigned)sizeof(T));
+}
 
 template <typename T> __device__ __forceinline__ T wave_max(T v)
 {
@@ -181,24 +201,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
             const int ly = ec / HX, lx = ec - ly * HX;
             const unsigned off = (unsigned)(ly * nx + lx);
 #pragma unroll
-            for (int v = 0; v < NV; v++) val[it][v] = gload(a.qs + v * plane + hb)[off];
-            if (BATHY) val[it][NV] = gload(a.bed + hb)[off];
+            for (int v = 0; v < NV; v++) val[it][v] = ld_off(a.qs + v * plane + hb, off);
+            if (BATHY) val[it][NV] = ld_off(a.bed + hb, off);
         }
     }
-    // q0 is needed only in the final combine: load it after the halo so its
-    // latency hides behind the face work
-    T q0r[RPW][NV];
-    if (a.a0 != T(0)) {
-#pragma unroll
-        for (int j = 0; j < RPW; j++) {
-            const int cy = r0 + j;
-            const bool in = x0 + lane < nx && y0 + cy < ny;
-            const unsigned off = in ? (unsigned)(cy * nx + lane) : 0u;
-#pragma unroll
-            for (int v = 0; v < NV; v++) q0r[j][v] = gload(a.q0 + v * plane + tbase)[off];
-        }
-    }
-
     if (inner) {
 #pragma unroll
         for (int it = 0; it < NIT; it++) {
@@ -297,6 +303,20 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
         if (BATHY) Ly[RPW - 1][2] += bed_centred(lowR[NV], lowR[NV + 1], up[NV], up[NV + 1], a.ph.g, a.rdy);
     }
 
+    // q0 is needed only in the final combine: issued here, its latency hides
+    // behind the x faces, and it holds no registers during the y faces
+    T q0r[RPW][NV];
+    if (a.a0 != T(0)) {
+#pragma unroll
+        for (int j = 0; j < RPW; j++) {
+            const int cy = r0 + j;
+            const bool in = x0 + lane < nx && y0 + cy < ny;
+            const unsigned off = in ? (unsigned)(cy * nx + lane) : 0u;
+#pragma unroll
+            for (int v = 0; v < NV; v++) q0r[j][v] = ld_off(a.q0 + v * plane + tbase, off);
+        }
+    }
+
     // 4. x faces, divergence, bed source, RK combine
     T lmax = T(0);
     bool bad = false;
@@ -326,7 +346,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
             for (int v = 0; v < NV; v++) {
                 T o = a.a1 * (st[v][2] + dt * Lv[v]);
                 if (a.a0 != T(0)) o = a.a0 * q0r[j][v] + o;
-                __builtin_nontemporal_store(o, gstore(a.out + v * plane + tbase) + off);
+                __builtin_nontemporal_store(o, st_off(a.out + v * plane + tbase, off));
                 qn[v] = o;
             }
             if (a.last) {
@@ -376,7 +396,9 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a, int tiles_x,
 // range contains w.  STAGE 1: S1 = q + dt L(q); STAGE 2: q = q/2 + (S1 + dt
 // L(S1))/2 (Heun).
 template <typename T, int EQN, bool BATHY, int STAGE>
-__global__ __launch_bounds__(256) void batch_stage_kernel(const BatchSolve *solves, const WorkItem *items,
+// Eight waves per SIMD (at most 64 VGPRs): every tile of a 1024^2 grid is then
+// resident at once instead of the last eighth running as a second round.
+__global__ __launch_bounds__(256, 8) void batch_stage_kernel(const BatchSolve *solves, const WorkItem *items,
                                                           const int *nitems, int ntiles, int one)
 {
     constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;

@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import sys
 import time
 
 import numpy as np
@@ -108,7 +109,7 @@ def run_server(stream, ics, arr, pool_bytes=24 << 30, steps_per_round=32, max_so
         a, qd = srv.round()
         rounds += 1
         if rounds % 200 == 0:
-            print(f"[serve] {nxt}/{len(stream)} submitted, {a} running, {qd} queued", flush=True)
+            print(f"[serve] {nxt}/{len(stream)} submitted, {a} running, {qd} queued", file=sys.stderr, flush=True)
         if a == 0 and qd == 0:
             if nxt >= len(stream):
                 break
@@ -167,7 +168,7 @@ def run_fifo(stream, ics, model=None, learned_dt=0.0):
         cells += n * n * steps
         lat.append(time.perf_counter() - t0)
         if (i + 1) % 200 == 0:
-            print(f"[fifo] {i + 1}/{len(stream)} done", flush=True)
+            print(f"[fifo] {i + 1}/{len(stream)} done", file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
     lat = np.array(lat)
     return {"wall_s": wall, "cell_updates": cells, "mcups": cells / wall / 1e6,
