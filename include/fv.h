@@ -317,16 +317,21 @@ fv_status fv_coarsen(const float *fine, int nvar, int nx, int ny, int factor, fl
  * all active solves of an equation type; for the learned solves each step
  * is six batched launches (the network pass of every learned solve in one
  * BF16 MFMA launch, the learned stage, both twice, then commit-or-redo and
- * redo).  Finished solves are copied back and their memory returns to the
- * pool.  The single-solve calls (fv_run, fv_learned_step) run the same
- * kernels as a batch of one, so a solve's result is bit-identical alone and
- * in any mix.
+ * redo).  A round's launches are recorded once, per kinds of work present
+ * and number of steps, into a hipGraph that every later round replays: the
+ * kernels read their tile counts from the device work-lists, and between
+ * replays the host rewrites those lists and sets each launch's grid to its
+ * list's tiles.
+ * Finished solves are copied back and their memory returns to the pool.
+ * The single-solve calls (fv_run, fv_learned_step) run the same kernels as a
+ * batch of one, so a solve's result is bit-identical alone and in any mix.
  * ------------------------------------------------------------------------ */
 typedef struct {
     uint32_t struct_size;    /* sizeof(fv_server_config) */
     int32_t max_solves;      /* solve slots */
     int32_t steps_per_round; /* K: steps between admission/retirement points */
-    int32_t reserved0;       /* must be 0 */
+    int32_t direct;          /* 0: replay captured graphs; 1: launch every kernel directly (same
+                                results; for comparison) */
     uint64_t max_items;      /* most tiles (workgroups) one batched launch may hold: admission keeps
                                 every launch within it; a request that alone needs more is rejected */
     const fv_model *model;   /* network of the learned requests (NULL: none accepted); its
@@ -361,6 +366,17 @@ typedef struct {
 
 typedef struct fv_server fv_server;
 
+typedef struct {
+    int64_t rounds;          /* rounds that launched work */
+    int64_t graph_replays;   /* of which replayed from a captured graph */
+    int64_t grid_updates;    /* launch grids reset before replays */
+    int32_t graphs_captured; /* distinct graphs captured so far */
+    int32_t pad;
+    double host_launch_s;    /* host seconds spent enqueueing rounds' launches (or graphs) */
+    double host_wait_s;      /* host seconds spent waiting for rounds' work to finish */
+    double host_capture_s;   /* host seconds spent capturing and instantiating graphs */
+} fv_server_stats;
+
 /* Pool bytes taken by the server's tables (solve table, work-lists). */
 size_t fv_server_pool_overhead(const fv_server_config *cfg);
 
@@ -368,7 +384,9 @@ size_t fv_server_pool_overhead(const fv_server_config *cfg);
 size_t fv_request_bytes(const fv_request *r);
 
 /* Create a server over a caller-owned device pool (256-byte aligned); its
- * work is enqueued on stream. */
+ * work is enqueued on stream.  A NULL stream (where graphs cannot be
+ * captured) makes the server create a non-blocking stream of its own, which
+ * fv_server_destroy destroys; every round ends synchronised either way. */
 fv_status fv_server_create(const fv_server_config *cfg, void *pool, size_t pool_bytes, void *stream,
                            fv_server **out);
 
@@ -380,6 +398,9 @@ fv_status fv_server_submit(fv_server *s, const fv_request *r, int64_t *id);
 fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued);
 
 fv_status fv_server_info(fv_server *s, int64_t id, fv_request_info *info);
+
+/* Round and graph counters. */
+fv_status fv_server_get_stats(fv_server *s, fv_server_stats *out);
 
 /* Copy a finished request's final state to dst (host, [nvar][n][n]);
  * FV_E_INADMISSIBLE if it failed (dst then holds the failing state). */

@@ -324,14 +324,17 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_kernel(const float *q, co
 }
 
 // Work-list form: workgroup w finds its solve by binary search over the
-// items' first network tile.  STAGE 1 reads q, STAGE 2 reads S1.
+// items' first network tile.  STAGE 1 reads q, STAGE 2 reads S1.  ntiles ==
+// 0: the tile count is read from the list header (nitems[1]; graph replay).
 template <int STAGE>
-__global__ __launch_bounds__(FNW * 64) void conv_fused_batch_kernel(const LSolve *tab, const LItem *items,
-                                                                    const int *nitems, int ntiles, int one,
-                                                                    const char *P, Packed pk, Norm nrm, Proj pr)
+__global__ __launch_bounds__(FNW * 64) void conv_fused_batch_kernel(const LSolve *__restrict__ tab,
+                                                                    const LItem *__restrict__ items,
+                                                                    const int *__restrict__ nitems, int ntiles,
+                                                                    int one, const char *P, Packed pk, Norm nrm,
+                                                                    Proj pr)
 {
     const int w = blockIdx.x;
-    if (w >= ntiles) return;
+    if (w >= (ntiles > 0 ? ntiles : nitems[1])) return;
     LItem it;
     if (one) {
         it = items[0];
@@ -498,6 +501,21 @@ hipError_t launch_forward_batch(int stage, const void *packed, const Norm &nrm, 
     else
         hipLaunchKernelGGL(conv_fused_batch_kernel<2>, dim3(ntiles), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
                            one, (const char *)packed, pk, nrm, pr);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_batch_list(int stage, const void *packed, const Norm &nrm, const Proj &pr,
+                                     const LSolve *tab, const LItem *items, const int *list, int wgs,
+                                     hipStream_t st)
+{
+    if (wgs <= 0) return hipErrorInvalidValue;
+    const Packed pk = packed_layout();
+    if (stage == 1)
+        hipLaunchKernelGGL(conv_fused_batch_kernel<1>, dim3(wgs), dim3(FNW * 64), 0, st, tab, items, list, 0, 0,
+                           (const char *)packed, pk, nrm, pr);
+    else
+        hipLaunchKernelGGL(conv_fused_batch_kernel<2>, dim3(wgs), dim3(FNW * 64), 0, st, tab, items, list, 0, 0,
+                           (const char *)packed, pk, nrm, pr);
     return hipGetLastError();
 }
 

@@ -71,9 +71,17 @@ struct WorkItem {
 #define FV_TILE_Y 8
 #endif
 constexpr int TILE_X = 64, TILE_Y = FV_TILE_Y;  // FP32 tile of the stage kernels
-// one != 0 declares that the list holds exactly one solve, solves[0].
+// One workgroup per tile: grid = the list's tiles.  one != 0 declares that
+// the list holds exactly one solve, solves[0].
 hipError_t launch_batch_stage(int eqn, int bathy, int stage, const BatchSolve *solves, const WorkItem *items,
                               const int *nitems, int grid, hipStream_t st, int one = 0);
+// The form recorded in graphs: wgs workgroups (a multiple of 8, set to
+// xcd_grid(tiles) before each replay), the tile count read from the list
+// header list = {items, tiles}.
+hipError_t launch_batch_stage_list(int eqn, int bathy, int stage, const BatchSolve *solves, const WorkItem *items,
+                                   const int *list, int wgs, hipStream_t st);
+// Grid of a tiled launch: the tiles padded to a multiple of the 8 XCDs.
+inline int xcd_grid(int ntiles) { return (ntiles + 7) & ~7; }
 
 // Reduce the CFL rate of q into ctl->rate[slot] and flag inadmissible cells.
 hipError_t launch_rate(const StageDesc &d, const void *q, Ctl *ctl, unsigned long long *rates, int slot,

@@ -82,13 +82,6 @@ template <typename T> __device__ __forceinline__ T wave_max(T v)
     return v;
 }
 
-// Largest CFL rate stored in slot k (max over its sub-slots), wave-uniform.
-static_assert(RATE_SUB == 64, "one sub-slot per lane");
-__device__ __forceinline__ double read_rate(unsigned long long *rates, int k)
-{
-    return wave_max(__longlong_as_double(*gload(rate_slot(rates, k, threadIdx.x & 63))));
-}
-
 __device__ __forceinline__ void push_rate(unsigned long long *rates, int k, double m, int block_linear)
 {
     atomicMax(rate_slot(rates, k, block_linear & (RATE_SUB - 1)), (unsigned long long)__double_as_longlong(m));
@@ -113,7 +106,37 @@ __device__ __forceinline__ float wave_max_nonneg(float v)
     const unsigned b = max((unsigned)__builtin_amdgcn_readlane((int)x, 47), (unsigned)__builtin_amdgcn_readlane((int)x, 63));
     return __uint_as_float(max(a, b));
 }
-__device__ __forceinline__ double wave_max_nonneg(double v) { return wave_max(v); }
+// The same for non-negative doubles, as 64-bit patterns in two halves (no
+// lane-index arithmetic, so nothing stays live across a workgroup's tiles).
+template <int CTRL> __device__ __forceinline__ unsigned long long dpp_u64(unsigned long long x)
+{
+    return (unsigned long long)dpp_u<CTRL>((unsigned)(x >> 32)) << 32 | dpp_u<CTRL>((unsigned)x);
+}
+__device__ __forceinline__ unsigned long long readlane_u64(unsigned long long x, int l)
+{
+    return (unsigned long long)(unsigned)__builtin_amdgcn_readlane((int)(x >> 32), l) << 32 |
+           (unsigned)__builtin_amdgcn_readlane((int)x, l);
+}
+__device__ __forceinline__ unsigned long long umax64(unsigned long long a, unsigned long long b) { return a > b ? a : b; }
+__device__ __forceinline__ double wave_max_nonneg(double v)
+{
+    unsigned long long x = (unsigned long long)__double_as_longlong(v);
+    x = umax64(x, dpp_u64<0x111>(x));
+    x = umax64(x, dpp_u64<0x112>(x));
+    x = umax64(x, dpp_u64<0x114>(x));
+    x = umax64(x, dpp_u64<0x118>(x));
+    const unsigned long long a = umax64(readlane_u64(x, 15), readlane_u64(x, 31));
+    const unsigned long long b = umax64(readlane_u64(x, 47), readlane_u64(x, 63));
+    return __longlong_as_double((long long)umax64(a, b));
+}
+
+// Largest CFL rate stored in slot k (max over its sub-slots, all >= 0),
+// wave-uniform.
+static_assert(RATE_SUB == 64, "one sub-slot per lane");
+__device__ __forceinline__ double read_rate(unsigned long long *rates, int k, int lane)
+{
+    return wave_max_nonneg(__longlong_as_double(*gload(rate_slot(rates, k, lane))));
+}
 
 // Block-wide max of v (threads 0..255) -> returned in thread 0.
 template <typename T> __device__ __forceinline__ T block_max256(T v, T *red)
@@ -155,8 +178,12 @@ __device__ __forceinline__ double from_right(double v, double edge)
 // owner inside the wave are the tile's right column (one lane per row, wave
 // 0, through LDS), the tile's top row (last wave) and the low face of each
 // wave's first row, which the wave below reads through LDS.
+// tid: threadIdx.x (a workgroup looping over tiles passes it opaquely, so
+// that per-lane index arithmetic is redone per tile instead of being held in
+// registers across the loop).
 template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int TX, int TY>
-__device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, const int y0, const int tile_linear)
+__device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, const int y0, const int tile_linear,
+                                           const int tid)
 {
     static_assert(TX == 64, "a tile row is one wave64");
     static_assert(TY % 4 == 0 && TY <= 64, "four waves, whole rows each");
@@ -173,14 +200,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
     // An earlier step failed: the state is frozen.  The flag is checked only
     // where something would be written, so its load is off the critical path.
     const bool frozen = gload(a.ctl)->bad != 0;
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6;
     const int r0 = wave * RPW;
     const int nx = a.nx, ny = a.ny;
     const size_t plane = (size_t)nx * ny;
     const size_t tbase = (size_t)y0 * nx + x0;
 
     if (wave == 1) {
-        const double d = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl / read_rate(a.rates, a.rate_in);
+        const double d = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl / read_rate(a.rates, a.rate_in, lane);
         if (lane == 0) s_dt = d;
     }
 
@@ -380,7 +407,6 @@ __device__ __forceinline__ int xcd_tile(int w, int grid)
 {
     return (grid & 7) ? w : (w & 7) * (grid >> 3) + (w >> 3);
 }
-inline int xcd_grid(int ntiles) { return (ntiles + 7) & ~7; }
 
 template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int TX, int TY>
 __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a, int tiles_x, int ntiles)
@@ -388,22 +414,18 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a, int tiles_x,
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
     const int ty = tile / tiles_x, tx = tile - ty * tiles_x;
-    stage_tile<T, EQN, BATHY, FLUX, RECON, TX, TY>(a, tx * TX, ty * TY, tile);
+    stage_tile<T, EQN, BATHY, FLUX, RECON, TX, TY>(a, tx * TX, ty * TY, tile, threadIdx.x);
 }
 
 // Batched stage over many solves: the step's list holds one item per solve
-// (sorted by tile_begin); workgroup w binary-searches the solve whose tile
-// range contains w.  STAGE 1: S1 = q + dt L(q); STAGE 2: q = q/2 + (S1 + dt
-// L(S1))/2 (Heun).
+// (sorted by tile_begin); the workgroup handling tile w binary-searches the
+// solve whose tile range contains w.  STAGE 1: S1 = q + dt L(q); STAGE 2:
+// q = q/2 + (S1 + dt L(S1))/2 (Heun).
 template <typename T, int EQN, bool BATHY, int STAGE>
-// Eight waves per SIMD (at most 64 VGPRs): every tile of a 1024^2 grid is then
-// resident at once instead of the last eighth running as a second round.
-__global__ __launch_bounds__(256, 8) void batch_stage_kernel(const BatchSolve *solves, const WorkItem *items,
-                                                          const int *nitems, int ntiles, int one)
+__device__ __forceinline__ void batch_tile(const BatchSolve *__restrict__ solves, const WorkItem *__restrict__ items,
+                                           const int *__restrict__ nitems, const int w, const int one, const int tid)
 {
     constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;
-    const int w = xcd_tile(blockIdx.x, gridDim.x);
-    if (w >= ntiles) return;
     // one != 0: the list is known to hold one solve, solves[0] (a single
     // solve stepping through this kernel); its descriptor and list entry are
     // then fetched together instead of one after the other
@@ -451,7 +473,24 @@ __global__ __launch_bounds__(256, 8) void batch_stage_kernel(const BatchSolve *s
     a.rate_clear = STAGE == 1 ? -1 : it.rc;
     a.last = STAGE == 2;
     const int ty = tile / it.tiles_x, tx = tile - ty * it.tiles_x;
-    stage_tile<T, EQN, BATHY, HLLE, MINMOD, TX, TY>(a, tx * TX, ty * TY, tile);
+    stage_tile<T, EQN, BATHY, HLLE, MINMOD, TX, TY>(a, tx * TX, ty * TY, tile, tid);
+}
+
+// ntiles > 0: the list holds ntiles tiles.  ntiles == 0: the tile count is
+// read from the list header (nitems[1]), so that a launch recorded in a graph
+// serves whatever list is uploaded before each replay.  The grid is
+// xcd_grid(tiles).  Eight waves per SIMD (at most 64 VGPRs): every tile of a
+// 1024^2 grid is then resident at once instead of the last eighth running as
+// a second round.
+template <typename T, int EQN, bool BATHY, int STAGE>
+__global__ __launch_bounds__(256, 8) void batch_stage_kernel(const BatchSolve *__restrict__ solves,
+                                                          const WorkItem *__restrict__ items,
+                                                          const int *__restrict__ nitems, int ntiles, int one)
+{
+    const int total = ntiles > 0 ? ntiles : nitems[1];
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    if (w >= total) return;
+    batch_tile<T, EQN, BATHY, STAGE>(solves, items, nitems, w, one, threadIdx.x);
 }
 
 // ------------------------------------------------------------ CFL rate of q
@@ -664,21 +703,35 @@ static hipError_t rate_t(const StageDesc &d, const void *q, Ctl *ctl, unsigned l
     return hipGetLastError();
 }
 
+template <int STAGE>
+static void batch_stage_go(int eqn, int bathy, dim3 g, const BatchSolve *solves, const WorkItem *items,
+                           const int *nitems, int ntiles, int one, hipStream_t st)
+{
+    const dim3 b(256);
+    if (eqn == EULER)
+        hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, STAGE>), g, b, 0, st, solves, items, nitems, ntiles, one);
+    else if (bathy)
+        hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, STAGE>), g, b, 0, st, solves, items, nitems, ntiles, one);
+    else
+        hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, STAGE>), g, b, 0, st, solves, items, nitems, ntiles, one);
+}
+
 hipError_t launch_batch_stage(int eqn, int bathy, int stage, const BatchSolve *solves, const WorkItem *items,
                               const int *nitems, int grid, hipStream_t st, int one)
 {
     if (grid <= 0) return hipSuccess;
-    dim3 g(xcd_grid(grid)), b(256);
-    if (eqn == EULER) {
-        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, 1>), g, b, 0, st, solves, items, nitems, grid, one);
-        else hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, 2>), g, b, 0, st, solves, items, nitems, grid, one);
-    } else if (bathy) {
-        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, 1>), g, b, 0, st, solves, items, nitems, grid, one);
-        else hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, 2>), g, b, 0, st, solves, items, nitems, grid, one);
-    } else {
-        if (stage == 1) hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, 1>), g, b, 0, st, solves, items, nitems, grid, one);
-        else hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, 2>), g, b, 0, st, solves, items, nitems, grid, one);
-    }
+    const dim3 g(xcd_grid(grid));
+    if (stage == 1) batch_stage_go<1>(eqn, bathy, g, solves, items, nitems, grid, one, st);
+    else batch_stage_go<2>(eqn, bathy, g, solves, items, nitems, grid, one, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_stage_list(int eqn, int bathy, int stage, const BatchSolve *solves, const WorkItem *items,
+                                   const int *list, int wgs, hipStream_t st)
+{
+    if (wgs <= 0 || (wgs & 7)) return hipErrorInvalidValue;
+    if (stage == 1) batch_stage_go<1>(eqn, bathy, dim3(wgs), solves, items, list, 0, 0, st);
+    else batch_stage_go<2>(eqn, bathy, dim3(wgs), solves, items, list, 0, 0, st);
     return hipGetLastError();
 }
 

@@ -248,12 +248,16 @@ __global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
 // Work-list form over a table of solves of any size (serving, and single
 // solves as a batch of one): workgroup w finds its solve by binary search
 // over the items' first stage tile.  MODE 0 with STAGE 1 or 2, MODE 2, 3.
+// ntiles == 0: the tile count is read from the list header (nitems[2]; graph
+// replay).
 template <int MODE, int STAGE>
-__global__ __launch_bounds__(256) void learned_batch_kernel(const LSolve *tab, const LItem *items, const int *nitems,
-                                                            int ntiles, int one, Proj pr)
+__global__ __launch_bounds__(256) void learned_batch_kernel(const LSolve *__restrict__ tab,
+                                                            const LItem *__restrict__ items,
+                                                            const int *__restrict__ nitems, int ntiles, int one,
+                                                            Proj pr)
 {
     const int w = blockIdx.x;
-    if (w >= ntiles) return;
+    if (w >= (ntiles > 0 ? ntiles : nitems[2])) return;
     LItem it;
     if (one) {
         it = items[0];
@@ -304,17 +308,30 @@ __global__ __launch_bounds__(256) void learned_batch_kernel(const LSolve *tab, c
     learned_tile<MODE, fvk::HLLE, true>(a, 0, tx * LTILE_X, ty * LTILE_Y, tile == 0);
 }
 
-hipError_t launch_learned_batch(int mode, int stage, const LSolve *tab, const LItem *items, const int *nitems,
-                                int ntiles, const Proj &pr, hipStream_t st, int one)
+static hipError_t learned_batch_go(int mode, int stage, dim3 g, const LSolve *tab, const LItem *items,
+                                   const int *nitems, int ntiles, int one, const Proj &pr, hipStream_t st)
 {
-    if (ntiles <= 0) return hipSuccess;
-    dim3 g(ntiles), b(256);
+    const dim3 b(256);
     if (mode == 0 && stage == 1) hipLaunchKernelGGL((learned_batch_kernel<0, 1>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
     else if (mode == 0 && stage == 2) hipLaunchKernelGGL((learned_batch_kernel<0, 2>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
     else if (mode == 2) hipLaunchKernelGGL((learned_batch_kernel<2, 0>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
     else if (mode == 3) hipLaunchKernelGGL((learned_batch_kernel<3, 0>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
     else return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+hipError_t launch_learned_batch(int mode, int stage, const LSolve *tab, const LItem *items, const int *nitems,
+                                int ntiles, const Proj &pr, hipStream_t st, int one)
+{
+    if (ntiles <= 0) return hipSuccess;
+    return learned_batch_go(mode, stage, dim3(ntiles), tab, items, nitems, ntiles, one, pr, st);
+}
+
+hipError_t launch_learned_batch_list(int mode, int stage, const LSolve *tab, const LItem *items, const int *list,
+                                     int wgs, const Proj &pr, hipStream_t st)
+{
+    if (wgs <= 0) return hipErrorInvalidValue;
+    return learned_batch_go(mode, stage, dim3(wgs), tab, items, list, 0, 0, pr, st);
 }
 
 // q[b] <- S2[b] for the solves whose learned step was admissible.

@@ -72,6 +72,20 @@ size_t req_bytes(const fv_request *r)
 
 }  // namespace
 
+// A captured round: its kernel nodes in launch order, each with the list
+// whose tile count sets its grid before a replay (kind 0: plain stage list
+// [step][type], 1: network pass of a step's learned list, 2: learned stage).
+struct GraphNode {
+    hipGraphNode_t node;
+    hipKernelNodeParams p;
+    int kind, idx;
+};
+struct RoundGraph {
+    hipGraph_t g = nullptr;  // kept alive: the nodes are updated through it
+    hipGraphExec_t x = nullptr;
+    std::vector<GraphNode> nodes;
+};
+
 struct fv_server {
     fv_server_config cfg;
     char *pool;
@@ -93,6 +107,12 @@ struct fv_server {
     cnn::LItem *h_litems = nullptr;    // pinned
     int *h_lnitems = nullptr;
     std::vector<cnn::LSolve> h_ltab;
+    hipStream_t own_stream = nullptr;  // created when the caller passes the null stream
+    // captured rounds, keyed by the kinds of work present | steps << 3
+    std::map<int, RoundGraph> graphs;
+    int64_t rounds = 0, replays = 0, grid_updates = 0;
+    double launch_s = 0, wait_s = 0;  // host time enqueueing rounds' work, and waiting for it
+    double capture_s = 0;             // host time capturing and instantiating graphs
 
     double now() const
     {
@@ -132,7 +152,22 @@ struct fv_server {
 
 namespace {
 
-// one list per step and equation type, one item per active solve
+void free_host(fv_server *s)
+{
+    if (s->h_items) (void)hipHostFree(s->h_items);
+    if (s->h_nitems) (void)hipHostFree(s->h_nitems);
+    if (s->h_litems) (void)hipHostFree(s->h_litems);
+    if (s->h_lnitems) (void)hipHostFree(s->h_lnitems);
+    s->h_items = nullptr;
+    s->h_nitems = nullptr;
+    s->h_litems = nullptr;
+    s->h_lnitems = nullptr;
+}
+
+// one list per step and equation type, one item per active solve; list
+// headers on the device: plain {items, tiles}, learned {items, network
+// tiles, stage tiles, 0}
+constexpr int HDR = 2, LHDR = 4;
 size_t items_capacity(const fv_server_config *c) { return (size_t)c->steps_per_round * 2 * c->max_solves; }
 
 fv_status validate(const fv_server_config *c)
@@ -141,7 +176,7 @@ fv_status validate(const fv_server_config *c)
     if (c->max_solves < 1 || c->steps_per_round < 1 || c->max_items < 1)
         return fail(FV_E_INVALID, "max_solves, steps_per_round and max_items must be >= 1");
     if (c->max_items > (uint64_t)1 << 31) return fail(FV_E_INVALID, "max_items above 2^31");
-    if (c->reserved0 != 0) return fail(FV_E_INVALID, "reserved0 must be 0");
+    if (c->direct != 0 && c->direct != 1) return fail(FV_E_INVALID, "direct must be 0 or 1");
     return FV_OK;
 }
 
@@ -152,11 +187,11 @@ size_t overhead(const fv_server_config *c)
 {
     size_t o = align256(sizeof(fvk::BatchSolve) * c->max_solves);
     o += align256(items_capacity(c) * sizeof(fvk::WorkItem));
-    o += align256((size_t)c->steps_per_round * 2 * sizeof(int));
+    o += align256((size_t)c->steps_per_round * 2 * HDR * sizeof(int));
     o += align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * 8 + 256);
     o += align256(sizeof(cnn::LSolve) * c->max_solves);
     o += align256(litems_capacity(c) * sizeof(cnn::LItem));
-    o += align256((size_t)c->steps_per_round * sizeof(int));
+    o += align256((size_t)c->steps_per_round * LHDR * sizeof(int));
     return o;
 }
 
@@ -284,6 +319,119 @@ fv_status admit(fv_server *s, Req *q, std::vector<Req *> &need_h0)
     return FV_OK;
 }
 
+// Launches of steps 0..nsteps-1 of a round over the uploaded lists, kinds
+// of work in mask (1 SWE, 2 Euler, 4 learned).  rec == NULL: direct launches
+// of one workgroup per tile with the given per-list tile counts, empty lists
+// skipped.  rec != NULL (graph capture): every launch of the mask, the tile
+// counts read from the list headers, each node recorded in rec; its grid is
+// a placeholder set before each replay.
+hipError_t enqueue_steps(fv_server *s, int mask, int nsteps, const int *grids, const int *lgrid_cnn,
+                         const int *lgrid_st, std::vector<GraphNode> *rec)
+{
+    char *P = s->pool;
+    const size_t ncap = (size_t)s->cfg.max_solves;
+    const fvk::BatchSolve *tab = (const fvk::BatchSolve *)(P + s->tab_off);
+    const fvk::WorkItem *d_items = (const fvk::WorkItem *)(P + s->items_off);
+    const int *d_nitems = (const int *)(P + s->nitems_off);
+    const cnn::LSolve *ltab = (const cnn::LSolve *)(P + s->ltab_off);
+    const cnn::LItem *d_litems = (const cnn::LItem *)(P + s->litems_off);
+    const int *d_lnitems = (const int *)(P + s->lnitems_off);
+    const fv_model *m = s->cfg.model;
+    auto record = [&](int kind, int idx) -> hipError_t {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        const hipGraphNode_t *deps = nullptr;
+        size_t nd = 0;
+        hipError_t e = hipStreamGetCaptureInfo_v2(s->stream, &cs, nullptr, nullptr, &deps, &nd);
+        if (e != hipSuccess) return e;
+        if (cs != hipStreamCaptureStatusActive || nd != 1 || !deps) return hipErrorStreamCaptureInvalidated;
+        rec->push_back(GraphNode{deps[0], hipKernelNodeParams{}, kind, idx});
+        return hipSuccess;
+    };
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < nsteps && e == hipSuccess; k++) {
+        for (int stage = 1; stage <= 2 && e == hipSuccess; stage++)
+            for (int type = 0; type < 2 && e == hipSuccess; type++) {
+                if (!(mask >> type & 1)) continue;
+                const size_t li = (size_t)k * 2 + type;
+                const int eqn = type == 1 ? FV_EULER : FV_SWE;
+                const fvk::WorkItem *it = d_items + li * ncap;
+                const int *hdr = d_nitems + li * HDR;
+                if (!rec) {
+                    e = fvk::launch_batch_stage(eqn, type == 0, stage, tab, it, hdr, grids[li], s->stream);
+                } else {
+                    e = fvk::launch_batch_stage_list(eqn, type == 0, stage, tab, it, hdr, 8, s->stream);
+                    if (e == hipSuccess) e = record(0, (int)li);
+                }
+            }
+        if (!(mask & 4) || e != hipSuccess || (!rec && !lgrid_st[k])) continue;
+        // learned solves: every network pass of the step in one launch
+        const cnn::LItem *it = d_litems + (size_t)k * ncap;
+        const int *hdr = d_lnitems + (size_t)k * LHDR;
+        const int mode[6] = {-1, 0, -1, 0, 2, 3}, stg[6] = {1, 1, 2, 2, 0, 0};
+        for (int j = 0; j < 6 && e == hipSuccess; j++) {
+            if (!rec) {
+                e = mode[j] < 0 ? cnn::launch_forward_batch(stg[j], m->packed, m->nrm, m->pr, ltab, it, hdr,
+                                                            lgrid_cnn[k], s->stream)
+                                : cnn::launch_learned_batch(mode[j], stg[j], ltab, it, hdr, lgrid_st[k], m->pr,
+                                                            s->stream);
+            } else {
+                e = mode[j] < 0 ? cnn::launch_forward_batch_list(stg[j], m->packed, m->nrm, m->pr, ltab, it, hdr, 1,
+                                                                 s->stream)
+                                : cnn::launch_learned_batch_list(mode[j], stg[j], ltab, it, hdr, 1, m->pr, s->stream);
+                if (e == hipSuccess) e = record(mode[j] < 0 ? 1 : 2, k);
+            }
+        }
+    }
+    return e;
+}
+
+// The captured graph of a round's launches for (mask, nsteps), captured and
+// instantiated on first use.
+fv_status round_graph(fv_server *s, int mask, int nsteps, RoundGraph **out)
+{
+    const int key = mask | nsteps << 3;
+    auto f = s->graphs.find(key);
+    if (f != s->graphs.end()) {
+        *out = &f->second;
+        return FV_OK;
+    }
+    RoundGraph rg;
+    const double t0 = s->now();
+    hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(e, "graph capture");
+    const hipError_t le = enqueue_steps(s, mask, nsteps, nullptr, nullptr, nullptr, &rg.nodes);
+    e = hipStreamEndCapture(s->stream, &rg.g);
+    if (e == hipSuccess) e = le;
+    for (size_t i = 0; i < rg.nodes.size() && e == hipSuccess; i++)
+        e = hipGraphKernelNodeGetParams(rg.nodes[i].node, &rg.nodes[i].p);
+    if (e == hipSuccess) e = hipGraphInstantiate(&rg.x, rg.g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        if (rg.g) (void)hipGraphDestroy(rg.g);
+        return hip_fail(e, "graph capture");
+    }
+    *out = &(s->graphs[key] = rg);
+    s->capture_s += s->now() - t0;
+    return FV_OK;
+}
+
+// Before a replay: every node's grid from its list's tile count (at least
+// one workgroup: an empty list's launch reads 0 tiles and does nothing).
+hipError_t set_grids(fv_server *s, RoundGraph *rg, const int *grids, const int *lgrid_cnn, const int *lgrid_st)
+{
+    for (GraphNode &n : rg->nodes) {
+        int want;
+        if (n.kind == 0) want = grids[n.idx] ? fvk::xcd_grid(grids[n.idx]) : 8;
+        else if (n.kind == 1) want = lgrid_cnn[n.idx] ? lgrid_cnn[n.idx] : 1;
+        else want = lgrid_st[n.idx] ? lgrid_st[n.idx] : 1;
+        if ((int)n.p.gridDim.x == want) continue;
+        n.p.gridDim.x = (unsigned)want;
+        const hipError_t e = hipGraphExecKernelNodeSetParams(rg->x, n.node, &n.p);
+        if (e != hipSuccess) return e;
+        s->grid_updates++;
+    }
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" {
@@ -311,7 +459,7 @@ fv_status fv_server_create(const fv_server_config *cfg, void *pool, size_t pool_
     s->tab_off = 0;
     s->items_off = align256(sizeof(fvk::BatchSolve) * cfg->max_solves);
     s->nitems_off = s->items_off + align256(items_capacity(cfg) * sizeof(fvk::WorkItem));
-    s->scratch_off = s->nitems_off + align256((size_t)cfg->steps_per_round * 2 * sizeof(int));
+    s->scratch_off = s->nitems_off + align256((size_t)cfg->steps_per_round * 2 * HDR * sizeof(int));
     s->ltab_off = s->scratch_off + align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * 8 + 256);
     s->litems_off = s->ltab_off + align256(sizeof(cnn::LSolve) * cfg->max_solves);
     s->lnitems_off = s->litems_off + align256(litems_capacity(cfg) * sizeof(cnn::LItem));
@@ -321,14 +469,23 @@ fv_status fv_server_create(const fv_server_config *cfg, void *pool, size_t pool_
     s->h_ltab.assign(cfg->max_solves, cnn::LSolve{});
     for (int i = cfg->max_solves - 1; i >= 0; i--) s->free_slots.push_back(i);
     hipError_t e = hipHostMalloc((void **)&s->h_items, items_capacity(cfg) * sizeof(fvk::WorkItem), 0);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_nitems, (size_t)cfg->steps_per_round * 2 * sizeof(int), 0);
+    if (e == hipSuccess)
+        e = hipHostMalloc((void **)&s->h_nitems, (size_t)cfg->steps_per_round * 2 * HDR * sizeof(int), 0);
     if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_litems, litems_capacity(cfg) * sizeof(cnn::LItem), 0);
-    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_lnitems, (size_t)cfg->steps_per_round * sizeof(int), 0);
+    if (e == hipSuccess) e = hipHostMalloc((void **)&s->h_lnitems, (size_t)cfg->steps_per_round * LHDR * sizeof(int), 0);
     if (e != hipSuccess) {
-        if (s->h_items) (void)hipHostFree(s->h_items);
-        if (s->h_nitems) (void)hipHostFree(s->h_nitems);
-        if (s->h_litems) (void)hipHostFree(s->h_litems);
+        free_host(s.get());
         return hip_fail(e, "pinned work-list buffers");
+    }
+    if (!stream) {
+        // graphs cannot be captured on the null stream: the server then
+        // runs on a stream of its own (default priority)
+        e = hipStreamCreateWithFlags(&s->own_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            free_host(s.get());
+            return hip_fail(e, "server stream");
+        }
+        s->stream = s->own_stream;
     }
     *out = s.release();
     return FV_OK;
@@ -483,7 +640,16 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
             counts[li]++;
             grids[li] += q->tiles;
         }
-    for (size_t i = 0; i < counts.size(); i++) s->h_nitems[i] = counts[i];
+    int mask = 0, nsteps = 0;  // kinds of work present (1 SWE, 2 Euler, 4 learned), last non-empty step + 1
+    for (int k = 0; k < K; k++) {
+        const int m = (counts[(size_t)k * 2] ? 1 : 0) | (counts[(size_t)k * 2 + 1] ? 2 : 0) | (lcounts[k] ? 4 : 0);
+        if (m) nsteps = k + 1;
+        mask |= m;
+    }
+    for (size_t li = 0; li < counts.size(); li++) {
+        s->h_nitems[li * HDR] = counts[li];
+        s->h_nitems[li * HDR + 1] = grids[li];
+    }
     fvk::WorkItem *d_items = (fvk::WorkItem *)(P + s->items_off);
     int *d_nitems = (int *)(P + s->nitems_off);
     size_t used = 0;  // the lists are uploaded up to the last non-empty one
@@ -491,42 +657,48 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
         if (counts[li]) used = li * ncap + counts[li];
     e = hipMemcpyAsync(d_items, s->h_items, used * sizeof(fvk::WorkItem), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(d_nitems, s->h_nitems, (size_t)K * 2 * sizeof(int), hipMemcpyHostToDevice, s->stream);
+        e = hipMemcpyAsync(d_nitems, s->h_nitems, (size_t)K * 2 * HDR * sizeof(int), hipMemcpyHostToDevice,
+                           s->stream);
     // learned lists
     cnn::LItem *d_litems = (cnn::LItem *)(P + s->litems_off);
     int *d_lnitems = (int *)(P + s->lnitems_off);
     size_t lused = 0;
     for (int k = 0; k < K; k++) {
-        s->h_lnitems[k] = lcounts[k];
+        s->h_lnitems[k * LHDR] = lcounts[k];
+        s->h_lnitems[k * LHDR + 1] = lgrid_cnn[k];
+        s->h_lnitems[k * LHDR + 2] = lgrid_st[k];
+        s->h_lnitems[k * LHDR + 3] = 0;
         if (lcounts[k]) lused = (size_t)k * ncap + lcounts[k];
     }
     if (e == hipSuccess && lused)
         e = hipMemcpyAsync(d_litems, s->h_litems, lused * sizeof(cnn::LItem), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess && lused)
-        e = hipMemcpyAsync(d_lnitems, s->h_lnitems, (size_t)K * sizeof(int), hipMemcpyHostToDevice, s->stream);
-    const fvk::BatchSolve *tab = (const fvk::BatchSolve *)(P + s->tab_off);
-    const cnn::LSolve *ltab = (const cnn::LSolve *)(P + s->ltab_off);
-    const fv_model *m = s->cfg.model;
-    for (int k = 0; k < K && e == hipSuccess; k++) {
-        for (int stage = 1; stage <= 2 && e == hipSuccess; stage++)
-            for (int type = 0; type < 2 && e == hipSuccess; type++) {
-                size_t li = (size_t)k * 2 + type;
-                e = fvk::launch_batch_stage(type == 1 ? FV_EULER : FV_SWE, type == 0, stage, tab, d_items + li * ncap,
-                                            d_nitems + li, grids[li], s->stream);
-            }
-        if (!lcounts[k] || e != hipSuccess) continue;
-        // learned solves: every network pass of the step in one launch
-        const cnn::LItem *it = d_litems + (size_t)k * ncap;
-        const int *nit = d_lnitems + k;
-        e = cnn::launch_forward_batch(1, m->packed, m->nrm, m->pr, ltab, it, nit, lgrid_cnn[k], s->stream);
-        if (e == hipSuccess) e = cnn::launch_learned_batch(0, 1, ltab, it, nit, lgrid_st[k], m->pr, s->stream);
-        if (e == hipSuccess) e = cnn::launch_forward_batch(2, m->packed, m->nrm, m->pr, ltab, it, nit, lgrid_cnn[k], s->stream);
-        if (e == hipSuccess) e = cnn::launch_learned_batch(0, 2, ltab, it, nit, lgrid_st[k], m->pr, s->stream);
-        if (e == hipSuccess) e = cnn::launch_learned_batch(2, 0, ltab, it, nit, lgrid_st[k], m->pr, s->stream);
-        if (e == hipSuccess) e = cnn::launch_learned_batch(3, 0, ltab, it, nit, lgrid_st[k], m->pr, s->stream);
+        e = hipMemcpyAsync(d_lnitems, s->h_lnitems, (size_t)K * LHDR * sizeof(int), hipMemcpyHostToDevice,
+                           s->stream);
+    if (e != hipSuccess) return hip_fail(e, "work-list upload");
+    if (nsteps) s->rounds++;
+    const double tl0 = s->now();
+    if (s->cfg.direct) {
+        e = enqueue_steps(s, mask, nsteps, grids.data(), lgrid_cnn.data(), lgrid_st.data(), nullptr);
+    } else if (nsteps) {
+        // the round's launches are one captured graph per (kinds present,
+        // steps rounded up to a power of two); between replays only the
+        // work-lists uploaded above and the launch grids change
+        int ng = 1;
+        while (ng < nsteps) ng <<= 1;
+        if (ng > K) ng = K;
+        RoundGraph *rg = nullptr;
+        fv_status rc = round_graph(s, mask, ng, &rg);
+        if (rc != FV_OK) return rc;
+        e = set_grids(s, rg, grids.data(), lgrid_cnn.data(), lgrid_st.data());
+        if (e == hipSuccess) e = hipGraphLaunch(rg->x, s->stream);
+        s->replays++;
     }
+    const double tl1 = s->now();
+    s->launch_s += tl1 - tl0;
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_fail(e, "round");
+    s->wait_s += s->now() - tl1;
     // ---- retire finished solves
     double tnow = s->now();
     for (auto it = s->active.begin(); it != s->active.end();) {
@@ -559,6 +731,20 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
     }
     if (n_active) *n_active = (int32_t)s->active.size();
     if (n_queued) *n_queued = (int32_t)s->queue.size();
+    return FV_OK;
+}
+
+fv_status fv_server_get_stats(fv_server *s, fv_server_stats *out)
+{
+    if (!s || !out) return fail(FV_E_INVALID, "NULL argument");
+    *out = fv_server_stats{};
+    out->rounds = s->rounds;
+    out->graph_replays = s->replays;
+    out->grid_updates = s->grid_updates;
+    out->graphs_captured = (int32_t)s->graphs.size();
+    out->host_launch_s = s->launch_s;
+    out->host_wait_s = s->wait_s;
+    out->host_capture_s = s->capture_s;
     return FV_OK;
 }
 
@@ -604,10 +790,12 @@ void fv_server_destroy(fv_server *s)
 {
     if (!s) return;
     (void)hipStreamSynchronize(s->stream);
-    if (s->h_items) (void)hipHostFree(s->h_items);
-    if (s->h_nitems) (void)hipHostFree(s->h_nitems);
-    if (s->h_litems) (void)hipHostFree(s->h_litems);
-    if (s->h_lnitems) (void)hipHostFree(s->h_lnitems);
+    for (auto &g : s->graphs) {
+        if (g.second.x) (void)hipGraphExecDestroy(g.second.x);
+        if (g.second.g) (void)hipGraphDestroy(g.second.g);
+    }
+    if (s->own_stream) (void)hipStreamDestroy(s->own_stream);
+    free_host(s);
     delete s;
 }
 

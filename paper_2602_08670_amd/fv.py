@@ -64,7 +64,7 @@ class fv_train_config(ctypes.Structure):
 
 class fv_server_config(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_solves", ctypes.c_int32),
-                ("steps_per_round", ctypes.c_int32), ("reserved0", ctypes.c_int32), ("max_items", ctypes.c_uint64),
+                ("steps_per_round", ctypes.c_int32), ("direct", ctypes.c_int32), ("max_items", ctypes.c_uint64),
                 ("model", ctypes.c_void_p)]
 
 
@@ -80,6 +80,12 @@ class fv_request_info(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("pad", ctypes.c_int32), ("steps_done", ctypes.c_int64),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
                 ("sim_time", ctypes.c_double), ("fallback_faces", ctypes.c_int64), ("redone_steps", ctypes.c_int64)]
+
+
+class fv_server_stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_int64), ("graph_replays", ctypes.c_int64), ("grid_updates", ctypes.c_int64),
+                ("graphs_captured", ctypes.c_int32), ("pad", ctypes.c_int32), ("host_launch_s", ctypes.c_double),
+                ("host_wait_s", ctypes.c_double), ("host_capture_s", ctypes.c_double)]
 
 
 def make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0), order=1, hidden=32) -> fv_model_desc:
@@ -146,6 +152,7 @@ def _load():
         "fv_server_submit": ([vp, ctypes.POINTER(fv_request), ctypes.POINTER(i64)], st),
         "fv_server_round": ([vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)], st),
         "fv_server_info": ([vp, i64, ctypes.POINTER(fv_request_info)], st),
+        "fv_server_get_stats": ([vp, ctypes.POINTER(fv_server_stats)], st),
         "fv_server_result": ([vp, i64, vp], st),
         "fv_server_release": ([vp, i64], st),
         "fv_server_destroy": ([vp], None),
@@ -427,15 +434,19 @@ class Server:
     """Continuous-batching server over a torch-allocated device pool."""
 
     def __init__(self, pool_bytes: int, max_solves: int = 1024, steps_per_round: int = 24,
-                 max_items: int = 1 << 18, device="cuda", stream=None, model=None):
+                 max_items: int = 1 << 18, device="cuda", stream=None, model=None, direct=False):
+        """direct: launch every kernel of a round directly instead of replaying
+        the round's captured graph (same results)."""
         import torch
 
         self.model = model  # kept alive while the server runs
         if model is not None:
             torch.cuda.synchronize()  # the model's packed weights are ready
-        self.cfg = fv_server_config(ctypes.sizeof(fv_server_config), max_solves, steps_per_round, 0, max_items,
-                                    None if model is None else model.h)
-        self.pool = torch.empty(pool_bytes, dtype=torch.uint8, device=device)
+        self.cfg = fv_server_config(ctypes.sizeof(fv_server_config), max_solves, steps_per_round,
+                                    1 if direct else 0, max_items, None if model is None else model.h)
+        # zero-filled: the pool's pages are mapped here rather than by the
+        # first rounds that reach them
+        self.pool = torch.zeros(pool_bytes, dtype=torch.uint8, device=device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(torch.device(device))
         h = ctypes.c_void_p()
         _check(lib.fv_server_create(ctypes.byref(self.cfg), self.pool.data_ptr(), pool_bytes,
@@ -462,6 +473,11 @@ class Server:
         inf = fv_request_info()
         _check(lib.fv_server_info(self.h, rid, ctypes.byref(inf)))
         return inf
+
+    def stats(self) -> fv_server_stats:
+        out = fv_server_stats()
+        _check(lib.fv_server_get_stats(self.h, ctypes.byref(out)))
+        return out
 
     def result(self, rid: int, shape):
         out = np.empty(shape, dtype=np.float32)

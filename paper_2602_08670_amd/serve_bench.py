@@ -86,13 +86,14 @@ def arrivals(n_req: int, rate: float, seed: int):
 
 
 def run_server(stream, ics, arr, pool_bytes=24 << 30, steps_per_round=32, max_solves=1024, model=None,
-               learned_dt=0.0):
-    """Drive the server with the given arrival times (seconds after start)."""
+               learned_dt=0.0, direct=False):
+    """Drive the server with the given arrival times (seconds after start).
+    direct: launch every kernel directly instead of replaying captured graphs."""
     import torch
 
     t_create = time.perf_counter()
     srv = fv.Server(pool_bytes, max_solves=max_solves, steps_per_round=steps_per_round, max_items=1 << 22,
-                    model=model)
+                    model=model, direct=direct)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     clock_offset = t0 - t_create  # server timestamps count from its creation
@@ -125,6 +126,11 @@ def run_server(stream, ics, arr, pool_bytes=24 << 30, steps_per_round=32, max_so
         done.append(inf.t_done - clock_offset)
         fallback += inf.fallback_faces
         redone += inf.redone_steps
+    st = srv.stats()
+    run_server.last_stats = {"rounds": st.rounds, "graph_replays": st.graph_replays,
+                             "graphs_captured": st.graphs_captured, "grid_updates": st.grid_updates,
+                             "host_launch_s": st.host_launch_s, "host_wait_s": st.host_wait_s,
+                             "host_capture_s": st.host_capture_s}
     srv.close()
     return wall, cells, np.array(done), ids, (fallback, redone)
 
@@ -144,6 +150,7 @@ def run_server_latency(stream, ics, arr, **kw):
     if "learned" in kinds:
         res["learned_fallback_faces"] = int(fb)
         res["learned_redone_steps"] = int(red)
+    res["server"] = dict(run_server.last_stats)
     return res
 
 
@@ -195,6 +202,12 @@ def main():
     ap.add_argument("--mixed", action="store_true", help="learned + plain shallow-water stream")
     ap.add_argument("--pool-gb", type=float, default=24.0)
     ap.add_argument("--no-fifo", action="store_true")
+    ap.add_argument("--compare-direct", action="store_true",
+                    help="also run the saturated stream with direct launches instead of graph replay")
+    ap.add_argument("--direct-last", action="store_true", help="with --compare-direct: run the direct pass "
+                    "after the graph pass")
+    ap.add_argument("--direct", action="store_true", help="launch every kernel directly instead of replaying "
+                    "captured graphs")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     model, ldt = (quick_model() if a.mixed else (None, 0.0))
@@ -203,10 +216,29 @@ def main():
     for kind, n, steps, s in stream:
         ics.get(kind, n, s)
     kw = {"pool_bytes": int(a.pool_gb * (1 << 30)), "model": model, "learned_dt": ldt}
+    if a.direct:
+        kw["direct"] = True
     res = {"requests": a.requests, "seed": a.seed, "mixed": a.mixed, "pool_gb": a.pool_gb}
+    # warm-up, not part of any figure: the first pass through a process loads
+    # the kernels' code and first-touches the host buffers of the request
+    # copies and results (about 1 s for the plain stream); the plain stream is
+    # replayed whole, the mixed one (a minute per pass) by its first requests
+    nw = min(64, a.requests) if a.mixed else a.requests
+    run_server(stream[:nw], ics, np.zeros(nw), **kw)
+    res["warmup_requests"] = nw
+    def direct_pass():
+        dsat = run_server_latency(stream, ics, np.zeros(a.requests), **{**kw, "direct": True})
+        res["batched_saturated_direct"] = dsat
+        print(f"[saturated, direct launches] {dsat['mcups']:.0f} Mcell-updates/s in {dsat['wall_s']:.1f} s",
+              flush=True)
+
+    if a.compare_direct and not a.direct_last:
+        direct_pass()
     sat = run_server_latency(stream, ics, np.zeros(a.requests), **kw)
     res["batched_saturated"] = sat
     print(f"[saturated] {sat['mcups']:.0f} Mcell-updates/s in {sat['wall_s']:.1f} s", flush=True)
+    if a.compare_direct and a.direct_last:
+        direct_pass()
     rate = a.load * a.requests / sat["wall_s"]
     res["poisson_rate_per_s"] = rate
     res["batched_poisson"] = run_server_latency(stream, ics, arrivals(a.requests, rate, a.seed), **kw)

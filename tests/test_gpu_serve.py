@@ -170,3 +170,63 @@ def test_learned_request_needs_model(fv):
     with pytest.raises(fv.FvError):
         srv.submit(q, 5, learned=True, dt_fixed=1e-3)
     srv.close()
+
+
+def test_graph_replay_equals_direct_launches(fv):
+    """Rounds replayed from captured graphs give the same bits as direct
+    launches.  Requests arrive over several rounds, so the work-lists, the
+    launch grids and the kinds of work present change between replays (and
+    eager admission work runs between them); steps whose lists are empty run
+    launches that read a tile count of zero."""
+    from paper_2602_08670_amd import learned_solver as LS
+
+    m = small_model(fv, 5, scale=0.03, bias_last=0.5)
+    waves = [
+        [("swe", 1024, 1, 7), ("swe", 256, 2, 9), ("euler", 128, 3, 30)],
+        [("learned", 1024, 4, 5), ("learned", 128, 5, 9), ("learned", 128, 6, 14)],
+        [("swe", 192, 7, 12), ("euler", 64, 8, 3)],
+        [],
+        [("learned", 64, 9, 6), ("euler", 1024, 10, 5)],
+    ]
+
+    def request(kind, n, seed):
+        if kind == "learned":
+            q = I.random_smooth_swe(n, seed=seed).astype(np.float32)
+            return q, None, dict(learned=True, dt_fixed=LS.fine_dt(2048) * 2048 / n)
+        q, b = make_req(kind, n, seed)
+        return q, b, {}
+
+    runs = []
+    for direct in (False, True):
+        srv = fv.Server(3 << 30, max_solves=16, steps_per_round=4, max_items=1 << 20, model=m, direct=direct)
+        ids = []
+        for wave in waves:
+            for kind, n, seed, steps in wave:
+                q, b, kw = request(kind, n, seed)
+                ids.append((srv.submit(q, steps, bed=b, **kw), q.shape))
+            srv.round()
+        rounds = 0
+        while srv.round() != (0, 0):
+            rounds += 1
+            assert rounds < 100
+        out = []
+        for rid, shape in ids:
+            inf = srv.info(rid)
+            out.append((srv.result(rid, shape), inf.state, inf.steps_done, inf.sim_time, inf.fallback_faces,
+                        inf.redone_steps))
+        st = srv.stats()
+        srv.close()
+        runs.append(out)
+        print(f"[serve graph] direct={direct}: {len(out)} requests, {st.rounds} rounds, {st.graph_replays} "
+              f"replays of {st.graphs_captured} graphs, {st.grid_updates} grid updates", flush=True)
+        if direct:
+            assert st.graph_replays == 0 and st.graphs_captured == 0
+        else:
+            assert st.graph_replays == st.rounds and 0 < st.graphs_captured < st.graph_replays
+            assert st.grid_updates > 0
+    specs = [s for wave in waves for s in wave]
+    for spec, g, d in zip(specs, runs[0], runs[1]):
+        assert g[1] == 2 and g[2] == spec[3], spec
+        assert np.array_equal(g[0], d[0]), spec
+        assert g[1:] == d[1:], spec
+    m.close()
