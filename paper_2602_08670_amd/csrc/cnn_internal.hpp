@@ -86,7 +86,7 @@ struct LItem {
     int solve, tb_cnn, tb_st, parity;
 };
 constexpr int LTILE_CNN = 8;            // network pass tile side
-constexpr int LTILE_X = 64, LTILE_Y = 8;  // stage tile
+constexpr int LTILE_X = 32, LTILE_Y = 4;  // stage tile
 inline int ltiles_cnn(int nx, int ny) { return (nx / LTILE_CNN) * (ny / LTILE_CNN); }
 inline int ltiles_st(int nx, int ny) { return ((nx + LTILE_X - 1) / LTILE_X) * ((ny + LTILE_Y - 1) / LTILE_Y); }
 

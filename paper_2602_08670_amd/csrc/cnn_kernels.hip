@@ -297,11 +297,30 @@ __device__ __forceinline__ void fused_hidden(const bf16x8 *in, int rin, bf16 *ou
     }
 }
 
-__device__ __forceinline__ void stage_weights(bf16x8 *s_w, const char *P, size_t off, int nel)
-{
-    const bf16x8 *gw = (const bf16x8 *)(P + off);
-    for (int i = threadIdx.x; i < nel / 8; i += blockDim.x) s_w[i] = gw[i];
-}
+// N chunks of 16 bytes, global -> registers (load) and registers -> LDS
+// (store), FNW * 64 threads striding; split so that every load of the
+// workgroup's staging can be issued before its first LDS store.
+template <int N> struct Chunks {
+    static constexpr int T = FNW * 64, IT = (N + T - 1) / T;
+    bf16x8 v[IT];
+    __device__ __forceinline__ void load(const char *P, size_t off)
+    {
+        const bf16x8 *g = (const bf16x8 *)(P + off);
+#pragma unroll
+        for (int k = 0; k < IT; k++) {
+            const int i = threadIdx.x + k * T;
+            if (i < N) v[k] = g[i];
+        }
+    }
+    __device__ __forceinline__ void store(bf16x8 *s) const
+    {
+#pragma unroll
+        for (int k = 0; k < IT; k++) {
+            const int i = threadIdx.x + k * T;
+            if (i < N) s[i] = v[k];
+        }
+    }
+};
 
 // ALPHA: instead of z, write the constrained coefficients alpha = base + P z
 // of every group of six (same operation order as the learned stage's own
@@ -371,17 +390,42 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
     const int g = lane >> 4, px = lane & 15;
     const size_t hw = (size_t)H * W;
 
-    // input region, normalised and rounded to BF16 as the first layer reads it
-    for (int i = threadIdx.x; i < 3 * FRI * FRI; i += FNW * 64) {
-        const int ci = i / (FRI * FRI), k = i - ci * FRI * FRI;
-        const int ry = k / FRI, rx = k - ry * FRI;
-        const int yy = wrap(y0 - 5 + ry, H), xx = wrap(x0 - 5 + rx, W);
-        s_in[ci][k] = (bf16)((qb[(size_t)ci * hw + (size_t)yy * W + xx] - nrm.mean[ci]) * nrm.inv_std[ci]);
-    }
-    stage_weights(s_wall, P, pk.w[0], 32 * 32);
+    // input region, normalised and rounded to BF16 as the first layer reads
+    // it, and all five layers' weights: every global load is issued before
+    // the first LDS store
+    constexpr int NIN = 3 * FRI * FRI, TIN = (NIN + FNW * 64 - 1) / (FNW * 64);
+    float xin[TIN];
 #pragma unroll
-    for (int l = 1; l < 4; l++) stage_weights(s_wall + W0 + (l - 1) * WH, P, pk.w[l], 9 * 32 * 32);
-    stage_weights(s_wall + W0 + 3 * WH, P, pk.w[4], FW_EL);
+    for (int k = 0; k < TIN; k++) {
+        const int i = threadIdx.x + k * FNW * 64;
+        if (i < NIN) {
+            const int ci = i / (FRI * FRI), r = i - ci * FRI * FRI;
+            const int ry = r / FRI, rx = r - ry * FRI;
+            const int yy = wrap(y0 - 5 + ry, H), xx = wrap(x0 - 5 + rx, W);
+            xin[k] = qb[(size_t)ci * hw + (size_t)yy * W + xx];
+        }
+    }
+    Chunks<W0> c0;
+    Chunks<WH> c1, c2, c3;
+    Chunks<W4> c4;
+    c0.load(P, pk.w[0]);
+    c1.load(P, pk.w[1]);
+    c2.load(P, pk.w[2]);
+    c3.load(P, pk.w[3]);
+    c4.load(P, pk.w[4]);
+#pragma unroll
+    for (int k = 0; k < TIN; k++) {
+        const int i = threadIdx.x + k * FNW * 64;
+        if (i < NIN) {
+            const int ci = i / (FRI * FRI);
+            s_in[ci][i - ci * FRI * FRI] = (bf16)((xin[k] - nrm.mean[ci]) * nrm.inv_std[ci]);
+        }
+    }
+    c0.store(s_wall);
+    c1.store(s_wall + W0);
+    c2.store(s_wall + W0 + WH);
+    c3.store(s_wall + W0 + 2 * WH);
+    c4.store(s_wall + W0 + 3 * WH);
     __syncthreads();
 
     // layer 0 on the FR0 x FR0 region (one row of 16 pixels per group)
@@ -472,20 +516,30 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
     }
     if (ALPHA) {
         __syncthreads();
-        // 64 pixels x 12 groups of six: (axis*2 + side)*3 + var
+        // 64 pixels x 12 groups of six, (axis*2 + side)*3 + var: alpha
+        // replaces z in place, then each tile row's 8 x 72 values, contiguous
+        // in the output, leave as 16-byte stores
         for (int task = threadIdx.x; task < FT * FT * 12; task += FNW * 64) {
             const int p = task / 12, grp = task - p * 12;
             const int side = (grp / 3) & 1;
-            const float *zz = s_z + p * 72 + grp * 6;
-            const int py = p / FT, pxx = p - py * FT;
-            float *dst = zb + ((size_t)(y0 + py) * W + x0 + pxx) * 72 + grp * 6;
+            float *zz = s_z + p * 72 + grp * 6;
+            float zv[6], al[6];
+#pragma unroll
+            for (int j = 0; j < 6; j++) zv[j] = zz[j];
 #pragma unroll
             for (int k = 0; k < 6; k++) {
-                float al = pr.base[side * 6 + k];
+                al[k] = pr.base[side * 6 + k];
 #pragma unroll
-                for (int j = 0; j < 6; j++) al += pr.P[k * 6 + j] * zz[j];
-                dst[k] = al;
+                for (int j = 0; j < 6; j++) al[k] += pr.P[k * 6 + j] * zv[j];
             }
+#pragma unroll
+            for (int k = 0; k < 6; k++) zz[k] = al[k];
+        }
+        __syncthreads();
+        constexpr int RV = FT * 72 / 4;  // float4 per tile row
+        for (int i = threadIdx.x; i < FT * RV; i += FNW * 64) {
+            const int row = i / RV, c = i - row * RV;
+            ((float4 *)(zb + ((size_t)(y0 + row) * W + x0) * 72))[c] = ((const float4 *)(s_z + row * FT * 72))[c];
         }
     }
 }

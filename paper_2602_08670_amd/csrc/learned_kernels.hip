@@ -114,13 +114,19 @@ __device__ __forceinline__ void flux3(const float *QL, const float *QR, const Ph
     F[TM] = G[2];
 }
 
-// One 64 x 8 tile of solve b at (x0, y0); `first` marks the solve's tile
-// that does the per-step bookkeeping of MODE 3.
+// One LTILE_X x LTILE_Y tile of solve b at (x0, y0); `first` marks the
+// solve's tile that does the per-step bookkeeping of MODE 3.  The tile is
+// small enough for every thread to own at most one x face, one y face and
+// one cell: the coefficients of both faces are loaded before any face is
+// evaluated, so a stage costs about one global-load latency on the small
+// grids of the learned solver.
 template <int MODE, int FLUX, bool AL>
 __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, const int x0, const int y0,
                                              const bool first)
 {
-    constexpr int TX = 64, TY = 8, HX = TX + 6, HY = TY + 6;
+    constexpr int TX = LTILE_X, TY = LTILE_Y, HX = TX + 6, HY = TY + 6;
+    constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX;
+    static_assert(NFX <= 256 && NFY <= 256 && TX * TY <= 256, "one face per axis and one cell per thread");
     __shared__ float s_q[3][HY][HX];
     __shared__ float s_fx[3][TY][TX + 1];
     __shared__ float s_fy[3][TY + 1][TX];
@@ -172,40 +178,53 @@ __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, 
     __syncthreads();
 
     int nfb = 0;
-    // x faces: owner cell (x0 - 1 + fi, y0 + fj) <-> halo column fi + 2
-    for (int f = tid; f < TY * (TX + 1); f += 256) {
-        int fj = f / (TX + 1), fi = f - fj * (TX + 1);
+    // this thread's x face: owner cell (x0 - 1 + xi, y0 + xj) <-> halo
+    // column xi + 2; its y face: owner cell (x0 + yi, y0 - 1 + yj) <-> halo
+    // row yj + 2.  Threads past a face count read a valid face's
+    // coefficients and discard them.
+    const bool hx = tid < NFX, hy = tid < NFY;
+    const int tx_ = hx ? tid : 0, ty_ = hy ? tid : 0;
+    const int xj = tx_ / (TX + 1), xi = tx_ - xj * (TX + 1);
+    const int yj = ty_ / TX, yi = ty_ - yj * TX;
+    float zx[36], zy[36];
+    if (FS == 0) {
+        const int gy = y0 + xj < ny ? y0 + xj : ny - 1;
+        const int gx = x0 + yi < nx ? x0 + yi : nx - 1;
+        const float4 *px = (const float4 *)(a.z + (((size_t)b * ny + gy) * nx + pwrap(x0 - 1 + xi, nx)) * 72);
+        const float4 *py = (const float4 *)(a.z + (((size_t)b * ny + pwrap(y0 - 1 + yj, ny)) * nx + gx) * 72 + 36);
+#pragma unroll
+        for (int k = 0; k < 9; k++) {
+            const float4 u = px[k], w = py[k];
+            zx[4 * k] = u.x; zx[4 * k + 1] = u.y; zx[4 * k + 2] = u.z; zx[4 * k + 3] = u.w;
+            zy[4 * k] = w.x; zy[4 * k + 1] = w.y; zy[4 * k + 2] = w.z; zy[4 * k + 3] = w.w;
+        }
+    }
+    if (hx) {
         float st[3][6];
 #pragma unroll
         for (int v = 0; v < 3; v++)
 #pragma unroll
-            for (int k = 0; k < 6; k++) st[v][k] = s_q[v][fj + 3][fi + k];
-        int gy = y0 + fj < ny ? y0 + fj : ny - 1;
-        const float *zc = a.z + (((size_t)b * ny + gy) * nx + pwrap(x0 - 1 + fi, nx)) * 72;
+            for (int k = 0; k < 6; k++) st[v][k] = s_q[v][xj + 3][xi + k];
         float QL[3], QR[3], F[3];
-        int c = face_states<FS, AL>(st, zc, a.pr, QL, QR);
+        int c = face_states<FS, AL>(st, zx, a.pr, QL, QR);
         // each face is counted once: as the left face of a cell of this tile
-        if (fi < TX && x0 + fi < nx && y0 + fj < ny) nfb += c;
+        if (xi < TX && x0 + xi < nx && y0 + xj < ny) nfb += c;
         flux3<FLUX, 0>(QL, QR, a.ph, F);
 #pragma unroll
-        for (int v = 0; v < 3; v++) s_fx[v][fj][fi] = F[v];
+        for (int v = 0; v < 3; v++) s_fx[v][xj][xi] = F[v];
     }
-    // y faces: owner cell (x0 + fi, y0 - 1 + fj) <-> halo row fj + 2
-    for (int f = tid; f < (TY + 1) * TX; f += 256) {
-        int fj = f / TX, fi = f - fj * TX;
+    if (hy) {
         float st[3][6];
 #pragma unroll
         for (int v = 0; v < 3; v++)
 #pragma unroll
-            for (int k = 0; k < 6; k++) st[v][k] = s_q[v][fj + k][fi + 3];
-        int gx = x0 + fi < nx ? x0 + fi : nx - 1;
-        const float *zc = a.z + (((size_t)b * ny + pwrap(y0 - 1 + fj, ny)) * nx + gx) * 72 + 36;
+            for (int k = 0; k < 6; k++) st[v][k] = s_q[v][yj + k][yi + 3];
         float QL[3], QR[3], F[3];
-        int c = face_states<FS, AL>(st, zc, a.pr, QL, QR);
-        if (fj < TY && y0 + fj < ny && x0 + fi < nx) nfb += c;
+        int c = face_states<FS, AL>(st, zy, a.pr, QL, QR);
+        if (yj < TY && y0 + yj < ny && x0 + yi < nx) nfb += c;
         flux3<FLUX, 1>(QL, QR, a.ph, F);
 #pragma unroll
-        for (int v = 0; v < 3; v++) s_fy[v][fj][fi] = F[v];
+        for (int v = 0; v < 3; v++) s_fy[v][yj][yi] = F[v];
     }
     __syncthreads();
 
@@ -242,7 +261,8 @@ __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, 
 template <int MODE, int FLUX, bool AL = false>
 __global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
 {
-    learned_tile<MODE, FLUX, AL>(a, blockIdx.z, blockIdx.x * 64, blockIdx.y * 8, blockIdx.x == 0 && blockIdx.y == 0);
+    learned_tile<MODE, FLUX, AL>(a, blockIdx.z, blockIdx.x * LTILE_X, blockIdx.y * LTILE_Y,
+                                 blockIdx.x == 0 && blockIdx.y == 0);
 }
 
 // Work-list form over a table of solves of any size (serving, and single
@@ -392,7 +412,7 @@ hipError_t learned_stage(int mode, int flux, const StageBatch &sb, hipStream_t s
     a.t = sb.t;
     a.steps = sb.steps;
     if ((mode == 2 && (!a.commit_src || !a.commit_dst)) || (mode == 3 && !a.bad_next)) return hipErrorInvalidValue;
-    dim3 grid((a.nx + 63) / 64, (a.ny + 7) / 8, a.B), blk(256);
+    dim3 grid((a.nx + LTILE_X - 1) / LTILE_X, (a.ny + LTILE_Y - 1) / LTILE_Y, a.B), blk(256);
     const bool rus = flux == fvk::RUSANOV;
     switch (mode) {
     case 0:
