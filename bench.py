@@ -54,6 +54,8 @@ def parse():
     p.add_argument("--n", type=int, default=1024, help="grid side")
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--no-euler", action="store_true")
+    p.add_argument("--learned-steps", type=int, default=1000,
+                   help="64^2 learned steps timed for extra.learned_64_step_us (0: skip)")
     p.add_argument("--serving-requests", type=int, default=64,
                    help="requests in the serving sample (0: skip); p50/p99 at 0.8 of the saturated rate")
     p.add_argument("--cpu-seconds", type=float, default=12.0, help="target oracle CPU time for the baseline")
@@ -110,6 +112,33 @@ def serving_sample(n_req):
     poi = sb.run_server_latency(stream, ics, sb.arrivals(n_req, rate, 0))
     return {"requests": n_req, "saturated_mcups": round(sat["mcups"], 1), "poisson_rate_per_s": round(rate, 2),
             "p50_s": round(poi["p50_s"], 4), "p99_s": round(poi["p99_s"], 4), "poisson_mcups": round(poi["mcups"], 1)}
+
+
+def learned_sample(steps, torch):
+    """Latency of one learned (Heun) step on the 64^2 coarse grid of the
+    learned-solver workload: periodic shallow water, fixed step = 32 x the
+    2048^2 fine step, a network with seeded random weights (the step's cost
+    does not depend on the weights).  HIP events on the solver's stream."""
+    from paper_2602_08670_amd import fv, inputs
+    from paper_2602_08670_amd import learned_solver as LS
+
+    rng = np.random.default_rng(0)
+    vec = (rng.standard_normal(49448) * 0.02).astype(np.float32)
+    m = fv.Model(vec, fv.make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0)))
+    q0 = inputs.random_smooth_swe(64, seed=5).astype(np.float32)
+    s = fv.Solver(q0, prec=fv.FV_F32, dt_fixed=LS.fine_dt(2048) * 32, learned=1)
+    s.learned_step(m, 20, want_stats=False)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(s.stream)
+    s.learned_step(m, steps, want_stats=False)
+    e1.record(s.stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / steps
+    s.close()
+    m.close()
+    return round(us, 2)
 
 
 def cpu_baseline(n, target_s):
@@ -175,6 +204,9 @@ def main():
         se.close()
         extra["euler_1024_fp32_mcups"] = round(n * n * esteps / eg / 1e6, 1)
         extra["euler_hbm_frac"] = round(BYTES_PER_CELL_UPDATE["euler"] * n * n * esteps / eg / 1e9 / HBM_PEAK_GBS, 4)
+
+    if args.learned_steps > 0:
+        extra["learned_64_step_us"] = learned_sample(args.learned_steps, torch)
 
     if args.serving_requests > 0:
         extra["serving"] = serving_sample(args.serving_requests)
