@@ -98,14 +98,19 @@ hipError_t launch_forward_batch(int stage, const void *packed, const Norm &nrm, 
                                 const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one = 0);
 hipError_t launch_learned_batch(int mode, int stage, const LSolve *tab, const LItem *items, const int *nitems,
                                 int ntiles, const Proj &pr, hipStream_t st, int one = 0);
-// The forms recorded in graphs: wgs workgroups (set to the list's tiles
-// before each replay), the tile counts read from the list header list =
-// {items, network tiles, stage tiles, 0}.
+// The forms recorded in graphs: wgs workgroups (set before each replay: the
+// list's stage tiles, and for the network pass at most fused_max_grid()),
+// the tile counts read from the list header list = {items, network tiles,
+// stage tiles, 0}.  The network pass's workgroups stride over its tiles.
 hipError_t launch_forward_batch_list(int stage, const void *packed, const Norm &nrm, const Proj &pr,
                                      const LSolve *tab, const LItem *items, const int *list, int wgs,
                                      hipStream_t st);
 hipError_t launch_learned_batch_list(int mode, int stage, const LSolve *tab, const LItem *items, const int *list,
                                      int wgs, const Proj &pr, hipStream_t st);
+// Workgroups of the tiled network pass resident at once on the current
+// device: its launches use at most this many, each striding over tiles and
+// staging the weights once.
+int fused_max_grid();
 
 // The same forward in one launch, without keeping activations: every
 // workgroup runs all five layers on an 8x8 tile of pixels (nx % 8 == 0,

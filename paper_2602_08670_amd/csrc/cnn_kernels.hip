@@ -325,21 +325,28 @@ template <int N> struct Chunks {
 // ALPHA: instead of z, write the constrained coefficients alpha = base + P z
 // of every group of six (same operation order as the learned stage's own
 // projection, so alpha is bit-identical to projecting this kernel's z).
+// load_w: stage the weights (a workgroup's first tile; its later tiles find
+// them in LDS).
 template <bool ALPHA>
 __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
-                                           int H, int W, int y0, int x0, const Proj &pr);
+                                           int H, int W, int y0, int x0, const Proj &pr, bool load_w);
 
+// Workgroups stride over the B x (H/FT) x (W/FT) tiles: a grid of at most the
+// workgroups resident at once stages the weights once per workgroup.
 template <bool ALPHA>
 __global__ __launch_bounds__(FNW * 64) void conv_fused_kernel(const float *q, const char *P, Packed pk, Norm nrm, float *z,
                                                               int B, int H, int W, Proj pr)
 {
-    const int tx_n = W / FT, ty_n = H / FT;
-    const int tile = blockIdx.x;
-    const int b = tile / (tx_n * ty_n);
-    const int r = tile - b * tx_n * ty_n;
+    const int tx_n = W / FT, ty_n = H / FT, total = B * tx_n * ty_n;
     const size_t hw = (size_t)H * W;
-    fused_tile<ALPHA>(q + (size_t)b * 3 * hw, P, pk, nrm, z + (size_t)b * hw * 72, H, W, (r / tx_n) * FT,
-                      (r % tx_n) * FT, pr);
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const bool first = tile == (int)blockIdx.x;
+        if (!first) __syncthreads();  // the previous tile's LDS reads are done
+        const int b = tile / (tx_n * ty_n);
+        const int r = tile - b * tx_n * ty_n;
+        fused_tile<ALPHA>(q + (size_t)b * 3 * hw, P, pk, nrm, z + (size_t)b * hw * 72, H, W, (r / tx_n) * FT,
+                          (r % tx_n) * FT, pr, first);
+    }
 }
 
 // Work-list form: workgroup w finds its solve by binary search over the
@@ -352,34 +359,40 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_batch_kernel(const LSolve
                                                                     int one, const char *P, Packed pk, Norm nrm,
                                                                     Proj pr)
 {
-    const int w = blockIdx.x;
-    if (w >= (ntiles > 0 ? ntiles : nitems[1])) return;
-    LItem it;
-    if (one) {
-        it = items[0];
-    } else {
-        const int n = *nitems;
-        int lo = 0, hi = n - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (items[mid].tb_cnn <= w) lo = mid;
-            else hi = mid - 1;
+    const int total = ntiles > 0 ? ntiles : nitems[1];
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const bool first = w == (int)blockIdx.x;
+        if (!first) __syncthreads();  // the previous tile's LDS reads are done
+        LItem it;
+        if (one) {
+            it = items[0];
+        } else {
+            const int n = *nitems;
+            int lo = 0, hi = n - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (items[mid].tb_cnn <= w) lo = mid;
+                else hi = mid - 1;
+            }
+            it = items[lo];
         }
-        it = items[lo];
+        const LSolve &d = tab[it.solve];
+        const int tile = w - it.tb_cnn, tx_n = d.nx / FT;
+        const int ty = tile / tx_n, tx = tile - ty * tx_n;
+        fused_tile<true>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, d.z, d.ny, d.nx, ty * FT, tx * FT, pr, first);
     }
-    const LSolve &d = tab[it.solve];
-    const int tile = w - it.tb_cnn, tx_n = d.nx / FT;
-    const int ty = tile / tx_n, tx = tile - ty * tx_n;
-    fused_tile<true>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, d.z, d.ny, d.nx, ty * FT, tx * FT, pr);
 }
 
 template <bool ALPHA>
 __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
-                                           int H, int W, int y0, int x0, const Proj &pr)
+                                           int H, int W, int y0, int x0, const Proj &pr, bool load_w)
 {
     __shared__ bf16 s_in[3][FRI * FRI];
-    __shared__ bf16x8 s_a0[FR0 * FR0 * 4];                  // 32 channels = 4 x bf16x8 per pixel
-    __shared__ bf16x8 s_a1[(FR0 - 2) * (FR0 - 2) * 4];
+    // activations, 32 channels = 4 x bf16x8 per pixel: layers 0 and 2 write
+    // s_a0, layers 1 and 3 write s_a1
+    __shared__ bf16x8 s_act[FR0 * FR0 * 4 + (FR0 - 2) * (FR0 - 2) * 4];
+    bf16x8 *const s_a0 = s_act;
+    bf16x8 *const s_a1 = s_act + FR0 * FR0 * 4;
     // all five layers' packed weights, loaded together at the start
     constexpr int W0 = 32 * 32 / 8, WH = 9 * 32 * 32 / 8, W4 = FW_EL / 8;
     __shared__ bf16x8 s_wall[W0 + 3 * WH + W4];
@@ -408,11 +421,13 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
     Chunks<W0> c0;
     Chunks<WH> c1, c2, c3;
     Chunks<W4> c4;
-    c0.load(P, pk.w[0]);
-    c1.load(P, pk.w[1]);
-    c2.load(P, pk.w[2]);
-    c3.load(P, pk.w[3]);
-    c4.load(P, pk.w[4]);
+    if (load_w) {
+        c0.load(P, pk.w[0]);
+        c1.load(P, pk.w[1]);
+        c2.load(P, pk.w[2]);
+        c3.load(P, pk.w[3]);
+        c4.load(P, pk.w[4]);
+    }
 #pragma unroll
     for (int k = 0; k < TIN; k++) {
         const int i = threadIdx.x + k * FNW * 64;
@@ -421,11 +436,13 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
             s_in[ci][i - ci * FRI * FRI] = (bf16)((xin[k] - nrm.mean[ci]) * nrm.inv_std[ci]);
         }
     }
-    c0.store(s_wall);
-    c1.store(s_wall + W0);
-    c2.store(s_wall + W0 + WH);
-    c3.store(s_wall + W0 + 2 * WH);
-    c4.store(s_wall + W0 + 3 * WH);
+    if (load_w) {
+        c0.store(s_wall);
+        c1.store(s_wall + W0);
+        c2.store(s_wall + W0 + WH);
+        c3.store(s_wall + W0 + 2 * WH);
+        c4.store(s_wall + W0 + 3 * WH);
+    }
     __syncthreads();
 
     // layer 0 on the FR0 x FR0 region (one row of 16 pixels per group)
@@ -472,7 +489,11 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
     // co tiles = 20 accumulation chains of 9 taps, chain c = (group c % 4,
     // co tile c / 4), dealt to the waves in turn
     const bf16x8 *s_w = s_wall + W0 + 3 * WH;
-    float *s_z = (float *)(s_wall + W0);  // [FT*FT][72] over the hidden layers' weights (ALPHA only)
+    // [FT*FT][72] over the activations (ALPHA only; the weights stay for the
+    // workgroup's next tile): it covers s_a0 and the start of s_a1, which
+    // layer 4 reads before the barrier that precedes its first store
+    float *s_z = (float *)s_act;
+    static_assert(FT * FT * 72 * 4 <= sizeof(s_act), "coefficient tile fits over the activations");
     {
         constexpr int NT = 5, RIN = FT + 2, NG = FT * FT / 16, NCH = NG * NT;
         constexpr int CPW = (NCH + FNW - 1) / FNW;  // chains per wave
@@ -495,7 +516,7 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
                 }
             }
         }
-        if (ALPHA) __syncthreads();  // every wave past the hidden layers' weights before they hold z
+        if (ALPHA) __syncthreads();  // every wave past its layer-4 reads of s_a1 before it holds z
 #pragma unroll
         for (int j = 0; j < CPW; j++) {
             const int c = wave + j * FNW;
@@ -544,16 +565,38 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
     }
 }
 
+int fused_max_grid()
+{
+    // resident workgroups of the tiled pass (one per CU: its LDS), per device
+    static int cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (dev < 0 || dev >= 64) return 256;
+    if (!cache[dev]) {
+        int cus = 0, a = 0, b = 0, c = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&a, conv_fused_batch_kernel<1>, FNW * 64, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, conv_fused_batch_kernel<2>, FNW * 64, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, conv_fused_kernel<true>, FNW * 64, 0) != hipSuccess)
+            return 256;
+        int m = a < b ? a : b;
+        m = m < c ? m : c;
+        cache[dev] = (m > 0 ? m : 1) * (cus > 0 ? cus : 256);
+    }
+    return cache[dev];
+}
+
 hipError_t launch_forward_batch(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve *tab,
                                 const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one)
 {
     if (ntiles <= 0) return hipSuccess;
     const Packed pk = packed_layout();
+    const int cap = fused_max_grid(), g = ntiles < cap ? ntiles : cap;
     if (stage == 1)
-        hipLaunchKernelGGL(conv_fused_batch_kernel<1>, dim3(ntiles), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
+        hipLaunchKernelGGL(conv_fused_batch_kernel<1>, dim3(g), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
                            one, (const char *)packed, pk, nrm, pr);
     else
-        hipLaunchKernelGGL(conv_fused_batch_kernel<2>, dim3(ntiles), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
+        hipLaunchKernelGGL(conv_fused_batch_kernel<2>, dim3(g), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
                            one, (const char *)packed, pk, nrm, pr);
     return hipGetLastError();
 }
@@ -577,12 +620,13 @@ hipError_t launch_forward_fused(const void *packed, const Norm &nrm, const float
                                 hipStream_t st, const Proj *alpha)
 {
     if (nx % FT || ny % FT) return hipErrorInvalidValue;
-    const int tiles = B * (nx / FT) * (ny / FT);
+    const int tiles = B * (nx / FT) * (ny / FT), cap = fused_max_grid();
+    const dim3 g(tiles < cap ? tiles : cap);
     if (alpha)
-        hipLaunchKernelGGL(conv_fused_kernel<true>, dim3(tiles), dim3(FNW * 64), 0, st, q, (const char *)packed,
+        hipLaunchKernelGGL(conv_fused_kernel<true>, g, dim3(FNW * 64), 0, st, q, (const char *)packed,
                            packed_layout(), nrm, z, B, ny, nx, *alpha);
     else
-        hipLaunchKernelGGL(conv_fused_kernel<false>, dim3(tiles), dim3(FNW * 64), 0, st, q, (const char *)packed,
+        hipLaunchKernelGGL(conv_fused_kernel<false>, g, dim3(FNW * 64), 0, st, q, (const char *)packed,
                            packed_layout(), nrm, z, B, ny, nx, Proj{});
     return hipGetLastError();
 }

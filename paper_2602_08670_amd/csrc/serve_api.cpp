@@ -111,6 +111,7 @@ struct fv_server {
     // captured rounds, keyed by the kinds of work present | steps << 3
     std::map<int, RoundGraph> graphs;
     int64_t rounds = 0, replays = 0, grid_updates = 0;
+    int cnn_cap = 256;  // most workgroups of a network-pass launch
     double launch_s = 0, wait_s = 0;  // host time enqueueing rounds' work, and waiting for it
     double capture_s = 0;             // host time capturing and instantiating graphs
 
@@ -421,7 +422,7 @@ hipError_t set_grids(fv_server *s, RoundGraph *rg, const int *grids, const int *
     for (GraphNode &n : rg->nodes) {
         int want;
         if (n.kind == 0) want = grids[n.idx] ? fvk::xcd_grid(grids[n.idx]) : 8;
-        else if (n.kind == 1) want = lgrid_cnn[n.idx] ? lgrid_cnn[n.idx] : 1;
+        else if (n.kind == 1) want = lgrid_cnn[n.idx] ? (lgrid_cnn[n.idx] < s->cnn_cap ? lgrid_cnn[n.idx] : s->cnn_cap) : 1;
         else want = lgrid_st[n.idx] ? lgrid_st[n.idx] : 1;
         if ((int)n.p.gridDim.x == want) continue;
         n.p.gridDim.x = (unsigned)want;
@@ -477,6 +478,7 @@ fv_status fv_server_create(const fv_server_config *cfg, void *pool, size_t pool_
         free_host(s.get());
         return hip_fail(e, "pinned work-list buffers");
     }
+    if (cfg->model) s->cnn_cap = cnn::fused_max_grid();
     if (!stream) {
         // graphs cannot be captured on the null stream: the server then
         // runs on a stream of its own (default priority)
