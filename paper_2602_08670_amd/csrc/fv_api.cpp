@@ -513,7 +513,7 @@ fv_status fv_model_create(const fv_model_desc *desc, const float *params, void *
     if (!out) return fail(FV_E_INVALID, "out is NULL");
     *out = nullptr;
     if (!desc || desc->struct_size != sizeof(fv_model_desc)) return fail(FV_E_INVALID, "model desc struct_size");
-    if (desc->hidden != 32) return fail(FV_E_UNSUPPORTED, "hidden width %d (this build: 32)", desc->hidden);
+    if (desc->hidden != 32) return fail(FV_E_UNSUPPORTED, "hidden width %d (the kernels implement 32)", desc->hidden);
     if (desc->order < 0 || desc->order > 1) return fail(FV_E_INVALID, "constraint order %d", desc->order);
     if (desc->reserved0 != 0) return fail(FV_E_INVALID, "reserved0 must be 0");
     if (!params || !workspace) return fail(FV_E_INVALID, "params or workspace is NULL");

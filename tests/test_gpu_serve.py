@@ -81,7 +81,7 @@ def test_admission_by_memory_and_late_arrivals(fv):
     r2 = srv.submit(q, 10, bed=b)
     r3 = srv.submit(q, 10, bed=b)
     a, qd = srv.round()
-    assert (a, qd) == (1, 1)  # r2 finished in round 1, r3 still queued (memory)
+    assert (a, qd) == (1, 1)  # r2 finished in the first server round, r3 still queued (memory)
     assert srv.info(r1).state == 1
     assert srv.info(r3).state == 0 and srv.info(r2).state == 2
     r4 = srv.submit(*make_req("euler", 64, 3)[:1], 20)  # late arrival, small
