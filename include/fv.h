@@ -315,9 +315,9 @@ fv_status fv_coarsen(const float *fine, int nvar, int nx, int ny, int factor, fl
  * not fit).  A round advances every active solve by up to steps_per_round
  * steps, each stage of each step being one batched launch over the tiles of
  * all active solves of an equation type; for the learned solves each step
- * is six batched launches (the network pass of every learned solve in one
- * BF16 MFMA launch, the learned stage, both twice, then commit-or-redo and
- * redo).  A round's launches are recorded once, per kinds of work present
+ * is four batched launches (per stage, one launch runs the network pass
+ * (BF16 MFMA) and the learned stage of every learned solve, the
+ * coefficients staying on chip; then commit-or-redo and redo).  A round's launches are recorded once, per kinds of work present
  * and number of steps, into a hipGraph that every later round replays: the
  * kernels read their tile counts from the device work-lists, and between
  * replays the host rewrites those lists and sets each launch's grid to its

@@ -111,6 +111,16 @@ hipError_t launch_learned_batch_list(int mode, int stage, const LSolve *tab, con
 // device: its launches use at most this many, each striding over tiles and
 // staging the weights once.
 int fused_max_grid();
+// Network pass and learned stage (MODE 0) of one stage in one launch over the
+// listed solves' network tiles (the coefficients stay in LDS; nx, ny multiples of
+// LTILE_CNN): stage 1 writes S1 from q, stage 2 writes S2 from S1 and q.
+// Same results as launch_forward_batch followed by launch_learned_batch
+// MODE 0.  The list form is the one recorded in graphs (wgs set before each
+// replay to at most fused_max_grid()).
+hipError_t launch_conv_learned(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve *tab,
+                               const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one = 0);
+hipError_t launch_conv_learned_list(int stage, const void *packed, const Norm &nrm, const Proj &pr,
+                                    const LSolve *tab, const LItem *items, const int *list, int wgs, hipStream_t st);
 
 // The same forward in one launch, without keeping activations: every
 // workgroup runs all five layers on an 8x8 tile of pixels (nx % 8 == 0,

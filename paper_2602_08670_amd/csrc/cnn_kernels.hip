@@ -12,6 +12,7 @@
 // 4*(lane/16) .. +3; lane group lane/16 carries the same 8 K indices in A
 // and B.
 #include "cnn_internal.hpp"
+#include "learned_device.hpp"
 
 namespace cnn {
 
@@ -238,8 +239,8 @@ hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, i
 // Layer l's output is computed on the (FT + 2(4 - l))^2 region around the
 // tile, so the next layer finds its 3x3 neighbourhood inside the block: the
 // input region (FT + 10)^2 is read once with periodic wrap, activations stay
-// in LDS (two ping-pong buffers), and each layer's packed weights are staged
-// into one LDS buffer in turn.  Each output pixel accumulates its MFMAs in
+// in LDS (two ping-pong buffers), and all five layers' packed weights are
+// staged into LDS together.  Each output pixel accumulates its MFMAs in
 // the same order as conv_fwd_kernel (taps 0..8, K slices within a tap), with
 // the same bias, ReLU and BF16 rounding, so z is bit-identical to the
 // layer-by-layer pass; only the halo pixels are computed more than once.
@@ -325,11 +326,19 @@ template <int N> struct Chunks {
 // ALPHA: instead of z, write the constrained coefficients alpha = base + P z
 // of every group of six (same operation order as the learned stage's own
 // projection, so alpha is bit-identical to projecting this kernel's z).
-// load_w: stage the weights (a workgroup's first tile; its later tiles find
-// them in LDS).
-template <bool ALPHA>
-__device__ __forceinline__ void fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
-                                           int H, int W, int y0, int x0, const Proj &pr, bool load_w);
+// One workgroup's network pass for the FO x FO output region at (x0 - FO +
+// FT, y0 - FO + FT): the FT x FT tile (FO = FT), or the tile and its low halo
+// row and column (FO = FT + 1).  OUT_Z writes raw z to zb, OUT_ALPHA the
+// constrained coefficients alpha = base + P z (same operation order as the
+// learned stage's own projection) to zb, OUT_Z_LDS keeps z in LDS
+// ([FO*FO][72], returned) and the tile's FP32 stage input with a 3-cell halo
+// in qf for a learned stage in the same workgroup, which projects each face's
+// coefficients itself (each group of six serves exactly one face).  load_w: stage the
+// weights (a workgroup's first tile; its later tiles find them in LDS).
+enum { OUT_Z = 0, OUT_ALPHA = 1, OUT_Z_LDS = 2 };
+template <int FO, int OUT>
+__device__ __forceinline__ float *fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
+                                             int H, int W, int y0, int x0, const Proj &pr, bool load_w, float *qf);
 
 // Workgroups stride over the B x (H/FT) x (W/FT) tiles: a grid of at most the
 // workgroups resident at once stages the weights once per workgroup.
@@ -344,8 +353,8 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_kernel(const float *q, co
         if (!first) __syncthreads();  // the previous tile's LDS reads are done
         const int b = tile / (tx_n * ty_n);
         const int r = tile - b * tx_n * ty_n;
-        fused_tile<ALPHA>(q + (size_t)b * 3 * hw, P, pk, nrm, z + (size_t)b * hw * 72, H, W, (r / tx_n) * FT,
-                          (r % tx_n) * FT, pr, first);
+        fused_tile<FT, ALPHA ? OUT_ALPHA : OUT_Z>(q + (size_t)b * 3 * hw, P, pk, nrm, z + (size_t)b * hw * 72, H, W,
+                                                  (r / tx_n) * FT, (r % tx_n) * FT, pr, first, nullptr);
     }
 }
 
@@ -379,21 +388,25 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_batch_kernel(const LSolve
         const LSolve &d = tab[it.solve];
         const int tile = w - it.tb_cnn, tx_n = d.nx / FT;
         const int ty = tile / tx_n, tx = tile - ty * tx_n;
-        fused_tile<true>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, d.z, d.ny, d.nx, ty * FT, tx * FT, pr, first);
+        fused_tile<FT, OUT_ALPHA>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, d.z, d.ny, d.nx, ty * FT, tx * FT, pr, first,
+                                  nullptr);
     }
 }
 
-template <bool ALPHA>
-__device__ __forceinline__ void fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
-                                           int H, int W, int y0, int x0, const Proj &pr, bool load_w)
+template <int FO, int OUT>
+__device__ __forceinline__ float *fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
+                                             int H, int W, int y0, int x0, const Proj &pr, bool load_w, float *qf)
 {
-    __shared__ bf16 s_in[3][FRI * FRI];
+    static_assert(FO == FT || (FO == FT + 1 && OUT == OUT_Z_LDS), "output region: the tile, or the tile and its low halo");
+    constexpr int OFF = FO - FT;          // the region starts OFF cells before the tile
+    constexpr int FRI_ = FO + 10, FR0_ = FO + 8;
+    __shared__ bf16 s_in[3][FRI_ * FRI_];
     // activations, 32 channels = 4 x bf16x8 per pixel: layers 0 and 2 write
     // s_a0, layers 1 and 3 write s_a1
-    __shared__ bf16x8 s_act[FR0 * FR0 * 4 + (FR0 - 2) * (FR0 - 2) * 4];
+    __shared__ bf16x8 s_act[FR0_ * FR0_ * 4 + (FR0_ - 2) * (FR0_ - 2) * 4];
     bf16x8 *const s_a0 = s_act;
-    bf16x8 *const s_a1 = s_act + FR0 * FR0 * 4;
-    // all five layers' packed weights, loaded together at the start
+    bf16x8 *const s_a1 = s_act + FR0_ * FR0_ * 4;
+    // all five layers' packed weights, staged together
     constexpr int W0 = 32 * 32 / 8, WH = 9 * 32 * 32 / 8, W4 = FW_EL / 8;
     __shared__ bf16x8 s_wall[W0 + 3 * WH + W4];
 
@@ -402,19 +415,21 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, px = lane & 15;
     const size_t hw = (size_t)H * W;
+    const int ry0 = y0 - OFF - 5, rx0 = x0 - OFF - 5;  // origin of the input region
 
     // input region, normalised and rounded to BF16 as the first layer reads
     // it, and all five layers' weights: every global load is issued before
-    // the first LDS store
-    constexpr int NIN = 3 * FRI * FRI, TIN = (NIN + FNW * 64 - 1) / (FNW * 64);
+    // the first LDS store.  qf (OUT_Z_LDS): the FP32 values of the
+    // (FT + 6)^2 cells from (x0 - 3, y0 - 3), kept for the learned stage.
+    constexpr int NIN = 3 * FRI_ * FRI_, TIN = (NIN + FNW * 64 - 1) / (FNW * 64);
     float xin[TIN];
 #pragma unroll
     for (int k = 0; k < TIN; k++) {
         const int i = threadIdx.x + k * FNW * 64;
         if (i < NIN) {
-            const int ci = i / (FRI * FRI), r = i - ci * FRI * FRI;
-            const int ry = r / FRI, rx = r - ry * FRI;
-            const int yy = wrap(y0 - 5 + ry, H), xx = wrap(x0 - 5 + rx, W);
+            const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
+            const int ry = r / FRI_, rx = r - ry * FRI_;
+            const int yy = wrap(ry0 + ry, H), xx = wrap(rx0 + rx, W);
             xin[k] = qb[(size_t)ci * hw + (size_t)yy * W + xx];
         }
     }
@@ -432,8 +447,14 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
     for (int k = 0; k < TIN; k++) {
         const int i = threadIdx.x + k * FNW * 64;
         if (i < NIN) {
-            const int ci = i / (FRI * FRI);
-            s_in[ci][i - ci * FRI * FRI] = (bf16)((xin[k] - nrm.mean[ci]) * nrm.inv_std[ci]);
+            const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
+            s_in[ci][r] = (bf16)((xin[k] - nrm.mean[ci]) * nrm.inv_std[ci]);
+            if (OUT == OUT_Z_LDS) {
+                // the halo's corner (x0 - 3, y0 - 3) is 2 + OFF cells into the input region
+                constexpr int QS = FT + 6, QO = 2 + OFF;
+                const int rr = r / FRI_, ry = rr - QO, rx = r - rr * FRI_ - QO;
+                if (ry >= 0 && ry < QS && rx >= 0 && rx < QS) qf[(ci * QS + ry) * QS + rx] = xin[k];
+            }
         }
     }
     if (load_w) {
@@ -445,12 +466,16 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
     }
     __syncthreads();
 
-    // layer 0 on the FR0 x FR0 region (one row of 16 pixels per group)
+    // layer 0 on the FR0_ x FR0_ region, 16 pixels per group
     {
         const float *bias = (const float *)(P + pk.b[0]);
         const bf16x8 A0 = s_wall[px * 4 + g], A1 = s_wall[(16 + px) * 4 + g];
-        for (int gi = wave; gi < FR0; gi += FNW) {
-            const int py = gi, pxx = px;
+        constexpr int NP0 = FR0_ * FR0_, NG0 = (NP0 + 15) / 16;
+        for (int gi = wave; gi < NG0; gi += FNW) {
+            const int p = gi * 16 + px;
+            const bool valid = p < NP0;
+            const int pc = valid ? p : 0;
+            const int py = pc / FR0_, pxx = pc - py * FR0_;
             bf16x8 bx;
 #pragma unroll
             for (int e = 0; e < 8; e++) {
@@ -458,44 +483,47 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
                 bf16 v = (bf16)0.0f;
                 if (k < 27) {
                     const int tap = k / 3, ci = k - 3 * tap;
-                    v = s_in[ci][(py + tap / 3) * FRI + pxx + tap % 3];
+                    v = s_in[ci][(py + tap / 3) * FRI_ + pxx + tap % 3];
                 }
                 bx[e] = v;
             }
             floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
             acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, bx, acc[0], 0, 0, 0);
             acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, bx, acc[1], 0, 0, 0);
-            const int p = py * FR0 + pxx;
+            if (valid) {
 #pragma unroll
-            for (int t = 0; t < 2; t++) {
-                const int co0 = 16 * t + 4 * g;
-                bf16x4 o;
+                for (int t = 0; t < 2; t++) {
+                    const int co0 = 16 * t + 4 * g;
+                    bf16x4 o;
 #pragma unroll
-                for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[t][i] + bias[co0 + i], 0.0f);
-                *(bf16x4 *)((bf16 *)s_a0 + (size_t)p * 32 + co0) = o;
+                    for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[t][i] + bias[co0 + i], 0.0f);
+                    *(bf16x4 *)((bf16 *)s_a0 + (size_t)p * 32 + co0) = o;
+                }
             }
         }
     }
     // hidden layers 1..3: s_a0 -> s_a1 -> s_a0 -> s_a1
     for (int l = 1; l < 4; l++) {
         __syncthreads();  // previous layer's output written
-        const int rin = FR0 - 2 * (l - 1);
+        const int rin = FR0_ - 2 * (l - 1);
         const bf16x8 *in = (l & 1) ? s_a0 : s_a1;
         bf16 *out = (bf16 *)((l & 1) ? s_a1 : s_a0);
         fused_hidden(in, rin, out, s_wall + W0 + (l - 1) * WH, (const float *)(P + pk.b[l]), wave, lane);
     }
     __syncthreads();
-    // layer 4: s_a1 (FT + 2)^2 -> z on the FT x FT tile: 4 pixel groups x 5
-    // co tiles = 20 accumulation chains of 9 taps, chain c = (group c % 4,
-    // co tile c / 4), dealt to the waves in turn
+    // layer 4: s_a1 (FO + 2)^2 -> z on the FO x FO region: NG pixel groups x
+    // 5 co tiles of accumulation chains of 9 taps, chain c = (group c % NG,
+    // co tile c / NG), dealt to the waves in turn
     const bf16x8 *s_w = s_wall + W0 + 3 * WH;
-    // [FT*FT][72] over the activations (ALPHA only; the weights stay for the
-    // workgroup's next tile): it covers s_a0 and the start of s_a1, which
-    // layer 4 reads before the barrier that precedes its first store
+    // [FO*FO][72] over the activations (modes that stage z in LDS; the
+    // weights stay for the workgroup's next tile): it covers s_a0 and the
+    // start of s_a1, which layer 4 reads before the barrier that precedes its
+    // first store
     float *s_z = (float *)s_act;
-    static_assert(FT * FT * 72 * 4 <= sizeof(s_act), "coefficient tile fits over the activations");
+    static_assert(FO * FO * 72 * 4 <= sizeof(s_act), "coefficient region fits over the activations");
+    constexpr bool ALPHA = OUT != OUT_Z;  // z staged in LDS
     {
-        constexpr int NT = 5, RIN = FT + 2, NG = FT * FT / 16, NCH = NG * NT;
+        constexpr int NT = 5, RIN = FO + 2, NPX = FO * FO, NG = (NPX + 15) / 16, NCH = NG * NT;
         constexpr int CPW = (NCH + FNW - 1) / FNW;  // chains per wave
         const float *bias = (const float *)(P + pk.b[4]);
         floatx4 acc[CPW];
@@ -507,7 +535,8 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
             if (c < NCH) {  // wave-uniform
                 const int gi = c % NG, t = c / NG;
                 const int p = gi * 16 + px;
-                const int py = p / FT, pxx = p - py * FT;
+                const int pc = p < NPX ? p : 0;
+                const int py = pc / FO, pxx = pc - py * FO;
 #pragma unroll
                 for (int tap = 0; tap < 9; tap++) {
                     const bf16x8 bx = s_a1[((py + tap / 3) * RIN + pxx + tap % 3) * 4 + g];
@@ -523,9 +552,9 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
             if (c < NCH) {
                 const int gi = c % NG, t = c / NG;
                 const int co0 = 16 * t + 4 * g;
-                if (co0 < 72) {
-                    const int p = gi * 16 + px;
-                    const int py = p / FT, pxx = p - py * FT;
+                const int p = gi * 16 + px;
+                if (co0 < 72 && p < NPX) {
+                    const int py = p / FO, pxx = p - py * FO;
                     floatx4 o;
 #pragma unroll
                     for (int i = 0; i < 4; i++) o[i] = acc[j][i] + bias[co0 + i];
@@ -535,12 +564,11 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
             }
         }
     }
-    if (ALPHA) {
-        __syncthreads();
-        // 64 pixels x 12 groups of six, (axis*2 + side)*3 + var: alpha
-        // replaces z in place, then each tile row's 8 x 72 values, contiguous
-        // in the output, leave as 16-byte stores
-        for (int task = threadIdx.x; task < FT * FT * 12; task += FNW * 64) {
+    if (ALPHA) __syncthreads();
+    if (OUT == OUT_ALPHA) {
+        // FO^2 pixels x 12 groups of six, (axis*2 + side)*3 + var: alpha
+        // replaces z in place
+        for (int task = threadIdx.x; task < FO * FO * 12; task += FNW * 64) {
             const int p = task / 12, grp = task - p * 12;
             const int side = (grp / 3) & 1;
             float *zz = s_z + p * 72 + grp * 6;
@@ -557,11 +585,151 @@ __device__ __forceinline__ void fused_tile(const float *qb, const char *P, const
             for (int k = 0; k < 6; k++) zz[k] = al[k];
         }
         __syncthreads();
+        // each tile row's 8 x 72 values, contiguous in the output, leave as
+        // 16-byte stores
         constexpr int RV = FT * 72 / 4;  // float4 per tile row
         for (int i = threadIdx.x; i < FT * RV; i += FNW * 64) {
             const int row = i / RV, c = i - row * RV;
             ((float4 *)(zb + ((size_t)(y0 + row) * W + x0) * 72))[c] = ((const float4 *)(s_z + row * FT * 72))[c];
         }
+    }
+    return s_z;
+}
+
+// ---------------------------------------- network pass + learned stage
+// The learned stage (learned-stage kernels, MODE 0, HLLE) on the FT x FT tile
+// at (x0, y0), in the workgroup that has just computed z on the tile and its
+// low halo (s_z, [(FT+1)^2][72] from (x0 - 1, y0 - 1)) and kept the stage
+// input with a 3-cell halo (qf, [3][FT+6][FT+6] from (x0 - 3, y0 - 3)): one x
+// face, one y face and one cell per thread, the face and cell arithmetic of
+// the learned-stage kernels; each face projects its owner's coefficients
+// (alpha = base + P z, the network pass's operation order).  STAGE 1: S1 = q + dt L(q); STAGE 2: S2 = q/2 +
+// (S1 + dt L(S1))/2.  Stage flags and fallback counts as there.
+template <int STAGE>
+__device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &it, const float *s_z, const float *qf,
+                                                 const Proj &pr, const int x0, const int y0)
+{
+    constexpr int TX = FT, TY = FT, QS = FT + 6, FO = FT + 1;
+    constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX, YB = 128;  // y faces start at thread YB
+    static_assert(NFX <= YB && YB + NFY <= FNW * 64 && TX * TY <= FNW * 64, "one face or cell per thread");
+    constexpr float a0 = STAGE == 1 ? 0.0f : 0.5f, a1 = STAGE == 1 ? 1.0f : 0.5f;
+    __shared__ float s_fx[3][TY][TX + 1];
+    __shared__ float s_fy[3][TY + 1][TX];
+    __shared__ int s_cnt;
+    __shared__ int s_bad;
+    const int tid = threadIdx.x;
+    const int nx = d.nx;
+    const size_t plane = (size_t)nx * d.ny;
+    int *bad = d.flags + it.parity;
+    Phys<float> ph;
+    ph.g = d.g;
+    ph.sqg = d.sqg;
+    ph.gamma = 1.4f;
+    ph.h0 = d.h0;
+    const float dt = d.dt[0];
+    // stage 2 of a solve whose stage 1 failed is evaluated (its result is
+    // discarded by the redo) but its fallback faces are not counted
+    const bool count = !(STAGE == 2 && (*bad & 1));
+    if (tid == 0) {
+        s_cnt = 0;
+        s_bad = 0;
+    }
+    int nfb = 0;
+    if (tid < NFX) {
+        // x face: owner cell (x0 - 1 + xi, y0 + xj)
+        const int xj = tid / (TX + 1), xi = tid - xj * (TX + 1);
+        float st[3][6];
+#pragma unroll
+        for (int v = 0; v < 3; v++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) st[v][k] = qf[(v * QS + xj + 3) * QS + xi + k];
+        float QL[3], QR[3], F[3];
+        const int c = face_states<0, false>(st, s_z + ((xj + 1) * FO + xi) * 72, pr, QL, QR);
+        if (xi < TX) nfb += c;  // each face counted once: as the left face of a cell of this tile
+        flux3<fvk::HLLE, 0>(QL, QR, ph, F);
+#pragma unroll
+        for (int v = 0; v < 3; v++) s_fx[v][xj][xi] = F[v];
+    }
+    if (tid >= YB && tid < YB + NFY) {
+        // y face: owner cell (x0 + yi, y0 - 1 + yj)
+        const int f = tid - YB, yj = f / TX, yi = f - yj * TX;
+        float st[3][6];
+#pragma unroll
+        for (int v = 0; v < 3; v++)
+#pragma unroll
+            for (int k = 0; k < 6; k++) st[v][k] = qf[(v * QS + yj + k) * QS + yi + 3];
+        float QL[3], QR[3], F[3];
+        const int c = face_states<0, false>(st, s_z + (yj * FO + yi + 1) * 72 + 36, pr, QL, QR);
+        if (yj < TY) nfb += c;
+        flux3<fvk::HLLE, 1>(QL, QR, ph, F);
+#pragma unroll
+        for (int v = 0; v < 3; v++) s_fy[v][yj][yi] = F[v];
+    }
+    __syncthreads();
+    bool bc = false;
+    if (tid < TX * TY) {
+        const int cy = tid / TX, cx = tid - cy * TX;
+        const size_t idx = (size_t)(y0 + cy) * nx + x0 + cx;
+        const float *q0 = d.q;
+        float *out = STAGE == 1 ? d.s1 : d.s2;
+        float qn[3];
+#pragma unroll
+        for (int v = 0; v < 3; v++) {
+            float L = -(s_fx[v][cy][cx + 1] - s_fx[v][cy][cx]) * d.rdx - (s_fy[v][cy + 1][cx] - s_fy[v][cy][cx]) * d.rdy;
+            float o = a1 * (qf[(v * QS + cy + 3) * QS + cx + 3] + dt * L);
+            if (a0 != 0.0f) o = a0 * q0[idx + v * plane] + o;
+            out[idx + v * plane] = o;
+            qn[v] = o;
+        }
+        const bool ok = qn[0] > 0.0f && __builtin_isfinite(qn[0]) && __builtin_isfinite(qn[1]) && __builtin_isfinite(qn[2]);
+        bc = !ok;
+    }
+    if (count && nfb) atomicAdd(&s_cnt, nfb);
+    if (bc) s_bad = 1;
+    __syncthreads();
+    if (tid == 0) {
+        if (s_cnt) atomicAdd(d.nfb, (unsigned long long)s_cnt);
+        if (s_bad) atomicOr(bad, STAGE);
+    }
+}
+
+// Network pass and learned stage of one step's stage for the listed solves:
+// workgroups stride over the lists' network tiles (FT x FT); each computes
+// z on its tile and low halo and runs the learned stage on the tile, so the
+// coefficients never leave LDS.  ntiles == 0: the tile count is read from the list
+// header (nitems[1]; graph replay).
+template <int STAGE>
+__global__ __launch_bounds__(FNW * 64) void conv_learned_batch_kernel(const LSolve *__restrict__ tab,
+                                                                      const LItem *__restrict__ items,
+                                                                      const int *__restrict__ nitems, int ntiles,
+                                                                      int one, const char *P, Packed pk, Norm nrm,
+                                                                      Proj pr)
+{
+    constexpr int QS = FT + 6;
+    __shared__ float s_qf[3 * QS * QS];
+    const int total = ntiles > 0 ? ntiles : nitems[1];
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const bool first = w == (int)blockIdx.x;
+        if (!first) __syncthreads();  // the previous tile's LDS reads are done
+        LItem it;
+        if (one) {
+            it = items[0];
+        } else {
+            const int n = *nitems;
+            int lo = 0, hi = n - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (items[mid].tb_cnn <= w) lo = mid;
+                else hi = mid - 1;
+            }
+            it = items[lo];
+        }
+        const LSolve &d = tab[it.solve];
+        const int tile = w - it.tb_cnn, tx_n = d.nx / FT;
+        const int ty = tile / tx_n, tx = tile - ty * tx_n;
+        const float *s_z = fused_tile<FT + 1, OUT_Z_LDS>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx,
+                                                             ty * FT, tx * FT, pr, first, s_qf);
+        learned_epilogue<STAGE>(d, it, s_z, s_qf, pr, tx * FT, ty * FT);
     }
 }
 
@@ -579,8 +747,14 @@ int fused_max_grid()
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, conv_fused_batch_kernel<2>, FNW * 64, 0) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, conv_fused_kernel<true>, FNW * 64, 0) != hipSuccess)
             return 256;
+        int e = 0, f = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, conv_learned_batch_kernel<1>, FNW * 64, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, conv_learned_batch_kernel<2>, FNW * 64, 0) != hipSuccess)
+            return 256;
         int m = a < b ? a : b;
         m = m < c ? m : c;
+        m = m < e ? m : e;
+        m = m < f ? m : f;
         cache[dev] = (m > 0 ? m : 1) * (cus > 0 ? cus : 256);
     }
     return cache[dev];
@@ -598,6 +772,35 @@ hipError_t launch_forward_batch(int stage, const void *packed, const Norm &nrm, 
     else
         hipLaunchKernelGGL(conv_fused_batch_kernel<2>, dim3(g), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
                            one, (const char *)packed, pk, nrm, pr);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_learned(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve *tab,
+                               const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const Packed pk = packed_layout();
+    const int cap = fused_max_grid(), g = ntiles < cap ? ntiles : cap;
+    if (stage == 1)
+        hipLaunchKernelGGL(conv_learned_batch_kernel<1>, dim3(g), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
+                           one, (const char *)packed, pk, nrm, pr);
+    else
+        hipLaunchKernelGGL(conv_learned_batch_kernel<2>, dim3(g), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
+                           one, (const char *)packed, pk, nrm, pr);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_learned_list(int stage, const void *packed, const Norm &nrm, const Proj &pr,
+                                    const LSolve *tab, const LItem *items, const int *list, int wgs, hipStream_t st)
+{
+    if (wgs <= 0) return hipErrorInvalidValue;
+    const Packed pk = packed_layout();
+    if (stage == 1)
+        hipLaunchKernelGGL(conv_learned_batch_kernel<1>, dim3(wgs), dim3(FNW * 64), 0, st, tab, items, list, 0, 0,
+                           (const char *)packed, pk, nrm, pr);
+    else
+        hipLaunchKernelGGL(conv_learned_batch_kernel<2>, dim3(wgs), dim3(FNW * 64), 0, st, tab, items, list, 0, 0,
+                           (const char *)packed, pk, nrm, pr);
     return hipGetLastError();
 }
 

@@ -613,9 +613,10 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
     const int fl = c.flux == FV_FLUX_RUSANOV ? 1 : 0;  // kernel flux ids: 0 HLLE, 1 Rusanov
     hipError_t e = hipSuccess;
     if (fl == 0 && c.nx % 8 == 0 && c.ny % 8 == 0) {
-        // the server's work-list kernels as a batch of one: six launches per
-        // step (network pass and learned stage twice, commit-or-redo, redo
-        // and bookkeeping), bit-identical to the same solve in a served mix
+        // the server's work-list kernels as a batch of one: four launches per
+        // step (network pass with the learned stage, twice; commit-or-redo;
+        // redo and bookkeeping), bit-identical to the same solve in a served
+        // mix
         const char *B = ws + L.lbatch;
         const auto *tab = (const cnn::LSolve *)(B + LB_TAB);
         const auto *items0 = (const cnn::LItem *)(B + LB_ITEMS);
@@ -623,10 +624,8 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
         const int tc = cnn::ltiles_cnn(c.nx, c.ny), ts = cnn::ltiles_st(c.nx, c.ny);
         for (int64_t k = 0; k < nsteps && e == hipSuccess; k++, s->lsteps++) {
             const cnn::LItem *it = items0 + (s->lsteps & 1);
-            e = cnn::launch_forward_batch(1, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
-            if (e == hipSuccess) e = cnn::launch_learned_batch(0, 1, tab, it, nit, ts, m->pr, s->stream, 1);
-            if (e == hipSuccess) e = cnn::launch_forward_batch(2, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
-            if (e == hipSuccess) e = cnn::launch_learned_batch(0, 2, tab, it, nit, ts, m->pr, s->stream, 1);
+            e = cnn::launch_conv_learned(1, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
+            if (e == hipSuccess) e = cnn::launch_conv_learned(2, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
             if (e == hipSuccess) e = cnn::launch_learned_batch(2, 0, tab, it, nit, ts, m->pr, s->stream, 1);
             if (e == hipSuccess) e = cnn::launch_learned_batch(3, 0, tab, it, nit, ts, m->pr, s->stream, 1);
         }

@@ -1,0 +1,83 @@
+// Face states and fluxes of the learned reconstruction (thesis section
+// 2.5.3, fourth approach), shared by the learned-stage kernels and the
+// network pass that runs a learned stage in the same workgroup.
+#pragma once
+
+#include "cnn_internal.hpp"
+#include "fv_device.hpp"
+
+namespace cnn {
+
+using fvk::Phys;
+using fvk::SweV;
+
+__device__ __forceinline__ int pwrap(int i, int n) { return ((i % n) + n) % n; }
+
+// Face states of one face from the six stencil values st[v][0..5] (cells
+// i-2..i+3 along the normal).  MODE 0: learned with fallback; MODE 1: MINMOD.
+// AL: zc already holds alpha = base + P z (projected by the network pass).
+template <int MODE, bool AL = false>
+__device__ __forceinline__ int face_states(const float (*st)[6], const float *zc, const Proj &pr, float *QL,
+                                           float *QR)
+{
+    float ML[3], MR[3];
+#pragma unroll
+    for (int v = 0; v < 3; v++) fvk::recon_pair<float, fvk::MINMOD>(st[v][1], st[v][2], st[v][3], st[v][4], ML[v], MR[v]);
+    bool okl = ML[0] > 0.0f, okr = MR[0] > 0.0f;
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        ML[v] = okl ? ML[v] : st[v][2];
+        MR[v] = okr ? MR[v] : st[v][3];
+    }
+    if (MODE == 1) {
+#pragma unroll
+        for (int v = 0; v < 3; v++) {
+            QL[v] = ML[v];
+            QR[v] = MR[v];
+        }
+        return 0;
+    }
+#pragma unroll
+    for (int s = 0; s < 2; s++) {
+#pragma unroll
+        for (int v = 0; v < 3; v++) {
+            const float *zz = zc + (s * 3 + v) * 6;
+            float acc = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 6; k++) {
+                float al;
+                if (AL) {
+                    al = zz[k];
+                } else {
+                    al = pr.base[s * 6 + k];
+#pragma unroll
+                    for (int j = 0; j < 6; j++) al += pr.P[k * 6 + j] * zz[j];
+                }
+                acc += al * st[v][k];
+            }
+            (s == 0 ? QL : QR)[v] = acc;
+        }
+    }
+    bool ll = QL[0] > 0.0f, lr = QR[0] > 0.0f;
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        QL[v] = ll ? QL[v] : ML[v];
+        QR[v] = lr ? QR[v] : MR[v];
+    }
+    return (ll ? 0 : 1) + (lr ? 0 : 1);
+}
+
+template <int FLUX, int AXIS>
+__device__ __forceinline__ void flux3(const float *QL, const float *QR, const Phys<float> &ph, float *F)
+{
+    constexpr int NM = AXIS == 0 ? 1 : 2, TM = AXIS == 0 ? 2 : 1;
+    float il = fvk::rcp(QL[0]), ir = fvk::rcp(QR[0]);
+    SweV<float> L{QL[0], QL[NM] * il, QL[TM] * il}, R{QR[0], QR[NM] * ir, QR[TM] * ir};
+    float G[3];
+    fvk::swe_numflux<float, FLUX>(L, R, ph, G);
+    F[0] = G[0];
+    F[NM] = G[1];
+    F[TM] = G[2];
+}
+
+}  // namespace cnn

@@ -365,19 +365,20 @@ hipError_t enqueue_steps(fv_server *s, int mask, int nsteps, const int *grids, c
                 }
             }
         if (!(mask & 4) || e != hipSuccess || (!rec && !lgrid_st[k])) continue;
-        // learned solves: every network pass of the step in one launch
+        // learned solves: the network pass and learned stage of every
+        // learned solve in one launch per stage, then commit-or-redo and redo
         const cnn::LItem *it = d_litems + (size_t)k * ncap;
         const int *hdr = d_lnitems + (size_t)k * LHDR;
-        const int mode[6] = {-1, 0, -1, 0, 2, 3}, stg[6] = {1, 1, 2, 2, 0, 0};
-        for (int j = 0; j < 6 && e == hipSuccess; j++) {
+        const int mode[4] = {-1, -1, 2, 3}, stg[4] = {1, 2, 0, 0};
+        for (int j = 0; j < 4 && e == hipSuccess; j++) {
             if (!rec) {
-                e = mode[j] < 0 ? cnn::launch_forward_batch(stg[j], m->packed, m->nrm, m->pr, ltab, it, hdr,
-                                                            lgrid_cnn[k], s->stream)
+                e = mode[j] < 0 ? cnn::launch_conv_learned(stg[j], m->packed, m->nrm, m->pr, ltab, it, hdr,
+                                                           lgrid_cnn[k], s->stream)
                                 : cnn::launch_learned_batch(mode[j], stg[j], ltab, it, hdr, lgrid_st[k], m->pr,
                                                             s->stream);
             } else {
-                e = mode[j] < 0 ? cnn::launch_forward_batch_list(stg[j], m->packed, m->nrm, m->pr, ltab, it, hdr, 1,
-                                                                 s->stream)
+                e = mode[j] < 0 ? cnn::launch_conv_learned_list(stg[j], m->packed, m->nrm, m->pr, ltab, it, hdr, 1,
+                                                                s->stream)
                                 : cnn::launch_learned_batch_list(mode[j], stg[j], ltab, it, hdr, 1, m->pr, s->stream);
                 if (e == hipSuccess) e = record(mode[j] < 0 ? 1 : 2, k);
             }
