@@ -68,7 +68,8 @@ hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, i
 // flat bed, fixed Delta t) for the work-list kernels.
 struct LSolve {
     float *q, *s1, *s2;      // state and stage buffers [3][n][n]
-    float *z;                // constrained coefficients [n][n][72]
+    float *z;                // constrained coefficients [n][n][72] of the separate network pass (NULL when
+                             // only the fused network pass and learned stage run)
     const float *dt;         // fixed step (device)
     int *flags;              // two per-step flag slots
     unsigned long long *nfb, *redone;

@@ -47,7 +47,7 @@ struct Req {
     int tiles_x = 0, tiles = 0;
     double sim_time = 0;
     size_t q_off, s1_off, bed_off, ctl_off, rates_off;
-    size_t s2_off, z_off, small_off;  // learned requests
+    size_t s2_off, small_off;  // learned requests
     int64_t fallback_faces = 0, redone_steps = 0;
     int nvar() const { return r.eqn == FV_EULER ? 4 : 3; }
     bool learned() const { return r.learned != 0; }
@@ -62,8 +62,8 @@ constexpr size_t LS_DT = 0, LS_FLAGS = 8, LS_NFB = 16, LS_REDONE = 24, LS_BYTES 
 size_t req_bytes(const fv_request *r)
 {
     size_t n2 = (size_t)r->n * r->n;
-    if (r->learned)  // q, S1, S2, alpha, control block, counters
-        return 3 * align256(3 * n2 * 4) + align256(n2 * cnn::COUT * 4) + fvk::CTL_BYTES + LS_BYTES;
+    if (r->learned)  // q, S1, S2, control block, counters (the coefficients stay on chip)
+        return 3 * align256(3 * n2 * 4) + fvk::CTL_BYTES + LS_BYTES;
     int nvar = r->eqn == FV_EULER ? 4 : 3;
     size_t b = 2 * align256(nvar * n2 * 4) + fvk::CTL_BYTES + fvk::RATE_BYTES;
     if (r->eqn == FV_SWE) b += align256(n2 * 4);
@@ -227,8 +227,7 @@ fv_status admit_learned(fv_server *s, Req *q, std::vector<Req *> &need_h0)
     q->q_off = q->off;
     q->s1_off = q->q_off + st;
     q->s2_off = q->s1_off + st;
-    q->z_off = q->s2_off + st;
-    q->ctl_off = q->z_off + align256(n2 * cnn::COUT * 4);
+    q->ctl_off = q->s2_off + st;
     q->small_off = q->ctl_off + fvk::CTL_BYTES;
     char *P = s->pool;
     char small[LS_BYTES];
@@ -245,7 +244,7 @@ fv_status admit_learned(fv_server *s, Req *q, std::vector<Req *> &need_h0)
     d.q = (float *)(P + q->q_off);
     d.s1 = (float *)(P + q->s1_off);
     d.s2 = (float *)(P + q->s2_off);
-    d.z = (float *)(P + q->z_off);
+    d.z = nullptr;  // the fused network pass and learned stage keep z in LDS
     d.dt = (const float *)(P + q->small_off + LS_DT);
     d.flags = (int *)(P + q->small_off + LS_FLAGS);
     d.nfb = (unsigned long long *)(P + q->small_off + LS_NFB);
