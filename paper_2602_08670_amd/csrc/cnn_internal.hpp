@@ -91,21 +91,14 @@ constexpr int LTILE_X = 32, LTILE_Y = 4;  // stage tile
 inline int ltiles_cnn(int nx, int ny) { return (nx / LTILE_CNN) * (ny / LTILE_CNN); }
 inline int ltiles_st(int nx, int ny) { return ((nx + LTILE_X - 1) / LTILE_X) * ((ny + LTILE_Y - 1) / LTILE_Y); }
 
-// Work-list launches over the listed solves (one != 0: exactly one solve,
-// tab[items[0].solve]).  Network pass: stage 1 reads q, stage 2 reads S1,
-// both write alpha to z.  Learned stage: mode 0 with stage 1 or 2, mode 2, 3
-// (as learned_stage), HLLE.
-hipError_t launch_forward_batch(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve *tab,
-                                const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one = 0);
+// Work-list launches of the learned stage's MODE 2 and 3 (as learned_stage,
+// HLLE) over the listed solves' stage tiles (one != 0: exactly one solve,
+// tab[items[0].solve]).  The list form is the one recorded in graphs: wgs
+// workgroups (set before each replay to the list's stage tiles), the tile
+// count read from the list header list = {items, network tiles, stage
+// tiles, 0}.
 hipError_t launch_learned_batch(int mode, int stage, const LSolve *tab, const LItem *items, const int *nitems,
                                 int ntiles, const Proj &pr, hipStream_t st, int one = 0);
-// The forms recorded in graphs: wgs workgroups (set before each replay: the
-// list's stage tiles, and for the network pass at most fused_max_grid()),
-// the tile counts read from the list header list = {items, network tiles,
-// stage tiles, 0}.  The network pass's workgroups stride over its tiles.
-hipError_t launch_forward_batch_list(int stage, const void *packed, const Norm &nrm, const Proj &pr,
-                                     const LSolve *tab, const LItem *items, const int *list, int wgs,
-                                     hipStream_t st);
 hipError_t launch_learned_batch_list(int mode, int stage, const LSolve *tab, const LItem *items, const int *list,
                                      int wgs, const Proj &pr, hipStream_t st);
 // Workgroups of the tiled network pass resident at once on the current
@@ -113,11 +106,12 @@ hipError_t launch_learned_batch_list(int mode, int stage, const LSolve *tab, con
 // staging the weights once.
 int fused_max_grid();
 // Network pass and learned stage (MODE 0) of one stage in one launch over the
-// listed solves' network tiles (the coefficients stay in LDS; nx, ny multiples of
-// LTILE_CNN): stage 1 writes S1 from q, stage 2 writes S2 from S1 and q.
-// Same results as launch_forward_batch followed by launch_learned_batch
+// listed solves' network tiles (the coefficients stay in LDS; nx, ny
+// multiples of LTILE_CNN): stage 1 writes S1 from q, stage 2 writes S2 from
+// S1 and q; the same results as the network pass followed by learned_stage
 // MODE 0.  The list form is the one recorded in graphs (wgs set before each
-// replay to at most fused_max_grid()).
+// replay to at most fused_max_grid(), the network tile count read from the
+// list header).
 hipError_t launch_conv_learned(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve *tab,
                                const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one = 0);
 hipError_t launch_conv_learned_list(int stage, const void *packed, const Norm &nrm, const Proj &pr,
