@@ -317,7 +317,9 @@ fv_status fv_coarsen(const float *fine, int nvar, int nx, int ny, int factor, fl
  * all active solves of an equation type; for the learned solves each step
  * is four batched launches (per stage, one launch runs the network pass
  * (BF16 MFMA) and the learned stage of every learned solve, the
- * coefficients staying on chip; then commit-or-redo and redo).  A round's launches are recorded once, per kinds of work present
+ * coefficients staying on chip; then commit-or-redo and redo), or, in rounds
+ * with many learned tiles (learned_split), six (the network pass and the
+ * learned stage as separate launches).  A round's launches are recorded once, per kinds of work present
  * and number of steps, into a hipGraph that every later round replays: the
  * kernels read their tile counts from the device work-lists, and between
  * replays the host rewrites those lists and sets each launch's grid to its
@@ -336,6 +338,12 @@ typedef struct {
                                 every launch within it; a request that alone needs more is rejected */
     const fv_model *model;   /* network of the learned requests (NULL: none accepted); its
                                 packed weights must be ready (its stream synchronised) */
+    int32_t learned_split;   /* network tiles (8 x 8 cells) in a round's first step from which the
+                                round runs the network pass and the learned stage as separate
+                                launches (throughput) instead of one launch per stage that keeps
+                                the coefficients on chip (latency); 0: 4 x the workgroups of the
+                                network pass resident at once.  Same results either way. */
+    int32_t reserved1;       /* must be 0 */
 } fv_server_config;
 
 typedef struct {

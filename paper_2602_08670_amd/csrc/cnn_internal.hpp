@@ -68,8 +68,7 @@ hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, i
 // flat bed, fixed Delta t) for the work-list kernels.
 struct LSolve {
     float *q, *s1, *s2;      // state and stage buffers [3][n][n]
-    float *z;                // constrained coefficients [n][n][72] of the separate network pass (NULL when
-                             // only the fused network pass and learned stage run)
+    float *z;                // constrained coefficients [n][n][72] of the separate network pass
     const float *dt;         // fixed step (device)
     int *flags;              // two per-step flag slots
     unsigned long long *nfb, *redone;
@@ -91,14 +90,22 @@ constexpr int LTILE_X = 32, LTILE_Y = 4;  // stage tile
 inline int ltiles_cnn(int nx, int ny) { return (nx / LTILE_CNN) * (ny / LTILE_CNN); }
 inline int ltiles_st(int nx, int ny) { return ((nx + LTILE_X - 1) / LTILE_X) * ((ny + LTILE_Y - 1) / LTILE_Y); }
 
-// Work-list launches of the learned stage's MODE 2 and 3 (as learned_stage,
-// HLLE) over the listed solves' stage tiles (one != 0: exactly one solve,
-// tab[items[0].solve]).  The list form is the one recorded in graphs: wgs
-// workgroups (set before each replay to the list's stage tiles), the tile
-// count read from the list header list = {items, network tiles, stage
-// tiles, 0}.
+// Work-list launches over the listed solves (one != 0: exactly one solve,
+// tab[items[0].solve]).  Network pass: stage 1 reads q, stage 2 reads S1,
+// both write alpha to z; its workgroups (at most fused_max_grid()) stride
+// over the network tiles.  Learned stage: MODE 0 with stage 1 or 2 (reads
+// alpha from z), MODE 2, 3 (as learned_stage), HLLE, over the stage tiles.
+hipError_t launch_forward_batch(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve *tab,
+                                const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one = 0);
 hipError_t launch_learned_batch(int mode, int stage, const LSolve *tab, const LItem *items, const int *nitems,
                                 int ntiles, const Proj &pr, hipStream_t st, int one = 0);
+// The forms recorded in graphs: wgs workgroups (set before each replay: the
+// list's stage tiles, and for the network pass at most fused_max_grid()),
+// the tile counts read from the list header list = {items, network tiles,
+// stage tiles, 0}.
+hipError_t launch_forward_batch_list(int stage, const void *packed, const Norm &nrm, const Proj &pr,
+                                     const LSolve *tab, const LItem *items, const int *list, int wgs,
+                                     hipStream_t st);
 hipError_t launch_learned_batch_list(int mode, int stage, const LSolve *tab, const LItem *items, const int *list,
                                      int wgs, const Proj &pr, hipStream_t st);
 // Workgroups of the tiled network pass resident at once on the current

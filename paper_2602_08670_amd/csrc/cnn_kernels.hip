@@ -356,6 +356,41 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_kernel(const float *q, co
     }
 }
 
+// Work-list form: workgroup w finds its solve by binary search over the
+// items' first network tile.  STAGE 1 reads q, STAGE 2 reads S1.  ntiles ==
+// 0: the tile count is read from the list header (nitems[1]; graph replay).
+template <int STAGE>
+__global__ __launch_bounds__(FNW * 64) void conv_fused_batch_kernel(const LSolve *__restrict__ tab,
+                                                                    const LItem *__restrict__ items,
+                                                                    const int *__restrict__ nitems, int ntiles,
+                                                                    int one, const char *P, Packed pk, Norm nrm,
+                                                                    Proj pr)
+{
+    const int total = ntiles > 0 ? ntiles : nitems[1];
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const bool first = w == (int)blockIdx.x;
+        if (!first) __syncthreads();  // the previous tile's LDS reads are done
+        LItem it;
+        if (one) {
+            it = items[0];
+        } else {
+            const int n = *nitems;
+            int lo = 0, hi = n - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (items[mid].tb_cnn <= w) lo = mid;
+                else hi = mid - 1;
+            }
+            it = items[lo];
+        }
+        const LSolve &d = tab[it.solve];
+        const int tile = w - it.tb_cnn, tx_n = d.nx / FT;
+        const int ty = tile / tx_n, tx = tile - ty * tx_n;
+        fused_tile<FT, OUT_ALPHA>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, d.z, d.ny, d.nx, ty * FT, tx * FT, pr, first,
+                                  nullptr);
+    }
+}
+
 template <int FO, int OUT>
 __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
                                              int H, int W, int y0, int x0, const Proj &pr, bool load_w, float *qf)
@@ -711,12 +746,48 @@ int fused_max_grid()
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, conv_learned_batch_kernel<1>, FNW * 64, 0) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, conv_learned_batch_kernel<2>, FNW * 64, 0) != hipSuccess)
             return 256;
+        int f = 0, h = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, conv_fused_batch_kernel<1>, FNW * 64, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&h, conv_fused_batch_kernel<2>, FNW * 64, 0) != hipSuccess)
+            return 256;
         int m = a < b ? a : b;
         m = m < c ? m : c;
         m = m < e ? m : e;
+        m = m < f ? m : f;
+        m = m < h ? m : h;
         cache[dev] = (m > 0 ? m : 1) * (cus > 0 ? cus : 256);
     }
     return cache[dev];
+}
+
+hipError_t launch_forward_batch(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve *tab,
+                                const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one)
+{
+    if (ntiles <= 0) return hipSuccess;
+    const Packed pk = packed_layout();
+    const int cap = fused_max_grid(), g = ntiles < cap ? ntiles : cap;
+    if (stage == 1)
+        hipLaunchKernelGGL(conv_fused_batch_kernel<1>, dim3(g), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
+                           one, (const char *)packed, pk, nrm, pr);
+    else
+        hipLaunchKernelGGL(conv_fused_batch_kernel<2>, dim3(g), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
+                           one, (const char *)packed, pk, nrm, pr);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_batch_list(int stage, const void *packed, const Norm &nrm, const Proj &pr,
+                                     const LSolve *tab, const LItem *items, const int *list, int wgs,
+                                     hipStream_t st)
+{
+    if (wgs <= 0) return hipErrorInvalidValue;
+    const Packed pk = packed_layout();
+    if (stage == 1)
+        hipLaunchKernelGGL(conv_fused_batch_kernel<1>, dim3(wgs), dim3(FNW * 64), 0, st, tab, items, list, 0, 0,
+                           (const char *)packed, pk, nrm, pr);
+    else
+        hipLaunchKernelGGL(conv_fused_batch_kernel<2>, dim3(wgs), dim3(FNW * 64), 0, st, tab, items, list, 0, 0,
+                           (const char *)packed, pk, nrm, pr);
+    return hipGetLastError();
 }
 
 hipError_t launch_conv_learned(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve *tab,

@@ -613,19 +613,28 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
     const int fl = c.flux == FV_FLUX_RUSANOV ? 1 : 0;  // kernel flux ids: 0 HLLE, 1 Rusanov
     hipError_t e = hipSuccess;
     if (fl == 0 && c.nx % 8 == 0 && c.ny % 8 == 0) {
-        // the server's work-list kernels as a batch of one: four launches per
-        // step (network pass with the learned stage, twice; commit-or-redo;
-        // redo and bookkeeping), bit-identical to the same solve in a served
-        // mix
+        // the server's work-list kernels as a batch of one, chosen by the
+        // server's default rule: four launches per step (network pass with
+        // the learned stage, twice; commit-or-redo; redo and bookkeeping), or,
+        // for grids of at least 4 x the network pass's resident workgroups in
+        // tiles, the network pass and the learned stage as separate launches;
+        // bit-identical to the same solve in a served mix
         const char *B = ws + L.lbatch;
         const auto *tab = (const cnn::LSolve *)(B + LB_TAB);
         const auto *items0 = (const cnn::LItem *)(B + LB_ITEMS);
         const int *nit = (const int *)(B + LB_N);
         const int tc = cnn::ltiles_cnn(c.nx, c.ny), ts = cnn::ltiles_st(c.nx, c.ny);
+        const bool split = tc >= 4 * cnn::fused_max_grid();
         for (int64_t k = 0; k < nsteps && e == hipSuccess; k++, s->lsteps++) {
             const cnn::LItem *it = items0 + (s->lsteps & 1);
-            e = cnn::launch_conv_learned(1, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
-            if (e == hipSuccess) e = cnn::launch_conv_learned(2, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
+            for (int stage = 1; stage <= 2 && e == hipSuccess; stage++) {
+                if (!split) {
+                    e = cnn::launch_conv_learned(stage, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
+                } else {
+                    e = cnn::launch_forward_batch(stage, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
+                    if (e == hipSuccess) e = cnn::launch_learned_batch(0, stage, tab, it, nit, ts, m->pr, s->stream, 1);
+                }
+            }
             if (e == hipSuccess) e = cnn::launch_learned_batch(2, 0, tab, it, nit, ts, m->pr, s->stream, 1);
             if (e == hipSuccess) e = cnn::launch_learned_batch(3, 0, tab, it, nit, ts, m->pr, s->stream, 1);
         }

@@ -199,8 +199,10 @@ __global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
 
 // Work-list form over a table of solves of any size (serving, and single
 // solves as a batch of one): workgroup w finds its solve by binary search
-// over the items' first stage tile.  MODE 2 and 3: the end of a learned
-// step (commit or plain stage 1; plain stage 2 and bookkeeping).  ntiles == 0: the tile count is read from the list header (nitems[2]; graph
+// over the items' first stage tile.  MODE 0 with STAGE 1 or 2 (the learned
+// stage after a separate network pass that wrote alpha to z), MODE 2 and 3
+// (the end of a learned step: commit or plain stage 1; plain stage 2 and
+// bookkeeping).  ntiles == 0: the tile count is read from the list header (nitems[2]; graph
 // replay).
 template <int MODE, int STAGE>
 __global__ __launch_bounds__(256) void learned_batch_kernel(const LSolve *__restrict__ tab,
@@ -247,10 +249,11 @@ __global__ __launch_bounds__(256) void learned_batch_kernel(const LSolve *__rest
     a.pr = pr;
     a.commit_src = d.s2;
     a.commit_dst = d.q;
-    static_assert(MODE == 2 || MODE == 3, "the end of a learned step");
-    if (MODE == 3) {
+    if (MODE == 0 && STAGE == 2) {
+        a.qs = d.s1; a.q0 = d.q; a.out = d.s2; a.a0 = 0.5f; a.a1 = 0.5f;
+    } else if (MODE == 3) {
         a.qs = d.s1; a.q0 = d.q; a.out = d.q; a.a0 = 0.5f; a.a1 = 0.5f;
-    } else {  // MODE 2: q -> S1
+    } else {  // MODE 0 stage 1, MODE 2: q -> S1
         a.qs = d.q; a.q0 = d.q; a.out = d.s1; a.a0 = 0.0f; a.a1 = 1.0f;
     }
     const int tile = w - it.tb_st;
@@ -263,8 +266,9 @@ static hipError_t learned_batch_go(int mode, int stage, dim3 g, const LSolve *ta
                                    const int *nitems, int ntiles, int one, const Proj &pr, hipStream_t st)
 {
     const dim3 b(256);
-    (void)stage;
-    if (mode == 2) hipLaunchKernelGGL((learned_batch_kernel<2, 0>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
+    if (mode == 0 && stage == 1) hipLaunchKernelGGL((learned_batch_kernel<0, 1>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
+    else if (mode == 0 && stage == 2) hipLaunchKernelGGL((learned_batch_kernel<0, 2>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
+    else if (mode == 2) hipLaunchKernelGGL((learned_batch_kernel<2, 0>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
     else if (mode == 3) hipLaunchKernelGGL((learned_batch_kernel<3, 0>), g, b, 0, st, tab, items, nitems, ntiles, one, pr);
     else return hipErrorInvalidValue;
     return hipGetLastError();

@@ -47,7 +47,7 @@ struct Req {
     int tiles_x = 0, tiles = 0;
     double sim_time = 0;
     size_t q_off, s1_off, bed_off, ctl_off, rates_off;
-    size_t s2_off, small_off;  // learned requests
+    size_t s2_off, z_off, small_off;  // learned requests
     int64_t fallback_faces = 0, redone_steps = 0;
     int nvar() const { return r.eqn == FV_EULER ? 4 : 3; }
     bool learned() const { return r.learned != 0; }
@@ -62,8 +62,8 @@ constexpr size_t LS_DT = 0, LS_FLAGS = 8, LS_NFB = 16, LS_REDONE = 24, LS_BYTES 
 size_t req_bytes(const fv_request *r)
 {
     size_t n2 = (size_t)r->n * r->n;
-    if (r->learned)  // q, S1, S2, control block, counters (the coefficients stay on chip)
-        return 3 * align256(3 * n2 * 4) + fvk::CTL_BYTES + LS_BYTES;
+    if (r->learned)  // q, S1, S2, alpha (rounds with the separate network pass), control block, counters
+        return 3 * align256(3 * n2 * 4) + align256(n2 * cnn::COUT * 4) + fvk::CTL_BYTES + LS_BYTES;
     int nvar = r->eqn == FV_EULER ? 4 : 3;
     size_t b = 2 * align256(nvar * n2 * 4) + fvk::CTL_BYTES + fvk::RATE_BYTES;
     if (r->eqn == FV_SWE) b += align256(n2 * 4);
@@ -112,6 +112,7 @@ struct fv_server {
     std::map<int, RoundGraph> graphs;
     int64_t rounds = 0, replays = 0, grid_updates = 0;
     int cnn_cap = 256;  // most workgroups of a network-pass launch
+    int split_at = 1024;  // network tiles from which a round's learned steps use separate launches
     double launch_s = 0, wait_s = 0;  // host time enqueueing rounds' work, and waiting for it
     double capture_s = 0;             // host time capturing and instantiating graphs
 
@@ -178,6 +179,7 @@ fv_status validate(const fv_server_config *c)
         return fail(FV_E_INVALID, "max_solves, steps_per_round and max_items must be >= 1");
     if (c->max_items > (uint64_t)1 << 31) return fail(FV_E_INVALID, "max_items above 2^31");
     if (c->direct != 0 && c->direct != 1) return fail(FV_E_INVALID, "direct must be 0 or 1");
+    if (c->learned_split < 0 || c->reserved1 != 0) return fail(FV_E_INVALID, "learned_split < 0 or reserved1 != 0");
     return FV_OK;
 }
 
@@ -227,7 +229,8 @@ fv_status admit_learned(fv_server *s, Req *q, std::vector<Req *> &need_h0)
     q->q_off = q->off;
     q->s1_off = q->q_off + st;
     q->s2_off = q->s1_off + st;
-    q->ctl_off = q->s2_off + st;
+    q->z_off = q->s2_off + st;
+    q->ctl_off = q->z_off + align256(n2 * cnn::COUT * 4);
     q->small_off = q->ctl_off + fvk::CTL_BYTES;
     char *P = s->pool;
     char small[LS_BYTES];
@@ -244,7 +247,7 @@ fv_status admit_learned(fv_server *s, Req *q, std::vector<Req *> &need_h0)
     d.q = (float *)(P + q->q_off);
     d.s1 = (float *)(P + q->s1_off);
     d.s2 = (float *)(P + q->s2_off);
-    d.z = nullptr;  // the fused network pass and learned stage keep z in LDS
+    d.z = (float *)(P + q->z_off);
     d.dt = (const float *)(P + q->small_off + LS_DT);
     d.flags = (int *)(P + q->small_off + LS_FLAGS);
     d.nfb = (unsigned long long *)(P + q->small_off + LS_NFB);
@@ -320,7 +323,8 @@ fv_status admit(fv_server *s, Req *q, std::vector<Req *> &need_h0)
 }
 
 // Launches of steps 0..nsteps-1 of a round over the uploaded lists, kinds
-// of work in mask (1 SWE, 2 Euler, 4 learned).  rec == NULL: direct launches
+// of work in mask (1 SWE, 2 Euler, 4 learned, 8 learned steps with the
+// network pass and the learned stage as separate launches).  rec == NULL: direct launches
 // of one workgroup per tile with the given per-list tile counts, empty lists
 // skipped.  rec != NULL (graph capture): every launch of the mask, the tile
 // counts read from the list headers, each node recorded in rec; its grid is
@@ -365,21 +369,30 @@ hipError_t enqueue_steps(fv_server *s, int mask, int nsteps, const int *grids, c
             }
         if (!(mask & 4) || e != hipSuccess || (!rec && !lgrid_st[k])) continue;
         // learned solves: the network pass and learned stage of every
-        // learned solve in one launch per stage, then commit-or-redo and redo
+        // learned solve in one launch per stage (coefficients on chip), or,
+        // with mask bit 8, a network-pass launch writing alpha and a
+        // learned-stage launch per stage; then commit-or-redo and redo.
+        // Kind -2: fused pass, -1: network pass, >= 0: learned-stage mode.
         const cnn::LItem *it = d_litems + (size_t)k * ncap;
         const int *hdr = d_lnitems + (size_t)k * LHDR;
-        const int mode[4] = {-1, -1, 2, 3}, stg[4] = {1, 2, 0, 0};
-        for (int j = 0; j < 4 && e == hipSuccess; j++) {
+        const bool split = mask & 8;
+        const int fmode[4] = {-2, -2, 2, 3}, fstg[4] = {1, 2, 0, 0};
+        const int smode[6] = {-1, 0, -1, 0, 2, 3}, sstg[6] = {1, 1, 2, 2, 0, 0};
+        const int nl = split ? 6 : 4;
+        for (int j = 0; j < nl && e == hipSuccess; j++) {
+            const int md = split ? smode[j] : fmode[j], sg = split ? sstg[j] : fstg[j];
             if (!rec) {
-                e = mode[j] < 0 ? cnn::launch_conv_learned(stg[j], m->packed, m->nrm, m->pr, ltab, it, hdr,
-                                                           lgrid_cnn[k], s->stream)
-                                : cnn::launch_learned_batch(mode[j], stg[j], ltab, it, hdr, lgrid_st[k], m->pr,
-                                                            s->stream);
+                if (md == -2) e = cnn::launch_conv_learned(sg, m->packed, m->nrm, m->pr, ltab, it, hdr, lgrid_cnn[k],
+                                                           s->stream);
+                else if (md == -1) e = cnn::launch_forward_batch(sg, m->packed, m->nrm, m->pr, ltab, it, hdr,
+                                                                 lgrid_cnn[k], s->stream);
+                else e = cnn::launch_learned_batch(md, sg, ltab, it, hdr, lgrid_st[k], m->pr, s->stream);
             } else {
-                e = mode[j] < 0 ? cnn::launch_conv_learned_list(stg[j], m->packed, m->nrm, m->pr, ltab, it, hdr, 1,
-                                                                s->stream)
-                                : cnn::launch_learned_batch_list(mode[j], stg[j], ltab, it, hdr, 1, m->pr, s->stream);
-                if (e == hipSuccess) e = record(mode[j] < 0 ? 1 : 2, k);
+                if (md == -2) e = cnn::launch_conv_learned_list(sg, m->packed, m->nrm, m->pr, ltab, it, hdr, 1, s->stream);
+                else if (md == -1) e = cnn::launch_forward_batch_list(sg, m->packed, m->nrm, m->pr, ltab, it, hdr, 1,
+                                                                      s->stream);
+                else e = cnn::launch_learned_batch_list(md, sg, ltab, it, hdr, 1, m->pr, s->stream);
+                if (e == hipSuccess) e = record(md < 0 ? 1 : 2, k);
             }
         }
     }
@@ -390,7 +403,7 @@ hipError_t enqueue_steps(fv_server *s, int mask, int nsteps, const int *grids, c
 // instantiated on first use.
 fv_status round_graph(fv_server *s, int mask, int nsteps, RoundGraph **out)
 {
-    const int key = mask | nsteps << 3;
+    const int key = mask | nsteps << 4;
     auto f = s->graphs.find(key);
     if (f != s->graphs.end()) {
         *out = &f->second;
@@ -479,6 +492,7 @@ fv_status fv_server_create(const fv_server_config *cfg, void *pool, size_t pool_
         return hip_fail(e, "pinned work-list buffers");
     }
     if (cfg->model) s->cnn_cap = cnn::fused_max_grid();
+    s->split_at = cfg->learned_split > 0 ? cfg->learned_split : 4 * s->cnn_cap;
     if (!stream) {
         // graphs cannot be captured on the null stream: the server then
         // runs on a stream of its own (default priority)
@@ -648,6 +662,10 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
         if (m) nsteps = k + 1;
         mask |= m;
     }
+    // many learned tiles: separate network-pass and learned-stage launches
+    // (the network pass then strides over tiles at full occupancy of the
+    // learned stage); few: one launch per stage, coefficients on chip
+    if ((mask & 4) && lgrid_cnn[0] >= s->split_at) mask |= 8;
     for (size_t li = 0; li < counts.size(); li++) {
         s->h_nitems[li * HDR] = counts[li];
         s->h_nitems[li * HDR + 1] = grids[li];

@@ -65,7 +65,7 @@ class fv_train_config(ctypes.Structure):
 class fv_server_config(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_solves", ctypes.c_int32),
                 ("steps_per_round", ctypes.c_int32), ("direct", ctypes.c_int32), ("max_items", ctypes.c_uint64),
-                ("model", ctypes.c_void_p)]
+                ("model", ctypes.c_void_p), ("learned_split", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
 
 
 class fv_request(ctypes.Structure):
@@ -434,16 +434,21 @@ class Server:
     """Continuous-batching server over a torch-allocated device pool."""
 
     def __init__(self, pool_bytes: int, max_solves: int = 1024, steps_per_round: int = 24,
-                 max_items: int = 1 << 18, device="cuda", stream=None, model=None, direct=False):
+                 max_items: int = 1 << 18, device="cuda", stream=None, model=None, direct=False,
+                 learned_split: int = 0):
         """direct: launch every kernel of a round directly instead of replaying
-        the round's captured graph (same results)."""
+        the round's captured graph (same results).  learned_split: network
+        tiles in a round's first step from which the round runs the network
+        pass and the learned stage as separate launches (0: the library's
+        default)."""
         import torch
 
         self.model = model  # kept alive while the server runs
         if model is not None:
             torch.cuda.synchronize()  # the model's packed weights are ready
         self.cfg = fv_server_config(ctypes.sizeof(fv_server_config), max_solves, steps_per_round,
-                                    1 if direct else 0, max_items, None if model is None else model.h)
+                                    1 if direct else 0, max_items, None if model is None else model.h,
+                                    int(learned_split), 0)
         # zero-filled: the pool's pages are mapped here rather than by the
         # first rounds that reach them
         self.pool = torch.zeros(pool_bytes, dtype=torch.uint8, device=device)

@@ -230,3 +230,46 @@ def test_graph_replay_equals_direct_launches(fv):
         assert np.array_equal(g[0], d[0]), spec
         assert g[1:] == d[1:], spec
     m.close()
+
+
+def test_learned_split_and_fused_rounds_agree(fv):
+    """The two launch forms of a learned step -- the network pass and the
+    learned stage fused per stage with the coefficients in LDS, or separate
+    launches with alpha through HBM -- give the same bits (state, time,
+    fallback and redo counts), so a server may pick either per round."""
+    from paper_2602_08670_amd import learned_solver as LS
+
+    # zero last-layer weights and large per-channel biases: constant
+    # coefficients far from the constraint set, so many face sides fall back
+    rng = np.random.default_rng(7)
+    vec = (rng.standard_normal(49448) * 0.02).astype(np.float32)
+    vec[-72 - 72 * 288:-72] = 0.0
+    vec[-72:] = rng.uniform(-400, 400, 72).astype(np.float32)
+    m = fv.Model(vec, fv.make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0)))
+    dt = LS.fine_dt(2048) * 32
+    specs = [(32, 1, 13), (64, 2, 9), (128, 3, 7), (256, 4, 5)]
+    runs = []
+    for split in (1, 1 << 30):
+        srv = fv.Server(1 << 30, max_solves=8, steps_per_round=4, max_items=1 << 16, model=m, learned_split=split)
+        ids = []
+        for n, seed, steps in specs:
+            q = I.random_smooth_swe(n, seed=seed).astype(np.float32)
+            ids.append((srv.submit(q, steps, learned=True, dt_fixed=dt), q.shape))
+        rounds = 0
+        while srv.round() != (0, 0):
+            rounds += 1
+            assert rounds < 100
+        out = []
+        for rid, shape in ids:
+            inf = srv.info(rid)
+            out.append((srv.result(rid, shape), inf.state, inf.sim_time, inf.fallback_faces, inf.redone_steps))
+        srv.close()
+        runs.append(out)
+    fb = [o[3] for o in runs[0]]
+    print(f"[serve split] fallback faces per request {fb}", flush=True)
+    assert sum(fb) > 0  # the comparison covers fallback faces
+    for spec, a, b in zip(specs, runs[0], runs[1]):
+        assert a[1] in (2, 3), spec
+        assert np.array_equal(a[0], b[0], equal_nan=True), spec
+        assert a[1:] == b[1:], spec
+    m.close()
