@@ -272,4 +272,21 @@ def test_learned_split_and_fused_rounds_agree(fv):
         assert a[1] in (2, 3), spec
         assert np.array_equal(a[0], b[0], equal_nan=True), spec
         assert a[1:] == b[1:], spec
+    # the single-solve step picks its form by the same rule (256^2 and up:
+    # separate launches) and matches both
+    done = 0
+    for (n, seed, steps), a in zip(specs, runs[0]):
+        if a[1] != 2:
+            continue  # a failed solve reports an error alone; its served state was compared above
+        done += 1
+        q = I.random_smooth_swe(n, seed=seed).astype(np.float32)
+        s = fv.Solver(q, prec=fv.FV_F32, dt_fixed=dt, learned=1)
+        fbs, red = s.learned_step(m, steps)
+        ref = s.state().astype(np.float32)
+        t, _ = s.time()
+        s.close()
+        assert np.array_equal(a[0], ref, equal_nan=True), n
+        assert (a[2], a[3], a[4]) == (t, fbs, red), n
+    print(f"[serve split] states {[o[1] for o in runs[0]]}, {done} compared with the solve alone", flush=True)
+    assert runs[0][-1][1] == 2  # the 256^2 solve (separate launches alone) is among them
     m.close()
