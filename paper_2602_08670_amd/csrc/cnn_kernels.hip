@@ -455,13 +455,9 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
             }
         }
     }
-    if (load_w) {
-        c0.store(s_wall);
-        c1.store(s_wall + W0);
-        c2.store(s_wall + W0 + WH);
-        c3.store(s_wall + W0 + 2 * WH);
-        c4.store(s_wall + W0 + 3 * WH);
-    }
+    // layer 0's weights now; the others after layers 0 and 1, so that their
+    // loads complete behind layer 0's arithmetic
+    if (load_w) c0.store(s_wall);
     __syncthreads();
 
     // layer 0 on the FR0_ x FR0_ region, 16 pixels per group
@@ -501,8 +497,17 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
         }
     }
     // hidden layers 1..3: s_a0 -> s_a1 -> s_a0 -> s_a1
+#pragma unroll
     for (int l = 1; l < 4; l++) {
-        __syncthreads();  // previous layer's output written
+        if (load_w && l == 1) {
+            c1.store(s_wall + W0);
+            c2.store(s_wall + W0 + WH);
+        }
+        if (load_w && l == 2) {
+            c3.store(s_wall + W0 + 2 * WH);
+            c4.store(s_wall + W0 + 3 * WH);
+        }
+        __syncthreads();  // previous layer's output (and this layer's weights) written
         const int rin = FR0_ - 2 * (l - 1);
         const bf16x8 *in = (l & 1) ? s_a0 : s_a1;
         bf16 *out = (bf16 *)((l & 1) ? s_a1 : s_a0);
