@@ -253,6 +253,52 @@ constexpr int FW_EL = 9 * 5 * 16 * 32;  // largest packed weight block (layer 4)
 // reuses them for all its pixel groups; only B is read per group and tap.
 constexpr int FNW = 8;  // waves per workgroup of the fused pass
 
+// NG pixel groups gi, gi + FNW, ... of a hidden layer with both co tiles:
+// 2 NG accumulation chains advanced together.
+template <int NG>
+__device__ __forceinline__ void hidden_groups(const bf16x8 *in, int rin, bf16 *out, const bf16x8 (*A)[2],
+                                              const float (*bs)[4], int gi, int rout, int npx, int g, int px)
+{
+    constexpr int NT = 2;
+    int p[NG], bo[NG];
+#pragma unroll
+    for (int k = 0; k < NG; k++) {
+        p[k] = (gi + k * FNW) * 16 + px;
+        const int pc = p[k] < npx ? p[k] : 0;
+        const int py = pc / rout, pxx = pc - py * rout;
+        bo[k] = (py * rin + pxx) * 4 + g;
+    }
+    floatx4 acc[NG][NT];
+#pragma unroll
+    for (int k = 0; k < NG; k++)
+#pragma unroll
+        for (int t = 0; t < NT; t++) acc[k][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; tap++) {
+        const int tb = ((tap / 3) * rin + tap % 3) * 4;
+#pragma unroll
+        for (int k = 0; k < NG; k++) {
+            const bf16x8 bx = in[bo[k] + tb];
+#pragma unroll
+            for (int t = 0; t < NT; t++)
+                acc[k][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[tap][t], bx, acc[k][t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < NG; k++) {
+        if (p[k] < npx) {
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const int co0 = 16 * t + 4 * g;
+                bf16x4 o;
+#pragma unroll
+                for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[k][t][i] + bs[t][i], 0.0f);
+                *(bf16x4 *)(out + (size_t)p[k] * 32 + co0) = o;
+            }
+        }
+    }
+}
+
 __device__ __forceinline__ void fused_hidden(const bf16x8 *in, int rin, bf16 *out, const bf16x8 *w, const float *bias,
                                              int wave, int lane)
 {
@@ -269,30 +315,12 @@ __device__ __forceinline__ void fused_hidden(const bf16x8 *in, int rin, bf16 *ou
     for (int t = 0; t < NT; t++)
 #pragma unroll
         for (int i = 0; i < 4; i++) bs[t][i] = bias[16 * t + 4 * g + i];
-    for (int gi = wave; gi < ngrp; gi += FNW) {
-        const int p = gi * 16 + px;
-        const bool valid = p < npx;
-        const int pc = valid ? p : 0;
-        const int py = pc / rout, pxx = pc - py * rout;
-        floatx4 acc[NT];
-#pragma unroll
-        for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int tap = 0; tap < 9; tap++) {
-            const bf16x8 bx = in[((py + tap / 3) * rin + pxx + tap % 3) * 4 + g];
-#pragma unroll
-            for (int t = 0; t < NT; t++) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[tap][t], bx, acc[t], 0, 0, 0);
-        }
-        if (valid) {
-#pragma unroll
-            for (int t = 0; t < NT; t++) {
-                const int co0 = 16 * t + 4 * g;
-                bf16x4 o;
-#pragma unroll
-                for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[t][i] + bs[t][i], 0.0f);
-                *(bf16x4 *)(out + (size_t)p * 32 + co0) = o;
-            }
-        }
+    // groups gi and gi + FNW of this wave together (wave-uniform test, a
+    // real branch: an MFMA does not honour a partial EXEC), their four
+    // chains advanced tap by tap; each chain's taps keep their order
+    for (int gi = wave; gi < ngrp; gi += 2 * FNW) {
+        if (gi + FNW < ngrp) hidden_groups<2>(in, rin, out, A, bs, gi, rout, npx, g, px);
+        else hidden_groups<1>(in, rin, out, A, bs, gi, rout, npx, g, px);
     }
 }
 
@@ -464,27 +492,36 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     {
         const float *bias = (const float *)(P + pk.b[0]);
         const bf16x8 A0 = s_wall[px * 4 + g], A1 = s_wall[(16 + px) * 4 + g];
-        constexpr int NP0 = FR0_ * FR0_, NG0 = (NP0 + 15) / 16;
-        for (int gi = wave; gi < NG0; gi += FNW) {
-            const int p = gi * 16 + px;
-            const bool valid = p < NP0;
-            const int pc = valid ? p : 0;
+        constexpr int NP0 = FR0_ * FR0_, NG0 = (NP0 + 15) / 16, KG = (NG0 + FNW - 1) / FNW;
+        // all KG groups gi = wave + k FNW of this wave at once (a group past
+        // the region computes on pixel 0 and stores nothing), so that every
+        // operand read is issued before the MFMAs
+        bf16x8 bx[KG];
+        int pk_[KG];
+#pragma unroll
+        for (int k = 0; k < KG; k++) {
+            const int p = (wave + k * FNW) * 16 + px;
+            pk_[k] = p;
+            const int pc = p < NP0 ? p : 0;
             const int py = pc / FR0_, pxx = pc - py * FR0_;
-            bf16x8 bx;
 #pragma unroll
             for (int e = 0; e < 8; e++) {
-                const int k = 8 * g + e;
+                const int kk = 8 * g + e;
                 bf16 v = (bf16)0.0f;
-                if (k < 27) {
-                    const int tap = k / 3, ci = k - 3 * tap;
+                if (kk < 27) {
+                    const int tap = kk / 3, ci = kk - 3 * tap;
                     v = s_in[ci][(py + tap / 3) * FRI_ + pxx + tap % 3];
                 }
-                bx[e] = v;
+                bx[k][e] = v;
             }
+        }
+#pragma unroll
+        for (int k = 0; k < KG; k++) {
             floatx4 acc[2] = {floatx4{0.f, 0.f, 0.f, 0.f}, floatx4{0.f, 0.f, 0.f, 0.f}};
-            acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, bx, acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, bx, acc[1], 0, 0, 0);
-            if (valid) {
+            acc[0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A0, bx[k], acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A1, bx[k], acc[1], 0, 0, 0);
+            const int p = pk_[k];
+            if (p < NP0) {
 #pragma unroll
                 for (int t = 0; t < 2; t++) {
                     const int co0 = 16 * t + 4 * g;
@@ -515,8 +552,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     }
     __syncthreads();
     // layer 4: s_a1 (FO + 2)^2 -> z on the FO x FO region: NG pixel groups x
-    // 5 co tiles of accumulation chains of 9 taps, chain c = (group c % NG,
-    // co tile c / NG), dealt to the waves in turn
+    // 5 co tiles of accumulation chains of 9 taps
     const bf16x8 *s_w = s_wall + W0 + 3 * WH;
     // [FO*FO][72] over the activations (modes that stage z in LDS; the
     // weights stay for the workgroup's next tile): it covers s_a0 and the
@@ -526,41 +562,39 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     static_assert(FO * FO * 72 * 4 <= sizeof(s_act), "coefficient region fits over the activations");
     constexpr bool ALPHA = OUT != OUT_Z;  // z staged in LDS
     {
-        constexpr int NT = 5, RIN = FO + 2, NPX = FO * FO, NG = (NPX + 15) / 16, NCH = NG * NT;
-        constexpr int CPW = (NCH + FNW - 1) / FNW;  // chains per wave
+        // wave w < NG: pixel group w with all NT co tiles, its activation
+        // fragment read once per tap for NT MFMAs; each co tile's chain keeps
+        // the tap order 0..8
+        constexpr int NT = 5, RIN = FO + 2, NPX = FO * FO, NG = (NPX + 15) / 16;
+        static_assert(NG <= FNW, "one pixel group per wave");
         const float *bias = (const float *)(P + pk.b[4]);
-        floatx4 acc[CPW];
+        floatx4 acc[NT];
 #pragma unroll
-        for (int j = 0; j < CPW; j++) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+        const int p = wave * 16 + px;
+        if (wave < NG) {  // wave-uniform, a real branch: an MFMA does not honour a partial EXEC
+            const int pc = p < NPX ? p : 0;
+            const int py = pc / FO, pxx = pc - py * FO;
+            const int bo = (py * RIN + pxx) * 4 + g;
 #pragma unroll
-        for (int j = 0; j < CPW; j++) {
-            const int c = wave + j * FNW;
-            if (c < NCH) {  // wave-uniform
-                const int gi = c % NG, t = c / NG;
-                const int p = gi * 16 + px;
-                const int pc = p < NPX ? p : 0;
-                const int py = pc / FO, pxx = pc - py * FO;
+            for (int tap = 0; tap < 9; tap++) {
+                const bf16x8 bx = s_a1[bo + ((tap / 3) * RIN + tap % 3) * 4];
 #pragma unroll
-                for (int tap = 0; tap < 9; tap++) {
-                    const bf16x8 bx = s_a1[((py + tap / 3) * RIN + pxx + tap % 3) * 4 + g];
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * 4 + g], bx,
-                                                                     acc[j], 0, 0, 0);
-                }
+                for (int t = 0; t < NT; t++)
+                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * 4 + g], bx,
+                                                                     acc[t], 0, 0, 0);
             }
         }
         if (ALPHA) __syncthreads();  // every wave past its layer-4 reads of s_a1 before it holds z
+        if (wave < NG && p < NPX) {
+            const int py = p / FO, pxx = p - py * FO;
 #pragma unroll
-        for (int j = 0; j < CPW; j++) {
-            const int c = wave + j * FNW;
-            if (c < NCH) {
-                const int gi = c % NG, t = c / NG;
+            for (int t = 0; t < NT; t++) {
                 const int co0 = 16 * t + 4 * g;
-                const int p = gi * 16 + px;
-                if (co0 < 72 && p < NPX) {
-                    const int py = p / FO, pxx = p - py * FO;
+                if (co0 < 72) {
                     floatx4 o;
 #pragma unroll
-                    for (int i = 0; i < 4; i++) o[i] = acc[j][i] + bias[co0 + i];
+                    for (int i = 0; i < 4; i++) o[i] = acc[t][i] + bias[co0 + i];
                     if (ALPHA) *(floatx4 *)(s_z + p * 72 + co0) = o;
                     else *(floatx4 *)(zb + ((size_t)(y0 + py) * W + x0 + pxx) * 72 + co0) = o;
                 }
