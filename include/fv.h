@@ -383,6 +383,8 @@ typedef struct {
     double host_launch_s;    /* host seconds spent enqueueing rounds' launches (or graphs) */
     double host_wait_s;      /* host seconds spent waiting for rounds' work to finish */
     double host_capture_s;   /* host seconds spent capturing and instantiating graphs */
+    double host_admit_s;     /* host seconds spent admitting requests (uploads, first CFL rates) */
+    double host_retire_s;    /* host seconds spent copying back finished requests */
 } fv_server_stats;
 
 /* Pool bytes taken by the server's tables (solve table, work-lists). */

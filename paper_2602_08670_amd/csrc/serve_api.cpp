@@ -115,6 +115,7 @@ struct fv_server {
     int split_at = 1024;  // network tiles from which a round's learned steps use separate launches
     double launch_s = 0, wait_s = 0;  // host time enqueueing rounds' work, and waiting for it
     double capture_s = 0;             // host time capturing and instantiating graphs
+    double admit_s = 0, retire_s = 0;  // host time admitting requests and retiring finished ones
 
     double now() const
     {
@@ -546,6 +547,7 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
     const int K = s->cfg.steps_per_round;
     char *P = s->pool;
     // ---- admission (FIFO, later requests may pass one that does not fit)
+    const double ta0 = s->now();
     std::vector<Req *> admitted, need_h0;
     // tiles per launch of each kind (plain SWE, Euler, learned network pass,
     // learned stage): a request is admitted only while its launches stay
@@ -615,6 +617,7 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
                                hipMemcpyHostToDevice, s->stream);
         if (e != hipSuccess) return hip_fail(e, "solve table upload");
     }
+    s->admit_s += s->now() - ta0;
     // ---- work-lists of the round: one list per [step][type] (type 0 = SWE,
     // 1 = Euler) of the solves still running at that step, packed back to
     // back; tiles per launch are capped by max_items
@@ -749,6 +752,7 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
         q->slot = -1;
         it = s->active.erase(it);
     }
+    s->retire_s += s->now() - tnow;
     if (n_active) *n_active = (int32_t)s->active.size();
     if (n_queued) *n_queued = (int32_t)s->queue.size();
     return FV_OK;
@@ -765,6 +769,8 @@ fv_status fv_server_get_stats(fv_server *s, fv_server_stats *out)
     out->host_launch_s = s->launch_s;
     out->host_wait_s = s->wait_s;
     out->host_capture_s = s->capture_s;
+    out->host_admit_s = s->admit_s;
+    out->host_retire_s = s->retire_s;
     return FV_OK;
 }
 

@@ -85,7 +85,8 @@ class fv_request_info(ctypes.Structure):
 class fv_server_stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("graph_replays", ctypes.c_int64), ("grid_updates", ctypes.c_int64),
                 ("graphs_captured", ctypes.c_int32), ("pad", ctypes.c_int32), ("host_launch_s", ctypes.c_double),
-                ("host_wait_s", ctypes.c_double), ("host_capture_s", ctypes.c_double)]
+                ("host_wait_s", ctypes.c_double), ("host_capture_s", ctypes.c_double),
+                ("host_admit_s", ctypes.c_double), ("host_retire_s", ctypes.c_double)]
 
 
 def make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0), order=1, hidden=32) -> fv_model_desc:
