@@ -1062,28 +1062,43 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const bf16 *G, const bf16 *I
     if (tid < NCO) pp[9 * NCO * CI + tid] = bacc;
 }
 
-// grads[W_l, b_l] += sum over blocks (in block order) of the partials.
-__global__ void wgrad_reduce_kernel(const float *partial, int nblocks, int NCO, int CI, int co_real, int ci_real,
-                                    int woff, int boff, float *grads)
+// grads[W_l, b_l] += sum over blocks of the partials.  A workgroup owns 64
+// consecutive entries; its wave w sums the partials of blocks w, w + 16,
+// w + 32, ... in that order and wave 0 adds the sixteen wave sums in wave
+// order: the order is fixed, independent of scheduling.
+constexpr int RED_WAVES = 16;
+__global__ __launch_bounds__(RED_WAVES * 64) void wgrad_reduce_kernel(const float *partial, int nblocks, int NCO,
+                                                                      int CI, int co_real, int ci_real, int woff,
+                                                                      int boff, float *grads)
 {
+    __shared__ float red[RED_WAVES][64];
     const int per = 9 * NCO * CI + NCO;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < per; e += gridDim.x * blockDim.x) {
-        int co, ci = 0, tap = 0;
-        bool isb = e >= 9 * NCO * CI;
-        if (isb) {
-            co = e - 9 * NCO * CI;
-        } else {
-            tap = e / (NCO * CI);
-            int r = e - tap * NCO * CI;
-            co = r / CI;
-            ci = r - co * CI;
-        }
-        if (co >= co_real || ci >= ci_real) continue;
-        float s = 0.0f;
-        for (int k = 0; k < nblocks; k++) s += partial[(size_t)k * per + e];
-        if (isb) grads[boff + co] += s;
-        else grads[woff + (co * ci_real + ci) * 9 + tap] += s;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + lane;
+    float s = 0.0f;
+    if (e < per) {
+#pragma unroll 4
+        for (int k = wave; k < nblocks; k += RED_WAVES) s += partial[(size_t)k * per + e];
     }
+    red[wave][lane] = s;
+    __syncthreads();
+    if (wave != 0 || e >= per) return;
+    float t = 0.0f;
+#pragma unroll
+    for (int w = 0; w < RED_WAVES; w++) t += red[w][lane];
+    int co, ci = 0, tap = 0;
+    const bool isb = e >= 9 * NCO * CI;
+    if (isb) {
+        co = e - 9 * NCO * CI;
+    } else {
+        tap = e / (NCO * CI);
+        int r = e - tap * NCO * CI;
+        co = r / CI;
+        ci = r - co * CI;
+    }
+    if (co >= co_real || ci >= ci_real) return;
+    if (isb) grads[boff + co] += t;
+    else grads[woff + (co * ci_real + ci) * 9 + tap] += t;
 }
 
 static int ppb_for(long npix)
@@ -1111,7 +1126,7 @@ static void wgrad(const bf16 *G, const bf16 *In, int B, int H, int W, float *par
     int nblocks = (int)((npix + ppb - 1) / ppb);
     hipLaunchKernelGGL((wgrad_kernel<CG, CO_T, CI>), dim3(nblocks), dim3(256), 0, st, G, In, B, H, W, ppb, partial);
     int per = 9 * CO_T * 16 * CI + CO_T * 16;
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((per + 255) / 256), dim3(256), 0, st, (const float *)partial, nblocks,
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((per + 63) / 64), dim3(RED_WAVES * 64), 0, st, (const float *)partial, nblocks,
                        CO_T * 16, CI, co_real, ci_real, woff, boff, grads);
 }
 

@@ -27,13 +27,20 @@ __global__ __launch_bounds__(256) void loss_kernel(const float *pred, const floa
     if (threadIdx.x == 0) partials[blockIdx.x] = s[0];
 }
 
-__global__ void loss_final_kernel(const double *partials, int nblocks, double *loss_acc)
+// loss_acc += sum of the block partials: thread i adds partials i, i + 256,
+// ... in order, then a fixed tree over the 256 thread sums.
+__global__ __launch_bounds__(256) void loss_final_kernel(const double *partials, int nblocks, double *loss_acc)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double t = 0.0;
-        for (int b = 0; b < nblocks; b++) t += partials[b];
-        *loss_acc += t;
+    __shared__ double s[256];
+    double t = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += 256) t += partials[b];
+    s[threadIdx.x] = t;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+        __syncthreads();
     }
+    if (threadIdx.x == 0) *loss_acc += s[0];
 }
 
 hipError_t launch_loss(const float *pred, const float *tgt, const float *scale3, int B, int nx, int ny, float *G,
@@ -43,7 +50,7 @@ hipError_t launch_loss(const float *pred, const float *tgt, const float *scale3,
     int blocks = (int)((n + 255) / 256);
     if (blocks > max_blocks) blocks = max_blocks;
     hipLaunchKernelGGL(loss_kernel, dim3(blocks), dim3(256), 0, st, pred, tgt, scale3, B, nx * ny, G, partials);
-    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(64), 0, st, (const double *)partials, blocks, loss_acc);
+    hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, (const double *)partials, blocks, loss_acc);
     return hipGetLastError();
 }
 
