@@ -35,7 +35,7 @@ struct AdjArgs {
     Phys<float> ph;
     Proj pr;
     const int *plain;   // per solve: 1 = this step ran the plain scheme (or NULL)
-    float *contrib;     // [2][B][ny][nx][18]
+    float *contrib;     // [2][B][ny][nx][ADJ_REC] (18 used)
     float *gz;          // [B][ny][nx][72]
 };
 
@@ -119,8 +119,18 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
         float al[2][3][6];
         float QS[2][3];
         bool useL[2] = {false, false};
-        const float *zc = a.z + ((size_t)b * plane + cell) * 72 + axis * 36;
         if (learned) {
+            // this face's 36 raw coefficients: nine 16-byte loads
+            float zc[36];
+            const float4 *z4 = (const float4 *)(a.z + ((size_t)b * plane + cell) * 72 + axis * 36);
+#pragma unroll
+            for (int q4 = 0; q4 < 9; q4++) {
+                const float4 t = z4[q4];
+                zc[4 * q4] = t.x;
+                zc[4 * q4 + 1] = t.y;
+                zc[4 * q4 + 2] = t.z;
+                zc[4 * q4 + 3] = t.w;
+            }
 #pragma unroll
             for (int s = 0; s < 2; s++)
 #pragma unroll
@@ -180,9 +190,9 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
             gQ[1][v] = sr;
         }
 
-        // stencil contributions and coefficient adjoints
-        float *co = a.contrib + (((size_t)axis * a.B + b) * plane + cell) * 18;
-        float *gzc = a.gz + ((size_t)b * plane + cell) * 72 + axis * 36;
+        // stencil contributions and coefficient adjoints, stored as 16-byte
+        // vectors (the record of a face is ADJ_REC floats)
+        float co[ADJ_REC], gzc[36];
 #pragma unroll
         for (int v = 0; v < 3; v++) {
 #pragma unroll
@@ -204,6 +214,16 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
                 }
             }
         }
+#pragma unroll
+        for (int k = 18; k < ADJ_REC; k++) co[k] = 0.f;
+        float4 *co4 = (float4 *)(a.contrib + (((size_t)axis * a.B + b) * plane + cell) * ADJ_REC);
+#pragma unroll
+        for (int q4 = 0; q4 < ADJ_REC / 4; q4++)
+            co4[q4] = make_float4(co[4 * q4], co[4 * q4 + 1], co[4 * q4 + 2], co[4 * q4 + 3]);
+        float4 *gz4 = (float4 *)(a.gz + ((size_t)b * plane + cell) * 72 + axis * 36);
+#pragma unroll
+        for (int q4 = 0; q4 < 9; q4++)
+            gz4[q4] = make_float4(gzc[4 * q4], gzc[4 * q4 + 1], gzc[4 * q4 + 2], gzc[4 * q4 + 3]);
     }
 }
 
@@ -225,7 +245,7 @@ __global__ __launch_bounds__(256) void adj_gather_kernel(float *out, const float
             for (int k = 0; k < 6; k++) {
                 // this cell is stencil entry k of the face owned by cell - (k - 2)
                 int own = axis == 0 ? y * nx + pw(x + 2 - k, nx) : pw(y + 2 - k, ny) * nx + x;
-                const float *co = contrib + (((size_t)axis * B + b) * plane + own) * 18;
+                const float *co = contrib + (((size_t)axis * B + b) * plane + own) * ADJ_REC;
 #pragma unroll
                 for (int v = 0; v < 3; v++) acc[v] += co[v * 6 + k];
             }

@@ -189,12 +189,15 @@ struct AdjStage {
     float rdx, rdy, g, h0;
     Proj pr;
     const int *plain;  // per solve: the step ran the plain scheme (or NULL)
-    float *contrib;    // scratch [2][B][ny][nx][18]
+    float *contrib;    // scratch [2][B][ny][nx][ADJ_REC]
     float *gz;         // [B][ny][nx][72]
     float *gqs;
     int accumulate;
 };
 hipError_t launch_adjoint(int flux, const AdjStage &s, hipStream_t st);
+// Floats per face in the adjoint's contribution scratch: 18 used, padded so
+// that a record is whole 16-byte vectors.
+constexpr int ADJ_REC = 20;
 
 // Backward of the network for B solves: adds d loss / d theta into grads
 // (master layout, FP32) and d loss / d q into dq ([B][3][ny][nx], FP32),

@@ -962,84 +962,141 @@ __global__ __launch_bounds__(256) void conv_dgrad_kernel(const bf16 *G, const bf
     }
 }
 
-// Weight and bias gradient of a convolution over a chunk of pixels:
+// Weight and bias gradient of a convolution over a range of pixels:
 //   dW[t][co][ci] += sum_p G[p][co] In[p + d_t][ci],  db[co] += sum_p G[p][co].
-// MFMA with K = pixels: both operands are staged transposed in LDS per 64
-// pixels (rows = channels, 64 pixels contiguous), so a fragment is one
-// 16-byte LDS read.  Each block writes its partial sums; a fixed-order
-// reduction adds the partials of all blocks.
+// MFMA with K = pixels.  Per 64-pixel chunk the block stages G and the nine
+// tap-shifted inputs transposed in LDS (rows = channels, 64 pixels
+// contiguous), so an operand fragment is one 16-byte LDS read.  Each thread
+// owns one staging job: eight consecutive pixels' eight channels of G or of
+// one tap's input (one 16-byte load per pixel; W % 16 == 0 keeps the eight in
+// one image row, so only the first and last can wrap), transposed in
+// registers and written as eight 16-byte rows.  The loads run WG_PD chunks
+// ahead of the MFMAs; a thread's pixel position advances by 64 per chunk
+// without divisions.  The bias is one more MFMA per co tile against a
+// fragment whose column 0 is all ones.  Each block writes its partial sums;
+// a fixed-order reduction adds the partials of all blocks.
+constexpr int WG_PD = 2;
+template <int CO_T, int CI>
+struct WgradShape {
+    static constexpr int NCO = CO_T * 16;
+    static constexpr int JG = 8 * (NCO / 8);          // G jobs per chunk (pixel octet, channel octet)
+    static constexpr int NJ = JG + 9 * 8 * (CI / 8);  // plus the input jobs of the nine taps
+    static constexpr int NW = (NJ + 63) / 64;         // waves per block
+};
+
 template <int CG, int CO_T, int CI>
-__global__ __launch_bounds__(256) void wgrad_kernel(const bf16 *G, const bf16 *In, int B, int H, int W, int ppb,
-                                                    float *partial)
+__global__ __launch_bounds__((WgradShape<CO_T, CI>::NW * 64)) void wgrad_kernel(const bf16 *G, const bf16 *In, int B,
+                                                                                int H, int W, int ppb, float *partial)
 {
+    using S = WgradShape<CO_T, CI>;
     constexpr int CI_T = CI / 16;
-    constexpr int NCO = CO_T * 16;
+    constexpr int NCO = S::NCO, JG = S::JG, NJ = S::NJ, NW = S::NW;
     constexpr int NTILE = CO_T * CI_T;
-    constexpr int TPW = (NTILE + 3) / 4;
+    constexpr int TPW = (NTILE + NW - 1) / NW;
     constexpr int LD = 72;  // row stride in BF16 (64 pixels + pad, 16-byte multiple)
-    __shared__ bf16 sG[NCO * LD];
-    __shared__ bf16 sI[CI * LD];
+    __shared__ bf16x8 sG[NCO * LD / 8];
+    __shared__ bf16x8 sI[9 * CI * LD / 8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, r16 = lane & 15;
-    const long npix = (long)B * H * W;
+    const int npix = B * H * W;  // <= 2^30 (checked by the caller)
     const int hw = H * W;
-    floatx4 acc[TPW][9];
+
+    floatx4 acc[TPW][9], accb[TPW];
 #pragma unroll
-    for (int j = 0; j < TPW; j++)
+    for (int j = 0; j < TPW; j++) {
+        accb[j] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 9; t++) acc[j][t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    float bacc = 0.0f;
-    const long pbeg = (long)blockIdx.x * ppb;
-    for (int sub = 0; sub < ppb; sub += 64) {
-        const long base = pbeg + sub;
-        if (base >= npix) break;
-        __syncthreads();
-        // G chunk, transposed: sG[co][px]
-        for (int i = tid; i < 64 * (NCO / 8); i += 256) {
-            int pxl = i / (NCO / 8), c8 = i - pxl * (NCO / 8);
-            long p = base + pxl;
-            bf16x8 v;
-            if (p < npix) v = *(const bf16x8 *)(G + (size_t)p * CG + c8 * 8);
-            else
-                for (int e = 0; e < 8; e++) v[e] = (bf16)0.0f;
+    }
+    bf16x8 ones;
 #pragma unroll
-            for (int e = 0; e < 8; e++) sG[(c8 * 8 + e) * LD + pxl] = v[e];
-        }
-        __syncthreads();
-        if (tid < NCO) {
-            float s = 0.0f;
-            for (int k = 0; k < 64; k++) s += (float)sG[tid * LD + k];
-            bacc += s;
-        }
-        for (int tap = 0; tap < 9; tap++) {
-            const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-            __syncthreads();
-            for (int i = tid; i < 64 * (CI / 8); i += 256) {
-                int pxl = i / (CI / 8), c8 = i - pxl * (CI / 8);
-                long p = base + pxl;
-                bf16x8 v;
-                if (p < npix) {
-                    int b = (int)(p / hw), rem = (int)(p - (long)b * hw);
-                    int y = rem / W, x = rem - y * W;
-                    int yy = wrap(y + dy, H), xx = wrap(x + dx, W);
-                    v = *(const bf16x8 *)(In + ((size_t)b * hw + yy * W + xx) * CI + c8 * 8);
-                } else {
-                    for (int e = 0; e < 8; e++) v[e] = (bf16)0.0f;
-                }
+    for (int e = 0; e < 8; e++) ones[e] = (bf16)(r16 == 0 ? 1.0f : 0.0f);
+
+    const int pbeg = blockIdx.x * ppb;
+    const int pend = ppb < npix - pbeg ? pbeg + ppb : npix;
+    const int nch = pend > pbeg ? (pend - pbeg + 63) / 64 : 0;
+
+    // this thread's job
+    const bool isG = tid < JG, active = tid < NJ;
+    const int jj = tid - JG;
+    const int tap = isG ? 0 : jj / (8 * (CI / 8));
+    const int po = isG ? (tid & 7) : (jj - tap * (8 * (CI / 8))) & 7;
+    const int c8 = isG ? (tid >> 3) : (jj - tap * (8 * (CI / 8))) >> 3;
+    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
+    bf16x8 *const dst = isG ? sG + (c8 * 8) * (LD / 8) + po : sI + (tap * CI + c8 * 8) * (LD / 8) + po;
+    // first pixel of the octet the next load reads, and its (solve, row, column)
+    int p = pbeg + po * 8;
+    int b = p / hw, y = (p - b * hw) / W;
+    int x = p - b * hw - y * W;
+
+    bf16x8 v[WG_PD][8];
+    auto load = [&](bf16x8 *r) {
+        if (active) {
+            if (isG) {
+                const bf16 *src = G + (size_t)p * CG + c8 * 8;
 #pragma unroll
-                for (int e = 0; e < 8; e++) sI[(c8 * 8 + e) * LD + pxl] = v[e];
+                for (int i = 0; i < 8; i++) r[i] = *(const bf16x8 *)(src + i * CG);
+            } else {
+                const int yy = wrap(y + dy, H), x0 = x + dx;
+                const bf16 *row = In + ((size_t)b * hw + (size_t)yy * W) * CI + c8 * 8;
+                r[0] = *(const bf16x8 *)(row + (x0 < 0 ? W - 1 : x0) * CI);
+#pragma unroll
+                for (int i = 1; i < 7; i++) r[i] = *(const bf16x8 *)(row + (x0 + i) * CI);
+                r[7] = *(const bf16x8 *)(row + (x0 + 7 >= W ? 0 : x0 + 7) * CI);
             }
+        }
+        p += 64;
+        x += 64;
+        while (x >= W) {
+            x -= W;
+            if (++y == H) {
+                y = 0;
+                ++b;
+            }
+        }
+    };
+    auto store = [&](const bf16x8 *r) {
+        if (!active) return;
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            bf16x8 w;
+#pragma unroll
+            for (int i = 0; i < 8; i++) w[i] = r[i][c];
+            dst[c * (LD / 8)] = w;
+        }
+    };
+
+#pragma unroll
+    for (int k = 0; k < WG_PD; k++)
+        if (k < nch) load(v[k]);
+    for (int c0 = 0; c0 < nch; c0 += WG_PD) {
+#pragma unroll
+        for (int k = 0; k < WG_PD; k++) {
+            const int ch = c0 + k;
+            if (ch >= nch) break;
+            if (ch > 0) __syncthreads();  // the previous chunk's MFMAs have read the tiles
+            store(v[k]);
             __syncthreads();
+            if (ch + WG_PD < nch) load(v[k]);
+            // a tile's twenty operand reads are all issued before its MFMAs
 #pragma unroll
             for (int j = 0; j < TPW; j++) {
-                const int id = wave + 4 * j;
+                const int id = wave + NW * j;
                 if (id < NTILE) {
                     const int cot = id / CI_T, cit = id - cot * CI_T;
+                    bf16x8 af[2], bf[2][9];
 #pragma unroll
                     for (int ks = 0; ks < 2; ks++) {
-                        bf16x8 af = *(const bf16x8 *)(sG + (cot * 16 + r16) * LD + ks * 32 + 8 * g);
-                        bf16x8 bf = *(const bf16x8 *)(sI + (cit * 16 + r16) * LD + ks * 32 + 8 * g);
-                        acc[j][tap] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf, acc[j][tap], 0, 0, 0);
+                        af[ks] = sG[(cot * 16 + r16) * (LD / 8) + ks * 4 + g];
+#pragma unroll
+                        for (int t = 0; t < 9; t++) bf[ks][t] = sI[(t * CI + cit * 16 + r16) * (LD / 8) + ks * 4 + g];
+                    }
+#pragma unroll
+                    for (int ks = 0; ks < 2; ks++) {
+#pragma unroll
+                        for (int t = 0; t < 9; t++)
+                            acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks], bf[ks][t], acc[j][t], 0, 0, 0);
+                        if (cit == 0) accb[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks], ones, accb[j], 0, 0, 0);
                     }
                 }
             }
@@ -1049,17 +1106,20 @@ __global__ __launch_bounds__(256) void wgrad_kernel(const bf16 *G, const bf16 *I
     float *pp = partial + (size_t)blockIdx.x * (9 * NCO * CI + NCO);
 #pragma unroll
     for (int j = 0; j < TPW; j++) {
-        const int id = wave + 4 * j;
+        const int id = wave + NW * j;
         if (id < NTILE) {
             const int cot = id / CI_T, cit = id - cot * CI_T;
 #pragma unroll
-            for (int tap = 0; tap < 9; tap++)
+            for (int t = 0; t < 9; t++)
 #pragma unroll
                 for (int i = 0; i < 4; i++)
-                    pp[((size_t)tap * NCO + cot * 16 + 4 * g + i) * CI + cit * 16 + r16] = acc[j][tap][i];
+                    pp[((size_t)t * NCO + cot * 16 + 4 * g + i) * CI + cit * 16 + r16] = acc[j][t][i];
+            if (cit == 0 && r16 == 0) {
+#pragma unroll
+                for (int i = 0; i < 4; i++) pp[9 * NCO * CI + cot * 16 + 4 * g + i] = accb[j][i];
+            }
         }
     }
-    if (tid < NCO) pp[9 * NCO * CI + tid] = bacc;
 }
 
 // grads[W_l, b_l] += sum over blocks of the partials.  A workgroup owns 64
@@ -1124,7 +1184,8 @@ static void wgrad(const bf16 *G, const bf16 *In, int B, int H, int W, float *par
     long npix = (long)B * H * W;
     int ppb = ppb_for(npix);
     int nblocks = (int)((npix + ppb - 1) / ppb);
-    hipLaunchKernelGGL((wgrad_kernel<CG, CO_T, CI>), dim3(nblocks), dim3(256), 0, st, G, In, B, H, W, ppb, partial);
+    hipLaunchKernelGGL((wgrad_kernel<CG, CO_T, CI>), dim3(nblocks), dim3(WgradShape<CO_T, CI>::NW * 64), 0, st, G, In,
+                       B, H, W, ppb, partial);
     int per = 9 * CO_T * 16 * CI + CO_T * 16;
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((per + 63) / 64), dim3(RED_WAVES * 64), 0, st, (const float *)partial, nblocks,
                        CO_T * 16, CI, co_real, ci_real, woff, boff, grads);
@@ -1138,6 +1199,9 @@ hipError_t launch_backward(const void *packed, const Norm &nrm, const float *q, 
     const MasterLayout ml = master_layout();
     const char *P = (const char *)packed;
     const long npix = (long)B * nx * ny;
+    // the weight-gradient staging takes whole 64-pixel chunks and pixel
+    // octets inside one image row
+    if (nx % 16 || npix % 64 || npix > (1L << 30)) return hipErrorInvalidValue;
     char *sc = (char *)scratch;
     bf16 *dz = (bf16 *)sc;
     sc += al256(npix * 96 * 2);

@@ -69,7 +69,7 @@ TrainLayout layout_of(const fv_train_config *c)
     L.gz = o;
     o += L.zb;
     L.contrib = o;
-    o += align256(npix * 2 * 18 * 4);
+    o += align256(npix * 2 * cnn::ADJ_REC * 4);
     L.G = o;
     o += L.st;
     L.Gn = o;

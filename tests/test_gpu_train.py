@@ -124,6 +124,43 @@ def test_gradients_bitwise_repeatable(fv, L):
     m.close()
 
 
+def test_gradients_batch_equals_mean_of_solves(fv, L):
+    """At 64^2 x 16 solves every weight-gradient block takes four 64-pixel
+    chunks (its loads for the next chunk overlap the current one's MFMAs);
+    alone, a solve's blocks take one.  The loss of eq 2.28 averages over the
+    batch, so the batch gradient is the mean of the sixteen single-solve
+    gradients: per pixel the two runs compute the same values, only the
+    order of the FP32 sums over pixels differs."""
+    n, B, T, dt = 64, 16, 2, 6.0e-4
+    p = params(L, 24)
+    q0 = torch.tensor(batch(n, B, 70), device="cuda")
+    tgt = torch.stack([q0 * 1.001, q0 * 0.999])
+    print(f"[gpu] train batch vs solves B={B} {n}x{n}", flush=True)
+    m = fv.Model(vec(fv, p), fv.make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0)))
+    tr = fv.Trainer(m, fv.make_train_config(B, n, n, T, dt))
+    lb, _ = tr.step(q0, tgt)
+    gb = tr.grads.double().cpu().numpy()
+    tr.close()
+    tr1 = fv.Trainer(m, fv.make_train_config(1, n, n, T, dt))
+    gs, ls = np.zeros_like(gb), 0.0
+    for b in range(B):
+        l1, _ = tr1.step(q0[b:b + 1].contiguous(), tgt[:, b:b + 1].contiguous())
+        gs += tr1.grads.double().cpu().numpy() / B
+        ls += l1 / B
+    tr1.close()
+    m.close()
+    rel = np.linalg.norm(gb - gs) / np.linalg.norm(gs)
+    print(f"[grad] batch loss {lb:.6e} mean {ls:.6e}; rel {rel:.2e}", flush=True)
+    assert abs(lb - ls) <= 1e-6 * ls
+    assert rel <= 1e-4
+    off = 0
+    for l in range(5):
+        k = p["w"][l].numel() + p["b"][l].numel()
+        a, o = gb[off:off + k], gs[off:off + k]
+        assert np.linalg.norm(a - o) <= 1e-4 * np.linalg.norm(o), l
+        off += k
+
+
 def test_adam_reduces_loss(fv, L):
     """A few Adam steps on one batch lower the unrolled loss."""
     n, B, T, dt = 32, 4, 3, 1.0e-3
