@@ -36,7 +36,7 @@ struct AdjArgs {
     Proj pr;
     const int *plain;   // per solve: 1 = this step ran the plain scheme (or NULL)
     float *contrib;     // [2][B][ny][nx][ADJ_REC] (18 used)
-    float *gz;          // [B][ny][nx][72]
+    __bf16 *dz;         // [B][ny][nx][DZ_CH]
 };
 
 __device__ __forceinline__ int pw(int i, int n) { return ((i % n) + n) % n; }
@@ -220,10 +220,15 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
 #pragma unroll
         for (int q4 = 0; q4 < ADJ_REC / 4; q4++)
             co4[q4] = make_float4(co[4 * q4], co[4 * q4 + 1], co[4 * q4 + 2], co[4 * q4 + 3]);
-        float4 *gz4 = (float4 *)(a.gz + ((size_t)b * plane + cell) * 72 + axis * 36);
+        typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+        bf16x4 *dz4 = (bf16x4 *)(a.dz + ((size_t)b * plane + cell) * DZ_CH + axis * 36);
 #pragma unroll
-        for (int q4 = 0; q4 < 9; q4++)
-            gz4[q4] = make_float4(gzc[4 * q4], gzc[4 * q4 + 1], gzc[4 * q4 + 2], gzc[4 * q4 + 3]);
+        for (int q4 = 0; q4 < 9; q4++) {
+            bf16x4 o;
+#pragma unroll
+            for (int e = 0; e < 4; e++) o[e] = (__bf16)gzc[4 * q4 + e];
+            dz4[q4] = o;
+        }
     }
 }
 
@@ -277,7 +282,7 @@ hipError_t launch_adjoint(int flux, const AdjStage &s, hipStream_t st)
     a.pr = s.pr;
     a.plain = s.plain;
     a.contrib = s.contrib;
-    a.gz = s.gz;
+    a.dz = (__bf16 *)s.dz;
     size_t nf = (size_t)2 * s.B * s.nx * s.ny;
     unsigned blocks = (unsigned)((nf + 255) / 256);
     if (flux == 1) hipLaunchKernelGGL((adj_face_kernel<fvk::RUSANOV>), dim3(blocks), dim3(256), 0, st, a);

@@ -180,8 +180,9 @@ hipError_t launch_flags_or(const int *flags, int B, int *any, hipStream_t st);
 hipError_t launch_coarsen(const float *fine, int nvar, int nx, int ny, int f, float *coarse, hipStream_t st);
 
 // Reverse pass of one learned stage (adjoint_kernels.hip): writes
-// gqs = (accumulate ? gqs : 0) + a1*gout + (FV part of the adjoint), and gz,
-// the adjoint of the raw coefficients z of this stage.
+// gqs = (accumulate ? gqs : 0) + a1*gout + (FV part of the adjoint), and dz,
+// the adjoint of the raw coefficients z of this stage rounded to BF16 in the
+// network backward's layout.
 struct AdjStage {
     const float *qs, *z, *gout;
     float a1, dt;
@@ -190,7 +191,7 @@ struct AdjStage {
     Proj pr;
     const int *plain;  // per solve: the step ran the plain scheme (or NULL)
     float *contrib;    // scratch [2][B][ny][nx][ADJ_REC]
-    float *gz;         // [B][ny][nx][72]
+    void *dz;          // [B][ny][nx][DZ_CH] BF16: channels 0..71 written, the rest left as they are (zero)
     float *gqs;
     int accumulate;
 };
@@ -198,13 +199,17 @@ hipError_t launch_adjoint(int flux, const AdjStage &s, hipStream_t st);
 // Floats per face in the adjoint's contribution scratch: 18 used, padded so
 // that a record is whole 16-byte vectors.
 constexpr int ADJ_REC = 20;
+// Channels per pixel of dz: the 72 coefficients padded to three 32-channel K
+// blocks of the layer-4 input-gradient convolution.
+constexpr int DZ_CH = 96;
 
 // Backward of the network for B solves: adds d loss / d theta into grads
 // (master layout, FP32) and d loss / d q into dq ([B][3][ny][nx], FP32),
-// given gz = d loss / d z and the activations saved by the forward.
+// given dz = d loss / d z (BF16 [p][DZ_CH], channels >= 72 zero) and the
+// activations saved by the forward.
 size_t backward_scratch_bytes(int B, int nx, int ny);
 hipError_t launch_backward(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny,
-                           void *const acts[4], const float *gz, float *dq, float *grads, void *scratch,
+                           void *const acts[4], const void *dz, float *dq, float *grads, void *scratch,
                            hipStream_t st);
 
 // Projector onto the null space of the moment conditions of the given order

@@ -140,19 +140,16 @@ hipError_t launch_pack(const float *master, void *packed, hipStream_t st)
 // ----------------------------------------------------------------- forward
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// MODE 0: first layer, input = states (FP32 planar) normalised and rounded
-//         to BF16 on the fly, K = 27 (tap*3 + ci) padded to 32;
-// MODE 1: hidden layer, NHWC BF16 in and out (bias, ReLU, round to BF16);
-// MODE 2: last layer, 72 FP32 outputs (bias only).
-template <int MODE>
-__global__ __launch_bounds__(256) void conv_fwd_kernel(const void *in, const bf16 *wp, const float *bias, void *out,
-                                                       int B, int H, int W, Norm nrm)
+// First layer: input = states (FP32 planar) normalised and rounded to BF16
+// on the fly, K = 27 (tap*3 + ci) padded to 32, one 16-pixel group per wave;
+// bias, ReLU, BF16 NHWC out [p][32].
+__global__ __launch_bounds__(256) void conv_first_kernel(const float *q, const bf16 *wp, const float *bias, bf16 *out,
+                                                         int B, int H, int W, Norm nrm)
 {
-    constexpr int NT = MODE == 2 ? 5 : 2;
-    constexpr int WEL = MODE == 0 ? 32 * 32 : 9 * NT * 16 * 32;
-    __shared__ bf16x8 s_w[WEL / 8];
+    constexpr int NT = 2;
+    __shared__ bf16x8 s_w[32 * 32 / 8];
     const bf16x8 *gw = (const bf16x8 *)wp;
-    for (int i = threadIdx.x; i < WEL / 8; i += 256) s_w[i] = gw[i];
+    for (int i = threadIdx.x; i < 32 * 32 / 8; i += 256) s_w[i] = gw[i];
     __syncthreads();
 
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -166,55 +163,159 @@ __global__ __launch_bounds__(256) void conv_fwd_kernel(const void *in, const bf1
     const int rem = (int)(p - (long)b * hw);
     const int y = rem / W, x = rem - y * W;
 
-    floatx4 acc[NT];
+    const float *qb = q + (size_t)b * 3 * hw;
+    bf16x8 bx;
 #pragma unroll
-    for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-
-    if (MODE == 0) {
-        const float *q = (const float *)in + (size_t)b * 3 * hw;
-        bf16x8 bx;
-#pragma unroll
-        for (int e = 0; e < 8; e++) {
-            int k = 8 * g + e;
-            float v = 0.0f;
-            if (k < 27) {
-                int tap = k / 3, ci = k - 3 * tap;
-                int yy = wrap(y + tap / 3 - 1, H), xx = wrap(x + tap % 3 - 1, W);
-                v = (q[(size_t)ci * hw + yy * W + xx] - nrm.mean[ci]) * nrm.inv_std[ci];
-            }
-            bx[e] = (bf16)v;
-        }
-#pragma unroll
-        for (int t = 0; t < NT; t++)
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[(t * 16 + px) * 4 + g], bx, acc[t], 0, 0, 0);
-    } else {
-        const bf16 *act = (const bf16 *)in + (size_t)b * hw * 32;
-#pragma unroll
-        for (int tap = 0; tap < 9; tap++) {
+    for (int e = 0; e < 8; e++) {
+        int k = 8 * g + e;
+        float v = 0.0f;
+        if (k < 27) {
+            int tap = k / 3, ci = k - 3 * tap;
             int yy = wrap(y + tap / 3 - 1, H), xx = wrap(x + tap % 3 - 1, W);
-            bf16x8 bx = *(const bf16x8 *)(act + (size_t)(yy * W + xx) * 32 + 8 * g);
-#pragma unroll
-            for (int t = 0; t < NT; t++)
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * 4 + g], bx, acc[t],
-                                                                 0, 0, 0);
+            v = (qb[(size_t)ci * hw + yy * W + xx] - nrm.mean[ci]) * nrm.inv_std[ci];
         }
+        bx[e] = (bf16)v;
     }
-
 #pragma unroll
     for (int t = 0; t < NT; t++) {
+        const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[(t * 16 + px) * 4 + g], bx,
+                                                                    floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
         const int co0 = 16 * t + 4 * g;
-        if (MODE < 2) {
-            bf16x4 o;
+        bf16x4 o;
 #pragma unroll
-            for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[t][i] + bias[co0 + i], 0.0f);
-            *(bf16x4 *)((bf16 *)out + (size_t)p * 32 + co0) = o;
-        } else if (co0 < 72) {
-            floatx4 o;
-#pragma unroll
-            for (int i = 0; i < 4; i++) o[i] = acc[t][i] + bias[co0 + i];
-            *(floatx4 *)((float *)out + (size_t)p * 72 + co0) = o;
+        for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[i] + bias[co0 + i], 0.0f);
+        *(bf16x4 *)(out + (size_t)p * 32 + co0) = o;
+    }
+}
+
+// 3x3 convolution over a 16-pixel-wide, 4R-row tile of one solve per
+// workgroup (K = KB*32 input channels, NT tiles of 16 output channels):
+//   out[p][co] = sum_tap sum_ci Wp[tap][co][ci] in[p + d_tap][ci]
+// with the packed layout [9 tap][rows][KB*32] of the forward weights or of
+// the transposed, tap-flipped ones.  The workgroup stages the layer's
+// weights and the 18 x (4R + 2) halo of its input tile in LDS once; wave w
+// computes tile rows Rw .. Rw+R-1 (one 16-pixel MFMA column group each) and
+// reuses each weight fragment for its R rows.  R = 4 where the grid still
+// has many workgroups per CU, else fewer rows per workgroup keep enough
+// workgroups resident to overlap staging with MFMAs.  Per output the MFMAs
+// run in the order
+// of the per-pixel kernels (taps 0..8, K blocks within a tap), so the results
+// are the same bits.  The halo's 16-byte channel octets are XOR-swizzled by
+// column so that sixteen consecutive pixels' reads of one octet hit distinct
+// banks.  Rows past ny are computed from wrapped rows and not stored.
+// EPI 0: forward hidden layer, + bias, ReLU, BF16 [p][32];
+// EPI 1: forward last layer, + bias, FP32 [p][72] (NT = 5);
+// EPI 2: input gradient of a hidden layer, times the ReLU mask of the
+//        previous activation (act > 0), BF16 [p][32].
+constexpr int HT = 16;  // tile width
+template <int KB, int NT, int EPI, int R>
+__global__ __launch_bounds__(256) void conv_halo_kernel(const bf16 *in, const bf16 *wp, const float *bias,
+                                                        const bf16 *mask, void *out, int H, int W)
+{
+    constexpr int CG = KB * 32;
+    constexpr int OCT = CG / 8;  // 16-byte octets per pixel
+    constexpr int WEL = 9 * NT * 16 * CG;
+    constexpr int TR = 4 * R;  // tile rows
+    constexpr int HP = (TR + 2) * (HT + 2);
+    __shared__ bf16x8 s_w[WEL / 8];
+    __shared__ bf16x8 s_a[HP * OCT];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, px = lane & 15;
+    const int x0 = blockIdx.x * HT, y0 = blockIdx.y * TR, b = blockIdx.z;
+    const size_t hw = (size_t)H * W;
+    const bf16 *src = in + (size_t)b * hw * CG;
+    {
+        const bf16x8 *gw = (const bf16x8 *)wp;
+        for (int i = tid; i < WEL / 8; i += 256) s_w[i] = gw[i];
+        for (int i = tid; i < HP * OCT; i += 256) {
+            const int hp = i / OCT, o = i - hp * OCT;
+            const int hr = hp / (HT + 2), hc = hp - hr * (HT + 2);
+            int yy = y0 - 1 + hr;
+            yy = yy < 0 ? yy + H : yy % H;
+            const int xx = wrap(x0 - 1 + hc, W);
+            const int pos = (o & ~3) | ((o & 3) ^ ((hc >> 2) & 3));
+            s_a[hp * OCT + pos] = *(const bf16x8 *)(src + ((size_t)yy * W + xx) * CG + o * 8);
         }
     }
+    __syncthreads();
+
+    floatx4 acc[R][NT];
+#pragma unroll
+    for (int r = 0; r < R; r++)
+#pragma unroll
+        for (int t = 0; t < NT; t++) acc[r][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int tap = 0; tap < 9; tap++) {
+        const int dy = tap / 3, dx = tap % 3;  // halo offsets (d + 1)
+        const int hc = px + dx;
+#pragma unroll
+        for (int kb = 0; kb < KB; kb++) {
+            bf16x8 af[NT], bx[R];
+#pragma unroll
+            for (int t = 0; t < NT; t++) af[t] = s_w[((tap * NT + t) * 16 + px) * OCT + kb * 4 + g];
+            const int pos = kb * 4 + (g ^ ((hc >> 2) & 3));
+#pragma unroll
+            for (int r = 0; r < R; r++) bx[r] = s_a[((wave * R + r + dy) * (HT + 2) + hc) * OCT + pos];
+#pragma unroll
+            for (int r = 0; r < R; r++)
+#pragma unroll
+                for (int t = 0; t < NT; t++)
+                    acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[t], bx[r], acc[r][t], 0, 0, 0);
+        }
+    }
+
+#pragma unroll
+    for (int r = 0; r < R; r++) {
+        const int y = y0 + wave * R + r;
+        if (y >= H) break;
+        const size_t p = (size_t)b * hw + (size_t)y * W + x0 + px;
+#pragma unroll
+        for (int t = 0; t < NT; t++) {
+            const int co0 = 16 * t + 4 * g;
+            if (EPI == 0) {
+                bf16x4 o;
+#pragma unroll
+                for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[r][t][i] + bias[co0 + i], 0.0f);
+                *(bf16x4 *)((bf16 *)out + p * 32 + co0) = o;
+            } else if (EPI == 1) {
+                if (co0 < 72) {
+                    floatx4 o;
+#pragma unroll
+                    for (int i = 0; i < 4; i++) o[i] = acc[r][t][i] + bias[co0 + i];
+                    *(floatx4 *)((float *)out + p * 72 + co0) = o;
+                }
+            } else {
+                const bf16x4 m = *(const bf16x4 *)(mask + p * 32 + co0);
+                bf16x4 o;
+#pragma unroll
+                for (int i = 0; i < 4; i++) o[i] = (bf16)((float)m[i] > 0.0f ? acc[r][t][i] : 0.0f);
+                *(bf16x4 *)((bf16 *)out + p * 32 + co0) = o;
+            }
+        }
+    }
+}
+
+// Rows per wave of the halo-tile convolutions: 4 while that leaves at least
+// 2048 workgroups (eight per CU), else 2, else 1.
+static int halo_rows(int B, int nx, int ny)
+{
+    for (int R = 4; R > 1; R /= 2)
+        if ((long)B * (nx / HT) * ((ny + 4 * R - 1) / (4 * R)) >= 2048) return R;
+    return 1;
+}
+static dim3 halo_grid(int B, int nx, int ny, int R)
+{
+    return dim3((unsigned)(nx / HT), (unsigned)((ny + 4 * R - 1) / (4 * R)), (unsigned)B);
+}
+template <int KB, int NT, int EPI>
+static void launch_halo(const bf16 *in, const bf16 *wp, const float *bias, const bf16 *mask, void *out, int B, int nx,
+                        int ny, hipStream_t st)
+{
+    const int R = halo_rows(B, nx, ny);
+    const dim3 grid = halo_grid(B, nx, ny, R), blk(256);
+    if (R == 4) hipLaunchKernelGGL((conv_halo_kernel<KB, NT, EPI, 4>), grid, blk, 0, st, in, wp, bias, mask, out, ny, nx);
+    else if (R == 2) hipLaunchKernelGGL((conv_halo_kernel<KB, NT, EPI, 2>), grid, blk, 0, st, in, wp, bias, mask, out, ny, nx);
+    else hipLaunchKernelGGL((conv_halo_kernel<KB, NT, EPI, 1>), grid, blk, 0, st, in, wp, bias, mask, out, ny, nx);
 }
 
 hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny,
@@ -223,14 +324,15 @@ hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, i
     const Packed pk = packed_layout();
     const char *P = (const char *)packed;
     const long npix = (long)B * nx * ny;
+    if (nx % HT) return hipErrorInvalidValue;
     dim3 grid((unsigned)((npix + 63) / 64)), blk(256);
-    hipLaunchKernelGGL(conv_fwd_kernel<0>, grid, blk, 0, st, (const void *)q, (const bf16 *)(P + pk.w[0]),
-                       (const float *)(P + pk.b[0]), acts[0], B, ny, nx, nrm);
+    hipLaunchKernelGGL(conv_first_kernel, grid, blk, 0, st, q, (const bf16 *)(P + pk.w[0]), (const float *)(P + pk.b[0]),
+                       (bf16 *)acts[0], B, ny, nx, nrm);
     for (int l = 1; l < 4; l++)
-        hipLaunchKernelGGL(conv_fwd_kernel<1>, grid, blk, 0, st, (const void *)acts[l - 1], (const bf16 *)(P + pk.w[l]),
-                           (const float *)(P + pk.b[l]), acts[l], B, ny, nx, nrm);
-    hipLaunchKernelGGL(conv_fwd_kernel<2>, grid, blk, 0, st, (const void *)acts[3], (const bf16 *)(P + pk.w[4]),
-                       (const float *)(P + pk.b[4]), (void *)z, B, ny, nx, nrm);
+        launch_halo<1, 2, 0>((const bf16 *)acts[l - 1], (const bf16 *)(P + pk.w[l]), (const float *)(P + pk.b[l]),
+                             nullptr, acts[l], B, nx, ny, st);
+    launch_halo<1, 5, 1>((const bf16 *)acts[3], (const bf16 *)(P + pk.w[4]), (const float *)(P + pk.b[4]), nullptr,
+                         (void *)z, B, nx, ny, st);
     return hipGetLastError();
 }
 
@@ -241,7 +343,7 @@ hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, i
 // input region (FT + 10)^2 is read once with periodic wrap, activations stay
 // in LDS (two ping-pong buffers), and all five layers' packed weights are
 // staged into LDS together.  Each output pixel accumulates its MFMAs in
-// the same order as conv_fwd_kernel (taps 0..8, K slices within a tap), with
+// the same order as the layer-by-layer pass (taps 0..8, K slices within a tap), with
 // the same bias, ReLU and BF16 rounding, so z is bit-identical to the
 // layer-by-layer pass; only the halo pixels are computed more than once.
 constexpr int FT = 8;            // output tile side
@@ -878,17 +980,6 @@ hipError_t launch_forward_fused(const void *packed, const Norm &nrm, const float
 // ================================================================ backward
 namespace cnn {
 
-// gz [p][72] FP32 -> dz [p][96] BF16 (zero padded K for the 3 K blocks of
-// the layer-4 input-gradient convolution).
-__global__ void dz_prep_kernel(const float *gz, bf16 *dz, long npix)
-{
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < npix * 96; i += (long)gridDim.x * blockDim.x) {
-        long p = i / 96;
-        int c = (int)(i - p * 96);
-        dz[i] = (bf16)(c < 72 ? gz[p * 72 + c] : 0.0f);
-    }
-}
-
 // Network input as the forward rounds it: x0 = bf16((q - mean) * inv_std),
 // NHWC with 16 channels (3 used) for the layer-0 weight gradient.
 __global__ void x0_kernel(const float *q, bf16 *x0, int B, int H, int W, Norm nrm)
@@ -903,18 +994,14 @@ __global__ void x0_kernel(const float *q, bf16 *x0, int B, int H, int W, Norm nr
     }
 }
 
-// Input gradient of a convolution: dIn[p] = sum_t Wt[t] G[p + d_t] with the
-// transposed, tap-flipped weights (same implicit-GEMM layout as the forward).
-// EPI 0: hidden layer, multiply by the ReLU mask of the previous activation
-//        (act > 0 <=> pre-activation > 0) and store BF16 [p][32];
-// EPI 1: network input, add dq[c] += dx0[c] * inv_std[c] into the FP32
-//        planar state gradient.
-template <int KB, int NT, int EPI>
-__global__ __launch_bounds__(256) void conv_dgrad_kernel(const bf16 *G, const bf16 *wt, const bf16 *act_prev,
-                                                         bf16 *out, float *dq, int B, int H, int W, Norm nrm)
+// Input gradient of the first layer: dx0[p] = sum_t Wt[t] G[p + d_t] with the
+// transposed, tap-flipped weights (16 output rows, 3 used), one 16-pixel
+// group per wave; adds dq[c] += dx0[c] * inv_std[c] into the FP32 planar
+// state gradient.
+__global__ __launch_bounds__(256) void conv_dgrad_input_kernel(const bf16 *G, const bf16 *wt, float *dq, int B, int H,
+                                                               int W, Norm nrm)
 {
-    constexpr int CG = KB * 32;
-    constexpr int WEL = 9 * NT * 16 * CG;
+    constexpr int WEL = 9 * 16 * 32;
     __shared__ bf16x8 s_w[WEL / 8];
     const bf16x8 *gw = (const bf16x8 *)wt;
     for (int i = threadIdx.x; i < WEL / 8; i += 256) s_w[i] = gw[i];
@@ -929,36 +1016,17 @@ __global__ __launch_bounds__(256) void conv_dgrad_kernel(const bf16 *G, const bf
     const int b = (int)(p / hw);
     const int rem = (int)(p - (long)b * hw);
     const int y = rem / W, x = rem - y * W;
-    floatx4 acc[NT];
-#pragma unroll
-    for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const bf16 *gb = G + (size_t)b * hw * CG;
+    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+    const bf16 *gb = G + (size_t)b * hw * 32;
 #pragma unroll
     for (int tap = 0; tap < 9; tap++) {
         int yy = wrap(y + tap / 3 - 1, H), xx = wrap(x + tap % 3 - 1, W);
-        const bf16 *src = gb + (size_t)(yy * W + xx) * CG;
-#pragma unroll
-        for (int kb = 0; kb < KB; kb++) {
-            bf16x8 bx = *(const bf16x8 *)(src + kb * 32 + 8 * g);
-#pragma unroll
-            for (int t = 0; t < NT; t++)
-                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * (CG / 8) + kb * 4 + g],
-                                                                 bx, acc[t], 0, 0, 0);
-        }
+        const bf16x8 bx = *(const bf16x8 *)(gb + (size_t)(yy * W + xx) * 32 + 8 * g);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[(tap * 16 + px) * 4 + g], bx, acc, 0, 0, 0);
     }
-    if (EPI == 0) {
+    if (g == 0) {
 #pragma unroll
-        for (int t = 0; t < NT; t++) {
-            const int c0 = 16 * t + 4 * g;
-            bf16x4 m = *(const bf16x4 *)(act_prev + (size_t)p * 32 + c0);
-            bf16x4 o;
-#pragma unroll
-            for (int i = 0; i < 4; i++) o[i] = (bf16)((float)m[i] > 0.0f ? acc[t][i] : 0.0f);
-            *(bf16x4 *)(out + (size_t)p * 32 + c0) = o;
-        }
-    } else if (g == 0) {
-#pragma unroll
-        for (int c = 0; c < 3; c++) dq[((size_t)b * 3 + c) * hw + rem] += acc[0][c] * nrm.inv_std[c];
+        for (int c = 0; c < 3; c++) dq[((size_t)b * 3 + c) * hw + rem] += acc[c] * nrm.inv_std[c];
     }
 }
 
@@ -1174,7 +1242,7 @@ size_t backward_scratch_bytes(int B, int nx, int ny)
     int ppb = ppb_for(npix);
     long nblocks = (npix + ppb - 1) / ppb;
     size_t part = (size_t)nblocks * (9 * 80 * 32 + 80) * 4;
-    return al256(npix * 96 * 2) + 2 * al256(npix * 32 * 2) + al256(npix * 16 * 2) + al256(part);
+    return 2 * al256(npix * 32 * 2) + al256(npix * 16 * 2) + al256(part);
 }
 
 template <int CG, int CO_T, int CI>
@@ -1192,7 +1260,7 @@ static void wgrad(const bf16 *G, const bf16 *In, int B, int H, int W, float *par
 }
 
 hipError_t launch_backward(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny,
-                           void *const acts[4], const float *gz, float *dq, float *grads, void *scratch,
+                           void *const acts[4], const void *dzv, float *dq, float *grads, void *scratch,
                            hipStream_t st)
 {
     const Packed pk = packed_layout();
@@ -1202,9 +1270,8 @@ hipError_t launch_backward(const void *packed, const Norm &nrm, const float *q, 
     // the weight-gradient staging takes whole 64-pixel chunks and pixel
     // octets inside one image row
     if (nx % 16 || npix % 64 || npix > (1L << 30)) return hipErrorInvalidValue;
+    const bf16 *dz = (const bf16 *)dzv;
     char *sc = (char *)scratch;
-    bf16 *dz = (bf16 *)sc;
-    sc += al256(npix * 96 * 2);
     bf16 *dA = (bf16 *)sc;
     sc += al256(npix * 32 * 2);
     bf16 *dB = (bf16 *)sc;
@@ -1213,21 +1280,18 @@ hipError_t launch_backward(const void *packed, const Norm &nrm, const float *q, 
     sc += al256(npix * 16 * 2);
     float *partial = (float *)sc;
     const bf16 *a[4] = {(const bf16 *)acts[0], (const bf16 *)acts[1], (const bf16 *)acts[2], (const bf16 *)acts[3]};
-    unsigned eg = (unsigned)((npix * 96 + 255) / 256);
+    unsigned eg = (unsigned)((npix * 16 + 255) / 256);
     if (eg > 8192) eg = 8192;
     dim3 cg((unsigned)((npix + 63) / 64)), blk(256);
 
-    hipLaunchKernelGGL(dz_prep_kernel, dim3(eg), blk, 0, st, gz, dz, npix);
     // layer 4: 32 -> 72
     wgrad<96, 5, 32>(dz, a[3], B, ny, nx, partial, 72, 32, ml.w[4], ml.b[4], grads, st);
-    hipLaunchKernelGGL((conv_dgrad_kernel<3, 2, 0>), cg, blk, 0, st, (const bf16 *)dz,
-                       (const bf16 *)(P + pk.wt[4]), a[3], dA, (float *)nullptr, B, ny, nx, nrm);
+    launch_halo<3, 2, 2>(dz, (const bf16 *)(P + pk.wt[4]), nullptr, a[3], (void *)dA, B, nx, ny, st);
     // layers 3, 2, 1: 32 -> 32
     bf16 *cur = dA, *nxt = dB;
     for (int l = 3; l >= 1; l--) {
         wgrad<32, 2, 32>(cur, a[l - 1], B, ny, nx, partial, 32, 32, ml.w[l], ml.b[l], grads, st);
-        hipLaunchKernelGGL((conv_dgrad_kernel<1, 2, 0>), cg, blk, 0, st, (const bf16 *)cur,
-                           (const bf16 *)(P + pk.wt[l]), a[l - 1], nxt, (float *)nullptr, B, ny, nx, nrm);
+        launch_halo<1, 2, 2>(cur, (const bf16 *)(P + pk.wt[l]), nullptr, a[l - 1], (void *)nxt, B, nx, ny, st);
         bf16 *t = cur;
         cur = nxt;
         nxt = t;
@@ -1235,8 +1299,8 @@ hipError_t launch_backward(const void *packed, const Norm &nrm, const float *q, 
     // layer 0: 3 -> 32 (input rebuilt as the forward rounds it)
     hipLaunchKernelGGL(x0_kernel, dim3(eg), blk, 0, st, q, x0, B, ny, nx, nrm);
     wgrad<32, 2, 16>(cur, x0, B, ny, nx, partial, 32, 3, ml.w[0], ml.b[0], grads, st);
-    hipLaunchKernelGGL((conv_dgrad_kernel<1, 1, 1>), cg, blk, 0, st, (const bf16 *)cur,
-                       (const bf16 *)(P + pk.wt[0]), (const bf16 *)nullptr, (bf16 *)nullptr, dq, B, ny, nx, nrm);
+    hipLaunchKernelGGL(conv_dgrad_input_kernel, cg, blk, 0, st, (const bf16 *)cur, (const bf16 *)(P + pk.wt[0]), dq, B,
+                       ny, nx, nrm);
     return hipGetLastError();
 }
 

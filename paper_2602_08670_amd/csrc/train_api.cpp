@@ -14,7 +14,7 @@ using fvapi::hip_fail;
 namespace {
 
 struct TrainLayout {
-    size_t states, s1, acts, z, plain, s2, bad, dt, nfb, redone, fatal, gz, contrib, G, Gn, gS1, bwd, lossp, loss,
+    size_t states, s1, acts, z, plain, s2, bad, dt, nfb, redone, fatal, dz, contrib, G, Gn, gS1, bwd, lossp, loss,
         scale, total;
     size_t st, act, zb;  // per-unit sizes
 };
@@ -66,8 +66,8 @@ TrainLayout layout_of(const fv_train_config *c)
     o += align256(c->B * 8);
     L.fatal = o;
     o += align256(c->B * 4);
-    L.gz = o;
-    o += L.zb;
+    L.dz = o;
+    o += align256(npix * cnn::DZ_CH * 2);
     L.contrib = o;
     o += align256(npix * 2 * cnn::ADJ_REC * 4);
     L.G = o;
@@ -139,6 +139,8 @@ fv_status fv_train_create(const fv_train_config *cfg, fv_model *m, float *grads,
     if (e == hipSuccess)
         e = hipMemcpyAsync(tr->ws + L.scale, cfg->scale, 3 * sizeof(float), hipMemcpyHostToDevice, m->stream);
     if (e == hipSuccess) e = hipMemsetAsync(tr->ws + L.bad, 0, align256(cfg->B * 4), m->stream);
+    // dz's padding channels (72 .. DZ_CH-1) stay zero: the adjoint writes 0 .. 71
+    if (e == hipSuccess) e = hipMemsetAsync(tr->ws + L.dz, 0, L.contrib - L.dz, m->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
     if (e != hipSuccess) {
         delete tr;
@@ -219,7 +221,7 @@ fv_status fv_train_step(fv_trainer *tr, const float *q0, const float *targets, i
     as.h0 = sb.h0;
     as.pr = tr->m->pr;
     as.contrib = (float *)(ws + L.contrib);
-    as.gz = (float *)(ws + L.gz);
+    as.dz = ws + L.dz;
     for (int t = T; t >= 1 && e == hipSuccess; t--) {
         e = cnn::launch_loss(tr->st(t), targets + (size_t)(t - 1) * nst, (const float *)(ws + L.scale), B, nx, ny, G,
                              (double *)(ws + L.lossp), 1024, (double *)(ws + L.loss), st);
@@ -231,14 +233,14 @@ fv_status fv_train_step(fv_trainer *tr, const float *q0, const float *targets, i
         as.gqs = gS1; as.accumulate = 0;
         if (e == hipSuccess) e = cnn::launch_adjoint(fl, as, st);
         if (e == hipSuccess)
-            e = cnn::launch_backward(tr->m->packed, tr->m->nrm, tr->s1(k), B, nx, ny, a1, as.gz, gS1, tr->grads,
+            e = cnn::launch_backward(tr->m->packed, tr->m->nrm, tr->s1(k), B, nx, ny, a1, as.dz, gS1, tr->grads,
                                      ws + L.bwd, st);
         // stage 1: S1 = q + dt L(q); the q/2 term of stage 2 first
         if (e == hipSuccess) e = cnn::launch_scale(Gn, G, 0.5f, nst, st);
         as.qs = tr->st(k); as.z = tr->zb(k, 0); as.gout = gS1; as.a1 = 1.0f; as.gqs = Gn; as.accumulate = 1;
         if (e == hipSuccess) e = cnn::launch_adjoint(fl, as, st);
         if (e == hipSuccess)
-            e = cnn::launch_backward(tr->m->packed, tr->m->nrm, tr->st(k), B, nx, ny, a0, as.gz, Gn, tr->grads,
+            e = cnn::launch_backward(tr->m->packed, tr->m->nrm, tr->st(k), B, nx, ny, a0, as.dz, Gn, tr->grads,
                                      ws + L.bwd, st);
         float *tmp = G;
         G = Gn;

@@ -98,10 +98,10 @@ def train(data, iters: int, B: int = 16, T_max: int = 8, lr: float = 1e-3, seed:
     t0 = time.perf_counter()
     for it in range(iters):
         T = min(T_max, 1 + (it * T_max) // max(1, iters // 2))
-        ti = rng.integers(0, n_traj, B)
-        ki = rng.integers(0, S1 - T, B)
-        q0 = torch.stack([data[a, k] for a, k in zip(ti, ki)])
-        tg = torch.stack([torch.stack([data[a, k + 1 + t] for a, k in zip(ti, ki)]) for t in range(T)])
+        ti = torch.as_tensor(rng.integers(0, n_traj, B), device=data.device)
+        ki = torch.as_tensor(rng.integers(0, S1 - T, B), device=data.device)
+        q0 = data[ti, ki]
+        tg = data[ti[None, :], ki[None, :] + torch.arange(1, T + 1, device=data.device)[:, None]]  # [T, B, 3, n, n]
         loss, stats = tr.step(q0, tg)
         if lr_final is not None:
             tr.set_lr(lr_final + 0.5 * (lr - lr_final) * (1.0 + math.cos(math.pi * it / max(1, iters - 1))))

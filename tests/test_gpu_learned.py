@@ -98,7 +98,8 @@ def test_tiled_forward_bitwise_equals_layer_by_layer(fv, L):
     across tile and grid edges, batches)."""
     p = oracle_params(L, 3, scale_last=0.3)
     m = gpu_model(fv, p)
-    for ny, nx, B in ((64, 64, 3), (32, 32, 5), (8, 16, 1), (24, 48, 2)):
+    # the last three select 16-, 8- and 16-row workgroup tiles in the layer-by-layer pass
+    for ny, nx, B in ((64, 64, 3), (32, 32, 5), (8, 16, 1), (24, 48, 2), (64, 64, 128), (64, 64, 64), (24, 64, 256)):
         q = (1.0 + 0.1 * np.random.default_rng(7 * ny + nx + B).standard_normal((B, 3, ny, nx))).astype(np.float32)
         qt = torch.tensor(q, device="cuda")
         z1 = m.forward(qt).cpu().numpy()
@@ -106,6 +107,24 @@ def test_tiled_forward_bitwise_equals_layer_by_layer(fv, L):
         ndiff = int(np.sum(z1 != z2))
         print(f"[tiled] {ny}x{nx} B={B}: {ndiff} differing of {z1.size}", flush=True)
         assert ndiff == 0
+    m.close()
+
+
+def test_layer_by_layer_forward_independent_of_batch(fv, L):
+    """The layer-by-layer pass picks its workgroup tile height from the grid
+    size (16, 8 or 4 rows); a solve's z is the same bits in a large batch
+    (16- or 8-row tiles, the last tile cut by ny) as alone (4-row tiles)."""
+    p = oracle_params(L, 4, scale_last=0.3)
+    m = gpu_model(fv, p)
+    for ny, nx, B in ((36, 64, 128), (24, 64, 256)):
+        q = (1.0 + 0.1 * np.random.default_rng(ny + B).standard_normal((B, 3, ny, nx))).astype(np.float32)
+        qt = torch.tensor(q, device="cuda")
+        zb = m.forward(qt).cpu().numpy()
+        for b in (0, B // 2, B - 1):
+            z1 = m.forward(qt[b:b + 1].contiguous()).cpu().numpy()
+            ndiff = int(np.sum(z1[0] != zb[b]))
+            print(f"[batch] {ny}x{nx} B={B} solve {b}: {ndiff} differing", flush=True)
+            assert ndiff == 0
     m.close()
 
 

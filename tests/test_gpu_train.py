@@ -55,28 +55,34 @@ def cos(a, b):
     return float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
 
 
-def batch(n, B, seed0):
+def batch(n, B, seed0, ny=None):
+    """B smooth states on an n x n grid; with ny < n the first ny rows (the
+    periodic seam then carries a jump)."""
     q = np.stack([I.random_smooth_swe(n, seed=seed0 + b) for b in range(B)])
     q[:, 1] = 0.02 * np.sin(2 * np.pi * np.arange(n) / n)[None, None, :]
+    if ny is not None:
+        q = q[:, :, :ny].copy()
     return q.astype(np.float32)
 
 
-@pytest.mark.parametrize("flux", ["hlle", "rusanov"])
-def test_gradients_match_oracle(fv, L, flux):
-    n, B, T, dt = 32, 2, 2, 1.2e-3
+@pytest.mark.parametrize("flux,ny,nx", [("hlle", 32, 32), ("rusanov", 32, 32), ("hlle", 24, 48)])
+def test_gradients_match_oracle(fv, L, flux, ny, nx):
+    """Square grids, and 24 x 48: rows past the last full 16-row tile of the
+    input-gradient convolutions."""
+    B, T, dt = 2, 2, 1.2e-3 * 32 / nx
     p = params(L, 21)
-    q0 = batch(n, B, 40)
+    q0 = batch(nx, B, 40, ny)
     # targets: the plain scheme from slightly perturbed states (non-zero loss)
     with torch.no_grad():
         tg, qq = [], torch.tensor(q0.astype(np.float64)) * 1.002
         for _ in range(T):
-            qq = L.plain_step(qq, dt, 1 / n, 1 / n, flux=flux)
+            qq = L.plain_step(qq, dt, 1 / nx, 1 / ny, flux=flux)
             tg.append(qq.float().double())
-        tg = torch.stack(tg, 1)  # [B, T, 3, n, n]
+        tg = torch.stack(tg, 1)  # [B, T, 3, ny, nx]
     scale = (0.05, 0.02, 0.02)
-    print(f"[gpu] train grad parity {flux} B={B} T={T} {n}x{n}", flush=True)
+    print(f"[gpu] train grad parity {flux} B={B} T={T} {ny}x{nx}", flush=True)
     m = fv.Model(vec(fv, p), fv.make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0)))
-    cfg = fv.make_train_config(B, n, n, T, dt, flux=fv.FV_FLUX_HLLE if flux == "hlle" else fv.FV_FLUX_RUSANOV,
+    cfg = fv.make_train_config(B, nx, ny, T, dt, flux=fv.FV_FLUX_HLLE if flux == "hlle" else fv.FV_FLUX_RUSANOV,
                                scale=scale, h_ref=1.0)
     tr = fv.Trainer(m, cfg)
     tgt = torch.tensor(tg.permute(1, 0, 2, 3, 4).numpy().astype(np.float32), device="cuda")
@@ -89,7 +95,7 @@ def test_gradients_match_oracle(fv, L, flux):
     for t in p["w"] + p["b"]:
         t.requires_grad_(True)
     qv = torch.tensor(q0.astype(np.float64), requires_grad=True)
-    lo = L.rollout_loss(p, qv, tg, dt, 1 / n, 1 / n, scale, flux=flux)
+    lo = L.rollout_loss(p, qv, tg, dt, 1 / nx, 1 / ny, scale, flux=flux)
     gw = torch.autograd.grad(lo, p["w"] + p["b"] + [qv])
     g_or = grad_vec(gw[:5], gw[5:10])
     gq_or = gw[10].numpy()
