@@ -1030,44 +1030,101 @@ __global__ __launch_bounds__(256) void conv_dgrad_input_kernel(const bf16 *G, co
     }
 }
 
-// Weight and bias gradient of a convolution over a range of pixels:
+// Weight and bias gradient of a convolution over one 16 x 16 tile of pixels
+// of one solve per workgroup:
 //   dW[t][co][ci] += sum_p G[p][co] In[p + d_t][ci],  db[co] += sum_p G[p][co].
-// MFMA with K = pixels.  Per 64-pixel chunk the block stages G and the nine
-// tap-shifted inputs transposed in LDS (rows = channels, 64 pixels
-// contiguous), so an operand fragment is one 16-byte LDS read.  Each thread
-// owns one staging job: eight consecutive pixels' eight channels of G or of
-// one tap's input (one 16-byte load per pixel; W % 16 == 0 keeps the eight in
-// one image row, so only the first and last can wrap), transposed in
-// registers and written as eight 16-byte rows.  The loads run WG_PD chunks
-// ahead of the MFMAs; a thread's pixel position advances by 64 per chunk
-// without divisions.  The bias is one more MFMA per co tile against a
-// fragment whose column 0 is all ones.  Each block writes its partial sums;
-// a fixed-order reduction adds the partials of all blocks.
-constexpr int WG_PD = 2;
+// MFMA with K = the tile's pixels, two tile rows (32 pixels) per step.  The
+// workgroup stages G transposed ([co][256 pixels]) and the input's 18-row
+// halo transposed three times, shifted by dx = -1, 0, +1 ([dx][ci][18 rows]
+// [16 columns]), so that for every tap the operand fragment (eight pixels of
+// one row, one channel) is one aligned 16-byte LDS read and every input pixel
+// is loaded once per tile instead of once per tap.  A staging job loads eight
+// (G) or ten (input: the union of the three shifts) consecutive pixels' eight
+// channels and transposes them in registers.  Rows past ny contribute nothing
+// (their G is staged as zero).  The bias is one more MFMA per co tile against
+// a fragment whose column 0 is all ones.  Each workgroup writes its partial
+// sums; a fixed-order reduction adds the partials of all workgroups.
 template <int CO_T, int CI>
 struct WgradShape {
     static constexpr int NCO = CO_T * 16;
-    static constexpr int JG = 8 * (NCO / 8);          // G jobs per chunk (pixel octet, channel octet)
-    static constexpr int NJ = JG + 9 * 8 * (CI / 8);  // plus the input jobs of the nine taps
-    static constexpr int NW = (NJ + 63) / 64;         // waves per block
+    static constexpr int JI = (HT + 2) * 2 * (CI / 8);   // input jobs: halo row, column octet, channel octet
+    static constexpr int JG = HT * 2 * (NCO / 8);        // G jobs: tile row, column octet, channel octet
+    static constexpr int SLOTS = (JI + JG + 255) / 256;
+    static constexpr int GLD = HT * HT + 8;              // G^T row stride (BF16)
+    static constexpr int ILD = (HT + 2) * HT + 8;        // input^T stride per (shift, channel) (BF16)
+    static constexpr int PER = 9 * NCO * CI + NCO;       // partial floats per workgroup
 };
 
 template <int CG, int CO_T, int CI>
-__global__ __launch_bounds__((WgradShape<CO_T, CI>::NW * 64)) void wgrad_kernel(const bf16 *G, const bf16 *In, int B,
-                                                                                int H, int W, int ppb, float *partial)
+__global__ __launch_bounds__(256) void wgrad_kernel(const bf16 *G, const bf16 *In, int H, int W, float *partial)
 {
     using S = WgradShape<CO_T, CI>;
-    constexpr int CI_T = CI / 16;
-    constexpr int NCO = S::NCO, JG = S::JG, NJ = S::NJ, NW = S::NW;
+    constexpr int CI_T = CI / 16, NCO = S::NCO, JI = S::JI, JG = S::JG, SLOTS = S::SLOTS;
+    constexpr int GLD = S::GLD, ILD = S::ILD;
     constexpr int NTILE = CO_T * CI_T;
-    constexpr int TPW = (NTILE + NW - 1) / NW;
-    constexpr int LD = 72;  // row stride in BF16 (64 pixels + pad, 16-byte multiple)
-    __shared__ bf16x8 sG[NCO * LD / 8];
-    __shared__ bf16x8 sI[9 * CI * LD / 8];
+    constexpr int TPW = (NTILE + 3) / 4;
+    __shared__ bf16x8 sG[NCO * GLD / 8];
+    __shared__ bf16x8 sI[3 * CI * ILD / 8];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, r16 = lane & 15;
-    const int npix = B * H * W;  // <= 2^30 (checked by the caller)
-    const int hw = H * W;
+    const int x0 = blockIdx.x * HT, y0 = blockIdx.y * HT, b = blockIdx.z;
+    const size_t hw = (size_t)H * W;
+
+    // staging: loads first, then the transposes and LDS writes
+    bf16x8 v[SLOTS][10];
+#pragma unroll
+    for (int s = 0; s < SLOTS; s++) {
+        const int j = tid + 256 * s;
+        if (j < JI) {
+            const int c8 = j % (CI / 8), q = (j / (CI / 8)) & 1, h = j / (2 * (CI / 8));
+            int yy = y0 - 1 + h;
+            yy = yy < 0 ? yy + H : yy % H;
+            const bf16 *row = In + ((size_t)b * hw + (size_t)yy * W) * CI + c8 * 8;
+            const int xs = x0 + 8 * q - 1;  // first of the ten columns
+#pragma unroll
+            for (int i = 0; i < 10; i++) v[s][i] = *(const bf16x8 *)(row + (size_t)wrap(xs + i, W) * CI);
+        } else if (j < JI + JG) {
+            const int jj = j - JI;
+            const int c8 = jj % (NCO / 8), q = (jj / (NCO / 8)) & 1, r = jj / (2 * (NCO / 8));
+            if (y0 + r < H) {
+                const bf16 *src = G + ((size_t)b * hw + (size_t)(y0 + r) * W + x0 + 8 * q) * CG + c8 * 8;
+#pragma unroll
+                for (int i = 0; i < 8; i++) v[s][i] = *(const bf16x8 *)(src + (size_t)i * CG);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 8; i++)
+#pragma unroll
+                    for (int e = 0; e < 8; e++) v[s][i][e] = (bf16)0.0f;
+            }
+        }
+    }
+#pragma unroll
+    for (int s = 0; s < SLOTS; s++) {
+        const int j = tid + 256 * s;
+        if (j < JI) {
+            const int c8 = j % (CI / 8), q = (j / (CI / 8)) & 1, h = j / (2 * (CI / 8));
+#pragma unroll
+            for (int d = 0; d < 3; d++)
+#pragma unroll
+                for (int c = 0; c < 8; c++) {
+                    bf16x8 w;
+#pragma unroll
+                    for (int i = 0; i < 8; i++) w[i] = v[s][i + d][c];
+                    sI[((d * CI + c8 * 8 + c) * ILD + h * HT + 8 * q) / 8] = w;
+                }
+        } else if (j < JI + JG) {
+            const int jj = j - JI;
+            const int c8 = jj % (NCO / 8), q = (jj / (NCO / 8)) & 1, r = jj / (2 * (NCO / 8));
+#pragma unroll
+            for (int c = 0; c < 8; c++) {
+                bf16x8 w;
+#pragma unroll
+                for (int i = 0; i < 8; i++) w[i] = v[s][i][c];
+                sG[((c8 * 8 + c) * GLD + r * HT + 8 * q) / 8] = w;
+            }
+        }
+    }
+    __syncthreads();
 
     floatx4 acc[TPW][9], accb[TPW];
 #pragma unroll
@@ -1079,102 +1136,32 @@ __global__ __launch_bounds__((WgradShape<CO_T, CI>::NW * 64)) void wgrad_kernel(
     bf16x8 ones;
 #pragma unroll
     for (int e = 0; e < 8; e++) ones[e] = (bf16)(r16 == 0 ? 1.0f : 0.0f);
-
-    const int pbeg = blockIdx.x * ppb;
-    const int pend = ppb < npix - pbeg ? pbeg + ppb : npix;
-    const int nch = pend > pbeg ? (pend - pbeg + 63) / 64 : 0;
-
-    // this thread's job
-    const bool isG = tid < JG, active = tid < NJ;
-    const int jj = tid - JG;
-    const int tap = isG ? 0 : jj / (8 * (CI / 8));
-    const int po = isG ? (tid & 7) : (jj - tap * (8 * (CI / 8))) & 7;
-    const int c8 = isG ? (tid >> 3) : (jj - tap * (8 * (CI / 8))) >> 3;
-    const int dy = tap / 3 - 1, dx = tap % 3 - 1;
-    bf16x8 *const dst = isG ? sG + (c8 * 8) * (LD / 8) + po : sI + (tap * CI + c8 * 8) * (LD / 8) + po;
-    // first pixel of the octet the next load reads, and its (solve, row, column)
-    int p = pbeg + po * 8;
-    int b = p / hw, y = (p - b * hw) / W;
-    int x = p - b * hw - y * W;
-
-    bf16x8 v[WG_PD][8];
-    auto load = [&](bf16x8 *r) {
-        if (active) {
-            if (isG) {
-                const bf16 *src = G + (size_t)p * CG + c8 * 8;
+    // lane (r16, g) of step ks: tile row 2 ks + (g >> 1), columns 8 (g & 1) .. +7
 #pragma unroll
-                for (int i = 0; i < 8; i++) r[i] = *(const bf16x8 *)(src + i * CG);
-            } else {
-                const int yy = wrap(y + dy, H), x0 = x + dx;
-                const bf16 *row = In + ((size_t)b * hw + (size_t)yy * W) * CI + c8 * 8;
-                r[0] = *(const bf16x8 *)(row + (x0 < 0 ? W - 1 : x0) * CI);
+    for (int j = 0; j < TPW; j++) {
+        const int id = wave + 4 * j;
+        if (id < NTILE) {
+            const int cot = id / CI_T, cit = id - cot * CI_T;
+            for (int ks = 0; ks < HT / 2; ks++) {
+                const int r = 2 * ks + (g >> 1), cq = 8 * (g & 1);
+                const bf16x8 af = sG[((cot * 16 + r16) * GLD + r * HT + cq) / 8];
+                bf16x8 bf[9];
 #pragma unroll
-                for (int i = 1; i < 7; i++) r[i] = *(const bf16x8 *)(row + (x0 + i) * CI);
-                r[7] = *(const bf16x8 *)(row + (x0 + 7 >= W ? 0 : x0 + 7) * CI);
-            }
-        }
-        p += 64;
-        x += 64;
-        while (x >= W) {
-            x -= W;
-            if (++y == H) {
-                y = 0;
-                ++b;
-            }
-        }
-    };
-    auto store = [&](const bf16x8 *r) {
-        if (!active) return;
+                for (int t = 0; t < 9; t++)
+                    bf[t] = sI[(((t % 3) * CI + cit * 16 + r16) * ILD + (r + t / 3) * HT + cq) / 8];
 #pragma unroll
-        for (int c = 0; c < 8; c++) {
-            bf16x8 w;
-#pragma unroll
-            for (int i = 0; i < 8; i++) w[i] = r[i][c];
-            dst[c * (LD / 8)] = w;
-        }
-    };
-
-#pragma unroll
-    for (int k = 0; k < WG_PD; k++)
-        if (k < nch) load(v[k]);
-    for (int c0 = 0; c0 < nch; c0 += WG_PD) {
-#pragma unroll
-        for (int k = 0; k < WG_PD; k++) {
-            const int ch = c0 + k;
-            if (ch >= nch) break;
-            if (ch > 0) __syncthreads();  // the previous chunk's MFMAs have read the tiles
-            store(v[k]);
-            __syncthreads();
-            if (ch + WG_PD < nch) load(v[k]);
-            // a tile's twenty operand reads are all issued before its MFMAs
-#pragma unroll
-            for (int j = 0; j < TPW; j++) {
-                const int id = wave + NW * j;
-                if (id < NTILE) {
-                    const int cot = id / CI_T, cit = id - cot * CI_T;
-                    bf16x8 af[2], bf[2][9];
-#pragma unroll
-                    for (int ks = 0; ks < 2; ks++) {
-                        af[ks] = sG[(cot * 16 + r16) * (LD / 8) + ks * 4 + g];
-#pragma unroll
-                        for (int t = 0; t < 9; t++) bf[ks][t] = sI[(t * CI + cit * 16 + r16) * (LD / 8) + ks * 4 + g];
-                    }
-#pragma unroll
-                    for (int ks = 0; ks < 2; ks++) {
-#pragma unroll
-                        for (int t = 0; t < 9; t++)
-                            acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks], bf[ks][t], acc[j][t], 0, 0, 0);
-                        if (cit == 0) accb[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ks], ones, accb[j], 0, 0, 0);
-                    }
-                }
+                for (int t = 0; t < 9; t++)
+                    acc[j][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bf[t], acc[j][t], 0, 0, 0);
+                if (cit == 0) accb[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, ones, accb[j], 0, 0, 0);
             }
         }
     }
     // partial layout: [9][NCO][CI] then [NCO] bias
-    float *pp = partial + (size_t)blockIdx.x * (9 * NCO * CI + NCO);
+    const int blk = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    float *pp = partial + (size_t)blk * S::PER;
 #pragma unroll
     for (int j = 0; j < TPW; j++) {
-        const int id = wave + NW * j;
+        const int id = wave + 4 * j;
         if (id < NTILE) {
             const int cot = id / CI_T, cit = id - cot * CI_T;
 #pragma unroll
@@ -1229,19 +1216,13 @@ __global__ __launch_bounds__(RED_WAVES * 64) void wgrad_reduce_kernel(const floa
     else grads[woff + (co * ci_real + ci) * 9 + tap] += t;
 }
 
-static int ppb_for(long npix)
-{
-    long ppb = (npix + 255) / 256;
-    ppb = (ppb + 63) / 64 * 64;
-    return (int)(ppb < 64 ? 64 : ppb);
-}
+static dim3 wgrad_grid(int B, int nx, int ny) { return dim3((unsigned)(nx / HT), (unsigned)((ny + HT - 1) / HT), (unsigned)B); }
 
 size_t backward_scratch_bytes(int B, int nx, int ny)
 {
     long npix = (long)B * nx * ny;
-    int ppb = ppb_for(npix);
-    long nblocks = (npix + ppb - 1) / ppb;
-    size_t part = (size_t)nblocks * (9 * 80 * 32 + 80) * 4;
+    const dim3 wg = wgrad_grid(B, nx, ny);
+    size_t part = (size_t)wg.x * wg.y * wg.z * WgradShape<5, 32>::PER * 4;
     return 2 * al256(npix * 32 * 2) + al256(npix * 16 * 2) + al256(part);
 }
 
@@ -1249,14 +1230,12 @@ template <int CG, int CO_T, int CI>
 static void wgrad(const bf16 *G, const bf16 *In, int B, int H, int W, float *partial, int co_real, int ci_real,
                   int woff, int boff, float *grads, hipStream_t st)
 {
-    long npix = (long)B * H * W;
-    int ppb = ppb_for(npix);
-    int nblocks = (int)((npix + ppb - 1) / ppb);
-    hipLaunchKernelGGL((wgrad_kernel<CG, CO_T, CI>), dim3(nblocks), dim3(WgradShape<CO_T, CI>::NW * 64), 0, st, G, In,
-                       B, H, W, ppb, partial);
-    int per = 9 * CO_T * 16 * CI + CO_T * 16;
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((per + 63) / 64), dim3(RED_WAVES * 64), 0, st, (const float *)partial, nblocks,
-                       CO_T * 16, CI, co_real, ci_real, woff, boff, grads);
+    const dim3 wg = wgrad_grid(B, W, H);
+    const int nblocks = (int)(wg.x * wg.y * wg.z);
+    hipLaunchKernelGGL((wgrad_kernel<CG, CO_T, CI>), wg, dim3(256), 0, st, G, In, H, W, partial);
+    const int per = WgradShape<CO_T, CI>::PER;
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((per + 63) / 64), dim3(RED_WAVES * 64), 0, st, (const float *)partial,
+                       nblocks, CO_T * 16, CI, co_real, ci_real, woff, boff, grads);
 }
 
 hipError_t launch_backward(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny,
@@ -1267,9 +1246,8 @@ hipError_t launch_backward(const void *packed, const Norm &nrm, const float *q, 
     const MasterLayout ml = master_layout();
     const char *P = (const char *)packed;
     const long npix = (long)B * nx * ny;
-    // the weight-gradient staging takes whole 64-pixel chunks and pixel
-    // octets inside one image row
-    if (nx % 16 || npix % 64 || npix > (1L << 30)) return hipErrorInvalidValue;
+    // the halo-tile kernels take 16-pixel-wide tiles
+    if (nx % HT) return hipErrorInvalidValue;
     const bf16 *dz = (const bf16 *)dzv;
     char *sc = (char *)scratch;
     bf16 *dA = (bf16 *)sc;

@@ -131,12 +131,11 @@ def test_gradients_bitwise_repeatable(fv, L):
 
 
 def test_gradients_batch_equals_mean_of_solves(fv, L):
-    """At 64^2 x 16 solves every weight-gradient block takes four 64-pixel
-    chunks (its loads for the next chunk overlap the current one's MFMAs);
-    alone, a solve's blocks take one.  The loss of eq 2.28 averages over the
-    batch, so the batch gradient is the mean of the sixteen single-solve
-    gradients: per pixel the two runs compute the same values, only the
-    order of the FP32 sums over pixels differs."""
+    """The loss of eq 2.28 averages over the batch, so the gradient of a
+    batch of sixteen 64^2 solves is the mean of the sixteen single-solve
+    gradients: per pixel the two runs compute the same values (the batch
+    takes 16, 8 or 4-row tiles where a solve alone takes others), only the
+    order of the FP32 sums over pixels and workgroups differs."""
     n, B, T, dt = 64, 16, 2, 6.0e-4
     p = params(L, 24)
     q0 = torch.tensor(batch(n, B, 70), device="cuda")
