@@ -319,7 +319,8 @@ fv_status fv_coarsen(const float *fine, int nvar, int nx, int ny, int factor, fl
  * (BF16 MFMA) and the learned stage of every learned solve, the
  * coefficients staying on chip; then commit-or-redo and redo), or, in rounds
  * with many learned tiles (learned_split), six (the network pass and the
- * learned stage as separate launches).  A round's launches are recorded once, per kinds of work present
+ * learned stage as separate launches), the network pass itself running
+ * layer by layer in rounds with more learned cells still (learned_layered).  A round's launches are recorded once, per kinds of work present
  * and number of steps, into a hipGraph that every later round replays: the
  * kernels read their tile counts from the device work-lists, and between
  * replays the host rewrites those lists and sets each launch's grid to its
@@ -343,7 +344,15 @@ typedef struct {
                                 launches (throughput) instead of one launch per stage that keeps
                                 the coefficients on chip (latency); 0: 4 x the workgroups of the
                                 network pass resident at once.  Same results either way. */
-    int32_t reserved1;       /* must be 0 */
+    int32_t learned_layered; /* 16 x 16-cell tiles in a round's first step from which a round with
+                                separate launches runs the network pass layer by layer (five
+                                launches per stage on 16 x 16 tiles, activations in the pool's
+                                scratch; all learned sides multiples of 16) instead of as one
+                                launch; 0: 768; -1: never.  Same results either way. */
+    uint64_t act_pixels;     /* capacity in cells of that activation scratch (128 bytes per cell,
+                                counted in fv_server_pool_overhead); rounds with more learned cells
+                                use the one-launch network pass; 0: no scratch (never layer by
+                                layer) */
 } fv_server_config;
 
 typedef struct {
@@ -379,7 +388,7 @@ typedef struct {
     int64_t graph_replays;   /* of which replayed from a captured graph */
     int64_t grid_updates;    /* launch grids reset before replays */
     int32_t graphs_captured; /* distinct graphs captured so far */
-    int32_t pad;
+    int32_t layered_rounds;  /* rounds whose network pass ran layer by layer */
     double host_launch_s;    /* host seconds spent enqueueing rounds' launches (or graphs) */
     double host_wait_s;      /* host seconds spent waiting for rounds' work to finish */
     double host_capture_s;   /* host seconds spent capturing and instantiating graphs */

@@ -84,6 +84,7 @@ struct LSolve {
 // step uses.
 struct LItem {
     int solve, tb_cnn, tb_st, parity;
+    int tb_h;  // first 16 x 16 tile in the layer-by-layer network pass's numbering
 };
 constexpr int LTILE_CNN = 8;            // network pass tile side
 constexpr int LTILE_X = 32, LTILE_Y = 4;  // stage tile
@@ -108,6 +109,16 @@ hipError_t launch_forward_batch_list(int stage, const void *packed, const Norm &
                                      hipStream_t st);
 hipError_t launch_learned_batch_list(int mode, int stage, const LSolve *tab, const LItem *items, const int *list,
                                      int wgs, const Proj &pr, hipStream_t st);
+// One layer (0..4) of the layer-by-layer network pass of the listed solves
+// (nx, ny multiples of 16) on 16 x 16 tiles, wgs workgroups (the list
+// header's fourth entry, 16 x 16 tiles): layer 0 reads q (stage 1) or S1
+// (stage 2) into act0, layers 1..3 go act0 -> act1 -> act0 -> act1, layer 4
+// writes alpha to each solve's z.  act0 and act1 hold [pixels][32] BF16,
+// solve d's pixels at offset tb_h * 256.  The same alpha as
+// launch_forward_batch_list.
+hipError_t launch_layer_list(int layer, int stage, const void *packed, const Norm &nrm, const Proj &pr,
+                             const LSolve *tab, const LItem *items, const int *list, int wgs, void *act0, void *act1,
+                             hipStream_t st);
 // Workgroups of the tiled network pass resident at once on the current
 // device: its launches use at most this many, each striding over tiles and
 // staging the weights once.

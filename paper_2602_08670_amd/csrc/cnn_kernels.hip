@@ -140,13 +140,59 @@ hipError_t launch_pack(const float *master, void *packed, hipStream_t st)
 // ----------------------------------------------------------------- forward
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
-// First layer: input = states (FP32 planar) normalised and rounded to BF16
-// on the fly, K = 27 (tap*3 + ci) padded to 32, one 16-pixel group per wave;
-// bias, ReLU, BF16 NHWC out [p][32].
+// Constrained coefficients of one group of six (side 0: left state, 1: right
+// state), in place: alpha_k = base_k + sum_j P[k][j] z_j.
+__device__ __forceinline__ void alpha_group(float *zz, int side, const Proj &pr)
+{
+    float zv[6], al[6];
+#pragma unroll
+    for (int j = 0; j < 6; j++) zv[j] = zz[j];
+#pragma unroll
+    for (int k = 0; k < 6; k++) {
+        al[k] = pr.base[side * 6 + k];
+#pragma unroll
+        for (int j = 0; j < 6; j++) al[k] += pr.P[k * 6 + j] * zv[j];
+    }
+#pragma unroll
+    for (int k = 0; k < 6; k++) zz[k] = al[k];
+}
+
+// First layer on one 16-pixel group (lane (g, px): pixel (y, x) of the
+// group): input = states (FP32 planar [3][H][W]) normalised and rounded to
+// BF16 on the fly, K = 27 (tap*3 + ci) padded to 32; bias, ReLU, BF16 out
+// [32] at outp (the pixel's activation).
+__device__ __forceinline__ void first_layer_group(const float *qb, int H, int W, int y, int x, const bf16x8 *s_w,
+                                                  const float *bias, const Norm &nrm, bf16 *outp, int g, int px)
+{
+    const int hw = H * W;
+    bf16x8 bx;
+#pragma unroll
+    for (int e = 0; e < 8; e++) {
+        int k = 8 * g + e;
+        float v = 0.0f;
+        if (k < 27) {
+            int tap = k / 3, ci = k - 3 * tap;
+            int yy = wrap(y + tap / 3 - 1, H), xx = wrap(x + tap % 3 - 1, W);
+            v = (qb[(size_t)ci * hw + yy * W + xx] - nrm.mean[ci]) * nrm.inv_std[ci];
+        }
+        bx[e] = (bf16)v;
+    }
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+        const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[(t * 16 + px) * 4 + g], bx,
+                                                                    floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+        const int co0 = 16 * t + 4 * g;
+        bf16x4 o;
+#pragma unroll
+        for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[i] + bias[co0 + i], 0.0f);
+        *(bf16x4 *)(outp + co0) = o;
+    }
+}
+
+// First layer of B solves, one 16-pixel group per wave; BF16 NHWC out [p][32].
 __global__ __launch_bounds__(256) void conv_first_kernel(const float *q, const bf16 *wp, const float *bias, bf16 *out,
                                                          int B, int H, int W, Norm nrm)
 {
-    constexpr int NT = 2;
     __shared__ bf16x8 s_w[32 * 32 / 8];
     const bf16x8 *gw = (const bf16x8 *)wp;
     for (int i = threadIdx.x; i < 32 * 32 / 8; i += 256) s_w[i] = gw[i];
@@ -162,30 +208,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float *q, const b
     const int b = (int)(p / hw);
     const int rem = (int)(p - (long)b * hw);
     const int y = rem / W, x = rem - y * W;
-
-    const float *qb = q + (size_t)b * 3 * hw;
-    bf16x8 bx;
-#pragma unroll
-    for (int e = 0; e < 8; e++) {
-        int k = 8 * g + e;
-        float v = 0.0f;
-        if (k < 27) {
-            int tap = k / 3, ci = k - 3 * tap;
-            int yy = wrap(y + tap / 3 - 1, H), xx = wrap(x + tap % 3 - 1, W);
-            v = (qb[(size_t)ci * hw + yy * W + xx] - nrm.mean[ci]) * nrm.inv_std[ci];
-        }
-        bx[e] = (bf16)v;
-    }
-#pragma unroll
-    for (int t = 0; t < NT; t++) {
-        const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[(t * 16 + px) * 4 + g], bx,
-                                                                    floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        const int co0 = 16 * t + 4 * g;
-        bf16x4 o;
-#pragma unroll
-        for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[i] + bias[co0 + i], 0.0f);
-        *(bf16x4 *)(out + (size_t)p * 32 + co0) = o;
-    }
+    first_layer_group(q + (size_t)b * 3 * hw, H, W, y, x, s_w, bias, nrm, out + (size_t)p * 32, g, px);
 }
 
 // 3x3 convolution over a 16-pixel-wide, 4R-row tile of one solve per
@@ -208,22 +231,29 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float *q, const b
 // EPI 2: input gradient of a hidden layer, times the ReLU mask of the
 //        previous activation (act > 0), BF16 [p][32].
 constexpr int HT = 16;  // tile width
-template <int KB, int NT, int EPI, int R>
-__global__ __launch_bounds__(256) void conv_halo_kernel(const bf16 *in, const bf16 *wp, const float *bias,
-                                                        const bf16 *mask, void *out, int H, int W)
+template <int KB, int NT, int R>
+struct HaloShape {
+    static constexpr int CG = KB * 32, OCT = CG / 8;     // channels, 16-byte octets per pixel
+    static constexpr int WEL = 9 * NT * 16 * CG;         // packed weights (BF16)
+    static constexpr int TR = 4 * R;                     // tile rows
+    static constexpr int HP = (TR + 2) * (HT + 2);       // halo pixels
+    static constexpr int BYTES = WEL * 2 + HP * OCT * 16;  // LDS: weights, then the halo
+};
+
+// The convolution of one tile (columns x0 .. x0+15, rows y0 .. y0+4R-1 of an
+// H x W NHWC input src with KB*32 channels) into acc: stage the weights and
+// the halo into smem, then lane (g, px) of wave w accumulates output pixel
+// (y0 + Rw + r, x0 + px), channels 16 t + 4 g .. +3, in acc[r][t].
+template <int KB, int NT, int R>
+__device__ __forceinline__ void halo_conv(const bf16 *src, const bf16 *wp, int H, int W, int x0, int y0, char *smem,
+                                          floatx4 (&acc)[R][NT])
 {
-    constexpr int CG = KB * 32;
-    constexpr int OCT = CG / 8;  // 16-byte octets per pixel
-    constexpr int WEL = 9 * NT * 16 * CG;
-    constexpr int TR = 4 * R;  // tile rows
-    constexpr int HP = (TR + 2) * (HT + 2);
-    __shared__ bf16x8 s_w[WEL / 8];
-    __shared__ bf16x8 s_a[HP * OCT];
+    using S = HaloShape<KB, NT, R>;
+    constexpr int OCT = S::OCT, WEL = S::WEL, TR = S::TR, HP = S::HP, CG = S::CG;
+    bf16x8 *s_w = (bf16x8 *)smem;
+    bf16x8 *s_a = (bf16x8 *)(smem + WEL * 2);
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, px = lane & 15;
-    const int x0 = blockIdx.x * HT, y0 = blockIdx.y * TR, b = blockIdx.z;
-    const size_t hw = (size_t)H * W;
-    const bf16 *src = in + (size_t)b * hw * CG;
     {
         const bf16x8 *gw = (const bf16x8 *)wp;
         for (int i = tid; i < WEL / 8; i += 256) s_w[i] = gw[i];
@@ -238,8 +268,7 @@ __global__ __launch_bounds__(256) void conv_halo_kernel(const bf16 *in, const bf
         }
     }
     __syncthreads();
-
-    floatx4 acc[R][NT];
+    static_assert(TR == 4 * R, "tile rows");
 #pragma unroll
     for (int r = 0; r < R; r++)
 #pragma unroll
@@ -263,6 +292,20 @@ __global__ __launch_bounds__(256) void conv_halo_kernel(const bf16 *in, const bf
                     acc[r][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[t], bx[r], acc[r][t], 0, 0, 0);
         }
     }
+}
+
+template <int KB, int NT, int EPI, int R>
+__global__ __launch_bounds__(256) void conv_halo_kernel(const bf16 *in, const bf16 *wp, const float *bias,
+                                                        const bf16 *mask, void *out, int H, int W)
+{
+    using S = HaloShape<KB, NT, R>;
+    __shared__ __align__(16) char smem[S::BYTES];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, px = lane & 15;
+    const int x0 = blockIdx.x * HT, y0 = blockIdx.y * S::TR, b = blockIdx.z;
+    const size_t hw = (size_t)H * W;
+    floatx4 acc[R][NT];
+    halo_conv<KB, NT, R>(in + (size_t)b * hw * S::CG, wp, H, W, x0, y0, smem, acc);
 
 #pragma unroll
     for (int r = 0; r < R; r++) {
@@ -316,6 +359,146 @@ static void launch_halo(const bf16 *in, const bf16 *wp, const float *bias, const
     if (R == 4) hipLaunchKernelGGL((conv_halo_kernel<KB, NT, EPI, 4>), grid, blk, 0, st, in, wp, bias, mask, out, ny, nx);
     else if (R == 2) hipLaunchKernelGGL((conv_halo_kernel<KB, NT, EPI, 2>), grid, blk, 0, st, in, wp, bias, mask, out, ny, nx);
     else hipLaunchKernelGGL((conv_halo_kernel<KB, NT, EPI, 1>), grid, blk, 0, st, in, wp, bias, mask, out, ny, nx);
+}
+
+// ------------------------------------------- layer-by-layer work lists
+// The network pass of a round's listed learned solves, one launch per layer
+// on 16 x 16 tiles (nx, ny multiples of 16): workgroup w is tile w of the
+// list (items' tb_h prefix, binary search).  Solve d's activations are NHWC
+// [ny][nx][32] BF16 at pixel offset tb_h * 256 of two ping-pong buffers.
+// Layer 0 reads q (stage 1) or S1 (stage 2); the last layer writes
+// alpha = base + P z (per group of six) to d.z.  Per output the arithmetic is
+// the one-launch pass's, so alpha is the same bits.  The tile count is read
+// from the list header (list = {items, network tiles, stage tiles, 16 x 16
+// tiles}); workgroups past it exit.
+__device__ __forceinline__ LItem find_item_h(const LItem *__restrict__ items, int n, int w)
+{
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].tb_h <= w) lo = mid;
+        else hi = mid - 1;
+    }
+    return items[lo];
+}
+
+template <int STAGE>
+__global__ __launch_bounds__(256) void conv_first_list_kernel(const LSolve *__restrict__ tab,
+                                                              const LItem *__restrict__ items,
+                                                              const int *__restrict__ list, const bf16 *wp,
+                                                              const float *bias, bf16 *act, Norm nrm)
+{
+    const int w = blockIdx.x;
+    if (w >= list[3]) return;
+    __shared__ bf16x8 s_w[32 * 32 / 8];
+    const bf16x8 *gw = (const bf16x8 *)wp;
+    for (int i = threadIdx.x; i < 32 * 32 / 8; i += 256) s_w[i] = gw[i];
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, px = lane & 15;
+    const LItem it = find_item_h(items, list[0], w);
+    const LSolve &d = tab[it.solve];
+    const int tile = w - it.tb_h, tx_n = d.nx / HT;
+    const int ty = tile / tx_n, tx = tile - ty * tx_n;
+    bf16 *ab = act + (size_t)it.tb_h * HT * HT * 32;
+    const int x = tx * HT + px;
+#pragma unroll
+    for (int r = 0; r < 4; r++) {
+        const int y = ty * HT + wave * 4 + r;
+        first_layer_group(STAGE == 1 ? d.q : d.s1, d.ny, d.nx, y, x, s_w, bias, nrm,
+                          ab + ((size_t)y * d.nx + x) * 32, g, px);
+    }
+}
+
+// EPI 0: hidden layer (+ bias, ReLU, BF16 act); EPI 1: last layer (+ bias,
+// then alpha through LDS, FP32 [ny][nx][72] to d.z).
+template <int NT, int EPI>
+__global__ __launch_bounds__(256) void conv_halo_list_kernel(const LSolve *__restrict__ tab,
+                                                             const LItem *__restrict__ items,
+                                                             const int *__restrict__ list, const bf16 *wp,
+                                                             const float *bias, const bf16 *in, bf16 *out, Proj pr)
+{
+    using S = HaloShape<1, NT, 4>;
+    constexpr int ZB = EPI == 1 ? HT * HT * 72 * 4 : 0;  // the tile's z for the alpha epilogue
+    __shared__ __align__(16) char smem[S::BYTES > ZB ? S::BYTES : ZB];
+    const int w = blockIdx.x;
+    if (w >= list[3]) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int g = lane >> 4, px = lane & 15;
+    const LItem it = find_item_h(items, list[0], w);
+    const LSolve &d = tab[it.solve];
+    const int tile = w - it.tb_h, tx_n = d.nx / HT;
+    const int ty = tile / tx_n, tx = tile - ty * tx_n;
+    const int x0 = tx * HT, y0 = ty * HT;
+    const size_t off = (size_t)it.tb_h * HT * HT;  // the solve's first pixel in the activation buffers
+    floatx4 acc[4][NT];
+    halo_conv<1, NT, 4>(in + off * 32, wp, d.ny, d.nx, x0, y0, smem, acc);
+    if (EPI == 0) {
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const size_t p = off + (size_t)(y0 + wave * 4 + r) * d.nx + x0 + px;
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const int co0 = 16 * t + 4 * g;
+                bf16x4 o;
+#pragma unroll
+                for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[r][t][i] + bias[co0 + i], 0.0f);
+                *(bf16x4 *)(out + p * 32 + co0) = o;
+            }
+        }
+    } else {
+        float *s_z = (float *)smem;  // [256 tile pixels][72]
+        __syncthreads();             // the MFMAs' LDS reads are done
+#pragma unroll
+        for (int r = 0; r < 4; r++) {
+            const int pl = (wave * 4 + r) * HT + px;
+#pragma unroll
+            for (int t = 0; t < NT; t++) {
+                const int co0 = 16 * t + 4 * g;
+                if (co0 < 72) {
+                    floatx4 o;
+#pragma unroll
+                    for (int i = 0; i < 4; i++) o[i] = acc[r][t][i] + bias[co0 + i];
+                    *(floatx4 *)(s_z + pl * 72 + co0) = o;
+                }
+            }
+        }
+        __syncthreads();
+        for (int task = threadIdx.x; task < HT * HT * 12; task += 256) {
+            const int pl = task / 12, grp = task - pl * 12;
+            alpha_group(s_z + pl * 72 + grp * 6, (grp / 3) & 1, pr);
+        }
+        __syncthreads();
+        // each tile row's 16 x 72 values are contiguous in d.z
+        constexpr int RV = HT * 72 / 4;  // float4 per tile row
+        for (int i = threadIdx.x; i < HT * RV; i += 256) {
+            const int row = i / RV, c = i - row * RV;
+            ((float4 *)(d.z + ((size_t)(y0 + row) * d.nx + x0) * 72))[c] = ((const float4 *)(s_z + row * HT * 72))[c];
+        }
+    }
+}
+
+hipError_t launch_layer_list(int layer, int stage, const void *packed, const Norm &nrm, const Proj &pr,
+                             const LSolve *tab, const LItem *items, const int *list, int wgs, void *act0, void *act1,
+                             hipStream_t st)
+{
+    const Packed pk = packed_layout();
+    const char *P = (const char *)packed;
+    const dim3 grid((unsigned)(wgs > 0 ? wgs : 1)), blk(256);
+    bf16 *a[2] = {(bf16 *)act0, (bf16 *)act1};
+    const bf16 *w = (const bf16 *)(P + pk.w[layer]);
+    const float *b = (const float *)(P + pk.b[layer]);
+    if (layer == 0) {
+        if (stage == 1) hipLaunchKernelGGL(conv_first_list_kernel<1>, grid, blk, 0, st, tab, items, list, w, b, a[0], nrm);
+        else hipLaunchKernelGGL(conv_first_list_kernel<2>, grid, blk, 0, st, tab, items, list, w, b, a[0], nrm);
+    } else if (layer < 4) {
+        hipLaunchKernelGGL((conv_halo_list_kernel<2, 0>), grid, blk, 0, st, tab, items, list, w, b,
+                           (const bf16 *)a[(layer - 1) & 1], a[layer & 1], pr);
+    } else {
+        hipLaunchKernelGGL((conv_halo_list_kernel<5, 1>), grid, blk, 0, st, tab, items, list, w, b,
+                           (const bf16 *)a[1], (bf16 *)nullptr, pr);
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny,
@@ -709,19 +892,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
         // replaces z in place
         for (int task = threadIdx.x; task < FO * FO * 12; task += FNW * 64) {
             const int p = task / 12, grp = task - p * 12;
-            const int side = (grp / 3) & 1;
-            float *zz = s_z + p * 72 + grp * 6;
-            float zv[6], al[6];
-#pragma unroll
-            for (int j = 0; j < 6; j++) zv[j] = zz[j];
-#pragma unroll
-            for (int k = 0; k < 6; k++) {
-                al[k] = pr.base[side * 6 + k];
-#pragma unroll
-                for (int j = 0; j < 6; j++) al[k] += pr.P[k * 6 + j] * zv[j];
-            }
-#pragma unroll
-            for (int k = 0; k < 6; k++) zz[k] = al[k];
+            alpha_group(s_z + p * 72 + grp * 6, (grp / 3) & 1, pr);
         }
         __syncthreads();
         // each tile row's 8 x 72 values, contiguous in the output, leave as

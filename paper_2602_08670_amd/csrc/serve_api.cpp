@@ -93,7 +93,7 @@ struct fv_server {
     hipStream_t stream;
     std::chrono::steady_clock::time_point t0;
     // pool regions
-    size_t tab_off, items_off, nitems_off, scratch_off, ltab_off, litems_off, lnitems_off, heap_off;
+    size_t tab_off, items_off, nitems_off, scratch_off, ltab_off, litems_off, lnitems_off, act_off, heap_off;
     std::map<size_t, size_t> free_list;  // offset -> size
     // host side
     std::deque<Req *> queue;
@@ -108,11 +108,12 @@ struct fv_server {
     int *h_lnitems = nullptr;
     std::vector<cnn::LSolve> h_ltab;
     hipStream_t own_stream = nullptr;  // created when the caller passes the null stream
-    // captured rounds, keyed by the kinds of work present | steps << 3
+    // captured rounds, keyed by the kinds of work present | steps << 5
     std::map<int, RoundGraph> graphs;
-    int64_t rounds = 0, replays = 0, grid_updates = 0;
+    int64_t rounds = 0, replays = 0, grid_updates = 0, layered_rounds = 0;
     int cnn_cap = 256;  // most workgroups of a network-pass launch
     int split_at = 1024;  // network tiles from which a round's learned steps use separate launches
+    int layered_at = 768;  // 16 x 16 tiles from which such a round's network pass runs layer by layer (-1: never)
     double launch_s = 0, wait_s = 0;  // host time enqueueing rounds' work, and waiting for it
     double capture_s = 0;             // host time capturing and instantiating graphs
     double admit_s = 0, retire_s = 0;  // host time admitting requests and retiring finished ones
@@ -171,6 +172,7 @@ void free_host(fv_server *s)
 // headers on the device: plain {items, tiles}, learned {items, network
 // tiles, stage tiles, 0}
 constexpr int HDR = 2, LHDR = 4;
+constexpr size_t ACT_BYTES = 2 * 32 * 2;  // per cell: two BF16 32-channel activations
 size_t items_capacity(const fv_server_config *c) { return (size_t)c->steps_per_round * 2 * c->max_solves; }
 
 fv_status validate(const fv_server_config *c)
@@ -180,7 +182,8 @@ fv_status validate(const fv_server_config *c)
         return fail(FV_E_INVALID, "max_solves, steps_per_round and max_items must be >= 1");
     if (c->max_items > (uint64_t)1 << 31) return fail(FV_E_INVALID, "max_items above 2^31");
     if (c->direct != 0 && c->direct != 1) return fail(FV_E_INVALID, "direct must be 0 or 1");
-    if (c->learned_split < 0 || c->reserved1 != 0) return fail(FV_E_INVALID, "learned_split < 0 or reserved1 != 0");
+    if (c->learned_split < 0 || c->learned_layered < -1) return fail(FV_E_INVALID, "learned_split < 0 or learned_layered < -1");
+    if (c->act_pixels > ((uint64_t)1 << 34)) return fail(FV_E_INVALID, "act_pixels above 2^34");
     return FV_OK;
 }
 
@@ -196,6 +199,7 @@ size_t overhead(const fv_server_config *c)
     o += align256(sizeof(cnn::LSolve) * c->max_solves);
     o += align256(litems_capacity(c) * sizeof(cnn::LItem));
     o += align256((size_t)c->steps_per_round * LHDR * sizeof(int));
+    o += align256((size_t)c->act_pixels * ACT_BYTES);
     return o;
 }
 
@@ -325,13 +329,14 @@ fv_status admit(fv_server *s, Req *q, std::vector<Req *> &need_h0)
 
 // Launches of steps 0..nsteps-1 of a round over the uploaded lists, kinds
 // of work in mask (1 SWE, 2 Euler, 4 learned, 8 learned steps with the
-// network pass and the learned stage as separate launches).  rec == NULL: direct launches
+// network pass and the learned stage as separate launches, 16 that network
+// pass layer by layer).  rec == NULL: direct launches
 // of one workgroup per tile with the given per-list tile counts, empty lists
 // skipped.  rec != NULL (graph capture): every launch of the mask, the tile
 // counts read from the list headers, each node recorded in rec; its grid is
 // a placeholder set before each replay.
 hipError_t enqueue_steps(fv_server *s, int mask, int nsteps, const int *grids, const int *lgrid_cnn,
-                         const int *lgrid_st, std::vector<GraphNode> *rec)
+                         const int *lgrid_st, const int *lgrid_h, std::vector<GraphNode> *rec)
 {
     char *P = s->pool;
     const size_t ncap = (size_t)s->cfg.max_solves;
@@ -371,8 +376,9 @@ hipError_t enqueue_steps(fv_server *s, int mask, int nsteps, const int *grids, c
         if (!(mask & 4) || e != hipSuccess || (!rec && !lgrid_st[k])) continue;
         // learned solves: the network pass and learned stage of every
         // learned solve in one launch per stage (coefficients on chip), or,
-        // with mask bit 8, a network-pass launch writing alpha and a
-        // learned-stage launch per stage; then commit-or-redo and redo.
+        // with mask bit 8, a network-pass launch writing alpha (with mask
+        // bit 16: five launches, one per layer) and a learned-stage launch
+        // per stage; then commit-or-redo and redo.
         // Kind -2: fused pass, -1: network pass, >= 0: learned-stage mode.
         const cnn::LItem *it = d_litems + (size_t)k * ncap;
         const int *hdr = d_lnitems + (size_t)k * LHDR;
@@ -382,6 +388,15 @@ hipError_t enqueue_steps(fv_server *s, int mask, int nsteps, const int *grids, c
         const int nl = split ? 6 : 4;
         for (int j = 0; j < nl && e == hipSuccess; j++) {
             const int md = split ? smode[j] : fmode[j], sg = split ? sstg[j] : fstg[j];
+            if (md == -1 && (mask & 16)) {
+                void *a0 = P + s->act_off, *a1 = P + s->act_off + (size_t)s->cfg.act_pixels * (ACT_BYTES / 2);
+                for (int layer = 0; layer < 5 && e == hipSuccess; layer++) {
+                    e = cnn::launch_layer_list(layer, sg, m->packed, m->nrm, m->pr, ltab, it, hdr,
+                                               rec ? 1 : lgrid_h[k], a0, a1, s->stream);
+                    if (e == hipSuccess && rec) e = record(3, k);
+                }
+                continue;
+            }
             if (!rec) {
                 if (md == -2) e = cnn::launch_conv_learned(sg, m->packed, m->nrm, m->pr, ltab, it, hdr, lgrid_cnn[k],
                                                            s->stream);
@@ -404,7 +419,7 @@ hipError_t enqueue_steps(fv_server *s, int mask, int nsteps, const int *grids, c
 // instantiated on first use.
 fv_status round_graph(fv_server *s, int mask, int nsteps, RoundGraph **out)
 {
-    const int key = mask | nsteps << 4;
+    const int key = mask | nsteps << 5;
     auto f = s->graphs.find(key);
     if (f != s->graphs.end()) {
         *out = &f->second;
@@ -414,7 +429,7 @@ fv_status round_graph(fv_server *s, int mask, int nsteps, RoundGraph **out)
     const double t0 = s->now();
     hipError_t e = hipStreamBeginCapture(s->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(e, "graph capture");
-    const hipError_t le = enqueue_steps(s, mask, nsteps, nullptr, nullptr, nullptr, &rg.nodes);
+    const hipError_t le = enqueue_steps(s, mask, nsteps, nullptr, nullptr, nullptr, nullptr, &rg.nodes);
     e = hipStreamEndCapture(s->stream, &rg.g);
     if (e == hipSuccess) e = le;
     for (size_t i = 0; i < rg.nodes.size() && e == hipSuccess; i++)
@@ -431,12 +446,14 @@ fv_status round_graph(fv_server *s, int mask, int nsteps, RoundGraph **out)
 
 // Before a replay: every node's grid from its list's tile count (at least
 // one workgroup: an empty list's launch reads 0 tiles and does nothing).
-hipError_t set_grids(fv_server *s, RoundGraph *rg, const int *grids, const int *lgrid_cnn, const int *lgrid_st)
+hipError_t set_grids(fv_server *s, RoundGraph *rg, const int *grids, const int *lgrid_cnn, const int *lgrid_st,
+                     const int *lgrid_h)
 {
     for (GraphNode &n : rg->nodes) {
         int want;
         if (n.kind == 0) want = grids[n.idx] ? fvk::xcd_grid(grids[n.idx]) : 8;
         else if (n.kind == 1) want = lgrid_cnn[n.idx] ? (lgrid_cnn[n.idx] < s->cnn_cap ? lgrid_cnn[n.idx] : s->cnn_cap) : 1;
+        else if (n.kind == 3) want = lgrid_h[n.idx] ? lgrid_h[n.idx] : 1;
         else want = lgrid_st[n.idx] ? lgrid_st[n.idx] : 1;
         if ((int)n.p.gridDim.x == want) continue;
         n.p.gridDim.x = (unsigned)want;
@@ -478,6 +495,7 @@ fv_status fv_server_create(const fv_server_config *cfg, void *pool, size_t pool_
     s->ltab_off = s->scratch_off + align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * 8 + 256);
     s->litems_off = s->ltab_off + align256(sizeof(cnn::LSolve) * cfg->max_solves);
     s->lnitems_off = s->litems_off + align256(litems_capacity(cfg) * sizeof(cnn::LItem));
+    s->act_off = s->lnitems_off + align256((size_t)cfg->steps_per_round * LHDR * sizeof(int));
     s->heap_off = ov;
     s->free_list[s->heap_off] = pool_bytes - s->heap_off;
     s->h_tab.assign(cfg->max_solves, fvk::BatchSolve{});
@@ -494,6 +512,7 @@ fv_status fv_server_create(const fv_server_config *cfg, void *pool, size_t pool_
     }
     if (cfg->model) s->cnn_cap = cnn::fused_max_grid();
     s->split_at = cfg->learned_split > 0 ? cfg->learned_split : 4 * s->cnn_cap;
+    s->layered_at = cfg->learned_layered > 0 ? cfg->learned_layered : (cfg->learned_layered == 0 ? 768 : -1);
     if (!stream) {
         // graphs cannot be captured on the null stream: the server then
         // runs on a stream of its own (default priority)
@@ -623,7 +642,8 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
     // back; tiles per launch are capped by max_items
     const size_t ncap = (size_t)s->cfg.max_solves;
     std::vector<int> counts((size_t)K * 2, 0), grids((size_t)K * 2, 0);
-    std::vector<int> lcounts((size_t)K, 0), lgrid_cnn((size_t)K, 0), lgrid_st((size_t)K, 0);
+    std::vector<int> lcounts((size_t)K, 0), lgrid_cnn((size_t)K, 0), lgrid_st((size_t)K, 0), lgrid_h((size_t)K, 0);
+    bool all16 = true;  // every learned side a multiple of 16 (the layer-by-layer pass's tiles)
     for (int k = 0; k < K; k++)
         for (Req *q : s->active) {
             if (q->r.steps - q->done_steps <= k) continue;
@@ -637,9 +657,12 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
                 w.tb_cnn = lgrid_cnn[k];
                 w.tb_st = lgrid_st[k];
                 w.parity = (int)((q->done_steps + k) & 1);
+                w.tb_h = lgrid_h[k];
                 lcounts[k]++;
                 lgrid_cnn[k] += tc;
                 lgrid_st[k] += ts;
+                if (q->r.n % 16) all16 = false;
+                else lgrid_h[k] += (q->r.n / 16) * (q->r.n / 16);
                 continue;
             }
             int type = q->r.eqn == FV_EULER ? 1 : 0;
@@ -669,6 +692,11 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
     // (the network pass then strides over tiles at full occupancy of the
     // learned stage); few: one launch per stage, coefficients on chip
     if ((mask & 4) && lgrid_cnn[0] >= s->split_at) mask |= 8;
+    // many more: the network pass layer by layer (activations in the pool's
+    // scratch; a step's lists only shrink over the round)
+    if ((mask & 8) && all16 && s->layered_at > 0 && lgrid_h[0] >= s->layered_at &&
+        (uint64_t)lgrid_h[0] * 256 <= s->cfg.act_pixels)
+        mask |= 16;
     for (size_t li = 0; li < counts.size(); li++) {
         s->h_nitems[li * HDR] = counts[li];
         s->h_nitems[li * HDR + 1] = grids[li];
@@ -690,7 +718,7 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
         s->h_lnitems[k * LHDR] = lcounts[k];
         s->h_lnitems[k * LHDR + 1] = lgrid_cnn[k];
         s->h_lnitems[k * LHDR + 2] = lgrid_st[k];
-        s->h_lnitems[k * LHDR + 3] = 0;
+        s->h_lnitems[k * LHDR + 3] = lgrid_h[k];
         if (lcounts[k]) lused = (size_t)k * ncap + lcounts[k];
     }
     if (e == hipSuccess && lused)
@@ -700,9 +728,10 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
                            s->stream);
     if (e != hipSuccess) return hip_fail(e, "work-list upload");
     if (nsteps) s->rounds++;
+    if (nsteps && (mask & 16)) s->layered_rounds++;
     const double tl0 = s->now();
     if (s->cfg.direct) {
-        e = enqueue_steps(s, mask, nsteps, grids.data(), lgrid_cnn.data(), lgrid_st.data(), nullptr);
+        e = enqueue_steps(s, mask, nsteps, grids.data(), lgrid_cnn.data(), lgrid_st.data(), lgrid_h.data(), nullptr);
     } else if (nsteps) {
         // the round's launches are one captured graph per (kinds present,
         // steps rounded up to a power of two); between replays only the
@@ -713,7 +742,7 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
         RoundGraph *rg = nullptr;
         fv_status rc = round_graph(s, mask, ng, &rg);
         if (rc != FV_OK) return rc;
-        e = set_grids(s, rg, grids.data(), lgrid_cnn.data(), lgrid_st.data());
+        e = set_grids(s, rg, grids.data(), lgrid_cnn.data(), lgrid_st.data(), lgrid_h.data());
         if (e == hipSuccess) e = hipGraphLaunch(rg->x, s->stream);
         s->replays++;
     }
@@ -766,6 +795,7 @@ fv_status fv_server_get_stats(fv_server *s, fv_server_stats *out)
     out->graph_replays = s->replays;
     out->grid_updates = s->grid_updates;
     out->graphs_captured = (int32_t)s->graphs.size();
+    out->layered_rounds = (int32_t)s->layered_rounds;
     out->host_launch_s = s->launch_s;
     out->host_wait_s = s->wait_s;
     out->host_capture_s = s->capture_s;

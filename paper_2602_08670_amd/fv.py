@@ -65,7 +65,8 @@ class fv_train_config(ctypes.Structure):
 class fv_server_config(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_solves", ctypes.c_int32),
                 ("steps_per_round", ctypes.c_int32), ("direct", ctypes.c_int32), ("max_items", ctypes.c_uint64),
-                ("model", ctypes.c_void_p), ("learned_split", ctypes.c_int32), ("reserved1", ctypes.c_int32)]
+                ("model", ctypes.c_void_p), ("learned_split", ctypes.c_int32), ("learned_layered", ctypes.c_int32),
+                ("act_pixels", ctypes.c_uint64)]
 
 
 class fv_request(ctypes.Structure):
@@ -84,7 +85,7 @@ class fv_request_info(ctypes.Structure):
 
 class fv_server_stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_int64), ("graph_replays", ctypes.c_int64), ("grid_updates", ctypes.c_int64),
-                ("graphs_captured", ctypes.c_int32), ("pad", ctypes.c_int32), ("host_launch_s", ctypes.c_double),
+                ("graphs_captured", ctypes.c_int32), ("layered_rounds", ctypes.c_int32), ("host_launch_s", ctypes.c_double),
                 ("host_wait_s", ctypes.c_double), ("host_capture_s", ctypes.c_double),
                 ("host_admit_s", ctypes.c_double), ("host_retire_s", ctypes.c_double)]
 
@@ -436,20 +437,26 @@ class Server:
 
     def __init__(self, pool_bytes: int, max_solves: int = 1024, steps_per_round: int = 24,
                  max_items: int = 1 << 18, device="cuda", stream=None, model=None, direct=False,
-                 learned_split: int = 0):
+                 learned_split: int = 0, learned_layered: int = 0, act_pixels: int | None = None):
         """direct: launch every kernel of a round directly instead of replaying
         the round's captured graph (same results).  learned_split: network
         tiles in a round's first step from which the round runs the network
         pass and the learned stage as separate launches (0: the library's
-        default)."""
+        default).  learned_layered: 16 x 16 tiles from which such a round's
+        network pass runs layer by layer (0: the library's default, -1:
+        never); act_pixels: cells of its activation scratch, 128 bytes each
+        out of the pool (None: with a model, an eighth of the pool up to 64 Mi
+        cells; without, none)."""
         import torch
 
         self.model = model  # kept alive while the server runs
         if model is not None:
             torch.cuda.synchronize()  # the model's packed weights are ready
+        if act_pixels is None:
+            act_pixels = min(pool_bytes // 8 // 128, 1 << 26) if model is not None else 0
         self.cfg = fv_server_config(ctypes.sizeof(fv_server_config), max_solves, steps_per_round,
                                     1 if direct else 0, max_items, None if model is None else model.h,
-                                    int(learned_split), 0)
+                                    int(learned_split), int(learned_layered), int(act_pixels))
         # zero-filled: the pool's pages are mapped here rather than by the
         # first rounds that reach them
         self.pool = torch.zeros(pool_bytes, dtype=torch.uint8, device=device)

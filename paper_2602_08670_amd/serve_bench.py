@@ -129,6 +129,7 @@ def run_server(stream, ics, arr, pool_bytes=24 << 30, steps_per_round=32, max_so
     st = srv.stats()
     run_server.last_stats = {"rounds": st.rounds, "graph_replays": st.graph_replays,
                              "graphs_captured": st.graphs_captured, "grid_updates": st.grid_updates,
+                             "layered_rounds": st.layered_rounds,
                              "host_launch_s": st.host_launch_s, "host_wait_s": st.host_wait_s,
                              "host_capture_s": st.host_capture_s, "host_admit_s": st.host_admit_s,
                              "host_retire_s": st.host_retire_s}

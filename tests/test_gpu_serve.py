@@ -233,10 +233,11 @@ def test_graph_replay_equals_direct_launches(fv):
 
 
 def test_learned_split_and_fused_rounds_agree(fv):
-    """The two launch forms of a learned step -- the network pass and the
-    learned stage fused per stage with the coefficients in LDS, or separate
-    launches with alpha through HBM -- give the same bits (state, time,
-    fallback and redo counts), so a server may pick either per round."""
+    """The three launch forms of a learned step -- the network pass and the
+    learned stage fused per stage with the coefficients in LDS, separate
+    launches with alpha through HBM, and separate launches with the network
+    pass layer by layer on 16 x 16 tiles -- give the same bits (state, time,
+    fallback and redo counts), so a server may pick any per round."""
     from paper_2602_08670_amd import learned_solver as LS
 
     # zero last-layer weights and large per-channel biases: constant
@@ -249,8 +250,9 @@ def test_learned_split_and_fused_rounds_agree(fv):
     dt = LS.fine_dt(2048) * 32
     specs = [(32, 1, 13), (64, 2, 9), (128, 3, 7), (256, 4, 5)]
     runs = []
-    for split in (1, 1 << 30):
-        srv = fv.Server(1 << 30, max_solves=8, steps_per_round=4, max_items=1 << 16, model=m, learned_split=split)
+    for split, layered in ((1, -1), (1 << 30, 0), (1, 1)):
+        srv = fv.Server(1 << 30, max_solves=8, steps_per_round=4, max_items=1 << 16, model=m, learned_split=split,
+                        learned_layered=layered)
         ids = []
         for n, seed, steps in specs:
             q = I.random_smooth_swe(n, seed=seed).astype(np.float32)
@@ -263,15 +265,21 @@ def test_learned_split_and_fused_rounds_agree(fv):
         for rid, shape in ids:
             inf = srv.info(rid)
             out.append((srv.result(rid, shape), inf.state, inf.sim_time, inf.fallback_faces, inf.redone_steps))
+        st = srv.stats()
+        print(f"[serve split] split {split} layered {layered}: {st.rounds} rounds, {st.layered_rounds} layer by layer",
+              flush=True)
+        assert (st.layered_rounds > 0) == (layered == 1)
         srv.close()
         runs.append(out)
     fb = [o[3] for o in runs[0]]
     print(f"[serve split] fallback faces per request {fb}", flush=True)
     assert sum(fb) > 0  # the comparison covers fallback faces
-    for spec, a, b in zip(specs, runs[0], runs[1]):
+    for spec, a, b, c in zip(specs, runs[0], runs[1], runs[2]):
         assert a[1] in (2, 3), spec
         assert np.array_equal(a[0], b[0], equal_nan=True), spec
         assert a[1:] == b[1:], spec
+        assert np.array_equal(a[0], c[0], equal_nan=True), spec
+        assert a[1:] == c[1:], spec
     # the single-solve step picks its form by the same rule (256^2 and up:
     # separate launches) and matches both
     done = 0
