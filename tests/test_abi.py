@@ -55,3 +55,25 @@ def test_workspace_sizes(fv):
     state = 3 * 1024 * 1024 * 4
     assert fv.fv_workspace_bytes(c3) - fv.fv_workspace_bytes(c2) == state
     assert fv.fv_workspace_bytes(c2) >= state
+
+
+def test_server_config_validation_and_activation_scratch(fv):
+    """The layer-by-layer network pass's activation scratch is counted in the
+    pool overhead at 128 bytes per cell; out-of-range serving settings are
+    rejected (overhead 0) without touching a device."""
+
+    def overhead(**kw):
+        c = fv.fv_server_config(ctypes.sizeof(fv.fv_server_config), 8, 4, 0, 1 << 14)
+        for k, v in kw.items():
+            setattr(c, k, v)
+        return fv.lib.fv_server_pool_overhead(ctypes.byref(c))
+
+    base = overhead()
+    assert base > 0
+    assert overhead(act_pixels=1 << 20) - base == 128 << 20
+    assert overhead(act_pixels=1000) - base == (128 * 1000 + 255) // 256 * 256
+    assert overhead(learned_layered=-1) == base and overhead(learned_layered=5) == base
+    assert overhead(learned_layered=-2) == 0
+    assert overhead(act_pixels=(1 << 34) + 1) == 0
+    assert overhead(learned_split=-1) == 0
+    assert overhead(direct=2) == 0
