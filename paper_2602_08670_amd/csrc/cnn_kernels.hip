@@ -157,58 +157,74 @@ __device__ __forceinline__ void alpha_group(float *zz, int side, const Proj &pr)
     for (int k = 0; k < 6; k++) zz[k] = al[k];
 }
 
-// First layer on one 16-pixel group (lane (g, px): pixel (y, x) of the
-// group): input = states (FP32 planar [3][H][W]) normalised and rounded to
-// BF16 on the fly, K = 27 (tap*3 + ci) padded to 32; bias, ReLU, BF16 out
-// [32] at outp (the pixel's activation).
-__device__ __forceinline__ void first_layer_group(const float *qb, int H, int W, int y, int x, const bf16x8 *s_w,
-                                                  const float *bias, const Norm &nrm, bf16 *outp, int g, int px)
+constexpr int HT = 16;  // width of the layer-by-layer pass's tiles
+
+// First layer on a 16-pixel-wide, 4R-row tile (columns x0 .. x0+15, rows
+// y0 .. y0+4R-1 of an H x W solve): the normalised, BF16-rounded input of the
+// tile's halo is staged in LDS once ([3][4R + 2][18]), then lane (g, px) of
+// wave w builds its K = 27 operand from LDS for rows Rw .. Rw+R-1 and
+// stores act[(y * W + x) * 32 ..].  Input = states (FP32 planar [3][H][W])
+// normalised per channel and rounded to BF16, K = 27 (tap*3 + ci) padded to
+// 32; bias, ReLU, BF16 out.  Rows past H are not stored.
+template <int R>
+__device__ __forceinline__ void first_layer_tile(const float *qb, int H, int W, int x0, int y0, bf16x8 *s_w,
+                                                 bf16 *s_q, const float *bias, const Norm &nrm, bf16 *act)
 {
+    constexpr int HR = 4 * R + 2, HC = HT + 2;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, px = lane & 15;
     const int hw = H * W;
-    bf16x8 bx;
-#pragma unroll
-    for (int e = 0; e < 8; e++) {
-        int k = 8 * g + e;
-        float v = 0.0f;
-        if (k < 27) {
-            int tap = k / 3, ci = k - 3 * tap;
-            int yy = wrap(y + tap / 3 - 1, H), xx = wrap(x + tap % 3 - 1, W);
-            v = (qb[(size_t)ci * hw + yy * W + xx] - nrm.mean[ci]) * nrm.inv_std[ci];
-        }
-        bx[e] = (bf16)v;
+    for (int i = tid; i < 3 * HR * HC; i += 256) {
+        const int ci = i / (HR * HC), r = i - ci * (HR * HC);
+        const int hr = r / HC, hc = r - hr * HC;
+        int yy = y0 - 1 + hr;
+        yy = yy < 0 ? yy + H : yy % H;
+        const int xx = wrap(x0 - 1 + hc, W);
+        s_q[i] = (bf16)((qb[(size_t)ci * hw + yy * W + xx] - nrm.mean[ci]) * nrm.inv_std[ci]);
     }
+    __syncthreads();
 #pragma unroll
-    for (int t = 0; t < 2; t++) {
-        const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[(t * 16 + px) * 4 + g], bx,
-                                                                    floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-        const int co0 = 16 * t + 4 * g;
-        bf16x4 o;
+    for (int rr = 0; rr < R; rr++) {
+        const int ry = wave * R + rr, y = y0 + ry;
+        bf16x8 bx;
 #pragma unroll
-        for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[i] + bias[co0 + i], 0.0f);
-        *(bf16x4 *)(outp + co0) = o;
+        for (int e = 0; e < 8; e++) {
+            const int k = 8 * g + e;
+            bf16 v = (bf16)0.0f;
+            if (k < 27) {
+                const int tap = k / 3, ci = k - 3 * tap;
+                v = s_q[(ci * HR + ry + tap / 3) * HC + px + tap % 3];
+            }
+            bx[e] = v;
+        }
+        if (y >= H) continue;
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+            const floatx4 acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[(t * 16 + px) * 4 + g], bx,
+                                                                        floatx4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+            const int co0 = 16 * t + 4 * g;
+            bf16x4 o;
+#pragma unroll
+            for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[i] + bias[co0 + i], 0.0f);
+            *(bf16x4 *)(act + ((size_t)y * W + x0 + px) * 32 + co0) = o;
+        }
     }
 }
 
-// First layer of B solves, one 16-pixel group per wave; BF16 NHWC out [p][32].
+// First layer of B solves on 16-pixel-wide, 4R-row tiles (grid: tile
+// columns, tile rows, solves); BF16 NHWC out [p][32].
+template <int R>
 __global__ __launch_bounds__(256) void conv_first_kernel(const float *q, const bf16 *wp, const float *bias, bf16 *out,
-                                                         int B, int H, int W, Norm nrm)
+                                                         int H, int W, Norm nrm)
 {
     __shared__ bf16x8 s_w[32 * 32 / 8];
+    __shared__ bf16 s_q[3 * (4 * R + 2) * (HT + 2)];
     const bf16x8 *gw = (const bf16x8 *)wp;
     for (int i = threadIdx.x; i < 32 * 32 / 8; i += 256) s_w[i] = gw[i];
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 4, px = lane & 15;
-    const long npix = (long)B * H * W;
-    const long p0 = ((long)blockIdx.x * 4 + wave) * 16;
-    if (p0 >= npix) return;
-    const long p = p0 + px;
-    const int hw = H * W;
-    const int b = (int)(p / hw);
-    const int rem = (int)(p - (long)b * hw);
-    const int y = rem / W, x = rem - y * W;
-    first_layer_group(q + (size_t)b * 3 * hw, H, W, y, x, s_w, bias, nrm, out + (size_t)p * 32, g, px);
+    const int b = blockIdx.z;
+    const size_t hw = (size_t)H * W;
+    first_layer_tile<R>(q + (size_t)b * 3 * hw, H, W, blockIdx.x * HT, blockIdx.y * 4 * R, s_w, s_q, bias, nrm,
+                        out + (size_t)b * hw * 32);
 }
 
 // 3x3 convolution over a 16-pixel-wide, 4R-row tile of one solve per
@@ -230,7 +246,6 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float *q, const b
 // EPI 1: forward last layer, + bias, FP32 [p][72] (NT = 5);
 // EPI 2: input gradient of a hidden layer, times the ReLU mask of the
 //        previous activation (act > 0), BF16 [p][32].
-constexpr int HT = 16;  // tile width
 template <int KB, int NT, int R>
 struct HaloShape {
     static constexpr int CG = KB * 32, OCT = CG / 8;     // channels, 16-byte octets per pixel
@@ -391,23 +406,15 @@ __global__ __launch_bounds__(256) void conv_first_list_kernel(const LSolve *__re
     const int w = blockIdx.x;
     if (w >= list[3]) return;
     __shared__ bf16x8 s_w[32 * 32 / 8];
+    __shared__ bf16 s_q[3 * 18 * (HT + 2)];
     const bf16x8 *gw = (const bf16x8 *)wp;
     for (int i = threadIdx.x; i < 32 * 32 / 8; i += 256) s_w[i] = gw[i];
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int g = lane >> 4, px = lane & 15;
     const LItem it = find_item_h(items, list[0], w);
     const LSolve &d = tab[it.solve];
     const int tile = w - it.tb_h, tx_n = d.nx / HT;
     const int ty = tile / tx_n, tx = tile - ty * tx_n;
-    bf16 *ab = act + (size_t)it.tb_h * HT * HT * 32;
-    const int x = tx * HT + px;
-#pragma unroll
-    for (int r = 0; r < 4; r++) {
-        const int y = ty * HT + wave * 4 + r;
-        first_layer_group(STAGE == 1 ? d.q : d.s1, d.ny, d.nx, y, x, s_w, bias, nrm,
-                          ab + ((size_t)y * d.nx + x) * 32, g, px);
-    }
+    first_layer_tile<4>(STAGE == 1 ? d.q : d.s1, d.ny, d.nx, tx * HT, ty * HT, s_w, s_q, bias, nrm,
+                        act + (size_t)it.tb_h * HT * HT * 32);
 }
 
 // EPI 0: hidden layer (+ bias, ReLU, BF16 act); EPI 1: last layer (+ bias,
@@ -506,11 +513,17 @@ hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, i
 {
     const Packed pk = packed_layout();
     const char *P = (const char *)packed;
-    const long npix = (long)B * nx * ny;
     if (nx % HT) return hipErrorInvalidValue;
-    dim3 grid((unsigned)((npix + 63) / 64)), blk(256);
-    hipLaunchKernelGGL(conv_first_kernel, grid, blk, 0, st, q, (const bf16 *)(P + pk.w[0]), (const float *)(P + pk.b[0]),
-                       (bf16 *)acts[0], B, ny, nx, nrm);
+    const dim3 blk(256);
+    {
+        const int R = halo_rows(B, nx, ny);
+        const dim3 fg = halo_grid(B, nx, ny, R);
+        const bf16 *w0 = (const bf16 *)(P + pk.w[0]);
+        const float *b0 = (const float *)(P + pk.b[0]);
+        if (R == 4) hipLaunchKernelGGL(conv_first_kernel<4>, fg, blk, 0, st, q, w0, b0, (bf16 *)acts[0], ny, nx, nrm);
+        else if (R == 2) hipLaunchKernelGGL(conv_first_kernel<2>, fg, blk, 0, st, q, w0, b0, (bf16 *)acts[0], ny, nx, nrm);
+        else hipLaunchKernelGGL(conv_first_kernel<1>, fg, blk, 0, st, q, w0, b0, (bf16 *)acts[0], ny, nx, nrm);
+    }
     for (int l = 1; l < 4; l++)
         launch_halo<1, 2, 0>((const bf16 *)acts[l - 1], (const bf16 *)(P + pk.w[l]), (const float *)(P + pk.b[l]),
                              nullptr, acts[l], B, nx, ny, st);
