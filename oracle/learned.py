@@ -259,6 +259,66 @@ def learned_step(params, q, dt, dx, dy, g=9.81, flux="hlle", order=1, round_bf16
     return q2, {"fallback_faces": int(nfb.sum()), "redone": bad}
 
 
+# ---- direct face states (thesis section 5.3, planar shallow water) -------
+# The network maps the cell averages to the states at the four faces of each
+# cell, Q^l, Q^r, Q^b, Q^u (left, right, bottom, top); the flux of a face is
+# the numerical flux of the states its two cells give it, so the face is
+# shared and the scheme stays conservative.  Reading of the output: channel
+# 3f + v (f = l, r, b, u) is a correction to the cell average in the input's
+# normalised units, Q^f_v = q_v + z_{3f+v} / inv_std_v (a zero head is the
+# first-order scheme); the other output channels are unused.
+
+def direct_faces(params, q, round_bf16=True):
+    """(Ql, Qr, Qb, Qu), each (B, 3, H, W): the network's four face states of every cell."""
+    z = cnn(params, q, round_bf16)
+    sig = (1.0 / params["inv_std"])[None, :, None, None]
+    return tuple(q + sig * z[:, 3 * f:3 * f + 3] for f in range(4))
+
+
+def direct_rhs(params, q, dx, dy, g=9.81, flux="hlle", round_bf16=True):
+    """L(q) of the direct face-state scheme: the flux of face i+1/2 from
+    cell i's right state and cell i+1's left state (x), cell j's top state and
+    cell j+1's bottom state (y).  A face side whose depth is not positive takes
+    its MINMOD state (counted).  Returns (L, per-solve fallback face sides)."""
+    fn = FLUXES[flux]
+    Ql, Qr, Qb, Qu = direct_faces(params, q, round_bf16)
+    L = torch.zeros_like(q)
+    nfb = torch.zeros(q.shape[0], dtype=torch.int64)
+    for axis, (dim, d, lo, hi) in enumerate(((3, dx, Qr, Ql), (2, dy, Qu, Qb))):
+        ML, MR = minmod_faces(q, dim)
+        QL, QR = lo, _shift(hi, 1, dim)  # face i+1/2: cell i's high side, cell i+1's low side
+        okl, okr = QL[:, :1] > 0, QR[:, :1] > 0
+        nfb = nfb + (~okl).flatten(1).sum(1) + (~okr).flatten(1).sum(1)
+        QL = torch.where(okl, QL, ML)
+        QR = torch.where(okr, QR, MR)
+        nm, tm = (1, 2) if axis == 0 else (2, 1)
+        F = fn(QL[:, 0], QL[:, nm], QL[:, tm], QR[:, 0], QR[:, nm], QR[:, tm], g)
+        Fc = [None, None, None]
+        Fc[0], Fc[nm], Fc[tm] = F
+        Fc = torch.stack(Fc, dim=1)
+        L = L - (Fc - _shift(Fc, -1, dim)) / d
+    return L, nfb
+
+
+def direct_step(params, q, dt, dx, dy, g=9.81, flux="hlle", round_bf16=True):
+    """One Heun step of the direct face-state scheme, with the same
+    admissibility rule as the learned step: a solve with a non-positive depth
+    after either stage redoes the step with the plain scheme.  Returns
+    (q_next, stats) as learned_step."""
+    L0, f0 = direct_rhs(params, q, dx, dy, g, flux, round_bf16)
+    q1 = q + dt * L0
+    bad1 = (q1[:, 0] <= 0).flatten(1).any(dim=1)
+    q1s = torch.where(bad1[:, None, None, None], q, q1)
+    L1, f1 = direct_rhs(params, q1s, dx, dy, g, flux, round_bf16)
+    q2 = 0.5 * q + 0.5 * (q1s + dt * L1)
+    bad = bad1 | (q2[:, 0] <= 0).flatten(1).any(dim=1)
+    if bool(bad.any()):
+        qp = plain_step(q, dt, dx, dy, g, flux)
+        q2 = torch.where(bad[:, None, None, None], qp, q2)
+    nfb = f0 + torch.where(bad1, torch.zeros_like(f1), f1)
+    return q2, {"fallback_faces": int(nfb.sum()), "redone": bad}
+
+
 def rollout_loss(params, q0, targets, dt, dx, dy, scale, g=9.81, flux="hlle", round_bf16=True):
     """eq 2.28: sum over t = 1..T of the MSE between the learned rollout and
     the reference targets (B, T, 3, H, W); variable v is divided by scale[v]."""

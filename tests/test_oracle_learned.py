@@ -201,3 +201,100 @@ def test_autograd_matches_central_differences(L):
             assert abs(fd - an) <= 1e-6 * abs(fd) + 1e-10, (fd, an)
             checked += 1
     assert checked == 3 * len(leaves + [qv])
+
+
+# ---- direct face states (section 5.3) --------------------------------------
+
+def _params_head(L, seed, head_bias=None, scale_last=0.0):
+    p = L.init_params(seed, scale_last=scale_last)
+    if head_bias is not None:
+        p["b"][-1] = p["b"][-1].clone()
+        p["b"][-1][:len(head_bias)] = torch.tensor(head_bias, dtype=F64)
+    return p
+
+
+@pytest.mark.parametrize("flux,cflux", [("hlle", 0), ("rusanov", 1)])
+def test_direct_zero_head_is_first_order_classic(L, orc, flux, cflux):
+    """A zero head leaves every face state at its cell average: the direct
+    scheme is then the first-order scheme of the classic oracle (recon=FIRST),
+    operator and Heun step."""
+    q0, _ = I.swe_bathy(32, seed=5)
+    q0[1] = 0.05 * np.sin(2 * np.pi * np.arange(32) / 32)[None, :]
+    q0[2] = -0.04 * np.cos(2 * np.pi * np.arange(32) / 32)[:, None]
+    q = torch.tensor(q0)[None]
+    p = _params_head(L, 1)
+    Lq, nfb = L.direct_rhs(p, q, 1 / 32, 1 / 32, flux=flux)
+    ref = orc.rhs(orc.Config(nx=32, ny=32, recon=orc.FIRST, flux=cflux), q0)
+    assert int(nfb.sum()) == 0
+    assert np.abs(Lq[0].numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    qs, st = L.direct_step(p, q, 1e-3, 1 / 32, 1 / 32, flux=flux)
+    ref, *_ = orc.run(orc.Config(nx=32, ny=32, recon=orc.FIRST, flux=cflux, dt_fixed=1e-3), q0, None, 1)
+    assert np.abs(qs[0].numpy() - ref).max() <= 1e-13
+    assert not bool(st["redone"].any())
+
+
+def test_direct_face_pairing_reproduces_minmod(L, monkeypatch):
+    """With a head that outputs the MINMOD corrections (+s/2 on the right and
+    top sides, -s/2 on the left and bottom, in normalised units), cell i's
+    right state and cell i+1's left state are MINMOD's two states of face
+    i+1/2 on both axes: the direct operator equals the plain MINMOD one.  Pins
+    which cell's side meets which, and the de-normalisation."""
+    q0 = I.random_smooth_swe(24, seed=6)
+    q0[1] = 0.03 * np.sin(2 * np.pi * np.arange(24) / 24)[None, :]
+    q = torch.tensor(q0)[None]
+    p = _params_head(L, 2)
+    inv = p["inv_std"][None, :, None, None]
+
+    def slope(x, dim):
+        return L._minmod(x - L._shift(x, -1, dim), L._shift(x, 1, dim) - x)
+
+    def fake_cnn(params, x, round_bf16=True, shadow_f32=False):
+        sx, sy = slope(x, 3), slope(x, 2)
+        z = torch.zeros(x.shape[0], 72, x.shape[2], x.shape[3], dtype=F64)
+        z[:, 0:3] = -0.5 * sx * inv   # left
+        z[:, 3:6] = 0.5 * sx * inv    # right
+        z[:, 6:9] = -0.5 * sy * inv   # bottom
+        z[:, 9:12] = 0.5 * sy * inv   # top
+        return z
+
+    monkeypatch.setattr(L, "cnn", fake_cnn)
+    Lq, nfb = L.direct_rhs(p, q, 1 / 24, 1 / 24)
+    ref, _ = L.rhs(q, None, 1 / 24, 1 / 24)
+    assert int(nfb.sum()) == 0
+    assert torch.abs(Lq - ref).max() <= 1e-12 * torch.abs(ref).max()
+
+
+def test_direct_step_conserves_and_keeps_uniform_states(L):
+    """Any head: the periodic direct step conserves mass and momentum (each
+    face's flux is shared by its two cells), and a uniform state stays
+    unchanged (the network's output is then uniform, every face flux equal)."""
+    q0 = I.random_smooth_swe(32, seed=7)
+    q0[1] = 0.05 * np.sin(2 * np.pi * np.arange(32) / 32)[None, :]
+    q = torch.tensor(q0)[None]
+    p = _params_head(L, 3, scale_last=0.3)
+    q1, st = L.direct_step(p, q, 1e-3, 1 / 32, 1 / 32)
+    assert not bool(st["redone"].any())
+    assert not torch.equal(q1, q)
+    for v in range(3):
+        a, b = float(q[0, v].sum()), float(q1[0, v].sum())
+        assert abs(a - b) <= 1e-12 * float(q[0, 0].abs().sum()), v
+    u = torch.zeros(1, 3, 16, 16, dtype=F64)
+    u[:, 0], u[:, 1], u[:, 2] = 1.2, 0.1, -0.05
+    Lu, _ = L.direct_rhs(p, u, 1 / 16, 1 / 16)
+    assert torch.equal(Lu, torch.zeros_like(Lu))
+
+
+def test_direct_all_faces_fall_back_gives_plain_scheme(L):
+    """A head that drives every face depth negative sends every side to its
+    MINMOD state: the operator equals the plain one exactly, 4 sides per cell
+    counted."""
+    q0 = I.random_smooth_swe(16, seed=8)
+    q = torch.tensor(q0)[None]
+    hb = [0.0] * 12
+    for f in range(4):
+        hb[3 * f] = -1e4
+    p = _params_head(L, 4, head_bias=hb)
+    Lq, nfb = L.direct_rhs(p, q, 1 / 16, 1 / 16)
+    ref, _ = L.rhs(q, None, 1 / 16, 1 / 16)
+    assert int(nfb.sum()) == 2 * 2 * 16 * 16
+    assert torch.equal(Lq, ref)
