@@ -232,6 +232,20 @@ fv_status fv_model_forward_tiled(const fv_model *m, const float *q, int B, int n
  * of the plain redo are reported by fv_time as FV_E_INADMISSIBLE. */
 fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats);
 
+/* Enqueue nsteps Heun steps of the direct face-state scheme (thesis section
+ * 5.3, planar shallow water): the network maps the cell averages to the
+ * states at the four faces of every cell, and each face's flux (HLLE or
+ * Rusanov) is taken between the states its two cells give it, so the scheme
+ * is conservative.  The model's output channels 3f + v (f = 0 left, 1 right,
+ * 2 bottom, 3 top; v = h, hu, hv) are corrections to the cell average in the
+ * input's normalised units, Q^f_v = q_v + z_{3f+v} / inv_std_v (a zero head
+ * is the first-order scheme); channels 12..71 are not used.  A face side
+ * whose depth is not positive takes its MINMOD state (counted as a fallback
+ * face); a step with a non-positive depth after either stage is redone with
+ * the plain scheme (counted).  Same solver requirements, statistics and
+ * error reporting as fv_learned_step, whose counters it shares. */
+fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *fv_last_error(void);
 

@@ -167,6 +167,8 @@ struct StageBatch {
     unsigned long long *redone;  // mode 3: per solve, +1 when the step was redone (or NULL)
     double *t;                   // mode 3: solve 0's time and step count advance (or NULL)
     long long *steps;
+    int direct;                  // mode 0: the direct face-state scheme (z raw, channels 0..11)
+    float sig[3];                // direct: 1 / inv_std of the network's input normalisation
 };
 // mode 0: learned stage with fallback (sets bad bits);
 // mode 1: plain MINMOD stage, only for solves with bad != 0;

@@ -681,4 +681,76 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
     return FV_OK;
 }
 
+// Direct face-state scheme (thesis section 5.3): per stage the
+// layer-by-layer network pass (raw output in z) and the direct stage; then
+// the learned step's commit-or-redo and redo launches.
+fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats)
+{
+    if (!s || !m) return fail(FV_E_INVALID, "NULL argument");
+    const fv_config &c = s->cfg;
+    if (c.eqn != FV_SWE || c.prec != FV_F32 || c.bc_x != FV_BC_PERIODIC || c.bc_y != FV_BC_PERIODIC || s->bed ||
+        c.rk_stages != 2 || !(c.dt_fixed > 0) || !c.learned || c.nx % 16 || ((int64_t)c.nx * c.ny) % 64 ||
+        (c.flux != FV_FLUX_HLLE && c.flux != FV_FLUX_RUSANOV))
+        return fail(FV_E_UNSUPPORTED,
+                    "direct steps need SWE, FP32, periodic, flat bed, Heun, dt_fixed > 0, learned = 1, "
+                    "HLLE or Rusanov, nx %% 16 == 0 and nx*ny %% 64 == 0");
+    if (nsteps < 0) return fail(FV_E_INVALID, "nsteps < 0");
+    char *ws = s->ws;
+    const Layout &L = s->L;
+    float *q = (float *)s->q;
+    float *S1 = (float *)(ws + L.s1), *S2 = (float *)(ws + L.s2l), *z = (float *)(ws + L.z);
+    char *sm = ws + L.small;
+    void *acts[4] = {ws + L.act0, ws + L.act1, ws + L.act0, ws + L.act1};
+    cnn::StageBatch sb{};
+    sb.B = 1;
+    sb.nx = c.nx;
+    sb.ny = c.ny;
+    sb.rdx = (float)s->d.rdx;
+    sb.rdy = (float)s->d.rdy;
+    sb.g = (float)c.g;
+    sb.h0 = (float)s->d.h0;
+    sb.dt = (const float *)(sm + SM_DT);
+    sb.nfb = (unsigned long long *)(sm + SM_NFB);
+    sb.fatal = &s->ctl()->bad;
+    sb.pr = m->pr;
+    sb.z = z;
+    for (int v = 0; v < 3; v++) sb.sig[v] = 1.0f / m->nrm.inv_std[v];
+    int *flags = (int *)(sm + SM_BAD);  // two slots: this step's and the next step's
+    sb.redone = (unsigned long long *)(sm + SM_REDONE);
+    sb.t = &s->ctl()->t;
+    sb.steps = &s->ctl()->step;
+    const int fl = c.flux == FV_FLUX_RUSANOV ? 1 : 0;
+    hipError_t e = hipSuccess;
+    for (int64_t k = 0; k < nsteps && e == hipSuccess; k++, s->lsteps++) {
+        sb.bad = flags + (s->lsteps & 1);
+        sb.bad_next = flags + ((s->lsteps + 1) & 1);
+        sb.direct = 1;
+        // stage 1: face states of q, q1 = q + dt L(q)
+        e = cnn::launch_forward(m->packed, m->nrm, q, 1, c.nx, c.ny, acts, z, s->stream);
+        sb.qs = q; sb.q0 = q; sb.out = S1; sb.a0 = 0.f; sb.a1 = 1.f; sb.flagbit = 1;
+        if (e == hipSuccess) e = cnn::learned_stage(0, fl, sb, s->stream);
+        // stage 2: face states of q1, q2 = q/2 + (q1 + dt L(q1))/2
+        if (e == hipSuccess) e = cnn::launch_forward(m->packed, m->nrm, S1, 1, c.nx, c.ny, acts, z, s->stream);
+        sb.qs = S1; sb.q0 = q; sb.out = S2; sb.a0 = 0.5f; sb.a1 = 0.5f; sb.flagbit = 2;
+        if (e == hipSuccess) e = cnn::learned_stage(0, fl, sb, s->stream);
+        // admissible: q <- S2; otherwise redo the step with the plain scheme
+        sb.direct = 0;
+        sb.qs = q; sb.q0 = q; sb.out = S1; sb.a0 = 0.f; sb.a1 = 1.f;
+        sb.commit_src = S2; sb.commit_dst = q;
+        if (e == hipSuccess) e = cnn::learned_stage(2, fl, sb, s->stream);
+        sb.qs = S1; sb.q0 = q; sb.out = q; sb.a0 = 0.5f; sb.a1 = 0.5f;
+        if (e == hipSuccess) e = cnn::learned_stage(3, fl, sb, s->stream);
+    }
+    if (e != hipSuccess) return hip_fail(e, "direct step launch");
+    if (stats) {
+        e = hipStreamSynchronize(s->stream);
+        unsigned long long cnt[2];
+        if (e == hipSuccess) e = hipMemcpy(cnt, sm + SM_NFB, sizeof cnt, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "read learned counters");
+        stats->fallback_faces = (int64_t)cnt[0];
+        stats->redone_steps = (int64_t)cnt[1];
+    }
+    return FV_OK;
+}
+
 }  // extern "C"

@@ -67,6 +67,35 @@ __device__ __forceinline__ int face_states(const float (*st)[6], const float *zc
     return (ll ? 0 : 1) + (lr ? 0 : 1);
 }
 
+// Face states of one face in the direct scheme (thesis section 5.3): the
+// owner cell's high-side state and the neighbour's low-side state, each its
+// cell average plus the network's correction in normalised units,
+// Q = q + zc / inv_std (zo: the owner's three values for its right or top
+// side, zn: the neighbour's for its left or bottom side; sig = 1 / inv_std).
+// A side whose depth is not positive takes its MINMOD state (counted).
+__device__ __forceinline__ int face_states_direct(const float (*st)[6], const float *zo, const float *zn,
+                                                  const float *sig, float *QL, float *QR)
+{
+    float ML[3], MR[3];
+#pragma unroll
+    for (int v = 0; v < 3; v++) fvk::recon_pair<float, fvk::MINMOD>(st[v][1], st[v][2], st[v][3], st[v][4], ML[v], MR[v]);
+    bool okl = ML[0] > 0.0f, okr = MR[0] > 0.0f;
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        ML[v] = okl ? ML[v] : st[v][2];
+        MR[v] = okr ? MR[v] : st[v][3];
+        QL[v] = st[v][2] + sig[v] * zo[v];
+        QR[v] = st[v][3] + sig[v] * zn[v];
+    }
+    bool ll = QL[0] > 0.0f, lr = QR[0] > 0.0f;
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        QL[v] = ll ? QL[v] : ML[v];
+        QR[v] = lr ? QR[v] : MR[v];
+    }
+    return (ll ? 0 : 1) + (lr ? 0 : 1);
+}
+
 template <int FLUX, int AXIS>
 __device__ __forceinline__ void flux3(const float *QL, const float *QR, const Phys<float> &ph, float *F)
 {

@@ -44,6 +44,7 @@ struct LearnedArgs {
     unsigned long long *redone;
     double *t;
     long long *steps;
+    float sig[3];                // direct scheme: 1 / inv_std of the network's input normalisation
 };
 
 // One LTILE_X x LTILE_Y tile of solve b at (x0, y0); `first` marks the
@@ -52,7 +53,11 @@ struct LearnedArgs {
 // one cell: the coefficients of both faces are loaded before any face is
 // evaluated, so a stage costs about one global-load latency on the small
 // grids of the learned solver.
-template <int MODE, int FLUX, bool AL>
+// DIR (MODE 0 only): the direct face-state scheme of section 5.3, z holding
+// the network's raw output (channels 0..11: left, right, bottom, top states'
+// corrections); the MINMOD fallback, flags and counters are the learned
+// stage's.
+template <int MODE, int FLUX, bool AL, bool DIR = false>
 __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, const int x0, const int y0,
                                              const bool first)
 {
@@ -119,7 +124,25 @@ __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, 
     const int xj = tx_ / (TX + 1), xi = tx_ - xj * (TX + 1);
     const int yj = ty_ / TX, yi = ty_ - yj * TX;
     float zx[36], zy[36];
-    if (FS == 0) {
+    if (DIR) {
+        // x face: the owner's right state (channels 3..5) and the neighbour's
+        // left state (0..2); y face: the owner's top state (9..11) and the
+        // neighbour's bottom state (6..8)
+        const int gy = y0 + xj < ny ? y0 + xj : ny - 1;
+        const int gx = x0 + yi < nx ? x0 + yi : nx - 1;
+        const float *zb = a.z + (size_t)b * ny * nx * 72;
+        const float *ox = zb + ((size_t)gy * nx + pwrap(x0 - 1 + xi, nx)) * 72;
+        const float *nxp = zb + ((size_t)gy * nx + pwrap(x0 + xi, nx)) * 72;
+        const float *oy = zb + ((size_t)pwrap(y0 - 1 + yj, ny) * nx + gx) * 72;
+        const float *nyp = zb + ((size_t)pwrap(y0 + yj, ny) * nx + gx) * 72;
+#pragma unroll
+        for (int v = 0; v < 3; v++) {
+            zx[v] = ox[3 + v];
+            zx[3 + v] = nxp[v];
+            zy[v] = oy[9 + v];
+            zy[3 + v] = nyp[6 + v];
+        }
+    } else if (FS == 0) {
         const int gy = y0 + xj < ny ? y0 + xj : ny - 1;
         const int gx = x0 + yi < nx ? x0 + yi : nx - 1;
         const float4 *px = (const float4 *)(a.z + (((size_t)b * ny + gy) * nx + pwrap(x0 - 1 + xi, nx)) * 72);
@@ -138,7 +161,7 @@ __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, 
 #pragma unroll
             for (int k = 0; k < 6; k++) st[v][k] = s_q[v][xj + 3][xi + k];
         float QL[3], QR[3], F[3];
-        int c = face_states<FS, AL>(st, zx, a.pr, QL, QR);
+        int c = DIR ? face_states_direct(st, zx, zx + 3, a.sig, QL, QR) : face_states<FS, AL>(st, zx, a.pr, QL, QR);
         // each face is counted once: as the left face of a cell of this tile
         if (xi < TX && x0 + xi < nx && y0 + xj < ny) nfb += c;
         flux3<FLUX, 0>(QL, QR, a.ph, F);
@@ -152,7 +175,7 @@ __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, 
 #pragma unroll
             for (int k = 0; k < 6; k++) st[v][k] = s_q[v][yj + k][yi + 3];
         float QL[3], QR[3], F[3];
-        int c = face_states<FS, AL>(st, zy, a.pr, QL, QR);
+        int c = DIR ? face_states_direct(st, zy, zy + 3, a.sig, QL, QR) : face_states<FS, AL>(st, zy, a.pr, QL, QR);
         if (yj < TY && y0 + yj < ny && x0 + yi < nx) nfb += c;
         flux3<FLUX, 1>(QL, QR, a.ph, F);
 #pragma unroll
@@ -190,11 +213,11 @@ __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, 
     }
 }
 
-template <int MODE, int FLUX, bool AL = false>
+template <int MODE, int FLUX, bool AL = false, bool DIR = false>
 __global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
 {
-    learned_tile<MODE, FLUX, AL>(a, blockIdx.z, blockIdx.x * LTILE_X, blockIdx.y * LTILE_Y,
-                                 blockIdx.x == 0 && blockIdx.y == 0);
+    learned_tile<MODE, FLUX, AL, DIR>(a, blockIdx.z, blockIdx.x * LTILE_X, blockIdx.y * LTILE_Y,
+                                      blockIdx.x == 0 && blockIdx.y == 0);
 }
 
 // Work-list form over a table of solves of any size (serving, and single
@@ -345,12 +368,17 @@ hipError_t learned_stage(int mode, int flux, const StageBatch &sb, hipStream_t s
     a.redone = sb.redone;
     a.t = sb.t;
     a.steps = sb.steps;
+    for (int v = 0; v < 3; v++) a.sig[v] = sb.sig[v];
     if ((mode == 2 && (!a.commit_src || !a.commit_dst)) || (mode == 3 && !a.bad_next)) return hipErrorInvalidValue;
+    if (sb.direct && (mode != 0 || sb.alpha)) return hipErrorInvalidValue;
     dim3 grid((a.nx + LTILE_X - 1) / LTILE_X, (a.ny + LTILE_Y - 1) / LTILE_Y, a.B), blk(256);
     const bool rus = flux == fvk::RUSANOV;
     switch (mode) {
     case 0:
-        if (sb.alpha) {
+        if (sb.direct) {
+            if (rus) hipLaunchKernelGGL((learned_stage_kernel<0, fvk::RUSANOV, false, true>), grid, blk, 0, st, a);
+            else hipLaunchKernelGGL((learned_stage_kernel<0, fvk::HLLE, false, true>), grid, blk, 0, st, a);
+        } else if (sb.alpha) {
             if (rus) hipLaunchKernelGGL((learned_stage_kernel<0, fvk::RUSANOV, true>), grid, blk, 0, st, a);
             else hipLaunchKernelGGL((learned_stage_kernel<0, fvk::HLLE, true>), grid, blk, 0, st, a);
         } else {
