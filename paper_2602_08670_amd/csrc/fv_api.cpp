@@ -681,9 +681,9 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
     return FV_OK;
 }
 
-// Direct face-state scheme (thesis section 5.3): per stage the
-// layer-by-layer network pass (raw output in z) and the direct stage; then
-// the learned step's commit-or-redo and redo launches.
+// Direct face-state scheme (thesis section 5.3): per stage the network pass
+// (raw output in z) and the direct stage; then the learned step's
+// commit-or-redo and redo launches.
 fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats)
 {
     if (!s || !m) return fail(FV_E_INVALID, "NULL argument");
@@ -720,17 +720,24 @@ fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_lea
     sb.t = &s->ctl()->t;
     sb.steps = &s->ctl()->step;
     const int fl = c.flux == FV_FLUX_RUSANOV ? 1 : 0;
+    // the network's raw output: one launch per evaluation (the tiled pass,
+    // bit-identical) where the grid allows it, else one launch per layer
+    const bool tiled = c.ny % 8 == 0;
+    auto forward = [&](const float *in) {
+        return tiled ? cnn::launch_forward_fused(m->packed, m->nrm, in, 1, c.nx, c.ny, z, s->stream, nullptr)
+                     : cnn::launch_forward(m->packed, m->nrm, in, 1, c.nx, c.ny, acts, z, s->stream);
+    };
     hipError_t e = hipSuccess;
     for (int64_t k = 0; k < nsteps && e == hipSuccess; k++, s->lsteps++) {
         sb.bad = flags + (s->lsteps & 1);
         sb.bad_next = flags + ((s->lsteps + 1) & 1);
         sb.direct = 1;
         // stage 1: face states of q, q1 = q + dt L(q)
-        e = cnn::launch_forward(m->packed, m->nrm, q, 1, c.nx, c.ny, acts, z, s->stream);
+        e = forward(q);
         sb.qs = q; sb.q0 = q; sb.out = S1; sb.a0 = 0.f; sb.a1 = 1.f; sb.flagbit = 1;
         if (e == hipSuccess) e = cnn::learned_stage(0, fl, sb, s->stream);
         // stage 2: face states of q1, q2 = q/2 + (q1 + dt L(q1))/2
-        if (e == hipSuccess) e = cnn::launch_forward(m->packed, m->nrm, S1, 1, c.nx, c.ny, acts, z, s->stream);
+        if (e == hipSuccess) e = forward(S1);
         sb.qs = S1; sb.q0 = q; sb.out = S2; sb.a0 = 0.5f; sb.a1 = 0.5f; sb.flagbit = 2;
         if (e == hipSuccess) e = cnn::learned_stage(0, fl, sb, s->stream);
         // admissible: q <- S2; otherwise redo the step with the plain scheme

@@ -48,11 +48,11 @@ def params(L, seed, scale_last, head_bias=None):
 
 def run_direct(fv, L, p, q0, dt, nsteps, flux="hlle"):
     fl = fv.FV_FLUX_HLLE if flux == "hlle" else fv.FV_FLUX_RUSANOV
-    n = q0.shape[-1]
+    ny, n = q0.shape[-2:]
     vec = fv.params_to_vector([w.numpy() for w in p["w"]], [b.numpy() for b in p["b"]])
     m = fv.Model(vec, fv.make_model_desc(mean=tuple(p["mean"].tolist()), inv_std=tuple(p["inv_std"].tolist())))
     s = fv.Solver(q0.astype(np.float32), prec=fv.FV_F32, dt_fixed=dt, learned=1, flux=fl)
-    print(f"[gpu] direct step {flux} {n}x{n} x{nsteps}", flush=True)
+    print(f"[gpu] direct step {flux} {ny}x{n} x{nsteps}", flush=True)
     stats = s.direct_step(m, nsteps)
     t, k = s.time()
     out = s.state()
@@ -62,7 +62,7 @@ def run_direct(fv, L, p, q0, dt, nsteps, flux="hlle"):
     fb, red = 0, 0
     with torch.no_grad():
         for _ in range(nsteps):
-            qo, st = L.direct_step(p, qo, dt, 1.0 / n, 1.0 / n, flux=flux)
+            qo, st = L.direct_step(p, qo, dt, 1.0 / n, 1.0 / ny, flux=flux)
             fb += st["fallback_faces"]
             red += int(st["redone"].sum())
     return out, qo[0].numpy(), stats, (fb, red), (t, k)
@@ -81,6 +81,20 @@ def test_direct_step_parity(fv, L, flux):
     print(f"[direct 50 steps] {rel_errors(out, ref)} stats gpu {stats} oracle {ostats}", flush=True)
     assert state_rel(out, ref) <= 1e-3
     assert stats == (0, 0) and ostats == (0, 0)
+
+
+def test_direct_step_parity_layer_by_layer_pass(fv, L):
+    """64 x 20 (rows not a multiple of 8): the step's network pass runs
+    layer by layer instead of as one tiled launch; parity as above."""
+    p = params(L, 7, scale_last=0.05)
+    q0 = I.random_smooth_swe(64, seed=25)[:, :20].copy()
+    out, ref, stats, ostats, _ = run_direct(fv, L, p, q0, 4e-4, 1)
+    print(f"[direct 64x20 1 step] {rel_errors(out, ref)}", flush=True)
+    assert state_rel(out, ref) <= 1e-4
+    out, ref, stats, ostats, _ = run_direct(fv, L, p, q0, 4e-4, 20)
+    print(f"[direct 64x20 20 steps] {rel_errors(out, ref)} stats gpu {stats} oracle {ostats}", flush=True)
+    assert state_rel(out, ref) <= 1e-3
+    assert stats == ostats
 
 
 def test_direct_zero_head_is_first_order(fv, L):
