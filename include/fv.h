@@ -272,6 +272,9 @@ typedef struct {
     double h_ref;         /* reference depth of the pressure term, > 0 */
     float scale[3];       /* loss scale of h, hu, hv */
     float lr, beta1, beta2, eps; /* Adam */
+    int32_t direct;       /* 0: the learned stencil-coefficient scheme (fv_learned_step); 1: the
+                             direct face-state scheme (fv_direct_step, section 5.3) */
+    int32_t reserved0;    /* must be 0 */
 } fv_train_config;
 
 typedef struct fv_trainer fv_trainer;

@@ -37,6 +37,7 @@ struct AdjArgs {
     const int *plain;   // per solve: 1 = this step ran the plain scheme (or NULL)
     float *contrib;     // [2][B][ny][nx][ADJ_REC] (18 used)
     __bf16 *dz;         // [B][ny][nx][DZ_CH]
+    float sig[3];       // direct scheme: 1 / inv_std of the network's input normalisation
 };
 
 __device__ __forceinline__ int pw(int i, int n) { return ((i % n) + n) % n; }
@@ -69,7 +70,13 @@ __device__ __forceinline__ void minmod_right(const float *c, float &val, float *
     if (pb) { dv[4] -= 0.5f; dv[3] += 0.5f; }
 }
 
-template <int FLUX>
+// DIR: the direct face-state scheme (section 5.3): the face's left state is
+// the owner's right (top) state q_i + sig z_i[hi] and its right state the
+// neighbour's left (bottom) state q_{i+1} + sig z_{i+1}[lo], so a learned
+// side passes g_Q to its own cell and g_Q sig to its own cell's channels of
+// z; this face writes the owner's high-side and the neighbour's low-side
+// channels of dz (each written by exactly one face).
+template <int FLUX, bool DIR>
 __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
 {
     const int nx = a.nx, ny = a.ny;
@@ -119,7 +126,24 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
         float al[2][3][6];
         float QS[2][3];
         bool useL[2] = {false, false};
-        if (learned) {
+        // the cell across the face (the owner's +x or +y neighbour)
+        const int nbc = axis == 0 ? y * nx + pw(x + 1, nx) : pw(y + 1, ny) * nx + x;
+        if (DIR && learned) {
+            const float *zo = a.z + ((size_t)b * plane + cell) * 72 + (axis == 0 ? 3 : 9);
+            const float *zn = a.z + ((size_t)b * plane + nbc) * 72 + (axis == 0 ? 0 : 6);
+#pragma unroll
+            for (int v = 0; v < 3; v++) {
+                QS[0][v] = st[v][2] + a.sig[v] * zo[v];
+                QS[1][v] = st[v][3] + a.sig[v] * zn[v];
+#pragma unroll
+                for (int k = 0; k < 6; k++) {
+                    al[0][v][k] = k == 2 ? 1.f : 0.f;
+                    al[1][v][k] = k == 3 ? 1.f : 0.f;
+                }
+            }
+            useL[0] = QS[0][0] > 0.f;
+            useL[1] = QS[1][0] > 0.f;
+        } else if (learned) {
             // this face's 36 raw coefficients: nine 16-byte loads
             float zc[36];
             const float4 *z4 = (const float4 *)(a.z + ((size_t)b * plane + cell) * 72 + axis * 36);
@@ -172,7 +196,7 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
 
         // adjoint of the face flux
         const float rd = axis == 0 ? a.rdx : a.rdy;
-        const int nb = axis == 0 ? y * nx + pw(x + 1, nx) : pw(y + 1, ny) * nx + x;
+        const int nb = nbc;
         const float *go = a.gout + (size_t)b * 3 * plane;
         float gF[3];
 #pragma unroll
@@ -206,7 +230,7 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
 #pragma unroll
                 for (int j = 0; j < 6; j++) {
                     float t = 0.f;
-                    if (useL[s]) {
+                    if (!DIR && useL[s]) {
 #pragma unroll
                         for (int k = 0; k < 6; k++) t += a.pr.P[k * 6 + j] * (gQ[s][v] * st[v][k]);
                     }
@@ -220,14 +244,24 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
 #pragma unroll
         for (int q4 = 0; q4 < ADJ_REC / 4; q4++)
             co4[q4] = make_float4(co[4 * q4], co[4 * q4 + 1], co[4 * q4 + 2], co[4 * q4 + 3]);
-        typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-        bf16x4 *dz4 = (bf16x4 *)(a.dz + ((size_t)b * plane + cell) * DZ_CH + axis * 36);
+        if (DIR) {
+            __bf16 *dzo = a.dz + ((size_t)b * plane + cell) * DZ_CH + (axis == 0 ? 3 : 9);
+            __bf16 *dzn = a.dz + ((size_t)b * plane + nbc) * DZ_CH + (axis == 0 ? 0 : 6);
 #pragma unroll
-        for (int q4 = 0; q4 < 9; q4++) {
-            bf16x4 o;
+            for (int v = 0; v < 3; v++) {
+                dzo[v] = (__bf16)(useL[0] ? gQ[0][v] * a.sig[v] : 0.f);
+                dzn[v] = (__bf16)(useL[1] ? gQ[1][v] * a.sig[v] : 0.f);
+            }
+        } else {
+            typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+            bf16x4 *dz4 = (bf16x4 *)(a.dz + ((size_t)b * plane + cell) * DZ_CH + axis * 36);
 #pragma unroll
-            for (int e = 0; e < 4; e++) o[e] = (__bf16)gzc[4 * q4 + e];
-            dz4[q4] = o;
+            for (int q4 = 0; q4 < 9; q4++) {
+                bf16x4 o;
+#pragma unroll
+                for (int e = 0; e < 4; e++) o[e] = (__bf16)gzc[4 * q4 + e];
+                dz4[q4] = o;
+            }
         }
     }
 }
@@ -283,10 +317,16 @@ hipError_t launch_adjoint(int flux, const AdjStage &s, hipStream_t st)
     a.plain = s.plain;
     a.contrib = s.contrib;
     a.dz = (__bf16 *)s.dz;
+    for (int v = 0; v < 3; v++) a.sig[v] = s.sig[v];
     size_t nf = (size_t)2 * s.B * s.nx * s.ny;
     unsigned blocks = (unsigned)((nf + 255) / 256);
-    if (flux == 1) hipLaunchKernelGGL((adj_face_kernel<fvk::RUSANOV>), dim3(blocks), dim3(256), 0, st, a);
-    else hipLaunchKernelGGL((adj_face_kernel<fvk::HLLE>), dim3(blocks), dim3(256), 0, st, a);
+    if (s.direct) {
+        if (flux == 1) hipLaunchKernelGGL((adj_face_kernel<fvk::RUSANOV, true>), dim3(blocks), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((adj_face_kernel<fvk::HLLE, true>), dim3(blocks), dim3(256), 0, st, a);
+    } else {
+        if (flux == 1) hipLaunchKernelGGL((adj_face_kernel<fvk::RUSANOV, false>), dim3(blocks), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((adj_face_kernel<fvk::HLLE, false>), dim3(blocks), dim3(256), 0, st, a);
+    }
     size_t nc = (size_t)s.B * s.nx * s.ny;
     hipLaunchKernelGGL(adj_gather_kernel, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, s.gqs, s.gout, s.a1,
                        (const float *)s.contrib, s.B, s.nx, s.ny, s.accumulate);

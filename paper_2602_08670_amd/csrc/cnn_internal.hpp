@@ -207,6 +207,8 @@ struct AdjStage {
     void *dz;          // [B][ny][nx][DZ_CH] BF16: channels 0..71 written, the rest left as they are (zero)
     float *gqs;
     int accumulate;
+    int direct;        // the direct face-state scheme (dz channels 0..11 written, the rest left zero)
+    float sig[3];      // direct: 1 / inv_std of the network's input normalisation
 };
 hipError_t launch_adjoint(int flux, const AdjStage &s, hipStream_t st);
 // Floats per face in the adjoint's contribution scratch: 18 used, padded so

@@ -32,6 +32,8 @@ fv_status validate(const fv_train_config *c)
         if (!(c->scale[v] > 0)) return fail(FV_E_INVALID, "loss scale must be positive");
     if (!(c->lr > 0) || !(c->beta1 >= 0 && c->beta1 < 1) || !(c->beta2 >= 0 && c->beta2 < 1) || !(c->eps > 0))
         return fail(FV_E_INVALID, "Adam hyper-parameters");
+    if ((c->direct != 0 && c->direct != 1) || c->reserved0 != 0)
+        return fail(FV_E_INVALID, "direct must be 0 or 1, reserved0 0");
     return FV_OK;
 }
 
@@ -179,6 +181,7 @@ fv_status fv_train_step(fv_trainer *tr, const float *q0, const float *targets, i
     sb.nfb = (unsigned long long *)(ws + L.nfb);
     sb.fatal = (int *)(ws + L.fatal);
     sb.pr = tr->m->pr;
+    for (int v = 0; v < 3; v++) sb.sig[v] = 1.0f / tr->m->nrm.inv_std[v];
     float *S2 = (float *)(ws + L.s2);
 
     // ---------------------------------------------------------------- forward
@@ -187,7 +190,7 @@ fv_status fv_train_step(fv_trainer *tr, const float *q0, const float *targets, i
         void *a1[4] = {tr->act(t, 1, 0), tr->act(t, 1, 1), tr->act(t, 1, 2), tr->act(t, 1, 3)};
         e = cnn::launch_forward(tr->m->packed, tr->m->nrm, tr->st(t), B, nx, ny, a0, tr->zb(t, 0), st);
         sb.qs = tr->st(t); sb.q0 = tr->st(t); sb.out = tr->s1(t); sb.z = tr->zb(t, 0);
-        sb.a0 = 0.f; sb.a1 = 1.f; sb.flagbit = 1;
+        sb.a0 = 0.f; sb.a1 = 1.f; sb.flagbit = 1; sb.direct = c.direct;
         if (e == hipSuccess) e = cnn::learned_stage(0, fl, sb, st);
         if (e == hipSuccess) e = cnn::launch_forward(tr->m->packed, tr->m->nrm, tr->s1(t), B, nx, ny, a1, tr->zb(t, 1), st);
         sb.qs = tr->s1(t); sb.q0 = tr->st(t); sb.out = S2; sb.z = tr->zb(t, 1);
@@ -196,6 +199,7 @@ fv_status fv_train_step(fv_trainer *tr, const float *q0, const float *targets, i
         if (e == hipSuccess) e = cnn::launch_commit(tr->st(t + 1), S2, sb.bad, (size_t)3 * nx * ny, B, st);
         // solves whose learned step was inadmissible: plain step, which also
         // overwrites the saved stage input so the reverse pass sees it
+        sb.direct = 0;
         sb.qs = tr->st(t); sb.q0 = tr->st(t); sb.out = tr->s1(t); sb.a0 = 0.f; sb.a1 = 1.f;
         if (e == hipSuccess) e = cnn::learned_stage(1, fl, sb, st);
         sb.qs = tr->s1(t); sb.q0 = tr->st(t); sb.out = tr->st(t + 1); sb.a0 = 0.5f; sb.a1 = 0.5f;
@@ -211,6 +215,8 @@ fv_status fv_train_step(fv_trainer *tr, const float *q0, const float *targets, i
     if (e == hipSuccess) e = hipMemsetAsync(G, 0, nst * 4, st);
     if (e == hipSuccess) e = hipMemsetAsync(tr->grads, 0, (size_t)cnn::NPARAM * 4, st);
     cnn::AdjStage as;
+    as.direct = c.direct;
+    for (int v = 0; v < 3; v++) as.sig[v] = 1.0f / tr->m->nrm.inv_std[v];
     as.dt = (float)c.dt;
     as.B = B;
     as.nx = nx;

@@ -65,10 +65,14 @@ def batch(n, B, seed0, ny=None):
     return q.astype(np.float32)
 
 
-@pytest.mark.parametrize("flux,ny,nx", [("hlle", 32, 32), ("rusanov", 32, 32), ("hlle", 24, 48)])
-def test_gradients_match_oracle(fv, L, flux, ny, nx):
+@pytest.mark.parametrize("flux,ny,nx,direct", [("hlle", 32, 32, False), ("rusanov", 32, 32, False),
+                                               ("hlle", 24, 48, False), ("hlle", 32, 32, True),
+                                               ("rusanov", 32, 32, True)])
+def test_gradients_match_oracle(fv, L, flux, ny, nx, direct):
     """Square grids, and 24 x 48: rows past the last full 16-row tile of the
-    input-gradient convolutions."""
+    input-gradient convolutions; the learned scheme and the direct face-state
+    scheme (section 5.3: the adjoint passes each side's gradient to its own
+    cell and to its own cell's channels of the network output)."""
     B, T, dt = 2, 2, 1.2e-3 * 32 / nx
     p = params(L, 21)
     q0 = batch(nx, B, 40, ny)
@@ -80,10 +84,10 @@ def test_gradients_match_oracle(fv, L, flux, ny, nx):
             tg.append(qq.float().double())
         tg = torch.stack(tg, 1)  # [B, T, 3, ny, nx]
     scale = (0.05, 0.02, 0.02)
-    print(f"[gpu] train grad parity {flux} B={B} T={T} {ny}x{nx}", flush=True)
+    print(f"[gpu] train grad parity {flux} B={B} T={T} {ny}x{nx} direct={direct}", flush=True)
     m = fv.Model(vec(fv, p), fv.make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0)))
     cfg = fv.make_train_config(B, nx, ny, T, dt, flux=fv.FV_FLUX_HLLE if flux == "hlle" else fv.FV_FLUX_RUSANOV,
-                               scale=scale, h_ref=1.0)
+                               scale=scale, h_ref=1.0, direct=direct)
     tr = fv.Trainer(m, cfg)
     tgt = torch.tensor(tg.permute(1, 0, 2, 3, 4).numpy().astype(np.float32), device="cuda")
     loss, stats = tr.step(torch.tensor(q0, device="cuda"), tgt)
@@ -95,7 +99,7 @@ def test_gradients_match_oracle(fv, L, flux, ny, nx):
     for t in p["w"] + p["b"]:
         t.requires_grad_(True)
     qv = torch.tensor(q0.astype(np.float64), requires_grad=True)
-    lo = L.rollout_loss(p, qv, tg, dt, 1 / nx, 1 / ny, scale, flux=flux)
+    lo = L.rollout_loss(p, qv, tg, dt, 1 / nx, 1 / ny, scale, flux=flux, direct=direct)
     gw = torch.autograd.grad(lo, p["w"] + p["b"] + [qv])
     g_or = grad_vec(gw[:5], gw[5:10])
     gq_or = gw[10].numpy()
@@ -166,8 +170,10 @@ def test_gradients_batch_equals_mean_of_solves(fv, L):
         off += k
 
 
-def test_adam_reduces_loss(fv, L):
-    """A few Adam steps on one batch lower the unrolled loss."""
+@pytest.mark.parametrize("direct", [False, True])
+def test_adam_reduces_loss(fv, L, direct):
+    """A few Adam steps on one batch lower the unrolled loss (learned and
+    direct face-state schemes)."""
     n, B, T, dt = 32, 4, 3, 1.0e-3
     p = params(L, 23, scale_last=0.02)
     q0 = torch.tensor(batch(n, B, 60), device="cuda")
@@ -179,13 +185,13 @@ def test_adam_reduces_loss(fv, L):
             tg.append(qq.float())
     tgt = torch.stack(tg).cuda()
     m = fv.Model(vec(fv, p))
-    tr = fv.Trainer(m, fv.make_train_config(B, n, n, T, dt, lr=3e-4))
+    tr = fv.Trainer(m, fv.make_train_config(B, n, n, T, dt, lr=3e-4, direct=direct))
     losses = []
     for _ in range(30):
         loss, _ = tr.step(q0, tgt)
         losses.append(loss)
         tr.adam()
-    print(f"[adam] loss {losses[0]:.4e} -> {losses[-1]:.4e}", flush=True)
+    print(f"[adam] direct={direct} loss {losses[0]:.4e} -> {losses[-1]:.4e}", flush=True)
     assert losses[-1] < 0.5 * losses[0]
     tr.close()
     m.close()

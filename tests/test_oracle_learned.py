@@ -158,10 +158,12 @@ def test_rollout_loss_zero_on_own_rollout(L):
 
 
 @pytest.mark.slow
-def test_autograd_matches_central_differences(L):
+@pytest.mark.parametrize("direct", [False, True])
+def test_autograd_matches_central_differences(L, direct):
     """d loss / d theta and d loss / d q0 from automatic differentiation agree
     with central finite differences (h = 1e-6) on a small network and grid
-    (bfloat16 rounding off so the loss is smooth)."""
+    (bfloat16 rounding off so the loss is smooth), for the learned and the
+    direct face-state rollouts."""
     p = L.init_params(4, hidden=4, scale_last=0.2, layers=[(3, 4), (4, 4), (4, 72)])
     p["b"][0] = torch.full((4,), 0.3, dtype=F64)
     q0 = torch.tensor(I.random_smooth_swe(8, seed=7, humps=2))[None]
@@ -178,7 +180,7 @@ def test_autograd_matches_central_differences(L):
     for t in leaves:
         t.requires_grad_(True)
     qv = q0.clone().requires_grad_(True)
-    loss = L.rollout_loss(p, qv, tg, dt, 1 / 8, 1 / 8, [0.1, 0.05, 0.05], round_bf16=False)
+    loss = L.rollout_loss(p, qv, tg, dt, 1 / 8, 1 / 8, [0.1, 0.05, 0.05], round_bf16=False, direct=direct)
     grads = torch.autograd.grad(loss, leaves + [qv])
     g = torch.Generator().manual_seed(11)
     h = 1e-6
@@ -191,10 +193,10 @@ def test_autograd_matches_central_differences(L):
                 old = flat[k].item()
                 flat[k] = old + h
                 lp = L.rollout_loss(p, qv.detach() if t is not qv else qv, tg, dt, 1 / 8, 1 / 8, [0.1, 0.05, 0.05],
-                                    round_bf16=False)
+                                    round_bf16=False, direct=direct)
                 flat[k] = old - h
                 lm = L.rollout_loss(p, qv.detach() if t is not qv else qv, tg, dt, 1 / 8, 1 / 8, [0.1, 0.05, 0.05],
-                                    round_bf16=False)
+                                    round_bf16=False, direct=direct)
                 flat[k] = old
             fd = (lp - lm).item() / (2 * h)
             an = gr.view(-1)[k].item()
