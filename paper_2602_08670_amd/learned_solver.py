@@ -79,7 +79,7 @@ def init_params(seed: int) -> np.ndarray:
 
 def train(data, iters: int, B: int = 16, T_max: int = 8, lr: float = 1e-3, seed: int = 0, log_every: int = 0,
           model=None, dt_c: float | None = None, n_fine: int | None = None, factor: int | None = None,
-          lr_final: float | None = None):
+          lr_final: float | None = None, direct: bool = False):
     """Curriculum training on windows of the coarse trajectories data
     [n_traj, S+1, 3, n, n].  T grows 1 -> T_max over the first half; with
     lr_final the learning rate follows a cosine from lr to lr_final."""
@@ -91,7 +91,7 @@ def train(data, iters: int, B: int = 16, T_max: int = 8, lr: float = 1e-3, seed:
     mean, inv_std, std = normalisation(data)
     if model is None:
         model = fv.Model(init_params(seed), fv.make_model_desc(mean=mean, inv_std=inv_std))
-    cfg = fv.make_train_config(B, n, n, T_max, dt_c, h_ref=1.0, scale=tuple(std), lr=lr)
+    cfg = fv.make_train_config(B, n, n, T_max, dt_c, h_ref=1.0, scale=tuple(std), lr=lr, direct=direct)
     tr = fv.Trainer(model, cfg)
     rng = np.random.default_rng(seed + 1)
     hist = []
@@ -143,7 +143,8 @@ def graph_replay(launch, total: int, chunk: int, stream):
     return time.perf_counter() - t0
 
 
-def evaluate(model, seeds, n_fine, factor, n_coarse_steps, plain_sizes=(64, 128, 256, 512), chunk=50):
+def evaluate(model, seeds, n_fine, factor, n_coarse_steps, plain_sizes=(64, 128, 256, 512), chunk=50,
+             direct: bool = False):
     """Errors at the final time of the learned coarse solver and of the plain
     scheme at plain_sizes against the fine reference (block-averaged), and
     graph-replayed time-to-solution of each."""
@@ -161,10 +162,11 @@ def evaluate(model, seeds, n_fine, factor, n_coarse_steps, plain_sizes=(64, 128,
         q0c = fv.coarsen(q0f, factor).cpu().numpy()
         st = torch.cuda.Stream()
         sl = fv.Solver(q0c, prec=fv.FV_F32, dt_fixed=dt_c, learned=1, h_ref=1.0, stream=st)
-        times["learned"].append(graph_replay(lambda k: fv.fv_learned_step(sl.h, model.h, k, want_stats=False),
+        lstep = fv.fv_direct_step if direct else fv.fv_learned_step
+        times["learned"].append(graph_replay(lambda k: lstep(sl.h, model.h, k, want_stats=False),
                                              n_coarse_steps, chunk, st))
         out = sl.state()
-        fb["learned"].append(fv.fv_learned_step(sl.h, model.h, 0, want_stats=True))
+        fb["learned"].append(lstep(sl.h, model.h, 0, want_stats=True))
         errs["learned"].append(rel_l2(out[0], ref[0]))
         hs["learned"].append(mean_rel_h(out[0], ref[0]))
         sl.close()
@@ -204,6 +206,8 @@ def main():
     ap.add_argument("--eval-steps", type=int, default=1000)
     ap.add_argument("--plain-sizes", default="64,128,256,512",
                     help="grid sides of the plain-scheme comparison runs (multiples of the coarse side)")
+    ap.add_argument("--direct", action="store_true",
+                    help="the direct face-state scheme of section 5.3 instead of the stencil coefficients")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     plain_sizes = tuple(int(v) for v in a.plain_sizes.split(",") if v)
@@ -212,14 +216,16 @@ def main():
     tdata = time.perf_counter() - t0
     print(f"[data] {tuple(data.shape)} in {tdata:.1f} s", flush=True)
     model, hist, wall = train(data, a.iters, a.batch, a.T, a.lr, log_every=100, n_fine=a.n_fine, factor=a.factor,
-                              lr_final=a.lr_final if a.lr_final > 0 else None)
+                              lr_final=a.lr_final if a.lr_final > 0 else None, direct=a.direct)
     print(f"[train] {a.iters} iterations in {wall:.1f} s, loss {hist[0][2]:.3e} -> {hist[-1][2]:.3e}", flush=True)
-    res = evaluate(model, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps, plain_sizes=plain_sizes)
+    res = evaluate(model, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps, plain_sizes=plain_sizes,
+                   direct=a.direct)
     print(f"[eval] " + ", ".join(f"{k}: rel L2(h) {v['rel_l2_h']:.3e} in {v['time_to_solution_s'] * 1e3:.1f} ms"
                                  for k, v in res["cases"].items()), flush=True)
     untrained = fv.Model(init_params(0), model.desc)
     res["untrained"] = evaluate(untrained, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps,
-                                plain_sizes=())["cases"]["learned"]
+                                plain_sizes=(), direct=a.direct)["cases"]["learned"]
+    res["scheme"] = "direct face states" if a.direct else "stencil coefficients"
     res["train"] = {"iters": a.iters, "batch": a.batch, "T": a.T, "wall_s": wall, "data_s": tdata,
                     "loss_first": hist[0][2], "loss_last": hist[-1][2], "snapshots": int(data.shape[0] * data.shape[1])}
     print(json.dumps(res, indent=1), flush=True)
