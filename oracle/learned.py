@@ -200,10 +200,12 @@ def rusanov(hl, ml, tl, hr, mr, tr, g):
 FLUXES = {"hlle": hlle, "rusanov": rusanov}
 
 
-def rhs(q: torch.Tensor, alpha, dx: float, dy: float, g: float = 9.81, flux: str = "hlle"):
+def rhs(q: torch.Tensor, alpha, dx: float, dy: float, g: float = 9.81, flux: str = "hlle", blend: bool = False):
     """Spatial operator L(q) with learned face states (alpha given) or the
-    plain MINMOD states (alpha None).  Returns (L, per-solve number of face
-    sides that fell back to MINMOD)."""
+    plain MINMOD states (alpha None).  blend (learned only): each face's flux
+    is the flux-limiter blend of section 2.5.3 (second approach), see
+    blend_flux.  Returns (L, per-solve number of face sides that fell back to
+    MINMOD)."""
     fn = FLUXES[flux]
     L = torch.zeros_like(q)
     nfb = torch.zeros(q.shape[0], dtype=torch.int64)
@@ -222,8 +224,42 @@ def rhs(q: torch.Tensor, alpha, dx: float, dy: float, g: float = 9.81, flux: str
         Fc = [None, None, None]
         Fc[0], Fc[nm], Fc[tm] = F
         Fc = torch.stack(Fc, dim=1)  # flux through face i+1/2, Cartesian order
+        if blend and alpha is not None:
+            Fc = blend_flux(q, Fc, dim, nm, tm, fn, g)
         L = L - (Fc - _shift(Fc, -1, dim)) / d
     return L, nfb
+
+
+# ---- flux-limiter blend (section 2.5.3, second approach) ------------------
+# The flux of face i+1/2 is pulled from a high-resolution flux (here: the
+# learned face states' flux) towards the low-resolution one (the flux of the
+# two cell averages) by a flux limiter of the ratio of successive gradients at
+# cell i:  F = F_low - phi(r_i) (F_low - F_high),
+# r_i = (q_i - q_{i-1}) / (q_{i+1} - q_i).  Readings: the limiter is MINMOD
+# (the limiter the thesis uses throughout), phi(r) = max(0, min(1, r)); r is
+# taken per conserved variable (h, hu, hv) and always at the face's low-index
+# cell i, as printed, whatever the flow direction; where q_{i+1} = q_i the
+# ratio is undefined and phi = 0 (the low-resolution flux).
+
+def limiter_minmod(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
+    """phi(r) of the MINMOD flux limiter for r = a / b (a = q_i - q_{i-1},
+    b = q_{i+1} - q_i); 0 where b = 0."""
+    nz = b != 0
+    r = torch.where(nz, a / torch.where(nz, b, torch.ones_like(b)), torch.zeros_like(a))
+    return torch.clamp(r, 0.0, 1.0)
+
+
+def blend_flux(q, F_high, dim, nm, tm, fn, g):
+    """Blended flux of every face i+1/2 along dim (Cartesian order, like
+    F_high): the low-resolution flux is the numerical flux of the cell
+    averages q_i and q_{i+1}."""
+    qa, qb = q, _shift(q, 1, dim)
+    Fl = fn(qa[:, 0], qa[:, nm], qa[:, tm], qb[:, 0], qb[:, nm], qb[:, tm], g)
+    F_low = [None, None, None]
+    F_low[0], F_low[nm], F_low[tm] = Fl
+    F_low = torch.stack(F_low, dim=1)
+    phi = limiter_minmod(q - _shift(q, -1, dim), _shift(q, 1, dim) - q)
+    return F_low - phi * (F_low - F_high)
 
 
 def plain_step(q, dt, dx, dy, g=9.81, flux="hlle"):
@@ -234,22 +270,23 @@ def plain_step(q, dt, dx, dy, g=9.81, flux="hlle"):
     return 0.5 * q + 0.5 * (q1 + dt * L1)
 
 
-def learned_step(params, q, dt, dx, dy, g=9.81, flux="hlle", order=1, round_bf16=True):
-    """One Heun step of the learned scheme.  The network runs on the input of
+def learned_step(params, q, dt, dx, dy, g=9.81, flux="hlle", order=1, round_bf16=True, blend=False):
+    """One Heun step of the learned scheme (blend: with the flux-limiter blend
+    of its face fluxes, see blend_flux).  The network runs on the input of
     each stage.  Returns (q_next, stats) with stats = dict(fallback_faces,
     redone = per-solve flags of steps redone with the plain scheme).  Face
     sides of the second stage are not counted for a solve whose first stage
     was already inadmissible (its step is redone either way)."""
     P = projector(order)
     a0 = coefficients(cnn(params, q, round_bf16), P)
-    L0, f0 = rhs(q, a0, dx, dy, g, flux)
+    L0, f0 = rhs(q, a0, dx, dy, g, flux, blend)
     q1 = q + dt * L0
     bad1 = (q1[:, 0] <= 0).flatten(1).any(dim=1)
     # a solve whose first stage is already inadmissible is redone; evaluate the
     # second stage on a safe copy so nothing non-finite enters the graph
     q1s = torch.where(bad1[:, None, None, None], q, q1)
     a1 = coefficients(cnn(params, q1s, round_bf16), P)
-    L1, f1 = rhs(q1s, a1, dx, dy, g, flux)
+    L1, f1 = rhs(q1s, a1, dx, dy, g, flux, blend)
     q2 = 0.5 * q + 0.5 * (q1s + dt * L1)
     bad = bad1 | (q2[:, 0] <= 0).flatten(1).any(dim=1)
     if bool(bad.any()):

@@ -300,3 +300,111 @@ def test_direct_all_faces_fall_back_gives_plain_scheme(L):
     ref, _ = L.rhs(q, None, 1 / 16, 1 / 16)
     assert int(nfb.sum()) == 2 * 2 * 16 * 16
     assert torch.equal(Lq, ref)
+
+
+# ---- flux-limiter blend (section 2.5.3, second approach) --------------------
+
+def test_limiter_minmod_values(L):
+    """The MINMOD flux limiter phi(r) = max(0, min(1, r)) at textbook points:
+    0 for r <= 0, r on (0, 1), 1 from r = 1 on; and the undefined ratio
+    (q_{i+1} = q_i) takes the low-resolution flux."""
+    a = torch.tensor([2.0, 1.0, -1.0, 1.0, 0.0, -3.0, -1.0, 0.0, 3.0], dtype=F64)
+    b = torch.tensor([1.0, 2.0, 1.0, 0.0, 0.0, -2.0, -4.0, 5.0, -0.5], dtype=F64)
+    want = torch.tensor([1.0, 0.5, 0.0, 0.0, 0.0, 1.0, 0.25, 0.0, 0.0], dtype=F64)
+    assert torch.equal(L.limiter_minmod(a, b), want)
+
+
+def _x_profile(hx, hux, hv, n):
+    q = torch.zeros(1, 3, n, n, dtype=F64)
+    q[0, 0] = torch.as_tensor(hx, dtype=F64)[None, :]
+    q[0, 1] = torch.as_tensor(hux, dtype=F64)[None, :]
+    q[0, 2] = hv
+    return q
+
+
+def _alpha(L, p, q):
+    return L.coefficients(L.cnn(p, q), L.projector(1))
+
+
+@pytest.mark.parametrize("flux,cflux", [("hlle", 0), ("rusanov", 1)])
+def test_blend_at_extrema_is_first_order_classic(L, orc, flux, cflux):
+    """Every cell an extremum along x (alternating values) and no variation
+    along y: phi = 0 at every face, so the blended operator is the
+    first-order scheme of the classic oracle whatever the network, while the
+    unblended learned operator is not."""
+    n = 32
+    sgn = (-1.0) ** np.arange(n)
+    q = _x_profile(1.0 + 0.1 * sgn, 0.05 + 0.02 * sgn, 0.01, n)
+    p = _params_head(L, 5, scale_last=0.3)
+    a = _alpha(L, p, q)
+    Lb, _ = L.rhs(q, a, 1 / n, 1 / n, flux=flux, blend=True)
+    Lh, _ = L.rhs(q, a, 1 / n, 1 / n, flux=flux)
+    ref = orc.rhs(orc.Config(nx=n, ny=n, recon=orc.FIRST, flux=cflux), q[0].numpy())
+    assert np.abs(Lb[0].numpy() - ref).max() <= 1e-12 * np.abs(ref).max()
+    assert np.abs(Lh[0].numpy() - ref).max() > 1e-3 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("flux,cflux", [("hlle", 0), ("rusanov", 1)])
+def test_blend_half_limiter_on_geometric_differences(L, orc, flux, cflux):
+    """Successive differences doubling along x (q_{i+1} - q_i = 2^i / 4096 for
+    i = 0..11): r = 1/2 at cells 1..11, so both faces of cells 2..11 take
+    phi = 1/2 for h and hu and the blended operator there is the mean of the
+    first-order and the learned ones; hv is uniform (phi = 0: first order).
+    Pins the ratio's orientation (its inverse gives phi = 1)."""
+    n = 32
+    i = np.arange(n)
+    h = np.where(i <= 12, 1.0 + (2.0 ** np.minimum(i, 12) - 1) / 4096, 0.0)
+    h[13:] = h[12] - (h[12] - 1.0) * (i[13:] - 12) / 20
+    hu = (h - 1.0) / 8 + 1 / 64
+    q = _x_profile(h, hu, 1 / 32, n)
+    p = _params_head(L, 6, scale_last=0.3)
+    a = _alpha(L, p, q)
+    Lb, _ = L.rhs(q, a, 1 / n, 1 / n, flux=flux, blend=True)
+    Lh, _ = L.rhs(q, a, 1 / n, 1 / n, flux=flux)
+    Ll = torch.tensor(orc.rhs(orc.Config(nx=n, ny=n, recon=orc.FIRST, flux=cflux), q[0].numpy()))[None]
+    sc = float(Lh.abs().max())
+    cells = slice(2, 12)
+    assert torch.abs(Lb[:, :2, :, cells] - 0.5 * (Ll + Lh)[:, :2, :, cells]).max() <= 1e-12 * sc
+    assert torch.abs(Lb[:, 2, :, cells] - Ll[:, 2, :, cells]).max() <= 1e-12 * sc
+    assert torch.abs(Lh - Ll)[:, :2, :, cells].max() > 1e-4 * sc
+
+
+@pytest.mark.parametrize("flux,cflux", [("hlle", 0), ("rusanov", 1)])
+def test_blend_limiter_taken_at_the_low_index_cell(L, orc, flux, cflux):
+    """A flat state that turns into a linear ramp at cell 8 (q_8 = q_7, then
+    equal differences): cell 8's faces take phi(r_7) and phi(r_8), both 0,
+    so its blended operator is first order; cells 10..30 have r = 1 at both
+    faces and take the learned operator.  Taking face i+1/2's ratio at cell
+    i+1 instead would give cell 8 phi = 1 on its right face."""
+    n = 32
+    i = np.arange(n)
+    h = 1.0 + np.maximum(i - 8, 0) / 64
+    q = _x_profile(h, (h - 1.0) / 2 + 1 / 32, 1 / 64, n)
+    p = _params_head(L, 7, scale_last=0.3)
+    a = _alpha(L, p, q)
+    Lb, _ = L.rhs(q, a, 1 / n, 1 / n, flux=flux, blend=True)
+    Lh, _ = L.rhs(q, a, 1 / n, 1 / n, flux=flux)
+    Ll = torch.tensor(orc.rhs(orc.Config(nx=n, ny=n, recon=orc.FIRST, flux=cflux), q[0].numpy()))[None]
+    sc = float(Lh.abs().max())
+    assert torch.abs(Lb[..., 8] - Ll[..., 8]).max() <= 1e-12 * sc
+    assert torch.abs(Lh[..., 8] - Ll[..., 8]).max() > 1e-4 * sc
+    assert torch.abs(Lb[:, :2, :, 10:31] - Lh[:, :2, :, 10:31]).max() <= 1e-12 * sc
+
+
+def test_blend_step_conserves_and_keeps_uniform_states(L):
+    """The blended flux is still one flux per face: the periodic step
+    conserves mass and momentum; a uniform state stays unchanged."""
+    q0 = I.random_smooth_swe(32, seed=9)
+    q0[1] = 0.05 * np.sin(2 * np.pi * np.arange(32) / 32)[None, :]
+    q = torch.tensor(q0)[None]
+    p = _params_head(L, 8, scale_last=0.3)
+    q1, st = L.learned_step(p, q, 1e-3, 1 / 32, 1 / 32, blend=True)
+    q1u, _ = L.learned_step(p, q, 1e-3, 1 / 32, 1 / 32)
+    assert not bool(st["redone"].any())
+    assert torch.abs(q1 - q1u).max() > 1e-9
+    for v in range(3):
+        assert abs(float(q[0, v].sum()) - float(q1[0, v].sum())) <= 1e-12 * float(q[0, 0].abs().sum()), v
+    u = torch.zeros(1, 3, 16, 16, dtype=F64)
+    u[:, 0], u[:, 1], u[:, 2] = 1.2, 0.1, -0.05
+    Lu, _ = L.rhs(u, _alpha(L, p, u), 1 / 16, 1 / 16, blend=True)
+    assert torch.abs(Lu).max() <= 1e-13
