@@ -114,12 +114,13 @@ def serving_sample(n_req):
             "p50_s": round(poi["p50_s"], 4), "p99_s": round(poi["p99_s"], 4), "poisson_mcups": round(poi["mcups"], 1)}
 
 
-def learned_sample(steps, torch, direct=False):
+def learned_sample(steps, torch, direct=False, blend=False):
     """Latency of one learned (Heun) step on the 64^2 coarse grid of the
     learned-solver workload: periodic shallow water, fixed step = 32 x the
     2048^2 fine step, a network with seeded random weights (the step's cost
     does not depend on the weights).  HIP events on the solver's stream.
-    direct: the direct face-state scheme's step instead."""
+    direct: the direct face-state scheme's step instead; blend: the learned
+    step with the flux-limiter blend of its face fluxes."""
     from paper_2602_08670_amd import fv, inputs
     from paper_2602_08670_amd import learned_solver as LS
 
@@ -128,7 +129,7 @@ def learned_sample(steps, torch, direct=False):
     m = fv.Model(vec, fv.make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0)))
     q0 = inputs.random_smooth_swe(64, seed=5).astype(np.float32)
     s = fv.Solver(q0, prec=fv.FV_F32, dt_fixed=LS.fine_dt(2048) * 32, learned=1)
-    step = s.direct_step if direct else s.learned_step
+    step = s.direct_step if direct else s.blend_step if blend else s.learned_step
     step(m, 20, want_stats=False)
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -210,6 +211,7 @@ def main():
     if args.learned_steps > 0:
         extra["learned_64_step_us"] = learned_sample(args.learned_steps, torch)
         extra["direct_64_step_us"] = learned_sample(args.learned_steps, torch, direct=True)
+        extra["blend_64_step_us"] = learned_sample(args.learned_steps, torch, blend=True)
 
     if args.serving_requests > 0:
         extra["serving"] = serving_sample(args.serving_requests)

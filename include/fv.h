@@ -246,6 +246,18 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
  * error reporting as fv_learned_step, whose counters it shares. */
 fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats);
 
+/* Enqueue nsteps learned Heun steps (the coefficient network of
+ * fv_learned_step) with the flux-limiter blend of thesis section 2.5.3
+ * (second approach): the flux of face i+1/2 is
+ *   F = F_low - phi(r_i) (F_low - F_high),
+ * F_high the learned face states' flux (MINMOD fallback as fv_learned_step),
+ * F_low the flux of the two cell averages, phi the MINMOD flux limiter
+ * max(0, min(1, r)) of r_i = (q_i - q_{i-1}) / (q_{i+1} - q_i) per conserved
+ * variable at the face's low-index cell i (phi = 0 where q_{i+1} = q_i).
+ * Same solver requirements, statistics and error reporting as
+ * fv_learned_step, whose counters it shares. */
+fv_status fv_blend_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *fv_last_error(void);
 

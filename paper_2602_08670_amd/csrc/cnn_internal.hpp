@@ -169,6 +169,7 @@ struct StageBatch {
     long long *steps;
     int direct;                  // mode 0: the direct face-state scheme (z raw, channels 0..11)
     float sig[3];                // direct: 1 / inv_std of the network's input normalisation
+    int blend;                   // mode 0: flux-limiter blend of the learned fluxes (z raw)
 };
 // mode 0: learned stage with fallback (sets bad bits);
 // mode 1: plain MINMOD stage, only for solves with bad != 0;

@@ -684,7 +684,12 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
 // Direct face-state scheme (thesis section 5.3): per stage the network pass
 // (raw output in z) and the direct stage; then the learned step's
 // commit-or-redo and redo launches.
-fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats)
+// Heun steps of a scheme whose stages take the network's raw output (one
+// network pass per stage, then the stage kernel): the direct face-state
+// scheme (direct) or the learned scheme with the flux-limiter blend (blend).
+// The end of a step (commit or plain redo) is the learned step's.
+static fv_status raw_head_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats, int direct,
+                               int blend)
 {
     if (!s || !m) return fail(FV_E_INVALID, "NULL argument");
     const fv_config &c = s->cfg;
@@ -692,8 +697,8 @@ fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_lea
         c.rk_stages != 2 || !(c.dt_fixed > 0) || !c.learned || c.nx % 16 || ((int64_t)c.nx * c.ny) % 64 ||
         (c.flux != FV_FLUX_HLLE && c.flux != FV_FLUX_RUSANOV))
         return fail(FV_E_UNSUPPORTED,
-                    "direct steps need SWE, FP32, periodic, flat bed, Heun, dt_fixed > 0, learned = 1, "
-                    "HLLE or Rusanov, nx %% 16 == 0 and nx*ny %% 64 == 0");
+                    "%s steps need SWE, FP32, periodic, flat bed, Heun, dt_fixed > 0, learned = 1, "
+                    "HLLE or Rusanov, nx %% 16 == 0 and nx*ny %% 64 == 0", direct ? "direct" : "blend");
     if (nsteps < 0) return fail(FV_E_INVALID, "nsteps < 0");
     char *ws = s->ws;
     const Layout &L = s->L;
@@ -731,7 +736,8 @@ fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_lea
     for (int64_t k = 0; k < nsteps && e == hipSuccess; k++, s->lsteps++) {
         sb.bad = flags + (s->lsteps & 1);
         sb.bad_next = flags + ((s->lsteps + 1) & 1);
-        sb.direct = 1;
+        sb.direct = direct;
+        sb.blend = blend;
         // stage 1: face states of q, q1 = q + dt L(q)
         e = forward(q);
         sb.qs = q; sb.q0 = q; sb.out = S1; sb.a0 = 0.f; sb.a1 = 1.f; sb.flagbit = 1;
@@ -742,13 +748,14 @@ fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_lea
         if (e == hipSuccess) e = cnn::learned_stage(0, fl, sb, s->stream);
         // admissible: q <- S2; otherwise redo the step with the plain scheme
         sb.direct = 0;
+        sb.blend = 0;
         sb.qs = q; sb.q0 = q; sb.out = S1; sb.a0 = 0.f; sb.a1 = 1.f;
         sb.commit_src = S2; sb.commit_dst = q;
         if (e == hipSuccess) e = cnn::learned_stage(2, fl, sb, s->stream);
         sb.qs = S1; sb.q0 = q; sb.out = q; sb.a0 = 0.5f; sb.a1 = 0.5f;
         if (e == hipSuccess) e = cnn::learned_stage(3, fl, sb, s->stream);
     }
-    if (e != hipSuccess) return hip_fail(e, "direct step launch");
+    if (e != hipSuccess) return hip_fail(e, direct ? "direct step launch" : "blend step launch");
     if (stats) {
         e = hipStreamSynchronize(s->stream);
         unsigned long long cnt[2];
@@ -758,6 +765,16 @@ fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_lea
         stats->redone_steps = (int64_t)cnt[1];
     }
     return FV_OK;
+}
+
+fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats)
+{
+    return raw_head_step(s, m, nsteps, stats, 1, 0);
+}
+
+fv_status fv_blend_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats)
+{
+    return raw_head_step(s, m, nsteps, stats, 0, 1);
 }
 
 }  // extern "C"

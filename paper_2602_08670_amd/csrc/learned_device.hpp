@@ -109,4 +109,29 @@ __device__ __forceinline__ void flux3(const float *QL, const float *QR, const Ph
     F[TM] = G[2];
 }
 
+// Flux-limiter blend (thesis section 2.5.3, second approach): the face flux F
+// of the learned states is pulled towards the flux of the two cell averages,
+// F <- F_low - phi (F_low - F), with phi the MINMOD flux limiter of the ratio
+// r = (q_i - q_{i-1}) / (q_{i+1} - q_i) of the face's low-index cell i
+// (stencil index 2), per conserved variable; phi = 0 where the ratio is
+// undefined.  The limiter is taken without forming r where it is 0 or 1.
+template <int FLUX, int AXIS>
+__device__ __forceinline__ void blend_flux(const float (*st)[6], const Phys<float> &ph, float *F)
+{
+    float lo[3], hi[3], Fl[3];
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        lo[v] = st[v][2];
+        hi[v] = st[v][3];
+    }
+    flux3<FLUX, AXIS>(lo, hi, ph, Fl);
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        const float a = st[v][2] - st[v][1], b = st[v][3] - st[v][2];
+        float phi = 0.0f;
+        if ((a > 0.0f && b > 0.0f) || (a < 0.0f && b < 0.0f)) phi = __builtin_fabsf(a) >= __builtin_fabsf(b) ? 1.0f : a / b;
+        F[v] = Fl[v] - phi * (Fl[v] - F[v]);
+    }
+}
+
 }  // namespace cnn

@@ -57,7 +57,9 @@ struct LearnedArgs {
 // the network's raw output (channels 0..11: left, right, bottom, top states'
 // corrections); the MINMOD fallback, flags and counters are the learned
 // stage's.
-template <int MODE, int FLUX, bool AL, bool DIR = false>
+// BL (MODE 0 only): every face's flux is the flux-limiter blend of the
+// learned flux and the flux of the two cell averages (blend_flux).
+template <int MODE, int FLUX, bool AL, bool DIR = false, bool BL = false>
 __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, const int x0, const int y0,
                                              const bool first)
 {
@@ -165,6 +167,7 @@ __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, 
         // each face is counted once: as the left face of a cell of this tile
         if (xi < TX && x0 + xi < nx && y0 + xj < ny) nfb += c;
         flux3<FLUX, 0>(QL, QR, a.ph, F);
+        if (BL) blend_flux<FLUX, 0>(st, a.ph, F);
 #pragma unroll
         for (int v = 0; v < 3; v++) s_fx[v][xj][xi] = F[v];
     }
@@ -178,6 +181,7 @@ __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, 
         int c = DIR ? face_states_direct(st, zy, zy + 3, a.sig, QL, QR) : face_states<FS, AL>(st, zy, a.pr, QL, QR);
         if (yj < TY && y0 + yj < ny && x0 + yi < nx) nfb += c;
         flux3<FLUX, 1>(QL, QR, a.ph, F);
+        if (BL) blend_flux<FLUX, 1>(st, a.ph, F);
 #pragma unroll
         for (int v = 0; v < 3; v++) s_fy[v][yj][yi] = F[v];
     }
@@ -213,10 +217,10 @@ __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, 
     }
 }
 
-template <int MODE, int FLUX, bool AL = false, bool DIR = false>
+template <int MODE, int FLUX, bool AL = false, bool DIR = false, bool BL = false>
 __global__ __launch_bounds__(256) void learned_stage_kernel(LearnedArgs a)
 {
-    learned_tile<MODE, FLUX, AL, DIR>(a, blockIdx.z, blockIdx.x * LTILE_X, blockIdx.y * LTILE_Y,
+    learned_tile<MODE, FLUX, AL, DIR, BL>(a, blockIdx.z, blockIdx.x * LTILE_X, blockIdx.y * LTILE_Y,
                                       blockIdx.x == 0 && blockIdx.y == 0);
 }
 
@@ -370,7 +374,8 @@ hipError_t learned_stage(int mode, int flux, const StageBatch &sb, hipStream_t s
     a.steps = sb.steps;
     for (int v = 0; v < 3; v++) a.sig[v] = sb.sig[v];
     if ((mode == 2 && (!a.commit_src || !a.commit_dst)) || (mode == 3 && !a.bad_next)) return hipErrorInvalidValue;
-    if (sb.direct && (mode != 0 || sb.alpha)) return hipErrorInvalidValue;
+    if ((sb.direct || sb.blend) && (mode != 0 || sb.alpha)) return hipErrorInvalidValue;
+    if (sb.direct && sb.blend) return hipErrorInvalidValue;
     dim3 grid((a.nx + LTILE_X - 1) / LTILE_X, (a.ny + LTILE_Y - 1) / LTILE_Y, a.B), blk(256);
     const bool rus = flux == fvk::RUSANOV;
     switch (mode) {
@@ -378,6 +383,9 @@ hipError_t learned_stage(int mode, int flux, const StageBatch &sb, hipStream_t s
         if (sb.direct) {
             if (rus) hipLaunchKernelGGL((learned_stage_kernel<0, fvk::RUSANOV, false, true>), grid, blk, 0, st, a);
             else hipLaunchKernelGGL((learned_stage_kernel<0, fvk::HLLE, false, true>), grid, blk, 0, st, a);
+        } else if (sb.blend) {
+            if (rus) hipLaunchKernelGGL((learned_stage_kernel<0, fvk::RUSANOV, false, false, true>), grid, blk, 0, st, a);
+            else hipLaunchKernelGGL((learned_stage_kernel<0, fvk::HLLE, false, false, true>), grid, blk, 0, st, a);
         } else if (sb.alpha) {
             if (rus) hipLaunchKernelGGL((learned_stage_kernel<0, fvk::RUSANOV, true>), grid, blk, 0, st, a);
             else hipLaunchKernelGGL((learned_stage_kernel<0, fvk::HLLE, true>), grid, blk, 0, st, a);

@@ -139,6 +139,7 @@ def _load():
         "fv_model_forward_tiled": ([vp, vp, ctypes.c_int, ctypes.c_int, ctypes.c_int, vp], st),
         "fv_learned_step": ([vp, vp, i64, ctypes.POINTER(fv_learned_stats)], st),
         "fv_direct_step": ([vp, vp, i64, ctypes.POINTER(fv_learned_stats)], st),
+        "fv_blend_step": ([vp, vp, i64, ctypes.POINTER(fv_learned_stats)], st),
         "fv_train_workspace_bytes": ([ctypes.POINTER(fv_train_config)], ctypes.c_size_t),
         "fv_train_create": ([ctypes.POINTER(fv_train_config), vp, vp, vp, vp, vp, ctypes.c_size_t,
                              ctypes.POINTER(vp)], st),
@@ -294,6 +295,12 @@ def fv_learned_step(h, m, nsteps: int, want_stats: bool = True):
 def fv_direct_step(h, m, nsteps: int, want_stats: bool = True):
     st = fv_learned_stats()
     _check(lib.fv_direct_step(h, m, int(nsteps), ctypes.byref(st) if want_stats else None))
+    return (st.fallback_faces, st.redone_steps) if want_stats else None
+
+
+def fv_blend_step(h, m, nsteps: int, want_stats: bool = True):
+    st = fv_learned_stats()
+    _check(lib.fv_blend_step(h, m, int(nsteps), ctypes.byref(st) if want_stats else None))
     return (st.fallback_faces, st.redone_steps) if want_stats else None
 
 
@@ -639,6 +646,10 @@ class Solver:
     def direct_step(self, model: "Model", nsteps: int, want_stats: bool = True):
         """Steps of the direct face-state scheme (the model's channels 0..11)."""
         return fv_direct_step(self.h, model.h, nsteps, want_stats)
+
+    def blend_step(self, model: "Model", nsteps: int, want_stats: bool = True):
+        """Learned steps with the flux-limiter blend of the face fluxes."""
+        return fv_blend_step(self.h, model.h, nsteps, want_stats)
 
     def face_fluxes(self):
         import torch
