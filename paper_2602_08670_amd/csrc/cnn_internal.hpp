@@ -129,9 +129,10 @@ int fused_max_grid();
 // S1 and q; the same results as the network pass followed by learned_stage
 // MODE 0.  The list form is the one recorded in graphs (wgs set before each
 // replay to at most fused_max_grid(), the network tile count read from the
-// list header).
+// list header).  blend: the flux-limiter blend of the face fluxes (blend_flux).
 hipError_t launch_conv_learned(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve *tab,
-                               const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one = 0);
+                               const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one = 0,
+                               int blend = 0);
 hipError_t launch_conv_learned_list(int stage, const void *packed, const Norm &nrm, const Proj &pr,
                                     const LSolve *tab, const LItem *items, const int *list, int wgs, hipStream_t st);
 

@@ -928,7 +928,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
 // the learned-stage kernels; each face projects its owner's coefficients
 // (alpha = base + P z, the network pass's operation order).  STAGE 1: S1 = q + dt L(q); STAGE 2: S2 = q/2 +
 // (S1 + dt L(S1))/2.  Stage flags and fallback counts as there.
-template <int STAGE>
+template <int STAGE, bool BL = false>
 __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &it, const float *s_z, const float *qf,
                                                  const Proj &pr, const int x0, const int y0)
 {
@@ -970,6 +970,7 @@ __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &i
         const int c = face_states<0, false>(st, s_z + ((xj + 1) * FO + xi) * 72, pr, QL, QR);
         if (xi < TX) nfb += c;  // each face counted once: as the left face of a cell of this tile
         flux3<fvk::HLLE, 0>(QL, QR, ph, F);
+        if (BL) blend_flux<fvk::HLLE, 0>(st, ph, F);
 #pragma unroll
         for (int v = 0; v < 3; v++) s_fx[v][xj][xi] = F[v];
     }
@@ -985,6 +986,7 @@ __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &i
         const int c = face_states<0, false>(st, s_z + (yj * FO + yi + 1) * 72 + 36, pr, QL, QR);
         if (yj < TY) nfb += c;
         flux3<fvk::HLLE, 1>(QL, QR, ph, F);
+        if (BL) blend_flux<fvk::HLLE, 1>(st, ph, F);
 #pragma unroll
         for (int v = 0; v < 3; v++) s_fy[v][yj][yi] = F[v];
     }
@@ -1020,8 +1022,9 @@ __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &i
 // workgroups stride over the lists' network tiles (FT x FT); each computes
 // z on its tile and low halo and runs the learned stage on the tile, so the
 // coefficients never leave LDS.  ntiles == 0: the tile count is read from the list
-// header (nitems[1]; graph replay).
-template <int STAGE>
+// header (nitems[1]; graph replay).  BL: the flux-limiter blend of the face
+// fluxes (blend_flux).
+template <int STAGE, bool BL = false>
 __global__ __launch_bounds__(FNW * 64) void conv_learned_batch_kernel(const LSolve *__restrict__ tab,
                                                                       const LItem *__restrict__ items,
                                                                       const int *__restrict__ nitems, int ntiles,
@@ -1052,7 +1055,7 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_batch_kernel(const LSol
         const int ty = tile / tx_n, tx = tile - ty * tx_n;
         const float *s_z = fused_tile<FT + 1, OUT_Z_LDS>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx,
                                                              ty * FT, tx * FT, pr, first, s_qf);
-        learned_epilogue<STAGE>(d, it, s_z, s_qf, pr, tx * FT, ty * FT);
+        learned_epilogue<STAGE, BL>(d, it, s_z, s_qf, pr, tx * FT, ty * FT);
     }
 }
 
@@ -1116,11 +1119,20 @@ hipError_t launch_forward_batch_list(int stage, const void *packed, const Norm &
 }
 
 hipError_t launch_conv_learned(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve *tab,
-                               const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one)
+                               const LItem *items, const int *nitems, int ntiles, hipStream_t st, int one, int blend)
 {
     if (ntiles <= 0) return hipSuccess;
     const Packed pk = packed_layout();
     const int cap = fused_max_grid(), g = ntiles < cap ? ntiles : cap;
+    if (blend) {
+        if (stage == 1)
+            hipLaunchKernelGGL((conv_learned_batch_kernel<1, true>), dim3(g), dim3(FNW * 64), 0, st, tab, items, nitems,
+                               ntiles, one, (const char *)packed, pk, nrm, pr);
+        else
+            hipLaunchKernelGGL((conv_learned_batch_kernel<2, true>), dim3(g), dim3(FNW * 64), 0, st, tab, items, nitems,
+                               ntiles, one, (const char *)packed, pk, nrm, pr);
+        return hipGetLastError();
+    }
     if (stage == 1)
         hipLaunchKernelGGL(conv_learned_batch_kernel<1>, dim3(g), dim3(FNW * 64), 0, st, tab, items, nitems, ntiles,
                            one, (const char *)packed, pk, nrm, pr);

@@ -579,7 +579,10 @@ fv_status fv_model_forward_tiled(const fv_model *m, const float *q, int B, int n
     return e == hipSuccess ? FV_OK : hip_fail(e, "network launch");
 }
 
-fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats)
+// blend: the flux-limiter blend of the face fluxes; callers pass it only
+// where the work-list branch below runs (HLLE, nx % 8 == ny % 8 == 0, no split).
+static fv_status learned_step_impl(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats,
+                                   int blend)
 {
     if (!s || !m) return fail(FV_E_INVALID, "NULL argument");
     const fv_config &c = s->cfg;
@@ -625,11 +628,13 @@ fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_le
         const int *nit = (const int *)(B + LB_N);
         const int tc = cnn::ltiles_cnn(c.nx, c.ny), ts = cnn::ltiles_st(c.nx, c.ny);
         const bool split = tc >= 4 * cnn::fused_max_grid();
+        if (blend && split) return fail(FV_E_UNSUPPORTED, "blend: grid too large for the fused form");
         for (int64_t k = 0; k < nsteps && e == hipSuccess; k++, s->lsteps++) {
             const cnn::LItem *it = items0 + (s->lsteps & 1);
             for (int stage = 1; stage <= 2 && e == hipSuccess; stage++) {
                 if (!split) {
-                    e = cnn::launch_conv_learned(stage, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
+                    e = cnn::launch_conv_learned(stage, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1,
+                                                 blend);
                 } else {
                     e = cnn::launch_forward_batch(stage, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
                     if (e == hipSuccess) e = cnn::launch_learned_batch(0, stage, tab, it, nit, ts, m->pr, s->stream, 1);
@@ -772,8 +777,19 @@ fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_lea
     return raw_head_step(s, m, nsteps, stats, 1, 0);
 }
 
+fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats)
+{
+    return learned_step_impl(s, m, nsteps, stats, 0);
+}
+
 fv_status fv_blend_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats)
 {
+    // HLLE grids of whole 8 x 8 tiles below the split size: the network pass
+    // and the blended stage in one launch per stage (z stays in LDS); else
+    // the network's raw output through HBM and a separate blended stage
+    if (s && m && s->cfg.flux == FV_FLUX_HLLE && s->cfg.nx % 8 == 0 && s->cfg.ny % 8 == 0 &&
+        cnn::ltiles_cnn(s->cfg.nx, s->cfg.ny) < 4 * cnn::fused_max_grid())
+        return learned_step_impl(s, m, nsteps, stats, 1);
     return raw_head_step(s, m, nsteps, stats, 0, 1);
 }
 

@@ -144,7 +144,7 @@ def graph_replay(launch, total: int, chunk: int, stream):
 
 
 def evaluate(model, seeds, n_fine, factor, n_coarse_steps, plain_sizes=(64, 128, 256, 512), chunk=50,
-             direct: bool = False):
+             direct: bool = False, blend: bool = False):
     """Errors at the final time of the learned coarse solver and of the plain
     scheme at plain_sizes against the fine reference (block-averaged), and
     graph-replayed time-to-solution of each."""
@@ -162,7 +162,7 @@ def evaluate(model, seeds, n_fine, factor, n_coarse_steps, plain_sizes=(64, 128,
         q0c = fv.coarsen(q0f, factor).cpu().numpy()
         st = torch.cuda.Stream()
         sl = fv.Solver(q0c, prec=fv.FV_F32, dt_fixed=dt_c, learned=1, h_ref=1.0, stream=st)
-        lstep = fv.fv_direct_step if direct else fv.fv_learned_step
+        lstep = fv.fv_direct_step if direct else fv.fv_blend_step if blend else fv.fv_learned_step
         times["learned"].append(graph_replay(lambda k: lstep(sl.h, model.h, k, want_stats=False),
                                              n_coarse_steps, chunk, st))
         out = sl.state()
@@ -208,6 +208,8 @@ def main():
                     help="grid sides of the plain-scheme comparison runs (multiples of the coarse side)")
     ap.add_argument("--direct", action="store_true",
                     help="the direct face-state scheme of section 5.3 instead of the stencil coefficients")
+    ap.add_argument("--eval-blend", action="store_true",
+                    help="also evaluate the trained network with the flux-limiter blend of its face fluxes")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     plain_sizes = tuple(int(v) for v in a.plain_sizes.split(",") if v)
@@ -225,6 +227,11 @@ def main():
     untrained = fv.Model(init_params(0), model.desc)
     res["untrained"] = evaluate(untrained, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps,
                                 plain_sizes=(), direct=a.direct)["cases"]["learned"]
+    if a.eval_blend and not a.direct:
+        res["blend"] = evaluate(model, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps,
+                                plain_sizes=(), blend=True)["cases"]["learned"]
+        print(f"[eval] blended: rel L2(h) {res['blend']['rel_l2_h']:.3e} in "
+              f"{res['blend']['time_to_solution_s'] * 1e3:.1f} ms", flush=True)
     res["scheme"] = "direct face states" if a.direct else "stencil coefficients"
     res["train"] = {"iters": a.iters, "batch": a.batch, "T": a.T, "wall_s": wall, "data_s": tdata,
                     "loss_first": hist[0][2], "loss_last": hist[-1][2], "snapshots": int(data.shape[0] * data.shape[1])}
