@@ -300,16 +300,35 @@ def learned_step(params, q, dt, dx, dy, g=9.81, flux="hlle", order=1, round_bf16
 # The network maps the cell averages to the states at the four faces of each
 # cell, Q^l, Q^r, Q^b, Q^u (left, right, bottom, top); the flux of a face is
 # the numerical flux of the states its two cells give it, so the face is
-# shared and the scheme stays conservative.  Reading of the output: channel
-# 3f + v (f = l, r, b, u) is a correction to the cell average in the input's
-# normalised units, Q^f_v = q_v + z_{3f+v} / inv_std_v (a zero head is the
-# first-order scheme); the other output channels are unused.
+# shared and the scheme stays conservative.  Section 2.5.3 (third approach)
+# splits the network's output into a height part and a momentum part and ends
+# the height part in a Softplus so that every reconstructed depth is
+# positive.  Reading of the output: channel 3f + v (f = l, r, b, u) belongs to
+# face state f and variable v;
+#   depth     Q^f_h = q_h * softplus(z_{3f} + c),  c = ln(e - 1), softplus(c) = 1,
+#   momentum  Q^f_m = q_m + z_{3f+m} / inv_std_m   (m = hu, hv),
+# so a zero head is the first-order scheme and a face depth is positive
+# wherever its cell's is (the Softplus part is the depth relative to the
+# cell's own).  The other output channels are unused.
+
+SOFTPLUS_SHIFT = math.log(math.e - 1.0)
+
+
+def softplus(x: torch.Tensor) -> torch.Tensor:
+    """ln(1 + e^x), evaluated without overflow."""
+    return torch.logaddexp(x, torch.zeros_like(x))
+
 
 def direct_faces(params, q, round_bf16=True):
     """(Ql, Qr, Qb, Qu), each (B, 3, H, W): the network's four face states of every cell."""
     z = cnn(params, q, round_bf16)
-    sig = (1.0 / params["inv_std"])[None, :, None, None]
-    return tuple(q + sig * z[:, 3 * f:3 * f + 3] for f in range(4))
+    sig = (1.0 / params["inv_std"])[None, 1:, None, None]
+    out = []
+    for f in range(4):
+        zf = z[:, 3 * f:3 * f + 3]
+        depth = q[:, :1] * softplus(zf[:, :1] + SOFTPLUS_SHIFT)
+        out.append(torch.cat([depth, q[:, 1:] + sig * zf[:, 1:]], dim=1))
+    return tuple(out)
 
 
 def direct_rhs(params, q, dx, dy, g=9.81, flux="hlle", round_bf16=True):
@@ -371,6 +390,8 @@ def rollout_loss(params, q0, targets, dt, dx, dy, scale, g=9.81, flux="hlle", ro
 
 
 def block_average(q: torch.Tensor, f: int) -> torch.Tensor:
-    """Exact cell-average coarsening by an f x f block mean."""
-    B, V, H, W = q.shape
-    return q.reshape(B, V, H // f, f, W // f, f).mean(dim=(3, 5))
+    """Exact cell-average coarsening (training targets of section 2.5.1 come
+    from coarsened high-resolution runs): coarse cell (I, J) is the mean of
+    the f x f fine cells it covers, q (..., H, W) with H, W multiples of f."""
+    *lead, H, W = q.shape
+    return q.reshape(*lead, H // f, f, W // f, f).mean(dim=(-3, -1))

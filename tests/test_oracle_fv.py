@@ -128,13 +128,13 @@ def test_supersonic_upwinding(orc, eqn, name, fl):
 
 # ------------------------------------------------------ exact Riemann pins
 
-def _run_to(orc, c, q, t_end):
+def _run_to(orc, c, q, t_end, b=None):
     """Run with a fixed step chosen so that CFL <= 0.4 holds throughout."""
     amax = orc.max_rate(c, q)
     # star states are faster than the initial ones: bound by 1.6x
     n = int(math.ceil(t_end * amax * 1.6 / 0.4))
     c.dt_fixed = t_end / n
-    out, t, *_ , rc = orc.run(c, q, None, n)
+    out, t, *_ , rc = orc.run(c, q, b, n)
     assert rc == 0
     assert abs(t - t_end) < 1e-12
     return out
@@ -373,3 +373,133 @@ def test_first_order_mode_is_first_order_and_more_diffusive(orc):
     e2 = [run(n, 0) for n in (128, 256)]
     assert e1[1] < e1[0]
     assert e2[0] < e1[0] and e2[1] < e1[1]
+
+
+# ---------------------------------------------------- energy of eq 5.1
+
+@pytest.mark.parametrize("eqn", [0, 1])
+def test_totals_uniform_state_closed_form(orc, eqn):
+    """Uniform state on [0, 1] x [0, 2]: each conserved total is its value
+    times the area; the SWE energy of eq 5.1 is (g h^2/2 + h (u^2 + v^2)/2)
+    times the area, the Euler one the kinetic rho (u^2 + v^2)/2 times the area."""
+    n, area = 12, 2.0
+    if eqn == 0:
+        h, u, v = 1.7, 0.3, -0.2
+        q = I.uniform_state(n, h, u, v)
+        want = [h * area, h * u * area, h * v * area, (0.5 * 9.81 * h * h + 0.5 * h * (u * u + v * v)) * area]
+    else:
+        rho, u, v, p = 0.8, -0.4, 0.25, 1.3
+        q = np.zeros((4, n, n))
+        q[0], q[1], q[2] = rho, rho * u, rho * v
+        q[3] = p / 0.4 + 0.5 * rho * (u * u + v * v)
+        want = [rho * area, rho * u * area, rho * v * area, q[3, 0, 0] * area, 0.5 * rho * (u * u + v * v) * area]
+    got = orc.totals(cfg(orc, eqn=eqn, nx=n, ny=n, lx=1.0, ly=2.0), q)
+    assert np.allclose(got, want, rtol=1e-14, atol=0), (got, want)
+
+
+def test_energy_of_moving_hump_by_quadrature(orc):
+    """Config-1 hump h = 1 + 0.1 exp(-r^2/s), s = 0.01, moving at the uniform
+    velocity (0.3, -0.2): the energy of eq 5.1 is g/2 int h^2 + |u|^2/2 int h,
+    with int h = 1 + 0.1 pi s erf(1/(2 sqrt s))^2 and
+    int h^2 = 1 + 0.2 pi s erf(1/(2 sqrt s))^2 + 0.01 (pi s / 2) erf(1/sqrt(2 s))^2
+    over the unit square.  Cell-centre sums of this Gaussian are exact to
+    ~1e-14 at 64^2 (the midpoint rule on a function that is flat to e^-25 at
+    the border).  A wrong factor on either energy term, or the kinetic term
+    taken with the momenta instead of the velocities, fails by far more."""
+    u, v, s = 0.3, -0.2, 0.01
+    q = I.gaussian_hump(64)
+    q[1], q[2] = q[0] * u, q[0] * v
+    e1 = math.erf(0.5 / math.sqrt(s)) ** 2
+    e2 = math.erf(0.5 * math.sqrt(2.0 / s)) ** 2
+    int_h = 1.0 + 0.1 * math.pi * s * e1
+    int_h2 = 1.0 + 0.2 * math.pi * s * e1 + 0.01 * (math.pi * s / 2.0) * e2
+    want = 0.5 * 9.81 * int_h2 + 0.5 * (u * u + v * v) * int_h
+    got = orc.totals(cfg(orc, nx=64, ny=64), q)
+    assert abs(got[0] - int_h) <= 1e-13 * int_h
+    assert abs(got[1] - u * int_h) <= 1e-13 * int_h and abs(got[2] - v * int_h) <= 1e-13 * int_h
+    assert abs(got[3] - want) <= 1e-13 * want, (got[3], want)
+
+
+# ------------------------------------- moving steady flow over a bed
+
+def _bernoulli_steady(x, amp=0.1, disch=0.5, h_far=1.0, g=9.81):
+    """y-invariant steady flow over the periodic bump b = amp (1 - cos 2 pi x)/2
+    with constant discharge hu = disch: the depth solves
+    disch^2 / (2 h^2) + g (h + b) = disch^2 / (2 h_far^2) + g h_far on the
+    subcritical branch (Newton from h_far - b).  This is an exact steady
+    solution of the shallow-water equations with a bed source (eq 2.3):
+    d(hu)/dx = 0 and d(hu^2 + g h^2/2)/dx = -g h db/dx."""
+    b = amp * 0.5 * (1.0 - np.cos(2.0 * np.pi * x))
+    E = disch ** 2 / (2.0 * h_far ** 2) + g * h_far
+    h = h_far - b
+    for _ in range(60):
+        f = disch ** 2 / (2.0 * h * h) + g * (h + b) - E
+        h = h - f / (g - disch ** 2 / h ** 3)
+    return h, b
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,fl", FLUXES)
+def test_moving_steady_flow_over_bed_converges(orc, name, fl):
+    """Subcritical flow over a smooth bump (Froude number <= 0.19), started at
+    the exact steady state (point values at cell centres), periodic: after
+    t = 0.1 the L1 deviation of h and hu from that state falls at observed
+    order >= 1.5 over N = 64 .. 512, for every flux.  The hydrostatic
+    reconstruction must carry the face velocities (rescaling the momenta by
+    h*/h); keeping the momenta, dropping the interface correction or the
+    centred bed source leaves an O(dx) imbalance in moving water, which the
+    lake at rest (u = 0) cannot see."""
+    errs = []
+    sizes = [64, 128, 256, 512]
+    for n in sizes:
+        x = I.centres(n)
+        h, b1 = _bernoulli_steady(x)
+        ny = 4
+        q = np.zeros((3, ny, n))
+        q[0] = h[None, :]
+        q[1] = 0.5
+        b = np.repeat(b1[None, :], ny, axis=0)
+        c = cfg(orc, nx=n, ny=ny, ly=ny / n, flux=fl, nthreads=4)
+        out = _run_to(orc, c, q, 0.1, b)
+        assert np.abs(out[:, 1:, :] - out[:, :1, :]).max() == 0.0  # stays y-invariant
+        assert np.abs(out[2]).max() == 0.0
+        errs.append(np.abs(out[0, 0] - h).mean() + np.abs(out[1, 0] - 0.5).mean())
+    orders = [math.log2(errs[k] / errs[k + 1]) for k in range(len(errs) - 1)]
+    order = math.log2(errs[0] / errs[-1]) / (len(errs) - 1)
+    assert order >= 1.5, (errs, orders)
+    assert min(orders) >= 1.2, (errs, orders)
+
+
+@pytest.mark.parametrize("name,fl", FLUXES)
+@pytest.mark.parametrize("axis", [0, 1])
+def test_emerged_face_ignores_the_dry_sides_momentum(orc, name, fl, axis):
+    """Moving shallow water (depth 0.2, surface 0.2) against a bed step whose
+    top (0.5) stands above that surface, deeper water at rest on the step
+    (surface 0.8): at the step's face the low side's hydrostatic depth is
+    zero, so that side carries no water and no momentum, and the face flux
+    must not depend on how fast the low side's water moves.  A hydrostatic
+    reconstruction that keeps the low side's momentum instead of its velocity
+    (h* u) puts that momentum into the mass flux; the lake at rest and the
+    smooth moving steady state cannot see this."""
+    n = 8
+    b1 = np.where(np.arange(n) >= 4, 0.5, 0.0)
+    eta = np.where(np.arange(n) >= 4, 0.8, 0.2)
+
+    def face_flux(u_low):
+        q = np.zeros((3, 2, n))
+        q[0] = (eta - b1)[None, :]
+        q[1 + axis] = np.where(np.arange(n) < 4, 0.2 * u_low, 0.0)[None, :]
+        b = np.repeat(b1[None, :], 2, axis=0)
+        if axis == 1:
+            q = np.stack([q[0].T, q[2].T, q[1].T])
+            b = b.T.copy()
+        ny, nx = q.shape[1:]
+        c = cfg(orc, nx=nx, ny=ny, lx=nx / 8, ly=ny / 8, flux=fl, bc_x=1, bc_y=1)
+        Fx, Fy = orc.face_fluxes(c, q, b)
+        return Fx[:, 0, 4].copy() if axis == 0 else Fy[:, 4, 0].copy()
+
+    base = face_flux(0.0)
+    for u_low in (-0.3, 0.25, 0.6):
+        f = face_flux(u_low)
+        assert np.array_equal(f, base), (u_low, f, base)
+    assert base[0] < 0.0  # water from the step spills towards the low side

@@ -3,6 +3,7 @@ exactness on linear data, special cases that reduce to the (separately
 pinned) classic oracle, brute-force convolution, bfloat16 rounding, the
 fallback wiring, and autograd gradients against central finite differences."""
 import itertools
+import math
 
 import numpy as np
 import pytest
@@ -236,13 +237,16 @@ def test_direct_zero_head_is_first_order_classic(L, orc, flux, cflux):
 
 
 def test_direct_face_pairing_reproduces_minmod(L, monkeypatch):
-    """With a head that outputs the MINMOD corrections (+s/2 on the right and
-    top sides, -s/2 on the left and bottom, in normalised units), cell i's
-    right state and cell i+1's left state are MINMOD's two states of face
-    i+1/2 on both axes: the direct operator equals the plain MINMOD one.  Pins
-    which cell's side meets which, and the de-normalisation."""
+    """With a head that outputs the MINMOD face states (depth: the ratio
+    (q_h +- s_h/2) / q_h through the inverse of the shifted Softplus;
+    momenta: +-s/2 in normalised units; + on the right and top sides, - on
+    the left and bottom), cell i's right state and cell i+1's left state are
+    MINMOD's two states of face i+1/2 on both axes: the direct operator
+    equals the plain MINMOD one.  Pins which cell's side meets which, the
+    depth's scaling by its own cell, and the de-normalisation of the momenta."""
     q0 = I.random_smooth_swe(24, seed=6)
     q0[1] = 0.03 * np.sin(2 * np.pi * np.arange(24) / 24)[None, :]
+    q0[2] = 0.02 * np.cos(2 * np.pi * np.arange(24) / 24)[:, None]
     q = torch.tensor(q0)[None]
     p = _params_head(L, 2)
     inv = p["inv_std"][None, :, None, None]
@@ -250,13 +254,18 @@ def test_direct_face_pairing_reproduces_minmod(L, monkeypatch):
     def slope(x, dim):
         return L._minmod(x - L._shift(x, -1, dim), L._shift(x, 1, dim) - x)
 
+    def head(x, s, sign):
+        ratio = (x[:, :1] + sign * 0.5 * s[:, :1]) / x[:, :1]
+        zh = torch.log(torch.expm1(ratio)) - L.SOFTPLUS_SHIFT
+        return torch.cat([zh, sign * 0.5 * s[:, 1:] * inv[:, 1:]], dim=1)
+
     def fake_cnn(params, x, round_bf16=True, shadow_f32=False):
         sx, sy = slope(x, 3), slope(x, 2)
         z = torch.zeros(x.shape[0], 72, x.shape[2], x.shape[3], dtype=F64)
-        z[:, 0:3] = -0.5 * sx * inv   # left
-        z[:, 3:6] = 0.5 * sx * inv    # right
-        z[:, 6:9] = -0.5 * sy * inv   # bottom
-        z[:, 9:12] = 0.5 * sy * inv   # top
+        z[:, 0:3] = head(x, sx, -1.0)   # left
+        z[:, 3:6] = head(x, sx, 1.0)    # right
+        z[:, 6:9] = head(x, sy, -1.0)   # bottom
+        z[:, 9:12] = head(x, sy, 1.0)   # top
         return z
 
     monkeypatch.setattr(L, "cnn", fake_cnn)
@@ -264,6 +273,41 @@ def test_direct_face_pairing_reproduces_minmod(L, monkeypatch):
     ref, _ = L.rhs(q, None, 1 / 24, 1 / 24)
     assert int(nfb.sum()) == 0
     assert torch.abs(Lq - ref).max() <= 1e-12 * torch.abs(ref).max()
+
+
+def test_softplus_values(L):
+    """softplus(0) = ln 2, softplus(c) = 1 for the shift c = ln(e - 1), the
+    asymptotes x (large x) and e^x (very negative x), and no overflow."""
+    x = torch.tensor([0.0, L.SOFTPLUS_SHIFT, 800.0, -40.0, -700.0], dtype=F64)
+    y = L.softplus(x)
+    assert abs(float(y[0]) - math.log(2.0)) <= 1e-16
+    assert abs(float(y[1]) - 1.0) <= 2e-16
+    assert float(y[2]) == 800.0
+    assert abs(float(y[3]) / math.exp(-40.0) - 1.0) <= 1e-15
+    assert 0.0 < float(y[4]) and abs(float(y[4]) / math.exp(-700.0) - 1.0) <= 1e-12
+
+
+def test_direct_depths_positive_for_any_head(L):
+    """The Softplus depth head of section 2.5.3 (third approach): a strongly
+    negative height head still gives positive face depths, so no face side
+    falls back, and each depth is its cell's depth times e^(b + c) to first
+    order; a random large head gives positive depths everywhere too."""
+    q0 = I.random_smooth_swe(16, seed=10)
+    q = torch.tensor(q0)[None]
+    hb = [0.0] * 12
+    for f in range(4):
+        hb[3 * f] = -30.0
+    p = _params_head(L, 11, head_bias=hb)
+    faces = L.direct_faces(p, q)
+    for Qf in faces:
+        assert bool((Qf[:, 0] > 0).all())
+        assert torch.allclose(Qf[:, 0], q[:, 0] * math.exp(-30.0 + L.SOFTPLUS_SHIFT), rtol=1e-12, atol=0)
+        assert torch.equal(Qf[:, 1:], q[:, 1:])
+    _, nfb = L.direct_rhs(p, q, 1 / 16, 1 / 16)
+    assert int(nfb.sum()) == 0
+    p = _params_head(L, 12, scale_last=5.0)
+    for Qf in L.direct_faces(p, q):
+        assert bool((Qf[:, 0] > 0).all())
 
 
 def test_direct_step_conserves_and_keeps_uniform_states(L):
@@ -287,9 +331,9 @@ def test_direct_step_conserves_and_keeps_uniform_states(L):
 
 
 def test_direct_all_faces_fall_back_gives_plain_scheme(L):
-    """A head that drives every face depth negative sends every side to its
-    MINMOD state: the operator equals the plain one exactly, 4 sides per cell
-    counted."""
+    """A height head so negative that the Softplus underflows to zero depth
+    sends every side to its MINMOD state: the operator equals the plain one
+    exactly, 4 sides per cell counted."""
     q0 = I.random_smooth_swe(16, seed=8)
     q = torch.tensor(q0)[None]
     hb = [0.0] * 12
@@ -408,3 +452,74 @@ def test_blend_step_conserves_and_keeps_uniform_states(L):
     u[:, 0], u[:, 1], u[:, 2] = 1.2, 0.1, -0.05
     Lu, _ = L.rhs(u, _alpha(L, p, u), 1 / 16, 1 / 16, blend=True)
     assert torch.abs(Lu).max() <= 1e-13
+
+
+# ---- admissibility redo (section 5.2: a negative depth gives NaN) ----------
+
+REDO_SCHEMES = ["learned", "direct", "blend"]
+
+
+def _step(L, scheme, p, q, dt, n):
+    if scheme == "direct":
+        return L.direct_step(p, q, dt, 1 / n, 1 / n)
+    return L.learned_step(p, q, dt, 1 / n, 1 / n, blend=scheme == "blend")
+
+
+@pytest.mark.parametrize("scheme", REDO_SCHEMES)
+def test_inadmissible_step_is_redone_with_the_plain_scheme(L, scheme):
+    """A shallow state (depth about 0.1) and a large random head: the learned
+    stages leave cells with non-positive depth, so the whole step is redone
+    and its result is exactly the plain MINMOD Heun step of the same state;
+    the plain step stays admissible."""
+    n = 32
+    q = torch.tensor(I.random_smooth_swe(n, seed=2))[None]
+    q[:, 0] *= 0.1
+    p = L.init_params(2, scale_last=10.0)
+    qn, st = _step(L, scheme, p, q, 1e-3, n)
+    qp = L.plain_step(q, 1e-3, 1 / n, 1 / n)
+    assert bool(st["redone"][0])
+    assert bool((qp[:, 0] > 0).all())
+    assert torch.equal(qn, qp)
+
+
+@pytest.mark.parametrize("scheme", REDO_SCHEMES)
+def test_redo_is_per_solve(L, scheme):
+    """In a batch, only the solve whose step is inadmissible is redone; the
+    other (a weak hump at depth 1) keeps its learned result, equal to that
+    solve stepped alone."""
+    n = 32
+    qa = torch.tensor(I.random_smooth_swe(n, seed=2))[None]
+    qa[:, 0] *= 0.1
+    qb = torch.tensor(I.random_smooth_swe(n, seed=3))[None]
+    qb[:, 0] = 1.0 + 0.01 * (qb[:, 0] - 1.0)
+    p = L.init_params(2, scale_last=10.0)
+    qab, st = _step(L, scheme, p, torch.cat([qa, qb]), 1e-3, n)
+    assert st["redone"].tolist() == [True, False]
+    assert torch.equal(qab[:1], L.plain_step(qa, 1e-3, 1 / n, 1 / n))
+    qb1, stb = _step(L, scheme, p, qb, 1e-3, n)
+    assert not bool(stb["redone"][0])
+    assert torch.allclose(qab[1:], qb1, rtol=0, atol=1e-14)
+
+
+def test_block_average_brute_force(L):
+    """Coarse cell (I, J) is the plain mean of the fine cells (f I + a, f J + c),
+    a, c < f, summed by explicit loops."""
+    g = torch.Generator().manual_seed(3)
+    x = torch.rand(2, 3, 12, 8, generator=g, dtype=F64)
+    f = 4
+    c = L.block_average(x, f)
+    assert c.shape == (2, 3, 3, 2)
+    for b in range(2):
+        for v in range(3):
+            for I_ in range(3):
+                for J in range(2):
+                    acc = 0.0
+                    for a in range(f):
+                        for d in range(f):
+                            acc += float(x[b, v, f * I_ + a, f * J + d])
+                    assert abs(float(c[b, v, I_, J]) - acc / (f * f)) <= 1e-15
+    # a field linear in x and y keeps its value at the coarse cell centres
+    yy, xx = torch.meshgrid(torch.arange(16, dtype=F64) + 0.5, torch.arange(16, dtype=F64) + 0.5, indexing="ij")
+    lin = (0.3 + 0.02 * xx - 0.05 * yy)[None]
+    cy, cx = torch.meshgrid(4 * torch.arange(4, dtype=F64) + 2, 4 * torch.arange(4, dtype=F64) + 2, indexing="ij")
+    assert torch.allclose(L.block_average(lin, 4)[0], 0.3 + 0.02 * cx - 0.05 * cy, atol=1e-14)
