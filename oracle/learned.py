@@ -304,8 +304,10 @@ def learned_step(params, q, dt, dx, dy, g=9.81, flux="hlle", order=1, round_bf16
 # splits the network's output into a height part and a momentum part and ends
 # the height part in a Softplus so that every reconstructed depth is
 # positive.  Reading of the output: channel 3f + v (f = l, r, b, u) belongs to
-# face state f and variable v;
-#   depth     Q^f_h = q_h * softplus(z_{3f} + c),  c = ln(e - 1), softplus(c) = 1,
+# face state f and variable v, in the input's normalised units (de-normalised
+# by 1/inv_std_v);
+#   depth     Q^f_h = q_h * softplus(z_{3f} / inv_std_h + c),  c = ln(e - 1),
+#             softplus(c) = 1,
 #   momentum  Q^f_m = q_m + z_{3f+m} / inv_std_m   (m = hu, hv),
 # so a zero head is the first-order scheme and a face depth is positive
 # wherever its cell's is (the Softplus part is the depth relative to the
@@ -322,12 +324,12 @@ def softplus(x: torch.Tensor) -> torch.Tensor:
 def direct_faces(params, q, round_bf16=True):
     """(Ql, Qr, Qb, Qu), each (B, 3, H, W): the network's four face states of every cell."""
     z = cnn(params, q, round_bf16)
-    sig = (1.0 / params["inv_std"])[None, 1:, None, None]
+    sig = (1.0 / params["inv_std"])[None, :, None, None]
     out = []
     for f in range(4):
-        zf = z[:, 3 * f:3 * f + 3]
+        zf = sig * z[:, 3 * f:3 * f + 3]
         depth = q[:, :1] * softplus(zf[:, :1] + SOFTPLUS_SHIFT)
-        out.append(torch.cat([depth, q[:, 1:] + sig * zf[:, 1:]], dim=1))
+        out.append(torch.cat([depth, q[:, 1:] + zf[:, 1:]], dim=1))
     return tuple(out)
 
 

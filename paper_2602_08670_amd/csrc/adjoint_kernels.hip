@@ -18,6 +18,7 @@
 #include "cnn_internal.hpp"
 #include "dual.hpp"
 #include "fv_device.hpp"
+#include "learned_device.hpp"
 
 namespace cnn {
 
@@ -71,11 +72,14 @@ __device__ __forceinline__ void minmod_right(const float *c, float &val, float *
 }
 
 // DIR: the direct face-state scheme (section 5.3): the face's left state is
-// the owner's right (top) state q_i + sig z_i[hi] and its right state the
-// neighbour's left (bottom) state q_{i+1} + sig z_{i+1}[lo], so a learned
-// side passes g_Q to its own cell and g_Q sig to its own cell's channels of
-// z; this face writes the owner's high-side and the neighbour's low-side
-// channels of dz (each written by exactly one face).
+// the owner's right (top) state and its right state the neighbour's left
+// (bottom) state; a side's depth is h_c softplus(sig_h z_h + c) and its
+// momenta m_c + sig z_m (h_c, m_c: its own cell's), so a learned side passes
+// g_Q softplus(sig_h z_h + c) (depth) and g_Q (momenta) to its own cell, and
+// g_Q h_c sig_h sigmoid(sig_h z_h + c) and g_Q sig to its own cell's channels
+// of z; this
+// face writes the owner's high-side and the neighbour's low-side channels of
+// dz (each written by exactly one face).
 template <int FLUX, bool DIR>
 __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
 {
@@ -128,17 +132,22 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
         bool useL[2] = {false, false};
         // the cell across the face (the owner's +x or +y neighbour)
         const int nbc = axis == 0 ? y * nx + pw(x + 1, nx) : pw(y + 1, ny) * nx + x;
+        float dsp[2] = {0.f, 0.f};  // direct: d depth / d z_h of each side
         if (DIR && learned) {
             const float *zo = a.z + ((size_t)b * plane + cell) * 72 + (axis == 0 ? 3 : 9);
             const float *zn = a.z + ((size_t)b * plane + nbc) * 72 + (axis == 0 ? 0 : 6);
+            const float ao = a.sig[0] * zo[0] + kSoftplusShift, an = a.sig[0] * zn[0] + kSoftplusShift;
+            const float so = softplusf(ao), sn = softplusf(an);
+            dsp[0] = st[0][2] * a.sig[0] / (1.f + expf(-ao));
+            dsp[1] = st[0][3] * a.sig[0] / (1.f + expf(-an));
 #pragma unroll
             for (int v = 0; v < 3; v++) {
-                QS[0][v] = st[v][2] + a.sig[v] * zo[v];
-                QS[1][v] = st[v][3] + a.sig[v] * zn[v];
+                QS[0][v] = v == 0 ? st[0][2] * so : st[v][2] + a.sig[v] * zo[v];
+                QS[1][v] = v == 0 ? st[0][3] * sn : st[v][3] + a.sig[v] * zn[v];
 #pragma unroll
                 for (int k = 0; k < 6; k++) {
-                    al[0][v][k] = k == 2 ? 1.f : 0.f;
-                    al[1][v][k] = k == 3 ? 1.f : 0.f;
+                    al[0][v][k] = k == 2 ? (v == 0 ? so : 1.f) : 0.f;
+                    al[1][v][k] = k == 3 ? (v == 0 ? sn : 1.f) : 0.f;
                 }
             }
             useL[0] = QS[0][0] > 0.f;
@@ -249,8 +258,8 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
             __bf16 *dzn = a.dz + ((size_t)b * plane + nbc) * DZ_CH + (axis == 0 ? 0 : 6);
 #pragma unroll
             for (int v = 0; v < 3; v++) {
-                dzo[v] = (__bf16)(useL[0] ? gQ[0][v] * a.sig[v] : 0.f);
-                dzn[v] = (__bf16)(useL[1] ? gQ[1][v] * a.sig[v] : 0.f);
+                dzo[v] = (__bf16)(useL[0] ? gQ[0][v] * (v == 0 ? dsp[0] : a.sig[v]) : 0.f);
+                dzn[v] = (__bf16)(useL[1] ? gQ[1][v] * (v == 0 ? dsp[1] : a.sig[v]) : 0.f);
             }
         } else {
             typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;

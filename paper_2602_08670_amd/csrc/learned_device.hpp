@@ -67,12 +67,27 @@ __device__ __forceinline__ int face_states(const float (*st)[6], const float *zc
     return (ll ? 0 : 1) + (lr ? 0 : 1);
 }
 
-// Face states of one face in the direct scheme (thesis section 5.3): the
-// owner cell's high-side state and the neighbour's low-side state, each its
-// cell average plus the network's correction in normalised units,
-// Q = q + zc / inv_std (zo: the owner's three values for its right or top
-// side, zn: the neighbour's for its left or bottom side; sig = 1 / inv_std).
-// A side whose depth is not positive takes its MINMOD state (counted).
+// Direct face states (thesis section 2.5.3, third approach; section 5.3):
+// the network's output is split into a depth part and a momentum part, and
+// the depth part ends in a Softplus so every reconstructed depth is positive.
+// The outputs are in the input's normalised units (de-normalised by
+// 1 / inv_std): a face state's depth is its cell's depth times
+// softplus(z / inv_std + c), with c = ln(e - 1) so that softplus(c) = 1 (a
+// zero head is the first-order scheme); its momenta are the cell's plus
+// z / inv_std.
+constexpr float kSoftplusShift = 0.541324854612918f;  // ln(e - 1)
+
+// ln(1 + e^x) without overflow or loss of the small values.
+__device__ __forceinline__ float softplusf(float x)
+{
+    return __builtin_fmaxf(x, 0.0f) + log1pf(expf(-__builtin_fabsf(x)));
+}
+
+// Face states of one face in the direct scheme: the owner cell's high-side
+// state and the neighbour's low-side state (zo: the owner's three outputs for
+// its right or top side, zn: the neighbour's for its left or bottom side;
+// sig = 1 / inv_std).  A side whose depth is not positive (the Softplus
+// underflowed) takes its MINMOD state (counted).
 __device__ __forceinline__ int face_states_direct(const float (*st)[6], const float *zo, const float *zn,
                                                   const float *sig, float *QL, float *QR)
 {
@@ -84,6 +99,11 @@ __device__ __forceinline__ int face_states_direct(const float (*st)[6], const fl
     for (int v = 0; v < 3; v++) {
         ML[v] = okl ? ML[v] : st[v][2];
         MR[v] = okr ? MR[v] : st[v][3];
+    }
+    QL[0] = st[0][2] * softplusf(sig[0] * zo[0] + kSoftplusShift);
+    QR[0] = st[0][3] * softplusf(sig[0] * zn[0] + kSoftplusShift);
+#pragma unroll
+    for (int v = 1; v < 3; v++) {
         QL[v] = st[v][2] + sig[v] * zo[v];
         QR[v] = st[v][3] + sig[v] * zn[v];
     }

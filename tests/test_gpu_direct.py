@@ -109,21 +109,36 @@ def test_direct_zero_head_is_first_order(fv, L):
     assert stats == (0, 0)
 
 
-def test_direct_fallback_counts_and_state(fv, L):
-    """Depth corrections near minus the depth on the left and bottom sides
-    (bias -9.5 and -10.2 in normalised units, inv_std = 10, depths 0.88..1.13)
-    send part of those face sides to MINMOD: counts and states agree with the
-    oracle (about 8000 fallback sides)."""
+def test_direct_negative_depth_head_keeps_depths_positive(fv, L):
+    """Height-head bias -200 on every side (-20 de-normalised): the Softplus
+    keeps every face depth positive (about 4e-9 of its cell's), so no side
+    falls back, on the GPU as in the oracle, and the states agree."""
     hb = [0.0] * 12
-    hb[0], hb[6] = -9.5, -10.2  # depth corrections of the left and bottom states
+    for f in range(4):
+        hb[3 * f] = -200.0
+    p = params(L, 5, scale_last=0.0, head_bias=hb)
+    q0 = I.random_smooth_swe(64, seed=23, humps=4)
+    out, ref, stats, ostats, _ = run_direct(fv, L, p, q0, 2e-4, 2)
+    print(f"[direct positive] gpu {stats} oracle {ostats} err {state_rel(out, ref):.2e}", flush=True)
+    assert stats == (0, 0) and ostats == (0, 0)
+    assert state_rel(out, ref) <= 1e-5
+
+
+def test_direct_fallback_counts_and_state(fv, L):
+    """Height-head bias -1e4 (-1e3 de-normalised): the Softplus underflows to
+    zero depth in FP32 and in FP64 alike, so every face side of both stages takes its MINMOD state
+    (2 axes x 2 sides per cell and stage, counted on both sides) and the step
+    is the plain MINMOD step."""
+    hb = [0.0] * 12
+    for f in range(4):
+        hb[3 * f] = -1.0e4
     p = params(L, 5, scale_last=0.3, head_bias=hb)
     q0 = I.random_smooth_swe(64, seed=23, humps=4)
     out, ref, stats, ostats, _ = run_direct(fv, L, p, q0, 2e-4, 1)
     print(f"[direct fallback] gpu {stats} oracle {ostats} err {state_rel(out, ref):.2e}", flush=True)
-    assert 1000 < ostats[0] < 2 * 4 * 64 * 64
-    assert abs(stats[0] - ostats[0]) <= 0.01 * ostats[0] + 2
-    assert stats[1] == ostats[1]
-    assert state_rel(out, ref) <= 1e-4
+    assert ostats == (2 * 4 * 64 * 64, 0)
+    assert stats == ostats
+    assert state_rel(out, ref) <= 1e-5
 
 
 def test_direct_step_conserves_mass(fv, L):

@@ -173,9 +173,13 @@ def test_fp32_dam_break_2d_shock(fv, orc):
 
 def test_fp32_swe_bathy_1024_full_size(fv, orc):
     """The 1024^2 shallow-water workload over the seeded bed, walls, in the
-    launch configuration the benchmark times: 10 steps against the oracle
-    (FP32 smooth tolerance), then 1000 steps with mass conserved in FP64
-    totals."""
+    launch configuration the benchmark times, for all of its 1000 steps: after
+    10 steps against the oracle (FP32 smooth tolerance, per variable within 2x
+    the FP32-storage floor), after 1000 steps against the oracle's 1000-step
+    FP64 run (state relative L2 <= 1e-5, simulated time 1e-6), and the FP64
+    totals of the GPU state (mass, both momenta, eq 5.1 energy) against the
+    oracle's totals of its own state: mass to 2e-6 of its initial value, the
+    energy and the momenta to 1e-6 of the energy."""
     q0, b = I.swe_bathy(1024, seed=0)
     kw = dict(bc_x=1, bc_y=1)
     s = fv.Solver(q0, b, prec=fv.FV_F32, **kw)
@@ -185,10 +189,52 @@ def test_fp32_swe_bathy_1024_full_size(fv, orc):
     fp32_smooth_check(orc, out, q0, b, 10, **kw)
     s.run(990)
     t, n = s.time()
-    m1 = s.totals()[0]
+    tot = s.totals()
+    out = s.state()
     s.close()
     assert n == 1000
-    assert abs(m1 - m0) <= 2e-6 * m0
+    assert abs(tot[0] - m0) <= 2e-6 * m0
+    c = orc_cfg(orc, q0, **kw)
+    c.nthreads = 16
+    print("[oracle] 1024^2 shallow water over the bed, 1000 steps (FP64, 16 threads)", flush=True)
+    ref, t_ref, *_, rc = orc.run(c, q0, b, 1000)
+    assert rc == 0
+    tref = orc.totals(c, ref)
+    print(f"[fp32 1000 steps] state rel L2 {state_rel(out, ref):.2e}; per var {rel_errors(out, ref)}; "
+          f"totals gpu {tot} oracle {tref}", flush=True)
+    assert abs(t - t_ref) <= 1e-6 * t_ref
+    assert state_rel(out, ref) <= 1e-5
+    assert abs(tot[0] - tref[0]) <= 2e-6 * tref[0]
+    assert np.abs(tot[1:] - tref[1:]).max() <= 1e-6 * tref[3]
+
+
+@pytest.mark.parametrize("eqn", [0, 1])
+def test_totals_every_output_matches_oracle(fv, orc, eqn):
+    """fv_totals returns the nvar conserved totals and the eq 5.1 energy in
+    FP64; each equals the oracle's totals of the same cell values to 1e-13 of
+    the largest total (two FP64 sums in different orders): the initial state
+    in FP64 and in FP32 (the FP32 values widened exactly), and the GPU's own
+    state after 5 steps.  Shallow water: the config-1 hump moving at (0.3, -0.2);
+    Euler: seeded four-quadrant data."""
+    if eqn == 0:
+        q0 = I.gaussian_hump(96)
+        q0[1], q0[2] = 0.3 * q0[0], -0.2 * q0[0]
+    else:
+        q0 = I.euler_quadrants(96, seed=1)
+    c = orc_cfg(orc, q0)
+    for prec in (fv.FV_F64, fv.FV_F32):
+        s = fv.Solver(q0, prec=prec)
+        got = s.totals()
+        qv = q0 if prec == fv.FV_F64 else q0.astype(np.float32).astype(np.float64)
+        ref = orc.totals(c, qv)
+        print(f"[totals eqn={eqn} prec={prec}] gpu {got} oracle {ref}", flush=True)
+        assert got.shape == (q0.shape[0] + 1,)
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), (got, ref)
+        s.run(5)
+        got = s.totals()
+        ref = orc.totals(c, s.state())
+        s.close()
+        assert np.abs(got - ref).max() <= 1e-13 * np.abs(ref).max(), (got, ref)
 
 
 def test_fp32_euler_1024_full_size(fv, orc):

@@ -1,0 +1,81 @@
+"""GPU admissibility redo of the learned schemes (section 5.2: a negative depth
+makes the learned solve produce NaN): a shallow state (depth about 0.1) and a
+large random head make a learned stage leave cells with non-positive depth,
+so the solve's whole step is redone with the plain MINMOD scheme.  The
+oracle pins that case to its plain step exactly (tests/test_oracle_learned.py);
+here the GPU must take the same redo decisions and reach the oracle's state
+(the redone step is the plain FP32 step: relative L2 <= 1e-5 after one step).
+Over three steps the redo counts must agree and the states stay within the
+learned step's tolerance."""
+import numpy as np
+import pytest
+import torch
+
+from parity import rel_errors, state_rel
+from paper_2602_08670_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fv():
+    if not torch.cuda.is_available():
+        pytest.skip("no HIP device")
+    from paper_2602_08670_amd import fv as F
+
+    return F
+
+
+@pytest.fixture(scope="module")
+def L():
+    from oracle import learned
+
+    return learned
+
+
+def shallow_state(n=32):
+    q0 = I.random_smooth_swe(n, seed=2)
+    q0[0] *= 0.1
+    return q0
+
+
+def run(fv, L, scheme, p, q0, dt, nsteps, flux="hlle"):
+    fl = fv.FV_FLUX_HLLE if flux == "hlle" else fv.FV_FLUX_RUSANOV
+    ny, n = q0.shape[-2:]
+    vec = fv.params_to_vector([w.numpy() for w in p["w"]], [b.numpy() for b in p["b"]])
+    m = fv.Model(vec, fv.make_model_desc(mean=tuple(p["mean"].tolist()), inv_std=tuple(p["inv_std"].tolist())))
+    s = fv.Solver(q0.astype(np.float32), prec=fv.FV_F32, dt_fixed=dt, learned=1, flux=fl)
+    print(f"[gpu] redo {scheme} {flux} {ny}x{n} x{nsteps}", flush=True)
+    step = {"learned": s.learned_step, "direct": s.direct_step, "blend": s.blend_step}[scheme]
+    stats = step(m, nsteps)
+    out = s.state()
+    s.close()
+    m.close()
+    qo = torch.tensor(q0.astype(np.float32).astype(np.float64))[None]
+    red = 0
+    with torch.no_grad():
+        for _ in range(nsteps):
+            if scheme == "direct":
+                qo, st = L.direct_step(p, qo, dt, 1.0 / n, 1.0 / ny, flux=flux)
+            else:
+                qo, st = L.learned_step(p, qo, dt, 1.0 / n, 1.0 / ny, flux=flux, blend=scheme == "blend")
+            red += int(st["redone"].sum())
+    return out, qo[0].numpy(), stats, red
+
+
+@pytest.mark.parametrize("scheme", ["learned", "direct", "blend"])
+@pytest.mark.parametrize("flux", ["hlle", "rusanov"])
+def test_forced_redo_matches_oracle(fv, L, scheme, flux):
+    p = L.init_params(2, scale_last=10.0)
+    q0 = shallow_state()
+    out, ref, stats, ored = run(fv, L, scheme, p, q0, 1e-3, 1, flux)
+    print(f"[redo {scheme} {flux} 1 step] gpu {stats} oracle redo {ored} {rel_errors(out, ref)}", flush=True)
+    assert ored == 1
+    assert stats[1] == 1
+    assert state_rel(out, ref) <= 1e-5
+    qp = L.plain_step(torch.tensor(q0.astype(np.float32).astype(np.float64))[None], 1e-3, 1 / 32, 1 / 32)
+    assert state_rel(out, qp[0].numpy()) <= 1e-5
+    out, ref, stats, ored = run(fv, L, scheme, p, q0, 1e-3, 3, flux)
+    print(f"[redo {scheme} {flux} 3 steps] gpu {stats} oracle redo {ored} {rel_errors(out, ref)}", flush=True)
+    assert ored >= 1 and stats[1] == ored
+    assert state_rel(out, ref) <= 1e-4

@@ -256,7 +256,7 @@ def test_direct_face_pairing_reproduces_minmod(L, monkeypatch):
 
     def head(x, s, sign):
         ratio = (x[:, :1] + sign * 0.5 * s[:, :1]) / x[:, :1]
-        zh = torch.log(torch.expm1(ratio)) - L.SOFTPLUS_SHIFT
+        zh = (torch.log(torch.expm1(ratio)) - L.SOFTPLUS_SHIFT) * inv[:, :1]
         return torch.cat([zh, sign * 0.5 * s[:, 1:] * inv[:, 1:]], dim=1)
 
     def fake_cnn(params, x, round_bf16=True, shadow_f32=False):
@@ -289,14 +289,15 @@ def test_softplus_values(L):
 
 def test_direct_depths_positive_for_any_head(L):
     """The Softplus depth head of section 2.5.3 (third approach): a strongly
-    negative height head still gives positive face depths, so no face side
-    falls back, and each depth is its cell's depth times e^(b + c) to first
-    order; a random large head gives positive depths everywhere too."""
+    negative height head (bias -300 in normalised units, -30 de-normalised)
+    still gives positive face depths, so no face side falls back, and each
+    depth is its cell's depth times e^(-30 + c) to first order; a random large
+    head gives positive depths everywhere too."""
     q0 = I.random_smooth_swe(16, seed=10)
     q = torch.tensor(q0)[None]
     hb = [0.0] * 12
     for f in range(4):
-        hb[3 * f] = -30.0
+        hb[3 * f] = -300.0
     p = _params_head(L, 11, head_bias=hb)
     faces = L.direct_faces(p, q)
     for Qf in faces:
@@ -305,7 +306,7 @@ def test_direct_depths_positive_for_any_head(L):
         assert torch.equal(Qf[:, 1:], q[:, 1:])
     _, nfb = L.direct_rhs(p, q, 1 / 16, 1 / 16)
     assert int(nfb.sum()) == 0
-    p = _params_head(L, 12, scale_last=5.0)
+    p = _params_head(L, 12, scale_last=50.0)
     for Qf in L.direct_faces(p, q):
         assert bool((Qf[:, 0] > 0).all())
 
