@@ -56,7 +56,7 @@ template <typename T> struct Phys {
     T g;      // gravity
     T sqg;    // sqrt(g)
     T gamma;  // ratio of specific heats
-    T h0;     // reference depth: the SWE pressure is carried as g (h - h0)(h + h0) / 2
+    T h0;     // reference depth: the SWE pressure is carried as g (h^2 - h0^2) / 2
 };
 
 // ------------------------------------------------------------ shallow water
@@ -64,18 +64,20 @@ template <typename T> struct Phys {
 template <typename T> struct SweV { T h, u, v; };
 
 // Numerical flux of two normal-frame shallow-water states.  The pressure
-// g h^2/2 is carried relative to the constant g h0^2/2: every flux below is
-// affine in (F_L, F_R) with weights summing to one (and equal to (F_L+F_R)/2
-// when both sides are dry), so the constant shifts all face fluxes equally
-// and cancels in every cell's divergence, while the rounding error of the
-// momentum flux scales with |h - h0| instead of h.
+// g h^2/2 is carried relative to the constant g c/2, c = h0^2 rounded to the
+// working precision: every flux below is affine in (F_L, F_R) with weights
+// summing to one (and equal to F_L when both sides are dry), so the constant
+// shifts all face fluxes equally and cancels in every cell's divergence,
+// while h^2 - c, formed as one fused multiply-add, carries a rounding error
+// that scales with |h^2 - h0^2| instead of h^2.
 template <typename T, int FLUX>
 __device__ __forceinline__ void swe_numflux(const SweV<T> &L, const SweV<T> &R, const Phys<T> &ph, T F[3])
 {
     const T hg = T(0.5) * ph.g;
+    const T c0 = ph.h0 * ph.h0;
     T ml = L.h * L.u, mr = R.h * R.u;
-    T fl[3] = {ml, ml * L.u + hg * (L.h - ph.h0) * (L.h + ph.h0), ml * L.v};
-    T fr[3] = {mr, mr * R.u + hg * (R.h - ph.h0) * (R.h + ph.h0), mr * R.v};
+    T fl[3] = {ml, ml * L.u + hg * (L.h * L.h - c0), ml * L.v};
+    T fr[3] = {mr, mr * R.u + hg * (R.h * R.h - c0), mr * R.v};
     T dq[3] = {R.h - L.h, mr - ml, R.h * R.v - L.h * L.v};
     T wl = fsqrt(L.h), wr = fsqrt(R.h);
     T cl = ph.sqg * wl, cr = ph.sqg * wr;
@@ -95,11 +97,13 @@ __device__ __forceinline__ void swe_numflux(const SweV<T> &L, const SweV<T> &R, 
         // is then never zero: where it would be (both sides dry, sL = sR = 0)
         // the formula returns F_L exactly, which equals (F_L + F_R)/2 there;
         // elsewhere the floor moves the flux by a relative 2^-60 at most.
+        // (sR F_L - sL F_R + sL sR dQ) / (sR - sL) = F_L + t (sR dQ - (F_R - F_L)),
+        // t = sL / (sR - sL)
         T sL = tmin(tmin(L.u - cl, ua - ca), T(0));
         T sR = tmax(tmax(R.u + cr, ua + ca), tiny<T>());
-        T id = rcp(sR - sL), ss = sL * sR;
+        T t = sL * rcp(sR - sL);
 #pragma unroll
-        for (int k = 0; k < 3; k++) F[k] = (sR * fl[k] - sL * fr[k] + ss * dq[k]) * id;
+        for (int k = 0; k < 3; k++) F[k] = fl[k] + t * (sR * dq[k] - (fr[k] - fl[k]));
         return;
     }
     // Roe: three waves u-c, u (shear), u+c
@@ -327,12 +331,13 @@ __device__ __forceinline__ void face_eval(const T (*st)[4], const Phys<T> &ph, T
     }
 }
 
-// Centred bed source of one cell along one axis (hydrostatic reconstruction):
-// -g (h_{i-1/2+} + h_{i+1/2-})/2 (z_{i+1/2-} - z_{i-1/2+}) / dx, from the
-// face state at the cell's low face (hL, zL) and at its high face (hR, zR).
-template <typename T> __device__ __forceinline__ T bed_centred(T hL, T zL, T hR, T zR, T g, T rdx)
+// Centred bed source of one cell along one axis (hydrostatic reconstruction),
+// times the cell width: -g (h_{i-1/2+} + h_{i+1/2-})/2 (z_{i+1/2-} - z_{i-1/2+}),
+// from the face state at the cell's low face (hL, zL) and at its high face
+// (hR, zR); it is added to the cell's flux difference along that axis.
+template <typename T> __device__ __forceinline__ T bed_term(T hL, T zL, T hR, T zR, T g)
 {
-    return -g * T(0.5) * (hL + hR) * (zR - zL) * rdx;
+    return -g * T(0.5) * (hL + hR) * (zR - zL);
 }
 
 }  // namespace fvk

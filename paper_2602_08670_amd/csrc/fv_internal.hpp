@@ -68,7 +68,7 @@ struct WorkItem {
     unsigned char ri, ro, rc, pad;
 };
 #ifndef FV_TILE_Y
-#define FV_TILE_Y 8
+#define FV_TILE_Y 32
 #endif
 constexpr int TILE_X = 64, TILE_Y = FV_TILE_Y;  // FP32 tile of the stage kernels
 // One workgroup per tile: grid = the list's tiles.  one != 0 declares that
@@ -81,7 +81,8 @@ hipError_t launch_batch_stage(int eqn, int bathy, int stage, const BatchSolve *s
 hipError_t launch_batch_stage_list(int eqn, int bathy, int stage, const BatchSolve *solves, const WorkItem *items,
                                    const int *list, int wgs, hipStream_t st);
 // Grid of a tiled launch: the tiles padded to a multiple of the 8 XCDs.
-inline int xcd_grid(int ntiles) { return (ntiles + 7) & ~7; }
+__host__ __device__ inline int xcd_grid(int ntiles) { return (ntiles + 7) & ~7; }
+
 
 // Reduce the CFL rate of q into ctl->rate[slot] and flag inadmissible cells.
 hipError_t launch_rate(const StageDesc &d, const void *q, Ctl *ctl, unsigned long long *rates, int slot,

@@ -1,6 +1,6 @@
 // Finite-volume stage kernels for gfx950 (MI355X).
 //
-// One workgroup of 256 threads (four wave64) owns a TX x TY tile of cells.
+// One workgroup of TY/2 wave64 (two tile rows per wave) owns a TX x TY tile of cells.
 //  1. The tile plus a two-cell halo of every variable (and eta = h + b with a
 //     bed) is staged into LDS with coalesced row loads; ghost cells are
 //     synthesised during the load (periodic wrap or wall mirror with the
@@ -166,12 +166,121 @@ __device__ __forceinline__ double from_right(double v, double edge)
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// One RK stage on the TX x TY tile at (x0, y0).  `tile_linear` is the tile's
-// index within its solve; the tile with index 0 does the per-step
-// bookkeeping of the solve.  Shared by the single-solve kernel and the
-// batched kernel, so a solve computes bit-identical results in both.
+// LDS of one stage tile: the halo tile of every variable (and eta), the
+// faces handed between waves, and the step's Delta t.
+template <typename T, int EQN, bool BATHY, int TX, int TY> struct StageLds {
+    static constexpr int RPW = 2;             // tile rows per wave
+    static constexpr int NW = TY / RPW;       // waves per workgroup
+    static constexpr int NTH = 64 * NW;       // threads per workgroup
+    static_assert(TY % RPW == 0 && NW >= 2 && NW <= 16, "whole rows per wave, 2..16 waves");
+    static constexpr int NV = EQN == SWE ? 3 : 4;
+    static constexpr int NL = NV + (BATHY ? 1 : 0);  // LDS planes: variables (+ eta)
+    static constexpr int NT = FaceSide<T, EQN, BATHY>::N;
+    static constexpr int HX = TX + 4, HY = TY + 4;
+    static constexpr int NIT = (HY * HX + NTH - 1) / NTH;  // halo elements per thread
+    T q[NL][HY][HX];
+    T edge[NT][TY];         // right face of column TX-1, handed to that cell
+    T low[NW - 1][NT][TX];  // low y face of wave w+1's first row, handed to wave w
+    double dt;
+};
+
+// Halo values of one inner tile held in registers between the issue of their
+// loads and their store to LDS.
+template <typename T, int EQN, bool BATHY, int TX, int TY> struct HaloRegs {
+    using L = StageLds<T, EQN, BATHY, TX, TY>;
+    T val[L::NIT][L::NL];
+};
+
+// A tile whose two-cell halo lies inside the grid (all but the border tiles)
+// loads without ghost synthesis.
+template <int TX, int TY> __device__ __forceinline__ bool inner_tile(int x0, int y0, int nx, int ny)
+{
+    return x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= nx && y0 + TY + 2 <= ny;
+}
+
+// Issue every halo load of an inner tile (no LDS access, no wait).  The last
+// pass re-reads the tile's first halo element on lanes past the end.
+template <typename T, int EQN, bool BATHY, int TX, int TY>
+__device__ __forceinline__ void halo_issue(const StageArgs<T> &a, const int x0, const int y0, const int tid,
+                                           HaloRegs<T, EQN, BATHY, TX, TY> &r)
+{
+    using L = StageLds<T, EQN, BATHY, TX, TY>;
+    const int nx = a.nx;
+    const size_t plane = (size_t)nx * a.ny;
+    const size_t hb = (size_t)y0 * nx + x0 - 2 * (size_t)nx - 2;
+#pragma unroll
+    for (int it = 0; it < L::NIT; it++) {
+        const int e = tid + it * L::NTH;
+        const int ec = e < L::HY * L::HX ? e : 0;
+        const int ly = ec / L::HX, lx = ec - ly * L::HX;
+        const unsigned off = (unsigned)(ly * nx + lx);
+#pragma unroll
+        for (int v = 0; v < L::NV; v++) r.val[it][v] = ld_off(a.qs + v * plane + hb, off);
+        if constexpr (BATHY) r.val[it][L::NV] = ld_off(a.bed + hb, off);
+    }
+}
+
+template <typename T, int EQN, bool BATHY, int TX, int TY>
+__device__ __forceinline__ void halo_commit(const HaloRegs<T, EQN, BATHY, TX, TY> &r,
+                                            StageLds<T, EQN, BATHY, TX, TY> &sh, const int tid)
+{
+    using L = StageLds<T, EQN, BATHY, TX, TY>;
+#pragma unroll
+    for (int it = 0; it < L::NIT; it++) {
+        const int e = tid + it * L::NTH;
+        if (e < L::HY * L::HX) {
+            const int ly = e / L::HX, lx = e - ly * L::HX;
+#pragma unroll
+            for (int v = 0; v < L::NV; v++) sh.q[v][ly][lx] = r.val[it][v];
+            if constexpr (BATHY) sh.q[L::NV][ly][lx] = r.val[it][0] + r.val[it][L::NV];
+        }
+    }
+}
+
+// Border tiles: ghost cells synthesised during the load (periodic wrap or
+// wall mirror with the normal momentum negated).
+template <typename T, int EQN, bool BATHY, int TX, int TY>
+__device__ __forceinline__ void halo_border(const StageArgs<T> &a, const int x0, const int y0, const int tid,
+                                            StageLds<T, EQN, BATHY, TX, TY> &sh)
+{
+    using L = StageLds<T, EQN, BATHY, TX, TY>;
+    const int nx = a.nx, ny = a.ny;
+    const size_t plane = (size_t)nx * ny;
+    for (int k = tid; k < L::HY * L::HX; k += L::NTH) {
+        int ly = k / L::HX, lx = k - ly * L::HX;
+        bool fx = false, fy = false;
+        int ix = map_index(x0 - 2 + lx, nx, a.bc_x, fx);
+        int iy = map_index(y0 - 2 + ly, ny, a.bc_y, fy);
+        size_t idx = (size_t)iy * nx + ix;
+        T val[L::NV];
+#pragma unroll
+        for (int v = 0; v < L::NV; v++) val[v] = gload(a.qs)[v * plane + idx];
+        const T b = BATHY ? gload(a.bed)[idx] : T(0);
+#pragma unroll
+        for (int v = 0; v < L::NV; v++) sh.q[v][ly][lx] = ((v == 1 && fx) || (v == 2 && fy)) ? -val[v] : val[v];
+        if constexpr (BATHY) sh.q[L::NV][ly][lx] = val[0] + b;
+    }
+}
+
+// Delta t of the step = CFL / (max over the previous step's rate sub-slots),
+// read by wave 1 into LDS.
+template <typename T, int EQN, bool BATHY, int TX, int TY>
+__device__ __forceinline__ void stage_dt(const StageArgs<T> &a, const int tid, StageLds<T, EQN, BATHY, TX, TY> &sh)
+{
+    if ((tid >> 6) == 1) {
+        const int lane = tid & 63;
+        const double d = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl / read_rate(a.rates, a.rate_in, lane);
+        if (lane == 0) sh.dt = d;
+    }
+}
+
+// One RK stage on the TX x TY tile at (x0, y0) whose halo, faces and Delta t
+// are staged in `sh` (after a barrier).  `tile_linear` is the tile's index
+// within its solve; the tile with index 0 does the per-step bookkeeping of
+// the solve.  Shared by every stage kernel, so a solve computes bit-identical
+// results in all of them.
 //
-// Work split: lane = column, wave w owns tile rows [w*RPW, (w+1)*RPW).  Each
+// Work split: lane = column, wave w owns tile rows [2w, 2w+1].  Each
 // lane evaluates the low x face and the low y face of each of its cells, so
 // face results stay in registers: the high x face arrives from lane + 1 by a
 // DPP shift, the high y face from the same lane's next row.  Faces with no
@@ -182,20 +291,17 @@ __device__ __forceinline__ double from_right(double v, double edge)
 // that per-lane index arithmetic is redone per tile instead of being held in
 // registers across the loop).
 template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int TX, int TY>
-__device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, const int y0, const int tile_linear,
-                                           const int tid)
+__device__ __forceinline__ void stage_compute(const StageArgs<T> &a, const int x0, const int y0,
+                                              const int tile_linear, const int tid,
+                                              StageLds<T, EQN, BATHY, TX, TY> &sh)
 {
     static_assert(TX == 64, "a tile row is one wave64");
-    static_assert(TY % 4 == 0 && TY <= 64, "four waves, whole rows each");
-    constexpr int NW = 4, RPW = TY / NW;
-    constexpr int NV = EQN == SWE ? 3 : 4;
-    constexpr int NL = NV + (BATHY ? 1 : 0);  // LDS planes: variables (+ eta)
-    constexpr int NT = FaceSide<T, EQN, BATHY>::N;
-    constexpr int HX = TX + 4, HY = TY + 4;
-    __shared__ T s_q[NL][HY][HX];
-    __shared__ T s_edge[NT][TY];         // right face of column TX-1, handed to that cell
-    __shared__ T s_low[NW - 1][NT][TX];  // low y face of wave w+1's first row, handed to wave w
-    __shared__ double s_dt;
+    using LD = StageLds<T, EQN, BATHY, TX, TY>;
+    constexpr int NW = LD::NW, RPW = LD::RPW;
+    constexpr int NV = LD::NV, NL = LD::NL, NT = LD::NT;
+    auto &s_q = sh.q;
+    auto &s_edge = sh.edge;
+    auto &s_low = sh.low;
 
     // An earlier step failed: the state is frozen.  The flag is checked only
     // where something would be written, so its load is off the critical path.
@@ -205,62 +311,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
     const int nx = a.nx, ny = a.ny;
     const size_t plane = (size_t)nx * ny;
     const size_t tbase = (size_t)y0 * nx + x0;
-
-    if (wave == 1) {
-        const double d = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl / read_rate(a.rates, a.rate_in, lane);
-        if (lane == 0) s_dt = d;
-    }
-
-    // 1. halo tile -> LDS with ghost synthesis.  Tiles whose halo lies inside
-    //    the grid (all but the border tiles) index directly.
-    const bool inner = x0 >= 2 && y0 >= 2 && x0 + TX + 2 <= nx && y0 + TY + 2 <= ny;
-    // every halo load is issued before the first LDS store, and before the
-    // q0 loads; the last pass re-reads the tile's first halo element on lanes
-    // past the end
-    constexpr int NIT = (HY * HX + 255) / 256;
-    T val[NIT][NL];
-    if (inner) {
-        const size_t hb = tbase - 2 * (size_t)nx - 2;
-#pragma unroll
-        for (int it = 0; it < NIT; it++) {
-            const int e = tid + it * 256;
-            const int ec = e < HY * HX ? e : 0;
-            const int ly = ec / HX, lx = ec - ly * HX;
-            const unsigned off = (unsigned)(ly * nx + lx);
-#pragma unroll
-            for (int v = 0; v < NV; v++) val[it][v] = ld_off(a.qs + v * plane + hb, off);
-            if (BATHY) val[it][NV] = ld_off(a.bed + hb, off);
-        }
-    }
-    if (inner) {
-#pragma unroll
-        for (int it = 0; it < NIT; it++) {
-            const int e = tid + it * 256;
-            if (e < HY * HX) {
-                const int ly = e / HX, lx = e - ly * HX;
-#pragma unroll
-                for (int v = 0; v < NV; v++) s_q[v][ly][lx] = val[it][v];
-                if (BATHY) s_q[NV][ly][lx] = val[it][0] + val[it][NV];
-            }
-        }
-    } else {
-        for (int k = tid; k < HY * HX; k += 256) {
-            int ly = k / HX, lx = k - ly * HX;
-            bool fx = false, fy = false;
-            int ix = map_index(x0 - 2 + lx, nx, a.bc_x, fx);
-            int iy = map_index(y0 - 2 + ly, ny, a.bc_y, fy);
-            size_t idx = (size_t)iy * nx + ix;
-            T val[NV];
-#pragma unroll
-            for (int v = 0; v < NV; v++) val[v] = gload(a.qs)[v * plane + idx];
-            const T b = BATHY ? gload(a.bed)[idx] : T(0);
-#pragma unroll
-            for (int v = 0; v < NV; v++) s_q[v][ly][lx] = ((v == 1 && fx) || (v == 2 && fy)) ? -val[v] : val[v];
-            if (BATHY) s_q[NV][ly][lx] = val[0] + b;
-        }
-    }
-    __syncthreads();
-    const T dt = (T)s_dt;
+    const T dt = (T)sh.dt;
+    // stage weight times Delta t over the cell width, per axis
+    const T cxs = a.a1 * dt * a.rdx, cys = a.a1 * dt * a.rdy;
 
     // 2. faces with no owner lane: the tile's right column and top row
     if (wave == 0 && lane < TY) {
@@ -302,16 +355,16 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
         if (j == RPW - 1) {
             if (wave == NW - 1) {
 #pragma unroll
-                for (int v = 0; v < NV; v++) Ly[j][v] = -(top[v] - tr[v]) * a.rdy;
-                if (BATHY) Ly[j][2] += bed_centred(tr[NV], tr[NV + 1], top[NV], top[NV + 1], a.ph.g, a.rdy);
+                for (int v = 0; v < NV; v++) Ly[j][v] = tr[v] - top[v];
+                if constexpr (BATHY) Ly[j][2] += bed_term(tr[NV], tr[NV + 1], top[NV], top[NV + 1], a.ph.g);
             } else {
 #pragma unroll
                 for (int k = 0; k < NT; k++) lowR[k] = tr[k];  // finished after the exchange
             }
         } else {
 #pragma unroll
-            for (int v = 0; v < NV; v++) Ly[j][v] = -(top[v] - tr[v]) * a.rdy;
-            if (BATHY) Ly[j][2] += bed_centred(tr[NV], tr[NV + 1], top[NV], top[NV + 1], a.ph.g, a.rdy);
+            for (int v = 0; v < NV; v++) Ly[j][v] = tr[v] - top[v];
+            if constexpr (BATHY) Ly[j][2] += bed_term(tr[NV], tr[NV + 1], top[NV], top[NV + 1], a.ph.g);
         }
         if (j == 0 && wave > 0) {
 #pragma unroll
@@ -326,8 +379,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
 #pragma unroll
         for (int k = 0; k < NT; k++) up[k] = s_low[wave][k][lane];
 #pragma unroll
-        for (int v = 0; v < NV; v++) Ly[RPW - 1][v] = -(up[v] - lowR[v]) * a.rdy;
-        if (BATHY) Ly[RPW - 1][2] += bed_centred(lowR[NV], lowR[NV + 1], up[NV], up[NV + 1], a.ph.g, a.rdy);
+        for (int v = 0; v < NV; v++) Ly[RPW - 1][v] = lowR[v] - up[v];
+        if constexpr (BATHY) Ly[RPW - 1][2] += bed_term(lowR[NV], lowR[NV + 1], up[NV], up[NV + 1], a.ph.g);
     }
 
     // q0 is needed only in the final combine: issued here, its latency hides
@@ -361,17 +414,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
         for (int k = 0; k < NT; k++) rt[k] = from_right(tl[k], s_edge[k][cy]);
         T Lv[NV];
 #pragma unroll
-        for (int v = 0; v < NV; v++) Lv[v] = -(rt[v] - tr[v]) * a.rdx;
-        if (BATHY) Lv[1] += bed_centred(tr[NV], tr[NV + 1], rt[NV], rt[NV + 1], a.ph.g, a.rdx);
-#pragma unroll
-        for (int v = 0; v < NV; v++) Lv[v] = Lv[v] + Ly[j][v];  // each axis complete, then summed
+        for (int v = 0; v < NV; v++) Lv[v] = tr[v] - rt[v];
+        if constexpr (BATHY) Lv[1] += bed_term(tr[NV], tr[NV + 1], rt[NV], rt[NV + 1], a.ph.g);
         const bool in = x0 + lane < nx && y0 + cy < ny && !frozen;
         if (in) {
             const unsigned off = (unsigned)(cy * nx + lane);
             T qn[NV];
 #pragma unroll
             for (int v = 0; v < NV; v++) {
-                T o = a.a1 * (st[v][2] + dt * Lv[v]);
+                // out = a0 q0 + a1 (q + dt L), L = (x flux difference) / dx + (y flux difference) / dy;
+                // the increment is summed first, so the result is rounded
+                // twice at its own magnitude (once per added state)
+                const T inc = cxs * Lv[v] + cys * Ly[j][v];
+                T o = a.a1 * st[v][2] + inc;
                 if (a.a0 != T(0)) o = a.a0 * q0r[j][v] + o;
                 __builtin_nontemporal_store(o, st_off(a.out + v * plane + tbase, off));
                 qn[v] = o;
@@ -392,11 +447,30 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
     }
     if (tile_linear == 0) {
         if (tid == 0) {
-            a.ctl->t += (double)s_dt;
+            a.ctl->t += sh.dt;
             a.ctl->step += 1;
         }
         if (a.rate_clear >= 0 && tid < RATE_SUB) *rate_slot(a.rates, a.rate_clear, tid) = 0ull;
     }
+}
+
+// One RK stage on one tile, loaded and computed by the calling workgroup.
+template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int TX, int TY>
+__device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, const int y0, const int tile_linear,
+                                           const int tid)
+{
+    __shared__ StageLds<T, EQN, BATHY, TX, TY> sh;
+    stage_dt(a, tid, sh);
+    if (inner_tile<TX, TY>(x0, y0, a.nx, a.ny)) {
+        // every halo load is issued before the first LDS store
+        HaloRegs<T, EQN, BATHY, TX, TY> r;
+        halo_issue(a, x0, y0, tid, r);
+        halo_commit(r, sh, tid);
+    } else {
+        halo_border(a, x0, y0, tid, sh);
+    }
+    __syncthreads();
+    stage_compute<T, EQN, BATHY, FLUX, RECON, TX, TY>(a, x0, y0, tile_linear, tid, sh);
 }
 
 // Workgroups are handed to the eight XCDs in turn (workgroup w runs on XCD
@@ -409,7 +483,8 @@ __device__ __forceinline__ int xcd_tile(int w, int grid)
 }
 
 template <typename T, int EQN, bool BATHY, int FLUX, int RECON, int TX, int TY>
-__global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a, int tiles_x, int ntiles)
+__global__ __launch_bounds__((StageLds<T, EQN, BATHY, TX, TY>::NTH)) void stage_kernel(StageArgs<T> a, int tiles_x,
+                                                                                   int ntiles)
 {
     const int tile = xcd_tile(blockIdx.x, gridDim.x);
     if (tile >= ntiles) return;
@@ -418,12 +493,17 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs<T> a, int tiles_x,
 }
 
 // Batched stage over many solves: the step's list holds one item per solve
-// (sorted by tile_begin); the workgroup handling tile w binary-searches the
-// solve whose tile range contains w.  STAGE 1: S1 = q + dt L(q); STAGE 2:
+// (sorted by tile_begin); tile w of the launch belongs to the solve whose tile
+// range contains it (binary search).  STAGE 1: S1 = q + dt L(q); STAGE 2:
 // q = q/2 + (S1 + dt L(S1))/2 (Heun).
-template <typename T, int EQN, bool BATHY, int STAGE>
-__device__ __forceinline__ void batch_tile(const BatchSolve *__restrict__ solves, const WorkItem *__restrict__ items,
-                                           const int *__restrict__ nitems, const int w, const int one, const int tid)
+struct TileRef {
+    int x0, y0, tile;
+};
+
+template <typename T, int STAGE>
+__device__ __forceinline__ TileRef batch_resolve(const BatchSolve *__restrict__ solves,
+                                                 const WorkItem *__restrict__ items, const int *__restrict__ nitems,
+                                                 const int w, const int one, StageArgs<T> &a)
 {
     constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;
     // one != 0: the list is known to hold one solve, solves[0] (a single
@@ -447,7 +527,6 @@ __device__ __forceinline__ void batch_tile(const BatchSolve *__restrict__ solves
     }
     const int tile = w - it.tile_begin;
     const BatchSolve &d = *dp;
-    StageArgs<T> a;
     a.qs = (const T *)(STAGE == 1 ? d.q : d.s1);
     a.q0 = (const T *)d.q;
     a.out = (T *)(STAGE == 1 ? d.s1 : d.q);
@@ -473,24 +552,26 @@ __device__ __forceinline__ void batch_tile(const BatchSolve *__restrict__ solves
     a.rate_clear = STAGE == 1 ? -1 : it.rc;
     a.last = STAGE == 2;
     const int ty = tile / it.tiles_x, tx = tile - ty * it.tiles_x;
-    stage_tile<T, EQN, BATHY, HLLE, MINMOD, TX, TY>(a, tx * TX, ty * TY, tile, tid);
+    return TileRef{tx * TX, ty * TY, tile};
 }
 
-// ntiles > 0: the list holds ntiles tiles.  ntiles == 0: the tile count is
-// read from the list header (nitems[1]), so that a launch recorded in a graph
-// serves whatever list is uploaded before each replay.  The grid is
-// xcd_grid(tiles).  Eight waves per SIMD (at most 64 VGPRs): every tile of a
-// 1024^2 grid is then resident at once instead of the last eighth running as
-// a second round.
+// One workgroup per tile.  ntiles > 0: the list holds ntiles tiles.
+// ntiles == 0: the tile count is read from the list header (nitems[1]), so
+// that a launch recorded in a graph serves whatever list is uploaded before
+// each replay.  The grid is xcd_grid(tiles).  Eight waves per SIMD (at most
+// 64 VGPRs): every tile of a 1024^2 grid is then resident at once.
 template <typename T, int EQN, bool BATHY, int STAGE>
-__global__ __launch_bounds__(256, 8) void batch_stage_kernel(const BatchSolve *__restrict__ solves,
-                                                          const WorkItem *__restrict__ items,
-                                                          const int *__restrict__ nitems, int ntiles, int one)
+__global__ __launch_bounds__((StageLds<T, EQN, BATHY, Tile<T>::X, Tile<T>::Y>::NTH), 8) void batch_stage_kernel(
+    const BatchSolve *__restrict__ solves, const WorkItem *__restrict__ items, const int *__restrict__ nitems,
+    int ntiles, int one)
 {
+    constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;
     const int total = ntiles > 0 ? ntiles : nitems[1];
     const int w = xcd_tile(blockIdx.x, gridDim.x);
     if (w >= total) return;
-    batch_tile<T, EQN, BATHY, STAGE>(solves, items, nitems, w, one, threadIdx.x);
+    StageArgs<T> a;
+    const TileRef t = batch_resolve<T, STAGE>(solves, items, nitems, w, one, a);
+    stage_tile<T, EQN, BATHY, HLLE, MINMOD, TX, TY>(a, t.x0, t.y0, t.tile, threadIdx.x);
 }
 
 // ------------------------------------------------------------ CFL rate of q
@@ -640,7 +721,8 @@ static hipError_t stage_t(const StageDesc &d, const void *qs, const void *q0, vo
     a.last = last;
     constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;
     const int tiles_x = (d.nx + TX - 1) / TX, ntiles = tiles_x * ((d.ny + TY - 1) / TY);
-    hipLaunchKernelGGL((stage_kernel<T, EQN, BATHY, FLUX, RECON, TX, TY>), dim3(xcd_grid(ntiles)), dim3(256), 0, st, a,
+    constexpr int NTH = StageLds<T, EQN, BATHY, TX, TY>::NTH;
+    hipLaunchKernelGGL((stage_kernel<T, EQN, BATHY, FLUX, RECON, TX, TY>), dim3(xcd_grid(ntiles)), dim3(NTH), 0, st, a,
                        tiles_x, ntiles);
     return hipGetLastError();
 }
@@ -707,13 +789,16 @@ template <int STAGE>
 static void batch_stage_go(int eqn, int bathy, dim3 g, const BatchSolve *solves, const WorkItem *items,
                            const int *nitems, int ntiles, int one, hipStream_t st)
 {
-    const dim3 b(256);
+    constexpr int TX = Tile<float>::X, TY = Tile<float>::Y;
     if (eqn == EULER)
-        hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, STAGE>), g, b, 0, st, solves, items, nitems, ntiles, one);
+        hipLaunchKernelGGL((batch_stage_kernel<float, EULER, false, STAGE>), g,
+                           dim3(StageLds<float, EULER, false, TX, TY>::NTH), 0, st, solves, items, nitems, ntiles, one);
     else if (bathy)
-        hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, STAGE>), g, b, 0, st, solves, items, nitems, ntiles, one);
+        hipLaunchKernelGGL((batch_stage_kernel<float, SWE, true, STAGE>), g,
+                           dim3(StageLds<float, SWE, true, TX, TY>::NTH), 0, st, solves, items, nitems, ntiles, one);
     else
-        hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, STAGE>), g, b, 0, st, solves, items, nitems, ntiles, one);
+        hipLaunchKernelGGL((batch_stage_kernel<float, SWE, false, STAGE>), g,
+                           dim3(StageLds<float, SWE, false, TX, TY>::NTH), 0, st, solves, items, nitems, ntiles, one);
 }
 
 hipError_t launch_batch_stage(int eqn, int bathy, int stage, const BatchSolve *solves, const WorkItem *items,
