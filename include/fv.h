@@ -74,9 +74,9 @@ typedef struct {
     double g;             /* gravity (SWE), > 0 */
     double gamma;         /* ratio of specific heats (Euler), > 1 */
     double h_ref;         /* SWE: reference depth h0 of the pressure term, carried as
-                             g (h - h0)(h + h0)/2 (a constant shift of every face flux that
+                             g (h^2 - h0^2)/2 (a constant shift of every face flux that
                              cancels in each cell's divergence and keeps float rounding
-                             proportional to |h - h0|); 0 = mean depth of the initial state */
+                             proportional to |h^2 - h0^2|); 0 = mean depth of the initial state */
 } fv_config;
 
 typedef struct fv_solver fv_solver;
@@ -147,6 +147,49 @@ fv_status fv_face_fluxes(fv_solver *s, void *fx, void *fy);
 
 /* Release the handle (not the caller's buffers).  Waits for queued work. */
 void fv_destroy(fv_solver *s);
+
+/* ------------------------------------------------------------------------
+ * Allocation-free stepping, for callers that cannot allocate device memory:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  fv_run_noalloc does what fv_init + fv_run + fv_time do, with the
+ * same kernels and bit-identical results, but takes its workspace (control
+ * block, CFL rate slots, stage buffers, descriptor) from a device array the
+ * library holds: FV_NOALLOC_SCRATCH_BYTES per GPU, reserved when the library
+ * is loaded and kept until the process ends.  It calls no allocating routine,
+ * no memset and no host synchronisation: everything is enqueued on `stream`.
+ *
+ *   cfg      as for fv_init, with learned = 0; for SWE, h_ref > 0 is required
+ *            (the mean-depth default would need a reduction and a host read);
+ *   q        device state, updated in place by nsteps full steps;
+ *   bathy    device bed or NULL (SWE only);
+ *   nsteps   >= 0;
+ *   stream   hipStream_t as void*;
+ *   info_dev NULL, or a device fv_run_info that receives the simulated time,
+ *            the completed steps and the inadmissible flag when the steps end.
+ * Errors: FV_E_INVALID (bad configuration or arguments), FV_E_UNSUPPORTED
+ * (learned = 0 required), FV_E_NOMEM (the configuration needs more than
+ * FV_NOALLOC_SCRATCH_BYTES: see fv_noalloc_bytes), FV_E_HIP.  An initial
+ * state that is not admissible is reported through info_dev->inadmissible
+ * (the state is then left unchanged), not by the return code.
+ * Every call on one GPU uses the same array and leaves its contents behind;
+ * each call resets what must start at zero.  Calls that overlap on one GPU
+ * (concurrent host threads, or streams that run at the same time) race on
+ * the array and must not be issued. */
+#define FV_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+typedef struct {
+    double t;             /* simulated time */
+    int64_t steps;        /* completed steps */
+    int32_t inadmissible; /* 1: a cell became inadmissible (h <= 0, rho <= 0, p <= 0 or non-finite) */
+    int32_t reserved;
+} fv_run_info;
+
+/* Scratch bytes fv_run_noalloc needs for cfg (fv_workspace_bytes of the
+ * classic scheme); 0 if cfg is invalid. */
+size_t fv_noalloc_bytes(const fv_config *cfg);
+
+fv_status fv_run_noalloc(const fv_config *cfg, void *q, const void *bathy, int64_t nsteps, void *stream,
+                         fv_run_info *info_dev);
 
 /* ------------------------------------------------------------------------
  * Learned stencil coefficients (thesis section 2.5.3, fourth approach:

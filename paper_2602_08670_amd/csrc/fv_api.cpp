@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "api_common.hpp"
@@ -252,10 +253,10 @@ fv_status upload_lbatch(fv_solver *s)
 }
 
 // Descriptor and step lists of the batch-of-one path (see runs_batched).
-fv_status upload_batch(fv_solver *s)
+static_assert(sizeof(fvk::DescBlock) == BATCH_BYTES, "descriptor block size");
+void batch_block(fv_solver *s, char *buf)
 {
-    alignas(16) char buf[BATCH_BYTES];
-    std::memset(buf, 0, sizeof buf);
+    std::memset(buf, 0, BATCH_BYTES);
     fvk::BatchSolve d{};
     d.q = s->q;
     d.s1 = s->ws + s->L.s1;
@@ -287,10 +288,49 @@ fv_status upload_batch(fv_solver *s)
     }
     const int one = 1;
     std::memcpy(buf + BATCH_N, &one, sizeof one);
+}
+
+fv_status upload_batch(fv_solver *s)
+{
+    alignas(16) char buf[BATCH_BYTES];
+    batch_block(s, buf);
     hipError_t e = hipMemcpyAsync(s->ws + s->L.batch, buf, sizeof buf, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // buf is on this stack frame
     if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
     return FV_OK;
+}
+
+// The solver fields fv_init and fv_run_noalloc share (h0 is set by the caller).
+void setup_solver(fv_solver *s, const fv_config *cfg, void *q, const void *bathy, char *ws, const Layout &L,
+                  hipStream_t stream)
+{
+    s->cfg = *cfg;
+    s->q = q;
+    s->bed = bathy;
+    s->ws = ws;
+    s->L = L;
+    s->stream = stream;
+    s->enq = 0;
+    s->lsteps = 0;
+    s->state_bytes = (size_t)nvar_of(cfg) * cfg->nx * cfg->ny * (cfg->prec == FV_F64 ? 8 : 4);
+    fvk::StageDesc &d = s->d;
+    d.prec = cfg->prec;
+    d.eqn = cfg->eqn;
+    d.bathy = bathy ? 1 : 0;
+    d.flux = cfg->flux;
+    d.recon = cfg->recon;
+    d.nx = cfg->nx;
+    d.ny = cfg->ny;
+    d.bc_x = cfg->bc_x;
+    d.bc_y = cfg->bc_y;
+    d.rdx = cfg->nx / cfg->lx;
+    d.rdy = cfg->ny / cfg->ly;
+    d.g = cfg->g;
+    d.gamma = cfg->gamma;
+    d.cfl = cfg->cfl;
+    d.dt_fixed = cfg->dt_fixed;
+    d.h0 = 0.0;
+    s->batched = runs_batched(cfg);
 }
 
 }  // namespace
@@ -320,31 +360,7 @@ fv_status fv_init(const fv_config *cfg, void *q, const void *bathy, void *worksp
         return fail(FV_E_NOMEM, "workspace %zu bytes < required %zu", workspace_bytes, L.total);
 
     fv_solver *s = new fv_solver();
-    s->cfg = *cfg;
-    s->q = q;
-    s->bed = bathy;
-    s->ws = (char *)workspace;
-    s->L = L;
-    s->stream = (hipStream_t)stream;
-    s->enq = 0;
-    s->state_bytes = (size_t)nvar_of(cfg) * cfg->nx * cfg->ny * (cfg->prec == FV_F64 ? 8 : 4);
-    fvk::StageDesc &d = s->d;
-    d.prec = cfg->prec;
-    d.eqn = cfg->eqn;
-    d.bathy = bathy ? 1 : 0;
-    d.flux = cfg->flux;
-    d.recon = cfg->recon;
-    d.nx = cfg->nx;
-    d.ny = cfg->ny;
-    d.bc_x = cfg->bc_x;
-    d.bc_y = cfg->bc_y;
-    d.rdx = cfg->nx / cfg->lx;
-    d.rdy = cfg->ny / cfg->ly;
-    d.g = cfg->g;
-    d.gamma = cfg->gamma;
-    d.cfl = cfg->cfl;
-    d.dt_fixed = cfg->dt_fixed;
-    d.h0 = 0.0;
+    setup_solver(s, cfg, q, bathy, (char *)workspace, L, (hipStream_t)stream);
 
     fvk::Ctl fresh;
     std::memset(&fresh, 0, sizeof fresh);
@@ -375,7 +391,6 @@ fv_status fv_init(const fv_config *cfg, void *q, const void *bathy, void *worksp
         rc = fv_totals(s, tot);
         if (rc == FV_OK) s->d.h0 = tot[0] / (cfg->lx * cfg->ly);
     }
-    s->batched = runs_batched(cfg);
     if (rc == FV_OK && s->batched) rc = upload_batch(s);
     if (rc == FV_OK && cfg->learned) rc = upload_lbatch(s);
     if (rc != FV_OK) {
@@ -481,6 +496,98 @@ fv_status fv_face_fluxes(fv_solver *s, void *fx, void *fy)
     if (e != hipSuccess) return hip_fail(e, "face kernel");
     e = hipStreamSynchronize(s->stream);
     if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return FV_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------- allocation-free stepping
+//
+// fv_run_noalloc runs the kernels of fv_init + fv_run on a device array the
+// library holds, `scratch`, instead of a caller workspace.  Host code never
+// passes the array's name to a kernel or copy (in host code it is only a
+// stand-in for the device symbol): each device's address comes from
+// hipGetSymbolAddress on that device's first call and is kept per device.
+namespace {
+
+constexpr size_t NOALLOC_BYTES = (size_t)64 << 20;
+static_assert(NOALLOC_BYTES == FV_NOALLOC_SCRATCH_BYTES, "scratch size in the header");
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[NOALLOC_BYTES];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[NOALLOC_MAX_DEVICES];
+
+fv_status scratch_on_current_device(void **out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(FV_E_UNSUPPORTED, "device %d beyond %d", dev, NOALLOC_MAX_DEVICES);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!p || ((uintptr_t)p & 255) != 0) return fail(FV_E_HIP, "scratch address %p not 256-byte aligned", p);
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FV_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t fv_noalloc_bytes(const fv_config *cfg)
+{
+    if (validate(cfg) != FV_OK) return 0;
+    return layout_of(cfg).total;
+}
+
+fv_status fv_run_noalloc(const fv_config *cfg, void *q, const void *bathy, int64_t nsteps, void *stream,
+                         fv_run_info *info_dev)
+{
+    fv_status rc = validate(cfg);
+    if (rc != FV_OK) return rc;
+    if (!q) return fail(FV_E_INVALID, "state is NULL");
+    if (nsteps < 0) return fail(FV_E_INVALID, "nsteps %lld < 0", (long long)nsteps);
+    if (bathy && cfg->eqn != FV_SWE) return fail(FV_E_INVALID, "a bed is only defined for the shallow-water equations");
+    if (cfg->learned) return fail(FV_E_UNSUPPORTED, "the allocation-free path runs the classic scheme only (learned = 0)");
+    if (cfg->eqn == FV_SWE && !(cfg->h_ref > 0))
+        return fail(FV_E_INVALID, "the allocation-free path needs h_ref > 0 for shallow water (no reduction of the initial depth)");
+    const Layout L = layout_of(cfg);
+    if (L.total > NOALLOC_BYTES)
+        return fail(FV_E_NOMEM, "this configuration needs %zu bytes of scratch; the allocation-free path holds %zu",
+                    L.total, NOALLOC_BYTES);
+    void *ws = nullptr;
+    rc = scratch_on_current_device(&ws);
+    if (rc != FV_OK) return rc;
+
+    fv_solver s;
+    setup_solver(&s, cfg, q, bathy, (char *)ws, L, (hipStream_t)stream);
+    s.d.h0 = cfg->eqn == FV_SWE ? cfg->h_ref : 0.0;
+    fvk::DescBlock blk;
+    std::memset(&blk, 0, sizeof blk);
+    if (s.batched) batch_block(&s, (char *)blk.b);
+    hipError_t e = fvk::launch_reset(s.ctl(), s.rates(), s.ws + L.batch, blk, s.batched ? (int)BATCH_BYTES : 0,
+                                     s.stream);
+    if (e == hipSuccess) e = fvk::launch_rate(s.d, s.q, s.ctl(), s.rates(), 0, s.stream);
+    if (e != hipSuccess) return hip_fail(e, "reset and rate kernels");
+    for (int64_t k = 0; k < nsteps; k++) {
+        rc = enqueue_step(&s);
+        if (rc != FV_OK) return rc;
+    }
+    if (info_dev) {
+        e = fvk::launch_report(s.ctl(), info_dev, s.stream);
+        if (e != hipSuccess) return hip_fail(e, "report kernel");
+    }
     return FV_OK;
 }
 

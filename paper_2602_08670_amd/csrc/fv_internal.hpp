@@ -97,4 +97,17 @@ hipError_t launch_face_fluxes(const StageDesc &d, const void *q, void *fx, void 
 
 constexpr int TOTALS_MAX_BLOCKS = 1024;
 
+// A solve's descriptor block for the batch-of-one path, passed by value.
+struct DescBlock {
+    alignas(16) unsigned char b[512];
+};
+// Reset a solve's control block and CFL rate slots on the device (a kernel:
+// nothing host-side, no memset node), and copy `len` bytes of blk to dst
+// (len 0: none).
+hipError_t launch_reset(Ctl *ctl, unsigned long long *rates, void *dst, const DescBlock &blk, int len,
+                        hipStream_t st);
+// Copy a solve's simulated time, completed steps and inadmissible flag into
+// the caller's device record {double t; int64 steps; int32 bad; int32 pad}.
+hipError_t launch_report(const Ctl *ctl, void *info, hipStream_t st);
+
 }  // namespace fvk

@@ -647,6 +647,47 @@ __global__ __launch_bounds__(256) void totals_final_kernel(const double *partial
     if (threadIdx.x == 0) out[o] = s[0];
 }
 
+// ------------------------------------------------------- solve reset/report
+__global__ __launch_bounds__(256) void reset_kernel(Ctl *ctl, unsigned long long *rates, unsigned char *dst,
+                                                    DescBlock blk, int len)
+{
+    const int t = threadIdx.x;
+    for (int k = t; k < (int)(RATE_BYTES / sizeof(unsigned long long)); k += 256) rates[k] = 0ull;
+    if (t < (int)(sizeof(Ctl) / sizeof(unsigned long long))) ((unsigned long long *)ctl)[t] = 0ull;
+    for (int k = t; k < len; k += 256) dst[k] = blk.b[k];
+}
+
+struct RunInfo {
+    double t;
+    long long steps;
+    int bad;
+    int pad;
+};
+
+__global__ void report_kernel(const Ctl *ctl, RunInfo *info)
+{
+    if (threadIdx.x == 0) {
+        info->t = ctl->t;
+        info->steps = ctl->step;
+        info->bad = ctl->bad;
+        info->pad = 0;
+    }
+}
+
+hipError_t launch_reset(Ctl *ctl, unsigned long long *rates, void *dst, const DescBlock &blk, int len,
+                        hipStream_t st)
+{
+    if (len < 0 || len > (int)sizeof(blk.b)) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, st, ctl, rates, (unsigned char *)dst, blk, len);
+    return hipGetLastError();
+}
+
+hipError_t launch_report(const Ctl *ctl, void *info, hipStream_t st)
+{
+    hipLaunchKernelGGL(report_kernel, dim3(1), dim3(64), 0, st, ctl, (RunInfo *)info);
+    return hipGetLastError();
+}
+
 // --------------------------------------------------------------- face export
 template <typename T, int EQN, int FLUX, int RECON>
 __global__ void face_kernel(const T *q, int nx, int ny, int bc_x, int bc_y, Phys<T> ph, T *fx, T *fy)

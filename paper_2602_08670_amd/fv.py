@@ -45,6 +45,11 @@ def make_config(eqn=FV_SWE, prec=FV_F32, nx=64, ny=64, bc_x=FV_BC_PERIODIC, bc_y
                      lx, ly, cfl, dt_fixed, g, gamma, h_ref)
 
 
+class fv_run_info(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("steps", ctypes.c_int64), ("inadmissible", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 class fv_model_desc(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("hidden", ctypes.c_int32), ("order", ctypes.c_int32),
                 ("reserved0", ctypes.c_int32), ("mean", ctypes.c_float * 3), ("inv_std", ctypes.c_float * 3)]
@@ -129,6 +134,8 @@ def _load():
         "fv_set_stream": ([vp, vp], st),
         "fv_face_fluxes": ([vp, vp, vp], st),
         "fv_destroy": ([vp], None),
+        "fv_noalloc_bytes": ([cp], ctypes.c_size_t),
+        "fv_run_noalloc": ([cp, vp, vp, i64, vp, vp], st),
         "fv_model_param_count": ([], ctypes.c_size_t),
         "fv_model_workspace_bytes": ([ctypes.POINTER(fv_model_desc)], ctypes.c_size_t),
         "fv_model_create": ([ctypes.POINTER(fv_model_desc), vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], st),
@@ -243,6 +250,18 @@ def fv_face_fluxes(h, fx_ptr: int, fy_ptr: int):
 
 def fv_destroy(h):
     lib.fv_destroy(h)
+
+
+def fv_noalloc_bytes(cfg: fv_config) -> int:
+    return lib.fv_noalloc_bytes(ctypes.byref(cfg))
+
+
+def fv_run_noalloc(cfg: fv_config, q_ptr: int, bathy_ptr: int | None, nsteps: int, stream: int = 0,
+                   info_ptr: int | None = None):
+    _check(lib.fv_run_noalloc(ctypes.byref(cfg), q_ptr, bathy_ptr, nsteps, stream, info_ptr))
+
+
+FV_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def fv_last_error() -> str:

@@ -77,3 +77,25 @@ def test_server_config_validation_and_activation_scratch(fv):
     assert overhead(act_pixels=(1 << 34) + 1) == 0
     assert overhead(learned_split=-1) == 0
     assert overhead(direct=2) == 0
+
+
+def test_noalloc_host_checks(fv):
+    """The allocation-free entry point rejects, before touching a device: a
+    configuration beyond its scratch (with the size it would need), learned
+    configurations, shallow water without h_ref, and negative step counts."""
+    ok = fv.make_config(nx=1024, ny=1024, h_ref=1.0)
+    need = fv.fv_noalloc_bytes(ok)
+    assert 12 * 1024 * 1024 < need < fv.FV_NOALLOC_SCRATCH_BYTES
+    assert need == fv.fv_workspace_bytes(ok)
+    fake = 256  # never dereferenced: every case fails in the host checks
+    big = fv.make_config(eqn=fv.FV_EULER, nx=4096, ny=4096)
+    assert fv.fv_noalloc_bytes(big) > fv.FV_NOALLOC_SCRATCH_BYTES
+    for cfg, steps, code in ((big, 1, fv.FV_E_NOMEM), (fv.make_config(h_ref=1.0, learned=1), 1, fv.FV_E_UNSUPPORTED),
+                             (fv.make_config(h_ref=0.0), 1, fv.FV_E_INVALID), (ok, -1, fv.FV_E_INVALID),
+                             (fv.make_config(nx=2), 1, fv.FV_E_INVALID)):
+        with pytest.raises(fv.FvError) as e:
+            fv.fv_run_noalloc(cfg, fake, None, steps)
+        assert e.value.code == code, (e.value, code)
+    with pytest.raises(fv.FvError) as e:
+        fv.fv_run_noalloc(big, fake, None, 1)
+    assert "scratch" in str(e.value) and str(fv.fv_noalloc_bytes(big)) in str(e.value)
