@@ -40,7 +40,12 @@ BYTES_PER_CELL_UPDATE = {"swe_bathy": 28, "euler": 32}  # read q (+b), write q, 
 # operations: 114 per face and two faces per cell per stage, plus divergence,
 # bed source and stage combine: 261 for stage 1, 270 for stage 2, and 12 for
 # the CFL rate of the new state.
-FLOP_PER_CELL_UPDATE = {"swe_bathy": 543}
+FLOP_PER_CELL_UPDATE = {"swe_bathy": 543, "euler": 715}
+# Euler (HLLE, MINMOD on rho, rho u, rho v, E, Heun), counted the same way:
+# per face 158 (reconstruction of 4 variables 36, pressure positivity checks
+# of the two face states 18, HLLE with Roe-averaged speeds and enthalpy 104),
+# two faces per cell and stage plus divergence and combine: 344 for stage 1,
+# 356 for stage 2, and 15 for the CFL rate of the new state.
 # FP32 vector peak without packed math: 256 CUs x 64 lanes x 2 (FMA) x 2.4 GHz.
 ALU_PEAK_TFLOPS = 256 * 64 * 2 * 2.4e9 / 1e12
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_stage_kernel_swe_bathy_1024_fp32.json")
@@ -144,13 +149,21 @@ def learned_sample(steps, torch, direct=False, blend=False):
     return round(us, 2)
 
 
-def cpu_baseline(n, target_s):
+def cpu_baseline(n, target_s, euler=False):
+    """The oracle on the host cores over a bounded number of steps of the same
+    workload (shallow water over the bed, or the Euler quadrants)."""
     import oracle
     from paper_2602_08670_amd import inputs
 
     threads = min(16, os.cpu_count() or 1)
-    q0, b = inputs.swe_bathy(n, seed=0)
-    cfg = oracle.Config(nx=n, ny=n, bc_x=oracle.WALL, bc_y=oracle.WALL, nthreads=threads)
+    if euler:
+        q0, b = inputs.euler_quadrants(n, seed=0), None
+        cfg = oracle.Config(eqn=oracle.EULER, nx=n, ny=n, bc_x=oracle.WALL, bc_y=oracle.WALL, nthreads=threads)
+        what = "Euler four-quadrant"
+    else:
+        q0, b = inputs.swe_bathy(n, seed=0)
+        cfg = oracle.Config(nx=n, ny=n, bc_x=oracle.WALL, bc_y=oracle.WALL, nthreads=threads)
+        what = "shallow-water bed"
     t0 = time.perf_counter()
     q1, *_ = oracle.run(cfg, q0, b, 1)
     one = time.perf_counter() - t0
@@ -160,7 +173,7 @@ def cpu_baseline(n, target_s):
     el = time.perf_counter() - t0
     return {"value": round(n * n * steps / el / 1e6, 3), "unit": "Mcell-updates/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{steps} steps of the {n}^2 FP64 shallow-water bed workload (after 1 untimed step), "
+            "sample": f"{steps} steps of the {n}^2 FP64 {what} workload (after 1 untimed step), "
                       f"{el:.1f} s, OpenMP rows"}
 
 
@@ -205,8 +218,17 @@ def main():
         esteps = max(1, args.steps // 2)
         eg, _ = timed_run(se, esteps, max(1, args.warmup // 2), torch)
         se.close()
-        extra["euler_1024_fp32_mcups"] = round(n * n * esteps / eg / 1e6, 1)
-        extra["euler_hbm_frac"] = round(BYTES_PER_CELL_UPDATE["euler"] * n * n * esteps / eg / 1e9 / HBM_PEAK_GBS, 4)
+        e_launch = eg / (2 * esteps)
+        e_ach = FLOP_PER_CELL_UPDATE["euler"] * n * n / 2 / e_launch / 1e12
+        e_hbm = BYTES_PER_CELL_UPDATE["euler"] * n * n / 2 / e_launch / 1e9
+        extra["euler"] = {
+            "workload": f"euler_quadrants_{n}x{n}_fp32_walls_hlle_minmod_heun_cfl0.4", "steps": esteps,
+            "value": round(n * n * esteps / eg / 1e6, 1), "unit": "Mcell-updates/s",
+            "roofline": {"bound": "alu", "achieved": round(e_ach, 2), "peak": round(ALU_PEAK_TFLOPS, 1),
+                         "unit": "TFLOP/s", "frac": round(e_ach / ALU_PEAK_TFLOPS, 4), "traffic": None},
+            "hbm_gbs_algorithmic": round(e_hbm, 1), "hbm_frac": round(e_hbm / HBM_PEAK_GBS, 4)}
+        if not args.no_cpu_baseline:
+            extra["euler"]["cpu_baseline"] = cpu_baseline(n, args.cpu_seconds / 3, euler=True)
 
     if args.learned_steps > 0:
         extra["learned_64_step_us"] = learned_sample(args.learned_steps, torch)

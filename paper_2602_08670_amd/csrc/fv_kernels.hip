@@ -178,7 +178,11 @@ template <typename T, int EQN, bool BATHY, int TX, int TY> struct StageLds {
     static constexpr int NT = FaceSide<T, EQN, BATHY>::N;
     static constexpr int HX = TX + 4, HY = TY + 4;
     static constexpr int NIT = (HY * HX + NTH - 1) / NTH;  // halo elements per thread
-    T q[NL][HY][HX];
+    // rows past HY pad each plane to NIT * NTH elements: the last pass of the
+    // halo staging then stores unconditionally (its extra lanes write padding),
+    // so every halo load is issued before the first store
+    static constexpr int HYP = (NIT * NTH + HX - 1) / HX;
+    T q[NL][HYP][HX];
     T edge[NT][TY];         // right face of column TX-1, handed to that cell
     T low[NW - 1][NT][TX];  // low y face of wave w+1's first row, handed to wave w
     double dt;
@@ -228,12 +232,10 @@ __device__ __forceinline__ void halo_commit(const HaloRegs<T, EQN, BATHY, TX, TY
 #pragma unroll
     for (int it = 0; it < L::NIT; it++) {
         const int e = tid + it * L::NTH;
-        if (e < L::HY * L::HX) {
-            const int ly = e / L::HX, lx = e - ly * L::HX;
+        const int ly = e / L::HX, lx = e - ly * L::HX;
 #pragma unroll
-            for (int v = 0; v < L::NV; v++) sh.q[v][ly][lx] = r.val[it][v];
-            if constexpr (BATHY) sh.q[L::NV][ly][lx] = r.val[it][0] + r.val[it][L::NV];
-        }
+        for (int v = 0; v < L::NV; v++) sh.q[v][ly][lx] = r.val[it][v];
+        if constexpr (BATHY) sh.q[L::NV][ly][lx] = r.val[it][0] + r.val[it][L::NV];
     }
 }
 
@@ -460,13 +462,15 @@ __device__ __forceinline__ void stage_tile(const StageArgs<T> &a, const int x0, 
                                            const int tid)
 {
     __shared__ StageLds<T, EQN, BATHY, TX, TY> sh;
-    stage_dt(a, tid, sh);
     if (inner_tile<TX, TY>(x0, y0, a.nx, a.ny)) {
-        // every halo load is issued before the first LDS store
+        // every halo load is issued before the first LDS store and before
+        // the Delta t read, whose reduction would otherwise hold them back
         HaloRegs<T, EQN, BATHY, TX, TY> r;
         halo_issue(a, x0, y0, tid, r);
+        stage_dt(a, tid, sh);
         halo_commit(r, sh, tid);
     } else {
+        stage_dt(a, tid, sh);
         halo_border(a, x0, y0, tid, sh);
     }
     __syncthreads();
