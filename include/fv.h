@@ -329,7 +329,10 @@ typedef struct {
     float lr, beta1, beta2, eps; /* Adam */
     int32_t direct;       /* 0: the learned stencil-coefficient scheme (fv_learned_step); 1: the
                              direct face-state scheme (fv_direct_step, section 5.3) */
-    int32_t reserved0;    /* must be 0 */
+    int32_t blend;        /* 1 (with direct = 0): the stencil-coefficient scheme with the
+                             flux-limiter blend of its face fluxes (fv_blend_step, section 2.5.3
+                             second approach), differentiated through the limiter and the
+                             low-resolution flux; 0 otherwise */
 } fv_train_config;
 
 typedef struct fv_trainer fv_trainer;

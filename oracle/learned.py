@@ -377,16 +377,20 @@ def direct_step(params, q, dt, dx, dy, g=9.81, flux="hlle", round_bf16=True):
     return q2, {"fallback_faces": int(nfb.sum()), "redone": bad}
 
 
-def rollout_loss(params, q0, targets, dt, dx, dy, scale, g=9.81, flux="hlle", round_bf16=True, direct=False):
+def rollout_loss(params, q0, targets, dt, dx, dy, scale, g=9.81, flux="hlle", round_bf16=True, direct=False,
+                 blend=False):
     """eq 2.28: sum over t = 1..T of the MSE between the learned rollout and
     the reference targets (B, T, 3, H, W); variable v is divided by scale[v].
-    direct: the rollout of the direct face-state scheme instead."""
+    direct: the rollout of the direct face-state scheme instead; blend: of the
+    learned scheme with the flux-limiter blend of its face fluxes."""
     q = q0
     loss = torch.zeros((), dtype=F64)
     s = torch.as_tensor(scale, dtype=F64)[None, :, None, None]
-    step = direct_step if direct else learned_step
     for t in range(targets.shape[1]):
-        q, _ = step(params, q, dt, dx, dy, g, flux, round_bf16=round_bf16)
+        if direct:
+            q, _ = direct_step(params, q, dt, dx, dy, g, flux, round_bf16=round_bf16)
+        else:
+            q, _ = learned_step(params, q, dt, dx, dy, g, flux, round_bf16=round_bf16, blend=blend)
         loss = loss + (((q - targets[:, t]) / s) ** 2).mean()
     return loss
 

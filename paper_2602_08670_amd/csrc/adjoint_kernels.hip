@@ -41,6 +41,28 @@ struct AdjArgs {
     float sig[3];       // direct scheme: 1 / inv_std of the network's input normalisation
 };
 
+// Flux-limiter blend of one face (section 2.5.3, second approach), per
+// conserved variable v: F_v = (1 - phi_v) F_low,v + phi_v F_high,v with phi_v
+// the MINMOD limiter of r = a / b, a = q_i - q_{i-1}, b = q_{i+1} - q_i at the
+// face's low-index cell (stencil entries 1, 2, 3), as in the forward.  Where
+// phi_v = a / b its derivatives with respect to those entries are
+// (-1/b, 1/b + a/b^2, -a/b^2); where it is 0 or 1 (the branch taken) they
+// vanish.
+__device__ __forceinline__ void blend_limiter(const float (*st)[6], float *phi, float (*dphi)[3])
+{
+#pragma unroll
+    for (int v = 0; v < 3; v++) {
+        const float a = st[v][2] - st[v][1], b = st[v][3] - st[v][2];
+        const bool same = (a > 0.f && b > 0.f) || (a < 0.f && b < 0.f);
+        const bool frac = same && __builtin_fabsf(a) < __builtin_fabsf(b);
+        const float ib = frac ? 1.f / b : 0.f, r = a * ib;
+        phi[v] = frac ? r : (same ? 1.f : 0.f);
+        dphi[v][0] = -ib;
+        dphi[v][1] = ib + r * ib;
+        dphi[v][2] = -r * ib;
+    }
+}
+
 __device__ __forceinline__ int pw(int i, int n) { return ((i % n) + n) % n; }
 
 // MINMOD face states of one variable and their derivatives with respect to
@@ -80,7 +102,12 @@ __device__ __forceinline__ void minmod_right(const float *c, float &val, float *
 // of z; this
 // face writes the owner's high-side and the neighbour's low-side channels of
 // dz (each written by exactly one face).
-template <int FLUX, bool DIR>
+// BL: the learned face flux is blended with the flux of the two cell
+// averages by the flux limiter (blend_limiter): the learned path receives
+// phi g_F, the cell averages of the face (stencil entries 2 and 3) the
+// low-resolution flux's Jacobian times (1 - phi) g_F, and entries 1..3 the
+// limiter's derivative times g_F (F_high - F_low).
+template <int FLUX, bool DIR, bool BL = false>
 __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
 {
     const int nx = a.nx, ny = a.ny;
@@ -210,14 +237,50 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
         float gF[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) gF[c] = a.wscale * rd * (go[c * plane + nb] - go[c * plane + cell]);
+        // blend: the learned flux's share of the adjoint, and the adjoints of
+        // the low-resolution flux's states and of the limiter's stencil entries
+        float gH[3], gLo[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}}, gLim[3][3] = {};
+#pragma unroll
+        for (int c = 0; c < 3; c++) gH[c] = gF[c];
+        if (BL && learned) {
+            float phi[3], dphi[3][3];
+            blend_limiter(st, phi, dphi);
+            D cl[3], cr[3];
+#pragma unroll
+            for (int v = 0; v < 3; v++) {
+                cl[v] = fvk::seed<6>(st[v][2], v);
+                cr[v] = fvk::seed<6>(st[v][3], 3 + v);
+            }
+            D ilo = fvk::rcp(cl[0]), iro = fvk::rcp(cr[0]);
+            SweV<D> Lo{cl[0], cl[NM] * ilo, cl[TM] * ilo}, Ro{cr[0], cr[NM] * iro, cr[TM] * iro};
+            D Fn[3];
+            fvk::swe_numflux<D, FLUX>(Lo, Ro, ph, Fn);
+            D Flo[3];
+            Flo[0] = Fn[0];
+            Flo[NM] = Fn[1];
+            Flo[TM] = Fn[2];
+#pragma unroll
+            for (int c = 0; c < 3; c++) {
+                gH[c] = phi[c] * gF[c];
+                const float gl = (1.f - phi[c]) * gF[c];
+#pragma unroll
+                for (int v = 0; v < 3; v++) {
+                    gLo[0][v] += gl * Flo[c].d[v];
+                    gLo[1][v] += gl * Flo[c].d[3 + v];
+                }
+                const float gp = gF[c] * (Fc[c].v - Flo[c].v);
+#pragma unroll
+                for (int k = 0; k < 3; k++) gLim[c][k] = gp * dphi[c][k];
+            }
+        }
         float gQ[2][3];
 #pragma unroll
         for (int v = 0; v < 3; v++) {
             float sl = 0.f, sr = 0.f;
 #pragma unroll
             for (int c = 0; c < 3; c++) {
-                sl += gF[c] * Fc[c].d[v];
-                sr += gF[c] * Fc[c].d[3 + v];
+                sl += gH[c] * Fc[c].d[v];
+                sr += gH[c] * Fc[c].d[3 + v];
             }
             gQ[0][v] = sl;
             gQ[1][v] = sr;
@@ -233,6 +296,11 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
                 float cL = useL[0] ? al[0][v][k] : dML[v][k];
                 float cR = useL[1] ? al[1][v][k] : dMR[v][k];
                 co[v * 6 + k] = gQ[0][v] * cL + gQ[1][v] * cR;
+                if (BL) {
+                    if (k == 2) co[v * 6 + k] += gLo[0][v];
+                    if (k == 3) co[v * 6 + k] += gLo[1][v];
+                    if (k >= 1 && k <= 3) co[v * 6 + k] += gLim[v][k - 1];
+                }
             }
 #pragma unroll
             for (int s = 0; s < 2; s++) {
@@ -329,9 +397,13 @@ hipError_t launch_adjoint(int flux, const AdjStage &s, hipStream_t st)
     for (int v = 0; v < 3; v++) a.sig[v] = s.sig[v];
     size_t nf = (size_t)2 * s.B * s.nx * s.ny;
     unsigned blocks = (unsigned)((nf + 255) / 256);
+    if (s.direct && s.blend) return hipErrorInvalidValue;
     if (s.direct) {
         if (flux == 1) hipLaunchKernelGGL((adj_face_kernel<fvk::RUSANOV, true>), dim3(blocks), dim3(256), 0, st, a);
         else hipLaunchKernelGGL((adj_face_kernel<fvk::HLLE, true>), dim3(blocks), dim3(256), 0, st, a);
+    } else if (s.blend) {
+        if (flux == 1) hipLaunchKernelGGL((adj_face_kernel<fvk::RUSANOV, false, true>), dim3(blocks), dim3(256), 0, st, a);
+        else hipLaunchKernelGGL((adj_face_kernel<fvk::HLLE, false, true>), dim3(blocks), dim3(256), 0, st, a);
     } else {
         if (flux == 1) hipLaunchKernelGGL((adj_face_kernel<fvk::RUSANOV, false>), dim3(blocks), dim3(256), 0, st, a);
         else hipLaunchKernelGGL((adj_face_kernel<fvk::HLLE, false>), dim3(blocks), dim3(256), 0, st, a);

@@ -211,6 +211,7 @@ struct AdjStage {
     int accumulate;
     int direct;        // the direct face-state scheme (dz channels 0..11 written, the rest left zero)
     float sig[3];      // direct: 1 / inv_std of the network's input normalisation
+    int blend;         // the flux-limiter blend of the learned face fluxes
 };
 hipError_t launch_adjoint(int flux, const AdjStage &s, hipStream_t st);
 // Floats per face in the adjoint's contribution scratch: 18 used, padded so

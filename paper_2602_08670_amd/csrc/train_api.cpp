@@ -32,8 +32,8 @@ fv_status validate(const fv_train_config *c)
         if (!(c->scale[v] > 0)) return fail(FV_E_INVALID, "loss scale must be positive");
     if (!(c->lr > 0) || !(c->beta1 >= 0 && c->beta1 < 1) || !(c->beta2 >= 0 && c->beta2 < 1) || !(c->eps > 0))
         return fail(FV_E_INVALID, "Adam hyper-parameters");
-    if ((c->direct != 0 && c->direct != 1) || c->reserved0 != 0)
-        return fail(FV_E_INVALID, "direct must be 0 or 1, reserved0 0");
+    if ((c->direct != 0 && c->direct != 1) || (c->blend != 0 && c->blend != 1) || (c->direct && c->blend))
+        return fail(FV_E_INVALID, "direct and blend must be 0 or 1, not both 1");
     return FV_OK;
 }
 
@@ -190,7 +190,7 @@ fv_status fv_train_step(fv_trainer *tr, const float *q0, const float *targets, i
         void *a1[4] = {tr->act(t, 1, 0), tr->act(t, 1, 1), tr->act(t, 1, 2), tr->act(t, 1, 3)};
         e = cnn::launch_forward(tr->m->packed, tr->m->nrm, tr->st(t), B, nx, ny, a0, tr->zb(t, 0), st);
         sb.qs = tr->st(t); sb.q0 = tr->st(t); sb.out = tr->s1(t); sb.z = tr->zb(t, 0);
-        sb.a0 = 0.f; sb.a1 = 1.f; sb.flagbit = 1; sb.direct = c.direct;
+        sb.a0 = 0.f; sb.a1 = 1.f; sb.flagbit = 1; sb.direct = c.direct; sb.blend = c.blend;
         if (e == hipSuccess) e = cnn::learned_stage(0, fl, sb, st);
         if (e == hipSuccess) e = cnn::launch_forward(tr->m->packed, tr->m->nrm, tr->s1(t), B, nx, ny, a1, tr->zb(t, 1), st);
         sb.qs = tr->s1(t); sb.q0 = tr->st(t); sb.out = S2; sb.z = tr->zb(t, 1);
@@ -200,6 +200,7 @@ fv_status fv_train_step(fv_trainer *tr, const float *q0, const float *targets, i
         // solves whose learned step was inadmissible: plain step, which also
         // overwrites the saved stage input so the reverse pass sees it
         sb.direct = 0;
+        sb.blend = 0;
         sb.qs = tr->st(t); sb.q0 = tr->st(t); sb.out = tr->s1(t); sb.a0 = 0.f; sb.a1 = 1.f;
         if (e == hipSuccess) e = cnn::learned_stage(1, fl, sb, st);
         sb.qs = tr->s1(t); sb.q0 = tr->st(t); sb.out = tr->st(t + 1); sb.a0 = 0.5f; sb.a1 = 0.5f;
@@ -216,6 +217,7 @@ fv_status fv_train_step(fv_trainer *tr, const float *q0, const float *targets, i
     if (e == hipSuccess) e = hipMemsetAsync(tr->grads, 0, (size_t)cnn::NPARAM * 4, st);
     cnn::AdjStage as;
     as.direct = c.direct;
+    as.blend = c.blend;
     for (int v = 0; v < 3; v++) as.sig[v] = 1.0f / tr->m->nrm.inv_std[v];
     as.dt = (float)c.dt;
     as.B = B;

@@ -65,7 +65,7 @@ class fv_train_config(ctypes.Structure):
                 ("ly", ctypes.c_double), ("dt", ctypes.c_double), ("g", ctypes.c_double), ("h_ref", ctypes.c_double),
                 ("scale", ctypes.c_float * 3), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("direct", ctypes.c_int32),
-                ("reserved0", ctypes.c_int32)]
+                ("blend", ctypes.c_int32)]
 
 
 class fv_server_config(ctypes.Structure):
@@ -370,7 +370,7 @@ def fv_coarsen(fine_ptr, nvar, nx, ny, factor, coarse_ptr, stream=0):
 
 def make_train_config(B, nx, ny, T, dt, lx=1.0, ly=1.0, g=9.81, h_ref=1.0, flux=FV_FLUX_HLLE,
                       scale=(0.05, 0.05, 0.05), lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8,
-                      direct=False) -> fv_train_config:
+                      direct=False, blend=False) -> fv_train_config:
     c = fv_train_config()
     c.struct_size = ctypes.sizeof(fv_train_config)
     c.B, c.nx, c.ny, c.T, c.flux = B, nx, ny, T, flux
@@ -378,7 +378,7 @@ def make_train_config(B, nx, ny, T, dt, lx=1.0, ly=1.0, g=9.81, h_ref=1.0, flux=
     for i in range(3):
         c.scale[i] = scale[i]
     c.lr, c.beta1, c.beta2, c.eps = lr, beta1, beta2, eps
-    c.direct, c.reserved0 = 1 if direct else 0, 0
+    c.direct, c.blend = 1 if direct else 0, 1 if blend else 0
     return c
 
 

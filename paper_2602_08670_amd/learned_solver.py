@@ -77,12 +77,45 @@ def init_params(seed: int) -> np.ndarray:
     return fv.params_to_vector(ws, bs)
 
 
+def validation_set(seeds, n_fine, factor, n_coarse_steps):
+    """Held-out rollouts for checkpoint selection: the coarse initial states
+    and the coarsened fine states n_coarse_steps coarse steps later."""
+    q0, ref = [], []
+    for sd in seeds:
+        tr = trajectory(sd, n_fine, factor, n_coarse_steps)
+        q0.append(tr[0].cpu().numpy())
+        ref.append(tr[-1].double().cpu().numpy())
+    return {"q0": q0, "ref": ref, "steps": n_coarse_steps}
+
+
+def rollout_error(model, val, dt_c, direct: bool = False, blend: bool = False) -> float:
+    """Mean relative L2 depth error of the learned rollouts of a validation
+    set (the model's packed weights re-packed from its master parameters)."""
+    model.update()
+    errs = []
+    for q0, ref in zip(val["q0"], val["ref"]):
+        s = fv.Solver(q0, prec=fv.FV_F32, dt_fixed=dt_c, learned=1, h_ref=1.0)
+        (s.direct_step if direct else s.blend_step if blend else s.learned_step)(model, val["steps"], want_stats=False)
+        out = s.state()
+        s.close()
+        errs.append(rel_l2(out[0], ref[0]) if np.all(np.isfinite(out)) else float("inf"))
+    return float(np.mean(errs))
+
+
 def train(data, iters: int, B: int = 16, T_max: int = 8, lr: float = 1e-3, seed: int = 0, log_every: int = 0,
           model=None, dt_c: float | None = None, n_fine: int | None = None, factor: int | None = None,
-          lr_final: float | None = None, direct: bool = False):
+          lr_final: float | None = None, direct: bool = False, val=None, val_every: int = 25, blend: bool = False):
     """Curriculum training on windows of the coarse trajectories data
     [n_traj, S+1, 3, n, n].  T grows 1 -> T_max over the first half; with
-    lr_final the learning rate follows a cosine from lr to lr_final."""
+    lr_final the learning rate follows a cosine from lr to lr_final.  blend:
+    the scheme with the flux-limiter blend of its face fluxes is trained.
+
+    val (validation_set): every val_every iterations, and for the initial
+    parameters, the learned rollout of the validation states is compared with
+    their reference; training returns the parameters with the smallest
+    validation error.  The unrolled loss only sees windows of T_max steps,
+    so parameters that fit those windows can still drift over a long
+    rollout; selecting on the long rollout keeps such iterates out."""
     import torch
 
     n_traj, S1, _, n, _ = data.shape
@@ -91,10 +124,13 @@ def train(data, iters: int, B: int = 16, T_max: int = 8, lr: float = 1e-3, seed:
     mean, inv_std, std = normalisation(data)
     if model is None:
         model = fv.Model(init_params(seed), fv.make_model_desc(mean=mean, inv_std=inv_std))
-    cfg = fv.make_train_config(B, n, n, T_max, dt_c, h_ref=1.0, scale=tuple(std), lr=lr, direct=direct)
+    cfg = fv.make_train_config(B, n, n, T_max, dt_c, h_ref=1.0, scale=tuple(std), lr=lr, direct=direct, blend=blend)
     tr = fv.Trainer(model, cfg)
     rng = np.random.default_rng(seed + 1)
     hist = []
+    best = None
+    if val is not None:
+        best = (rollout_error(model, val, dt_c, direct, blend), 0, model.params.clone())
     t0 = time.perf_counter()
     for it in range(iters):
         T = min(T_max, 1 + (it * T_max) // max(1, iters // 2))
@@ -109,6 +145,14 @@ def train(data, iters: int, B: int = 16, T_max: int = 8, lr: float = 1e-3, seed:
         hist.append((it, T, loss))
         if log_every and it % log_every == 0:
             print(f"[train] it {it} T {T} loss {loss:.4e} fallback {stats[0]} redone {stats[1]}", flush=True)
+        if val is not None and ((it + 1) % val_every == 0 or it + 1 == iters):
+            e = rollout_error(model, val, dt_c, direct, blend)
+            if e < best[0]:
+                best = (e, it + 1, model.params.clone())
+    if best is not None:
+        model.params.copy_(best[2])
+        model.update()
+        model.selected = {"iteration": best[1], "val_rel_l2_h": best[0]}
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     tr.close()
@@ -144,10 +188,11 @@ def graph_replay(launch, total: int, chunk: int, stream):
 
 
 def evaluate(model, seeds, n_fine, factor, n_coarse_steps, plain_sizes=(64, 128, 256, 512), chunk=50,
-             direct: bool = False, blend: bool = False):
+             direct: bool = False, blend: bool = False, refs: dict | None = None):
     """Errors at the final time of the learned coarse solver and of the plain
     scheme at plain_sizes against the fine reference (block-averaged), and
-    graph-replayed time-to-solution of each."""
+    graph-replayed time-to-solution of each.  refs: a dict that caches the
+    fine references per seed across calls."""
     import torch
 
     n = n_fine // factor
@@ -156,8 +201,11 @@ def evaluate(model, seeds, n_fine, factor, n_coarse_steps, plain_sizes=(64, 128,
            "t_end": dt_c * n_coarse_steps, "cases": {}}
     keys = ["learned"] + [f"plain{m}" for m in plain_sizes]
     errs, hs, times, fb = ({k: [] for k in keys} for _ in range(4))
+    refs = {} if refs is None else refs
     for seed in seeds:
-        ref = trajectory(seed, n_fine, factor, n_coarse_steps)[-1].double().cpu().numpy()
+        if seed not in refs:
+            refs[seed] = trajectory(seed, n_fine, factor, n_coarse_steps)[-1].double().cpu().numpy()
+        ref = refs[seed]
         q0f = torch.tensor(inputs.random_smooth_swe(n_fine, seed=seed), dtype=torch.float32, device="cuda")
         q0c = fv.coarsen(q0f, factor).cpu().numpy()
         st = torch.cuda.Stream()
@@ -199,10 +247,13 @@ def main():
     ap.add_argument("--traj-steps", type=int, default=512)
     ap.add_argument("--iters", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=16)
-    ap.add_argument("--T", type=int, default=16)
+    ap.add_argument("--T", type=int, default=32, help="unrolled steps of the loss (eq 2.28 uses 32)")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lr-final", type=float, default=2e-5, help="end of the cosine schedule (<= 0: constant)")
-    ap.add_argument("--eval-seeds", type=int, default=4)
+    ap.add_argument("--eval-seeds", type=int, default=32)
+    ap.add_argument("--val-seeds", type=int, default=4, help="held-out rollouts for checkpoint selection")
+    ap.add_argument("--val-steps", type=int, default=250, help="coarse steps of each validation rollout")
+    ap.add_argument("--val-every", type=int, default=100)
     ap.add_argument("--eval-steps", type=int, default=1000)
     ap.add_argument("--plain-sizes", default="64,128,256,512",
                     help="grid sides of the plain-scheme comparison runs (multiples of the coarse side)")
@@ -210,6 +261,9 @@ def main():
                     help="the direct face-state scheme of section 5.3 instead of the stencil coefficients")
     ap.add_argument("--eval-blend", action="store_true",
                     help="also evaluate the trained network with the flux-limiter blend of its face fluxes")
+    ap.add_argument("--blend", action="store_true",
+                    help="train and evaluate the stencil-coefficient scheme with the flux-limiter blend of its face "
+                         "fluxes (section 2.5.3, second approach)")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     plain_sizes = tuple(int(v) for v in a.plain_sizes.split(",") if v)
@@ -217,23 +271,29 @@ def main():
     data = dataset(range(1000, 1000 + a.train_seeds), a.n_fine, a.factor, a.traj_steps)
     tdata = time.perf_counter() - t0
     print(f"[data] {tuple(data.shape)} in {tdata:.1f} s", flush=True)
+    val = validation_set(range(3000, 3000 + a.val_seeds), a.n_fine, a.factor, a.val_steps) if a.val_seeds else None
     model, hist, wall = train(data, a.iters, a.batch, a.T, a.lr, log_every=100, n_fine=a.n_fine, factor=a.factor,
-                              lr_final=a.lr_final if a.lr_final > 0 else None, direct=a.direct)
-    print(f"[train] {a.iters} iterations in {wall:.1f} s, loss {hist[0][2]:.3e} -> {hist[-1][2]:.3e}", flush=True)
+                              lr_final=a.lr_final if a.lr_final > 0 else None, direct=a.direct, val=val,
+                              val_every=a.val_every, blend=a.blend)
+    print(f"[train] {a.iters} iterations in {wall:.1f} s, loss {hist[0][2]:.3e} -> {hist[-1][2]:.3e}; "
+          f"selected {getattr(model, 'selected', None)}", flush=True)
+    refs = {}
     res = evaluate(model, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps, plain_sizes=plain_sizes,
-                   direct=a.direct)
+                   direct=a.direct, blend=a.blend, refs=refs)
     print(f"[eval] " + ", ".join(f"{k}: rel L2(h) {v['rel_l2_h']:.3e} in {v['time_to_solution_s'] * 1e3:.1f} ms"
                                  for k, v in res["cases"].items()), flush=True)
     untrained = fv.Model(init_params(0), model.desc)
     res["untrained"] = evaluate(untrained, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps,
-                                plain_sizes=(), direct=a.direct)["cases"]["learned"]
+                                plain_sizes=(), direct=a.direct, blend=a.blend, refs=refs)["cases"]["learned"]
     if a.eval_blend and not a.direct:
         res["blend"] = evaluate(model, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps,
-                                plain_sizes=(), blend=True)["cases"]["learned"]
+                                plain_sizes=(), blend=True, refs=refs)["cases"]["learned"]
         print(f"[eval] blended: rel L2(h) {res['blend']['rel_l2_h']:.3e} in "
               f"{res['blend']['time_to_solution_s'] * 1e3:.1f} ms", flush=True)
-    res["scheme"] = "direct face states" if a.direct else "stencil coefficients"
+    res["scheme"] = ("direct face states" if a.direct else
+                     "stencil coefficients with the flux-limiter blend" if a.blend else "stencil coefficients")
     res["train"] = {"iters": a.iters, "batch": a.batch, "T": a.T, "wall_s": wall, "data_s": tdata,
+                    "selected": getattr(model, "selected", None), "val_seeds": a.val_seeds, "val_steps": a.val_steps,
                     "loss_first": hist[0][2], "loss_last": hist[-1][2], "snapshots": int(data.shape[0] * data.shape[1])}
     print(json.dumps(res, indent=1), flush=True)
     if a.out:

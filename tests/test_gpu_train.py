@@ -6,7 +6,16 @@ Gradient tolerance: the GPU backward runs the network in BF16 with FP32
 accumulation (activations, weights and the back-propagated signals are
 BF16), the oracle in double precision with bfloat16 rounding passed
 straight through, so the gradients agree to a few bfloat16 ulps per
-operation: cosine similarity >= 0.999 and relative L2 <= 1e-2."""
+operation: cosine similarity >= 0.999 and relative L2 <= 1e-2.
+
+With the flux-limiter blend, d loss / d q0 also runs through the limiter
+phi = (q_i - q_{i-1}) / (q_{i+1} - q_i), whose derivative grows like one over
+the local difference: wherever a field is nearly flat the input gradient is
+ill-conditioned, in the oracle too (perturbing the initial state by FP32
+rounding moves its double-precision input gradient by several percent).
+The blend cases therefore use states whose three fields all vary across the
+grid, keep the parameter-gradient bounds, and bound the input-gradient error
+by three times that measured sensitivity of the oracle (and 1e-2)."""
 import numpy as np
 import pytest
 import torch
@@ -55,6 +64,20 @@ def cos(a, b):
     return float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
 
 
+def batch_varying(n, B, seed0, ny=None):
+    """The states of batch() plus waves in every field (depth along x + 2y,
+    hu along x and y, hv along x - y and 2y), so that no field is flat."""
+    q = np.stack([I.random_smooth_swe(n, seed=seed0 + b) for b in range(B)])
+    x = (np.arange(n) + 0.5) / n
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    q[:, 0] += 0.03 * np.sin(2 * np.pi * (X + 2 * Y))[None]
+    q[:, 1] = (0.02 * np.sin(2 * np.pi * X) + 0.01 * np.cos(2 * np.pi * Y))[None]
+    q[:, 2] = (0.015 * np.cos(2 * np.pi * (X - Y)) + 0.01 * np.sin(4 * np.pi * Y))[None]
+    if ny is not None:
+        q = q[:, :, :ny].copy()
+    return q.astype(np.float32)
+
+
 def batch(n, B, seed0, ny=None):
     """B smooth states on an n x n grid; with ny < n the first ny rows (the
     periodic seam then carries a jump)."""
@@ -65,17 +88,20 @@ def batch(n, B, seed0, ny=None):
     return q.astype(np.float32)
 
 
-@pytest.mark.parametrize("flux,ny,nx,direct", [("hlle", 32, 32, False), ("rusanov", 32, 32, False),
-                                               ("hlle", 24, 48, False), ("hlle", 32, 32, True),
-                                               ("rusanov", 32, 32, True)])
-def test_gradients_match_oracle(fv, L, flux, ny, nx, direct):
+@pytest.mark.parametrize("flux,ny,nx,direct,blend", [("hlle", 32, 32, False, False), ("rusanov", 32, 32, False, False),
+                                                     ("hlle", 24, 48, False, False), ("hlle", 32, 32, True, False),
+                                                     ("rusanov", 32, 32, True, False), ("hlle", 32, 32, False, True),
+                                                     ("rusanov", 32, 32, False, True), ("hlle", 24, 48, False, True)])
+def test_gradients_match_oracle(fv, L, flux, ny, nx, direct, blend):
     """Square grids, and 24 x 48: rows past the last full 16-row tile of the
-    input-gradient convolutions; the learned scheme and the direct face-state
+    input-gradient convolutions; the learned scheme, the direct face-state
     scheme (section 5.3: the adjoint passes each side's gradient to its own
-    cell and to its own cell's channels of the network output)."""
+    cell and to its own cell's channels of the network output) and the
+    learned scheme with the flux-limiter blend (section 2.5.3, second
+    approach: through the limiter's branch and the low-resolution flux)."""
     B, T, dt = 2, 2, 1.2e-3 * 32 / nx
     p = params(L, 21)
-    q0 = batch(nx, B, 40, ny)
+    q0 = batch_varying(nx, B, 40, ny) if blend else batch(nx, B, 40, ny)
     # targets: the plain scheme from slightly perturbed states (non-zero loss)
     with torch.no_grad():
         tg, qq = [], torch.tensor(q0.astype(np.float64)) * 1.002
@@ -84,10 +110,10 @@ def test_gradients_match_oracle(fv, L, flux, ny, nx, direct):
             tg.append(qq.float().double())
         tg = torch.stack(tg, 1)  # [B, T, 3, ny, nx]
     scale = (0.05, 0.02, 0.02)
-    print(f"[gpu] train grad parity {flux} B={B} T={T} {ny}x{nx} direct={direct}", flush=True)
+    print(f"[gpu] train grad parity {flux} B={B} T={T} {ny}x{nx} direct={direct} blend={blend}", flush=True)
     m = fv.Model(vec(fv, p), fv.make_model_desc(mean=(1.0, 0.0, 0.0), inv_std=(10.0, 10.0, 10.0)))
     cfg = fv.make_train_config(B, nx, ny, T, dt, flux=fv.FV_FLUX_HLLE if flux == "hlle" else fv.FV_FLUX_RUSANOV,
-                               scale=scale, h_ref=1.0, direct=direct)
+                               scale=scale, h_ref=1.0, direct=direct, blend=blend)
     tr = fv.Trainer(m, cfg)
     tgt = torch.tensor(tg.permute(1, 0, 2, 3, 4).numpy().astype(np.float32), device="cuda")
     loss, stats = tr.step(torch.tensor(q0, device="cuda"), tgt)
@@ -99,7 +125,7 @@ def test_gradients_match_oracle(fv, L, flux, ny, nx, direct):
     for t in p["w"] + p["b"]:
         t.requires_grad_(True)
     qv = torch.tensor(q0.astype(np.float64), requires_grad=True)
-    lo = L.rollout_loss(p, qv, tg, dt, 1 / nx, 1 / ny, scale, flux=flux, direct=direct)
+    lo = L.rollout_loss(p, qv, tg, dt, 1 / nx, 1 / ny, scale, flux=flux, direct=direct, blend=blend)
     gw = torch.autograd.grad(lo, p["w"] + p["b"] + [qv])
     g_or = grad_vec(gw[:5], gw[5:10])
     gq_or = gw[10].numpy()
@@ -109,7 +135,18 @@ def test_gradients_match_oracle(fv, L, flux, ny, nx, direct):
           f"q0 cos {cq:.6f} rel {relq:.2e}; stats {stats}", flush=True)
     assert abs(loss - lo.item()) <= 1e-3 * lo.item()
     assert c >= 0.999 and rel <= 1e-2
-    assert cq >= 0.999 and relq <= 1e-2
+    if blend:
+        # the oracle's own input-gradient change under an FP32-rounding-size
+        # perturbation of the initial state
+        rng = np.random.default_rng(3)
+        qp = torch.tensor(q0.astype(np.float64) * (1 + 6e-8 * rng.standard_normal(q0.shape)), requires_grad=True)
+        lp = L.rollout_loss(p, qp, tg, dt, 1 / nx, 1 / ny, scale, flux=flux, blend=True)
+        gqp = torch.autograd.grad(lp, [qp])[0].numpy()
+        floor = np.linalg.norm(gqp - gq_or) / np.linalg.norm(gq_or)
+        print(f"[grad] blend input-gradient sensitivity of the oracle {floor:.2e}", flush=True)
+        assert relq <= max(3.0 * floor, 1e-2) and cq >= 0.95
+    else:
+        assert cq >= 0.999 and relq <= 1e-2
     # per layer: the weight gradient of every layer is right (not only the large ones)
     off = 0
     for l, (w, b) in enumerate(zip(gw[:5], gw[5:10])):
@@ -170,8 +207,8 @@ def test_gradients_batch_equals_mean_of_solves(fv, L):
         off += k
 
 
-@pytest.mark.parametrize("direct", [False, True])
-def test_adam_reduces_loss(fv, L, direct):
+@pytest.mark.parametrize("direct,blend", [(False, False), (True, False), (False, True)])
+def test_adam_reduces_loss(fv, L, direct, blend):
     """A few Adam steps on one batch lower the unrolled loss (learned and
     direct face-state schemes)."""
     n, B, T, dt = 32, 4, 3, 1.0e-3
@@ -185,13 +222,13 @@ def test_adam_reduces_loss(fv, L, direct):
             tg.append(qq.float())
     tgt = torch.stack(tg).cuda()
     m = fv.Model(vec(fv, p))
-    tr = fv.Trainer(m, fv.make_train_config(B, n, n, T, dt, lr=3e-4, direct=direct))
+    tr = fv.Trainer(m, fv.make_train_config(B, n, n, T, dt, lr=3e-4, direct=direct, blend=blend))
     losses = []
     for _ in range(30):
         loss, _ = tr.step(q0, tgt)
         losses.append(loss)
         tr.adam()
-    print(f"[adam] direct={direct} loss {losses[0]:.4e} -> {losses[-1]:.4e}", flush=True)
+    print(f"[adam] direct={direct} blend={blend} loss {losses[0]:.4e} -> {losses[-1]:.4e}", flush=True)
     assert losses[-1] < 0.5 * losses[0]
     tr.close()
     m.close()
