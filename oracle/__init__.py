@@ -22,6 +22,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liborc.so")
 SRC_PATH = os.path.join(HERE, "fv_oracle.c")
+SPHERE_SRC_PATH = os.path.join(HERE, "sphere_oracle.c")
 
 SWE, EULER = 0, 1
 PERIODIC, WALL = 0, 1
@@ -31,10 +32,11 @@ MINMOD, FIRST = 0, 1
 
 def build(force: bool = False) -> str:
     """Compile the C oracle with gcc (no fast-math, OpenMP row loops)."""
-    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+    newest = max(os.path.getmtime(SRC_PATH), os.path.getmtime(SPHERE_SRC_PATH))
+    if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < newest:
         tmp = LIB_PATH + ".tmp"
         subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-Wall",
-                               "-o", tmp, SRC_PATH, "-lm"])
+                               "-o", tmp, SRC_PATH, SPHERE_SRC_PATH, "-lm"])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
 

@@ -145,3 +145,30 @@ def uniform_state(n: int, h: float = 1.0, u: float = 0.0, v: float = 0.0) -> np.
     q[1] = h * u
     q[2] = h * v
     return q
+
+
+def sphere_state(centres: np.ndarray, seed: int = 0, h0: float = 1.0, bumps: int = 4, u0: float = 0.0,
+                 omega: float = 0.0, g: float = 1.0) -> np.ndarray:
+    """Shallow water on the unit sphere in Cartesian form, sampled at given
+    cell centres [3][ny][nx] (unit vectors): an eastward solid-body flow
+    m = h u0 (z_hat x x) over the depth h0 - (omega u0 + u0^2/2) z^2 / g that
+    balances it on a sphere rotating at omega (a steady state), plus `bumps`
+    seeded Gaussian depth bumps A exp(-(angle to c)^2 / w^2), A ~ U[0.02, 0.08],
+    w ~ U[0.15, 0.35], c uniform on the sphere (draw order per bump: A, w,
+    then c as a normalised standard-normal 3-vector).  Returns [4][ny][nx]
+    float64: h, hu, hv, hw."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    x, y, z = centres
+    h = h0 - (omega * u0 + 0.5 * u0 * u0) * z * z / g
+    for _ in range(bumps):
+        a = rng.uniform(0.02, 0.08)
+        w = rng.uniform(0.15, 0.35)
+        c = rng.standard_normal(3)
+        c = c / np.linalg.norm(c)
+        ang = np.arccos(np.clip(c[0] * x + c[1] * y + c[2] * z, -1.0, 1.0))
+        h = h + a * np.exp(-(ang * ang) / (w * w))
+    q = np.zeros((4,) + x.shape)
+    q[0] = h
+    q[1] = h * u0 * (-y)
+    q[2] = h * u0 * x
+    return q
