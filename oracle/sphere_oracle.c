@@ -30,7 +30,8 @@
  *     and the CFL time step, as in the planar oracle.
  *
  * Readings where the thesis is silent (listed in the design notes):
- *   - the grid has n cells per hemisphere side: 2n x n cells, dx = dy = 2/n;
+ *   - the grid has n cells per hemisphere side: 2n x n cells, dx = dy = 2/n
+ *     (corner coordinates formed as exact ratios, coord_x / coord_y);
  *     cell corners are mapped, cell centres are the images of the
  *     computational cell centres;
  *   - neighbours across the domain boundary: x is periodic (x = -3 and x = 1
@@ -113,6 +114,13 @@ static void sphere_point(double xc, double yc, double p[3])
     p[2] = north ? z : -z;
 }
 
+/* Computational coordinates of corner column I and corner row J (twice
+ * the index: centres are odd), as one correctly rounded ratio of exact
+ * integers, so that the squares' edges x = -3, -1, 1 and y = -1, 1 come out
+ * exact for every n (-3 + I * (2/n) misses 1 by an ulp for some n). */
+static double coord_x(int nn, int twice_I) { return (double)(twice_I - 3 * nn) / nn; }
+static double coord_y(int nn, int twice_J) { return (double)(twice_J - nn) / nn; }
+
 static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
 static void cross3(const double *a, const double *b, double *c)
 {
@@ -155,10 +163,9 @@ typedef struct { double n[3], t[3], r[3], len; } face_geom;
  * from corner (I, j) to corner (I, j+1). */
 static void xface_geom(int nn, int I, int j, face_geom *f)
 {
-    const double dx = 2.0 / nn;
     double a[3], b[3];
-    sphere_point(-3.0 + I * dx, -1.0 + j * dx, a);
-    sphere_point(-3.0 + I * dx, -1.0 + (j + 1) * dx, b);
+    sphere_point(coord_x(nn, 2 * I), coord_y(nn, 2 * j), a);
+    sphere_point(coord_x(nn, 2 * I), coord_y(nn, 2 * j + 2), b);
     for (int k = 0; k < 3; k++) {
         f->t[k] = b[k] - a[k];
         f->r[k] = a[k] + b[k];
@@ -174,10 +181,9 @@ static void xface_geom(int nn, int I, int j, face_geom *f)
  * from corner (i, J) to corner (i+1, J). */
 static void yface_geom(int nn, int i, int J, face_geom *f)
 {
-    const double dx = 2.0 / nn;
     double a[3], b[3];
-    sphere_point(-3.0 + i * dx, -1.0 + J * dx, a);
-    sphere_point(-3.0 + (i + 1) * dx, -1.0 + J * dx, b);
+    sphere_point(coord_x(nn, 2 * i), coord_y(nn, 2 * J), a);
+    sphere_point(coord_x(nn, 2 * i + 2), coord_y(nn, 2 * J), b);
     for (int k = 0; k < 3; k++) {
         f->t[k] = b[k] - a[k];
         f->r[k] = a[k] + b[k];
@@ -194,13 +200,12 @@ typedef struct { double c[3], area, perim, N[3]; } cell_geom;
 
 static void cell_geometry(int nn, int i, int j, cell_geom *g)
 {
-    const double dx = 2.0 / nn;
     double p00[3], p10[3], p11[3], p01[3];
-    sphere_point(-3.0 + i * dx, -1.0 + j * dx, p00);
-    sphere_point(-3.0 + (i + 1) * dx, -1.0 + j * dx, p10);
-    sphere_point(-3.0 + (i + 1) * dx, -1.0 + (j + 1) * dx, p11);
-    sphere_point(-3.0 + i * dx, -1.0 + (j + 1) * dx, p01);
-    sphere_point(-3.0 + (i + 0.5) * dx, -1.0 + (j + 0.5) * dx, g->c);
+    sphere_point(coord_x(nn, 2 * i), coord_y(nn, 2 * j), p00);
+    sphere_point(coord_x(nn, 2 * i + 2), coord_y(nn, 2 * j), p10);
+    sphere_point(coord_x(nn, 2 * i + 2), coord_y(nn, 2 * j + 2), p11);
+    sphere_point(coord_x(nn, 2 * i), coord_y(nn, 2 * j + 2), p01);
+    sphere_point(coord_x(nn, 2 * i + 1), coord_y(nn, 2 * j + 1), g->c);
     g->area = tri_area(p00, p10, p11) + tri_area(p00, p11, p01);
     face_geom L, R, B, T;
     xface_geom(nn, i, j, &L);
@@ -388,7 +393,7 @@ static void project(const sph_config *c, double *q)
     for (int j = 0; j < ny; j++)
         for (int i = 0; i < nx; i++) {
             double x[3];
-            sphere_point(-3.0 + (i + 0.5) * (2.0 / nn), -1.0 + (j + 0.5) * (2.0 / nn), x);
+            sphere_point(coord_x(nn, 2 * i + 1), coord_y(nn, 2 * j + 1), x);
             size_t k = (size_t)j * nx + i;
             double m[3] = {q[plane + k], q[2 * plane + k], q[3 * plane + k]};
             double mr = dot3(m, x);

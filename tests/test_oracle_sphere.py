@@ -36,7 +36,24 @@ def test_disk_mapping_special_points(S):
         assert np.allclose(q, [p[0], p[1], -p[2]], atol=1e-15)
 
 
-@pytest.mark.parametrize("n", [4, 10, 32])
+@pytest.mark.parametrize("n", [4, 10, 12, 32, 49])
+def test_equator_edges_lie_on_the_equator(S, n):
+    """The squares' boundaries are the equator (section 2.4): every edge on
+    y = -+1 and on x = -3, -1, 1 has both corners at z = 0 exactly, whatever
+    n (-3 + i 2/n misses -1 or 1 by an ulp for some n, e.g. 49, and sqrt(1 -
+    r^2) would lift such a corner by ~1e-8)."""
+    c = S.Config(n=n)
+    for i in range(2 * n):
+        for J in (0, n):
+            _, t, r, _ = S.face(c, 1, i, J)
+            assert r[2] == 0.0 and t[2] == 0.0, (i, J, r, t)
+    for I in (0, n, 2 * n):
+        for j in range(n):
+            _, t, r, _ = S.face(c, 0, I, j)
+            assert r[2] == 0.0 and t[2] == 0.0, (I, j, r, t)
+
+
+@pytest.mark.parametrize("n", [4, 10, 32, 49])
 def test_grid_tiles_the_sphere(S, n):
     """Cell areas sum to 4 pi; every face is orthonormal (n, t, r) with n
     pointing from the low-index cell to the high-index one; the periodic x
