@@ -428,6 +428,12 @@ typedef struct {
                                 counted in fv_server_pool_overhead); rounds with more learned cells
                                 use the one-launch network pass; 0: no scratch (never layer by
                                 layer) */
+    int32_t max_bypass;      /* admission ageing: after a queued request has not fitted in this many
+                                rounds, no request queued behind it is admitted until it is, so a
+                                large request waits a bounded number of rounds (the running solves'
+                                remaining rounds plus max_bypass); 0: 8; -1: never (plain first fit,
+                                later requests may pass it indefinitely) */
+    int32_t reserved0;       /* must be 0 */
 } fv_server_config;
 
 typedef struct {
@@ -448,7 +454,7 @@ typedef struct {
 
 typedef struct {
     int32_t state;           /* 0 queued, 1 running, 2 done, 3 failed (inadmissible) */
-    int32_t pad;
+    int32_t rounds_queued;   /* rounds the request stayed queued before its admission */
     int64_t steps_done;
     double t_submit, t_admit, t_done; /* seconds since fv_server_create */
     double sim_time;         /* simulated time reached (done requests) */
@@ -504,6 +510,76 @@ fv_status fv_server_result(fv_server *s, int64_t id, float *dst);
 fv_status fv_server_release(fv_server *s, int64_t id);
 
 void fv_server_destroy(fv_server *s);
+
+/* ------------------------------------------------------------------------
+ * Shallow water on the sphere (thesis section 3.3, on the logically
+ * rectangular grid of section 2.4).
+ *
+ * Grid: 2n x n cells on the computational rectangle [-3,1] x [-1,1] (cell
+ * (i, j) spans x in [-3 + 2i/n, -3 + 2(i+1)/n], y in [-1 + 2j/n, ...]); the
+ * square [-1,1]^2 maps to the northern hemisphere (the disk mapping of
+ * section 2.4 with R = 1, D(d) = d/sqrt 2, lifted by z = sqrt(1 - x^2 - y^2)),
+ * the square [-3,-1] x [-1,1] reflected (x -> -2 - x) to the southern one.
+ * Neighbours: periodic in x; across y = -+1 the cell of column 2n-1-i.
+ * Unit sphere; time in the unit of the configured g and omega.
+ *
+ * State: [4][n][2n] (h, hu, hv, hw) with Cartesian momenta, element type of
+ * prec.  Per face a unit normal n and tangent t in the tangent plane at the
+ * edge midpoint (great-circle edge length); face states (MINMOD along the
+ * index lines, eq 2.18, or first order) rotated into (n, t, r), the 1D
+ * Riemann problem (HLLE, Rusanov or Roe; eq 2.12-2.16) along n, the flux
+ * rotated back (eq 2.24); every cell's momentum equation subtracts its own
+ * flux against the sum of its outward edge normals times lengths (eq 3.1)
+ * and adds the Coriolis force -2 omega z (x cross m) (eq 3.2); after every
+ * stage the momentum is projected onto the tangent plane at the cell centre
+ * (the tangency forcing of eq 3.2).  Delta t from the CFL condition: cfl /
+ * max over cells of (|m|/h + sqrt(g h)) perimeter / (2 area), reduced on the
+ * device every step, or dt_fixed.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t struct_size; /* sizeof(fv_sphere_config) */
+    int32_t prec;         /* FV_F32 | FV_F64 */
+    int32_t n;            /* cells per hemisphere side, 4..8192: grid 2n x n */
+    int32_t flux;         /* FV_FLUX_* */
+    int32_t recon;        /* FV_RECON_MINMOD | FV_RECON_FIRST */
+    int32_t rk_stages;    /* 1, 2 (Heun) or 3 */
+    int32_t reserved0;    /* must be 0 */
+    int32_t pad;
+    double cfl;           /* in (0, 1] unless dt_fixed > 0 */
+    double dt_fixed;      /* > 0: fixed Delta t */
+    double g;             /* gravity, > 0 */
+    double omega;         /* rotation rate of the Coriolis term */
+} fv_sphere_config;
+
+typedef struct fv_sphere fv_sphere;
+
+/* Device workspace bytes (geometry, face fluxes, stage buffers, reduction
+ * slots); 0 if cfg is invalid. */
+size_t fv_sphere_workspace_bytes(const fv_sphere_config *cfg);
+
+/* Create a solver over caller-owned device memory: q [4][n][2n] updated in
+ * place, workspace (256-byte aligned) of fv_sphere_workspace_bytes.
+ * Computes the grid geometry on the device and checks that the initial
+ * state is admissible (FV_E_INADMISSIBLE; this synchronises the stream). */
+fv_status fv_sphere_init(const fv_sphere_config *cfg, void *q, void *workspace, size_t workspace_bytes, void *stream,
+                         fv_sphere **out);
+
+/* Enqueue nsteps >= 0 full steps (no host synchronisation). */
+fv_status fv_sphere_run(fv_sphere *s, int64_t nsteps);
+
+/* Sync point: simulated time and completed steps; FV_E_INADMISSIBLE if a
+ * cell reached h <= 0 or a non-finite value (later steps were skipped). */
+fv_status fv_sphere_time(fv_sphere *s, double *t, int64_t *steps);
+
+/* Sync point: copy the cell centres (unit vectors, [3][n][2n], solver
+ * precision) to the device buffer dst, e.g. to sample initial states. */
+fv_status fv_sphere_centres(fv_sphere *s, void *dst);
+
+/* Sync point: total mass sum h A and energy sum (g h^2/2 + |m|^2/(2h)) A
+ * (eq 5.1) in double precision, fixed summation order; out holds 2 doubles. */
+fv_status fv_sphere_totals(fv_sphere *s, double *out);
+
+void fv_sphere_destroy(fv_sphere *s);
 
 #ifdef __cplusplus
 }

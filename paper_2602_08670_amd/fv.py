@@ -45,6 +45,19 @@ def make_config(eqn=FV_SWE, prec=FV_F32, nx=64, ny=64, bc_x=FV_BC_PERIODIC, bc_y
                      lx, ly, cfl, dt_fixed, g, gamma, h_ref)
 
 
+class fv_sphere_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("prec", ctypes.c_int32), ("n", ctypes.c_int32),
+                ("flux", ctypes.c_int32), ("recon", ctypes.c_int32), ("rk_stages", ctypes.c_int32),
+                ("reserved0", ctypes.c_int32), ("pad", ctypes.c_int32), ("cfl", ctypes.c_double),
+                ("dt_fixed", ctypes.c_double), ("g", ctypes.c_double), ("omega", ctypes.c_double)]
+
+
+def make_sphere_config(n, prec=FV_F32, flux=FV_FLUX_HLLE, recon=FV_RECON_MINMOD, rk_stages=2, cfl=0.4,
+                       dt_fixed=0.0, g=1.0, omega=0.0) -> fv_sphere_config:
+    return fv_sphere_config(ctypes.sizeof(fv_sphere_config), prec, n, flux, recon, rk_stages, 0, 0, cfl, dt_fixed,
+                            g, omega)
+
+
 class fv_run_info(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("steps", ctypes.c_int64), ("inadmissible", ctypes.c_int32),
                 ("reserved", ctypes.c_int32)]
@@ -72,7 +85,7 @@ class fv_server_config(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("max_solves", ctypes.c_int32),
                 ("steps_per_round", ctypes.c_int32), ("direct", ctypes.c_int32), ("max_items", ctypes.c_uint64),
                 ("model", ctypes.c_void_p), ("learned_split", ctypes.c_int32), ("learned_layered", ctypes.c_int32),
-                ("act_pixels", ctypes.c_uint64)]
+                ("act_pixels", ctypes.c_uint64), ("max_bypass", ctypes.c_int32), ("reserved0", ctypes.c_int32)]
 
 
 class fv_request(ctypes.Structure):
@@ -84,7 +97,7 @@ class fv_request(ctypes.Structure):
 
 
 class fv_request_info(ctypes.Structure):
-    _fields_ = [("state", ctypes.c_int32), ("pad", ctypes.c_int32), ("steps_done", ctypes.c_int64),
+    _fields_ = [("state", ctypes.c_int32), ("rounds_queued", ctypes.c_int32), ("steps_done", ctypes.c_int64),
                 ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double), ("t_done", ctypes.c_double),
                 ("sim_time", ctypes.c_double), ("fallback_faces", ctypes.c_int64), ("redone_steps", ctypes.c_int64)]
 
@@ -135,6 +148,13 @@ def _load():
         "fv_face_fluxes": ([vp, vp, vp], st),
         "fv_destroy": ([vp], None),
         "fv_noalloc_bytes": ([cp], ctypes.c_size_t),
+        "fv_sphere_workspace_bytes": ([ctypes.POINTER(fv_sphere_config)], ctypes.c_size_t),
+        "fv_sphere_init": ([ctypes.POINTER(fv_sphere_config), vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], st),
+        "fv_sphere_run": ([vp, i64], st),
+        "fv_sphere_time": ([vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)], st),
+        "fv_sphere_centres": ([vp, vp], st),
+        "fv_sphere_totals": ([vp, ctypes.POINTER(ctypes.c_double)], st),
+        "fv_sphere_destroy": ([vp], None),
         "fv_run_noalloc": ([cp, vp, vp, i64, vp, vp], st),
         "fv_model_param_count": ([], ctypes.c_size_t),
         "fv_model_workspace_bytes": ([ctypes.POINTER(fv_model_desc)], ctypes.c_size_t),
@@ -250,6 +270,43 @@ def fv_face_fluxes(h, fx_ptr: int, fy_ptr: int):
 
 def fv_destroy(h):
     lib.fv_destroy(h)
+
+
+def fv_sphere_workspace_bytes(cfg: fv_sphere_config) -> int:
+    n = lib.fv_sphere_workspace_bytes(ctypes.byref(cfg))
+    if n == 0:
+        raise FvError(FV_E_INVALID, lib.fv_last_error().decode())
+    return n
+
+
+def fv_sphere_init(cfg: fv_sphere_config, q_ptr: int, ws_ptr: int, ws_bytes: int, stream: int = 0):
+    h = ctypes.c_void_p()
+    _check(lib.fv_sphere_init(ctypes.byref(cfg), q_ptr, ws_ptr, ws_bytes, stream, ctypes.byref(h)))
+    return h
+
+
+def fv_sphere_run(h, nsteps: int):
+    _check(lib.fv_sphere_run(h, int(nsteps)))
+
+
+def fv_sphere_time(h):
+    t, n = ctypes.c_double(), ctypes.c_int64()
+    _check(lib.fv_sphere_time(h, ctypes.byref(t), ctypes.byref(n)))
+    return t.value, n.value
+
+
+def fv_sphere_centres(h, dst_ptr: int):
+    _check(lib.fv_sphere_centres(h, dst_ptr))
+
+
+def fv_sphere_totals(h) -> np.ndarray:
+    out = (ctypes.c_double * 2)()
+    _check(lib.fv_sphere_totals(h, out))
+    return np.array(out[:])
+
+
+def fv_sphere_destroy(h):
+    lib.fv_sphere_destroy(h)
 
 
 def fv_noalloc_bytes(cfg: fv_config) -> int:
@@ -473,7 +530,8 @@ class Server:
 
     def __init__(self, pool_bytes: int, max_solves: int = 1024, steps_per_round: int = 24,
                  max_items: int = 1 << 18, device="cuda", stream=None, model=None, direct=False,
-                 learned_split: int = 0, learned_layered: int = 0, act_pixels: int | None = None):
+                 learned_split: int = 0, learned_layered: int = 0, act_pixels: int | None = None,
+                 max_bypass: int = 0):
         """direct: launch every kernel of a round directly instead of replaying
         the round's captured graph (same results).  learned_split: network
         tiles in a round's first step from which the round runs the network
@@ -482,7 +540,9 @@ class Server:
         network pass runs layer by layer (0: the library's default, -1:
         never); act_pixels: cells of its activation scratch, 128 bytes each
         out of the pool (None: with a model, an eighth of the pool up to 64 Mi
-        cells; without, none)."""
+        cells; without, none).  max_bypass: rounds a queued request may go
+        without fitting before nothing behind it is admitted (0: the
+        library's default, -1: never)."""
         import torch
 
         self.model = model  # kept alive while the server runs
@@ -492,7 +552,7 @@ class Server:
             act_pixels = min(pool_bytes // 8 // 128, 1 << 26) if model is not None else 0
         self.cfg = fv_server_config(ctypes.sizeof(fv_server_config), max_solves, steps_per_round,
                                     1 if direct else 0, max_items, None if model is None else model.h,
-                                    int(learned_split), int(learned_layered), int(act_pixels))
+                                    int(learned_split), int(learned_layered), int(act_pixels), int(max_bypass), 0)
         # zero-filled: the pool's pages are mapped here rather than by the
         # first rounds that reach them
         self.pool = torch.zeros(pool_bytes, dtype=torch.uint8, device=device)
@@ -681,6 +741,58 @@ class Solver:
     def close(self):
         if self.h is not None:
             fv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SphereSolver:
+    """Shallow water on the sphere: state and workspace are torch CUDA tensors."""
+
+    def __init__(self, q0, device="cuda", stream=None, **cfg_kw):
+        import torch
+
+        q0 = np.asarray(q0)
+        assert q0.ndim == 3 and q0.shape[0] == 4 and q0.shape[2] == 2 * q0.shape[1], q0.shape
+        self.cfg = make_sphere_config(q0.shape[1], **cfg_kw)
+        self.dtype = torch.float64 if self.cfg.prec == FV_F64 else torch.float32
+        self.device = torch.device(device)
+        self.q = torch.tensor(q0, dtype=self.dtype, device=self.device).contiguous()
+        nbytes = fv_sphere_workspace_bytes(self.cfg)
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.h = fv_sphere_init(self.cfg, self.q.data_ptr(), self.ws.data_ptr(), nbytes, self.stream.cuda_stream)
+
+    def run(self, nsteps: int):
+        fv_sphere_run(self.h, nsteps)
+
+    def time(self):
+        return fv_sphere_time(self.h)
+
+    def totals(self) -> np.ndarray:
+        return fv_sphere_totals(self.h)
+
+    def centres(self) -> np.ndarray:
+        import torch
+
+        n = self.cfg.n
+        out = torch.empty((3, n, 2 * n), dtype=self.dtype, device=self.device)
+        fv_sphere_centres(self.h, out.data_ptr())
+        return out.double().cpu().numpy()
+
+    def state(self) -> np.ndarray:
+        import torch
+
+        torch.cuda.synchronize(self.device)
+        return self.q.double().cpu().numpy()
+
+    def close(self):
+        if self.h is not None:
+            fv_sphere_destroy(self.h)
             self.h = None
 
     def __del__(self):
