@@ -49,6 +49,8 @@ struct Req {
     size_t q_off, s1_off, bed_off, ctl_off, rates_off;
     size_t s2_off, z_off, small_off;  // learned requests
     int64_t fallback_faces = 0, redone_steps = 0;
+    int rounds_queued = 0;  // rounds this request stayed queued
+    int unfit = 0;          // rounds it did not fit (admission ageing)
     int nvar() const { return r.eqn == FV_EULER ? 4 : 3; }
     bool learned() const { return r.learned != 0; }
 };
@@ -184,7 +186,16 @@ fv_status validate(const fv_server_config *c)
     if (c->direct != 0 && c->direct != 1) return fail(FV_E_INVALID, "direct must be 0 or 1");
     if (c->learned_split < 0 || c->learned_layered < -1) return fail(FV_E_INVALID, "learned_split < 0 or learned_layered < -1");
     if (c->act_pixels > ((uint64_t)1 << 34)) return fail(FV_E_INVALID, "act_pixels above 2^34");
+    if (c->max_bypass < -1) return fail(FV_E_INVALID, "max_bypass %d < -1", c->max_bypass);
+    if (c->reserved0 != 0) return fail(FV_E_INVALID, "reserved0 must be 0");
     return FV_OK;
+}
+
+// reference-depth reductions of a round's admissions: the totals partials,
+// then one block of 8 doubles of output per solve slot
+size_t scratch_bytes(const fv_server_config *c)
+{
+    return (size_t)fvk::TOTALS_MAX_BLOCKS * 5 * 8 + (size_t)c->max_solves * 8 * sizeof(double);
 }
 
 // learned solves: one list per step, one item per active learned solve
@@ -195,7 +206,7 @@ size_t overhead(const fv_server_config *c)
     size_t o = align256(sizeof(fvk::BatchSolve) * c->max_solves);
     o += align256(items_capacity(c) * sizeof(fvk::WorkItem));
     o += align256((size_t)c->steps_per_round * 2 * HDR * sizeof(int));
-    o += align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * 8 + 256);
+    o += align256(scratch_bytes(c));
     o += align256(sizeof(cnn::LSolve) * c->max_solves);
     o += align256(litems_capacity(c) * sizeof(cnn::LItem));
     o += align256((size_t)c->steps_per_round * LHDR * sizeof(int));
@@ -492,7 +503,7 @@ fv_status fv_server_create(const fv_server_config *cfg, void *pool, size_t pool_
     s->items_off = align256(sizeof(fvk::BatchSolve) * cfg->max_solves);
     s->nitems_off = s->items_off + align256(items_capacity(cfg) * sizeof(fvk::WorkItem));
     s->scratch_off = s->nitems_off + align256((size_t)cfg->steps_per_round * 2 * HDR * sizeof(int));
-    s->ltab_off = s->scratch_off + align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * 8 + 256);
+    s->ltab_off = s->scratch_off + align256(scratch_bytes(cfg));
     s->litems_off = s->ltab_off + align256(sizeof(cnn::LSolve) * cfg->max_solves);
     s->lnitems_off = s->litems_off + align256(litems_capacity(cfg) * sizeof(cnn::LItem));
     s->act_off = s->lnitems_off + align256((size_t)cfg->steps_per_round * LHDR * sizeof(int));
@@ -565,8 +576,12 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
     if (!s) return fail(FV_E_INVALID, "server is NULL");
     const int K = s->cfg.steps_per_round;
     char *P = s->pool;
-    // ---- admission (FIFO, later requests may pass one that does not fit)
+    // ---- admission (FIFO, later requests may pass one that does not fit,
+    // unless it has not fitted for max_bypass rounds: then nothing behind it
+    // is admitted until it is)
     const double ta0 = s->now();
+    const int max_bypass = s->cfg.max_bypass == 0 ? 8 : s->cfg.max_bypass;
+    bool blocked = false;
     std::vector<Req *> admitted, need_h0;
     // tiles per launch of each kind (plain SWE, Euler, learned network pass,
     // learned stage): a request is admitted only while its launches stay
@@ -585,6 +600,11 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
     for (Req *q : s->active) kind_tiles(q, tiles);
     for (auto it = s->queue.begin(); it != s->queue.end();) {
         Req *q = *it;
+        if (blocked) {
+            q->rounds_queued++;
+            ++it;
+            continue;
+        }
         size_t off;
         uint64_t after[4] = {tiles[0], tiles[1], tiles[2], tiles[3]};
         kind_tiles(q, after);
@@ -603,27 +623,37 @@ fv_status fv_server_round(fv_server *s, int32_t *n_active, int32_t *n_queued)
             s->active.push_back(q);
             it = s->queue.erase(it);
         } else {
+            q->rounds_queued++;
+            if (max_bypass > 0 && ++q->unfit >= max_bypass) blocked = true;
             ++it;
         }
     }
     hipError_t e = hipSuccess;
     if (!need_h0.empty()) {
-        // reference depth = mean initial depth, as fv_init computes it
-        double *out = (double *)(P + s->scratch_off);
-        double *partials = out + 8;
-        for (Req *q : need_h0) {
+        // reference depth = mean initial depth, as fv_init computes it: the
+        // round's reductions are enqueued back to back (each into its own
+        // output block; they share the partials, in stream order), read back
+        // with one copy and one synchronisation
+        double *partials = (double *)(P + s->scratch_off);
+        double *outs = partials + (size_t)fvk::TOTALS_MAX_BLOCKS * 5;
+        for (size_t k = 0; k < need_h0.size() && e == hipSuccess; k++) {
+            const Req *q = need_h0[k];
             fvk::StageDesc sd{};
             sd.prec = 0;
             sd.eqn = FV_SWE;
             sd.nx = sd.ny = q->r.n;
             sd.rdx = sd.rdy = q->r.n / side(q->r);
             sd.g = q->r.g;
-            e = fvk::launch_totals(sd, P + q->q_off, partials, fvk::TOTALS_MAX_BLOCKS, out, s->stream);
-            double tot[4];
-            if (e == hipSuccess) e = hipMemcpyAsync(tot, out, sizeof tot, hipMemcpyDeviceToHost, s->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
-            if (e != hipSuccess) return hip_fail(e, "reference depth");
-            const double h0 = tot[0] / (side(q->r) * side(q->r));  // mean depth = mass / area
+            e = fvk::launch_totals(sd, P + q->q_off, partials, fvk::TOTALS_MAX_BLOCKS, outs + 8 * k, s->stream);
+        }
+        std::vector<double> tot(8 * need_h0.size());
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(tot.data(), outs, tot.size() * sizeof(double), hipMemcpyDeviceToHost, s->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        if (e != hipSuccess) return hip_fail(e, "reference depth");
+        for (size_t k = 0; k < need_h0.size(); k++) {
+            const Req *q = need_h0[k];
+            const double h0 = tot[8 * k] / (side(q->r) * side(q->r));  // mean depth = mass / area
             if (q->learned()) s->h_ltab[q->slot].h0 = (float)h0;
             else s->h_tab[q->slot].h0 = h0;
         }
@@ -811,7 +841,7 @@ fv_status fv_server_info(fv_server *s, int64_t id, fv_request_info *info)
     if (it == s->reqs.end()) return fail(FV_E_INVALID, "unknown request %lld", (long long)id);
     const Req &q = *it->second;
     info->state = q.state;
-    info->pad = 0;
+    info->rounds_queued = q.rounds_queued;
     info->steps_done = q.done_steps;
     info->t_submit = q.t_submit;
     info->t_admit = q.t_admit;

@@ -97,6 +97,46 @@ def test_admission_by_memory_and_late_arrivals(fv):
     srv.close()
 
 
+@pytest.mark.parametrize("max_bypass", [3, -1])
+def test_admission_ageing_bounds_the_wait_of_a_large_request(fv, max_bypass):
+    """A pool of about four 64^2 solves; four small solves finishing at
+    staggered rounds, then a 128^2 solve (about three small ones), then a
+    stream of small ones.  With plain first fit every freed hole goes to the
+    next small request and the large one waits until the stream runs dry;
+    with ageing (max_bypass 3) nothing is admitted behind it once it has not
+    fitted for 3 rounds, so it runs after at most 3 rounds plus the
+    remaining rounds of the solves already running."""
+    import ctypes
+
+    qs, bs = make_req("swe", 64, 11)
+    ql, bl = make_req("swe", 128, 12)
+    small = fv.Server.request_bytes(fv.make_request(qs, 8, bed=bs)[0])
+    large = fv.Server.request_bytes(fv.make_request(ql, 8, bed=bl)[0])
+    K = 8
+    ov = fv.lib.fv_server_pool_overhead(fv.fv_server_config(ctypes.sizeof(fv.fv_server_config), 64, K, 0, 1 << 14))
+    assert 2 * small < large < 4 * small
+    srv = fv.Server(ov + 4 * small + 65536, max_solves=64, steps_per_round=K, max_items=1 << 14,
+                    max_bypass=max_bypass)
+    first = [srv.submit(qs, K * (k + 1), bed=bs) for k in range(4)]
+    big = srv.submit(ql, K, bed=bl)
+    stream = [srv.submit(qs, 4 * K, bed=bs) for _ in range(24)]
+    rounds = 0
+    while srv.round() != (0, 0):
+        rounds += 1
+        assert rounds < 400
+    inf = srv.info(big)
+    waits = [srv.info(r).rounds_queued for r in stream]
+    print(f"[serve ageing] max_bypass {max_bypass}: large request queued {inf.rounds_queued} rounds, "
+          f"small ones up to {max(waits)}; {rounds} rounds", flush=True)
+    assert inf.state == 2 and inf.steps_done == K
+    assert all(srv.info(r).state == 2 for r in first + stream)
+    if max_bypass > 0:
+        assert inf.rounds_queued <= max_bypass + 4 + 1
+    else:
+        assert inf.rounds_queued >= 15
+    srv.close()
+
+
 def test_request_larger_than_pool_rejected(fv):
     q, b = make_req("swe", 512, 1)
     srv = fv.Server(4 << 20, max_solves=4, steps_per_round=4, max_items=1 << 12)
