@@ -139,6 +139,42 @@ def random_smooth_swe(n: int, seed: int = 0, humps: int | None = None, periodic:
     return q
 
 
+def random_smooth_euler(n: int, seed: int = 0, humps: int | None = None, gamma: float = GAMMA) -> np.ndarray:
+    """Periodic smooth Euler state for the learned Euler step: a uniform
+    drift (u, v) ~ U[-0.5, 0.5]^2 carrying K humps (K ~ U{1..4} unless
+    given) of density and pressure, each hump with amplitudes +-U[0.05, 0.2]
+    (density) and +-U[0.05, 0.2] (pressure) over rho = p = 1 (both stay
+    >= 0.2), width w ~ U[0.005, 0.02] in exp(-r^2 / w), centre ~ U[0,1]^2,
+    distance measured periodically.  Draw order: u, v, then per hump: density amplitude
+    magnitude and sign, pressure amplitude magnitude and sign, width,
+    centre.  Returns (rho, rho u, rho v, E)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u, v = rng.uniform(-0.5, 0.5, size=2)
+    k = int(rng.integers(1, 5)) if humps is None else humps
+    x = centres(n)
+    X, Y = np.meshgrid(x, x, indexing="xy")
+    rho = np.ones((n, n))
+    p = np.ones((n, n))
+    for _ in range(k):
+        ar = rng.uniform(0.05, 0.2) * (1.0 if rng.uniform() < 0.5 else -1.0)
+        ap = rng.uniform(0.05, 0.2) * (1.0 if rng.uniform() < 0.5 else -1.0)
+        w = rng.uniform(0.005, 0.02)
+        cx, cy = rng.uniform(0.0, 1.0, size=2)
+        dx = np.abs(X - cx)
+        dy = np.abs(Y - cy)
+        dx = np.minimum(dx, 1.0 - dx)
+        dy = np.minimum(dy, 1.0 - dy)
+        e = np.exp(-(dx * dx + dy * dy) / w)
+        rho += ar * e
+        p += ap * e
+    q = np.zeros((4, n, n))
+    q[0] = rho
+    q[1] = rho * u
+    q[2] = rho * v
+    q[3] = p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)
+    return q
+
+
 def uniform_state(n: int, h: float = 1.0, u: float = 0.0, v: float = 0.0) -> np.ndarray:
     q = np.zeros((3, n, n))
     q[0] = h
