@@ -5,10 +5,14 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product library never loads it and
 shares no code with it.  The classic solver is plain double-precision C
 (``fv_oracle.c``, loaded through ctypes); the learned path lives in
-``learned.py`` (double-precision PyTorch CPU operations).
+``learned.py`` (planar shallow water) and ``learned_euler.py`` (the Euler
+system), both double-precision PyTorch CPU operations; the spherical
+shallow-water solver is plain C (``sphere_oracle.c``, wrapped by
+``sphere.py``).
 
 Each function states the thesis passage it follows ("A Machine Learning
-accelerated geophysical fluid solver": sections 2.3 and 2.5, eq 2.3-2.28).
+accelerated geophysical fluid solver": sections 2.3-2.5, 3.3, 5.3, 6.2,
+eq 2.3-2.28, 3.1-3.2).
 """
 from __future__ import annotations
 
