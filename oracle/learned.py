@@ -200,11 +200,12 @@ def rusanov(hl, ml, tl, hr, mr, tr, g):
 FLUXES = {"hlle": hlle, "rusanov": rusanov}
 
 
-def rhs(q: torch.Tensor, alpha, dx: float, dy: float, g: float = 9.81, flux: str = "hlle", blend: bool = False):
+def rhs(q: torch.Tensor, alpha, dx: float, dy: float, g: float = 9.81, flux: str = "hlle", blend: bool = False,
+        limiter=None):
     """Spatial operator L(q) with learned face states (alpha given) or the
     plain MINMOD states (alpha None).  blend (learned only): each face's flux
     is the flux-limiter blend of section 2.5.3 (second approach), see
-    blend_flux.  Returns (L, per-solve number of face sides that fell back to
+    blend_flux (limiter: its frozen-limiter / tape argument).  Returns (L, per-solve number of face sides that fell back to
     MINMOD)."""
     fn = FLUXES[flux]
     L = torch.zeros_like(q)
@@ -225,7 +226,7 @@ def rhs(q: torch.Tensor, alpha, dx: float, dy: float, g: float = 9.81, flux: str
         Fc[0], Fc[nm], Fc[tm] = F
         Fc = torch.stack(Fc, dim=1)  # flux through face i+1/2, Cartesian order
         if blend and alpha is not None:
-            Fc = blend_flux(q, Fc, dim, nm, tm, fn, g)
+            Fc = blend_flux(q, Fc, dim, nm, tm, fn, g, limiter)
         L = L - (Fc - _shift(Fc, -1, dim)) / d
     return L, nfb
 
@@ -249,16 +250,33 @@ def limiter_minmod(a: torch.Tensor, b: torch.Tensor) -> torch.Tensor:
     return torch.clamp(r, 0.0, 1.0)
 
 
-def blend_flux(q, F_high, dim, nm, tm, fn, g):
+def blend_flux(q, F_high, dim, nm, tm, fn, g, limiter=None):
     """Blended flux of every face i+1/2 along dim (Cartesian order, like
     F_high): the low-resolution flux is the numerical flux of the cell
-    averages q_i and q_{i+1}."""
+    averages q_i and q_{i+1}.
+
+    limiter: None (phi differentiated like every other operation), or a
+    dict for training: {"frozen": True} treats phi as a constant in the
+    gradient (the frozen-limiter adjoint: d phi / d q ~ 1 / (q_{i+1} - q_i)
+    is unbounded where successive differences vanish, as on a flat
+    background, and overflows there in single precision); with a "tape"
+    list and "replay" False every phi is appended to the tape, with
+    "replay" True the phis are taken from the tape in order instead (so a
+    finite difference can hold them fixed)."""
     qa, qb = q, _shift(q, 1, dim)
     Fl = fn(qa[:, 0], qa[:, nm], qa[:, tm], qb[:, 0], qb[:, nm], qb[:, tm], g)
     F_low = [None, None, None]
     F_low[0], F_low[nm], F_low[tm] = Fl
     F_low = torch.stack(F_low, dim=1)
-    phi = limiter_minmod(q - _shift(q, -1, dim), _shift(q, 1, dim) - q)
+    if limiter is not None and limiter.get("replay"):
+        phi = limiter["tape"][limiter["pos"]]
+        limiter["pos"] += 1
+    else:
+        phi = limiter_minmod(q - _shift(q, -1, dim), _shift(q, 1, dim) - q)
+        if limiter is not None and limiter.get("frozen"):
+            phi = phi.detach()
+        if limiter is not None and "tape" in limiter:
+            limiter["tape"].append(phi.detach())
     return F_low - phi * (F_low - F_high)
 
 
@@ -270,23 +288,23 @@ def plain_step(q, dt, dx, dy, g=9.81, flux="hlle"):
     return 0.5 * q + 0.5 * (q1 + dt * L1)
 
 
-def learned_step(params, q, dt, dx, dy, g=9.81, flux="hlle", order=1, round_bf16=True, blend=False):
+def learned_step(params, q, dt, dx, dy, g=9.81, flux="hlle", order=1, round_bf16=True, blend=False, limiter=None):
     """One Heun step of the learned scheme (blend: with the flux-limiter blend
-    of its face fluxes, see blend_flux).  The network runs on the input of
+    of its face fluxes, see blend_flux and its limiter argument).  The network runs on the input of
     each stage.  Returns (q_next, stats) with stats = dict(fallback_faces,
     redone = per-solve flags of steps redone with the plain scheme).  Face
     sides of the second stage are not counted for a solve whose first stage
     was already inadmissible (its step is redone either way)."""
     P = projector(order)
     a0 = coefficients(cnn(params, q, round_bf16), P)
-    L0, f0 = rhs(q, a0, dx, dy, g, flux, blend)
+    L0, f0 = rhs(q, a0, dx, dy, g, flux, blend, limiter)
     q1 = q + dt * L0
     bad1 = (q1[:, 0] <= 0).flatten(1).any(dim=1)
     # a solve whose first stage is already inadmissible is redone; evaluate the
     # second stage on a safe copy so nothing non-finite enters the graph
     q1s = torch.where(bad1[:, None, None, None], q, q1)
     a1 = coefficients(cnn(params, q1s, round_bf16), P)
-    L1, f1 = rhs(q1s, a1, dx, dy, g, flux, blend)
+    L1, f1 = rhs(q1s, a1, dx, dy, g, flux, blend, limiter)
     q2 = 0.5 * q + 0.5 * (q1s + dt * L1)
     bad = bad1 | (q2[:, 0] <= 0).flatten(1).any(dim=1)
     if bool(bad.any()):
@@ -378,11 +396,15 @@ def direct_step(params, q, dt, dx, dy, g=9.81, flux="hlle", round_bf16=True):
 
 
 def rollout_loss(params, q0, targets, dt, dx, dy, scale, g=9.81, flux="hlle", round_bf16=True, direct=False,
-                 blend=False):
+                 blend=False, limiter=None):
     """eq 2.28: sum over t = 1..T of the MSE between the learned rollout and
     the reference targets (B, T, 3, H, W); variable v is divided by scale[v].
     direct: the rollout of the direct face-state scheme instead; blend: of the
-    learned scheme with the flux-limiter blend of its face fluxes."""
+    learned scheme with the flux-limiter blend of its face fluxes, trained
+    with the limiter frozen in the gradient (blend_flux) unless a limiter
+    dict is given."""
+    if blend and limiter is None:
+        limiter = {"frozen": True}
     q = q0
     loss = torch.zeros((), dtype=F64)
     s = torch.as_tensor(scale, dtype=F64)[None, :, None, None]
@@ -390,7 +412,7 @@ def rollout_loss(params, q0, targets, dt, dx, dy, scale, g=9.81, flux="hlle", ro
         if direct:
             q, _ = direct_step(params, q, dt, dx, dy, g, flux, round_bf16=round_bf16)
         else:
-            q, _ = learned_step(params, q, dt, dx, dy, g, flux, round_bf16=round_bf16, blend=blend)
+            q, _ = learned_step(params, q, dt, dx, dy, g, flux, round_bf16=round_bf16, blend=blend, limiter=limiter)
         loss = loss + (((q - targets[:, t]) / s) ** 2).mean()
     return loss
 

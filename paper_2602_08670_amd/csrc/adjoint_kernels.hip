@@ -44,22 +44,17 @@ struct AdjArgs {
 // Flux-limiter blend of one face (section 2.5.3, second approach), per
 // conserved variable v: F_v = (1 - phi_v) F_low,v + phi_v F_high,v with phi_v
 // the MINMOD limiter of r = a / b, a = q_i - q_{i-1}, b = q_{i+1} - q_i at the
-// face's low-index cell (stencil entries 1, 2, 3), as in the forward.  Where
-// phi_v = a / b its derivatives with respect to those entries are
-// (-1/b, 1/b + a/b^2, -a/b^2); where it is 0 or 1 (the branch taken) they
-// vanish.
-__device__ __forceinline__ void blend_limiter(const float (*st)[6], float *phi, float (*dphi)[3])
+// face's low-index cell, as in the forward.  The adjoint freezes phi (the
+// frozen-limiter adjoint): its derivative, of order 1 / b, is unbounded
+// where successive differences vanish and overflows on a flat background.
+__device__ __forceinline__ void blend_limiter(const float (*st)[6], float *phi)
 {
 #pragma unroll
     for (int v = 0; v < 3; v++) {
         const float a = st[v][2] - st[v][1], b = st[v][3] - st[v][2];
         const bool same = (a > 0.f && b > 0.f) || (a < 0.f && b < 0.f);
         const bool frac = same && __builtin_fabsf(a) < __builtin_fabsf(b);
-        const float ib = frac ? 1.f / b : 0.f, r = a * ib;
-        phi[v] = frac ? r : (same ? 1.f : 0.f);
-        dphi[v][0] = -ib;
-        dphi[v][1] = ib + r * ib;
-        dphi[v][2] = -r * ib;
+        phi[v] = frac ? a / b : (same ? 1.f : 0.f);
     }
 }
 
@@ -103,10 +98,9 @@ __device__ __forceinline__ void minmod_right(const float *c, float &val, float *
 // face writes the owner's high-side and the neighbour's low-side channels of
 // dz (each written by exactly one face).
 // BL: the learned face flux is blended with the flux of the two cell
-// averages by the flux limiter (blend_limiter): the learned path receives
-// phi g_F, the cell averages of the face (stencil entries 2 and 3) the
-// low-resolution flux's Jacobian times (1 - phi) g_F, and entries 1..3 the
-// limiter's derivative times g_F (F_high - F_low).
+// averages by the flux limiter (blend_limiter, phi frozen): the learned path
+// receives phi g_F and the cell averages of the face (stencil entries 2 and
+// 3) the low-resolution flux's Jacobian times (1 - phi) g_F.
 template <int FLUX, bool DIR, bool BL = false>
 __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
 {
@@ -237,14 +231,14 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
         float gF[3];
 #pragma unroll
         for (int c = 0; c < 3; c++) gF[c] = a.wscale * rd * (go[c * plane + nb] - go[c * plane + cell]);
-        // blend: the learned flux's share of the adjoint, and the adjoints of
-        // the low-resolution flux's states and of the limiter's stencil entries
-        float gH[3], gLo[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}}, gLim[3][3] = {};
+        // blend: the learned flux's share of the adjoint and the adjoint of
+        // the low-resolution flux's states (phi frozen)
+        float gH[3], gLo[2][3] = {{0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
 #pragma unroll
         for (int c = 0; c < 3; c++) gH[c] = gF[c];
         if (BL && learned) {
-            float phi[3], dphi[3][3];
-            blend_limiter(st, phi, dphi);
+            float phi[3];
+            blend_limiter(st, phi);
             D cl[3], cr[3];
 #pragma unroll
             for (int v = 0; v < 3; v++) {
@@ -268,9 +262,6 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
                     gLo[0][v] += gl * Flo[c].d[v];
                     gLo[1][v] += gl * Flo[c].d[3 + v];
                 }
-                const float gp = gF[c] * (Fc[c].v - Flo[c].v);
-#pragma unroll
-                for (int k = 0; k < 3; k++) gLim[c][k] = gp * dphi[c][k];
             }
         }
         float gQ[2][3];
@@ -299,7 +290,6 @@ __global__ __launch_bounds__(256) void adj_face_kernel(AdjArgs a)
                 if (BL) {
                     if (k == 2) co[v * 6 + k] += gLo[0][v];
                     if (k == 3) co[v * 6 + k] += gLo[1][v];
-                    if (k >= 1 && k <= 3) co[v * 6 + k] += gLim[v][k - 1];
                 }
             }
 #pragma unroll

@@ -8,14 +8,10 @@ BF16), the oracle in double precision with bfloat16 rounding passed
 straight through, so the gradients agree to a few bfloat16 ulps per
 operation: cosine similarity >= 0.999 and relative L2 <= 1e-2.
 
-With the flux-limiter blend, d loss / d q0 also runs through the limiter
-phi = (q_i - q_{i-1}) / (q_{i+1} - q_i), whose derivative grows like one over
-the local difference: wherever a field is nearly flat the input gradient is
-ill-conditioned, in the oracle too (perturbing the initial state by FP32
-rounding moves its double-precision input gradient by several percent).
-The blend cases therefore use states whose three fields all vary across the
-grid, keep the parameter-gradient bounds, and bound the input-gradient error
-by three times that measured sensitivity of the oracle (and 1e-2)."""
+The flux-limiter blend is trained with the limiter frozen in the gradient
+(its derivative, of order one over the local difference, overflows on a flat
+background): the blend cases use the same data as the others, flat
+background included, and the same bounds."""
 import numpy as np
 import pytest
 import torch
@@ -64,20 +60,6 @@ def cos(a, b):
     return float(np.dot(a, b) / (np.linalg.norm(a) * np.linalg.norm(b)))
 
 
-def batch_varying(n, B, seed0, ny=None):
-    """The states of batch() plus waves in every field (depth along x + 2y,
-    hu along x and y, hv along x - y and 2y), so that no field is flat."""
-    q = np.stack([I.random_smooth_swe(n, seed=seed0 + b) for b in range(B)])
-    x = (np.arange(n) + 0.5) / n
-    X, Y = np.meshgrid(x, x, indexing="xy")
-    q[:, 0] += 0.03 * np.sin(2 * np.pi * (X + 2 * Y))[None]
-    q[:, 1] = (0.02 * np.sin(2 * np.pi * X) + 0.01 * np.cos(2 * np.pi * Y))[None]
-    q[:, 2] = (0.015 * np.cos(2 * np.pi * (X - Y)) + 0.01 * np.sin(4 * np.pi * Y))[None]
-    if ny is not None:
-        q = q[:, :, :ny].copy()
-    return q.astype(np.float32)
-
-
 def batch(n, B, seed0, ny=None):
     """B smooth states on an n x n grid; with ny < n the first ny rows (the
     periodic seam then carries a jump)."""
@@ -98,10 +80,10 @@ def test_gradients_match_oracle(fv, L, flux, ny, nx, direct, blend):
     scheme (section 5.3: the adjoint passes each side's gradient to its own
     cell and to its own cell's channels of the network output) and the
     learned scheme with the flux-limiter blend (section 2.5.3, second
-    approach: through the limiter's branch and the low-resolution flux)."""
+    approach: through the low-resolution flux, the limiter frozen)."""
     B, T, dt = 2, 2, 1.2e-3 * 32 / nx
     p = params(L, 21)
-    q0 = batch_varying(nx, B, 40, ny) if blend else batch(nx, B, 40, ny)
+    q0 = batch(nx, B, 40, ny)
     # targets: the plain scheme from slightly perturbed states (non-zero loss)
     with torch.no_grad():
         tg, qq = [], torch.tensor(q0.astype(np.float64)) * 1.002
@@ -135,18 +117,8 @@ def test_gradients_match_oracle(fv, L, flux, ny, nx, direct, blend):
           f"q0 cos {cq:.6f} rel {relq:.2e}; stats {stats}", flush=True)
     assert abs(loss - lo.item()) <= 1e-3 * lo.item()
     assert c >= 0.999 and rel <= 1e-2
-    if blend:
-        # the oracle's own input-gradient change under an FP32-rounding-size
-        # perturbation of the initial state
-        rng = np.random.default_rng(3)
-        qp = torch.tensor(q0.astype(np.float64) * (1 + 6e-8 * rng.standard_normal(q0.shape)), requires_grad=True)
-        lp = L.rollout_loss(p, qp, tg, dt, 1 / nx, 1 / ny, scale, flux=flux, blend=True)
-        gqp = torch.autograd.grad(lp, [qp])[0].numpy()
-        floor = np.linalg.norm(gqp - gq_or) / np.linalg.norm(gq_or)
-        print(f"[grad] blend input-gradient sensitivity of the oracle {floor:.2e}", flush=True)
-        assert relq <= max(3.0 * floor, 1e-2) and cq >= 0.95
-    else:
-        assert cq >= 0.999 and relq <= 1e-2
+    assert np.all(np.isfinite(g_gpu)) and np.all(np.isfinite(gq_gpu))
+    assert cq >= 0.999 and relq <= 1e-2
     # per layer: the weight gradient of every layer is right (not only the large ones)
     off = 0
     for l, (w, b) in enumerate(zip(gw[:5], gw[5:10])):
