@@ -301,6 +301,128 @@ fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_lea
  * fv_learned_step, whose counters it shares. */
 fv_status fv_blend_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats);
 
+/* ------------------------------------------------------------------------
+ * Learned stencil coefficients for the Euler equations.  Thesis section 6.2
+ * names a data-driven Euler discretisation with positive density and energy
+ * as future work; this is the construction of section 2.5.3 (fourth
+ * approach) on the system of section 4.2, q = (rho, rho u, rho v, E),
+ * p = (gamma - 1)(E - |m|^2 / 2 rho):
+ *   - network 4 -> 32 -> 32 -> 32 -> 32 -> 96 (3x3 convolutions, periodic
+ *     padding, ReLU; BF16 weights and activations on MFMA, FP32
+ *     accumulation); per cell and axis the left and right state
+ *     coefficients of the cell's high face for the four variables, raw
+ *     channel ((axis*2 + side)*4 + var)*6 + k; alpha = Fromm base + P z per
+ *     group of six (exact for linear data at order 1);
+ *   - positivity: a learned face state with rho <= 0, p <= 0 or a non-finite
+ *     value takes its MINMOD state (the cell average where MINMOD itself is
+ *     inadmissible), counted per face side; a stage that leaves a cell with
+ *     rho <= 0 or p <= 0 makes that solve redo its step with the plain
+ *     MINMOD scheme;
+ *   - HLLE or Rusanov in the face's normal frame, Heun at a fixed step,
+ *     periodic domain; B solves of one size per object.
+ * Master parameters (FP32, caller-owned, fv_euler_net_param_count() floats):
+ * W_l[co][ci][ky][kx] then b_l, layer by layer.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    uint32_t struct_size;     /* sizeof(fv_euler_learned_config) */
+    int32_t B;                /* solves */
+    int32_t nx, ny;           /* periodic grid, nx % 16 == 0, ny >= 4 */
+    int32_t flux;             /* FV_FLUX_HLLE | FV_FLUX_RUSANOV */
+    int32_t order;            /* constraint order 0 or 1 */
+    double lx, ly;            /* domain side lengths */
+    double gamma;             /* ratio of specific heats, > 1 */
+    double dt;                /* the fixed step, > 0 */
+    float mean[4], inv_std[4]; /* input normalisation per variable */
+} fv_euler_learned_config;
+
+typedef struct fv_euler_learned fv_euler_learned;
+
+/* Number of FP32 master parameters (56672). */
+size_t fv_euler_net_param_count(void);
+
+/* Device bytes of the workspace: packed weights, two BF16 activation
+ * buffers, the raw coefficients, two stage buffers, per-solve flags and
+ * counters. */
+size_t fv_euler_learned_workspace_bytes(const fv_euler_learned_config *cfg);
+
+/* Create over caller-owned device memory: params (read now and by
+ * fv_euler_learned_update) and workspace (256-byte aligned, >=
+ * fv_euler_learned_workspace_bytes); work is enqueued on stream.  Packs
+ * the weights and clears the counters (async).  FV_E_INVALID for a bad
+ * configuration, FV_E_NOMEM for a small workspace. */
+fv_status fv_euler_learned_create(const fv_euler_learned_config *cfg, const float *params, void *workspace,
+                                  size_t workspace_bytes, void *stream, fv_euler_learned **out);
+
+/* Re-pack the weights after the master parameters changed (async). */
+fv_status fv_euler_learned_update(fv_euler_learned *e);
+
+/* Raw coefficients z (device [B][ny][nx][96] FP32, written) of the states
+ * q (device [B][4][ny][nx] FP32) (async). */
+fv_status fv_euler_learned_forward(fv_euler_learned *e, const float *q, float *z);
+
+/* nsteps learned Heun steps of the B solves in q (device [B][4][ny][nx]
+ * FP32, updated in place) (async).  A solve whose plain redo is still
+ * inadmissible is frozen at that state and reported by
+ * fv_euler_learned_stats. */
+fv_status fv_euler_learned_step(fv_euler_learned *e, float *q, int64_t nsteps);
+
+/* Synchronise the stream and copy the per-solve counters since creation
+ * (host arrays of B entries, each nullable): face sides that fell back,
+ * steps redone with the plain scheme, frozen flags.  FV_E_INADMISSIBLE if
+ * any solve is frozen. */
+fv_status fv_euler_learned_stats(fv_euler_learned *e, int64_t *fallback_faces, int64_t *redone_steps,
+                                 int32_t *frozen);
+
+void fv_euler_learned_destroy(fv_euler_learned *e);
+
+/* Training of the Euler network with the unrolled loss of eq 2.28 (the
+ * planar trainer's construction): T learned Heun steps at a fixed step from
+ * the initial states, kept with their activations and coefficients; loss =
+ * sum over t of the MSE against targets, variable v divided by scale[v];
+ * the reverse pass runs the Heun adjoint, the finite-volume adjoint (Euler
+ * flux Jacobians of the branch taken by forward-mode duals, MINMOD
+ * derivative on fallback sides, plain adjoint for redone steps) and the
+ * network's BF16 MFMA backward.  Gradient reductions in a fixed order. */
+typedef struct {
+    uint32_t struct_size;  /* sizeof(fv_euler_train_config) */
+    int32_t B;             /* windows per batch */
+    int32_t nx, ny;        /* periodic grid, nx % 16 == 0, ny >= 4 */
+    int32_t T;             /* largest number of unrolled steps */
+    int32_t flux;          /* FV_FLUX_HLLE | FV_FLUX_RUSANOV */
+    double lx, ly, gamma, dt;
+    float scale[4];        /* loss scale of rho, rho u, rho v, E */
+    float lr, beta1, beta2, eps; /* Adam */
+} fv_euler_train_config;
+
+typedef struct fv_euler_trainer fv_euler_trainer;
+
+size_t fv_euler_train_workspace_bytes(const fv_euler_train_config *cfg);
+
+/* net: its master parameters are trained in place (Adam re-packs its
+ * weights) and its stream is used; grads, adam_m, adam_v: device FP32
+ * vectors of fv_euler_net_param_count() entries (caller-owned, Adam moments
+ * zeroed by the caller); workspace 256-byte aligned. */
+fv_status fv_euler_train_create(const fv_euler_train_config *cfg, fv_euler_learned *net, float *grads,
+                                float *adam_m, float *adam_v, void *workspace, size_t workspace_bytes,
+                                fv_euler_trainer **out);
+
+/* Loss and gradients (grads overwritten) of one batch: q0 device
+ * [B][4][ny][nx], targets device [T][B][4][ny][nx], 1 <= T <= cfg T.
+ * Synchronises; loss and, when not NULL, the summed counters of the
+ * forward rollout are returned. */
+fv_status fv_euler_train_step(fv_euler_trainer *tr, const float *q0, const float *targets, int T, double *loss,
+                              fv_learned_stats *stats);
+
+/* d loss / d q0 of the last step (device [B][4][ny][nx]); synchronises. */
+fv_status fv_euler_train_input_grad(fv_euler_trainer *tr, float *dst);
+
+/* One Adam update of the net's master parameters from grads, then re-pack. */
+fv_status fv_euler_adam_step(fv_euler_trainer *tr);
+
+fv_status fv_euler_train_set_lr(fv_euler_trainer *tr, float lr);
+
+void fv_euler_train_destroy(fv_euler_trainer *tr);
+
 /* Message of the last failing call on this thread ("" if none). */
 const char *fv_last_error(void);
 

@@ -10,7 +10,8 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfv.so")
 
 SOURCES = ["fv_kernels.hip", "cnn_kernels.hip", "learned_kernels.hip", "adjoint_kernels.hip", "train_kernels.hip",
-           "sphere_kernels.hip", "fv_api.cpp", "train_api.cpp", "serve_api.cpp", "sphere_api.cpp"]
+           "sphere_kernels.hip", "euler_learned_kernels.hip", "fv_api.cpp", "train_api.cpp", "serve_api.cpp",
+           "sphere_api.cpp", "euler_learned_api.cpp"]
 
 # Packed FP32 instructions are disabled for all device code.
 HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",

@@ -187,7 +187,7 @@ hipError_t launch_finish(int *bad, unsigned long long *redone, int *record, int 
 // loss_acc += sum((pred - tgt)/s_v)^2 / N over the batch (N = B*3*ny*nx,
 // FP64 fixed-order reduction) and G += 2 (pred - tgt) / (s_v^2 N).
 hipError_t launch_loss(const float *pred, const float *tgt, const float *scale3, int B, int nx, int ny, float *G,
-                       double *partials, int max_blocks, double *loss_acc, hipStream_t st);
+                       double *partials, int max_blocks, double *loss_acc, hipStream_t st, int nvar = 3);
 hipError_t launch_scale(float *out, const float *in, float a, size_t n, hipStream_t st);
 hipError_t launch_adam(float *p, const float *g, float *m, float *v, size_t n, float lr, float b1, float b2,
                        float eps, float bc1, float bc2, hipStream_t st);
@@ -229,6 +229,45 @@ size_t backward_scratch_bytes(int B, int nx, int ny);
 hipError_t launch_backward(const void *packed, const Norm &nrm, const float *q, int B, int nx, int ny,
                            void *const acts[4], const void *dz, float *dq, float *grads, void *scratch,
                            hipStream_t st);
+
+// ------------------------------------------------------------------------
+// Network of the learned Euler step (the same stack on the four conserved
+// variables): 4 -> 32 -> 32 -> 32 -> 32 -> 96, z channel
+// ((axis*2 + side)*4 + var)*6 + k.  Master layout as the planar network's
+// (W_l[co][ci][ky][kx] then b_l, layer by layer; 56 672 floats).  Packed:
+//   layer 0  : [32 co][64 k]          k = tap*4 + ci (k >= 36 zero)
+//   layer 1-3: [9 tap][32 co][32 ci]  (as the planar network)
+//   layer 4  : [9 tap][96 co][32 ci]
+//   biases FP32 (32, 32, 32, 32, 96);
+// and the transposed, tap-flipped copies of the input-gradient
+// convolutions: layer 0 [9][16 ci (4 used)][32 co], layers 1-3
+// [9][32 ci][32 co], layer 4 [9][32 ci][96 co].
+constexpr int E_CIN = 4, E_COUT = 96;
+constexpr int E_NPARAM = (32 * 4 * 9 + 32) + 3 * (32 * 32 * 9 + 32) + (96 * 32 * 9 + 96);
+static_assert(E_NPARAM == 56672, "Euler network parameter count");
+struct EPacked {
+    size_t w[NL], wt[NL], b[NL], bytes;
+};
+EPacked euler_packed_layout();
+struct ENorm {
+    float mean[4], inv_std[4];
+};
+hipError_t launch_pack_euler(const float *master, void *packed, hipStream_t st);
+// Forward of B solves [B][4][ny][nx] (nx % 16 == 0): act0, act1 are two
+// activation buffers [B][ny][nx][32] BF16 (ping-pong), z [B][ny][nx][96] FP32.
+hipError_t launch_forward_euler(const void *packed, const ENorm &nrm, const float *q, int B, int nx, int ny,
+                                void *act0, void *act1, float *z, hipStream_t st);
+// The same forward keeping every layer's activation (acts[0..3], each
+// [B][ny][nx][32] BF16) for the backward.
+hipError_t launch_forward_euler_keep(const void *packed, const ENorm &nrm, const float *q, int B, int nx, int ny,
+                                     void *const acts[4], float *z, hipStream_t st);
+// Backward of the Euler network: grads (master layout) += d loss / d theta,
+// dq ([B][4][ny][nx]) += d loss / d q, given dz (BF16 [p][96]) and the
+// activations of launch_forward_euler_keep.
+size_t backward_scratch_bytes_euler(int B, int nx, int ny);
+hipError_t launch_backward_euler(const void *packed, const ENorm &nrm, const float *q, int B, int nx, int ny,
+                                 void *const acts[4], const void *dz, float *dq, float *grads, void *scratch,
+                                 hipStream_t st);
 
 // Projector onto the null space of the moment conditions of the given order
 // (exactness for cell averages of polynomials of degree <= order) and Fromm's

@@ -245,7 +245,9 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const float *q, const b
 // EPI 0: forward hidden layer, + bias, ReLU, BF16 [p][32];
 // EPI 1: forward last layer, + bias, FP32 [p][72] (NT = 5);
 // EPI 2: input gradient of a hidden layer, times the ReLU mask of the
-//        previous activation (act > 0), BF16 [p][32].
+//        previous activation (act > 0), BF16 [p][32];
+// EPI 3: forward last layer of the Euler network, + bias, FP32 [p][96]
+//        (NT = 6).
 template <int KB, int NT, int R>
 struct HaloShape {
     static constexpr int CG = KB * 32, OCT = CG / 8;     // channels, 16-byte octets per pixel
@@ -342,6 +344,11 @@ __global__ __launch_bounds__(256) void conv_halo_kernel(const bf16 *in, const bf
                     for (int i = 0; i < 4; i++) o[i] = acc[r][t][i] + bias[co0 + i];
                     *(floatx4 *)((float *)out + p * 72 + co0) = o;
                 }
+            } else if (EPI == 3) {
+                floatx4 o;
+#pragma unroll
+                for (int i = 0; i < 4; i++) o[i] = acc[r][t][i] + bias[co0 + i];
+                *(floatx4 *)((float *)out + p * E_COUT + co0) = o;
             } else {
                 const bf16x4 m = *(const bf16x4 *)(mask + p * 32 + co0);
                 bf16x4 o;
@@ -529,6 +536,227 @@ hipError_t launch_forward(const void *packed, const Norm &nrm, const float *q, i
                              nullptr, acts[l], B, nx, ny, st);
     launch_halo<1, 5, 1>((const bf16 *)acts[3], (const bf16 *)(P + pk.w[4]), (const float *)(P + pk.b[4]), nullptr,
                          (void *)z, B, nx, ny, st);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------- Euler network pass
+EPacked euler_packed_layout()
+{
+    EPacked p;
+    size_t off = 0;
+    p.w[0] = off;
+    off = al256(off + 32 * 64 * 2);
+    for (int l = 1; l < 4; l++) {
+        p.w[l] = off;
+        off = al256(off + 9 * 32 * 32 * 2);
+    }
+    p.w[4] = off;
+    off = al256(off + 9 * E_COUT * 32 * 2);
+    p.wt[0] = off;  // [9][16 ci (4 used)][32 co]
+    off = al256(off + 9 * 16 * 32 * 2);
+    for (int l = 1; l < 4; l++) {
+        p.wt[l] = off;  // [9][32 ci][32 co]
+        off = al256(off + 9 * 32 * 32 * 2);
+    }
+    p.wt[4] = off;  // [9][32 ci][96 co]
+    off = al256(off + 9 * 32 * E_COUT * 2);
+    for (int l = 0; l < NL; l++) {
+        p.b[l] = off;
+        off = al256(off + (l == 4 ? E_COUT : 32) * 4);
+    }
+    p.bytes = off;
+    return p;
+}
+
+// Master offsets of the Euler network (W_l then b_l).
+struct EMaster {
+    int w[NL], b[NL];
+};
+static EMaster euler_master()
+{
+    static const int ci[NL] = {E_CIN, 32, 32, 32, 32}, co[NL] = {32, 32, 32, 32, E_COUT};
+    EMaster m;
+    int off = 0;
+    for (int l = 0; l < NL; l++) {
+        m.w[l] = off;
+        off += co[l] * ci[l] * 9;
+        m.b[l] = off;
+        off += co[l];
+    }
+    return m;
+}
+
+// Element e of the packed buffer's sections: layer 0 [32][64], layers 1-3
+// [9][32][32], layer 4 [9][96][32], the transposed tap-flipped copies
+// (layer 0 [9][16][32], layers 1-3 [9][32][32], layer 4 [9][32][96]), then
+// the biases 4 x 32 + 96.
+__global__ void pack_euler_kernel(const float *M, char *P, EPacked p, EMaster m, int total)
+{
+    constexpr int n0 = 32 * 64, n1 = 9 * 32 * 32, n4 = 9 * E_COUT * 32, t0 = 9 * 16 * 32;
+    for (int e0 = blockIdx.x * blockDim.x + threadIdx.x; e0 < total; e0 += gridDim.x * blockDim.x) {
+        int e = e0;
+        if (e >= n0 + 3 * n1 + n4 && e < n0 + 3 * n1 + n4 + t0 + 3 * n1 + n4) {
+            int r = e - (n0 + 3 * n1 + n4);
+            if (r < t0) {  // W'[t][ci][co] = W[co][ci][8 - t], ci < 4
+                const int tap = r / 512, ci = (r / 32) % 16, co = r % 32;
+                const float v = ci < E_CIN ? M[m.w[0] + (co * E_CIN + ci) * 9 + (8 - tap)] : 0.0f;
+                ((bf16 *)(P + p.wt[0]))[r] = (bf16)v;
+                continue;
+            }
+            r -= t0;
+            if (r < 3 * n1) {
+                const int l = 1 + r / n1, rr = r % n1;
+                const int tap = rr / 1024, ci = (rr / 32) % 32, co = rr % 32;
+                ((bf16 *)(P + p.wt[l]))[rr] = (bf16)M[m.w[l] + (co * 32 + ci) * 9 + (8 - tap)];
+                continue;
+            }
+            r -= 3 * n1;
+            const int tap = r / (32 * E_COUT), ci = (r / E_COUT) % 32, co = r % E_COUT;
+            ((bf16 *)(P + p.wt[4]))[r] = (bf16)M[m.w[4] + (co * 32 + ci) * 9 + (8 - tap)];
+            continue;
+        }
+        if (e >= n0 + 3 * n1 + n4) e -= t0 + 3 * n1 + n4;  // past the transposed copies: the biases
+        if (e < n0) {
+            const int co = e / 64, k = e % 64;
+            float v = 0.0f;
+            if (k < 9 * E_CIN) v = M[m.w[0] + (co * E_CIN + k % E_CIN) * 9 + k / E_CIN];
+            ((bf16 *)(P + p.w[0]))[e] = (bf16)v;
+            continue;
+        }
+        e -= n0;
+        if (e < 3 * n1) {
+            const int l = 1 + e / n1, r = e % n1;
+            const int tap = r / 1024, co = (r / 32) % 32, ci = r % 32;
+            ((bf16 *)(P + p.w[l]))[r] = (bf16)M[m.w[l] + (co * 32 + ci) * 9 + tap];
+            continue;
+        }
+        e -= 3 * n1;
+        if (e < n4) {
+            const int tap = e / (E_COUT * 32), co = (e / 32) % E_COUT, ci = e % 32;
+            ((bf16 *)(P + p.w[4]))[e] = (bf16)M[m.w[4] + (co * 32 + ci) * 9 + tap];
+            continue;
+        }
+        e -= n4;
+        const int l = e < 128 ? e / 32 : 4, co = e < 128 ? e % 32 : e - 128;
+        ((float *)(P + p.b[l]))[co] = M[m.b[l] + co];
+    }
+}
+
+hipError_t launch_pack_euler(const float *master, void *packed, hipStream_t st)
+{
+    const int total = 32 * 64 + 3 * 9 * 32 * 32 + 9 * E_COUT * 32 + (9 * 16 * 32 + 3 * 9 * 32 * 32 + 9 * 32 * E_COUT) +
+                      4 * 32 + E_COUT;
+    hipLaunchKernelGGL(pack_euler_kernel, dim3((total + 255) / 256), dim3(256), 0, st, master, (char *)packed,
+                       euler_packed_layout(), euler_master(), total);
+    return hipGetLastError();
+}
+
+// First layer of the Euler network on 16-pixel-wide, 4R-row tiles: the
+// normalised, BF16-rounded input halo ([4][4R + 2][18]) staged in LDS once,
+// K = 36 (tap*4 + ci) padded to two 32-wide K blocks, accumulated in K
+// order; bias, ReLU, BF16 NHWC out [p][32].
+template <int R>
+__global__ __launch_bounds__(256) void conv_first_euler_kernel(const float *q, const bf16 *wp, const float *bias,
+                                                               bf16 *out, int H, int W, ENorm nrm)
+{
+    constexpr int HR = 4 * R + 2, HC = HT + 2;
+    __shared__ bf16x8 s_w[32 * 64 / 8];
+    __shared__ bf16 s_q[E_CIN * HR * HC];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int g = lane >> 4, px = lane & 15;
+    const int b = blockIdx.z, x0 = blockIdx.x * HT, y0 = blockIdx.y * 4 * R;
+    const int hw = H * W;
+    const float *qb = q + (size_t)b * E_CIN * hw;
+    bf16 *act = out + (size_t)b * hw * 32;
+    const bf16x8 *gw = (const bf16x8 *)wp;
+    for (int i = tid; i < 32 * 64 / 8; i += 256) s_w[i] = gw[i];
+    for (int i = tid; i < E_CIN * HR * HC; i += 256) {
+        const int ci = i / (HR * HC), r = i - ci * (HR * HC);
+        const int hr = r / HC, hc = r - hr * HC;
+        int yy = y0 - 1 + hr;
+        yy = yy < 0 ? yy + H : yy % H;
+        const int xx = wrap(x0 - 1 + hc, W);
+        s_q[i] = (bf16)((qb[(size_t)ci * hw + yy * W + xx] - nrm.mean[ci]) * nrm.inv_std[ci]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int rr = 0; rr < R; rr++) {
+        const int ry = wave * R + rr, y = y0 + ry;
+        bf16x8 bx[2];
+#pragma unroll
+        for (int kb = 0; kb < 2; kb++)
+#pragma unroll
+            for (int e = 0; e < 8; e++) {
+                const int k = 32 * kb + 8 * g + e;
+                bf16 v = (bf16)0.0f;
+                if (k < 9 * E_CIN) {
+                    const int tap = k / E_CIN, ci = k - E_CIN * tap;
+                    v = s_q[(ci * HR + ry + tap / 3) * HC + px + tap % 3];
+                }
+                bx[kb][e] = v;
+            }
+        if (y >= H) continue;
+#pragma unroll
+        for (int t = 0; t < 2; t++) {
+            floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 2; kb++)
+                acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[(t * 16 + px) * 8 + kb * 4 + g], bx[kb], acc, 0, 0, 0);
+            const int co0 = 16 * t + 4 * g;
+            bf16x4 o;
+#pragma unroll
+            for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[i] + bias[co0 + i], 0.0f);
+            *(bf16x4 *)(act + ((size_t)y * W + x0 + px) * 32 + co0) = o;
+        }
+    }
+}
+
+hipError_t launch_forward_euler_keep(const void *packed, const ENorm &nrm, const float *q, int B, int nx, int ny,
+                                     void *const acts[4], float *z, hipStream_t st)
+{
+    const EPacked pk = euler_packed_layout();
+    const char *P = (const char *)packed;
+    if (nx % HT) return hipErrorInvalidValue;
+    const int R = halo_rows(B, nx, ny);
+    const dim3 fg = halo_grid(B, nx, ny, R), blk(256);
+    const bf16 *w0 = (const bf16 *)(P + pk.w[0]);
+    const float *b0 = (const float *)(P + pk.b[0]);
+    bf16 *a0 = (bf16 *)acts[0];
+    if (R == 4) hipLaunchKernelGGL(conv_first_euler_kernel<4>, fg, blk, 0, st, q, w0, b0, a0, ny, nx, nrm);
+    else if (R == 2) hipLaunchKernelGGL(conv_first_euler_kernel<2>, fg, blk, 0, st, q, w0, b0, a0, ny, nx, nrm);
+    else hipLaunchKernelGGL(conv_first_euler_kernel<1>, fg, blk, 0, st, q, w0, b0, a0, ny, nx, nrm);
+    for (int l = 1; l < 4; l++)
+        launch_halo<1, 2, 0>((const bf16 *)acts[l - 1], (const bf16 *)(P + pk.w[l]), (const float *)(P + pk.b[l]),
+                             nullptr, acts[l], B, nx, ny, st);
+    launch_halo<1, 6, 3>((const bf16 *)acts[3], (const bf16 *)(P + pk.w[4]), (const float *)(P + pk.b[4]), nullptr,
+                         (void *)z, B, nx, ny, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_forward_euler(const void *packed, const ENorm &nrm, const float *q, int B, int nx, int ny,
+                                void *act0, void *act1, float *z, hipStream_t st)
+{
+    const EPacked pk = euler_packed_layout();
+    const char *P = (const char *)packed;
+    if (nx % HT) return hipErrorInvalidValue;
+    const int R = halo_rows(B, nx, ny);
+    const dim3 fg = halo_grid(B, nx, ny, R), blk(256);
+    const bf16 *w0 = (const bf16 *)(P + pk.w[0]);
+    const float *b0 = (const float *)(P + pk.b[0]);
+    bf16 *a0 = (bf16 *)act0, *a1 = (bf16 *)act1;
+    if (R == 4) hipLaunchKernelGGL(conv_first_euler_kernel<4>, fg, blk, 0, st, q, w0, b0, a0, ny, nx, nrm);
+    else if (R == 2) hipLaunchKernelGGL(conv_first_euler_kernel<2>, fg, blk, 0, st, q, w0, b0, a0, ny, nx, nrm);
+    else hipLaunchKernelGGL(conv_first_euler_kernel<1>, fg, blk, 0, st, q, w0, b0, a0, ny, nx, nrm);
+    bf16 *src = a0, *dst = a1;
+    for (int l = 1; l < 4; l++) {
+        launch_halo<1, 2, 0>(src, (const bf16 *)(P + pk.w[l]), (const float *)(P + pk.b[l]), nullptr, dst, B, nx, ny,
+                             st);
+        bf16 *t = src;
+        src = dst;
+        dst = t;
+    }
+    launch_halo<1, 6, 3>(src, (const bf16 *)(P + pk.w[4]), (const float *)(P + pk.b[4]), nullptr, (void *)z, B, nx,
+                         ny, st);
     return hipGetLastError();
 }
 
@@ -1178,14 +1406,15 @@ namespace cnn {
 
 // Network input as the forward rounds it: x0 = bf16((q - mean) * inv_std),
 // NHWC with 16 channels (3 used) for the layer-0 weight gradient.
-__global__ void x0_kernel(const float *q, bf16 *x0, int B, int H, int W, Norm nrm)
+template <int C, typename NormT>
+__global__ void x0_kernel(const float *q, bf16 *x0, int B, int H, int W, NormT nrm)
 {
     const long hw = (long)H * W, npix = (long)B * hw;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < npix * 16; i += (long)gridDim.x * blockDim.x) {
         long p = i / 16;
         int c = (int)(i - p * 16);
         long b = p / hw, r = p - b * hw;
-        float v = c < 3 ? (q[(b * 3 + c) * hw + r] - nrm.mean[c]) * nrm.inv_std[c] : 0.0f;
+        float v = c < C ? (q[(b * C + c) * hw + r] - nrm.mean[c]) * nrm.inv_std[c] : 0.0f;
         x0[i] = (bf16)v;
     }
 }
@@ -1194,8 +1423,9 @@ __global__ void x0_kernel(const float *q, bf16 *x0, int B, int H, int W, Norm nr
 // transposed, tap-flipped weights (16 output rows, 3 used), one 16-pixel
 // group per wave; adds dq[c] += dx0[c] * inv_std[c] into the FP32 planar
 // state gradient.
+template <int C, typename NormT>
 __global__ __launch_bounds__(256) void conv_dgrad_input_kernel(const bf16 *G, const bf16 *wt, float *dq, int B, int H,
-                                                               int W, Norm nrm)
+                                                               int W, NormT nrm)
 {
     constexpr int WEL = 9 * 16 * 32;
     __shared__ bf16x8 s_w[WEL / 8];
@@ -1222,7 +1452,7 @@ __global__ __launch_bounds__(256) void conv_dgrad_input_kernel(const bf16 *G, co
     }
     if (g == 0) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) dq[((size_t)b * 3 + c) * hw + rem] += acc[c] * nrm.inv_std[c];
+        for (int c = 0; c < C; c++) dq[((size_t)b * C + c) * hw + rem] += acc[c] * nrm.inv_std[c];
     }
 }
 
@@ -1471,10 +1701,61 @@ hipError_t launch_backward(const void *packed, const Norm &nrm, const float *q, 
         nxt = t;
     }
     // layer 0: 3 -> 32 (input rebuilt as the forward rounds it)
-    hipLaunchKernelGGL(x0_kernel, dim3(eg), blk, 0, st, q, x0, B, ny, nx, nrm);
+    hipLaunchKernelGGL((x0_kernel<3, Norm>), dim3(eg), blk, 0, st, q, x0, B, ny, nx, nrm);
     wgrad<32, 2, 16>(cur, x0, B, ny, nx, partial, 32, 3, ml.w[0], ml.b[0], grads, st);
-    hipLaunchKernelGGL(conv_dgrad_input_kernel, cg, blk, 0, st, (const bf16 *)cur, (const bf16 *)(P + pk.wt[0]), dq, B,
-                       ny, nx, nrm);
+    hipLaunchKernelGGL((conv_dgrad_input_kernel<3, Norm>), cg, blk, 0, st, (const bf16 *)cur,
+                       (const bf16 *)(P + pk.wt[0]), dq, B, ny, nx, nrm);
+    return hipGetLastError();
+}
+
+size_t backward_scratch_bytes_euler(int B, int nx, int ny)
+{
+    long npix = (long)B * nx * ny;
+    const dim3 wg = wgrad_grid(B, nx, ny);
+    size_t part = (size_t)wg.x * wg.y * wg.z * WgradShape<6, 32>::PER * 4;
+    return 2 * al256(npix * 32 * 2) + al256(npix * 16 * 2) + al256(part);
+}
+
+// The planar network's backward on the Euler network's shapes: layer 4
+// 32 -> 96 (six co tiles, dz read as three 32-channel K blocks), layer 0
+// 4 -> 32.
+hipError_t launch_backward_euler(const void *packed, const ENorm &nrm, const float *q, int B, int nx, int ny,
+                                 void *const acts[4], const void *dzv, float *dq, float *grads, void *scratch,
+                                 hipStream_t st)
+{
+    const EPacked pk = euler_packed_layout();
+    const EMaster ml = euler_master();
+    const char *P = (const char *)packed;
+    const long npix = (long)B * nx * ny;
+    if (nx % HT) return hipErrorInvalidValue;
+    const bf16 *dz = (const bf16 *)dzv;
+    char *sc = (char *)scratch;
+    bf16 *dA = (bf16 *)sc;
+    sc += al256(npix * 32 * 2);
+    bf16 *dB = (bf16 *)sc;
+    sc += al256(npix * 32 * 2);
+    bf16 *x0 = (bf16 *)sc;
+    sc += al256(npix * 16 * 2);
+    float *partial = (float *)sc;
+    const bf16 *a[4] = {(const bf16 *)acts[0], (const bf16 *)acts[1], (const bf16 *)acts[2], (const bf16 *)acts[3]};
+    unsigned eg = (unsigned)((npix * 16 + 255) / 256);
+    if (eg > 8192) eg = 8192;
+    dim3 cg((unsigned)((npix + 63) / 64)), blk(256);
+
+    wgrad<E_COUT, 6, 32>(dz, a[3], B, ny, nx, partial, E_COUT, 32, ml.w[4], ml.b[4], grads, st);
+    launch_halo<3, 2, 2>(dz, (const bf16 *)(P + pk.wt[4]), nullptr, a[3], (void *)dA, B, nx, ny, st);
+    bf16 *cur = dA, *nxt = dB;
+    for (int l = 3; l >= 1; l--) {
+        wgrad<32, 2, 32>(cur, a[l - 1], B, ny, nx, partial, 32, 32, ml.w[l], ml.b[l], grads, st);
+        launch_halo<1, 2, 2>(cur, (const bf16 *)(P + pk.wt[l]), nullptr, a[l - 1], (void *)nxt, B, nx, ny, st);
+        bf16 *t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    hipLaunchKernelGGL((x0_kernel<E_CIN, ENorm>), dim3(eg), blk, 0, st, q, x0, B, ny, nx, nrm);
+    wgrad<32, 2, 16>(cur, x0, B, ny, nx, partial, 32, E_CIN, ml.w[0], ml.b[0], grads, st);
+    hipLaunchKernelGGL((conv_dgrad_input_kernel<E_CIN, ENorm>), cg, blk, 0, st, (const bf16 *)cur,
+                       (const bf16 *)(P + pk.wt[0]), dq, B, ny, nx, nrm);
     return hipGetLastError();
 }
 

@@ -4,14 +4,14 @@
 namespace cnn {
 
 __global__ __launch_bounds__(256) void loss_kernel(const float *pred, const float *tgt, const float *scale3, int B,
-                                                   int plane, float *G, double *partials)
+                                                   int plane, float *G, double *partials, int nvar)
 {
     __shared__ double s[256];
-    const size_t n = (size_t)B * 3 * plane;
+    const size_t n = (size_t)B * nvar * plane;
     const double inv_n = 1.0 / (double)n;
     double acc = 0.0;
     for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
-        int v = (int)((i / plane) % 3);
+        int v = (int)((i / plane) % nvar);
         float sv = scale3[v];
         float d = pred[i] - tgt[i];
         double r = (double)d / sv;
@@ -44,12 +44,12 @@ __global__ __launch_bounds__(256) void loss_final_kernel(const double *partials,
 }
 
 hipError_t launch_loss(const float *pred, const float *tgt, const float *scale3, int B, int nx, int ny, float *G,
-                       double *partials, int max_blocks, double *loss_acc, hipStream_t st)
+                       double *partials, int max_blocks, double *loss_acc, hipStream_t st, int nvar)
 {
-    size_t n = (size_t)B * 3 * nx * ny;
+    size_t n = (size_t)B * nvar * nx * ny;
     int blocks = (int)((n + 255) / 256);
     if (blocks > max_blocks) blocks = max_blocks;
-    hipLaunchKernelGGL(loss_kernel, dim3(blocks), dim3(256), 0, st, pred, tgt, scale3, B, nx * ny, G, partials);
+    hipLaunchKernelGGL(loss_kernel, dim3(blocks), dim3(256), 0, st, pred, tgt, scale3, B, nx * ny, G, partials, nvar);
     hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, (const double *)partials, blocks, loss_acc);
     return hipGetLastError();
 }

@@ -52,6 +52,34 @@ class fv_sphere_config(ctypes.Structure):
                 ("dt_fixed", ctypes.c_double), ("g", ctypes.c_double), ("omega", ctypes.c_double)]
 
 
+class fv_euler_learned_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("B", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("flux", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("dt", ctypes.c_double), ("mean", ctypes.c_float * 4), ("inv_std", ctypes.c_float * 4)]
+
+
+def make_euler_learned_config(B, nx, ny, dt, flux=FV_FLUX_HLLE, order=1, lx=1.0, ly=1.0, gamma=1.4,
+                              mean=(1.0, 0.0, 0.0, 2.5), inv_std=(8.0, 4.0, 4.0, 2.0)) -> fv_euler_learned_config:
+    return fv_euler_learned_config(ctypes.sizeof(fv_euler_learned_config), B, nx, ny, flux, order, lx, ly, gamma,
+                                   dt, (ctypes.c_float * 4)(*mean), (ctypes.c_float * 4)(*inv_std))
+
+
+class fv_euler_train_config(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("B", ctypes.c_int32), ("nx", ctypes.c_int32),
+                ("ny", ctypes.c_int32), ("T", ctypes.c_int32), ("flux", ctypes.c_int32), ("lx", ctypes.c_double),
+                ("ly", ctypes.c_double), ("gamma", ctypes.c_double), ("dt", ctypes.c_double),
+                ("scale", ctypes.c_float * 4), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+def make_euler_train_config(B, nx, ny, T, dt, flux=FV_FLUX_HLLE, lx=1.0, ly=1.0, gamma=1.4,
+                            scale=(0.1, 0.1, 0.1, 0.2), lr=1e-3, beta1=0.9, beta2=0.999,
+                            eps=1e-8) -> fv_euler_train_config:
+    return fv_euler_train_config(ctypes.sizeof(fv_euler_train_config), B, nx, ny, T, flux, lx, ly, gamma, dt,
+                                 (ctypes.c_float * 4)(*scale), lr, beta1, beta2, eps)
+
+
 def make_sphere_config(n, prec=FV_F32, flux=FV_FLUX_HLLE, recon=FV_RECON_MINMOD, rk_stages=2, cfl=0.4,
                        dt_fixed=0.0, g=1.0, omega=0.0) -> fv_sphere_config:
     return fv_sphere_config(ctypes.sizeof(fv_sphere_config), prec, n, flux, recon, rk_stages, 0, 0, cfl, dt_fixed,
@@ -156,6 +184,24 @@ def _load():
         "fv_sphere_totals": ([vp, ctypes.POINTER(ctypes.c_double)], st),
         "fv_sphere_destroy": ([vp], None),
         "fv_run_noalloc": ([cp, vp, vp, i64, vp, vp], st),
+        "fv_euler_net_param_count": ([], ctypes.c_size_t),
+        "fv_euler_learned_workspace_bytes": ([ctypes.POINTER(fv_euler_learned_config)], ctypes.c_size_t),
+        "fv_euler_learned_create": ([ctypes.POINTER(fv_euler_learned_config), vp, vp, ctypes.c_size_t, vp,
+                                     ctypes.POINTER(vp)], st),
+        "fv_euler_learned_update": ([vp], st),
+        "fv_euler_learned_forward": ([vp, vp, vp], st),
+        "fv_euler_learned_step": ([vp, vp, i64], st),
+        "fv_euler_learned_stats": ([vp, vp, vp, vp], st),
+        "fv_euler_learned_destroy": ([vp], None),
+        "fv_euler_train_workspace_bytes": ([ctypes.POINTER(fv_euler_train_config)], ctypes.c_size_t),
+        "fv_euler_train_create": ([ctypes.POINTER(fv_euler_train_config), vp, vp, vp, vp, vp, ctypes.c_size_t,
+                                   ctypes.POINTER(vp)], st),
+        "fv_euler_train_step": ([vp, vp, vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double),
+                                 ctypes.POINTER(fv_learned_stats)], st),
+        "fv_euler_train_input_grad": ([vp, vp], st),
+        "fv_euler_adam_step": ([vp], st),
+        "fv_euler_train_set_lr": ([vp, ctypes.c_float], st),
+        "fv_euler_train_destroy": ([vp], None),
         "fv_model_param_count": ([], ctypes.c_size_t),
         "fv_model_workspace_bytes": ([ctypes.POINTER(fv_model_desc)], ctypes.c_size_t),
         "fv_model_create": ([ctypes.POINTER(fv_model_desc), vp, vp, ctypes.c_size_t, vp, ctypes.POINTER(vp)], st),
@@ -741,6 +787,124 @@ class Solver:
     def close(self):
         if self.h is not None:
             fv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class EulerLearned:
+    """Learned Euler step over B periodic solves; parameters, workspace and
+    states are torch CUDA tensors (argument marshalling only)."""
+
+    def __init__(self, params, B, nx, ny, dt, device="cuda", stream=None, **cfg_kw):
+        import torch
+
+        self.device = torch.device(device)
+        self.cfg = make_euler_learned_config(B, nx, ny, dt, **cfg_kw)
+        self.params = torch.as_tensor(np.asarray(params, dtype=np.float32), device=self.device).contiguous()
+        assert self.params.numel() == lib.fv_euler_net_param_count()
+        nb = lib.fv_euler_learned_workspace_bytes(ctypes.byref(self.cfg))
+        if nb == 0:
+            raise FvError(-1, lib.fv_last_error().decode())
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = ctypes.c_void_p()
+        _check(lib.fv_euler_learned_create(ctypes.byref(self.cfg), self.params.data_ptr(), self.ws.data_ptr(), nb,
+                                           self.stream.cuda_stream, ctypes.byref(h)))
+        self.h = h
+
+    def update(self):
+        _check(lib.fv_euler_learned_update(self.h))
+
+    def forward(self, q):
+        """Raw coefficients [B, ny, nx, 96] of the states q [B, 4, ny, nx]."""
+        import torch
+
+        c = self.cfg
+        q = q.contiguous()
+        z = torch.empty((c.B, c.ny, c.nx, 96), dtype=torch.float32, device=self.device)
+        _check(lib.fv_euler_learned_forward(self.h, q.data_ptr(), z.data_ptr()))
+        return z
+
+    def step(self, q, nsteps: int):
+        """nsteps learned Heun steps of q [B, 4, ny, nx] (float32, contiguous, in place)."""
+        assert q.is_contiguous()
+        _check(lib.fv_euler_learned_step(self.h, q.data_ptr(), int(nsteps)))
+
+    def stats(self):
+        """(fallback face sides, redone steps, frozen, rc) per solve, numpy arrays;
+        rc is FV_E_INADMISSIBLE when a solve is frozen."""
+        B = self.cfg.B
+        fb, rd = np.zeros(B, dtype=np.int64), np.zeros(B, dtype=np.int64)
+        fr = np.zeros(B, dtype=np.int32)
+        rc = lib.fv_euler_learned_stats(self.h, fb.ctypes.data, rd.ctypes.data, fr.ctypes.data)
+        return fb, rd, fr, rc
+
+    def close(self):
+        if self.h is not None:
+            lib.fv_euler_learned_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class EulerTrainer:
+    """Unrolled-loss training of an EulerLearned network (its master
+    parameters are updated in place by adam())."""
+
+    def __init__(self, net: EulerLearned, cfg: fv_euler_train_config):
+        import torch
+
+        self.net = net
+        self.cfg = cfg
+        n = lib.fv_euler_net_param_count()
+        self.grads = torch.zeros(n, dtype=torch.float32, device=net.device)
+        self.m = torch.zeros(n, dtype=torch.float32, device=net.device)
+        self.v = torch.zeros(n, dtype=torch.float32, device=net.device)
+        nb = lib.fv_euler_train_workspace_bytes(ctypes.byref(cfg))
+        if nb == 0:
+            raise FvError(-1, lib.fv_last_error().decode())
+        self.ws = torch.empty(nb, dtype=torch.uint8, device=net.device)
+        h = ctypes.c_void_p()
+        _check(lib.fv_euler_train_create(ctypes.byref(cfg), net.h, self.grads.data_ptr(), self.m.data_ptr(),
+                                         self.v.data_ptr(), self.ws.data_ptr(), nb, ctypes.byref(h)))
+        self.h = h
+
+    def step(self, q0, targets):
+        """q0 [B,4,ny,nx], targets [T,B,4,ny,nx] (torch CUDA float32) -> (loss, (fallbacks, redone))."""
+        q0 = q0.contiguous()
+        targets = targets.contiguous()
+        loss = ctypes.c_double()
+        stats = fv_learned_stats()
+        _check(lib.fv_euler_train_step(self.h, q0.data_ptr(), targets.data_ptr(), targets.shape[0],
+                                       ctypes.byref(loss), ctypes.byref(stats)))
+        return loss.value, (stats.fallback_faces, stats.redone_steps)
+
+    def input_grad(self):
+        import torch
+
+        c = self.cfg
+        out = torch.empty((c.B, 4, c.ny, c.nx), dtype=torch.float32, device=self.net.device)
+        _check(lib.fv_euler_train_input_grad(self.h, out.data_ptr()))
+        return out
+
+    def adam(self):
+        _check(lib.fv_euler_adam_step(self.h))
+
+    def set_lr(self, lr: float):
+        _check(lib.fv_euler_train_set_lr(self.h, lr))
+
+    def close(self):
+        if self.h is not None:
+            lib.fv_euler_train_destroy(self.h)
             self.h = None
 
     def __del__(self):
