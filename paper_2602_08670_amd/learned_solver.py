@@ -88,9 +88,13 @@ def validation_set(seeds, n_fine, factor, n_coarse_steps):
     return {"q0": q0, "ref": ref, "steps": n_coarse_steps}
 
 
-def rollout_error(model, val, dt_c, direct: bool = False, blend: bool = False) -> float:
-    """Mean relative L2 depth error of the learned rollouts of a validation
-    set (the model's packed weights re-packed from its master parameters)."""
+def rollout_error(model, val, dt_c, direct: bool = False, blend: bool = False):
+    """Score of the learned rollouts of a validation set (the model's packed
+    weights re-packed from its master parameters): (number of rollouts that
+    blew up -- non-finite, or a relative L2 depth error above 1 --, median
+    relative L2 depth error).  Lower is better, compared as a tuple: a
+    single hard validation state does not decide between two stable
+    iterates, a blow-up always does."""
     model.update()
     errs = []
     for q0, ref in zip(val["q0"], val["ref"]):
@@ -99,7 +103,8 @@ def rollout_error(model, val, dt_c, direct: bool = False, blend: bool = False) -
         out = s.state()
         s.close()
         errs.append(rel_l2(out[0], ref[0]) if np.all(np.isfinite(out)) else float("inf"))
-    return float(np.mean(errs))
+    errs = np.asarray(errs)
+    return int(np.sum(~(errs <= 1.0))), float(np.median(errs))
 
 
 def train(data, iters: int, B: int = 16, T_max: int = 8, lr: float = 1e-3, seed: int = 0, log_every: int = 0,
@@ -111,11 +116,11 @@ def train(data, iters: int, B: int = 16, T_max: int = 8, lr: float = 1e-3, seed:
     the scheme with the flux-limiter blend of its face fluxes is trained.
 
     val (validation_set): every val_every iterations, and for the initial
-    parameters, the learned rollout of the validation states is compared with
-    their reference; training returns the parameters with the smallest
-    validation error.  The unrolled loss only sees windows of T_max steps,
-    so parameters that fit those windows can still drift over a long
-    rollout; selecting on the long rollout keeps such iterates out."""
+    parameters, the learned rollout of the validation states is scored
+    (rollout_error); training returns the parameters with the best score.
+    The unrolled loss only sees windows of T_max steps, so parameters that
+    fit those windows can still drift over a long rollout; selecting on the
+    long rollout keeps such iterates out."""
     import torch
 
     n_traj, S1, _, n, _ = data.shape
@@ -152,7 +157,7 @@ def train(data, iters: int, B: int = 16, T_max: int = 8, lr: float = 1e-3, seed:
     if best is not None:
         model.params.copy_(best[2])
         model.update()
-        model.selected = {"iteration": best[1], "val_rel_l2_h": best[0]}
+        model.selected = {"iteration": best[1], "val_blowups": best[0][0], "val_median_rel_l2_h": best[0][1]}
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     tr.close()
@@ -188,7 +193,7 @@ def graph_replay(launch, total: int, chunk: int, stream):
 
 
 def evaluate(model, seeds, n_fine, factor, n_coarse_steps, plain_sizes=(64, 128, 256, 512), chunk=50,
-             direct: bool = False, blend: bool = False, refs: dict | None = None):
+             direct: bool = False, blend: bool = False, refs: dict | None = None, verbose: bool = False):
     """Errors at the final time of the learned coarse solver and of the plain
     scheme at plain_sizes against the fine reference (block-averaged), and
     graph-replayed time-to-solution of each.  refs: a dict that caches the
@@ -230,6 +235,8 @@ def evaluate(model, seeds, n_fine, factor, n_coarse_steps, plain_sizes=(64, 128,
             errs[f"plain{m}"].append(rel_l2(outm[0], ref[0]))
             hs[f"plain{m}"].append(mean_rel_h(outm[0], ref[0]))
             sp.close()
+        if verbose:
+            print(f"[eval] seed {seed}: " + ", ".join(f"{k} {errs[k][-1]:.3e}" for k in keys), flush=True)
     for k in keys:
         res["cases"][k] = {"rel_l2_h": float(np.mean(errs[k])), "mean_rel_h": float(np.mean(hs[k])),
                            "time_to_solution_s": float(np.median(times[k])), "per_seed_rel_l2_h": errs[k]}
@@ -244,61 +251,73 @@ def main():
     ap.add_argument("--n-fine", type=int, default=2048)
     ap.add_argument("--factor", type=int, default=32)
     ap.add_argument("--train-seeds", type=int, default=40)
-    ap.add_argument("--traj-steps", type=int, default=512)
+    ap.add_argument("--traj-steps", type=int, default=1000,
+                    help="coarse steps of each training trajectory (the evaluation horizon: a network trained on "
+                         "shorter trajectories meets states it never saw and can blow up)")
     ap.add_argument("--iters", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=16)
     ap.add_argument("--T", type=int, default=32, help="unrolled steps of the loss (eq 2.28 uses 32)")
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--lr-final", type=float, default=2e-5, help="end of the cosine schedule (<= 0: constant)")
     ap.add_argument("--eval-seeds", type=int, default=32)
-    ap.add_argument("--val-seeds", type=int, default=4, help="held-out rollouts for checkpoint selection")
-    ap.add_argument("--val-steps", type=int, default=250, help="coarse steps of each validation rollout")
+    ap.add_argument("--val-seeds", type=int, default=8, help="held-out rollouts for checkpoint selection")
+    ap.add_argument("--val-steps", type=int, default=1000, help="coarse steps of each validation rollout")
     ap.add_argument("--val-every", type=int, default=100)
     ap.add_argument("--eval-steps", type=int, default=1000)
     ap.add_argument("--plain-sizes", default="64,128,256,512",
                     help="grid sides of the plain-scheme comparison runs (multiples of the coarse side)")
-    ap.add_argument("--direct", action="store_true",
-                    help="the direct face-state scheme of section 5.3 instead of the stencil coefficients")
+    ap.add_argument("--schemes", default="stencil",
+                    help="comma-separated schemes trained and evaluated on the same data: stencil (the learned "
+                         "stencil coefficients), direct (the direct face states of section 5.3), blend (the "
+                         "stencil coefficients with the flux-limiter blend of section 2.5.3, second approach)")
     ap.add_argument("--eval-blend", action="store_true",
-                    help="also evaluate the trained network with the flux-limiter blend of its face fluxes")
-    ap.add_argument("--blend", action="store_true",
-                    help="train and evaluate the stencil-coefficient scheme with the flux-limiter blend of its face "
-                         "fluxes (section 2.5.3, second approach)")
+                    help="also evaluate the stencil network trained without the blend with the blend")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     plain_sizes = tuple(int(v) for v in a.plain_sizes.split(",") if v)
+    schemes = [x for x in a.schemes.split(",") if x]
+    assert all(x in ("stencil", "direct", "blend") for x in schemes), schemes
     t0 = time.perf_counter()
     data = dataset(range(1000, 1000 + a.train_seeds), a.n_fine, a.factor, a.traj_steps)
     tdata = time.perf_counter() - t0
     print(f"[data] {tuple(data.shape)} in {tdata:.1f} s", flush=True)
     val = validation_set(range(3000, 3000 + a.val_seeds), a.n_fine, a.factor, a.val_steps) if a.val_seeds else None
-    model, hist, wall = train(data, a.iters, a.batch, a.T, a.lr, log_every=100, n_fine=a.n_fine, factor=a.factor,
-                              lr_final=a.lr_final if a.lr_final > 0 else None, direct=a.direct, val=val,
-                              val_every=a.val_every, blend=a.blend)
-    print(f"[train] {a.iters} iterations in {wall:.1f} s, loss {hist[0][2]:.3e} -> {hist[-1][2]:.3e}; "
-          f"selected {getattr(model, 'selected', None)}", flush=True)
     refs = {}
-    res = evaluate(model, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps, plain_sizes=plain_sizes,
-                   direct=a.direct, blend=a.blend, refs=refs)
-    print(f"[eval] " + ", ".join(f"{k}: rel L2(h) {v['rel_l2_h']:.3e} in {v['time_to_solution_s'] * 1e3:.1f} ms"
-                                 for k, v in res["cases"].items()), flush=True)
-    untrained = fv.Model(init_params(0), model.desc)
-    res["untrained"] = evaluate(untrained, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps,
-                                plain_sizes=(), direct=a.direct, blend=a.blend, refs=refs)["cases"]["learned"]
-    if a.eval_blend and not a.direct:
-        res["blend"] = evaluate(model, range(5000, 5000 + a.eval_seeds), a.n_fine, a.factor, a.eval_steps,
-                                plain_sizes=(), blend=True, refs=refs)["cases"]["learned"]
-        print(f"[eval] blended: rel L2(h) {res['blend']['rel_l2_h']:.3e} in "
-              f"{res['blend']['time_to_solution_s'] * 1e3:.1f} ms", flush=True)
-    res["scheme"] = ("direct face states" if a.direct else
-                     "stencil coefficients with the flux-limiter blend" if a.blend else "stencil coefficients")
-    res["train"] = {"iters": a.iters, "batch": a.batch, "T": a.T, "wall_s": wall, "data_s": tdata,
-                    "selected": getattr(model, "selected", None), "val_seeds": a.val_seeds, "val_steps": a.val_steps,
-                    "loss_first": hist[0][2], "loss_last": hist[-1][2], "snapshots": int(data.shape[0] * data.shape[1])}
-    print(json.dumps(res, indent=1), flush=True)
+    out = {}
+    eval_seeds = range(5000, 5000 + a.eval_seeds)
+    for k, scheme in enumerate(schemes):
+        direct, blend = scheme == "direct", scheme == "blend"
+        model, hist, wall = train(data, a.iters, a.batch, a.T, a.lr, log_every=100, n_fine=a.n_fine,
+                                  factor=a.factor, lr_final=a.lr_final if a.lr_final > 0 else None, direct=direct,
+                                  val=val, val_every=a.val_every, blend=blend)
+        print(f"[train {scheme}] {a.iters} iterations in {wall:.1f} s, loss {hist[0][2]:.3e} -> {hist[-1][2]:.3e}; "
+              f"selected {getattr(model, 'selected', None)}", flush=True)
+        res = evaluate(model, eval_seeds, a.n_fine, a.factor, a.eval_steps, plain_sizes=plain_sizes if k == 0 else (),
+                       direct=direct, blend=blend, refs=refs, verbose=True)
+        print(f"[eval {scheme}] " + ", ".join(f"{c}: rel L2(h) {v['rel_l2_h']:.3e} in "
+                                             f"{v['time_to_solution_s'] * 1e3:.1f} ms" for c, v in res["cases"].items()),
+              flush=True)
+        untrained = fv.Model(init_params(0), model.desc)
+        res["untrained"] = evaluate(untrained, eval_seeds, a.n_fine, a.factor, a.eval_steps, plain_sizes=(),
+                                    direct=direct, blend=blend, refs=refs)["cases"]["learned"]
+        print(f"[eval {scheme}] untrained: rel L2(h) {res['untrained']['rel_l2_h']:.3e}", flush=True)
+        if a.eval_blend and scheme == "stencil":
+            res["blend"] = evaluate(model, eval_seeds, a.n_fine, a.factor, a.eval_steps, plain_sizes=(), blend=True,
+                                    refs=refs)["cases"]["learned"]
+            print(f"[eval {scheme}] with the blend: rel L2(h) {res['blend']['rel_l2_h']:.3e} in "
+                  f"{res['blend']['time_to_solution_s'] * 1e3:.1f} ms", flush=True)
+        res["scheme"] = {"stencil": "stencil coefficients", "direct": "direct face states",
+                         "blend": "stencil coefficients with the flux-limiter blend"}[scheme]
+        res["train"] = {"iters": a.iters, "batch": a.batch, "T": a.T, "wall_s": wall, "data_s": tdata,
+                        "selected": getattr(model, "selected", None), "val_seeds": a.val_seeds,
+                        "val_steps": a.val_steps, "traj_steps": a.traj_steps, "loss_first": hist[0][2],
+                        "loss_last": hist[-1][2], "snapshots": int(data.shape[0] * data.shape[1])}
+        out[scheme] = res
+        model.close()
+    print(json.dumps(out), flush=True)
     if a.out:
         with open(a.out, "w") as f:
-            json.dump(res, f, indent=1)
+            json.dump(out, f, indent=1)
     torch.cuda.synchronize()
 
 
