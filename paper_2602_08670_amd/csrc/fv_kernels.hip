@@ -6,13 +6,16 @@
 //     synthesised during the load (periodic wrap or wall mirror with the
 //     normal momentum negated).
 //  2. Every x face and y face of the tile is evaluated exactly once
-//     (reconstruction, hydrostatic step, numerical flux) and kept in LDS.
+//     (reconstruction, hydrostatic step, numerical flux), by the lane of its
+//     high-side cell, and stays in registers: a cell's high x face comes from
+//     the next lane by a DPP shift, its high y face from the lane's next row
+//     (faces at a wave's edge go through LDS).
 //  3. Each cell forms the flux divergence (eq 2.9 / eq 2.23), adds the bed
 //     source, combines the Runge-Kutta stage (eq 2.19 / eq 2.20) and writes
 //     its new value.  On the last stage the CFL rate of the new state is
-//     reduced with a wave64 shuffle max, across waves in LDS, then one
-//     atomicMax per workgroup into the device slot read by the next step, so
-//     Delta t never travels through the host.
+//     reduced over the wave with DPP, then one atomicMax per wave into a
+//     device sub-slot read by the next step, so Delta t never travels
+//     through the host.
 #include "fv_device.hpp"
 #include "fv_internal.hpp"
 
