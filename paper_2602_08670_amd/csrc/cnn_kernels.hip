@@ -1302,15 +1302,24 @@ int fused_max_grid()
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&c, conv_learned_batch_kernel<1>, FNW * 64, 0) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&e, conv_learned_batch_kernel<2>, FNW * 64, 0) != hipSuccess)
             return 256;
-        int f = 0, h = 0;
+        int f = 0, h = 0, i = 0, j = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&f, conv_fused_batch_kernel<1>, FNW * 64, 0) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&h, conv_fused_batch_kernel<2>, FNW * 64, 0) != hipSuccess)
+            return 256;
+        // the blended forms (a second numerical flux per face) are launched
+        // with the same cap
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&i, conv_learned_batch_kernel<1, true>, FNW * 64, 0) !=
+                hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&j, conv_learned_batch_kernel<2, true>, FNW * 64, 0) !=
+                hipSuccess)
             return 256;
         int m = a < b ? a : b;
         m = m < c ? m : c;
         m = m < e ? m : e;
         m = m < f ? m : f;
         m = m < h ? m : h;
+        m = m < i ? m : i;
+        m = m < j ? m : j;
         cache[dev] = (m > 0 ? m : 1) * (cus > 0 ? cus : 256);
     }
     return cache[dev];

@@ -116,7 +116,7 @@ def run_server(stream, ics, arr, pool_bytes=24 << 30, steps_per_round=32, max_so
                 break
             time.sleep(max(0.0, arr[nxt] - (time.perf_counter() - t0)))
     wall = time.perf_counter() - t0
-    done, cells = [], 0
+    done, cells, queued = [], 0, []
     fallback = redone = 0
     for i, rid in enumerate(ids):
         inf = srv.info(rid)
@@ -124,10 +124,12 @@ def run_server(stream, ics, arr, pool_bytes=24 << 30, steps_per_round=32, max_so
         kind, n, steps, _ = stream[i]
         cells += n * n * steps
         done.append(inf.t_done - clock_offset)
+        queued.append(inf.rounds_queued)
         fallback += inf.fallback_faces
         redone += inf.redone_steps
     st = srv.stats()
-    run_server.last_stats = {"rounds": st.rounds, "graph_replays": st.graph_replays,
+    run_server.last_stats = {"rounds_queued_max": int(max(queued)), "rounds_queued_p99": float(np.percentile(queued, 99)),
+                             "rounds": st.rounds, "graph_replays": st.graph_replays,
                              "graphs_captured": st.graphs_captured, "grid_updates": st.grid_updates,
                              "layered_rounds": st.layered_rounds,
                              "host_launch_s": st.host_launch_s, "host_wait_s": st.host_wait_s,
