@@ -357,8 +357,16 @@ fv_status fv_euler_learned_create(const fv_euler_learned_config *cfg, const floa
 fv_status fv_euler_learned_update(fv_euler_learned *e);
 
 /* Raw coefficients z (device [B][ny][nx][96] FP32, written) of the states
- * q (device [B][4][ny][nx] FP32) (async). */
+ * q (device [B][4][ny][nx] FP32), layer by layer through the workspace's
+ * activation buffers (async). */
 fv_status fv_euler_learned_forward(fv_euler_learned *e, const float *q, float *z);
+
+/* The same network pass in one launch: each workgroup runs all five layers
+ * on 8 x 8 tiles in LDS (recomputing the halo the 3x3 stack needs); z is
+ * bit-identical to fv_euler_learned_forward's.  Needs nx % 8 == 0 and
+ * ny % 8 == 0 (FV_E_UNSUPPORTED otherwise).  fv_euler_learned_step uses it
+ * on such grids. */
+fv_status fv_euler_learned_forward_tiled(fv_euler_learned *e, const float *q, float *z);
 
 /* nsteps learned Heun steps of the B solves in q (device [B][4][ny][nx]
  * FP32, updated in place) (async).  A solve whose plain redo is still

@@ -257,6 +257,10 @@ hipError_t launch_pack_euler(const float *master, void *packed, hipStream_t st);
 // activation buffers [B][ny][nx][32] BF16 (ping-pong), z [B][ny][nx][96] FP32.
 hipError_t launch_forward_euler(const void *packed, const ENorm &nrm, const float *q, int B, int nx, int ny,
                                 void *act0, void *act1, float *z, hipStream_t st);
+// The same forward in one launch (nx % 8 == 0, ny % 8 == 0): every
+// workgroup runs all five layers on 8 x 8 tiles in LDS; z is bit-identical.
+hipError_t launch_forward_euler_fused(const void *packed, const ENorm &nrm, const float *q, int B, int nx, int ny,
+                                      float *z, hipStream_t st);
 // The same forward keeping every layer's activation (acts[0..3], each
 // [B][ny][nx][32] BF16) for the backward.
 hipError_t launch_forward_euler_keep(const void *packed, const ENorm &nrm, const float *q, int B, int nx, int ny,

@@ -1147,6 +1147,186 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     return s_z;
 }
 
+// ------------------------------------------- Euler network, one launch
+// All five layers of the Euler network (4 -> 32 -> 32 -> 32 -> 32 -> 96) for
+// one FT x FT tile per workgroup pass, as fused_tile does for the planar
+// network: the normalised BF16 input region (FT + 10)^2 of the four
+// variables and every layer's weights staged in LDS, the activations kept in
+// two LDS buffers, layer l computed on the (FT + 2(4 - l))^2 region.  Per
+// output the MFMAs run in the layer-by-layer pass's order (layer 0: K blocks
+// 0, 1; other layers: taps 0..8), with the same bias, ReLU and BF16 rounding,
+// so z is bit-identical to launch_forward_euler's.  Workgroups stride over
+// the B x (H/FT) x (W/FT) tiles, staging the weights once.
+constexpr int EW0 = 32 * 64 / 8, EWH = 9 * 32 * 32 / 8, EW4 = 9 * 6 * 16 * 32 / 8;  // packed octets per layer
+__global__ __launch_bounds__(FNW * 64) void conv_fused_euler_kernel(const float *q, const char *P, EPacked pk,
+                                                                    ENorm nrm, float *z, int B, int H, int W)
+{
+    constexpr int FRI_ = FT + 10, FR0_ = FT + 8;
+    __shared__ bf16 s_in[E_CIN][FRI_ * FRI_];
+    __shared__ bf16x8 s_act[FR0_ * FR0_ * 4 + (FR0_ - 2) * (FR0_ - 2) * 4];
+    __shared__ bf16x8 s_wall[EW0 + 3 * EWH + EW4];
+    bf16x8 *const s_a0 = s_act;
+    bf16x8 *const s_a1 = s_act + FR0_ * FR0_ * 4;
+    const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int g = lane >> 4, px = lane & 15;
+    const size_t hw = (size_t)H * W;
+    const int tx_n = W / FT, ty_n = H / FT, total = B * tx_n * ty_n;
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const bool load_w = tile == (int)blockIdx.x;
+        if (!load_w) __syncthreads();  // the previous tile's LDS reads are done
+        const int b = tile / (tx_n * ty_n);
+        const int rt = tile - b * tx_n * ty_n;
+        const int y0 = (rt / tx_n) * FT, x0 = (rt % tx_n) * FT;
+        const float *qb = q + (size_t)b * E_CIN * hw;
+        float *zb = z + (size_t)b * hw * E_COUT;
+        const int ry0 = y0 - 5, rx0 = x0 - 5;
+        // every global load (input region, weights) before the first LDS store
+        constexpr int NIN = E_CIN * FRI_ * FRI_, TIN = (NIN + FNW * 64 - 1) / (FNW * 64);
+        float xin[TIN];
+#pragma unroll
+        for (int k = 0; k < TIN; k++) {
+            const int i = threadIdx.x + k * FNW * 64;
+            if (i < NIN) {
+                const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
+                const int ry = r / FRI_, rx = r - ry * FRI_;
+                xin[k] = qb[(size_t)ci * hw + (size_t)wrap(ry0 + ry, H) * W + wrap(rx0 + rx, W)];
+            }
+        }
+        Chunks<EW0> c0;
+        Chunks<EWH> c1, c2, c3;
+        Chunks<EW4> c4;
+        if (load_w) {
+            c0.load(P, pk.w[0]);
+            c1.load(P, pk.w[1]);
+            c2.load(P, pk.w[2]);
+            c3.load(P, pk.w[3]);
+            c4.load(P, pk.w[4]);
+        }
+#pragma unroll
+        for (int k = 0; k < TIN; k++) {
+            const int i = threadIdx.x + k * FNW * 64;
+            if (i < NIN) {
+                const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
+                s_in[ci][r] = (bf16)((xin[k] - nrm.mean[ci]) * nrm.inv_std[ci]);
+            }
+        }
+        if (load_w) {
+            c0.store(s_wall);
+            c1.store(s_wall + EW0);
+            c2.store(s_wall + EW0 + EWH);
+            c3.store(s_wall + EW0 + 2 * EWH);
+            c4.store(s_wall + EW0 + 3 * EWH);
+        }
+        __syncthreads();
+        // layer 0 on the FR0_ x FR0_ region: K = 36 (tap*4 + ci) in two blocks
+        {
+            const float *bias = (const float *)(P + pk.b[0]);
+            constexpr int NP0 = FR0_ * FR0_, NG0 = (NP0 + 15) / 16;
+            for (int gi = wave; gi < NG0; gi += FNW) {
+                const int p = gi * 16 + px;
+                const int pc = p < NP0 ? p : 0;
+                const int py = pc / FR0_, pxx = pc - py * FR0_;
+                bf16x8 bx[2];
+#pragma unroll
+                for (int kb = 0; kb < 2; kb++)
+#pragma unroll
+                    for (int e = 0; e < 8; e++) {
+                        const int kk = 32 * kb + 8 * g + e;
+                        bf16 v = (bf16)0.0f;
+                        if (kk < 9 * E_CIN) {
+                            const int tap = kk / E_CIN, ci = kk - E_CIN * tap;
+                            v = s_in[ci][(py + tap / 3) * FRI_ + pxx + tap % 3];
+                        }
+                        bx[kb][e] = v;
+                    }
+#pragma unroll
+                for (int t = 0; t < 2; t++) {
+                    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int kb = 0; kb < 2; kb++)
+                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_wall[(t * 16 + px) * 8 + kb * 4 + g], bx[kb], acc,
+                                                                      0, 0, 0);
+                    if (p < NP0) {
+                        const int co0 = 16 * t + 4 * g;
+                        bf16x4 o;
+#pragma unroll
+                        for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[i] + bias[co0 + i], 0.0f);
+                        *(bf16x4 *)((bf16 *)s_a0 + (size_t)p * 32 + co0) = o;
+                    }
+                }
+            }
+        }
+        // hidden layers 1..3: s_a0 -> s_a1 -> s_a0 -> s_a1
+#pragma unroll
+        for (int l = 1; l < 4; l++) {
+            __syncthreads();
+            const int rin = FR0_ - 2 * (l - 1);
+            const bf16x8 *in = (l & 1) ? s_a0 : s_a1;
+            bf16 *out = (bf16 *)((l & 1) ? s_a1 : s_a0);
+            fused_hidden(in, rin, out, s_wall + EW0 + (l - 1) * EWH, (const float *)(P + pk.b[l]), wave, lane);
+        }
+        __syncthreads();
+        // layer 4: s_a1 (FT + 2)^2 -> z on the tile, wave w < NG: pixel group w
+        // with all six co tiles, each chain in tap order
+        {
+            constexpr int NT = 6, RIN = FT + 2, NPX = FT * FT, NG = (NPX + 15) / 16;
+            static_assert(NG <= FNW, "one pixel group per wave");
+            const bf16x8 *s_w = s_wall + EW0 + 3 * EWH;
+            const float *bias = (const float *)(P + pk.b[4]);
+            if (wave < NG) {  // wave-uniform, a real branch: an MFMA does not honour a partial EXEC
+                floatx4 acc[NT];
+#pragma unroll
+                for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+                const int p = wave * 16 + px;
+                const int py = p / FT, pxx = p - py * FT;
+                const int bo = (py * RIN + pxx) * 4 + g;
+#pragma unroll
+                for (int tap = 0; tap < 9; tap++) {
+                    const bf16x8 bx = s_a1[bo + ((tap / 3) * RIN + tap % 3) * 4];
+#pragma unroll
+                    for (int t = 0; t < NT; t++)
+                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * 4 + g], bx,
+                                                                         acc[t], 0, 0, 0);
+                }
+#pragma unroll
+                for (int t = 0; t < NT; t++) {
+                    const int co0 = 16 * t + 4 * g;
+                    floatx4 o;
+#pragma unroll
+                    for (int i = 0; i < 4; i++) o[i] = acc[t][i] + bias[co0 + i];
+                    *(floatx4 *)(zb + ((size_t)(y0 + py) * W + x0 + pxx) * E_COUT + co0) = o;
+                }
+            }
+        }
+    }
+}
+
+int fused_euler_grid()
+{
+    static int cache[64];
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cache[dev]) {
+        int cus = 0, m = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, conv_fused_euler_kernel, FNW * 64, 0) != hipSuccess)
+            return 256;
+        cache[dev] = (m > 0 ? m : 1) * (cus > 0 ? cus : 256);
+    }
+    return cache[dev];
+}
+
+hipError_t launch_forward_euler_fused(const void *packed, const ENorm &nrm, const float *q, int B, int nx, int ny,
+                                      float *z, hipStream_t st)
+{
+    if (nx % FT || ny % FT) return hipErrorInvalidValue;
+    const int tiles = B * (nx / FT) * (ny / FT);
+    const int cap = fused_euler_grid();
+    hipLaunchKernelGGL(conv_fused_euler_kernel, dim3((unsigned)(tiles < cap ? tiles : cap)), dim3(FNW * 64), 0, st,
+                       q, (const char *)packed, euler_packed_layout(), nrm, z, B, ny, nx);
+    return hipGetLastError();
+}
+
 // ---------------------------------------- network pass + learned stage
 // The learned stage (learned-stage kernels, MODE 0, HLLE) on the FT x FT tile
 // at (x0, y0), in the workgroup that has just computed z on the tile and its

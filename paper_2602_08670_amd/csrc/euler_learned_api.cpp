@@ -137,6 +137,15 @@ fv_status fv_euler_learned_forward(fv_euler_learned *e, const float *q, float *z
     return h == hipSuccess ? FV_OK : hip_fail(h, "Euler network pass");
 }
 
+fv_status fv_euler_learned_forward_tiled(fv_euler_learned *e, const float *q, float *z)
+{
+    if (!e || !q || !z) return fail(FV_E_INVALID, "NULL argument");
+    const fv_euler_learned_config &c = e->cfg;
+    if (c.nx % 8 || c.ny % 8) return fail(FV_E_UNSUPPORTED, "the tiled pass needs nx and ny multiples of 8");
+    hipError_t h = cnn::launch_forward_euler_fused(e->ws + e->L.packed, e->nrm, q, c.B, c.nx, c.ny, z, e->stream);
+    return h == hipSuccess ? FV_OK : hip_fail(h, "Euler network pass");
+}
+
 fv_status fv_euler_learned_step(fv_euler_learned *e, float *q, int64_t nsteps)
 {
     if (!e || !q) return fail(FV_E_INVALID, "NULL argument");
@@ -161,17 +170,21 @@ fv_status fv_euler_learned_step(fv_euler_learned *e, float *q, int64_t nsteps)
     a.pr = e->pr;
     a.z = z;
     hipError_t h = hipSuccess;
+    // the network pass in one launch where the grid is whole 8 x 8 tiles
+    const bool tiled = c.nx % 8 == 0 && c.ny % 8 == 0;
+    auto net = [&](const float *in) {
+        return tiled ? cnn::launch_forward_euler_fused(ws + L.packed, e->nrm, in, c.B, c.nx, c.ny, z, e->stream)
+                     : cnn::launch_forward_euler(ws + L.packed, e->nrm, in, c.B, c.nx, c.ny, ws + L.act0, ws + L.act1,
+                                                 z, e->stream);
+    };
     for (int64_t k = 0; k < nsteps && h == hipSuccess; k++) {
         a.parity = (int)(e->steps_enq & 1);
         // stage 1: S1 = q + dt L(q)
-        h = cnn::launch_forward_euler(ws + L.packed, e->nrm, q, c.B, c.nx, c.ny, ws + L.act0, ws + L.act1, z,
-                                      e->stream);
+        h = net(q);
         a.qs = q; a.q0 = q; a.out = S1; a.a0 = 0.f; a.a1 = 1.f; a.flagbit = 1;
         if (h == hipSuccess) h = eln::stage(0, fl, a, e->stream);
         // stage 2: S2 = q/2 + (S1 + dt L(S1))/2
-        if (h == hipSuccess)
-            h = cnn::launch_forward_euler(ws + L.packed, e->nrm, S1, c.B, c.nx, c.ny, ws + L.act0, ws + L.act1, z,
-                                          e->stream);
+        if (h == hipSuccess) h = net(S1);
         a.qs = S1; a.q0 = q; a.out = S2; a.a0 = 0.5f; a.a1 = 0.5f; a.flagbit = 2;
         if (h == hipSuccess) h = eln::stage(0, fl, a, e->stream);
         // admissible solves commit S2; the others redo the step plainly

@@ -190,6 +190,7 @@ def _load():
                                      ctypes.POINTER(vp)], st),
         "fv_euler_learned_update": ([vp], st),
         "fv_euler_learned_forward": ([vp, vp, vp], st),
+        "fv_euler_learned_forward_tiled": ([vp, vp, vp], st),
         "fv_euler_learned_step": ([vp, vp, i64], st),
         "fv_euler_learned_stats": ([vp, vp, vp, vp], st),
         "fv_euler_learned_destroy": ([vp], None),
@@ -828,6 +829,16 @@ class EulerLearned:
         q = q.contiguous()
         z = torch.empty((c.B, c.ny, c.nx, 96), dtype=torch.float32, device=self.device)
         _check(lib.fv_euler_learned_forward(self.h, q.data_ptr(), z.data_ptr()))
+        return z
+
+    def forward_tiled(self, q):
+        """The same in one launch (nx, ny multiples of 8); bit-identical."""
+        import torch
+
+        c = self.cfg
+        q = q.contiguous()
+        z = torch.empty((c.B, c.ny, c.nx, 96), dtype=torch.float32, device=self.device)
+        _check(lib.fv_euler_learned_forward_tiled(self.h, q.data_ptr(), z.data_ptr()))
         return z
 
     def step(self, q, nsteps: int):

@@ -269,3 +269,20 @@ def test_adam_reduces_loss(fv, E):
     assert bool(torch.isfinite(net.params).all())
     tr.close()
     net.close()
+
+
+@pytest.mark.parametrize("B,ny,nx", [(1, 64, 64), (3, 48, 32), (2, 24, 80)])
+def test_tiled_forward_bitwise_equals_layer_by_layer(fv, E, B, ny, nx):
+    """The one-launch network pass (8 x 8 tiles, halo recomputed in LDS) gives
+    the same bits as the layer-by-layer pass: per output the MFMA order,
+    bias, ReLU and BF16 rounding are the same."""
+    p = oracle_params(E, 8, scale_last=0.3)
+    q = np.stack([I.random_smooth_euler(max(nx, ny), seed=30 + b)[:, :ny, :nx] for b in range(B)]).astype(np.float32)
+    vec = fv.params_to_vector([w.numpy() for w in p["w"]], [b.numpy() for b in p["b"]])
+    net = fv.EulerLearned(vec, B, nx, ny, 1e-3, mean=tuple(p["mean"].tolist()), inv_std=tuple(p["inv_std"].tolist()))
+    qd = torch.tensor(q, device="cuda")
+    z0 = net.forward(qd).cpu().numpy()
+    z1 = net.forward_tiled(qd).cpu().numpy()
+    net.close()
+    print(f"[euler tiled {B}x{ny}x{nx}] max |diff| {np.abs(z0 - z1).max():.3e}", flush=True)
+    assert np.array_equal(z0, z1)
