@@ -149,6 +149,31 @@ def learned_sample(steps, torch, direct=False, blend=False):
     return round(us, 2)
 
 
+def euler_learned_sample(steps, torch):
+    """Latency of one learned Euler (Heun) step on the 64^2 coarse grid of the
+    learned Euler workload: periodic Euler, fixed step = 8 x the 512^2 fine
+    step, one solve, a network with seeded random weights.  HIP events on the
+    network's stream."""
+    from paper_2602_08670_amd import fv, inputs
+    from paper_2602_08670_amd import learned_euler_solver as LE
+
+    rng = np.random.default_rng(0)
+    vec = (rng.standard_normal(fv.lib.fv_euler_net_param_count()) * 0.02).astype(np.float32)
+    net = fv.EulerLearned(vec, 1, 64, 64, LE.fine_dt(512) * 8)
+    q = torch.tensor(inputs.random_smooth_euler(64, seed=5)[None].astype(np.float32), device="cuda")
+    net.step(q, 20)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(net.stream)
+    net.step(q, steps)
+    e1.record(net.stream)
+    torch.cuda.synchronize()
+    us = e0.elapsed_time(e1) * 1e3 / steps
+    net.close()
+    return round(us, 2)
+
+
 def cpu_baseline(n, target_s, euler=False):
     """The oracle on the host cores over a bounded number of steps of the same
     workload (shallow water over the bed, or the Euler quadrants)."""
@@ -234,6 +259,7 @@ def main():
         extra["learned_64_step_us"] = learned_sample(args.learned_steps, torch)
         extra["direct_64_step_us"] = learned_sample(args.learned_steps, torch, direct=True)
         extra["blend_64_step_us"] = learned_sample(args.learned_steps, torch, blend=True)
+        extra["euler_learned_64_step_us"] = euler_learned_sample(args.learned_steps, torch)
 
     if args.serving_requests > 0:
         extra["serving"] = serving_sample(args.serving_requests)

@@ -135,6 +135,16 @@ hipError_t launch_conv_learned(int stage, const void *packed, const Norm &nrm, c
                                int blend = 0);
 hipError_t launch_conv_learned_list(int stage, const void *packed, const Norm &nrm, const Proj &pr,
                                     const LSolve *tab, const LItem *items, const int *list, int wgs, hipStream_t st);
+// One solve's stage (HLLE) in one launch, the solve passed by value: stage 1
+// reads d.q and writes d.s1, stage 2 reads d.s1 and d.q and writes d.s2 (the
+// step's output, kept apart from its input); flags in slot d.flags[parity].
+// Stage 1 with xprev (the previous step's input): when the previous step's
+// slot d.flags[parity ^ 1] is set, the previous step is first redone with the
+// plain scheme from xprev into d.q (counted in d.redone; an inadmissible
+// plain result sets d.fatal).  Stage 2 clears the previous step's slot and
+// advances d.t and d.steps.
+hipError_t launch_conv_learned_one(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve &d,
+                                   int parity, const float *xprev, hipStream_t st, int blend = 0);
 
 // The same forward in one launch, without keeping activations: every
 // workgroup runs all five layers on an 8x8 tile of pixels (nx % 8 == 0,
@@ -162,7 +172,7 @@ struct StageBatch {
     int *fatal;
     Proj pr;
     // modes 2 and 3 (the end of a step in two launches instead of four):
-    const float *commit_src;     // mode 2: S2, copied to commit_dst for admissible solves
+    const float *commit_src;     // mode 2: S2, copied to commit_dst for admissible solves (NULL: no copy)
     float *commit_dst;
     int *bad_next;               // mode 3: the next step's flags, cleared
     unsigned long long *redone;  // mode 3: per solve, +1 when the step was redone (or NULL)

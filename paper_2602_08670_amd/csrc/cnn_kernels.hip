@@ -875,6 +875,131 @@ template <int N> struct Chunks {
     }
 };
 
+// Plain (MINMOD, HLLE) Heun step of the previous state xprev on the R x R
+// region at (ox, oy), recomputed from xprev on the region grown by four
+// cells (two per stage): the redo of a step whose learned result was
+// inadmissible, on the region one workgroup of the next step reads, so that
+// no launch has to finish the redo first.  Each face flux, cell update and
+// Heun combine is the plain stage's (learned-stage kernels, MODES 2 and 3)
+// arithmetic on the same stencil values.  The FT x FT tile at (x0, y0) writes
+// its cells of the result to xk and raises fatal where a plain stage leaves
+// one of them inadmissible.  Needs 3 ((R + 8)^2 + (R + 4)^2 + R^2) floats of
+// LDS at buf; returns the region, [3][R][R], in buf.
+struct PlainRedo {
+    const float *xprev;  // the previous step's input [3][H][W]
+    float *xk;           // the redone state [3][H][W]: this tile's cells written
+    const float *dt;
+    float rdx, rdy;
+    Phys<float> ph;
+    int *fatal;
+};
+
+// The four face fluxes of the cell at (r, c) of an LDS field [3][N][N]:
+// left, right, bottom, top (the face between cells j and j + 1 of a line
+// takes the stencil j - 2 .. j + 3, of which MINMOD reads j - 1 .. j + 2).
+template <int N>
+__device__ __forceinline__ void plain_cell_fluxes(const float *f, int r, int c, const Phys<float> &ph, float (*F)[3])
+{
+#pragma unroll
+    for (int face = 0; face < 4; face++) {
+        const int ax = face >> 1, lo = face & 1;  // axis, and whether the face is on the cell's high side
+        float st[3][6];
+#pragma unroll
+        for (int v = 0; v < 3; v++) {
+            st[v][0] = 0.0f;
+            st[v][5] = 0.0f;
+#pragma unroll
+            for (int k = 1; k < 5; k++) {
+                const int o = k - 3 + lo;
+                st[v][k] = ax == 0 ? f[(v * N + r) * N + c + o] : f[(v * N + r + o) * N + c];
+            }
+        }
+        float QL[3], QR[3];
+        face_states<1>(st, nullptr, Proj{}, QL, QR);
+        if (ax == 0) flux3<fvk::HLLE, 0>(QL, QR, ph, F[face]);
+        else flux3<fvk::HLLE, 1>(QL, QR, ph, F[face]);
+    }
+}
+
+// Out of line, its arguments in registers: the common path (no redo) keeps
+// the network pass's register budget.
+template <int R>
+__device__ __noinline__ float *redo_region(const float *xprev, float *xk, const float *dtp, float rdx, float rdy,
+                                           float g, float sqg, float h0, int *fatal, int H, int W, int ox, int oy,
+                                           int x0, int y0, float *buf)
+{
+    constexpr int A = R + 8, S = R + 4, NT = FNW * 64;
+    PlainRedo rd;
+    rd.xprev = xprev;
+    rd.xk = xk;
+    rd.dt = dtp;
+    rd.rdx = rdx;
+    rd.rdy = rdy;
+    rd.ph.g = g;
+    rd.ph.sqg = sqg;
+    rd.ph.gamma = 1.4f;
+    rd.ph.h0 = h0;
+    rd.fatal = fatal;
+    float *sa = buf;              // [3][A][A] xprev from (ox - 4, oy - 4)
+    float *ss = sa + 3 * A * A;   // [3][S][S] plain stage 1 from (ox - 2, oy - 2)
+    float *sr = ss + 3 * S * S;   // [3][R][R] the redone state from (ox, oy)
+    const int tid = threadIdx.x;
+    const size_t plane = (size_t)H * W;
+    const float dt = rd.dt[0];
+    for (int k = tid; k < 3 * A * A; k += NT) {
+        const int v = k / (A * A), r = k - v * A * A, ry = r / A, rx = r - ry * A;
+        // up to ten cells out from a tile of a grid as small as 8 cells: the full modulo
+        sa[k] = rd.xprev[v * plane + (size_t)pwrap(oy - 4 + ry, H) * W + pwrap(ox - 4 + rx, W)];
+    }
+    __syncthreads();
+    bool bad = false;
+    // stage 1: S1 = q + dt L(q); cell (j, i) of ss is (j + 2, i + 2) of sa
+    for (int k = tid; k < S * S; k += NT) {
+        const int j = k / S, i = k - j * S;
+        float F[4][3];
+        plain_cell_fluxes<A>(sa, j + 2, i + 2, rd.ph, F);
+        const int gx = ox - 2 + i - x0, gy = oy - 2 + j - y0;  // tile-relative
+        const bool own = gx >= 0 && gx < FT && gy >= 0 && gy < FT;
+        float qn[3];
+#pragma unroll
+        for (int v = 0; v < 3; v++) {
+            float L = -(F[1][v] - F[0][v]) * rd.rdx - (F[3][v] - F[2][v]) * rd.rdy;
+            float o = 1.0f * (sa[(v * A + j + 2) * A + i + 2] + dt * L);
+            ss[(v * S + j) * S + i] = o;
+            qn[v] = o;
+        }
+        if (own) bad = bad || !(qn[0] > 0.0f && __builtin_isfinite(qn[0]) && __builtin_isfinite(qn[1]) &&
+                                __builtin_isfinite(qn[2]));
+    }
+    __syncthreads();
+    // stage 2: q/2 + (S1 + dt L(S1))/2; cell (j, i) of sr is (j + 2, i + 2) of ss
+    for (int k = tid; k < R * R; k += NT) {
+        const int j = k / R, i = k - j * R;
+        float F[4][3];
+        plain_cell_fluxes<S>(ss, j + 2, i + 2, rd.ph, F);
+        const int gx = ox + i - x0, gy = oy + j - y0;
+        const bool own = gx >= 0 && gx < FT && gy >= 0 && gy < FT;
+        float qn[3];
+#pragma unroll
+        for (int v = 0; v < 3; v++) {
+            float L = -(F[1][v] - F[0][v]) * rd.rdx - (F[3][v] - F[2][v]) * rd.rdy;
+            float o = 0.5f * (ss[(v * S + j + 2) * S + i + 2] + dt * L);
+            o = 0.5f * sa[(v * A + j + 4) * A + i + 4] + o;
+            sr[(v * R + j) * R + i] = o;
+            qn[v] = o;
+        }
+        if (own) {
+#pragma unroll
+            for (int v = 0; v < 3; v++) rd.xk[v * plane + (size_t)(y0 + gy) * W + x0 + gx] = qn[v];
+            bad = bad || !(qn[0] > 0.0f && __builtin_isfinite(qn[0]) && __builtin_isfinite(qn[1]) &&
+                           __builtin_isfinite(qn[2]));
+        }
+    }
+    if (bad) atomicExch(rd.fatal, 1);
+    __syncthreads();
+    return sr;
+}
+
 // ALPHA: instead of z, write the constrained coefficients alpha = base + P z
 // of every group of six (same operation order as the learned stage's own
 // projection, so alpha is bit-identical to projecting this kernel's z).
@@ -888,9 +1013,12 @@ template <int N> struct Chunks {
 // coefficients itself (each group of six serves exactly one face).  load_w: stage the
 // weights (a workgroup's first tile; its later tiles find them in LDS).
 enum { OUT_Z = 0, OUT_ALPHA = 1, OUT_Z_LDS = 2 };
+// rd (OUT_Z_LDS only, or NULL): when rd->xprev is set, the input region is
+// the plain redo of the previous step (redo_region) instead of qb.
 template <int FO, int OUT>
 __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
-                                             int H, int W, int y0, int x0, const Proj &pr, bool load_w, float *qf);
+                                             int H, int W, int y0, int x0, const Proj &pr, bool load_w, float *qf,
+                                             const PlainRedo *rd = nullptr);
 
 // Workgroups stride over the B x (H/FT) x (W/FT) tiles: a grid of at most the
 // workgroups resident at once stages the weights once per workgroup.
@@ -947,7 +1075,8 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_batch_kernel(const LSolve
 
 template <int FO, int OUT>
 __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
-                                             int H, int W, int y0, int x0, const Proj &pr, bool load_w, float *qf)
+                                             int H, int W, int y0, int x0, const Proj &pr, bool load_w, float *qf,
+                                             const PlainRedo *rd)
 {
     static_assert(FO == FT || (FO == FT + 1 && OUT == OUT_Z_LDS), "output region: the tile, or the tile and its low halo");
     constexpr int OFF = FO - FT;          // the region starts OFF cells before the tile
@@ -975,14 +1104,30 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     // (FT + 6)^2 cells from (x0 - 3, y0 - 3), kept for the learned stage.
     constexpr int NIN = 3 * FRI_ * FRI_, TIN = (NIN + FNW * 64 - 1) / (FNW * 64);
     float xin[TIN];
+    const float *sr = nullptr;
+    if constexpr (OUT == OUT_Z_LDS) {
+        // the activations' LDS is free until layer 0's first store, which
+        // follows the staging barrier below
+        if (rd && rd->xprev)
+            sr = redo_region<FRI_>(rd->xprev, rd->xk, rd->dt, rd->rdx, rd->rdy, rd->ph.g, rd->ph.sqg, rd->ph.h0,
+                                   rd->fatal, H, W, rx0, ry0, x0, y0, (float *)s_act);
+    }
+    if (sr) {
 #pragma unroll
-    for (int k = 0; k < TIN; k++) {
-        const int i = threadIdx.x + k * FNW * 64;
-        if (i < NIN) {
-            const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
-            const int ry = r / FRI_, rx = r - ry * FRI_;
-            const int yy = wrap(ry0 + ry, H), xx = wrap(rx0 + rx, W);
-            xin[k] = qb[(size_t)ci * hw + (size_t)yy * W + xx];
+        for (int k = 0; k < TIN; k++) {
+            const int i = threadIdx.x + k * FNW * 64;
+            if (i < NIN) xin[k] = sr[i];
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < TIN; k++) {
+            const int i = threadIdx.x + k * FNW * 64;
+            if (i < NIN) {
+                const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
+                const int ry = r / FRI_, rx = r - ry * FRI_;
+                const int yy = wrap(ry0 + ry, H), xx = wrap(rx0 + rx, W);
+                xin[k] = qb[(size_t)ci * hw + (size_t)yy * W + xx];
+            }
         }
     }
     Chunks<W0> c0;
@@ -1467,6 +1612,55 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_batch_kernel(const LSol
     }
 }
 
+// One solve's learned stage in a launch of its own (network pass and learned
+// stage per FT x FT tile, as conv_learned_batch_kernel), the solve passed by
+// value: d.q is the step's input, d.s2 the step's output (the other buffer of
+// a pair, so the input survives for a redo).  Stage 1 with xprev != NULL:
+// when the previous step's flag slot is set, every workgroup first redoes
+// that step from xprev on the region it reads (redo_region, the result's
+// tile written to d.q) and workgroup 0 counts the redo.  Stage 2's workgroup 0
+// clears the previous step's slot (every reader of it has finished: the
+// previous step's stage 2 and this step's stage 1) and advances the time.
+template <int STAGE, bool BL = false>
+__global__ __launch_bounds__(FNW * 64) void conv_learned_one_kernel(LSolve d, int parity, const float *xprev,
+                                                                    const char *P, Packed pk, Norm nrm, Proj pr)
+{
+    constexpr int QS = FT + 6;
+    __shared__ float s_qf[3 * QS * QS];
+    const int tx_n = d.nx / FT, total = tx_n * (d.ny / FT);
+    const LItem it{0, 0, 0, parity, 0};
+    const bool redo = STAGE == 1 && xprev && d.flags[parity ^ 1] != 0;
+    PlainRedo rd;
+    rd.xprev = redo ? xprev : nullptr;
+    {
+        rd.xk = d.q;
+        rd.dt = d.dt;
+        rd.rdx = d.rdx;
+        rd.rdy = d.rdy;
+        rd.ph.g = d.g;
+        rd.ph.sqg = d.sqg;
+        rd.ph.gamma = 1.4f;
+        rd.ph.h0 = d.h0;
+        rd.fatal = d.fatal;
+        if (redo && blockIdx.x == 0 && threadIdx.x == 0) *d.redone += 1;
+    }
+    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+        const bool first = w == (int)blockIdx.x;
+        if (!first) __syncthreads();  // the previous tile's LDS reads are done
+        const int ty = w / tx_n, tx = w - ty * tx_n;
+        const float *s_z = fused_tile<FT + 1, OUT_Z_LDS>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx,
+                                                             ty * FT, tx * FT, pr, first, s_qf, &rd);
+        learned_epilogue<STAGE, BL>(d, it, s_z, s_qf, pr, tx * FT, ty * FT);
+    }
+    if (STAGE == 2 && blockIdx.x == 0 && threadIdx.x == 0) {
+        d.flags[parity ^ 1] = 0;
+        if (d.t) {
+            *d.t += (double)d.dt[0];
+            *d.steps += 1;
+        }
+    }
+}
+
 int fused_max_grid()
 {
     // resident workgroups of the tiled pass (one per CU: its LDS), per device
@@ -1493,7 +1687,19 @@ int fused_max_grid()
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&j, conv_learned_batch_kernel<2, true>, FNW * 64, 0) !=
                 hipSuccess)
             return 256;
+        int k1 = 0, k2 = 0, k3 = 0, k4 = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k1, conv_learned_one_kernel<1>, FNW * 64, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&k2, conv_learned_one_kernel<2>, FNW * 64, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&k3, conv_learned_one_kernel<1, true>, FNW * 64, 0) !=
+                hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&k4, conv_learned_one_kernel<2, true>, FNW * 64, 0) !=
+                hipSuccess)
+            return 256;
         int m = a < b ? a : b;
+        m = m < k1 ? m : k1;
+        m = m < k2 ? m : k2;
+        m = m < k3 ? m : k3;
+        m = m < k4 ? m : k4;
         m = m < c ? m : c;
         m = m < e ? m : e;
         m = m < f ? m : f;
@@ -1570,6 +1776,29 @@ hipError_t launch_conv_learned_list(int stage, const void *packed, const Norm &n
     else
         hipLaunchKernelGGL(conv_learned_batch_kernel<2>, dim3(wgs), dim3(FNW * 64), 0, st, tab, items, list, 0, 0,
                            (const char *)packed, pk, nrm, pr);
+    return hipGetLastError();
+}
+
+hipError_t launch_conv_learned_one(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve &d,
+                                   int parity, const float *xprev, hipStream_t st, int blend)
+{
+    if (d.nx % FT || d.ny % FT || (parity & ~1) || (stage != 1 && stage != 2) || (stage == 2 && xprev))
+        return hipErrorInvalidValue;
+    const Packed pk = packed_layout();
+    const int tiles = (d.nx / FT) * (d.ny / FT), cap = fused_max_grid(), g = tiles < cap ? tiles : cap;
+    const char *Pc = (const char *)packed;
+    if (blend) {
+        if (stage == 1)
+            hipLaunchKernelGGL((conv_learned_one_kernel<1, true>), dim3(g), dim3(FNW * 64), 0, st, d, parity, xprev, Pc,
+                               pk, nrm, pr);
+        else
+            hipLaunchKernelGGL((conv_learned_one_kernel<2, true>), dim3(g), dim3(FNW * 64), 0, st, d, parity, xprev, Pc,
+                               pk, nrm, pr);
+    } else if (stage == 1) {
+        hipLaunchKernelGGL(conv_learned_one_kernel<1>, dim3(g), dim3(FNW * 64), 0, st, d, parity, xprev, Pc, pk, nrm, pr);
+    } else {
+        hipLaunchKernelGGL(conv_learned_one_kernel<2>, dim3(g), dim3(FNW * 64), 0, st, d, parity, xprev, Pc, pk, nrm, pr);
+    }
     return hipGetLastError();
 }
 

@@ -215,10 +215,10 @@ fv_status enqueue_step(fv_solver *s)
 // offsets inside the 256-byte block of learned counters
 constexpr size_t SM_DT = 0, SM_BAD = 8, SM_NFB = 16, SM_REDONE = 24;
 
-fv_status upload_lbatch(fv_solver *s)
+// The solve's descriptor for the learned kernels (device pointers into the
+// solver's workspace and control block).
+static cnn::LSolve lsolve_of(fv_solver *s)
 {
-    alignas(16) char buf[LBATCH_BYTES];
-    std::memset(buf, 0, sizeof buf);
     char *ws = s->ws, *sm = ws + s->L.small;
     cnn::LSolve d{};
     d.q = (float *)s->q;
@@ -239,6 +239,15 @@ fv_status upload_lbatch(fv_solver *s)
     d.g = (float)s->cfg.g;
     d.sqg = std::sqrt((float)s->cfg.g);
     d.h0 = (float)s->d.h0;
+    return d;
+}
+
+fv_status upload_lbatch(fv_solver *s)
+{
+    alignas(16) char buf[LBATCH_BYTES];
+    std::memset(buf, 0, sizeof buf);
+    char *ws = s->ws;
+    const cnn::LSolve d = lsolve_of(s);
     std::memcpy(buf + LB_TAB, &d, sizeof d);
     for (int p = 0; p < 2; p++) {
         cnn::LItem it{0, 0, 0, p};
@@ -722,30 +731,61 @@ static fv_status learned_step_impl(fv_solver *s, const fv_model *m, int64_t nste
     sb.z = z;
     const int fl = c.flux == FV_FLUX_RUSANOV ? 1 : 0;  // kernel flux ids: 0 HLLE, 1 Rusanov
     hipError_t e = hipSuccess;
-    if (fl == 0 && c.nx % 8 == 0 && c.ny % 8 == 0) {
-        // the server's work-list kernels as a batch of one, chosen by the
-        // server's default rule: four launches per step (network pass with
-        // the learned stage, twice; commit-or-redo; redo and bookkeeping), or,
-        // for grids of at least 4 x the network pass's resident workgroups in
-        // tiles, the network pass and the learned stage as separate launches;
-        // bit-identical to the same solve in a served mix
+    if (fl == 0 && c.nx % 8 == 0 && c.ny % 8 == 0 &&
+        cnn::ltiles_cnn(c.nx, c.ny) < 4 * cnn::fused_max_grid()) {
+        // two launches per step, each the network pass with the learned
+        // stage (the server's per-stage arithmetic, so bit-identical to the
+        // same solve in a served mix): the step's output goes to the other
+        // buffer of the pair (q, S2), its input stays for a redo, which the
+        // next step's first launch carries out where needed; the call's last
+        // step ends with the commit-or-redo and redo launches
+        cnn::LSolve d = lsolve_of(s);
+        float *X[2] = {q, S2};
+        int *flags = (int *)(sm + SM_BAD);
+        for (int64_t k = 0; k < nsteps && e == hipSuccess; k++, s->lsteps++) {
+            const int par = (int)(s->lsteps & 1);
+            d.q = X[k & 1];
+            d.s2 = X[(k + 1) & 1];
+            e = cnn::launch_conv_learned_one(1, m->packed, m->nrm, m->pr, d, par, k > 0 ? X[(k + 1) & 1] : nullptr,
+                                             s->stream, blend);
+            if (e == hipSuccess)
+                e = cnn::launch_conv_learned_one(2, m->packed, m->nrm, m->pr, d, par, nullptr, s->stream, blend);
+        }
+        if (nsteps > 0 && e == hipSuccess) {
+            // the last step's input xin and output xout: with an odd step
+            // count (q, S2), commit S2 -> q or redo from q; with an even one
+            // (S2, q), the result is in q already, or the step is redone from S2
+            float *xin = X[(nsteps - 1) & 1], *xout = X[nsteps & 1];
+            const int par = (int)((s->lsteps - 1) & 1);
+            sb.bad = flags + par;
+            sb.bad_next = flags + (par ^ 1);
+            sb.redone = (unsigned long long *)(sm + SM_REDONE);
+            sb.t = nullptr;  // advanced by each step's second launch
+            sb.steps = nullptr;
+            sb.qs = xin; sb.q0 = xin; sb.out = S1; sb.a0 = 0.f; sb.a1 = 1.f;
+            sb.commit_src = xout == q ? nullptr : xout;
+            sb.commit_dst = q;
+            e = cnn::learned_stage(2, fl, sb, s->stream);
+            sb.qs = S1; sb.q0 = xin; sb.out = q; sb.a0 = 0.5f; sb.a1 = 0.5f;
+            if (e == hipSuccess) e = cnn::learned_stage(3, fl, sb, s->stream);
+        }
+        nsteps = 0;  // done; fall through to the statistics
+    } else if (fl == 0 && c.nx % 8 == 0 && c.ny % 8 == 0) {
+        // larger grids: the server's work-list kernels as a batch of one,
+        // the network pass and the learned stage as separate launches, then
+        // commit-or-redo and redo; bit-identical to the same solve in a
+        // served mix
         const char *B = ws + L.lbatch;
         const auto *tab = (const cnn::LSolve *)(B + LB_TAB);
         const auto *items0 = (const cnn::LItem *)(B + LB_ITEMS);
         const int *nit = (const int *)(B + LB_N);
         const int tc = cnn::ltiles_cnn(c.nx, c.ny), ts = cnn::ltiles_st(c.nx, c.ny);
-        const bool split = tc >= 4 * cnn::fused_max_grid();
-        if (blend && split) return fail(FV_E_UNSUPPORTED, "blend: grid too large for the fused form");
+        if (blend) return fail(FV_E_UNSUPPORTED, "blend: grid too large for the fused form");
         for (int64_t k = 0; k < nsteps && e == hipSuccess; k++, s->lsteps++) {
             const cnn::LItem *it = items0 + (s->lsteps & 1);
             for (int stage = 1; stage <= 2 && e == hipSuccess; stage++) {
-                if (!split) {
-                    e = cnn::launch_conv_learned(stage, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1,
-                                                 blend);
-                } else {
-                    e = cnn::launch_forward_batch(stage, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
-                    if (e == hipSuccess) e = cnn::launch_learned_batch(0, stage, tab, it, nit, ts, m->pr, s->stream, 1);
-                }
+                e = cnn::launch_forward_batch(stage, m->packed, m->nrm, m->pr, tab, it, nit, tc, s->stream, 1);
+                if (e == hipSuccess) e = cnn::launch_learned_batch(0, stage, tab, it, nit, ts, m->pr, s->stream, 1);
             }
             if (e == hipSuccess) e = cnn::launch_learned_batch(2, 0, tab, it, nit, ts, m->pr, s->stream, 1);
             if (e == hipSuccess) e = cnn::launch_learned_batch(3, 0, tab, it, nit, ts, m->pr, s->stream, 1);

@@ -88,7 +88,9 @@ __device__ __forceinline__ void learned_tile(const LearnedArgs &a, const int b, 
         }
     }
     if (MODE == 2 && a.bad[b] == 0) {
-        // admissible learned step: q <- S2 on this tile
+        // admissible learned step: q <- S2 on this tile (no source: the
+        // result is already in place)
+        if (!a.commit_src) return;
         for (int k = tid; k < TX * TY; k += 256) {
             const int cy = k / TX, cx = k - cy * TX;
             if (x0 + cx >= nx || y0 + cy >= ny) continue;
@@ -373,7 +375,7 @@ hipError_t learned_stage(int mode, int flux, const StageBatch &sb, hipStream_t s
     a.t = sb.t;
     a.steps = sb.steps;
     for (int v = 0; v < 3; v++) a.sig[v] = sb.sig[v];
-    if ((mode == 2 && (!a.commit_src || !a.commit_dst)) || (mode == 3 && !a.bad_next)) return hipErrorInvalidValue;
+    if ((mode == 2 && a.commit_src && !a.commit_dst) || (mode == 3 && !a.bad_next)) return hipErrorInvalidValue;
     if ((sb.direct || sb.blend) && (mode != 0 || sb.alpha)) return hipErrorInvalidValue;
     if (sb.direct && sb.blend) return hipErrorInvalidValue;
     dim3 grid((a.nx + LTILE_X - 1) / LTILE_X, (a.ny + LTILE_Y - 1) / LTILE_Y, a.B), blk(256);

@@ -158,8 +158,8 @@ def small_model(fv, seed, scale=0.02, bias_last=0.0):
 def test_learned_mix_bitwise_equals_alone(fv):
     """Learned requests of several sizes served together with plain ones: each
     learned result (state, time, fallback and redo counts) is bit-identical to
-    fv_learned_step on the same solve alone -- both run the work-list kernels,
-    the single solve as a batch of one."""
+    fv_learned_step on the same solve alone -- the server's work-list kernels
+    and the single solve's own launches do the same arithmetic per stage."""
     from paper_2602_08670_amd import learned_solver as LS
 
     m = small_model(fv, 11, scale=0.03, bias_last=0.5)
