@@ -887,6 +887,7 @@ template <int N> struct Chunks {
 // LDS at buf; returns the region, [3][R][R], in buf.
 struct PlainRedo {
     const float *xprev;  // the previous step's input [3][H][W]
+    const int *flag;     // the previous step's flag slot: redo where it is set
     float *xk;           // the redone state [3][H][W]: this tile's cells written
     const float *dt;
     float rdx, rdy;
@@ -1013,8 +1014,9 @@ __device__ __noinline__ float *redo_region(const float *xprev, float *xk, const 
 // coefficients itself (each group of six serves exactly one face).  load_w: stage the
 // weights (a workgroup's first tile; its later tiles find them in LDS).
 enum { OUT_Z = 0, OUT_ALPHA = 1, OUT_Z_LDS = 2 };
-// rd (OUT_Z_LDS only, or NULL): when rd->xprev is set, the input region is
-// the plain redo of the previous step (redo_region) instead of qb.
+// rd (OUT_Z_LDS only, or NULL): when rd->xprev is set and *rd->flag is not
+// zero, the input region is the plain redo of the previous step
+// (redo_region) instead of qb.
 template <int FO, int OUT>
 __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
                                              int H, int W, int y0, int x0, const Proj &pr, bool load_w, float *qf,
@@ -1104,29 +1106,27 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     // (FT + 6)^2 cells from (x0 - 3, y0 - 3), kept for the learned stage.
     constexpr int NIN = 3 * FRI_ * FRI_, TIN = (NIN + FNW * 64 - 1) / (FNW * 64);
     float xin[TIN];
-    const float *sr = nullptr;
-    if constexpr (OUT == OUT_Z_LDS) {
-        // the activations' LDS is free until layer 0's first store, which
-        // follows the staging barrier below
-        if (rd && rd->xprev)
-            sr = redo_region<FRI_>(rd->xprev, rd->xk, rd->dt, rd->rdx, rd->rdy, rd->ph.g, rd->ph.sqg, rd->ph.h0,
-                                   rd->fatal, H, W, rx0, ry0, x0, y0, (float *)s_act);
-    }
-    if (sr) {
 #pragma unroll
-        for (int k = 0; k < TIN; k++) {
-            const int i = threadIdx.x + k * FNW * 64;
-            if (i < NIN) xin[k] = sr[i];
+    for (int k = 0; k < TIN; k++) {
+        const int i = threadIdx.x + k * FNW * 64;
+        if (i < NIN) {
+            const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
+            const int ry = r / FRI_, rx = r - ry * FRI_;
+            const int yy = wrap(ry0 + ry, H), xx = wrap(rx0 + rx, W);
+            xin[k] = qb[(size_t)ci * hw + (size_t)yy * W + xx];
         }
-    } else {
+    }
+    if constexpr (OUT == OUT_Z_LDS) {
+        // the redo decision after the loads have been issued (their values
+        // are discarded on a redo); the activations' LDS is free until layer
+        // 0's first store, which follows the staging barrier below
+        if (rd && rd->xprev && *rd->flag) {
+            const float *sr = redo_region<FRI_>(rd->xprev, rd->xk, rd->dt, rd->rdx, rd->rdy, rd->ph.g, rd->ph.sqg,
+                                                rd->ph.h0, rd->fatal, H, W, rx0, ry0, x0, y0, (float *)s_act);
 #pragma unroll
-        for (int k = 0; k < TIN; k++) {
-            const int i = threadIdx.x + k * FNW * 64;
-            if (i < NIN) {
-                const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
-                const int ry = r / FRI_, rx = r - ry * FRI_;
-                const int yy = wrap(ry0 + ry, H), xx = wrap(rx0 + rx, W);
-                xin[k] = qb[(size_t)ci * hw + (size_t)yy * W + xx];
+            for (int k = 0; k < TIN; k++) {
+                const int i = threadIdx.x + k * FNW * 64;
+                if (i < NIN) xin[k] = sr[i];
             }
         }
     }
@@ -1233,41 +1233,49 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     static_assert(FO * FO * 72 * 4 <= sizeof(s_act), "coefficient region fits over the activations");
     constexpr bool ALPHA = OUT != OUT_Z;  // z staged in LDS
     {
-        // wave w < NG: pixel group w with all NT co tiles, its activation
-        // fragment read once per tap for NT MFMAs; each co tile's chain keeps
-        // the tap order 0..8
-        constexpr int NT = 5, RIN = FO + 2, NPX = FO * FO, NG = (NPX + 15) / 16;
-        static_assert(NG <= FNW, "one pixel group per wave");
+        // pixel groups wave, wave + FNW, ... with all NT co tiles, the
+        // activation fragment read once per tap for NT MFMAs; each co tile's
+        // chain keeps the tap order 0..8
+        constexpr int NT = 5, RIN = FO + 2, NPX = FO * FO, NG = (NPX + 15) / 16, GPW = (NG + FNW - 1) / FNW;
         const float *bias = (const float *)(P + pk.b[4]);
-        floatx4 acc[NT];
+        floatx4 acc[GPW][NT];
 #pragma unroll
-        for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-        const int p = wave * 16 + px;
-        if (wave < NG) {  // wave-uniform, a real branch: an MFMA does not honour a partial EXEC
-            const int pc = p < NPX ? p : 0;
-            const int py = pc / FO, pxx = pc - py * FO;
-            const int bo = (py * RIN + pxx) * 4 + g;
+        for (int k = 0; k < GPW; k++)
 #pragma unroll
-            for (int tap = 0; tap < 9; tap++) {
-                const bf16x8 bx = s_a1[bo + ((tap / 3) * RIN + tap % 3) * 4];
+            for (int t = 0; t < NT; t++) acc[k][t] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-                for (int t = 0; t < NT; t++)
-                    acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * 4 + g], bx,
-                                                                     acc[t], 0, 0, 0);
+        for (int k = 0; k < GPW; k++) {
+            const int gi = wave + k * FNW, p = gi * 16 + px;
+            if (gi < NG) {  // wave-uniform, a real branch: an MFMA does not honour a partial EXEC
+                const int pc = p < NPX ? p : 0;
+                const int py = pc / FO, pxx = pc - py * FO;
+                const int bo = (py * RIN + pxx) * 4 + g;
+#pragma unroll
+                for (int tap = 0; tap < 9; tap++) {
+                    const bf16x8 bx = s_a1[bo + ((tap / 3) * RIN + tap % 3) * 4];
+#pragma unroll
+                    for (int t = 0; t < NT; t++)
+                        acc[k][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * 4 + g],
+                                                                            bx, acc[k][t], 0, 0, 0);
+                }
             }
         }
         if (ALPHA) __syncthreads();  // every wave past its layer-4 reads of s_a1 before it holds z
-        if (wave < NG && p < NPX) {
-            const int py = p / FO, pxx = p - py * FO;
 #pragma unroll
-            for (int t = 0; t < NT; t++) {
-                const int co0 = 16 * t + 4 * g;
-                if (co0 < 72) {
-                    floatx4 o;
+        for (int k = 0; k < GPW; k++) {
+            const int gi = wave + k * FNW, p = gi * 16 + px;
+            if (gi < NG && p < NPX) {
+                const int py = p / FO, pxx = p - py * FO;
 #pragma unroll
-                    for (int i = 0; i < 4; i++) o[i] = acc[t][i] + bias[co0 + i];
-                    if (ALPHA) *(floatx4 *)(s_z + p * 72 + co0) = o;
-                    else *(floatx4 *)(zb + ((size_t)(y0 + py) * W + x0 + pxx) * 72 + co0) = o;
+                for (int t = 0; t < NT; t++) {
+                    const int co0 = 16 * t + 4 * g;
+                    if (co0 < 72) {
+                        floatx4 o;
+#pragma unroll
+                        for (int i = 0; i < 4; i++) o[i] = acc[k][t][i] + bias[co0 + i];
+                        if (ALPHA) *(floatx4 *)(s_z + p * 72 + co0) = o;
+                        else *(floatx4 *)(zb + ((size_t)(y0 + py) * W + x0 + pxx) * 72 + co0) = o;
+                    }
                 }
             }
         }
@@ -1411,18 +1419,17 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_euler_kernel(const float 
             fused_hidden(in, rin, out, s_wall + EW0 + (l - 1) * EWH, (const float *)(P + pk.b[l]), wave, lane);
         }
         __syncthreads();
-        // layer 4: s_a1 (FT + 2)^2 -> z on the tile, wave w < NG: pixel group w
-        // with all six co tiles, each chain in tap order
+        // layer 4: s_a1 (FT + 2)^2 -> z on the tile, pixel groups wave, wave +
+        // FNW, ... with all six co tiles, each chain in tap order
         {
             constexpr int NT = 6, RIN = FT + 2, NPX = FT * FT, NG = (NPX + 15) / 16;
-            static_assert(NG <= FNW, "one pixel group per wave");
             const bf16x8 *s_w = s_wall + EW0 + 3 * EWH;
             const float *bias = (const float *)(P + pk.b[4]);
-            if (wave < NG) {  // wave-uniform, a real branch: an MFMA does not honour a partial EXEC
+            for (int gi = wave; gi < NG; gi += FNW) {  // wave-uniform: an MFMA does not honour a partial EXEC
                 floatx4 acc[NT];
 #pragma unroll
                 for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-                const int p = wave * 16 + px;
+                const int p = gi * 16 + px;
                 const int py = p / FT, pxx = p - py * FT;
                 const int bo = (py * RIN + pxx) * 4 + g;
 #pragma unroll
@@ -1629,9 +1636,9 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_one_kernel(LSolve d, in
     __shared__ float s_qf[3 * QS * QS];
     const int tx_n = d.nx / FT, total = tx_n * (d.ny / FT);
     const LItem it{0, 0, 0, parity, 0};
-    const bool redo = STAGE == 1 && xprev && d.flags[parity ^ 1] != 0;
     PlainRedo rd;
-    rd.xprev = redo ? xprev : nullptr;
+    rd.xprev = STAGE == 1 ? xprev : nullptr;
+    rd.flag = d.flags + (parity ^ 1);
     {
         rd.xk = d.q;
         rd.dt = d.dt;
@@ -1642,16 +1649,21 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_one_kernel(LSolve d, in
         rd.ph.gamma = 1.4f;
         rd.ph.h0 = d.h0;
         rd.fatal = d.fatal;
-        if (redo && blockIdx.x == 0 && threadIdx.x == 0) *d.redone += 1;
     }
-    for (int w = blockIdx.x; w < total; w += gridDim.x) {
+    // the grid never exceeds the tile count: every workgroup has a first
+    // tile, whose loads need not wait for the loop test
+    int w = blockIdx.x;
+    do {
         const bool first = w == (int)blockIdx.x;
         if (!first) __syncthreads();  // the previous tile's LDS reads are done
         const int ty = w / tx_n, tx = w - ty * tx_n;
         const float *s_z = fused_tile<FT + 1, OUT_Z_LDS>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx,
                                                              ty * FT, tx * FT, pr, first, s_qf, &rd);
         learned_epilogue<STAGE, BL>(d, it, s_z, s_qf, pr, tx * FT, ty * FT);
-    }
+        w += gridDim.x;
+    } while (w < total);
+    // no writer of the previous step's slot in stage 1
+    if (STAGE == 1 && xprev && blockIdx.x == 0 && threadIdx.x == 0 && d.flags[parity ^ 1]) *d.redone += 1;
     if (STAGE == 2 && blockIdx.x == 0 && threadIdx.x == 0) {
         d.flags[parity ^ 1] = 0;
         if (d.t) {
