@@ -46,7 +46,7 @@ using fvapi::hip_fail;
 namespace {
 
 struct Layout {
-    size_t ctl, rates, totals_out, partials, batch, s1, s2;
+    size_t ctl, rates, totals_out, partials, s1, s2;
     // buffers of the learned step (cfg.learned == 1)
     size_t act0, act1, z, s2l, small, lbatch;
     size_t total;
@@ -55,13 +55,10 @@ struct Layout {
 int nvar_of(const fv_config *c) { return c->eqn == FV_EULER ? 4 : 3; }
 
 // A solve in the configuration the server runs (FP32, HLLE, MINMOD, Heun,
-// CFL-controlled Delta t) steps through the server's batched stage kernels as
-// a batch of one, so it computes bit-identical results alone and in a mix.
-// Its device descriptor and the three per-step lists (one per rotation of
-// the CFL slots) sit in the workspace.
-constexpr size_t BATCH_TAB = 0, BATCH_ITEMS = 256, BATCH_N = 320, BATCH_BYTES = 512;
-static_assert(sizeof(fvk::BatchSolve) <= BATCH_ITEMS && BATCH_ITEMS + 3 * sizeof(fvk::WorkItem) <= BATCH_N,
-              "batch-of-one layout");
+// CFL-controlled Delta t) steps through the server's stage arithmetic, so it
+// computes bit-identical results alone and in a mix; its descriptor and the
+// three per-step list entries (one per rotation of the CFL slots) are kept
+// host-side and passed to the stage kernels by value.
 
 // The learned step's descriptor and its two one-item lists (flag slot 0
 // and 1) for the work-list kernels, as the server uses them.
@@ -106,8 +103,7 @@ Layout layout_of(const fv_config *c)
     L.rates = fvk::CTL_BYTES;
     L.totals_out = L.rates + fvk::RATE_BYTES;
     L.partials = L.totals_out + 256;
-    L.batch = L.partials + align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * sizeof(double));
-    L.s1 = L.batch + BATCH_BYTES;
+    L.s1 = L.partials + align256((size_t)fvk::TOTALS_MAX_BLOCKS * 5 * sizeof(double));
     L.s2 = L.s1 + st;
     size_t end = L.s2 + (c->rk_stages == 3 ? st : 0);
     if (c->learned) {
@@ -140,6 +136,8 @@ struct fv_solver {
     int64_t lsteps;  // learned steps enqueued (picks the slot of the step's flags)
     size_t state_bytes;
     bool batched;
+    fvk::BatchSolve bd;  // batched: the descriptor and the three step entries, as uploaded
+    fvk::WorkItem bi[3];
     fvk::Ctl *ctl() { return (fvk::Ctl *)(ws + L.ctl); }
     unsigned long long *rates() { return (unsigned long long *)(ws + L.rates); }
 };
@@ -178,13 +176,11 @@ fv_status enqueue_step(fv_solver *s)
     hipError_t e = hipSuccess;
     fvk::Ctl *ctl = s->ctl();
     if (s->batched) {
-        const char *B = s->ws + s->L.batch;
-        const auto *tab = (const fvk::BatchSolve *)(B + BATCH_TAB);
-        const auto *items = (const fvk::WorkItem *)(B + BATCH_ITEMS) + n;
-        const int *nitems = (const int *)(B + BATCH_N);
+        // the server's stage arithmetic on the solve's descriptor, passed by
+        // value (the copy in the workspace serves the learned kernels' list form)
         const int tiles = ((s->cfg.nx + fvk::TILE_X - 1) / fvk::TILE_X) * ((s->cfg.ny + fvk::TILE_Y - 1) / fvk::TILE_Y);
-        e = fvk::launch_batch_stage(s->d.eqn, s->d.bathy, 1, tab, items, nitems, tiles, s->stream, 1);
-        if (e == hipSuccess) e = fvk::launch_batch_stage(s->d.eqn, s->d.bathy, 2, tab, items, nitems, tiles, s->stream, 1);
+        e = fvk::launch_batch_stage_one(s->d.eqn, s->d.bathy, 1, s->bd, s->bi[n], tiles, s->stream);
+        if (e == hipSuccess) e = fvk::launch_batch_stage_one(s->d.eqn, s->d.bathy, 2, s->bd, s->bi[n], tiles, s->stream);
         if (e != hipSuccess) return hip_fail(e, "stage launch");
         s->enq++;
         return FV_OK;
@@ -261,11 +257,10 @@ fv_status upload_lbatch(fv_solver *s)
     return FV_OK;
 }
 
-// Descriptor and step lists of the batch-of-one path (see runs_batched).
-static_assert(sizeof(fvk::DescBlock) == BATCH_BYTES, "descriptor block size");
-void batch_block(fv_solver *s, char *buf)
+// Descriptor and step list entries of the batch-of-one path (see
+// runs_batched).
+void batch_block(fv_solver *s)
 {
-    std::memset(buf, 0, BATCH_BYTES);
     fvk::BatchSolve d{};
     d.q = s->q;
     d.s1 = s->ws + s->L.s1;
@@ -284,7 +279,7 @@ void batch_block(fv_solver *s, char *buf)
     d.h0 = s->d.h0;
     d.cfl = s->cfg.cfl;
     d.dt_fixed = 0.0;
-    std::memcpy(buf + BATCH_TAB, &d, sizeof d);
+    s->bd = d;
     for (int k = 0; k < 3; k++) {
         fvk::WorkItem it{};
         it.solve = 0;
@@ -293,20 +288,8 @@ void batch_block(fv_solver *s, char *buf)
         it.ri = (unsigned char)k;
         it.ro = (unsigned char)((k + 1) % 3);
         it.rc = (unsigned char)((k + 2) % 3);
-        std::memcpy(buf + BATCH_ITEMS + k * sizeof it, &it, sizeof it);
+        s->bi[k] = it;
     }
-    const int one = 1;
-    std::memcpy(buf + BATCH_N, &one, sizeof one);
-}
-
-fv_status upload_batch(fv_solver *s)
-{
-    alignas(16) char buf[BATCH_BYTES];
-    batch_block(s, buf);
-    hipError_t e = hipMemcpyAsync(s->ws + s->L.batch, buf, sizeof buf, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);  // buf is on this stack frame
-    if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
-    return FV_OK;
 }
 
 // The solver fields fv_init and fv_run_noalloc share (h0 is set by the caller).
@@ -400,7 +383,7 @@ fv_status fv_init(const fv_config *cfg, void *q, const void *bathy, void *worksp
         rc = fv_totals(s, tot);
         if (rc == FV_OK) s->d.h0 = tot[0] / (cfg->lx * cfg->ly);
     }
-    if (rc == FV_OK && s->batched) rc = upload_batch(s);
+    if (rc == FV_OK && s->batched) batch_block(s);
     if (rc == FV_OK && cfg->learned) rc = upload_lbatch(s);
     if (rc != FV_OK) {
         delete s;
@@ -582,11 +565,8 @@ fv_status fv_run_noalloc(const fv_config *cfg, void *q, const void *bathy, int64
     fv_solver s;
     setup_solver(&s, cfg, q, bathy, (char *)ws, L, (hipStream_t)stream);
     s.d.h0 = cfg->eqn == FV_SWE ? cfg->h_ref : 0.0;
-    fvk::DescBlock blk;
-    std::memset(&blk, 0, sizeof blk);
-    if (s.batched) batch_block(&s, (char *)blk.b);
-    hipError_t e = fvk::launch_reset(s.ctl(), s.rates(), s.ws + L.batch, blk, s.batched ? (int)BATCH_BYTES : 0,
-                                     s.stream);
+    if (s.batched) batch_block(&s);
+    hipError_t e = fvk::launch_reset(s.ctl(), s.rates(), s.stream);
     if (e == hipSuccess) e = fvk::launch_rate(s.d, s.q, s.ctl(), s.rates(), 0, s.stream);
     if (e != hipSuccess) return hip_fail(e, "reset and rate kernels");
     for (int64_t k = 0; k < nsteps; k++) {

@@ -75,6 +75,10 @@ constexpr int TILE_X = 64, TILE_Y = FV_TILE_Y;  // FP32 tile of the stage kernel
 // the list holds exactly one solve, solves[0].
 hipError_t launch_batch_stage(int eqn, int bathy, int stage, const BatchSolve *solves, const WorkItem *items,
                               const int *nitems, int grid, hipStream_t st, int one = 0);
+// One solve, descriptor and list entry by value (it.tile_begin == 0): the
+// launches of a single solve.
+hipError_t launch_batch_stage_one(int eqn, int bathy, int stage, const BatchSolve &d, const WorkItem &it, int grid,
+                                  hipStream_t st);
 // The form recorded in graphs: wgs workgroups (a multiple of 8, set to
 // xcd_grid(tiles) before each replay), the tile count read from the list
 // header list = {items, tiles}.
@@ -97,15 +101,9 @@ hipError_t launch_face_fluxes(const StageDesc &d, const void *q, void *fx, void 
 
 constexpr int TOTALS_MAX_BLOCKS = 1024;
 
-// A solve's descriptor block for the batch-of-one path, passed by value.
-struct DescBlock {
-    alignas(16) unsigned char b[512];
-};
 // Reset a solve's control block and CFL rate slots on the device (a kernel:
-// nothing host-side, no memset node), and copy `len` bytes of blk to dst
-// (len 0: none).
-hipError_t launch_reset(Ctl *ctl, unsigned long long *rates, void *dst, const DescBlock &blk, int len,
-                        hipStream_t st);
+// nothing host-side, no memset node).
+hipError_t launch_reset(Ctl *ctl, unsigned long long *rates, hipStream_t st);
 // Copy a solve's simulated time, completed steps and inadmissible flag into
 // the caller's device record {double t; int64 steps; int32 bad; int32 pad}.
 hipError_t launch_report(const Ctl *ctl, void *info, hipStream_t st);

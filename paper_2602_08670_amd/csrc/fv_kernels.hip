@@ -508,6 +508,9 @@ struct TileRef {
 };
 
 template <typename T, int STAGE>
+__device__ __forceinline__ TileRef batch_fill(const BatchSolve &d, const WorkItem &it, const int w, StageArgs<T> &a);
+
+template <typename T, int STAGE>
 __device__ __forceinline__ TileRef batch_resolve(const BatchSolve *__restrict__ solves,
                                                  const WorkItem *__restrict__ items, const int *__restrict__ nitems,
                                                  const int w, const int one, StageArgs<T> &a)
@@ -532,8 +535,15 @@ __device__ __forceinline__ TileRef batch_resolve(const BatchSolve *__restrict__ 
         it = items[lo];
         dp = solves + it.solve;
     }
+    return batch_fill<T, STAGE>(*dp, it, w, a);
+}
+
+// The stage arguments of workgroup w, whose solve is d with list entry it.
+template <typename T, int STAGE>
+__device__ __forceinline__ TileRef batch_fill(const BatchSolve &d, const WorkItem &it, const int w, StageArgs<T> &a)
+{
+    constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;
     const int tile = w - it.tile_begin;
-    const BatchSolve &d = *dp;
     a.qs = (const T *)(STAGE == 1 ? d.q : d.s1);
     a.q0 = (const T *)d.q;
     a.out = (T *)(STAGE == 1 ? d.s1 : d.q);
@@ -578,6 +588,21 @@ __global__ __launch_bounds__((StageLds<T, EQN, BATHY, Tile<T>::X, Tile<T>::Y>::N
     if (w >= total) return;
     StageArgs<T> a;
     const TileRef t = batch_resolve<T, STAGE>(solves, items, nitems, w, one, a);
+    stage_tile<T, EQN, BATHY, HLLE, MINMOD, TX, TY>(a, t.x0, t.y0, t.tile, threadIdx.x);
+}
+
+// One solve, its descriptor and list entry passed by value: the halo loads
+// wait for nothing but the arguments.  The same stage arguments, hence the
+// same results, as the list form.
+template <typename T, int EQN, bool BATHY, int STAGE>
+__global__ __launch_bounds__((StageLds<T, EQN, BATHY, Tile<T>::X, Tile<T>::Y>::NTH), 8) void batch_stage_one_kernel(
+    BatchSolve d, WorkItem it, int ntiles)
+{
+    constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    if (w >= ntiles) return;
+    StageArgs<T> a;
+    const TileRef t = batch_fill<T, STAGE>(d, it, w, a);
     stage_tile<T, EQN, BATHY, HLLE, MINMOD, TX, TY>(a, t.x0, t.y0, t.tile, threadIdx.x);
 }
 
@@ -655,13 +680,11 @@ __global__ __launch_bounds__(256) void totals_final_kernel(const double *partial
 }
 
 // ------------------------------------------------------- solve reset/report
-__global__ __launch_bounds__(256) void reset_kernel(Ctl *ctl, unsigned long long *rates, unsigned char *dst,
-                                                    DescBlock blk, int len)
+__global__ __launch_bounds__(256) void reset_kernel(Ctl *ctl, unsigned long long *rates)
 {
     const int t = threadIdx.x;
     for (int k = t; k < (int)(RATE_BYTES / sizeof(unsigned long long)); k += 256) rates[k] = 0ull;
     if (t < (int)(sizeof(Ctl) / sizeof(unsigned long long))) ((unsigned long long *)ctl)[t] = 0ull;
-    for (int k = t; k < len; k += 256) dst[k] = blk.b[k];
 }
 
 struct RunInfo {
@@ -681,11 +704,9 @@ __global__ void report_kernel(const Ctl *ctl, RunInfo *info)
     }
 }
 
-hipError_t launch_reset(Ctl *ctl, unsigned long long *rates, void *dst, const DescBlock &blk, int len,
-                        hipStream_t st)
+hipError_t launch_reset(Ctl *ctl, unsigned long long *rates, hipStream_t st)
 {
-    if (len < 0 || len > (int)sizeof(blk.b)) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, st, ctl, rates, (unsigned char *)dst, blk, len);
+    hipLaunchKernelGGL(reset_kernel, dim3(1), dim3(256), 0, st, ctl, rates);
     return hipGetLastError();
 }
 
@@ -856,6 +877,33 @@ hipError_t launch_batch_stage(int eqn, int bathy, int stage, const BatchSolve *s
     const dim3 g(xcd_grid(grid));
     if (stage == 1) batch_stage_go<1>(eqn, bathy, g, solves, items, nitems, grid, one, st);
     else batch_stage_go<2>(eqn, bathy, g, solves, items, nitems, grid, one, st);
+    return hipGetLastError();
+}
+
+template <int STAGE>
+static void batch_stage_one_go(int eqn, int bathy, dim3 g, const BatchSolve &d, const WorkItem &it, int ntiles,
+                               hipStream_t st)
+{
+    constexpr int TX = Tile<float>::X, TY = Tile<float>::Y;
+    if (eqn == EULER)
+        hipLaunchKernelGGL((batch_stage_one_kernel<float, EULER, false, STAGE>), g,
+                           dim3(StageLds<float, EULER, false, TX, TY>::NTH), 0, st, d, it, ntiles);
+    else if (bathy)
+        hipLaunchKernelGGL((batch_stage_one_kernel<float, SWE, true, STAGE>), g,
+                           dim3(StageLds<float, SWE, true, TX, TY>::NTH), 0, st, d, it, ntiles);
+    else
+        hipLaunchKernelGGL((batch_stage_one_kernel<float, SWE, false, STAGE>), g,
+                           dim3(StageLds<float, SWE, false, TX, TY>::NTH), 0, st, d, it, ntiles);
+}
+
+hipError_t launch_batch_stage_one(int eqn, int bathy, int stage, const BatchSolve &d, const WorkItem &it, int grid,
+                                  hipStream_t st)
+{
+    if (grid <= 0) return hipSuccess;
+    if (it.tile_begin != 0) return hipErrorInvalidValue;
+    const dim3 g(xcd_grid(grid));
+    if (stage == 1) batch_stage_one_go<1>(eqn, bathy, g, d, it, grid, st);
+    else batch_stage_one_go<2>(eqn, bathy, g, d, it, grid, st);
     return hipGetLastError();
 }
 
