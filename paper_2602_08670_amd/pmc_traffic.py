@@ -55,7 +55,7 @@ def _per_kernel(rows, counter):
     return out
 
 
-def summarize(fetch_dir: str, write_dir: str, calib_mb: int, match: str = "batch_stage_kernel<float, 0, true"):
+def summarize(fetch_dir: str, write_dir: str, calib_mb: int, match: str = "batch_stage_one_kernel<float, 0, true"):
     calib_kib = calib_mb * 1024.0
     fetch = _per_kernel(_rows(fetch_dir), "FETCH_SIZE")
     write = _per_kernel(_rows(write_dir), "WRITE_SIZE")
@@ -82,7 +82,7 @@ def main():
     ap.add_argument("fetch_dir")
     ap.add_argument("write_dir")
     ap.add_argument("--calib-mb", type=int, required=True)
-    ap.add_argument("--match", default="batch_stage_kernel<float, 0, true")
+    ap.add_argument("--match", default="batch_stage_one_kernel<float, 0, true")
     ap.add_argument("--out", default="")
     a = ap.parse_args()
     res = summarize(a.fetch_dir, a.write_dir, a.calib_mb, a.match)
