@@ -13,6 +13,8 @@
 // and B.
 #include "cnn_internal.hpp"
 #include "learned_device.hpp"
+#include "euler_learned_device.hpp"
+#include "euler_learned_internal.hpp"
 
 namespace cnn {
 
@@ -1302,19 +1304,27 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
 
 // ------------------------------------------- Euler network, one launch
 // All five layers of the Euler network (4 -> 32 -> 32 -> 32 -> 32 -> 96) for
-// one FT x FT tile per workgroup pass, as fused_tile does for the planar
-// network: the normalised BF16 input region (FT + 10)^2 of the four
+// one output region per workgroup pass, as fused_tile does for the planar
+// network: the normalised BF16 input region (FO + 10)^2 of the four
 // variables and every layer's weights staged in LDS, the activations kept in
-// two LDS buffers, layer l computed on the (FT + 2(4 - l))^2 region.  Per
+// two LDS buffers, layer l computed on the (FO + 2(4 - l))^2 region.  Per
 // output the MFMAs run in the layer-by-layer pass's order (layer 0: K blocks
 // 0, 1; other layers: taps 0..8), with the same bias, ReLU and BF16 rounding,
-// so z is bit-identical to launch_forward_euler's.  Workgroups stride over
-// the B x (H/FT) x (W/FT) tiles, staging the weights once.
+// so z is bit-identical to launch_forward_euler's.
 constexpr int EW0 = 32 * 64 / 8, EWH = 9 * 32 * 32 / 8, EW4 = 9 * 6 * 16 * 32 / 8;  // packed octets per layer
-__global__ __launch_bounds__(FNW * 64) void conv_fused_euler_kernel(const float *q, const char *P, EPacked pk,
-                                                                    ENorm nrm, float *z, int B, int H, int W)
+
+// The output region is the FT x FT tile at (x0, y0) (FO = FT: z written to
+// zb, [H][W][96]) or the tile and its low halo row and column (FO = FT + 1,
+// ZLDS: z kept in LDS as [FO*FO][96] from (x0 - 1, y0 - 1) and returned, and
+// the FP32 stage input with a three-cell halo in qf, [4][FT+6][FT+6] from
+// (x0 - 3, y0 - 3)).  load_w: stage the weights (the workgroup's first tile).
+template <int FO, bool ZLDS>
+__device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *P, const EPacked &pk,
+                                                   const ENorm &nrm, float *zb, int H, int W, int y0, int x0,
+                                                   bool load_w, float *qf)
 {
-    constexpr int FRI_ = FT + 10, FR0_ = FT + 8;
+    static_assert(FO == FT || (FO == FT + 1 && ZLDS), "output region: the tile, or the tile and its low halo");
+    constexpr int OFF = FO - FT, FRI_ = FO + 10, FR0_ = FO + 8;
     __shared__ bf16 s_in[E_CIN][FRI_ * FRI_];
     __shared__ bf16x8 s_act[FR0_ * FR0_ * 4 + (FR0_ - 2) * (FR0_ - 2) * 4];
     __shared__ bf16x8 s_wall[EW0 + 3 * EWH + EW4];
@@ -1323,132 +1333,261 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_euler_kernel(const float 
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, px = lane & 15;
     const size_t hw = (size_t)H * W;
-    const int tx_n = W / FT, ty_n = H / FT, total = B * tx_n * ty_n;
-    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
-        const bool load_w = tile == (int)blockIdx.x;
-        if (!load_w) __syncthreads();  // the previous tile's LDS reads are done
-        const int b = tile / (tx_n * ty_n);
-        const int rt = tile - b * tx_n * ty_n;
-        const int y0 = (rt / tx_n) * FT, x0 = (rt % tx_n) * FT;
-        const float *qb = q + (size_t)b * E_CIN * hw;
-        float *zb = z + (size_t)b * hw * E_COUT;
-        const int ry0 = y0 - 5, rx0 = x0 - 5;
-        // every global load (input region, weights) before the first LDS store
-        constexpr int NIN = E_CIN * FRI_ * FRI_, TIN = (NIN + FNW * 64 - 1) / (FNW * 64);
-        float xin[TIN];
+    const int ry0 = y0 - OFF - 5, rx0 = x0 - OFF - 5;
+    // every global load (input region, weights) before the first LDS store
+    constexpr int NIN = E_CIN * FRI_ * FRI_, TIN = (NIN + FNW * 64 - 1) / (FNW * 64);
+    float xin[TIN];
 #pragma unroll
-        for (int k = 0; k < TIN; k++) {
-            const int i = threadIdx.x + k * FNW * 64;
-            if (i < NIN) {
-                const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
-                const int ry = r / FRI_, rx = r - ry * FRI_;
-                xin[k] = qb[(size_t)ci * hw + (size_t)wrap(ry0 + ry, H) * W + wrap(rx0 + rx, W)];
+    for (int k = 0; k < TIN; k++) {
+        const int i = threadIdx.x + k * FNW * 64;
+        if (i < NIN) {
+            const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
+            const int ry = r / FRI_, rx = r - ry * FRI_;
+            xin[k] = qb[(size_t)ci * hw + (size_t)wrap(ry0 + ry, H) * W + wrap(rx0 + rx, W)];
+        }
+    }
+    Chunks<EW0> c0;
+    Chunks<EWH> c1, c2, c3;
+    Chunks<EW4> c4;
+    if (load_w) {
+        c0.load(P, pk.w[0]);
+        c1.load(P, pk.w[1]);
+        c2.load(P, pk.w[2]);
+        c3.load(P, pk.w[3]);
+        c4.load(P, pk.w[4]);
+    }
+#pragma unroll
+    for (int k = 0; k < TIN; k++) {
+        const int i = threadIdx.x + k * FNW * 64;
+        if (i < NIN) {
+            const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
+            s_in[ci][r] = (bf16)((xin[k] - nrm.mean[ci]) * nrm.inv_std[ci]);
+            if (ZLDS) {
+                // the halo's corner (x0 - 3, y0 - 3) is 2 + OFF cells into the input region
+                constexpr int QS = FT + 6, QO = 2 + OFF;
+                const int rr = r / FRI_, ry = rr - QO, rx = r - rr * FRI_ - QO;
+                if (ry >= 0 && ry < QS && rx >= 0 && rx < QS) qf[(ci * QS + ry) * QS + rx] = xin[k];
             }
         }
-        Chunks<EW0> c0;
-        Chunks<EWH> c1, c2, c3;
-        Chunks<EW4> c4;
-        if (load_w) {
-            c0.load(P, pk.w[0]);
-            c1.load(P, pk.w[1]);
-            c2.load(P, pk.w[2]);
-            c3.load(P, pk.w[3]);
-            c4.load(P, pk.w[4]);
-        }
+    }
+    if (load_w) {
+        c0.store(s_wall);
+        c1.store(s_wall + EW0);
+        c2.store(s_wall + EW0 + EWH);
+        c3.store(s_wall + EW0 + 2 * EWH);
+        c4.store(s_wall + EW0 + 3 * EWH);
+    }
+    __syncthreads();
+    // layer 0 on the FR0_ x FR0_ region: K = 36 (tap*4 + ci) in two blocks
+    {
+        const float *bias = (const float *)(P + pk.b[0]);
+        constexpr int NP0 = FR0_ * FR0_, NG0 = (NP0 + 15) / 16;
+        for (int gi = wave; gi < NG0; gi += FNW) {
+            const int p = gi * 16 + px;
+            const int pc = p < NP0 ? p : 0;
+            const int py = pc / FR0_, pxx = pc - py * FR0_;
+            bf16x8 bx[2];
 #pragma unroll
-        for (int k = 0; k < TIN; k++) {
-            const int i = threadIdx.x + k * FNW * 64;
-            if (i < NIN) {
-                const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
-                s_in[ci][r] = (bf16)((xin[k] - nrm.mean[ci]) * nrm.inv_std[ci]);
-            }
-        }
-        if (load_w) {
-            c0.store(s_wall);
-            c1.store(s_wall + EW0);
-            c2.store(s_wall + EW0 + EWH);
-            c3.store(s_wall + EW0 + 2 * EWH);
-            c4.store(s_wall + EW0 + 3 * EWH);
-        }
-        __syncthreads();
-        // layer 0 on the FR0_ x FR0_ region: K = 36 (tap*4 + ci) in two blocks
-        {
-            const float *bias = (const float *)(P + pk.b[0]);
-            constexpr int NP0 = FR0_ * FR0_, NG0 = (NP0 + 15) / 16;
-            for (int gi = wave; gi < NG0; gi += FNW) {
-                const int p = gi * 16 + px;
-                const int pc = p < NP0 ? p : 0;
-                const int py = pc / FR0_, pxx = pc - py * FR0_;
-                bf16x8 bx[2];
+            for (int kb = 0; kb < 2; kb++)
+#pragma unroll
+                for (int e = 0; e < 8; e++) {
+                    const int kk = 32 * kb + 8 * g + e;
+                    bf16 v = (bf16)0.0f;
+                    if (kk < 9 * E_CIN) {
+                        const int tap = kk / E_CIN, ci = kk - E_CIN * tap;
+                        v = s_in[ci][(py + tap / 3) * FRI_ + pxx + tap % 3];
+                    }
+                    bx[kb][e] = v;
+                }
+#pragma unroll
+            for (int t = 0; t < 2; t++) {
+                floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
                 for (int kb = 0; kb < 2; kb++)
+                    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_wall[(t * 16 + px) * 8 + kb * 4 + g], bx[kb], acc,
+                                                                  0, 0, 0);
+                if (p < NP0) {
+                    const int co0 = 16 * t + 4 * g;
+                    bf16x4 o;
 #pragma unroll
-                    for (int e = 0; e < 8; e++) {
-                        const int kk = 32 * kb + 8 * g + e;
-                        bf16 v = (bf16)0.0f;
-                        if (kk < 9 * E_CIN) {
-                            const int tap = kk / E_CIN, ci = kk - E_CIN * tap;
-                            v = s_in[ci][(py + tap / 3) * FRI_ + pxx + tap % 3];
-                        }
-                        bx[kb][e] = v;
-                    }
-#pragma unroll
-                for (int t = 0; t < 2; t++) {
-                    floatx4 acc = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-                    for (int kb = 0; kb < 2; kb++)
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_wall[(t * 16 + px) * 8 + kb * 4 + g], bx[kb], acc,
-                                                                      0, 0, 0);
-                    if (p < NP0) {
-                        const int co0 = 16 * t + 4 * g;
-                        bf16x4 o;
-#pragma unroll
-                        for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[i] + bias[co0 + i], 0.0f);
-                        *(bf16x4 *)((bf16 *)s_a0 + (size_t)p * 32 + co0) = o;
-                    }
+                    for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[i] + bias[co0 + i], 0.0f);
+                    *(bf16x4 *)((bf16 *)s_a0 + (size_t)p * 32 + co0) = o;
                 }
             }
         }
-        // hidden layers 1..3: s_a0 -> s_a1 -> s_a0 -> s_a1
+    }
+    // hidden layers 1..3: s_a0 -> s_a1 -> s_a0 -> s_a1
 #pragma unroll
-        for (int l = 1; l < 4; l++) {
-            __syncthreads();
-            const int rin = FR0_ - 2 * (l - 1);
-            const bf16x8 *in = (l & 1) ? s_a0 : s_a1;
-            bf16 *out = (bf16 *)((l & 1) ? s_a1 : s_a0);
-            fused_hidden(in, rin, out, s_wall + EW0 + (l - 1) * EWH, (const float *)(P + pk.b[l]), wave, lane);
-        }
+    for (int l = 1; l < 4; l++) {
         __syncthreads();
-        // layer 4: s_a1 (FT + 2)^2 -> z on the tile, pixel groups wave, wave +
-        // FNW, ... with all six co tiles, each chain in tap order
-        {
-            constexpr int NT = 6, RIN = FT + 2, NPX = FT * FT, NG = (NPX + 15) / 16;
-            const bf16x8 *s_w = s_wall + EW0 + 3 * EWH;
-            const float *bias = (const float *)(P + pk.b[4]);
-            for (int gi = wave; gi < NG; gi += FNW) {  // wave-uniform: an MFMA does not honour a partial EXEC
-                floatx4 acc[NT];
+        const int rin = FR0_ - 2 * (l - 1);
+        const bf16x8 *in = (l & 1) ? s_a0 : s_a1;
+        bf16 *out = (bf16 *)((l & 1) ? s_a1 : s_a0);
+        fused_hidden(in, rin, out, s_wall + EW0 + (l - 1) * EWH, (const float *)(P + pk.b[l]), wave, lane);
+    }
+    __syncthreads();
+    // layer 4: s_a1 (FO + 2)^2 -> z on the FO x FO region, pixel groups wave,
+    // wave + FNW, ... with all six co tiles, each chain in tap order.  ZLDS:
+    // z over the activations ([FO*FO][96] covers s_a0 and the start of s_a1),
+    // stored after every wave's layer-4 reads
+    float *s_z = (float *)s_act;
+    static_assert(!ZLDS || FO * FO * E_COUT * 4 <= sizeof(s_act), "coefficient region fits over the activations");
+    {
+        constexpr int NT = 6, RIN = FO + 2, NPX = FO * FO, NG = (NPX + 15) / 16, GPW = (NG + FNW - 1) / FNW;
+        const bf16x8 *s_w = s_wall + EW0 + 3 * EWH;
+        const float *bias = (const float *)(P + pk.b[4]);
+        floatx4 acc[GPW][NT];
 #pragma unroll
-                for (int t = 0; t < NT; t++) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
-                const int p = gi * 16 + px;
-                const int py = p / FT, pxx = p - py * FT;
+        for (int k = 0; k < GPW; k++) {
+#pragma unroll
+            for (int t = 0; t < NT; t++) acc[k][t] = floatx4{0.f, 0.f, 0.f, 0.f};
+            const int gi = wave + k * FNW, p = gi * 16 + px;
+            if (gi < NG) {  // wave-uniform, a real branch: an MFMA does not honour a partial EXEC
+                const int pc = p < NPX ? p : 0;
+                const int py = pc / FO, pxx = pc - py * FO;
                 const int bo = (py * RIN + pxx) * 4 + g;
 #pragma unroll
                 for (int tap = 0; tap < 9; tap++) {
                     const bf16x8 bx = s_a1[bo + ((tap / 3) * RIN + tap % 3) * 4];
 #pragma unroll
                     for (int t = 0; t < NT; t++)
-                        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * 4 + g], bx,
-                                                                         acc[t], 0, 0, 0);
+                        acc[k][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * 4 + g],
+                                                                            bx, acc[k][t], 0, 0, 0);
                 }
+            }
+        }
+        if (ZLDS) __syncthreads();
+#pragma unroll
+        for (int k = 0; k < GPW; k++) {
+            const int gi = wave + k * FNW, p = gi * 16 + px;
+            if (gi < NG && p < NPX) {
+                const int py = p / FO, pxx = p - py * FO;
 #pragma unroll
                 for (int t = 0; t < NT; t++) {
                     const int co0 = 16 * t + 4 * g;
                     floatx4 o;
 #pragma unroll
-                    for (int i = 0; i < 4; i++) o[i] = acc[t][i] + bias[co0 + i];
-                    *(floatx4 *)(zb + ((size_t)(y0 + py) * W + x0 + pxx) * E_COUT + co0) = o;
+                    for (int i = 0; i < 4; i++) o[i] = acc[k][t][i] + bias[co0 + i];
+                    if (ZLDS) *(floatx4 *)(s_z + p * E_COUT + co0) = o;
+                    else *(floatx4 *)(zb + ((size_t)(y0 + py) * W + x0 + pxx) * E_COUT + co0) = o;
                 }
             }
+        }
+    }
+    if (ZLDS) __syncthreads();
+    return s_z;
+}
+
+// Workgroups stride over the B x (H/FT) x (W/FT) tiles, staging the weights
+// once.
+__global__ __launch_bounds__(FNW * 64) void conv_fused_euler_kernel(const float *q, const char *P, EPacked pk,
+                                                                    ENorm nrm, float *z, int B, int H, int W)
+{
+    const size_t hw = (size_t)H * W;
+    const int tx_n = W / FT, ty_n = H / FT, total = B * tx_n * ty_n;
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const bool load_w = tile == (int)blockIdx.x;
+        if (!load_w) __syncthreads();  // the previous tile's LDS reads are done
+        const int b = tile / (tx_n * ty_n);
+        const int rt = tile - b * tx_n * ty_n;
+        fused_tile_euler<FT, false>(q + (size_t)b * E_CIN * hw, P, pk, nrm, z + (size_t)b * hw * E_COUT, H, W,
+                                    (rt / tx_n) * FT, (rt % tx_n) * FT, load_w, nullptr);
+    }
+}
+
+// Network pass and learned Euler stage (the learned Euler stage kernel's
+// MODE 0 arithmetic) of one stage for B solves, one FT x FT tile per
+// workgroup pass: the coefficients of the tile and its low halo stay in LDS,
+// each face projects its owner's 48, forms both states with the per-side
+// admissibility fallback and takes the Euler flux; one x face, one y face and
+// one cell per thread.  Frozen solves are skipped.  Flags and fallback counts
+// as the stage kernel's.
+template <int FLUX>
+__global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::StageArgs a, const char *P, EPacked pk,
+                                                                      ENorm nrm)
+{
+    constexpr int TX = FT, TY = FT, QS = FT + 6, FO = FT + 1;
+    constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX, YB = 128;  // y faces start at thread YB
+    static_assert(NFX <= YB && YB + NFY <= FNW * 64 && TX * TY <= FNW * 64, "one face or cell per thread");
+    __shared__ float s_qf[4 * QS * QS];
+    __shared__ float s_fx[4][TY][TX + 1];
+    __shared__ float s_fy[4][TY + 1][TX];
+    __shared__ int s_cnt, s_bad;
+    const int nx = a.nx, ny = a.ny, tid = threadIdx.x;
+    const size_t plane = (size_t)nx * ny;
+    const int tx_n = nx / FT, ty_n = ny / FT, total = a.B * tx_n * ty_n;
+    bool staged = false;  // this workgroup's weights are in LDS
+    for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
+        const int b = tile / (tx_n * ty_n);
+        if (a.fatal[b]) continue;  // frozen solve (wave-uniform)
+        if (staged) __syncthreads();  // the previous tile's LDS reads are done
+        const int rt = tile - b * tx_n * ty_n;
+        const int y0 = (rt / tx_n) * FT, x0 = (rt % tx_n) * FT;
+        const float *s_z = fused_tile_euler<FO, true>(a.qs + (size_t)b * 4 * plane, P, pk, nrm, nullptr, ny, nx, y0,
+                                                      x0, !staged, s_qf);
+        staged = true;
+        int *flag = a.flags + 2 * b + a.parity;
+        // stage 2 of a solve whose stage 1 failed is evaluated (its result is
+        // discarded by the redo) but its fallback sides are not counted
+        const bool count = !(a.flagbit == 2 && (*flag & 1));
+        if (tid == 0) {
+            s_cnt = 0;
+            s_bad = 0;
+        }
+        int nfb = 0;
+        if (tid < NFX) {
+            // x face: owner cell (x0 - 1 + xi, y0 + xj), pixel (xi, xj + 1) of the coefficient region
+            const int xj = tid / (TX + 1), xi = tid - xj * (TX + 1);
+            float st[4][6];
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+#pragma unroll
+                for (int k = 0; k < 6; k++) st[v][k] = s_qf[(v * QS + xj + 3) * QS + xi + k];
+            float QL[4], QR[4], F[4];
+            const int c = eln::face_states<true>(st, s_z + ((xj + 1) * FO + xi) * E_COUT, a.pr, a.gamma, QL, QR);
+            if (xi < TX) nfb += c;  // counted once: as a cell's low face
+            eln::flux4<FLUX, 0>(QL, QR, a.gamma, F);
+#pragma unroll
+            for (int v = 0; v < 4; v++) s_fx[v][xj][xi] = F[v];
+        }
+        if (tid >= YB && tid < YB + NFY) {
+            // y face: owner cell (x0 + yi, y0 - 1 + yj), pixel (yi + 1, yj)
+            const int f = tid - YB, yj = f / TX, yi = f - yj * TX;
+            float st[4][6];
+#pragma unroll
+            for (int v = 0; v < 4; v++)
+#pragma unroll
+                for (int k = 0; k < 6; k++) st[v][k] = s_qf[(v * QS + yj + k) * QS + yi + 3];
+            float QL[4], QR[4], F[4];
+            const int c = eln::face_states<true>(st, s_z + (yj * FO + yi + 1) * E_COUT + 48, a.pr, a.gamma, QL, QR);
+            if (yj < TY) nfb += c;
+            eln::flux4<FLUX, 1>(QL, QR, a.gamma, F);
+#pragma unroll
+            for (int v = 0; v < 4; v++) s_fy[v][yj][yi] = F[v];
+        }
+        __syncthreads();
+        bool bad = false;
+        if (tid < TX * TY) {
+            const int cy = tid / TX, cx = tid - cy * TX;
+            const size_t idx = (size_t)b * 4 * plane + (size_t)(y0 + cy) * nx + x0 + cx;
+            float qn[4];
+#pragma unroll
+            for (int v = 0; v < 4; v++) {
+                const float L = -(s_fx[v][cy][cx + 1] - s_fx[v][cy][cx]) * a.rdx -
+                                (s_fy[v][cy + 1][cx] - s_fy[v][cy][cx]) * a.rdy;
+                float o = a.a1 * (s_qf[(v * QS + cy + 3) * QS + cx + 3] + a.dt * L);
+                if (a.a0 != 0.0f) o = a.a0 * a.q0[idx + v * plane] + o;
+                a.out[idx + v * plane] = o;
+                qn[v] = o;
+            }
+            bad = !eln::admissible(qn, a.gamma);
+        }
+        if (count && nfb) atomicAdd(&s_cnt, nfb);
+        if (bad) s_bad = 1;
+        __syncthreads();
+        if (tid == 0) {
+            if (s_cnt) atomicAdd(&a.nfb[b], (unsigned long long)s_cnt);
+            if (s_bad) atomicOr(flag, a.flagbit);
         }
     }
 }
@@ -1460,9 +1599,16 @@ int fused_euler_grid()
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
     if (!cache[dev]) {
         int cus = 0, m = 0;
+        int m1 = 0, m2 = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
-            hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, conv_fused_euler_kernel, FNW * 64, 0) != hipSuccess)
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, conv_fused_euler_kernel, FNW * 64, 0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&m1, conv_learned_euler_kernel<fvk::HLLE>, FNW * 64, 0) !=
+                hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&m2, conv_learned_euler_kernel<fvk::RUSANOV>, FNW * 64, 0) !=
+                hipSuccess)
             return 256;
+        m = m < m1 ? m : m1;
+        m = m < m2 ? m : m2;
         cache[dev] = (m > 0 ? m : 1) * (cus > 0 ? cus : 256);
     }
     return cache[dev];
@@ -1476,6 +1622,21 @@ hipError_t launch_forward_euler_fused(const void *packed, const ENorm &nrm, cons
     const int cap = fused_euler_grid();
     hipLaunchKernelGGL(conv_fused_euler_kernel, dim3((unsigned)(tiles < cap ? tiles : cap)), dim3(FNW * 64), 0, st,
                        q, (const char *)packed, euler_packed_layout(), nrm, z, B, ny, nx);
+    return hipGetLastError();
+}
+
+hipError_t launch_learned_euler(int flux, const void *packed, const ENorm &nrm, const eln::StageArgs &a, hipStream_t st)
+{
+    if (a.nx % FT || a.ny % FT || a.B < 1 || (a.flagbit != 1 && a.flagbit != 2)) return hipErrorInvalidValue;
+    const int tiles = a.B * (a.nx / FT) * (a.ny / FT);
+    const int cap = fused_euler_grid();
+    const dim3 g((unsigned)(tiles < cap ? tiles : cap));
+    if (flux == fvk::RUSANOV)
+        hipLaunchKernelGGL(conv_learned_euler_kernel<fvk::RUSANOV>, g, dim3(FNW * 64), 0, st, a, (const char *)packed,
+                           euler_packed_layout(), nrm);
+    else
+        hipLaunchKernelGGL(conv_learned_euler_kernel<fvk::HLLE>, g, dim3(FNW * 64), 0, st, a, (const char *)packed,
+                           euler_packed_layout(), nrm);
     return hipGetLastError();
 }
 

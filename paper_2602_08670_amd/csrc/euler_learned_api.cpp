@@ -177,16 +177,25 @@ fv_status fv_euler_learned_step(fv_euler_learned *e, float *q, int64_t nsteps)
                      : cnn::launch_forward_euler(ws + L.packed, e->nrm, in, c.B, c.nx, c.ny, ws + L.act0, ws + L.act1,
                                                  z, e->stream);
     };
+    // network pass and learned stage in one launch per stage where the grid
+    // is whole 8 x 8 tiles and every tile gets a workgroup of its own (with
+    // more tiles a workgroup would run several tiles' network passes and face
+    // epilogues in turn: the separate launches spread the stage wider), else
+    // the network pass and the stage kernel
+    const bool fused = tiled && (int64_t)c.B * (c.nx / 8) * (c.ny / 8) <= cnn::fused_euler_grid();
+    auto learned = [&]() {
+        if (fused) return cnn::launch_learned_euler(fl, ws + L.packed, e->nrm, a, e->stream);
+        hipError_t r = net(a.qs);
+        return r == hipSuccess ? eln::stage(0, fl, a, e->stream) : r;
+    };
     for (int64_t k = 0; k < nsteps && h == hipSuccess; k++) {
         a.parity = (int)(e->steps_enq & 1);
         // stage 1: S1 = q + dt L(q)
-        h = net(q);
         a.qs = q; a.q0 = q; a.out = S1; a.a0 = 0.f; a.a1 = 1.f; a.flagbit = 1;
-        if (h == hipSuccess) h = eln::stage(0, fl, a, e->stream);
+        h = learned();
         // stage 2: S2 = q/2 + (S1 + dt L(S1))/2
-        if (h == hipSuccess) h = net(S1);
         a.qs = S1; a.q0 = q; a.out = S2; a.a0 = 0.5f; a.a1 = 0.5f; a.flagbit = 2;
-        if (h == hipSuccess) h = eln::stage(0, fl, a, e->stream);
+        if (h == hipSuccess) h = learned();
         // admissible solves commit S2; the others redo the step plainly
         a.qs = q; a.q0 = q; a.out = S1; a.a0 = 0.f; a.a1 = 1.f; a.commit_src = S2; a.commit_dst = q;
         if (h == hipSuccess) h = eln::stage(2, fl, a, e->stream);

@@ -47,3 +47,14 @@ struct AdjArgs {
 hipError_t adjoint(int flux, const AdjArgs &a, float *gqs, float a1, int accumulate, hipStream_t st);
 
 }  // namespace eln
+
+namespace cnn {
+// The network pass and the learned stage (MODE 0 of eln::stage, the same
+// arithmetic) of one stage in one launch, for grids of whole 8 x 8 tiles:
+// a.qs is the stage input and the network's, the coefficients stay in LDS
+// (a.z unused); a.flagbit is the stage (1 or 2).
+hipError_t launch_learned_euler(int flux, const void *packed, const ENorm &nrm, const eln::StageArgs &a,
+                                hipStream_t st);
+// Workgroups of the one-launch Euler network pass resident at once.
+int fused_euler_grid();
+}  // namespace cnn

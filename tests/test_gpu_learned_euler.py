@@ -171,6 +171,35 @@ def test_batch_equals_single(fv, E):
     assert np.array_equal(outs[0][1], outs[1][0])
 
 
+def test_fused_stage_equals_separate_launches(fv, E):
+    """A batch whose tiles outnumber the resident workgroups runs the network
+    pass and the learned stage as separate launches; one solve runs them
+    fused in one launch per stage.  The same bits per solve, over steps with
+    fallbacks."""
+    p = oracle_params(E, 7, scale_last=10.0)
+    B, n = 20, 64  # 20 x 64 tiles of 8 x 8 exceed one workgroup per CU
+    q0 = states(list(range(40, 40 + B)), n)
+    kin = 0.5 * (q0[:, 1] ** 2 + q0[:, 2] ** 2) / q0[:, 0]
+    q0[:, 3] = kin + 0.1 * (q0[:, 3] - kin)  # low pressure: some learned sides fall back
+    net = gpu_net(fv, p, B, n, 5e-4)
+    q = torch.tensor(q0, device="cuda").contiguous()
+    net.step(q, 6)
+    fb, _, _, _ = net.stats()
+    batched = q.cpu().numpy()
+    net.close()
+    print(f"[euler fused] batch of {B}: fallback sides {int(fb.sum())}", flush=True)
+    assert fb.sum() > 0
+    for b in (0, 7, B - 1):
+        one = gpu_net(fv, p, 1, n, 5e-4)
+        q1 = torch.tensor(q0[b:b + 1], device="cuda").contiguous()
+        one.step(q1, 6)
+        fb1, _, _, _ = one.stats()
+        one.close()
+        print(f"[euler fused] solve {b}: fallback sides {fb[b]} / alone {fb1[0]}", flush=True)
+        assert np.array_equal(q1.cpu().numpy()[0], batched[b])
+        assert fb1[0] == fb[b]
+
+
 def test_invalid_configurations_rejected(fv):
     vec = np.zeros(fv.lib.fv_euler_net_param_count(), dtype=np.float32)
     for kw in (dict(nx=40), dict(flux=fv.FV_FLUX_ROE), dict(dt=0.0)):
