@@ -515,7 +515,6 @@ __device__ __forceinline__ TileRef batch_resolve(const BatchSolve *__restrict__ 
                                                  const WorkItem *__restrict__ items, const int *__restrict__ nitems,
                                                  const int w, const int one, StageArgs<T> &a)
 {
-    constexpr int TX = Tile<T>::X, TY = Tile<T>::Y;
     // one != 0: the list is known to hold one solve, solves[0] (a single
     // solve stepping through this kernel); its descriptor and list entry are
     // then fetched together instead of one after the other

@@ -18,7 +18,7 @@ namespace {
 struct SphLayout {
     size_t ctl, rates, totals_out, partials;
     size_t cen, nsum, inv_area, rate_fac, area, xf, yf;
-    size_t fx, fy, s1, s2;
+    size_t s1, s2;
     size_t total;
 };
 
@@ -45,8 +45,6 @@ SphLayout sph_layout(const fv_sphere_config *c)
     L.area = take(P * sizeof(double));
     L.xf = take(10 * P * es);
     L.yf = take(10 * PY * es);
-    L.fx = take(4 * P * es);
-    L.fy = take(4 * PY * es);
     L.s1 = take(4 * P * es);
     L.s2 = take(c->rk_stages == 3 ? 4 * P * es : 0);
     L.total = o;
@@ -103,17 +101,11 @@ template <typename T> hipError_t stage(fv_sphere *s, const T *qs, T *out, double
                                        int ro, int rc)
 {
     const fv_sphere_config &c = s->cfg;
-    sph::Geometry<T> G = geometry_of<T>(s->ws, s->L);
-    T *fx = (T *)(s->ws + s->L.fx), *fy = (T *)(s->ws + s->L.fy);
-    hipError_t e = sph::faces<T>(c.flux, c.recon, qs, G, fx, fy, c.n, c.g, s->stream);
-    if (e != hipSuccess) return e;
     sph::CellArgs<T> a;
     a.qs = qs;
     a.q0 = (const T *)s->q;
     a.out = out;
-    a.fx = fx;
-    a.fy = fy;
-    a.G = G;
+    a.G = geometry_of<T>(s->ws, s->L);
     a.n = c.n;
     a.g = (T)c.g;
     a.omega = (T)c.omega;
@@ -127,7 +119,7 @@ template <typename T> hipError_t stage(fv_sphere *s, const T *qs, T *out, double
     a.rate_out = ro;
     a.rate_clear = rc;
     a.last = last;
-    return sph::cells<T>(a, s->stream);
+    return sph::stage<T>(c.flux, c.recon, a, s->stream);
 }
 
 template <typename T> hipError_t step(fv_sphere *s)

@@ -23,7 +23,6 @@ template <typename T> struct Geometry {
 template <typename T> struct CellArgs {
     const T *qs, *q0;
     T *out;
-    const T *fx, *fy;  // face fluxes times edge length [4][...]
     Geometry<T> G;
     int n;
     T g, omega, a0, a1;
@@ -34,9 +33,8 @@ template <typename T> struct CellArgs {
 };
 
 template <typename T> hipError_t geometry(const Geometry<T> &G, int n, hipStream_t st);
-template <typename T>
-hipError_t faces(int flux, int recon, const T *q, const Geometry<T> &G, T *fx, T *fy, int n, double g, hipStream_t st);
-template <typename T> hipError_t cells(const CellArgs<T> &a, hipStream_t st);
+// One Runge-Kutta stage (a.qs -> a.out) in one launch over tiles of cells.
+template <typename T> hipError_t stage(int flux, int recon, const CellArgs<T> &a, hipStream_t st);
 template <typename T>
 hipError_t rate(const T *q, const Geometry<T> &G, int n, double g, fvk::Ctl *ctl, unsigned long long *rates, int slot,
                 hipStream_t st);

@@ -19,11 +19,12 @@
 // sphere), and after every stage its momentum is projected onto the tangent
 // plane at its centre (the tangency forcing of eq 3.2).
 //
-// Kernels: geometry (once, in double precision), face fluxes (one thread
-// per face, each face once per stage, fluxes times edge length to a buffer),
-// cell update (divergence, correction, source, Runge-Kutta combine,
-// projection; on the last stage the CFL rate of the new state, reduced on
-// the device as in the planar stage kernels).
+// Kernels: geometry (once, in double precision); one launch per stage on
+// tiles of cells, the state and a two-cell halo in LDS, each face of the tile
+// evaluated once into LDS (fluxes times edge length), then the cell update
+// (divergence, correction, source, Runge-Kutta combine, projection; on the
+// last stage the CFL rate of the new state, reduced on the device as in the
+// planar stage kernels).
 #include <hip/hip_runtime.h>
 
 #include "fv_device.hpp"
@@ -251,40 +252,29 @@ __device__ __forceinline__ void numflux4(const T *L, const T *R, T g, T *F)
     F[3] = T(0.5) * (fl[3] + fr[3]) - T(0.5) * (l1 * wa + l2 * ar + l3 * wa);
 }
 
-// One thread per face: x faces k < nx*ny (the low face of cell k), then y
-// faces (nx*(ny+1), row J between rows J-1 and J).  Writes the flux times the
-// edge length, Cartesian, along the face's normal.
-template <typename T, int FLUX, int RECON>
-__global__ __launch_bounds__(256) void face_kernel(const T *__restrict__ q, Geometry<T> G, T *__restrict__ fx,
-                                                   T *__restrict__ fy, int n, T g)
+// ------------------------------------------------------------ stage tiles
+
+__device__ __forceinline__ unsigned long long dmax_bits(double v) { return (unsigned long long)__double_as_longlong(v); }
+
+template <typename T>
+__device__ __forceinline__ T wave_max(T v)
 {
-    const int nx = 2 * n, ny = n;
-    const int ncell = nx * ny, nyface = nx * (ny + 1);
-    const int k = blockIdx.x * 256 + threadIdx.x;
-    if (k >= ncell + nyface) return;
-    const bool xface = k < ncell;
-    const int f = xface ? k : k - ncell;
-    const int j = f / nx, i = f - j * nx;
-    // stencil cells along the normal index line: low-1, low, high, high+1
-    int idx[4];
-    if (xface) {
 #pragma unroll
-        for (int s = 0; s < 4; s++) idx[s] = cell_of(i - 2 + s, j, nx, ny);
-    } else {
-#pragma unroll
-        for (int s = 0; s < 4; s++) idx[s] = cell_of(i, j - 2 + s, nx, ny);
-    }
-    const size_t plane = (size_t)ncell;
+    for (int off = 32; off > 0; off >>= 1) v = fvk::tmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Flux of one face from the four stencil values c[v][0..3] along its index
+// line (low-1, low, high, high+1) and its frame F9 (n, t, r, length at
+// entry f of planes fp apart): MINMOD (or first-order) face states rotated
+// into (n, t, r), the 1D numerical flux along n with the t and r momenta
+// transported, rotated back and multiplied by the edge length.
+template <typename T, int FLUX, int RECON>
+__device__ __forceinline__ void face_flux(const T (*c)[4], const T *__restrict__ F9, size_t fp, int f, T g, T *out)
+{
     T QL[4], QR[4];
 #pragma unroll
-    for (int v = 0; v < 4; v++) {
-        T c[4];
-#pragma unroll
-        for (int s = 0; s < 4; s++) c[s] = q[v * plane + idx[s]];
-        fvk::recon_pair<T, RECON>(c[0], c[1], c[2], c[3], QL[v], QR[v]);
-    }
-    const T *F9 = xface ? G.xf : G.yf;
-    const size_t fp = xface ? plane : (size_t)nyface;
+    for (int v = 0; v < 4; v++) fvk::recon_pair<T, RECON>(c[v][0], c[v][1], c[v][2], c[v][3], QL[v], QR[v]);
     T nn[3], t[3], r[3];
 #pragma unroll
     for (int d = 0; d < 3; d++) {
@@ -299,55 +289,107 @@ __global__ __launch_bounds__(256) void face_kernel(const T *__restrict__ q, Geom
                QR[1] * r[0] + QR[2] * r[1] + QR[3] * r[2]};
     T F[4];
     numflux4<T, FLUX>(sl, sr, g, F);
-    T *out = xface ? fx : fy;
-    out[f] = len * F[0];
+    out[0] = len * F[0];
 #pragma unroll
-    for (int d = 0; d < 3; d++) out[(1 + d) * fp + f] = len * (F[1] * nn[d] + F[2] * t[d] + F[3] * r[d]);
+    for (int d = 0; d < 3; d++) out[1 + d] = len * (F[1] * nn[d] + F[2] * t[d] + F[3] * r[d]);
 }
 
-// ------------------------------------------------------------ cell update
+// One Runge-Kutta stage, out = a0 q0 + a1 (qs + dt L(qs)) with the momentum
+// then projected onto the tangent plane, on an STX x STY tile of cells per
+// workgroup: the state with a two-cell halo (periodic in x, mirrored across
+// y = -+1, as cell_of) staged in LDS; every face of the tile evaluated once
+// into LDS (a face on a tile edge is evaluated by both tiles: the same
+// value); then one cell per thread: flux divergence, eq 3.1 correction
+// against the cell's summed edge normals, Coriolis (eq 3.2), the combine and
+// the projection.  Face fluxes never reach HBM.  The last stage reduces the
+// CFL rate of out into slot rate_out, clears slot rate_clear, flags
+// inadmissible cells and advances time and step count.
+constexpr int STX = 32, STY = 8, SNT = STX * STY;
 
-__device__ __forceinline__ unsigned long long dmax_bits(double v) { return (unsigned long long)__double_as_longlong(v); }
-
-template <typename T>
-__device__ __forceinline__ T wave_max(T v)
+// Workgroups are handed to the eight XCDs in turn: for a grid that is a
+// multiple of 8, XCD k gets the contiguous k-th eighth of the tiles, so that
+// neighbouring tiles, which re-read each other's halo cells, share one L2.
+__device__ __forceinline__ int xcd_tile(int w, int grid)
 {
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v = fvk::tmax(v, __shfl_xor(v, off, 64));
-    return v;
+    return (grid & 7) ? w : (w & 7) * (grid >> 3) + (w >> 3);
 }
 
-// out = a0 q0 + a1 (qs + dt L(qs)) with the momentum then projected onto the
-// tangent plane; the last stage reduces the CFL rate of out into slot
-// rate_out, clears slot rate_clear, flags inadmissible cells and advances
-// time and step count.
-template <typename T>
-__global__ __launch_bounds__(256) void cell_kernel(CellArgs<T> a)
+template <typename T, int FLUX, int RECON>
+__global__ __launch_bounds__(SNT) void tile_kernel(CellArgs<T> a, int tiles_x)
 {
+    constexpr int HX = STX + 4, HY = STY + 4;
+    __shared__ T s_q[4][HY][HX];
+    __shared__ T s_fx[4][STY][STX + 1];
+    __shared__ T s_fy[4][STY + 1][STX];
     __shared__ double s_dt;
     const int nx = 2 * a.n, ny = a.n;
     const int ncell = nx * ny, nyface = nx * (ny + 1);
     const size_t plane = (size_t)ncell;
+    const int tid = threadIdx.x;
+    const int w = xcd_tile(blockIdx.x, gridDim.x);
+    const int ty = w / tiles_x, tx = w - ty * tiles_x;
+    const int x0 = tx * STX, y0 = ty * STY;
+    const int tw = nx - x0 < STX ? nx - x0 : STX, th = ny - y0 < STY ? ny - y0 : STY;  // cells of this tile
     const bool frozen = a.ctl->bad != 0;
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
+    // the state on the tile and its two-cell ring: x in [x0 - 2, x0 + tw + 2),
+    // y in [y0 - 2, y0 + th + 2), each within one period or mirror of the grid
+    for (int e = tid; e < HY * HX; e += SNT) {
+        const int ly = e / HX, lx = e - ly * HX;
+        if (lx >= tw + 4 || ly >= th + 4) continue;
+        const int k = cell_of(x0 - 2 + lx, y0 - 2 + ly, nx, ny);
+#pragma unroll
+        for (int v = 0; v < 4; v++) s_q[v][ly][lx] = a.qs[v * plane + k];
+    }
+    if (tid < 64) {
+        const int lane = tid;
         double m = 0.0;
         if (!(a.dt_fixed > 0.0)) m = __longlong_as_double((long long)*rate_slot(a.rates, a.rate_in, lane));
         m = wave_max(m);
         if (lane == 0) s_dt = a.dt_fixed > 0.0 ? a.dt_fixed : a.cfl / m;
     }
     __syncthreads();
+    const T g = a.g;
+    // x faces (fi, fj): between cells x0 + fi - 1 and x0 + fi of row y0 + fj;
+    // the x-face arrays index it by cell (x0 + fi) mod nx
+    for (int f = tid; f < (STX + 1) * STY; f += SNT) {
+        const int fj = f / (STX + 1), fi = f - fj * (STX + 1);
+        if (fi > tw || fj >= th) continue;
+        const int i = x0 + fi < nx ? x0 + fi : x0 + fi - nx;
+        T c[4][4];
+#pragma unroll
+        for (int v = 0; v < 4; v++)
+#pragma unroll
+            for (int s = 0; s < 4; s++) c[v][s] = s_q[v][fj + 2][fi + s];
+        T o[4];
+        face_flux<T, FLUX, RECON>(c, a.G.xf, plane, (y0 + fj) * nx + i, g, o);
+#pragma unroll
+        for (int v = 0; v < 4; v++) s_fx[v][fj][fi] = o[v];
+    }
+    // y faces (fi, fj): row y0 + fj of the y-face arrays (between cell rows
+    // y0 + fj - 1 and y0 + fj), column x0 + fi
+    for (int f = tid; f < (STY + 1) * STX; f += SNT) {
+        const int fj = f / STX, fi = f - fj * STX;
+        if (fi >= tw || fj > th) continue;
+        T c[4][4];
+#pragma unroll
+        for (int v = 0; v < 4; v++)
+#pragma unroll
+            for (int s = 0; s < 4; s++) c[v][s] = s_q[v][fj + s][fi + 2];
+        T o[4];
+        face_flux<T, FLUX, RECON>(c, a.G.yf, (size_t)nyface, (y0 + fj) * nx + x0 + fi, g, o);
+#pragma unroll
+        for (int v = 0; v < 4; v++) s_fy[v][fj][fi] = o[v];
+    }
+    __syncthreads();
     const T dt = (T)s_dt;
-    const int k = blockIdx.x * 256 + threadIdx.x;
+    const int cj = tid / STX, ci = tid - cj * STX;
     T rate = T(0);
     bool bad = false;
-    if (k < ncell && !frozen) {
-        const int j = k / nx, i = k - j * nx;
-        const int kr = j * nx + (i + 1 == nx ? 0 : i + 1);  // the high x face is the low face of the right cell
-        const int fb = j * nx + i, ft = (j + 1) * nx + i;
+    if (ci < tw && cj < th && !frozen) {
+        const int k = (y0 + cj) * nx + x0 + ci;
         T s[4];
 #pragma unroll
-        for (int v = 0; v < 4; v++) s[v] = a.qs[v * plane + k];
+        for (int v = 0; v < 4; v++) s[v] = s_q[v][cj + 2][ci + 2];
         const T ih = fvk::rcp(s[0]);
         const T N[3] = {a.G.nsum[k], a.G.nsum[plane + k], a.G.nsum[2 * plane + k]};
         const T x[3] = {a.G.cen[k], a.G.cen[plane + k], a.G.cen[2 * plane + k]};
@@ -357,7 +399,7 @@ __global__ __launch_bounds__(256) void cell_kernel(CellArgs<T> a)
         T o[4];
 #pragma unroll
         for (int v = 0; v < 4; v++) {
-            T div = (a.fx[v * plane + kr] - a.fx[v * plane + k]) + (a.fy[v * (size_t)nyface + ft] - a.fy[v * (size_t)nyface + fb]);
+            T div = (s_fx[v][cj][ci + 1] - s_fx[v][cj][ci]) + (s_fy[v][cj + 1][ci] - s_fy[v][cj][ci]);
             if (v > 0) div = div - (s[v] * un + pres * N[v - 1]);
             o[v] = -div * ia;
         }
@@ -388,16 +430,16 @@ __global__ __launch_bounds__(256) void cell_kernel(CellArgs<T> a)
     if (bad) atomicExch(&a.ctl->bad, 1);
     if (a.rate_out >= 0) {
         const T m = wave_max(rate);
-        if ((threadIdx.x & 63) == 0)
-            atomicMax(rate_slot(a.rates, a.rate_out, (blockIdx.x * 4 + (threadIdx.x >> 6)) & (RATE_SUB - 1)),
+        if ((tid & 63) == 0)
+            atomicMax(rate_slot(a.rates, a.rate_out, (blockIdx.x * 4 + (tid >> 6)) & (RATE_SUB - 1)),
                       dmax_bits((double)m));
     }
     if (blockIdx.x == 0) {
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             a.ctl->t += s_dt;
             a.ctl->step += 1;
         }
-        if (a.rate_clear >= 0 && threadIdx.x < RATE_SUB) *rate_slot(a.rates, a.rate_clear, threadIdx.x) = 0ull;
+        if (a.rate_clear >= 0 && tid < RATE_SUB) *rate_slot(a.rates, a.rate_clear, tid) = 0ull;
     }
 }
 
@@ -472,30 +514,22 @@ template <typename T> hipError_t geometry(const Geometry<T> &G, int n, hipStream
     return hipGetLastError();
 }
 
-template <typename T>
-hipError_t faces(int flux, int recon, const T *q, const Geometry<T> &G, T *fx, T *fy, int n, double g, hipStream_t st)
+template <typename T> hipError_t stage(int flux, int recon, const CellArgs<T> &a, hipStream_t st)
 {
-    const int total = 2 * n * n + 2 * n * (n + 1);
-    const dim3 grid((total + 255) / 256), blk(256);
-    const T gg = (T)g;
-#define SPH_FACE(FL, RC) hipLaunchKernelGGL((face_kernel<T, FL, RC>), grid, blk, 0, st, q, G, fx, fy, n, gg)
+    const int nx = 2 * a.n, ny = a.n;
+    const int tiles_x = (nx + STX - 1) / STX, tiles = tiles_x * ((ny + STY - 1) / STY);
+    const dim3 grid(tiles), blk(SNT);
+#define SPH_TILE(FL, RC) hipLaunchKernelGGL((tile_kernel<T, FL, RC>), grid, blk, 0, st, a, tiles_x)
     if (recon == fvk::FIRST) {
-        if (flux == fvk::RUSANOV) SPH_FACE(fvk::RUSANOV, fvk::FIRST);
-        else if (flux == fvk::ROE) SPH_FACE(fvk::ROE, fvk::FIRST);
-        else SPH_FACE(fvk::HLLE, fvk::FIRST);
+        if (flux == fvk::RUSANOV) SPH_TILE(fvk::RUSANOV, fvk::FIRST);
+        else if (flux == fvk::ROE) SPH_TILE(fvk::ROE, fvk::FIRST);
+        else SPH_TILE(fvk::HLLE, fvk::FIRST);
     } else {
-        if (flux == fvk::RUSANOV) SPH_FACE(fvk::RUSANOV, fvk::MINMOD);
-        else if (flux == fvk::ROE) SPH_FACE(fvk::ROE, fvk::MINMOD);
-        else SPH_FACE(fvk::HLLE, fvk::MINMOD);
+        if (flux == fvk::RUSANOV) SPH_TILE(fvk::RUSANOV, fvk::MINMOD);
+        else if (flux == fvk::ROE) SPH_TILE(fvk::ROE, fvk::MINMOD);
+        else SPH_TILE(fvk::HLLE, fvk::MINMOD);
     }
-#undef SPH_FACE
-    return hipGetLastError();
-}
-
-template <typename T> hipError_t cells(const CellArgs<T> &a, hipStream_t st)
-{
-    const int ncell = 2 * a.n * a.n;
-    hipLaunchKernelGGL((cell_kernel<T>), dim3((ncell + 255) / 256), dim3(256), 0, st, a);
+#undef SPH_TILE
     return hipGetLastError();
 }
 
@@ -522,8 +556,7 @@ hipError_t totals(const T *q, const double *area, int n, double g, double *parti
 
 #define SPH_INST(T)                                                                                                   \
     template hipError_t geometry<T>(const Geometry<T> &, int, hipStream_t);                                        \
-    template hipError_t faces<T>(int, int, const T *, const Geometry<T> &, T *, T *, int, double, hipStream_t);      \
-    template hipError_t cells<T>(const CellArgs<T> &, hipStream_t);                                                 \
+    template hipError_t stage<T>(int, int, const CellArgs<T> &, hipStream_t);                                      \
     template hipError_t rate<T>(const T *, const Geometry<T> &, int, double, Ctl *, unsigned long long *, int,      \
                                 hipStream_t);                                                                      \
     template hipError_t totals<T>(const T *, const double *, int, double, double *, int, double *, hipStream_t);

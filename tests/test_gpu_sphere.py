@@ -68,6 +68,29 @@ def test_fp64_parity(fv, S, flux, recon, rk):
     assert np.all(errs <= 1e-12), errs
 
 
+@pytest.mark.parametrize("n", [49, 70])
+def test_fp64_parity_ragged_tiles(fv, S, n):
+    """Grids of several stage tiles (32 x 8 cells) with ragged last tiles in
+    both directions: 98 x 49 cells leave 2 columns and 1 row, 140 x 70 leave
+    12 columns and 6 rows; the tiles' halos cross the periodic seam and the
+    mirrored edges y = -+1."""
+    steps = 8
+    q0, _ = state(S, n, 3)
+    kw = dict(flux=0, recon=0, rk_stages=2, g=1.0, omega=0.5)
+    print(f"[gpu] sphere FP64 n={n} {kw} x{steps}", flush=True)
+    s = fv.SphereSolver(q0, prec=fv.FV_F64, **kw)
+    s.run(steps)
+    t, k = s.time()
+    out = s.state()
+    s.close()
+    ref, t_ref, rc = S.run(S.Config(n=n, **kw), q0, steps)
+    assert rc == 0 and k == steps
+    assert abs(t - t_ref) <= 1e-13 * t_ref
+    errs = rel_errors(out, ref)
+    print(f"[sphere ragged] n={n} errs {errs}", flush=True)
+    assert np.all(errs <= 1e-12), errs
+
+
 def test_fp32_smooth_parity_and_mass(fv, S):
     n, steps = 48, 100
     q0, _ = state(S, n, 3)
