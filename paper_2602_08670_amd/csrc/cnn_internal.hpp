@@ -143,8 +143,10 @@ hipError_t launch_conv_learned_list(int stage, const void *packed, const Norm &n
 // plain scheme from xprev into d.q (counted in d.redone; an inadmissible
 // plain result sets d.fatal).  Stage 2 clears the previous step's slot and
 // advances d.t and d.steps.
+// direct: the direct face-state scheme (raw output, face_states_direct) instead of the
+// learned coefficients; blend: the flux-limiter blend of the learned fluxes.
 hipError_t launch_conv_learned_one(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve &d,
-                                   int parity, const float *xprev, hipStream_t st, int blend = 0);
+                                   int parity, const float *xprev, hipStream_t st, int blend = 0, int direct = 0);
 
 // The same forward in one launch, without keeping activations: every
 // workgroup runs all five layers on an 8x8 tile of pixels (nx % 8 == 0,

@@ -863,8 +863,11 @@ template <int N> struct Chunks {
         const bf16x8 *g = (const bf16x8 *)(P + off);
 #pragma unroll
         for (int k = 0; k < IT; k++) {
-            const int i = threadIdx.x + k * T;
-            if (i < N) v[k] = g[i];
+            // an unsigned 32-bit index: the loads take the uniform base
+            // address plus a 32-bit per-lane offset, not a 64-bit address
+            // per load in registers
+            const unsigned i = threadIdx.x + k * T;
+            if (i < (unsigned)N) v[k] = g[i];
         }
     }
     __device__ __forceinline__ void store(bf16x8 *s) const
@@ -1018,8 +1021,9 @@ __device__ __noinline__ float *redo_region(const float *xprev, float *xk, const 
 enum { OUT_Z = 0, OUT_ALPHA = 1, OUT_Z_LDS = 2 };
 // rd (OUT_Z_LDS only, or NULL): when rd->xprev is set and *rd->flag is not
 // zero, the input region is the plain redo of the previous step
-// (redo_region) instead of qb.
-template <int FO, int OUT>
+// (redo_region) instead of qb.  LO: cells of the output region before the
+// tile (FO - FT by default; 1 for the tile and a one-cell ring, FO = FT + 2).
+template <int FO, int OUT, int LO = FO - FT>
 __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
                                              int H, int W, int y0, int x0, const Proj &pr, bool load_w, float *qf,
                                              const PlainRedo *rd = nullptr);
@@ -1077,13 +1081,14 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_batch_kernel(const LSolve
     }
 }
 
-template <int FO, int OUT>
+template <int FO, int OUT, int LO>
 __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
                                              int H, int W, int y0, int x0, const Proj &pr, bool load_w, float *qf,
                                              const PlainRedo *rd)
 {
-    static_assert(FO == FT || (FO == FT + 1 && OUT == OUT_Z_LDS), "output region: the tile, or the tile and its low halo");
-    constexpr int OFF = FO - FT;          // the region starts OFF cells before the tile
+    static_assert((FO == FT && LO == 0) || (OUT == OUT_Z_LDS && ((FO == FT + 1 && LO == 1) || (FO == FT + 2 && LO == 1))),
+                  "output region: the tile, the tile and its low halo, or the tile and a one-cell ring");
+    constexpr int OFF = LO;               // the region starts OFF cells before the tile
     constexpr int FRI_ = FO + 10, FR0_ = FO + 8;
     __shared__ bf16 s_in[3][FRI_ * FRI_];
     // activations, 32 channels = 4 x bf16x8 per pixel: layers 0 and 2 write
@@ -1649,11 +1654,15 @@ hipError_t launch_learned_euler(int flux, const void *packed, const ENorm &nrm, 
 // the learned-stage kernels; each face projects its owner's coefficients
 // (alpha = base + P z, the network pass's operation order).  STAGE 1: S1 = q + dt L(q); STAGE 2: S2 = q/2 +
 // (S1 + dt L(S1))/2.  Stage flags and fallback counts as there.
-template <int STAGE, bool BL = false>
+// DIR: the direct face-state scheme (face_states_direct): s_z holds the raw
+// output on the tile and a one-cell ring ([(FT+2)^2][72] from (x0 - 1,
+// y0 - 1)); each face takes its owner's high-side and its neighbour's
+// low-side states (sig = 1 / inv_std of the network input).
+template <int STAGE, bool BL = false, bool DIR = false>
 __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &it, const float *s_z, const float *qf,
-                                                 const Proj &pr, const int x0, const int y0)
+                                                 const Proj &pr, const int x0, const int y0, const float *sig = nullptr)
 {
-    constexpr int TX = FT, TY = FT, QS = FT + 6, FO = FT + 1;
+    constexpr int TX = FT, TY = FT, QS = FT + 6, FO = DIR ? FT + 2 : FT + 1;
     constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX, YB = 128;  // y faces start at thread YB
     static_assert(NFX <= YB && YB + NFY <= FNW * 64 && TX * TY <= FNW * 64, "one face or cell per thread");
     constexpr float a0 = STAGE == 1 ? 0.0f : 0.5f, a1 = STAGE == 1 ? 1.0f : 0.5f;
@@ -1688,7 +1697,9 @@ __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &i
 #pragma unroll
             for (int k = 0; k < 6; k++) st[v][k] = qf[(v * QS + xj + 3) * QS + xi + k];
         float QL[3], QR[3], F[3];
-        const int c = face_states<0, false>(st, s_z + ((xj + 1) * FO + xi) * 72, pr, QL, QR);
+        const int c = DIR ? face_states_direct(st, s_z + ((xj + 1) * FO + xi) * 72 + 3,
+                                               s_z + ((xj + 1) * FO + xi + 1) * 72, sig, QL, QR)
+                          : face_states<0, false>(st, s_z + ((xj + 1) * FO + xi) * 72, pr, QL, QR);
         if (xi < TX) nfb += c;  // each face counted once: as the left face of a cell of this tile
         flux3<fvk::HLLE, 0>(QL, QR, ph, F);
         if (BL) blend_flux<fvk::HLLE, 0>(st, ph, F);
@@ -1704,7 +1715,9 @@ __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &i
 #pragma unroll
             for (int k = 0; k < 6; k++) st[v][k] = qf[(v * QS + yj + k) * QS + yi + 3];
         float QL[3], QR[3], F[3];
-        const int c = face_states<0, false>(st, s_z + (yj * FO + yi + 1) * 72 + 36, pr, QL, QR);
+        const int c = DIR ? face_states_direct(st, s_z + (yj * FO + yi + 1) * 72 + 9,
+                                               s_z + ((yj + 1) * FO + yi + 1) * 72 + 6, sig, QL, QR)
+                          : face_states<0, false>(st, s_z + (yj * FO + yi + 1) * 72 + 36, pr, QL, QR);
         if (yj < TY) nfb += c;
         flux3<fvk::HLLE, 1>(QL, QR, ph, F);
         if (BL) blend_flux<fvk::HLLE, 1>(st, ph, F);
@@ -1781,7 +1794,9 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_batch_kernel(const LSol
 }
 
 // One solve's learned stage in a launch of its own (network pass and learned
-// stage per FT x FT tile, as conv_learned_batch_kernel), the solve passed by
+// stage per FT x FT tile, as conv_learned_batch_kernel; DIR: the direct
+// face-state scheme on the network's raw output for the tile and a one-cell
+// ring, the stage of learned_tile<0, HLLE, false, true>), the solve passed by
 // value: d.q is the step's input, d.s2 the step's output (the other buffer of
 // a pair, so the input survives for a redo).  Stage 1 with xprev != NULL:
 // when the previous step's flag slot is set, every workgroup first redoes
@@ -1789,7 +1804,7 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_batch_kernel(const LSol
 // tile written to d.q) and workgroup 0 counts the redo.  Stage 2's workgroup 0
 // clears the previous step's slot (every reader of it has finished: the
 // previous step's stage 2 and this step's stage 1) and advances the time.
-template <int STAGE, bool BL = false>
+template <int STAGE, bool BL = false, bool DIR = false>
 __global__ __launch_bounds__(FNW * 64) void conv_learned_one_kernel(LSolve d, int parity, const float *xprev,
                                                                     const char *P, Packed pk, Norm nrm, Proj pr)
 {
@@ -1797,6 +1812,9 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_one_kernel(LSolve d, in
     __shared__ float s_qf[3 * QS * QS];
     const int tx_n = d.nx / FT, total = tx_n * (d.ny / FT);
     const LItem it{0, 0, 0, parity, 0};
+    float sig[3];  // DIR: the direct states' de-normalisation, 1 / inv_std (correctly rounded, as the host's)
+#pragma unroll
+    for (int v = 0; v < 3; v++) sig[v] = DIR ? 1.0f / nrm.inv_std[v] : 0.0f;
     PlainRedo rd;
     rd.xprev = STAGE == 1 ? xprev : nullptr;
     rd.flag = d.flags + (parity ^ 1);
@@ -1818,9 +1836,9 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_one_kernel(LSolve d, in
         const bool first = w == (int)blockIdx.x;
         if (!first) __syncthreads();  // the previous tile's LDS reads are done
         const int ty = w / tx_n, tx = w - ty * tx_n;
-        const float *s_z = fused_tile<FT + 1, OUT_Z_LDS>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx,
-                                                             ty * FT, tx * FT, pr, first, s_qf, &rd);
-        learned_epilogue<STAGE, BL>(d, it, s_z, s_qf, pr, tx * FT, ty * FT);
+        const float *s_z = fused_tile<DIR ? FT + 2 : FT + 1, OUT_Z_LDS, 1>(
+            STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx, ty * FT, tx * FT, pr, first, s_qf, &rd);
+        learned_epilogue<STAGE, BL, DIR>(d, it, s_z, s_qf, pr, tx * FT, ty * FT, sig);
         w += gridDim.x;
     } while (w < total);
     // no writer of the previous step's slot in stage 1
@@ -1868,6 +1886,14 @@ int fused_max_grid()
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&k4, conv_learned_one_kernel<2, true>, FNW * 64, 0) !=
                 hipSuccess)
             return 256;
+        int k5 = 0, k6 = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k5, conv_learned_one_kernel<1, false, true>, FNW * 64, 0) !=
+                hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&k6, conv_learned_one_kernel<2, false, true>, FNW * 64, 0) !=
+                hipSuccess)
+            return 256;
+        k4 = k4 < k5 ? k4 : k5;
+        k4 = k4 < k6 ? k4 : k6;
         int m = a < b ? a : b;
         m = m < k1 ? m : k1;
         m = m < k2 ? m : k2;
@@ -1953,14 +1979,22 @@ hipError_t launch_conv_learned_list(int stage, const void *packed, const Norm &n
 }
 
 hipError_t launch_conv_learned_one(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve &d,
-                                   int parity, const float *xprev, hipStream_t st, int blend)
+                                   int parity, const float *xprev, hipStream_t st, int blend, int direct)
 {
-    if (d.nx % FT || d.ny % FT || (parity & ~1) || (stage != 1 && stage != 2) || (stage == 2 && xprev))
+    if (d.nx % FT || d.ny % FT || (parity & ~1) || (stage != 1 && stage != 2) || (stage == 2 && xprev) ||
+        (blend && direct))
         return hipErrorInvalidValue;
     const Packed pk = packed_layout();
     const int tiles = (d.nx / FT) * (d.ny / FT), cap = fused_max_grid(), g = tiles < cap ? tiles : cap;
     const char *Pc = (const char *)packed;
-    if (blend) {
+    if (direct) {
+        if (stage == 1)
+            hipLaunchKernelGGL((conv_learned_one_kernel<1, false, true>), dim3(g), dim3(FNW * 64), 0, st, d, parity,
+                               xprev, Pc, pk, nrm, pr);
+        else
+            hipLaunchKernelGGL((conv_learned_one_kernel<2, false, true>), dim3(g), dim3(FNW * 64), 0, st, d, parity,
+                               xprev, Pc, pk, nrm, pr);
+    } else if (blend) {
         if (stage == 1)
             hipLaunchKernelGGL((conv_learned_one_kernel<1, true>), dim3(g), dim3(FNW * 64), 0, st, d, parity, xprev, Pc,
                                pk, nrm, pr);

@@ -675,10 +675,11 @@ fv_status fv_model_forward_tiled(const fv_model *m, const float *q, int B, int n
     return e == hipSuccess ? FV_OK : hip_fail(e, "network launch");
 }
 
-// blend: the flux-limiter blend of the face fluxes; callers pass it only
-// where the work-list branch below runs (HLLE, nx % 8 == ny % 8 == 0, no split).
+// blend: the flux-limiter blend of the face fluxes; direct: the direct
+// face-state scheme; callers pass either only where the two-launch branch
+// below runs (HLLE, nx % 8 == ny % 8 == 0, below the split size).
 static fv_status learned_step_impl(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats,
-                                   int blend)
+                                   int blend, int direct = 0)
 {
     if (!s || !m) return fail(FV_E_INVALID, "NULL argument");
     const fv_config &c = s->cfg;
@@ -727,9 +728,9 @@ static fv_status learned_step_impl(fv_solver *s, const fv_model *m, int64_t nste
             d.q = X[k & 1];
             d.s2 = X[(k + 1) & 1];
             e = cnn::launch_conv_learned_one(1, m->packed, m->nrm, m->pr, d, par, k > 0 ? X[(k + 1) & 1] : nullptr,
-                                             s->stream, blend);
+                                             s->stream, blend, direct);
             if (e == hipSuccess)
-                e = cnn::launch_conv_learned_one(2, m->packed, m->nrm, m->pr, d, par, nullptr, s->stream, blend);
+                e = cnn::launch_conv_learned_one(2, m->packed, m->nrm, m->pr, d, par, nullptr, s->stream, blend, direct);
         }
         if (nsteps > 0 && e == hipSuccess) {
             // the last step's input xin and output xout: with an odd step
@@ -760,7 +761,7 @@ static fv_status learned_step_impl(fv_solver *s, const fv_model *m, int64_t nste
         const auto *items0 = (const cnn::LItem *)(B + LB_ITEMS);
         const int *nit = (const int *)(B + LB_N);
         const int tc = cnn::ltiles_cnn(c.nx, c.ny), ts = cnn::ltiles_st(c.nx, c.ny);
-        if (blend) return fail(FV_E_UNSUPPORTED, "blend: grid too large for the fused form");
+        if (blend || direct) return fail(FV_E_UNSUPPORTED, "blend or direct: grid too large for the fused form");
         for (int64_t k = 0; k < nsteps && e == hipSuccess; k++, s->lsteps++) {
             const cnn::LItem *it = items0 + (s->lsteps & 1);
             for (int stage = 1; stage <= 2 && e == hipSuccess; stage++) {
@@ -901,6 +902,13 @@ static fv_status raw_head_step(fv_solver *s, const fv_model *m, int64_t nsteps, 
 
 fv_status fv_direct_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats)
 {
+    // HLLE grids of whole 8 x 8 tiles below the split size: the learned
+    // step's two-launch form, the network pass (on the tile and a one-cell
+    // ring) and the direct stage in one launch per stage; else the network's
+    // raw output through HBM and a separate direct stage
+    if (s && m && s->cfg.flux == FV_FLUX_HLLE && s->cfg.nx % 8 == 0 && s->cfg.ny % 8 == 0 &&
+        cnn::ltiles_cnn(s->cfg.nx, s->cfg.ny) < 4 * cnn::fused_max_grid())
+        return learned_step_impl(s, m, nsteps, stats, 0, 1);
     return raw_head_step(s, m, nsteps, stats, 1, 0);
 }
 
