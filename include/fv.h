@@ -272,7 +272,10 @@ fv_status fv_model_forward_tiled(const fv_model *m, const float *q, int B, int n
  * rk_stages = 2, dt_fixed > 0, learned = 1, nx % 16 == 0 and
  * nx*ny % 64 == 0 (FV_E_UNSUPPORTED otherwise).  When stats is not NULL the
  * call synchronises and fills the cumulative counters.  Inadmissible results
- * of the plain redo are reported by fv_time as FV_E_INADMISSIBLE. */
+ * of the plain redo are reported by fv_time as FV_E_INADMISSIBLE.  The
+ * steps' admissibility flags alternate between two slots, so a call
+ * captured in a graph for replay should enqueue an even number of steps (a
+ * replay starts on the slot its capture started on). */
 fv_status fv_learned_step(fv_solver *s, const fv_model *m, int64_t nsteps, fv_learned_stats *stats);
 
 /* Enqueue nsteps Heun steps of the direct face-state scheme (thesis section

@@ -129,3 +129,42 @@ def test_redo_inside_a_call_bitwise(fv, L, blend):
         assert np.array_equal(served, got.astype(np.float32))
         assert (inf.fallback_faces, inf.redone_steps) == (fb, red) and inf.sim_time == t
     m.close()
+
+
+@pytest.mark.parametrize("scheme", ["learned", "direct"])
+def test_graph_replay_with_redos_bitwise(fv, L, scheme):
+    """Learned steps captured in a HIP graph (an even number per graph, so
+    that the replays keep alternating the flag slots) and replayed three
+    times give the bits, time and redo count of the same steps called
+    directly, with every step redone."""
+    import torch
+
+    p = L.init_params(2, scale_last=10.0)
+    q0 = shallow_state().astype(np.float32)
+    vec = fv.params_to_vector([w.numpy() for w in p["w"]], [b.numpy() for b in p["b"]])
+    m = fv.Model(vec, fv.make_model_desc(mean=tuple(p["mean"].tolist()), inv_std=tuple(p["inv_std"].tolist())))
+    dt, chunk, reps = 1e-3, 4, 3
+    st = torch.cuda.Stream()
+    s = fv.Solver(q0, prec=fv.FV_F32, dt_fixed=dt, learned=1, stream=st)
+    step = s.direct_step if scheme == "direct" else s.learned_step
+    with torch.cuda.stream(st):
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g, stream=st):
+            step(m, chunk, want_stats=False)
+    torch.cuda.synchronize()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    got, (t, k) = s.state(), s.time()
+    fb, red = step(m, 0)
+    s.close()
+    s = fv.Solver(q0, prec=fv.FV_F32, dt_fixed=dt, learned=1)
+    step = s.direct_step if scheme == "direct" else s.learned_step
+    fb1, red1 = step(m, chunk * reps)
+    ref, (t1, k1) = s.state(), s.time()
+    s.close()
+    m.close()
+    print(f"[graph redo] {scheme}: replayed redone {red} fallback {fb}; direct redone {red1} fallback {fb1}",
+          flush=True)
+    assert red1 == chunk * reps and (fb, red) == (fb1, red1)
+    assert np.array_equal(got, ref) and (t, k) == (t1, k1)
