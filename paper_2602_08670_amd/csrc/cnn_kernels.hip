@@ -900,6 +900,16 @@ struct PlainRedo {
     int *fatal;
 };
 
+// The stage kernels store each face flux to LDS and form the divergence from
+// the stored values; a redo that uses its fluxes in registers keeps the
+// compiler from fusing a flux's last operation into the divergence (an
+// empty asm that may change the values), so it rounds as they do.
+template <int N> __device__ __forceinline__ void flux_barrier(float *F)
+{
+#pragma unroll
+    for (int v = 0; v < N; v++) __asm__ volatile("" : "+v"(F[v]));
+}
+
 // The four face fluxes of the cell at (r, c) of an LDS field [3][N][N]:
 // left, right, bottom, top (the face between cells j and j + 1 of a line
 // takes the stencil j - 2 .. j + 3, of which MINMOD reads j - 1 .. j + 2).
@@ -924,6 +934,7 @@ __device__ __forceinline__ void plain_cell_fluxes(const float *f, int r, int c, 
         face_states<1>(st, nullptr, Proj{}, QL, QR);
         if (ax == 0) flux3<fvk::HLLE, 0>(QL, QR, ph, F[face]);
         else flux3<fvk::HLLE, 1>(QL, QR, ph, F[face]);
+        flux_barrier<3>(F[face]);
     }
 }
 
@@ -1318,15 +1329,114 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
 // so z is bit-identical to launch_forward_euler's.
 constexpr int EW0 = 32 * 64 / 8, EWH = 9 * 32 * 32 / 8, EW4 = 9 * 6 * 16 * 32 / 8;  // packed octets per layer
 
+// Plain (MINMOD, FLUX) Heun step of one Euler solve's previous state xprev
+// on the R x R region at (ox, oy), recomputed from xprev on the region grown
+// by four cells, as redo_region does for shallow water: the redo of a flagged
+// step on the region one workgroup of the next step reads.  Each face's
+// states (MINMOD with the admissibility fallback), flux and each cell's
+// update are the learned Euler stage kernel's plain arithmetic (MODES 2 and
+// 3).  The FT x FT tile at (x0, y0) writes its cells of the result to xk and
+// raises *fatal where a plain stage leaves one of them inadmissible.  Needs
+// 4 ((R + 8)^2 + (R + 4)^2 + R^2) floats of LDS at buf; returns the region,
+// [4][R][R], in buf.  Out of line, its arguments in registers.
+template <int N, int FLUX>
+__device__ __forceinline__ void euler_cell_fluxes(const float *f, int r, int c, float gamma, float (*F)[4])
+{
+#pragma unroll
+    for (int face = 0; face < 4; face++) {
+        const int ax = face >> 1, hi = face & 1;  // axis, and whether the face is on the cell's high side
+        float st[4][6];
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            st[v][0] = 0.0f;
+            st[v][5] = 0.0f;
+#pragma unroll
+            for (int k = 1; k < 5; k++) {
+                const int o = k - 3 + hi;
+                st[v][k] = ax == 0 ? f[(v * N + r) * N + c + o] : f[(v * N + r + o) * N + c];
+            }
+        }
+        float QL[4], QR[4];
+        eln::face_states<false>(st, nullptr, Proj{}, gamma, QL, QR);
+        if (ax == 0) eln::flux4<FLUX, 0>(QL, QR, gamma, F[face]);
+        else eln::flux4<FLUX, 1>(QL, QR, gamma, F[face]);
+        flux_barrier<4>(F[face]);
+    }
+}
+
+template <int R, int FLUX>
+__device__ __noinline__ float *euler_redo_region(const float *xprev, float *xk, float dt, float rdx, float rdy,
+                                                 float gamma, int *fatal, int H, int W, int ox, int oy, int x0, int y0,
+                                                 float *buf)
+{
+    constexpr int A = R + 8, S = R + 4, NT = FNW * 64;
+    float *sa = buf;              // [4][A][A] xprev from (ox - 4, oy - 4)
+    float *ss = sa + 4 * A * A;   // [4][S][S] plain stage 1 from (ox - 2, oy - 2)
+    float *sr = ss + 4 * S * S;   // [4][R][R] the redone state from (ox, oy)
+    const int tid = threadIdx.x;
+    const size_t plane = (size_t)H * W;
+    for (int k = tid; k < 4 * A * A; k += NT) {
+        const int v = k / (A * A), r = k - v * A * A, ry = r / A, rx = r - ry * A;
+        // up to ten cells out from a tile of a grid as small as 16 cells: the full modulo
+        sa[k] = xprev[v * plane + (size_t)pwrap(oy - 4 + ry, H) * W + pwrap(ox - 4 + rx, W)];
+    }
+    __syncthreads();
+    bool bad = false;
+    // stage 1: S1 = q + dt L(q); cell (j, i) of ss is (j + 2, i + 2) of sa
+    for (int k = tid; k < S * S; k += NT) {
+        const int j = k / S, i = k - j * S;
+        float F[4][4];
+        euler_cell_fluxes<A, FLUX>(sa, j + 2, i + 2, gamma, F);
+        const int gx = ox - 2 + i - x0, gy = oy - 2 + j - y0;  // tile-relative
+        float qn[4];
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const float L = -(F[1][v] - F[0][v]) * rdx - (F[3][v] - F[2][v]) * rdy;
+            float o = 1.0f * (sa[(v * A + j + 2) * A + i + 2] + dt * L);
+            ss[(v * S + j) * S + i] = o;
+            qn[v] = o;
+        }
+        if (gx >= 0 && gx < FT && gy >= 0 && gy < FT) bad = bad || !eln::admissible(qn, gamma);
+    }
+    __syncthreads();
+    // stage 2: q/2 + (S1 + dt L(S1))/2; cell (j, i) of sr is (j + 2, i + 2) of ss
+    for (int k = tid; k < R * R; k += NT) {
+        const int j = k / R, i = k - j * R;
+        float F[4][4];
+        euler_cell_fluxes<S, FLUX>(ss, j + 2, i + 2, gamma, F);
+        const int gx = ox + i - x0, gy = oy + j - y0;
+        float qn[4];
+#pragma unroll
+        for (int v = 0; v < 4; v++) {
+            const float L = -(F[1][v] - F[0][v]) * rdx - (F[3][v] - F[2][v]) * rdy;
+            float o = 0.5f * (ss[(v * S + j + 2) * S + i + 2] + dt * L);
+            o = 0.5f * sa[(v * A + j + 4) * A + i + 4] + o;
+            sr[(v * R + j) * R + i] = o;
+            qn[v] = o;
+        }
+        if (gx >= 0 && gx < FT && gy >= 0 && gy < FT) {
+#pragma unroll
+            for (int v = 0; v < 4; v++) xk[v * plane + (size_t)(y0 + gy) * W + x0 + gx] = qn[v];
+            bad = bad || !eln::admissible(qn, gamma);
+        }
+    }
+    if (bad) atomicExch(fatal, 1);
+    __syncthreads();
+    return sr;
+}
+
 // The output region is the FT x FT tile at (x0, y0) (FO = FT: z written to
 // zb, [H][W][96]) or the tile and its low halo row and column (FO = FT + 1,
 // ZLDS: z kept in LDS as [FO*FO][96] from (x0 - 1, y0 - 1) and returned, and
 // the FP32 stage input with a three-cell halo in qf, [4][FT+6][FT+6] from
 // (x0 - 3, y0 - 3)).  load_w: stage the weights (the workgroup's first tile).
-template <int FO, bool ZLDS>
+// redo (ZLDS): the input region is the plain redo of the previous step from
+// redo_from (euler_redo_region, the tile's cells written to qb) instead of qb.
+template <int FO, bool ZLDS, int FLUX = 0>
 __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *P, const EPacked &pk,
                                                    const ENorm &nrm, float *zb, int H, int W, int y0, int x0,
-                                                   bool load_w, float *qf)
+                                                   bool load_w, float *qf, const float *redo_from = nullptr,
+                                                   const eln::StageArgs *ra = nullptr, int *fatal = nullptr)
 {
     static_assert(FO == FT || (FO == FT + 1 && ZLDS), "output region: the tile, or the tile and its low halo");
     constexpr int OFF = FO - FT, FRI_ = FO + 10, FR0_ = FO + 8;
@@ -1349,6 +1459,21 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
             const int ci = i / (FRI_ * FRI_), r = i - ci * FRI_ * FRI_;
             const int ry = r / FRI_, rx = r - ry * FRI_;
             xin[k] = qb[(size_t)ci * hw + (size_t)wrap(ry0 + ry, H) * W + wrap(rx0 + rx, W)];
+        }
+    }
+    if constexpr (ZLDS) {
+        // the redo decision after the loads have been issued (their values
+        // are discarded); the activations' LDS is free until layer 0's first
+        // store, which follows the staging barrier below
+        if (redo_from) {
+            const float *sr = euler_redo_region<FRI_, FLUX>(redo_from, (float *)qb, ra->dt, ra->rdx, ra->rdy,
+                                                            ra->gamma, fatal, H, W, rx0, ry0, x0, y0,
+                                                            (float *)s_act);
+#pragma unroll
+            for (int k = 0; k < TIN; k++) {
+                const int i = threadIdx.x + k * FNW * 64;
+                if (i < NIN) xin[k] = sr[i];
+            }
         }
     }
     Chunks<EW0> c0;
@@ -1509,7 +1634,7 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_euler_kernel(const float 
 // as the stage kernel's.
 template <int FLUX>
 __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::StageArgs a, const char *P, EPacked pk,
-                                                                      ENorm nrm)
+                                                                      ENorm nrm, const float *xprev)
 {
     constexpr int TX = FT, TY = FT, QS = FT + 6, FO = FT + 1;
     constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX, YB = 128;  // y faces start at thread YB
@@ -1528,9 +1653,14 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
         if (staged) __syncthreads();  // the previous tile's LDS reads are done
         const int rt = tile - b * tx_n * ty_n;
         const int y0 = (rt / tx_n) * FT, x0 = (rt % tx_n) * FT;
-        const float *s_z = fused_tile_euler<FO, true>(a.qs + (size_t)b * 4 * plane, P, pk, nrm, nullptr, ny, nx, y0,
-                                                      x0, !staged, s_qf);
+        // stage 1 with xprev: a solve whose previous step is flagged is redone
+        // on this workgroup's region first (no writer of that slot in stage 1)
+        const bool redo = a.flagbit == 1 && xprev && a.flags[2 * b + (a.parity ^ 1)] != 0;
+        const float *s_z = fused_tile_euler<FO, true, FLUX>(
+            a.qs + (size_t)b * 4 * plane, P, pk, nrm, nullptr, ny, nx, y0, x0, !staged, s_qf,
+            redo ? xprev + (size_t)b * 4 * plane : nullptr, &a, a.fatal + b);
         staged = true;
+        if (redo && rt == 0 && tid == 0) a.redone[b] += 1;
         int *flag = a.flags + 2 * b + a.parity;
         // stage 2 of a solve whose stage 1 failed is evaluated (its result is
         // discarded by the redo) but its fallback sides are not counted
@@ -1593,6 +1723,9 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
         if (tid == 0) {
             if (s_cnt) atomicAdd(&a.nfb[b], (unsigned long long)s_cnt);
             if (s_bad) atomicOr(flag, a.flagbit);
+            // stage 2: every reader of the previous step's slot has finished
+            // (its stage 2 and this step's stage 1)
+            if (a.flagbit == 2 && rt == 0) a.flags[2 * b + (a.parity ^ 1)] = 0;
         }
     }
 }
@@ -1630,18 +1763,20 @@ hipError_t launch_forward_euler_fused(const void *packed, const ENorm &nrm, cons
     return hipGetLastError();
 }
 
-hipError_t launch_learned_euler(int flux, const void *packed, const ENorm &nrm, const eln::StageArgs &a, hipStream_t st)
+hipError_t launch_learned_euler(int flux, const void *packed, const ENorm &nrm, const eln::StageArgs &a, hipStream_t st,
+                                const float *xprev)
 {
-    if (a.nx % FT || a.ny % FT || a.B < 1 || (a.flagbit != 1 && a.flagbit != 2)) return hipErrorInvalidValue;
+    if (a.nx % FT || a.ny % FT || a.B < 1 || (a.flagbit != 1 && a.flagbit != 2) || (a.flagbit == 2 && xprev))
+        return hipErrorInvalidValue;
     const int tiles = a.B * (a.nx / FT) * (a.ny / FT);
     const int cap = fused_euler_grid();
     const dim3 g((unsigned)(tiles < cap ? tiles : cap));
     if (flux == fvk::RUSANOV)
         hipLaunchKernelGGL(conv_learned_euler_kernel<fvk::RUSANOV>, g, dim3(FNW * 64), 0, st, a, (const char *)packed,
-                           euler_packed_layout(), nrm);
+                           euler_packed_layout(), nrm, xprev);
     else
         hipLaunchKernelGGL(conv_learned_euler_kernel<fvk::HLLE>, g, dim3(FNW * 64), 0, st, a, (const char *)packed,
-                           euler_packed_layout(), nrm);
+                           euler_packed_layout(), nrm, xprev);
     return hipGetLastError();
 }
 

@@ -181,13 +181,40 @@ fv_status fv_euler_learned_step(fv_euler_learned *e, float *q, int64_t nsteps)
     // is whole 8 x 8 tiles and every tile gets a workgroup of its own (with
     // more tiles a workgroup would run several tiles' network passes and face
     // epilogues in turn: the separate launches spread the stage wider), else
-    // the network pass and the stage kernel
+    // the network pass and the stage kernel, then commit-or-redo and redo
     const bool fused = tiled && (int64_t)c.B * (c.nx / 8) * (c.ny / 8) <= cnn::fused_euler_grid();
     auto learned = [&]() {
-        if (fused) return cnn::launch_learned_euler(fl, ws + L.packed, e->nrm, a, e->stream);
         hipError_t r = net(a.qs);
         return r == hipSuccess ? eln::stage(0, fl, a, e->stream) : r;
     };
+    if (fused) {
+        // two launches per step: the step's output goes to the other buffer
+        // of the pair (q, S2), its input stays for a redo, which the next
+        // step's first launch carries out where a solve's step was flagged;
+        // the call's last step ends with the commit-or-redo and redo launches
+        float *X[2] = {q, S2};
+        for (int64_t k = 0; k < nsteps && h == hipSuccess; k++, e->steps_enq++) {
+            a.parity = (int)(e->steps_enq & 1);
+            a.qs = X[k & 1]; a.q0 = X[k & 1]; a.out = S1; a.a0 = 0.f; a.a1 = 1.f; a.flagbit = 1;
+            h = cnn::launch_learned_euler(fl, ws + L.packed, e->nrm, a, e->stream, k > 0 ? X[(k + 1) & 1] : nullptr);
+            a.qs = S1; a.q0 = X[k & 1]; a.out = X[(k + 1) & 1]; a.a0 = 0.5f; a.a1 = 0.5f; a.flagbit = 2;
+            if (h == hipSuccess) h = cnn::launch_learned_euler(fl, ws + L.packed, e->nrm, a, e->stream);
+        }
+        if (nsteps > 0 && h == hipSuccess) {
+            // the last step's input xin and output xout: with an odd step
+            // count (q, S2), commit S2 -> q or redo from q; with an even one
+            // (S2, q), the result is in q already, or the step is redone from S2
+            float *xin = X[(nsteps - 1) & 1], *xout = X[nsteps & 1];
+            a.parity = (int)((e->steps_enq - 1) & 1);
+            a.qs = xin; a.q0 = xin; a.out = S1; a.a0 = 0.f; a.a1 = 1.f;
+            a.commit_src = xout == q ? nullptr : xout;
+            a.commit_dst = q;
+            h = eln::stage(2, fl, a, e->stream);
+            a.qs = S1; a.q0 = xin; a.out = q; a.a0 = 0.5f; a.a1 = 0.5f;
+            if (h == hipSuccess) h = eln::stage(3, fl, a, e->stream);
+        }
+        return h == hipSuccess ? FV_OK : hip_fail(h, "learned Euler step launch");
+    }
     for (int64_t k = 0; k < nsteps && h == hipSuccess; k++) {
         a.parity = (int)(e->steps_enq & 1);
         // stage 1: S1 = q + dt L(q)

@@ -21,7 +21,7 @@ struct StageArgs {
     unsigned long long *nfb, *redone;
     int *fatal;            // [B]: the plain redo failed, the solve is frozen
     cnn::Proj pr;
-    const float *commit_src;  // MODE 2: S2
+    const float *commit_src;  // MODE 2: S2 (NULL: the result is in place, nothing to copy)
     float *commit_dst;        // MODE 2: q
     int *record;              // MODE 3 (or NULL): per solve, 1 when this step was redone (training)
 };
@@ -53,8 +53,13 @@ namespace cnn {
 // arithmetic) of one stage in one launch, for grids of whole 8 x 8 tiles:
 // a.qs is the stage input and the network's, the coefficients stay in LDS
 // (a.z unused); a.flagbit is the stage (1 or 2).
+// xprev (stage 1, or NULL): the previous step's input; a solve whose
+// previous step is flagged (a.flags[2b + (a.parity ^ 1)]) is first redone
+// with the plain scheme from xprev, on the region each workgroup reads, into
+// a.qs (counted in a.redone; an inadmissible plain result freezes the solve).
+// Stage 2 clears the previous step's slot of each solve it steps.
 hipError_t launch_learned_euler(int flux, const void *packed, const ENorm &nrm, const eln::StageArgs &a,
-                                hipStream_t st);
+                                hipStream_t st, const float *xprev = nullptr);
 // Workgroups of the one-launch Euler network pass resident at once.
 int fused_euler_grid();
 }  // namespace cnn

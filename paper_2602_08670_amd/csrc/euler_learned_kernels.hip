@@ -16,8 +16,8 @@
 //   0  learned stage: out = a0 q0 + a1 (qs + dt L(qs)), flag bit set when a
 //      cell of the result is inadmissible, fallback sides counted (not for
 //      stage 2 of a solve whose stage 1 failed);
-//   2  solves whose flag is 0 commit S2 -> q; the others run the plain
-//      MINMOD first stage S1 = q + dt L(q);
+//   2  solves whose flag is 0 commit S2 -> q (commit_src NULL: nothing to
+//      copy); the others run the plain MINMOD first stage S1 = q + dt L(q);
 //   3  solves whose flag is set run the plain second stage
 //      q = (q + S1 + dt L(S1)) / 2 (a still inadmissible result freezes the
 //      solve); bookkeeping: redone count, the other slot cleared.
@@ -59,6 +59,7 @@ __global__ __launch_bounds__(256) void stage_kernel(StageArgs a)
     }
     const int fl = *flag;
     if (MODE == 2 && fl == 0) {
+        if (!a.commit_src) return;  // the result is already in place
         for (int k = tid; k < TX * TY; k += 256) {
             const int cy = k / TX, cx = k - cy * TX;
             if (x0 + cx >= nx || y0 + cy >= ny) continue;
