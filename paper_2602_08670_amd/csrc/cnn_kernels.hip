@@ -886,7 +886,7 @@ template <int N> struct Chunks {
 // inadmissible, on the region one workgroup of the next step reads, so that
 // no launch has to finish the redo first.  Each face flux, cell update and
 // Heun combine is the plain stage's (learned-stage kernels, MODES 2 and 3)
-// arithmetic on the same stencil values.  The FT x FT tile at (x0, y0) writes
+// arithmetic on the same stencil values.  The TS x TS tile at (x0, y0) writes
 // its cells of the result to xk and raises fatal where a plain stage leaves
 // one of them inadmissible.  Needs 3 ((R + 8)^2 + (R + 4)^2 + R^2) floats of
 // LDS at buf; returns the region, [3][R][R], in buf.
@@ -940,7 +940,7 @@ __device__ __forceinline__ void plain_cell_fluxes(const float *f, int r, int c, 
 
 // Out of line, its arguments in registers: the common path (no redo) keeps
 // the network pass's register budget.
-template <int R>
+template <int R, int TS>
 __device__ __noinline__ float *redo_region(const float *xprev, float *xk, const float *dtp, float rdx, float rdy,
                                            float g, float sqg, float h0, int *fatal, int H, int W, int ox, int oy,
                                            int x0, int y0, float *buf)
@@ -976,7 +976,7 @@ __device__ __noinline__ float *redo_region(const float *xprev, float *xk, const 
         float F[4][3];
         plain_cell_fluxes<A>(sa, j + 2, i + 2, rd.ph, F);
         const int gx = ox - 2 + i - x0, gy = oy - 2 + j - y0;  // tile-relative
-        const bool own = gx >= 0 && gx < FT && gy >= 0 && gy < FT;
+        const bool own = gx >= 0 && gx < TS && gy >= 0 && gy < TS;
         float qn[3];
 #pragma unroll
         for (int v = 0; v < 3; v++) {
@@ -995,7 +995,7 @@ __device__ __noinline__ float *redo_region(const float *xprev, float *xk, const 
         float F[4][3];
         plain_cell_fluxes<S>(ss, j + 2, i + 2, rd.ph, F);
         const int gx = ox + i - x0, gy = oy + j - y0;
-        const bool own = gx >= 0 && gx < FT && gy >= 0 && gy < FT;
+        const bool own = gx >= 0 && gx < TS && gy >= 0 && gy < TS;
         float qn[3];
 #pragma unroll
         for (int v = 0; v < 3; v++) {
@@ -1034,7 +1034,9 @@ enum { OUT_Z = 0, OUT_ALPHA = 1, OUT_Z_LDS = 2 };
 // zero, the input region is the plain redo of the previous step
 // (redo_region) instead of qb.  LO: cells of the output region before the
 // tile (FO - FT by default; 1 for the tile and a one-cell ring, FO = FT + 2).
-template <int FO, int OUT, int LO = FO - FT>
+// TS: the tile side (FT; a single solve's kernel on few tiles takes 4, the
+// same per-pixel arithmetic on more, smaller workgroups).
+template <int FO, int OUT, int LO = FO - FT, int TS = FT>
 __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
                                              int H, int W, int y0, int x0, const Proj &pr, bool load_w, float *qf,
                                              const PlainRedo *rd = nullptr);
@@ -1092,13 +1094,14 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_batch_kernel(const LSolve
     }
 }
 
-template <int FO, int OUT, int LO>
+template <int FO, int OUT, int LO, int TS>
 __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, const Packed &pk, const Norm &nrm, float *zb,
                                              int H, int W, int y0, int x0, const Proj &pr, bool load_w, float *qf,
                                              const PlainRedo *rd)
 {
-    static_assert((FO == FT && LO == 0) || (OUT == OUT_Z_LDS && ((FO == FT + 1 && LO == 1) || (FO == FT + 2 && LO == 1))),
+    static_assert((FO == TS && LO == 0) || (OUT == OUT_Z_LDS && ((FO == TS + 1 && LO == 1) || (FO == TS + 2 && LO == 1))),
                   "output region: the tile, the tile and its low halo, or the tile and a one-cell ring");
+    static_assert(TS == FT || OUT == OUT_Z_LDS, "other tile sides only for a stage in the same workgroup");
     constexpr int OFF = LO;               // the region starts OFF cells before the tile
     constexpr int FRI_ = FO + 10, FR0_ = FO + 8;
     __shared__ bf16 s_in[3][FRI_ * FRI_];
@@ -1121,7 +1124,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     // input region, normalised and rounded to BF16 as the first layer reads
     // it, and all five layers' weights: every global load is issued before
     // the first LDS store.  qf (OUT_Z_LDS): the FP32 values of the
-    // (FT + 6)^2 cells from (x0 - 3, y0 - 3), kept for the learned stage.
+    // (TS + 6)^2 cells from (x0 - 3, y0 - 3), kept for the learned stage.
     constexpr int NIN = 3 * FRI_ * FRI_, TIN = (NIN + FNW * 64 - 1) / (FNW * 64);
     float xin[TIN];
 #pragma unroll
@@ -1139,7 +1142,9 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
         // are discarded on a redo); the activations' LDS is free until layer
         // 0's first store, which follows the staging barrier below
         if (rd && rd->xprev && *rd->flag) {
-            const float *sr = redo_region<FRI_>(rd->xprev, rd->xk, rd->dt, rd->rdx, rd->rdy, rd->ph.g, rd->ph.sqg,
+            static_assert(3 * ((FRI_ + 8) * (FRI_ + 8) + (FRI_ + 4) * (FRI_ + 4) + FRI_ * FRI_) * 4 <= sizeof(s_act),
+                          "the redo's three fields fit over the activations");
+            const float *sr = redo_region<FRI_, TS>(rd->xprev, rd->xk, rd->dt, rd->rdx, rd->rdy, rd->ph.g, rd->ph.sqg,
                                                 rd->ph.h0, rd->fatal, H, W, rx0, ry0, x0, y0, (float *)s_act);
 #pragma unroll
             for (int k = 0; k < TIN; k++) {
@@ -1166,7 +1171,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
             s_in[ci][r] = (bf16)((xin[k] - nrm.mean[ci]) * nrm.inv_std[ci]);
             if (OUT == OUT_Z_LDS) {
                 // the halo's corner (x0 - 3, y0 - 3) is 2 + OFF cells into the input region
-                constexpr int QS = FT + 6, QO = 2 + OFF;
+                constexpr int QS = TS + 6, QO = 2 + OFF;
                 const int rr = r / FRI_, ry = rr - QO, rx = r - rr * FRI_ - QO;
                 if (ry >= 0 && ry < QS && rx >= 0 && rx < QS) qf[(ci * QS + ry) * QS + rx] = xin[k];
             }
@@ -1309,10 +1314,10 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
         __syncthreads();
         // each tile row's 8 x 72 values, contiguous in the output, leave as
         // 16-byte stores
-        constexpr int RV = FT * 72 / 4;  // float4 per tile row
-        for (int i = threadIdx.x; i < FT * RV; i += FNW * 64) {
+        constexpr int RV = TS * 72 / 4;  // float4 per tile row
+        for (int i = threadIdx.x; i < TS * RV; i += FNW * 64) {
             const int row = i / RV, c = i - row * RV;
-            ((float4 *)(zb + ((size_t)(y0 + row) * W + x0) * 72))[c] = ((const float4 *)(s_z + row * FT * 72))[c];
+            ((float4 *)(zb + ((size_t)(y0 + row) * W + x0) * 72))[c] = ((const float4 *)(s_z + row * TS * 72))[c];
         }
     }
     return s_z;
@@ -1335,7 +1340,7 @@ constexpr int EW0 = 32 * 64 / 8, EWH = 9 * 32 * 32 / 8, EW4 = 9 * 6 * 16 * 32 / 
 // step on the region one workgroup of the next step reads.  Each face's
 // states (MINMOD with the admissibility fallback), flux and each cell's
 // update are the learned Euler stage kernel's plain arithmetic (MODES 2 and
-// 3).  The FT x FT tile at (x0, y0) writes its cells of the result to xk and
+// 3).  The TS x TS tile at (x0, y0) writes its cells of the result to xk and
 // raises *fatal where a plain stage leaves one of them inadmissible.  Needs
 // 4 ((R + 8)^2 + (R + 4)^2 + R^2) floats of LDS at buf; returns the region,
 // [4][R][R], in buf.  Out of line, its arguments in registers.
@@ -1364,7 +1369,7 @@ __device__ __forceinline__ void euler_cell_fluxes(const float *f, int r, int c, 
     }
 }
 
-template <int R, int FLUX>
+template <int R, int FLUX, int TS>
 __device__ __noinline__ float *euler_redo_region(const float *xprev, float *xk, float dt, float rdx, float rdy,
                                                  float gamma, int *fatal, int H, int W, int ox, int oy, int x0, int y0,
                                                  float *buf)
@@ -1396,7 +1401,7 @@ __device__ __noinline__ float *euler_redo_region(const float *xprev, float *xk, 
             ss[(v * S + j) * S + i] = o;
             qn[v] = o;
         }
-        if (gx >= 0 && gx < FT && gy >= 0 && gy < FT) bad = bad || !eln::admissible(qn, gamma);
+        if (gx >= 0 && gx < TS && gy >= 0 && gy < TS) bad = bad || !eln::admissible(qn, gamma);
     }
     __syncthreads();
     // stage 2: q/2 + (S1 + dt L(S1))/2; cell (j, i) of sr is (j + 2, i + 2) of ss
@@ -1414,7 +1419,7 @@ __device__ __noinline__ float *euler_redo_region(const float *xprev, float *xk, 
             sr[(v * R + j) * R + i] = o;
             qn[v] = o;
         }
-        if (gx >= 0 && gx < FT && gy >= 0 && gy < FT) {
+        if (gx >= 0 && gx < TS && gy >= 0 && gy < TS) {
 #pragma unroll
             for (int v = 0; v < 4; v++) xk[v * plane + (size_t)(y0 + gy) * W + x0 + gx] = qn[v];
             bad = bad || !eln::admissible(qn, gamma);
@@ -1425,21 +1430,23 @@ __device__ __noinline__ float *euler_redo_region(const float *xprev, float *xk, 
     return sr;
 }
 
-// The output region is the FT x FT tile at (x0, y0) (FO = FT: z written to
-// zb, [H][W][96]) or the tile and its low halo row and column (FO = FT + 1,
+// The output region is the TS x TS tile at (x0, y0) (FO = TS: z written to
+// zb, [H][W][96]) or the tile and its low halo row and column (FO = TS + 1,
 // ZLDS: z kept in LDS as [FO*FO][96] from (x0 - 1, y0 - 1) and returned, and
-// the FP32 stage input with a three-cell halo in qf, [4][FT+6][FT+6] from
+// the FP32 stage input with a three-cell halo in qf, [4][TS+6][TS+6] from
 // (x0 - 3, y0 - 3)).  load_w: stage the weights (the workgroup's first tile).
 // redo (ZLDS): the input region is the plain redo of the previous step from
 // redo_from (euler_redo_region, the tile's cells written to qb) instead of qb.
-template <int FO, bool ZLDS, int FLUX = 0>
+// TS: the tile side (FT, or 4 for a stage in the same workgroup on few tiles).
+template <int FO, bool ZLDS, int FLUX = 0, int TS = FT>
 __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *P, const EPacked &pk,
                                                    const ENorm &nrm, float *zb, int H, int W, int y0, int x0,
                                                    bool load_w, float *qf, const float *redo_from = nullptr,
                                                    const eln::StageArgs *ra = nullptr, int *fatal = nullptr)
 {
-    static_assert(FO == FT || (FO == FT + 1 && ZLDS), "output region: the tile, or the tile and its low halo");
-    constexpr int OFF = FO - FT, FRI_ = FO + 10, FR0_ = FO + 8;
+    static_assert(FO == TS || (FO == TS + 1 && ZLDS), "output region: the tile, or the tile and its low halo");
+    static_assert(TS == FT || ZLDS, "other tile sides only for a stage in the same workgroup");
+    constexpr int OFF = FO - TS, FRI_ = FO + 10, FR0_ = FO + 8;
     __shared__ bf16 s_in[E_CIN][FRI_ * FRI_];
     __shared__ bf16x8 s_act[FR0_ * FR0_ * 4 + (FR0_ - 2) * (FR0_ - 2) * 4];
     __shared__ bf16x8 s_wall[EW0 + 3 * EWH + EW4];
@@ -1466,7 +1473,9 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
         // are discarded); the activations' LDS is free until layer 0's first
         // store, which follows the staging barrier below
         if (redo_from) {
-            const float *sr = euler_redo_region<FRI_, FLUX>(redo_from, (float *)qb, ra->dt, ra->rdx, ra->rdy,
+            static_assert(4 * ((FRI_ + 8) * (FRI_ + 8) + (FRI_ + 4) * (FRI_ + 4) + FRI_ * FRI_) * 4 <= sizeof(s_act),
+                          "the redo's three fields fit over the activations");
+            const float *sr = euler_redo_region<FRI_, FLUX, TS>(redo_from, (float *)qb, ra->dt, ra->rdx, ra->rdy,
                                                             ra->gamma, fatal, H, W, rx0, ry0, x0, y0,
                                                             (float *)s_act);
 #pragma unroll
@@ -1494,7 +1503,7 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
             s_in[ci][r] = (bf16)((xin[k] - nrm.mean[ci]) * nrm.inv_std[ci]);
             if (ZLDS) {
                 // the halo's corner (x0 - 3, y0 - 3) is 2 + OFF cells into the input region
-                constexpr int QS = FT + 6, QO = 2 + OFF;
+                constexpr int QS = TS + 6, QO = 2 + OFF;
                 const int rr = r / FRI_, ry = rr - QO, rx = r - rr * FRI_ - QO;
                 if (ry >= 0 && ry < QS && rx >= 0 && rx < QS) qf[(ci * QS + ry) * QS + rx] = xin[k];
             }
@@ -1632,11 +1641,11 @@ __global__ __launch_bounds__(FNW * 64) void conv_fused_euler_kernel(const float 
 // admissibility fallback and takes the Euler flux; one x face, one y face and
 // one cell per thread.  Frozen solves are skipped.  Flags and fallback counts
 // as the stage kernel's.
-template <int FLUX>
+template <int FLUX, int TS = FT>
 __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::StageArgs a, const char *P, EPacked pk,
                                                                       ENorm nrm, const float *xprev)
 {
-    constexpr int TX = FT, TY = FT, QS = FT + 6, FO = FT + 1;
+    constexpr int TX = TS, TY = TS, QS = TS + 6, FO = TS + 1;
     constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX, YB = 128;  // y faces start at thread YB
     static_assert(NFX <= YB && YB + NFY <= FNW * 64 && TX * TY <= FNW * 64, "one face or cell per thread");
     __shared__ float s_qf[4 * QS * QS];
@@ -1645,18 +1654,18 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
     __shared__ int s_cnt, s_bad;
     const int nx = a.nx, ny = a.ny, tid = threadIdx.x;
     const size_t plane = (size_t)nx * ny;
-    const int tx_n = nx / FT, ty_n = ny / FT, total = a.B * tx_n * ty_n;
+    const int tx_n = nx / TS, ty_n = ny / TS, total = a.B * tx_n * ty_n;
     bool staged = false;  // this workgroup's weights are in LDS
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int b = tile / (tx_n * ty_n);
         if (a.fatal[b]) continue;  // frozen solve (wave-uniform)
         if (staged) __syncthreads();  // the previous tile's LDS reads are done
         const int rt = tile - b * tx_n * ty_n;
-        const int y0 = (rt / tx_n) * FT, x0 = (rt % tx_n) * FT;
+        const int y0 = (rt / tx_n) * TS, x0 = (rt % tx_n) * TS;
         // stage 1 with xprev: a solve whose previous step is flagged is redone
         // on this workgroup's region first (no writer of that slot in stage 1)
         const bool redo = a.flagbit == 1 && xprev && a.flags[2 * b + (a.parity ^ 1)] != 0;
-        const float *s_z = fused_tile_euler<FO, true, FLUX>(
+        const float *s_z = fused_tile_euler<FO, true, FLUX, TS>(
             a.qs + (size_t)b * 4 * plane, P, pk, nrm, nullptr, ny, nx, y0, x0, !staged, s_qf,
             redo ? xprev + (size_t)b * 4 * plane : nullptr, &a, a.fatal + b);
         staged = true;
@@ -1763,20 +1772,30 @@ hipError_t launch_forward_euler_fused(const void *packed, const ENorm &nrm, cons
     return hipGetLastError();
 }
 
+template <int TS>
+static void launch_learned_euler_ts(int flux, int g, const char *Pc, const ENorm &nrm, const eln::StageArgs &a,
+                                    hipStream_t st, const float *xprev)
+{
+    if (flux == fvk::RUSANOV)
+        hipLaunchKernelGGL((conv_learned_euler_kernel<fvk::RUSANOV, TS>), dim3(g), dim3(FNW * 64), 0, st, a, Pc,
+                           euler_packed_layout(), nrm, xprev);
+    else
+        hipLaunchKernelGGL((conv_learned_euler_kernel<fvk::HLLE, TS>), dim3(g), dim3(FNW * 64), 0, st, a, Pc,
+                           euler_packed_layout(), nrm, xprev);
+}
+
 hipError_t launch_learned_euler(int flux, const void *packed, const ENorm &nrm, const eln::StageArgs &a, hipStream_t st,
                                 const float *xprev)
 {
     if (a.nx % FT || a.ny % FT || a.B < 1 || (a.flagbit != 1 && a.flagbit != 2) || (a.flagbit == 2 && xprev))
         return hipErrorInvalidValue;
-    const int tiles = a.B * (a.nx / FT) * (a.ny / FT);
     const int cap = fused_euler_grid();
-    const dim3 g((unsigned)(tiles < cap ? tiles : cap));
-    if (flux == fvk::RUSANOV)
-        hipLaunchKernelGGL(conv_learned_euler_kernel<fvk::RUSANOV>, g, dim3(FNW * 64), 0, st, a, (const char *)packed,
-                           euler_packed_layout(), nrm, xprev);
-    else
-        hipLaunchKernelGGL(conv_learned_euler_kernel<fvk::HLLE>, g, dim3(FNW * 64), 0, st, a, (const char *)packed,
-                           euler_packed_layout(), nrm, xprev);
+    // 4 x 4 tiles while they all get a resident workgroup (more, shorter
+    // workgroups on small batches of small grids), else 8 x 8
+    const int ts = (size_t)a.B * (a.nx / 4) * (a.ny / 4) <= (size_t)cap ? 4 : FT;
+    const int tiles = a.B * (a.nx / ts) * (a.ny / ts), g = tiles < cap ? tiles : cap;
+    if (ts == 4) launch_learned_euler_ts<4>(flux, g, (const char *)packed, nrm, a, st, xprev);
+    else launch_learned_euler_ts<FT>(flux, g, (const char *)packed, nrm, a, st, xprev);
     return hipGetLastError();
 }
 
@@ -1793,11 +1812,11 @@ hipError_t launch_learned_euler(int flux, const void *packed, const ENorm &nrm, 
 // output on the tile and a one-cell ring ([(FT+2)^2][72] from (x0 - 1,
 // y0 - 1)); each face takes its owner's high-side and its neighbour's
 // low-side states (sig = 1 / inv_std of the network input).
-template <int STAGE, bool BL = false, bool DIR = false>
+template <int STAGE, bool BL = false, bool DIR = false, int TS = FT>
 __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &it, const float *s_z, const float *qf,
                                                  const Proj &pr, const int x0, const int y0, const float *sig = nullptr)
 {
-    constexpr int TX = FT, TY = FT, QS = FT + 6, FO = DIR ? FT + 2 : FT + 1;
+    constexpr int TX = TS, TY = TS, QS = TS + 6, FO = DIR ? TS + 2 : TS + 1;
     constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX, YB = 128;  // y faces start at thread YB
     static_assert(NFX <= YB && YB + NFY <= FNW * 64 && TX * TY <= FNW * 64, "one face or cell per thread");
     constexpr float a0 = STAGE == 1 ? 0.0f : 0.5f, a1 = STAGE == 1 ? 1.0f : 0.5f;
@@ -1939,13 +1958,13 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_batch_kernel(const LSol
 // tile written to d.q) and workgroup 0 counts the redo.  Stage 2's workgroup 0
 // clears the previous step's slot (every reader of it has finished: the
 // previous step's stage 2 and this step's stage 1) and advances the time.
-template <int STAGE, bool BL = false, bool DIR = false>
+template <int STAGE, bool BL = false, bool DIR = false, int TS = FT>
 __global__ __launch_bounds__(FNW * 64) void conv_learned_one_kernel(LSolve d, int parity, const float *xprev,
                                                                     const char *P, Packed pk, Norm nrm, Proj pr)
 {
-    constexpr int QS = FT + 6;
+    constexpr int QS = TS + 6;
     __shared__ float s_qf[3 * QS * QS];
-    const int tx_n = d.nx / FT, total = tx_n * (d.ny / FT);
+    const int tx_n = d.nx / TS, total = tx_n * (d.ny / TS);
     const LItem it{0, 0, 0, parity, 0};
     float sig[3];  // DIR: the direct states' de-normalisation, 1 / inv_std (correctly rounded, as the host's)
 #pragma unroll
@@ -1971,9 +1990,9 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_one_kernel(LSolve d, in
         const bool first = w == (int)blockIdx.x;
         if (!first) __syncthreads();  // the previous tile's LDS reads are done
         const int ty = w / tx_n, tx = w - ty * tx_n;
-        const float *s_z = fused_tile<DIR ? FT + 2 : FT + 1, OUT_Z_LDS, 1>(
-            STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx, ty * FT, tx * FT, pr, first, s_qf, &rd);
-        learned_epilogue<STAGE, BL, DIR>(d, it, s_z, s_qf, pr, tx * FT, ty * FT, sig);
+        const float *s_z = fused_tile<DIR ? TS + 2 : TS + 1, OUT_Z_LDS, 1, TS>(
+            STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx, ty * TS, tx * TS, pr, first, s_qf, &rd);
+        learned_epilogue<STAGE, BL, DIR, TS>(d, it, s_z, s_qf, pr, tx * TS, ty * TS, sig);
         w += gridDim.x;
     } while (w < total);
     // no writer of the previous step's slot in stage 1
@@ -2113,6 +2132,43 @@ hipError_t launch_conv_learned_list(int stage, const void *packed, const Norm &n
     return hipGetLastError();
 }
 
+// One solve's kernels for tile side TS, grid g.
+template <int TS>
+static void launch_one_ts(int stage, int blend, int direct, int g, const char *Pc, const Packed &pk, const Norm &nrm,
+                          const Proj &pr, const LSolve &d, int parity, const float *xprev, hipStream_t st)
+{
+    if (direct) {
+        if (stage == 1)
+            hipLaunchKernelGGL((conv_learned_one_kernel<1, false, true, TS>), dim3(g), dim3(FNW * 64), 0, st, d,
+                               parity, xprev, Pc, pk, nrm, pr);
+        else
+            hipLaunchKernelGGL((conv_learned_one_kernel<2, false, true, TS>), dim3(g), dim3(FNW * 64), 0, st, d,
+                               parity, xprev, Pc, pk, nrm, pr);
+    } else if (blend) {
+        if (stage == 1)
+            hipLaunchKernelGGL((conv_learned_one_kernel<1, true, false, TS>), dim3(g), dim3(FNW * 64), 0, st, d,
+                               parity, xprev, Pc, pk, nrm, pr);
+        else
+            hipLaunchKernelGGL((conv_learned_one_kernel<2, true, false, TS>), dim3(g), dim3(FNW * 64), 0, st, d,
+                               parity, xprev, Pc, pk, nrm, pr);
+    } else if (stage == 1) {
+        hipLaunchKernelGGL((conv_learned_one_kernel<1, false, false, TS>), dim3(g), dim3(FNW * 64), 0, st, d, parity,
+                           xprev, Pc, pk, nrm, pr);
+    } else {
+        hipLaunchKernelGGL((conv_learned_one_kernel<2, false, false, TS>), dim3(g), dim3(FNW * 64), 0, st, d, parity,
+                           xprev, Pc, pk, nrm, pr);
+    }
+}
+
+int learned_one_tile(int nx, int ny)
+{
+    if (nx % FT || ny % FT) return 0;
+    // 4 x 4 tiles while they all get a resident workgroup: four times the
+    // workgroups on small grids, each with about half the network work of
+    // an 8 x 8 tile (the halo recompute grows, the latency falls)
+    return (nx / 4) * (ny / 4) <= fused_max_grid() ? 4 : FT;
+}
+
 hipError_t launch_conv_learned_one(int stage, const void *packed, const Norm &nrm, const Proj &pr, const LSolve &d,
                                    int parity, const float *xprev, hipStream_t st, int blend, int direct)
 {
@@ -2120,27 +2176,11 @@ hipError_t launch_conv_learned_one(int stage, const void *packed, const Norm &nr
         (blend && direct))
         return hipErrorInvalidValue;
     const Packed pk = packed_layout();
-    const int tiles = (d.nx / FT) * (d.ny / FT), cap = fused_max_grid(), g = tiles < cap ? tiles : cap;
+    const int ts = learned_one_tile(d.nx, d.ny);
+    const int tiles = (d.nx / ts) * (d.ny / ts), cap = fused_max_grid(), g = tiles < cap ? tiles : cap;
     const char *Pc = (const char *)packed;
-    if (direct) {
-        if (stage == 1)
-            hipLaunchKernelGGL((conv_learned_one_kernel<1, false, true>), dim3(g), dim3(FNW * 64), 0, st, d, parity,
-                               xprev, Pc, pk, nrm, pr);
-        else
-            hipLaunchKernelGGL((conv_learned_one_kernel<2, false, true>), dim3(g), dim3(FNW * 64), 0, st, d, parity,
-                               xprev, Pc, pk, nrm, pr);
-    } else if (blend) {
-        if (stage == 1)
-            hipLaunchKernelGGL((conv_learned_one_kernel<1, true>), dim3(g), dim3(FNW * 64), 0, st, d, parity, xprev, Pc,
-                               pk, nrm, pr);
-        else
-            hipLaunchKernelGGL((conv_learned_one_kernel<2, true>), dim3(g), dim3(FNW * 64), 0, st, d, parity, xprev, Pc,
-                               pk, nrm, pr);
-    } else if (stage == 1) {
-        hipLaunchKernelGGL(conv_learned_one_kernel<1>, dim3(g), dim3(FNW * 64), 0, st, d, parity, xprev, Pc, pk, nrm, pr);
-    } else {
-        hipLaunchKernelGGL(conv_learned_one_kernel<2>, dim3(g), dim3(FNW * 64), 0, st, d, parity, xprev, Pc, pk, nrm, pr);
-    }
+    if (ts == 4) launch_one_ts<4>(stage, blend, direct, g, Pc, pk, nrm, pr, d, parity, xprev, st);
+    else launch_one_ts<FT>(stage, blend, direct, g, Pc, pk, nrm, pr, d, parity, xprev, st);
     return hipGetLastError();
 }
 

@@ -200,14 +200,15 @@ def test_fused_stage_equals_separate_launches(fv, E):
         assert fb1[0] == fb[b]
 
 
-def test_redo_inside_a_call_bitwise(fv, E):
+@pytest.mark.parametrize("n", [32, 64])
+def test_redo_inside_a_call_bitwise(fv, E, n):
     """Two launches per step on whole 8 x 8 tiles: a solve whose step is
     flagged is redone inside the next step's first launch (each workgroup
     redoes it on the region it reads), the call's last step by the
-    commit-or-redo and redo launches.  Over steps in which both solves are
-    redone, states and counts equal one-step calls (every step ended by those
-    launches) bit for bit, for an even and an odd step count."""
-    n = 32
+    commit-or-redo and redo launches.  Over steps with redos of both solves,
+    states and counts equal one-step calls (every step ended by those
+    launches) bit for bit, for an even and an odd step count.  Two 32^2
+    solves run on 4 x 4 network tiles, two 64^2 solves on 8 x 8 tiles."""
     qa = I.random_smooth_euler(n, seed=2)
     kin = 0.5 * (qa[1] ** 2 + qa[2] ** 2) / qa[0]
     qa[3] = kin + 0.1 * (qa[3] - kin)
@@ -216,7 +217,7 @@ def test_redo_inside_a_call_bitwise(fv, E):
     for steps in (4, 5):
         res = []
         for calls in (1, steps):
-            net = gpu_net(fv, p, 2, n, 5e-3)
+            net = gpu_net(fv, p, 2, n, 5e-3 * 32 / n)
             q = torch.tensor(q0, device="cuda").contiguous()
             for _ in range(calls):
                 net.step(q, steps // calls)
@@ -225,7 +226,7 @@ def test_redo_inside_a_call_bitwise(fv, E):
             net.close()
         print(f"[euler redo in call] {steps} steps: one call {res[0][1:]} / one-step calls {res[1][1:]}", flush=True)
         assert res[0][4] == fv.FV_OK and max(res[0][3]) == 0
-        assert sum(res[0][2]) >= steps
+        assert sum(res[0][2]) >= (steps if n == 32 else 2)
         assert np.array_equal(res[0][0], res[1][0]) and res[0][1:] == res[1][1:]
 
 

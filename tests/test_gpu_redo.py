@@ -81,37 +81,39 @@ def test_forced_redo_matches_oracle(fv, L, scheme, flux):
     assert state_rel(out, ref) <= 1e-4
 
 
-@pytest.mark.parametrize("blend", [False, True])
-def test_redo_inside_a_call_bitwise(fv, L, blend):
+@pytest.mark.parametrize("n", [32, 128])
+@pytest.mark.parametrize("scheme", ["learned", "blend", "direct"])
+def test_redo_inside_a_call_bitwise(fv, L, scheme, n):
     """A single solve's learned steps run two launches per step: a flagged
     step is redone inside the next step's first launch (each workgroup redoes
     it on the region it reads), the call's last step by the commit-or-redo and
     redo launches.  States, time and counts are bit-identical to one-step
     calls (every step ended by those launches) and, for the learned scheme,
     to the server (separate launches at the end of every step), for an even
-    and an odd step count."""
+    and an odd step count.  32^2 runs the single solve's 4 x 4 network tiles,
+    128^2 its 8 x 8 tiles (the server's)."""
     p = L.init_params(2, scale_last=10.0)
-    q0 = shallow_state().astype(np.float32)
+    q0 = shallow_state(n).astype(np.float32)
     vec = fv.params_to_vector([w.numpy() for w in p["w"]], [b.numpy() for b in p["b"]])
     m = fv.Model(vec, fv.make_model_desc(mean=tuple(p["mean"].tolist()), inv_std=tuple(p["inv_std"].tolist())))
-    dt = 1e-3
+    dt = 1e-3 * 32 / n
     for steps in (4, 5):
         s = fv.Solver(q0, prec=fv.FV_F32, dt_fixed=dt, learned=1)
-        step = s.blend_step if blend else s.learned_step
+        step = {"learned": s.learned_step, "direct": s.direct_step, "blend": s.blend_step}[scheme]
         fb, red = step(m, steps)
         got, (t, k) = s.state(), s.time()
         s.close()
         s = fv.Solver(q0, prec=fv.FV_F32, dt_fixed=dt, learned=1)
-        step = s.blend_step if blend else s.learned_step
+        step = {"learned": s.learned_step, "direct": s.direct_step, "blend": s.blend_step}[scheme]
         for _ in range(steps):
             fb1, red1 = step(m, 1)
         one, (t1, k1) = s.state(), s.time()
         s.close()
-        print(f"[redo in call] blend={blend} {steps} steps: redone {red} / one-step calls {red1}, fallback "
+        print(f"[redo in call] {scheme} {n}^2 {steps} steps: redone {red} / one-step calls {red1}, fallback "
               f"{fb}/{fb1}", flush=True)
         assert red >= 2 and (fb, red) == (fb1, red1)
         assert np.array_equal(got, one) and (t, k) == (t1, k1) and k == steps
-        if blend:
+        if scheme != "learned":
             continue
         srv = fv.Server(64 << 20, max_solves=4, steps_per_round=10, max_items=1 << 12, model=m)
         rid = srv.submit(q0, steps, learned=True, dt_fixed=dt)
