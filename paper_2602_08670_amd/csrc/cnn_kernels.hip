@@ -833,6 +833,7 @@ __device__ __forceinline__ void fused_hidden(const bf16x8 *in, int rin, bf16 *ou
     constexpr int NT = 2;
     const int g = lane >> 4, px = lane & 15;
     const int rout = rin - 2, npx = rout * rout, ngrp = (npx + 15) >> 4;
+    if (wave >= ngrp) return;  // no group for this wave: its weight reads are skipped
     bf16x8 A[9][NT];
 #pragma unroll
     for (int tap = 0; tap < 9; tap++)
@@ -849,6 +850,36 @@ __device__ __forceinline__ void fused_hidden(const bf16x8 *in, int rin, bf16 *ou
     for (int gi = wave; gi < ngrp; gi += 2 * FNW) {
         if (gi + FNW < ngrp) hidden_groups<2>(in, rin, out, A, bs, gi, rout, npx, g, px);
         else hidden_groups<1>(in, rin, out, A, bs, gi, rout, npx, g, px);
+    }
+}
+
+// The last layer on few pixel groups (NG groups of 16 pixels of the FO x FO
+// region, its input region FO + 2 wide in act): wave t < NT takes co tile t
+// for every group, so that a wave reads one tile's 9 weight fragments and
+// NT waves share the layer; each chain keeps the tap order 0..8.  acc:
+// the wave's NG accumulators (zero for waves past NT).
+template <int NG, int NT, int FO>
+__device__ __forceinline__ void last_layer_by_tile(const bf16x8 *act, const bf16x8 *w, int wave, int g, int px,
+                                                   floatx4 (&acc)[NG])
+{
+    constexpr int RIN = FO + 2, NPX = FO * FO;
+#pragma unroll
+    for (int k = 0; k < NG; k++) acc[k] = floatx4{0.f, 0.f, 0.f, 0.f};
+    if (wave >= NT) return;  // wave-uniform: a real branch around the MFMAs
+    int bo[NG];
+#pragma unroll
+    for (int k = 0; k < NG; k++) {
+        const int p = k * 16 + px, pc = p < NPX ? p : 0;
+        const int py = pc / FO, pxx = pc - py * FO;
+        bo[k] = (py * RIN + pxx) * 4 + g;
+    }
+#pragma unroll
+    for (int tap = 0; tap < 9; tap++) {
+        const bf16x8 a = w[((tap * NT + wave) * 16 + px) * 4 + g];
+        const int tb = ((tap / 3) * RIN + tap % 3) * 4;
+#pragma unroll
+        for (int k = 0; k < NG; k++)
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[bo[k] + tb], acc[k], 0, 0, 0);
     }
 }
 
@@ -1255,7 +1286,31 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     float *s_z = (float *)s_act;
     static_assert(FO * FO * 72 * 4 <= sizeof(s_act), "coefficient region fits over the activations");
     constexpr bool ALPHA = OUT != OUT_Z;  // z staged in LDS
-    {
+    constexpr int NG4 = (FO * FO + 15) / 16;
+    if constexpr (NG4 <= 3) {
+        floatx4 acc[NG4];
+        last_layer_by_tile<NG4, 5, FO>(s_a1, s_w, wave, g, px, acc);
+        if (ALPHA) __syncthreads();  // every wave past its layer-4 reads of s_a1 before it holds z
+        const float *bias = (const float *)(P + pk.b[4]);
+        const int co0 = 16 * wave + 4 * g;
+        if (wave < 5 && co0 < 72) {
+#pragma unroll
+            for (int k = 0; k < NG4; k++) {
+                const int p = k * 16 + px;
+                if (p < FO * FO) {
+                    floatx4 o;
+#pragma unroll
+                    for (int i = 0; i < 4; i++) o[i] = acc[k][i] + bias[co0 + i];
+                    if (ALPHA) {
+                        *(floatx4 *)(s_z + p * 72 + co0) = o;
+                    } else {
+                        const int py = p / FO, pxx = p - py * FO;
+                        *(floatx4 *)(zb + ((size_t)(y0 + py) * W + x0 + pxx) * 72 + co0) = o;
+                    }
+                }
+            }
+        }
+    } else {
         // pixel groups wave, wave + FNW, ... with all NT co tiles, the
         // activation fragment read once per tap for NT MFMAs; each co tile's
         // chain keeps the tap order 0..8
@@ -1571,7 +1626,32 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
     // stored after every wave's layer-4 reads
     float *s_z = (float *)s_act;
     static_assert(!ZLDS || FO * FO * E_COUT * 4 <= sizeof(s_act), "coefficient region fits over the activations");
-    {
+    constexpr int NG4 = (FO * FO + 15) / 16;
+    if constexpr (NG4 <= 3) {
+        // few pixel groups: one co tile per wave (last_layer_by_tile)
+        floatx4 acc[NG4];
+        last_layer_by_tile<NG4, 6, FO>(s_a1, s_wall + EW0 + 3 * EWH, wave, g, px, acc);
+        if (ZLDS) __syncthreads();
+        const float *bias = (const float *)(P + pk.b[4]);
+        const int co0 = 16 * wave + 4 * g;
+        if (wave < 6) {
+#pragma unroll
+            for (int k = 0; k < NG4; k++) {
+                const int p = k * 16 + px;
+                if (p < FO * FO) {
+                    floatx4 o;
+#pragma unroll
+                    for (int i = 0; i < 4; i++) o[i] = acc[k][i] + bias[co0 + i];
+                    if (ZLDS) {
+                        *(floatx4 *)(s_z + p * E_COUT + co0) = o;
+                    } else {
+                        const int py = p / FO, pxx = p - py * FO;
+                        *(floatx4 *)(zb + ((size_t)(y0 + py) * W + x0 + pxx) * E_COUT + co0) = o;
+                    }
+                }
+            }
+        }
+    } else {
         constexpr int NT = 6, RIN = FO + 2, NPX = FO * FO, NG = (NPX + 15) / 16, GPW = (NG + FNW - 1) / FNW;
         const bf16x8 *s_w = s_wall + EW0 + 3 * EWH;
         const float *bias = (const float *)(P + pk.b[4]);
@@ -1665,7 +1745,7 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
         // stage 1 with xprev: a solve whose previous step is flagged is redone
         // on this workgroup's region first (no writer of that slot in stage 1)
         const bool redo = a.flagbit == 1 && xprev && a.flags[2 * b + (a.parity ^ 1)] != 0;
-        const float *s_z = fused_tile_euler<FO, true, FLUX, TS>(
+        float *s_z = fused_tile_euler<FO, true, FLUX, TS>(
             a.qs + (size_t)b * 4 * plane, P, pk, nrm, nullptr, ny, nx, y0, x0, !staged, s_qf,
             redo ? xprev + (size_t)b * 4 * plane : nullptr, &a, a.fatal + b);
         staged = true;
@@ -1678,6 +1758,13 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
             s_cnt = 0;
             s_bad = 0;
         }
+        // every pixel's sixteen groups of six projected in place by all the
+        // workgroup's threads, alpha = base + P z (the faces then read alpha)
+        for (int task = tid; task < FO * FO * 16; task += FNW * 64) {
+            const int p = task >> 4, grp = task & 15;
+            alpha_group(s_z + p * E_COUT + grp * 6, (grp >> 2) & 1, a.pr);
+        }
+        __syncthreads();
         int nfb = 0;
         if (tid < NFX) {
             // x face: owner cell (x0 - 1 + xi, y0 + xj), pixel (xi, xj + 1) of the coefficient region
@@ -1688,7 +1775,8 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
 #pragma unroll
                 for (int k = 0; k < 6; k++) st[v][k] = s_qf[(v * QS + xj + 3) * QS + xi + k];
             float QL[4], QR[4], F[4];
-            const int c = eln::face_states<true>(st, s_z + ((xj + 1) * FO + xi) * E_COUT, a.pr, a.gamma, QL, QR);
+            const int c = eln::face_states<true, true>(st, s_z + ((xj + 1) * FO + xi) * E_COUT, a.pr, a.gamma, QL,
+                                                       QR);
             if (xi < TX) nfb += c;  // counted once: as a cell's low face
             eln::flux4<FLUX, 0>(QL, QR, a.gamma, F);
 #pragma unroll
@@ -1703,7 +1791,8 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
 #pragma unroll
                 for (int k = 0; k < 6; k++) st[v][k] = s_qf[(v * QS + yj + k) * QS + yi + 3];
             float QL[4], QR[4], F[4];
-            const int c = eln::face_states<true>(st, s_z + (yj * FO + yi + 1) * E_COUT + 48, a.pr, a.gamma, QL, QR);
+            const int c = eln::face_states<true, true>(st, s_z + (yj * FO + yi + 1) * E_COUT + 48, a.pr, a.gamma,
+                                                       QL, QR);
             if (yj < TY) nfb += c;
             eln::flux4<FLUX, 1>(QL, QR, a.gamma, F);
 #pragma unroll
@@ -1813,7 +1902,7 @@ hipError_t launch_learned_euler(int flux, const void *packed, const ENorm &nrm, 
 // y0 - 1)); each face takes its owner's high-side and its neighbour's
 // low-side states (sig = 1 / inv_std of the network input).
 template <int STAGE, bool BL = false, bool DIR = false, int TS = FT>
-__device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &it, const float *s_z, const float *qf,
+__device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &it, float *s_z, const float *qf,
                                                  const Proj &pr, const int x0, const int y0, const float *sig = nullptr)
 {
     constexpr int TX = TS, TY = TS, QS = TS + 6, FO = DIR ? TS + 2 : TS + 1;
@@ -1841,6 +1930,15 @@ __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &i
         s_cnt = 0;
         s_bad = 0;
     }
+    if constexpr (!DIR) {
+        // every pixel's twelve groups of six projected in place by all the
+        // workgroup's threads, alpha = base + P z (the faces then read alpha)
+        for (int task = tid; task < FO * FO * 12; task += FNW * 64) {
+            const int p = task / 12, grp = task - p * 12;
+            alpha_group(s_z + p * 72 + grp * 6, (grp / 3) & 1, pr);
+        }
+        __syncthreads();
+    }
     int nfb = 0;
     if (tid < NFX) {
         // x face: owner cell (x0 - 1 + xi, y0 + xj)
@@ -1853,7 +1951,7 @@ __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &i
         float QL[3], QR[3], F[3];
         const int c = DIR ? face_states_direct(st, s_z + ((xj + 1) * FO + xi) * 72 + 3,
                                                s_z + ((xj + 1) * FO + xi + 1) * 72, sig, QL, QR)
-                          : face_states<0, false>(st, s_z + ((xj + 1) * FO + xi) * 72, pr, QL, QR);
+                          : face_states<0, true>(st, s_z + ((xj + 1) * FO + xi) * 72, pr, QL, QR);
         if (xi < TX) nfb += c;  // each face counted once: as the left face of a cell of this tile
         flux3<fvk::HLLE, 0>(QL, QR, ph, F);
         if (BL) blend_flux<fvk::HLLE, 0>(st, ph, F);
@@ -1871,7 +1969,7 @@ __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &i
         float QL[3], QR[3], F[3];
         const int c = DIR ? face_states_direct(st, s_z + (yj * FO + yi + 1) * 72 + 9,
                                                s_z + ((yj + 1) * FO + yi + 1) * 72 + 6, sig, QL, QR)
-                          : face_states<0, false>(st, s_z + (yj * FO + yi + 1) * 72 + 36, pr, QL, QR);
+                          : face_states<0, true>(st, s_z + (yj * FO + yi + 1) * 72 + 36, pr, QL, QR);
         if (yj < TY) nfb += c;
         flux3<fvk::HLLE, 1>(QL, QR, ph, F);
         if (BL) blend_flux<fvk::HLLE, 1>(st, ph, F);
@@ -1941,7 +2039,7 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_batch_kernel(const LSol
         const LSolve &d = tab[it.solve];
         const int tile = w - it.tb_cnn, tx_n = d.nx / FT;
         const int ty = tile / tx_n, tx = tile - ty * tx_n;
-        const float *s_z = fused_tile<FT + 1, OUT_Z_LDS>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx,
+        float *s_z = fused_tile<FT + 1, OUT_Z_LDS>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx,
                                                              ty * FT, tx * FT, pr, first, s_qf);
         learned_epilogue<STAGE, BL>(d, it, s_z, s_qf, pr, tx * FT, ty * FT);
     }
@@ -1990,7 +2088,7 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_one_kernel(LSolve d, in
         const bool first = w == (int)blockIdx.x;
         if (!first) __syncthreads();  // the previous tile's LDS reads are done
         const int ty = w / tx_n, tx = w - ty * tx_n;
-        const float *s_z = fused_tile<DIR ? TS + 2 : TS + 1, OUT_Z_LDS, 1, TS>(
+        float *s_z = fused_tile<DIR ? TS + 2 : TS + 1, OUT_Z_LDS, 1, TS>(
             STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx, ty * TS, tx * TS, pr, first, s_qf, &rd);
         learned_epilogue<STAGE, BL, DIR, TS>(d, it, s_z, s_qf, pr, tx * TS, ty * TS, sig);
         w += gridDim.x;

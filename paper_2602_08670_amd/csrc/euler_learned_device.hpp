@@ -21,8 +21,10 @@ __device__ __forceinline__ bool admissible(const float *Q, float gamma)
 
 // Face states from the stencil st[v][0..5] (cells i-2..i+3 along the
 // normal); LEARNED: from the owner's 48 raw coefficients of this axis
-// (zc[(side*4 + v)*6 + k]).  Returns the number of sides that fell back.
-template <bool LEARNED>
+// (zc[(side*4 + v)*6 + k]), or with AL from its 48 projected ones (alpha =
+// base + P z, the same operation order).  Returns the number of sides that
+// fell back.
+template <bool LEARNED, bool AL = false>
 __device__ __forceinline__ int face_states(const float (*st)[6], const float *zc, const cnn::Proj &pr, float gamma,
                                            float *QL, float *QR)
 {
@@ -51,9 +53,14 @@ __device__ __forceinline__ int face_states(const float (*st)[6], const float *zc
             float acc = 0.0f;
 #pragma unroll
             for (int k = 0; k < 6; k++) {
-                float al = pr.base[s * 6 + k];
+                float al;
+                if (AL) {
+                    al = zz[k];
+                } else {
+                    al = pr.base[s * 6 + k];
 #pragma unroll
-                for (int j = 0; j < 6; j++) al += pr.P[k * 6 + j] * zz[j];
+                    for (int j = 0; j < 6; j++) al += pr.P[k * 6 + j] * zz[j];
+                }
                 acc += al * st[v][k];
             }
             (s == 0 ? QL : QR)[v] = acc;
