@@ -781,20 +781,34 @@ constexpr int FW_EL = 9 * 5 * 16 * 32;  // largest packed weight block (layer 4)
 // reuses them for all its pixel groups; only B is read per group and tap.
 constexpr int FNW = 8;  // waves per workgroup of the fused pass
 
+// LDS layouts of the fused passes, chosen so that the 16 lanes of an MFMA
+// operand fragment that share a K block read 16 different 16-byte bank
+// groups.  Weights: the packed block's fragment of 64 octets (16 rows x 4 K
+// blocks, row-major) is stored K-block-major: octet (row, g) at g * 16 +
+// row.  Activations: pixel q's octet g (channels 8g .. 8g + 7) at
+// q * AS + g; AS = 5 octets per pixel (an odd stride: 16 consecutive pixels
+// fall in 16 different bank groups, and a tap's shift stays a constant
+// offset), AS = 4 (unpadded) where LDS has no room for the padding.
+__device__ __forceinline__ unsigned wfrag_slot(unsigned i) { return (i & ~63u) | ((i & 3u) << 4) | ((i >> 2) & 15u); }
+__device__ __forceinline__ int wfrag(int f, int row, int g) { return (f * 4 + g) * 16 + row; }
+template <int AS> __device__ __forceinline__ int act_slot(int q, int g) { return q * AS + g; }
+// bf16 offset of channels co0 .. co0 + 3 (co0 % 4 == 0) of pixel q
+template <int AS> __device__ __forceinline__ int act_off(int q, int co0) { return q * AS * 8 + co0; }
+
 // NG pixel groups gi, gi + FNW, ... of a hidden layer with both co tiles:
 // 2 NG accumulation chains advanced together.
-template <int NG>
+template <int NG, int AS>
 __device__ __forceinline__ void hidden_groups(const bf16x8 *in, int rin, bf16 *out, const bf16x8 (*A)[2],
                                               const float (*bs)[4], int gi, int rout, int npx, int g, int px)
 {
     constexpr int NT = 2;
-    int p[NG], bo[NG];
+    int p[NG], qb[NG];
 #pragma unroll
     for (int k = 0; k < NG; k++) {
         p[k] = (gi + k * FNW) * 16 + px;
         const int pc = p[k] < npx ? p[k] : 0;
         const int py = pc / rout, pxx = pc - py * rout;
-        bo[k] = (py * rin + pxx) * 4 + g;
+        qb[k] = py * rin + pxx;  // the input pixel of tap 0
     }
     floatx4 acc[NG][NT];
 #pragma unroll
@@ -803,10 +817,10 @@ __device__ __forceinline__ void hidden_groups(const bf16x8 *in, int rin, bf16 *o
         for (int t = 0; t < NT; t++) acc[k][t] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int tap = 0; tap < 9; tap++) {
-        const int tb = ((tap / 3) * rin + tap % 3) * 4;
+        const int tq = (tap / 3) * rin + tap % 3;
 #pragma unroll
         for (int k = 0; k < NG; k++) {
-            const bf16x8 bx = in[bo[k] + tb];
+            const bf16x8 bx = in[act_slot<AS>(qb[k] + tq, g)];
 #pragma unroll
             for (int t = 0; t < NT; t++)
                 acc[k][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[tap][t], bx, acc[k][t], 0, 0, 0);
@@ -821,12 +835,13 @@ __device__ __forceinline__ void hidden_groups(const bf16x8 *in, int rin, bf16 *o
                 bf16x4 o;
 #pragma unroll
                 for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[k][t][i] + bs[t][i], 0.0f);
-                *(bf16x4 *)(out + (size_t)p[k] * 32 + co0) = o;
+                *(bf16x4 *)(out + act_off<AS>(p[k], co0)) = o;
             }
         }
     }
 }
 
+template <int AS>
 __device__ __forceinline__ void fused_hidden(const bf16x8 *in, int rin, bf16 *out, const bf16x8 *w, const float *bias,
                                              int wave, int lane)
 {
@@ -838,7 +853,7 @@ __device__ __forceinline__ void fused_hidden(const bf16x8 *in, int rin, bf16 *ou
 #pragma unroll
     for (int tap = 0; tap < 9; tap++)
 #pragma unroll
-        for (int t = 0; t < NT; t++) A[tap][t] = w[((tap * NT + t) * 16 + px) * 4 + g];
+        for (int t = 0; t < NT; t++) A[tap][t] = w[wfrag(tap * NT + t, px, g)];
     float bs[NT][4];
 #pragma unroll
     for (int t = 0; t < NT; t++)
@@ -848,8 +863,8 @@ __device__ __forceinline__ void fused_hidden(const bf16x8 *in, int rin, bf16 *ou
     // real branch: an MFMA does not honour a partial EXEC), their four
     // chains advanced tap by tap; each chain's taps keep their order
     for (int gi = wave; gi < ngrp; gi += 2 * FNW) {
-        if (gi + FNW < ngrp) hidden_groups<2>(in, rin, out, A, bs, gi, rout, npx, g, px);
-        else hidden_groups<1>(in, rin, out, A, bs, gi, rout, npx, g, px);
+        if (gi + FNW < ngrp) hidden_groups<2, AS>(in, rin, out, A, bs, gi, rout, npx, g, px);
+        else hidden_groups<1, AS>(in, rin, out, A, bs, gi, rout, npx, g, px);
     }
 }
 
@@ -858,7 +873,7 @@ __device__ __forceinline__ void fused_hidden(const bf16x8 *in, int rin, bf16 *ou
 // for every group, so that a wave reads one tile's 9 weight fragments and
 // NT waves share the layer; each chain keeps the tap order 0..8.  acc:
 // the wave's NG accumulators (zero for waves past NT).
-template <int NG, int NT, int FO>
+template <int NG, int NT, int FO, int AS>
 __device__ __forceinline__ void last_layer_by_tile(const bf16x8 *act, const bf16x8 *w, int wave, int g, int px,
                                                    floatx4 (&acc)[NG])
 {
@@ -866,20 +881,20 @@ __device__ __forceinline__ void last_layer_by_tile(const bf16x8 *act, const bf16
 #pragma unroll
     for (int k = 0; k < NG; k++) acc[k] = floatx4{0.f, 0.f, 0.f, 0.f};
     if (wave >= NT) return;  // wave-uniform: a real branch around the MFMAs
-    int bo[NG];
+    int qb[NG];
 #pragma unroll
     for (int k = 0; k < NG; k++) {
         const int p = k * 16 + px, pc = p < NPX ? p : 0;
         const int py = pc / FO, pxx = pc - py * FO;
-        bo[k] = (py * RIN + pxx) * 4 + g;
+        qb[k] = py * RIN + pxx;
     }
 #pragma unroll
     for (int tap = 0; tap < 9; tap++) {
-        const bf16x8 a = w[((tap * NT + wave) * 16 + px) * 4 + g];
-        const int tb = ((tap / 3) * RIN + tap % 3) * 4;
+        const bf16x8 a = w[wfrag(tap * NT + wave, px, g)];
+        const int tq = (tap / 3) * RIN + tap % 3;
 #pragma unroll
         for (int k = 0; k < NG; k++)
-            acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[bo[k] + tb], acc[k], 0, 0, 0);
+            acc[k] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, act[act_slot<AS>(qb[k] + tq, g)], acc[k], 0, 0, 0);
     }
 }
 
@@ -901,12 +916,15 @@ template <int N> struct Chunks {
             if (i < (unsigned)N) v[k] = g[i];
         }
     }
-    __device__ __forceinline__ void store(bf16x8 *s) const
+    // PERM: each 64-octet fragment K-block-major (wfrag_slot; T is a
+    // multiple of 64, so octet i + k T goes to wfrag_slot(i) + k T)
+    template <bool PERM = true> __device__ __forceinline__ void store(bf16x8 *s) const
     {
+        static_assert(T % 64 == 0, "whole fragments per stride");
+        const unsigned b = PERM ? wfrag_slot(threadIdx.x) : threadIdx.x;
 #pragma unroll
         for (int k = 0; k < IT; k++) {
-            const int i = threadIdx.x + k * T;
-            if (i < N) s[i] = v[k];
+            if (threadIdx.x + k * T < (unsigned)N) s[b + k * T] = v[k];
         }
     }
 };
@@ -1138,9 +1156,10 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     __shared__ bf16 s_in[3][FRI_ * FRI_];
     // activations, 32 channels = 4 x bf16x8 per pixel: layers 0 and 2 write
     // s_a0, layers 1 and 3 write s_a1
-    __shared__ bf16x8 s_act[FR0_ * FR0_ * 4 + (FR0_ - 2) * (FR0_ - 2) * 4];
+    constexpr int AS = 5;  // activation octets per pixel (act_slot)
+    __shared__ bf16x8 s_act[FR0_ * FR0_ * AS + (FR0_ - 2) * (FR0_ - 2) * AS];
     bf16x8 *const s_a0 = s_act;
-    bf16x8 *const s_a1 = s_act + FR0_ * FR0_ * 4;
+    bf16x8 *const s_a1 = s_act + FR0_ * FR0_ * AS;
     // all five layers' packed weights, staged together
     constexpr int W0 = 32 * 32 / 8, WH = 9 * 32 * 32 / 8, W4 = FW_EL / 8;
     __shared__ bf16x8 s_wall[W0 + 3 * WH + W4];
@@ -1216,7 +1235,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     // layer 0 on the FR0_ x FR0_ region, 16 pixels per group
     {
         const float *bias = (const float *)(P + pk.b[0]);
-        const bf16x8 A0 = s_wall[px * 4 + g], A1 = s_wall[(16 + px) * 4 + g];
+        const bf16x8 A0 = s_wall[wfrag(0, px, g)], A1 = s_wall[wfrag(1, px, g)];
         constexpr int NP0 = FR0_ * FR0_, NG0 = (NP0 + 15) / 16, KG = (NG0 + FNW - 1) / FNW;
         // all KG groups gi = wave + k FNW of this wave at once (a group past
         // the region computes on pixel 0 and stores nothing), so that every
@@ -1253,7 +1272,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
                     bf16x4 o;
 #pragma unroll
                     for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[t][i] + bias[co0 + i], 0.0f);
-                    *(bf16x4 *)((bf16 *)s_a0 + (size_t)p * 32 + co0) = o;
+                    *(bf16x4 *)((bf16 *)s_a0 + act_off<AS>(p, co0)) = o;
                 }
             }
         }
@@ -1273,7 +1292,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
         const int rin = FR0_ - 2 * (l - 1);
         const bf16x8 *in = (l & 1) ? s_a0 : s_a1;
         bf16 *out = (bf16 *)((l & 1) ? s_a1 : s_a0);
-        fused_hidden(in, rin, out, s_wall + W0 + (l - 1) * WH, (const float *)(P + pk.b[l]), wave, lane);
+        fused_hidden<AS>(in, rin, out, s_wall + W0 + (l - 1) * WH, (const float *)(P + pk.b[l]), wave, lane);
     }
     __syncthreads();
     // layer 4: s_a1 (FO + 2)^2 -> z on the FO x FO region: NG pixel groups x
@@ -1289,7 +1308,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     constexpr int NG4 = (FO * FO + 15) / 16;
     if constexpr (NG4 <= 3) {
         floatx4 acc[NG4];
-        last_layer_by_tile<NG4, 5, FO>(s_a1, s_w, wave, g, px, acc);
+        last_layer_by_tile<NG4, 5, FO, AS>(s_a1, s_w, wave, g, px, acc);
         if (ALPHA) __syncthreads();  // every wave past its layer-4 reads of s_a1 before it holds z
         const float *bias = (const float *)(P + pk.b[4]);
         const int co0 = 16 * wave + 4 * g;
@@ -1327,14 +1346,14 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
             if (gi < NG) {  // wave-uniform, a real branch: an MFMA does not honour a partial EXEC
                 const int pc = p < NPX ? p : 0;
                 const int py = pc / FO, pxx = pc - py * FO;
-                const int bo = (py * RIN + pxx) * 4 + g;
+                const int qb = py * RIN + pxx;
 #pragma unroll
                 for (int tap = 0; tap < 9; tap++) {
-                    const bf16x8 bx = s_a1[bo + ((tap / 3) * RIN + tap % 3) * 4];
+                    const bf16x8 bx = s_a1[act_slot<AS>(qb + (tap / 3) * RIN + tap % 3, g)];
 #pragma unroll
                     for (int t = 0; t < NT; t++)
-                        acc[k][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * 4 + g],
-                                                                            bx, acc[k][t], 0, 0, 0);
+                        acc[k][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[wfrag(tap * NT + t, px, g)], bx,
+                                                                            acc[k][t], 0, 0, 0);
                 }
             }
         }
@@ -1503,10 +1522,13 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
     static_assert(TS == FT || ZLDS, "other tile sides only for a stage in the same workgroup");
     constexpr int OFF = FO - TS, FRI_ = FO + 10, FR0_ = FO + 8;
     __shared__ bf16 s_in[E_CIN][FRI_ * FRI_];
-    __shared__ bf16x8 s_act[FR0_ * FR0_ * 4 + (FR0_ - 2) * (FR0_ - 2) * 4];
+    // activation octets per pixel (act_slot): the padded layout, except on
+    // the largest region with the stage's buffers, where it would not fit
+    constexpr int AS = (ZLDS && FO == FT + 1) ? 4 : 5;
+    __shared__ bf16x8 s_act[FR0_ * FR0_ * AS + (FR0_ - 2) * (FR0_ - 2) * AS];
     __shared__ bf16x8 s_wall[EW0 + 3 * EWH + EW4];
     bf16x8 *const s_a0 = s_act;
-    bf16x8 *const s_a1 = s_act + FR0_ * FR0_ * 4;
+    bf16x8 *const s_a1 = s_act + FR0_ * FR0_ * AS;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int g = lane >> 4, px = lane & 15;
     const size_t hw = (size_t)H * W;
@@ -1565,7 +1587,7 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
         }
     }
     if (load_w) {
-        c0.store(s_wall);
+        c0.store<false>(s_wall);  // layer 0 reads its two K blocks in the packed order
         c1.store(s_wall + EW0);
         c2.store(s_wall + EW0 + EWH);
         c3.store(s_wall + EW0 + 2 * EWH);
@@ -1605,7 +1627,7 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
                     bf16x4 o;
 #pragma unroll
                     for (int i = 0; i < 4; i++) o[i] = (bf16)__builtin_fmaxf(acc[i] + bias[co0 + i], 0.0f);
-                    *(bf16x4 *)((bf16 *)s_a0 + (size_t)p * 32 + co0) = o;
+                    *(bf16x4 *)((bf16 *)s_a0 + act_off<AS>(p, co0)) = o;
                 }
             }
         }
@@ -1617,7 +1639,7 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
         const int rin = FR0_ - 2 * (l - 1);
         const bf16x8 *in = (l & 1) ? s_a0 : s_a1;
         bf16 *out = (bf16 *)((l & 1) ? s_a1 : s_a0);
-        fused_hidden(in, rin, out, s_wall + EW0 + (l - 1) * EWH, (const float *)(P + pk.b[l]), wave, lane);
+        fused_hidden<AS>(in, rin, out, s_wall + EW0 + (l - 1) * EWH, (const float *)(P + pk.b[l]), wave, lane);
     }
     __syncthreads();
     // layer 4: s_a1 (FO + 2)^2 -> z on the FO x FO region, pixel groups wave,
@@ -1630,7 +1652,7 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
     if constexpr (NG4 <= 3) {
         // few pixel groups: one co tile per wave (last_layer_by_tile)
         floatx4 acc[NG4];
-        last_layer_by_tile<NG4, 6, FO>(s_a1, s_wall + EW0 + 3 * EWH, wave, g, px, acc);
+        last_layer_by_tile<NG4, 6, FO, AS>(s_a1, s_wall + EW0 + 3 * EWH, wave, g, px, acc);
         if (ZLDS) __syncthreads();
         const float *bias = (const float *)(P + pk.b[4]);
         const int co0 = 16 * wave + 4 * g;
@@ -1664,14 +1686,14 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
             if (gi < NG) {  // wave-uniform, a real branch: an MFMA does not honour a partial EXEC
                 const int pc = p < NPX ? p : 0;
                 const int py = pc / FO, pxx = pc - py * FO;
-                const int bo = (py * RIN + pxx) * 4 + g;
+                const int qb = py * RIN + pxx;
 #pragma unroll
                 for (int tap = 0; tap < 9; tap++) {
-                    const bf16x8 bx = s_a1[bo + ((tap / 3) * RIN + tap % 3) * 4];
+                    const bf16x8 bx = s_a1[act_slot<AS>(qb + (tap / 3) * RIN + tap % 3, g)];
 #pragma unroll
                     for (int t = 0; t < NT; t++)
-                        acc[k][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[((tap * NT + t) * 16 + px) * 4 + g],
-                                                                            bx, acc[k][t], 0, 0, 0);
+                        acc[k][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(s_w[wfrag(tap * NT + t, px, g)], bx,
+                                                                            acc[k][t], 0, 0, 0);
                 }
             }
         }
