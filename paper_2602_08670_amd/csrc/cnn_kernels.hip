@@ -1767,6 +1767,14 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
         // stage 1 with xprev: a solve whose previous step is flagged is redone
         // on this workgroup's region first (no writer of that slot in stage 1)
         const bool redo = a.flagbit == 1 && xprev && a.flags[2 * b + (a.parity ^ 1)] != 0;
+        // stage 2 (a0 != 0): the cell's q^n loaded now, its latency behind the network pass
+        float q0v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (a.a0 != 0.0f && tid < TX * TY) {
+            const int cy = tid / TX, cx = tid - cy * TX;
+            const size_t idx = (size_t)b * 4 * plane + (size_t)(y0 + cy) * nx + x0 + cx;
+#pragma unroll
+            for (int v = 0; v < 4; v++) q0v[v] = a.q0[idx + v * plane];
+        }
         float *s_z = fused_tile_euler<FO, true, FLUX, TS>(
             a.qs + (size_t)b * 4 * plane, P, pk, nrm, nullptr, ny, nx, y0, x0, !staged, s_qf,
             redo ? xprev + (size_t)b * 4 * plane : nullptr, &a, a.fatal + b);
@@ -1831,7 +1839,7 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
                 const float L = -(s_fx[v][cy][cx + 1] - s_fx[v][cy][cx]) * a.rdx -
                                 (s_fy[v][cy + 1][cx] - s_fy[v][cy][cx]) * a.rdy;
                 float o = a.a1 * (s_qf[(v * QS + cy + 3) * QS + cx + 3] + a.dt * L);
-                if (a.a0 != 0.0f) o = a.a0 * a.q0[idx + v * plane] + o;
+                if (a.a0 != 0.0f) o = a.a0 * q0v[v] + o;
                 a.out[idx + v * plane] = o;
                 qn[v] = o;
             }
@@ -1923,9 +1931,11 @@ hipError_t launch_learned_euler(int flux, const void *packed, const ENorm &nrm, 
 // output on the tile and a one-cell ring ([(FT+2)^2][72] from (x0 - 1,
 // y0 - 1)); each face takes its owner's high-side and its neighbour's
 // low-side states (sig = 1 / inv_std of the network input).
+// q0v (STAGE 2, or NULL): the cell's q^n values, loaded by the caller.
 template <int STAGE, bool BL = false, bool DIR = false, int TS = FT>
 __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &it, float *s_z, const float *qf,
-                                                 const Proj &pr, const int x0, const int y0, const float *sig = nullptr)
+                                                 const Proj &pr, const int x0, const int y0, const float *sig = nullptr,
+                                                 const float *q0v = nullptr)
 {
     constexpr int TX = TS, TY = TS, QS = TS + 6, FO = DIR ? TS + 2 : TS + 1;
     constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX, YB = 128;  // y faces start at thread YB
@@ -2010,7 +2020,7 @@ __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &i
         for (int v = 0; v < 3; v++) {
             float L = -(s_fx[v][cy][cx + 1] - s_fx[v][cy][cx]) * d.rdx - (s_fy[v][cy + 1][cx] - s_fy[v][cy][cx]) * d.rdy;
             float o = a1 * (qf[(v * QS + cy + 3) * QS + cx + 3] + dt * L);
-            if (a0 != 0.0f) o = a0 * q0[idx + v * plane] + o;
+            if (a0 != 0.0f) o = a0 * (q0v ? q0v[v] : q0[idx + v * plane]) + o;
             out[idx + v * plane] = o;
             qn[v] = o;
         }
@@ -2110,9 +2120,19 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_one_kernel(LSolve d, in
         const bool first = w == (int)blockIdx.x;
         if (!first) __syncthreads();  // the previous tile's LDS reads are done
         const int ty = w / tx_n, tx = w - ty * tx_n;
+        // stage 2 on small tiles (register room): the cell's q^n loaded now,
+        // its latency behind the network pass
+        constexpr bool PRE = STAGE == 2 && TS == 4 && !DIR;
+        float q0v[3] = {0.0f, 0.0f, 0.0f};
+        if (PRE && threadIdx.x < TS * TS) {
+            const int cy = threadIdx.x / TS, cx = threadIdx.x - cy * TS;
+            const size_t idx = (size_t)(ty * TS + cy) * d.nx + tx * TS + cx, plane = (size_t)d.nx * d.ny;
+#pragma unroll
+            for (int v = 0; v < 3; v++) q0v[v] = d.q[idx + v * plane];
+        }
         float *s_z = fused_tile<DIR ? TS + 2 : TS + 1, OUT_Z_LDS, 1, TS>(
             STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx, ty * TS, tx * TS, pr, first, s_qf, &rd);
-        learned_epilogue<STAGE, BL, DIR, TS>(d, it, s_z, s_qf, pr, tx * TS, ty * TS, sig);
+        learned_epilogue<STAGE, BL, DIR, TS>(d, it, s_z, s_qf, pr, tx * TS, ty * TS, sig, PRE ? q0v : nullptr);
         w += gridDim.x;
     } while (w < total);
     // no writer of the previous step's slot in stage 1
