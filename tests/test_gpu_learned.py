@@ -163,6 +163,34 @@ def test_learned_step_parity(fv, L, flux):
     assert stats == (0, 0) and ostats == (0, 0)
 
 
+@pytest.mark.parametrize("ny,nx", [(48, 80), (24, 48), (96, 64)])
+def test_learned_step_parity_rectangular(fv, L, ny, nx):
+    """Rectangular periodic grids (rows cut from a square state: both sides
+    wrap the same data): 48 x 80 and 24 x 48 run the single solve's 4 x 4
+    network tiles, 96 x 64 its 8 x 8 tiles (more 4 x 4 tiles than resident
+    workgroups).  Three learned steps against the oracle with dx = 1/nx and
+    dy = 1/ny, within the learned step's tolerance."""
+    p = oracle_params(L, 3, scale_last=0.05)
+    q0 = I.random_smooth_swe(max(nx, ny), seed=21)[:, :ny, :nx].astype(np.float32)
+    dt, nsteps = 4e-4, 3
+    m = gpu_model(fv, p)
+    s = fv.Solver(q0, prec=fv.FV_F32, dt_fixed=dt, learned=1)
+    print(f"[gpu] learned step {ny}x{nx} x{nsteps}", flush=True)
+    stats = s.learned_step(m, nsteps)
+    out = s.state()
+    s.close()
+    m.close()
+    qo = torch.tensor(q0.astype(np.float64))[None]
+    fb = 0
+    with torch.no_grad():
+        for _ in range(nsteps):
+            qo, st = L.learned_step(p, qo, dt, 1.0 / nx, 1.0 / ny)
+            fb += st["fallback_faces"]
+    print(f"[learned {ny}x{nx}] {rel_errors(out, qo[0].numpy())} stats gpu {stats} oracle fallback {fb}", flush=True)
+    assert state_rel(out, qo[0].numpy()) <= 3e-4
+    assert stats[1] == 0 and abs(stats[0] - fb) <= 0.01 * fb + 2
+
+
 def test_zero_network_is_fromm(fv, L, orc):
     """A zero last layer gives alpha_base (Fromm); parity with the oracle."""
     p = oracle_params(L, 4, scale_last=0.0)

@@ -108,6 +108,30 @@ def test_learned_step_parity(fv, E, flux):
     assert st[1].tolist() == ost[1].tolist()
 
 
+def test_learned_step_parity_rectangular(fv, E):
+    """A rectangular 48 x 80 solve (rows cut from an 80 x 80 state), whose
+    4 x 4 network tiles all get a workgroup: three learned steps against the
+    oracle with dx = 1/80 and dy = 1/48."""
+    p = oracle_params(E, 3, scale_last=0.05)
+    ny, nx, dt, nsteps = 48, 80, 3e-4, 3
+    q0 = np.stack([I.random_smooth_euler(nx, seed=13)[:, :ny, :]]).astype(np.float32)
+    net = fv.EulerLearned(fv.params_to_vector([w.numpy() for w in p["w"]], [b.numpy() for b in p["b"]]), 1, nx, ny,
+                          dt, mean=tuple(p["mean"].tolist()), inv_std=tuple(p["inv_std"].tolist()))
+    print(f"[gpu] learned Euler {ny}x{nx} x{nsteps}", flush=True)
+    q = torch.tensor(q0, device="cuda").contiguous()
+    net.step(q, nsteps)
+    fb, rd, fr, rc = net.stats()
+    out = q.cpu().double().numpy()
+    net.close()
+    qo = torch.tensor(q0.astype(np.float64))
+    with torch.no_grad():
+        for _ in range(nsteps):
+            qo, _ = E.learned_step(p, qo, dt, 1.0 / nx, 1.0 / ny)
+    print(f"[euler {ny}x{nx}] {rel_errors(out[0], qo[0].numpy())}", flush=True)
+    assert rc == fv.FV_OK and int(rd.sum()) == 0
+    assert state_rel(out[0], qo[0].numpy()) <= 3e-4
+
+
 def test_zero_head_is_fromm_and_conserves(fv, E):
     """A zero last layer (Fromm's stencils): parity over 20 steps on a
     ragged 48 x 20 grid, and FP64 sums of every conserved variable kept."""
