@@ -898,6 +898,26 @@ __device__ __forceinline__ void last_layer_by_tile(const bf16x8 *act, const bf16
     }
 }
 
+// All five layers' biases in LDS ([4][32] hidden, then the last layer's
+// NL4), so that no layer waits on a global load for them: one float per
+// thread, loaded with the weights and stored with them.
+template <int NL4, class PK> struct BiasChunk {
+    static_assert(4 * 32 + NL4 <= FNW * 64, "one bias per thread");
+    float v = 0.0f;
+    __device__ __forceinline__ void load(const char *P, const PK &pk)
+    {
+        const int t = threadIdx.x;
+        if (t < 4 * 32 + NL4) {
+            const size_t off = t < 32 ? pk.b[0] : t < 64 ? pk.b[1] : t < 96 ? pk.b[2] : t < 128 ? pk.b[3] : pk.b[4];
+            v = ((const float *)(P + off))[t < 128 ? (t & 31) : t - 128];
+        }
+    }
+    __device__ __forceinline__ void store(float *s) const
+    {
+        if (threadIdx.x < 4 * 32 + NL4) s[threadIdx.x] = v;
+    }
+};
+
 // N chunks of 16 bytes, global -> registers (load) and registers -> LDS
 // (store), FNW * 64 threads striding; split so that every load of the
 // workgroup's staging can be issued before its first LDS store.
@@ -1163,6 +1183,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     // all five layers' packed weights, staged together
     constexpr int W0 = 32 * 32 / 8, WH = 9 * 32 * 32 / 8, W4 = FW_EL / 8;
     __shared__ bf16x8 s_wall[W0 + 3 * WH + W4];
+    __shared__ float s_bias[4 * 32 + 80];  // layer l < 4 at 32 l, layer 4 at 128
 
     // the wave index as a scalar: MFMAs under a wave-dependent condition
     // must sit behind a real branch (an MFMA does not honour a partial EXEC)
@@ -1206,7 +1227,9 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     Chunks<W0> c0;
     Chunks<WH> c1, c2, c3;
     Chunks<W4> c4;
+    BiasChunk<80, Packed> cb;
     if (load_w) {
+        cb.load(P, pk);
         c0.load(P, pk.w[0]);
         c1.load(P, pk.w[1]);
         c2.load(P, pk.w[2]);
@@ -1229,12 +1252,15 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     }
     // layer 0's weights now; the others after layers 0 and 1, so that their
     // loads complete behind layer 0's arithmetic
-    if (load_w) c0.store(s_wall);
+    if (load_w) {
+        c0.store(s_wall);
+        cb.store(s_bias);
+    }
     __syncthreads();
 
     // layer 0 on the FR0_ x FR0_ region, 16 pixels per group
     {
-        const float *bias = (const float *)(P + pk.b[0]);
+        const float *bias = s_bias;
         const bf16x8 A0 = s_wall[wfrag(0, px, g)], A1 = s_wall[wfrag(1, px, g)];
         constexpr int NP0 = FR0_ * FR0_, NG0 = (NP0 + 15) / 16, KG = (NG0 + FNW - 1) / FNW;
         // all KG groups gi = wave + k FNW of this wave at once (a group past
@@ -1292,7 +1318,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
         const int rin = FR0_ - 2 * (l - 1);
         const bf16x8 *in = (l & 1) ? s_a0 : s_a1;
         bf16 *out = (bf16 *)((l & 1) ? s_a1 : s_a0);
-        fused_hidden<AS>(in, rin, out, s_wall + W0 + (l - 1) * WH, (const float *)(P + pk.b[l]), wave, lane);
+        fused_hidden<AS>(in, rin, out, s_wall + W0 + (l - 1) * WH, s_bias + 32 * l, wave, lane);
     }
     __syncthreads();
     // layer 4: s_a1 (FO + 2)^2 -> z on the FO x FO region: NG pixel groups x
@@ -1310,7 +1336,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
         floatx4 acc[NG4];
         last_layer_by_tile<NG4, 5, FO, AS>(s_a1, s_w, wave, g, px, acc);
         if (ALPHA) __syncthreads();  // every wave past its layer-4 reads of s_a1 before it holds z
-        const float *bias = (const float *)(P + pk.b[4]);
+        const float *bias = s_bias + 128;
         const int co0 = 16 * wave + 4 * g;
         if (wave < 5 && co0 < 72) {
 #pragma unroll
@@ -1334,7 +1360,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
         // activation fragment read once per tap for NT MFMAs; each co tile's
         // chain keeps the tap order 0..8
         constexpr int NT = 5, RIN = FO + 2, NPX = FO * FO, NG = (NPX + 15) / 16, GPW = (NG + FNW - 1) / FNW;
-        const float *bias = (const float *)(P + pk.b[4]);
+        const float *bias = s_bias + 128;
         floatx4 acc[GPW][NT];
 #pragma unroll
         for (int k = 0; k < GPW; k++)
@@ -1527,6 +1553,7 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
     constexpr int AS = (ZLDS && FO == FT + 1) ? 4 : 5;
     __shared__ bf16x8 s_act[FR0_ * FR0_ * AS + (FR0_ - 2) * (FR0_ - 2) * AS];
     __shared__ bf16x8 s_wall[EW0 + 3 * EWH + EW4];
+    __shared__ float s_bias[4 * 32 + E_COUT];  // layer l < 4 at 32 l, layer 4 at 128
     bf16x8 *const s_a0 = s_act;
     bf16x8 *const s_a1 = s_act + FR0_ * FR0_ * AS;
     const int lane = threadIdx.x & 63, wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -1565,7 +1592,9 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
     Chunks<EW0> c0;
     Chunks<EWH> c1, c2, c3;
     Chunks<EW4> c4;
+    BiasChunk<E_COUT, EPacked> cb;
     if (load_w) {
+        cb.load(P, pk);
         c0.load(P, pk.w[0]);
         c1.load(P, pk.w[1]);
         c2.load(P, pk.w[2]);
@@ -1587,6 +1616,7 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
         }
     }
     if (load_w) {
+        cb.store(s_bias);
         c0.store<false>(s_wall);  // layer 0 reads its two K blocks in the packed order
         c1.store(s_wall + EW0);
         c2.store(s_wall + EW0 + EWH);
@@ -1596,7 +1626,7 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
     __syncthreads();
     // layer 0 on the FR0_ x FR0_ region: K = 36 (tap*4 + ci) in two blocks
     {
-        const float *bias = (const float *)(P + pk.b[0]);
+        const float *bias = s_bias;
         constexpr int NP0 = FR0_ * FR0_, NG0 = (NP0 + 15) / 16;
         for (int gi = wave; gi < NG0; gi += FNW) {
             const int p = gi * 16 + px;
@@ -1639,7 +1669,7 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
         const int rin = FR0_ - 2 * (l - 1);
         const bf16x8 *in = (l & 1) ? s_a0 : s_a1;
         bf16 *out = (bf16 *)((l & 1) ? s_a1 : s_a0);
-        fused_hidden<AS>(in, rin, out, s_wall + EW0 + (l - 1) * EWH, (const float *)(P + pk.b[l]), wave, lane);
+        fused_hidden<AS>(in, rin, out, s_wall + EW0 + (l - 1) * EWH, s_bias + 32 * l, wave, lane);
     }
     __syncthreads();
     // layer 4: s_a1 (FO + 2)^2 -> z on the FO x FO region, pixel groups wave,
@@ -1654,7 +1684,7 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
         floatx4 acc[NG4];
         last_layer_by_tile<NG4, 6, FO, AS>(s_a1, s_wall + EW0 + 3 * EWH, wave, g, px, acc);
         if (ZLDS) __syncthreads();
-        const float *bias = (const float *)(P + pk.b[4]);
+        const float *bias = s_bias + 128;
         const int co0 = 16 * wave + 4 * g;
         if (wave < 6) {
 #pragma unroll
@@ -1676,7 +1706,7 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
     } else {
         constexpr int NT = 6, RIN = FO + 2, NPX = FO * FO, NG = (NPX + 15) / 16, GPW = (NG + FNW - 1) / FNW;
         const bf16x8 *s_w = s_wall + EW0 + 3 * EWH;
-        const float *bias = (const float *)(P + pk.b[4]);
+        const float *bias = s_bias + 128;
         floatx4 acc[GPW][NT];
 #pragma unroll
         for (int k = 0; k < GPW; k++) {
@@ -1931,11 +1961,12 @@ hipError_t launch_learned_euler(int flux, const void *packed, const ENorm &nrm, 
 // output on the tile and a one-cell ring ([(FT+2)^2][72] from (x0 - 1,
 // y0 - 1)); each face takes its owner's high-side and its neighbour's
 // low-side states (sig = 1 / inv_std of the network input).
+// dt: the solve's step (*d.dt, read by the caller before the network pass);
 // q0v (STAGE 2, or NULL): the cell's q^n values, loaded by the caller.
 template <int STAGE, bool BL = false, bool DIR = false, int TS = FT>
 __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &it, float *s_z, const float *qf,
-                                                 const Proj &pr, const int x0, const int y0, const float *sig = nullptr,
-                                                 const float *q0v = nullptr)
+                                                 const Proj &pr, const int x0, const int y0, const float dt,
+                                                 const float *sig = nullptr, const float *q0v = nullptr)
 {
     constexpr int TX = TS, TY = TS, QS = TS + 6, FO = DIR ? TS + 2 : TS + 1;
     constexpr int NFX = TY * (TX + 1), NFY = (TY + 1) * TX, YB = 128;  // y faces start at thread YB
@@ -1954,7 +1985,6 @@ __device__ __forceinline__ void learned_epilogue(const LSolve &d, const LItem &i
     ph.sqg = d.sqg;
     ph.gamma = 1.4f;
     ph.h0 = d.h0;
-    const float dt = d.dt[0];
     // stage 2 of a solve whose stage 1 failed is evaluated (its result is
     // discarded by the redo) but its fallback faces are not counted
     const bool count = !(STAGE == 2 && (*bad & 1));
@@ -2071,9 +2101,10 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_batch_kernel(const LSol
         const LSolve &d = tab[it.solve];
         const int tile = w - it.tb_cnn, tx_n = d.nx / FT;
         const int ty = tile / tx_n, tx = tile - ty * tx_n;
-        float *s_z = fused_tile<FT + 1, OUT_Z_LDS>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx,
-                                                             ty * FT, tx * FT, pr, first, s_qf);
-        learned_epilogue<STAGE, BL>(d, it, s_z, s_qf, pr, tx * FT, ty * FT);
+        const float dt = d.dt[0];  // its latency behind the network pass
+        float *s_z = fused_tile<FT + 1, OUT_Z_LDS>(STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx, ty * FT,
+                                                   tx * FT, pr, first, s_qf);
+        learned_epilogue<STAGE, BL>(d, it, s_z, s_qf, pr, tx * FT, ty * FT, dt);
     }
 }
 
@@ -2113,6 +2144,7 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_one_kernel(LSolve d, in
         rd.ph.h0 = d.h0;
         rd.fatal = d.fatal;
     }
+    const float dt0 = d.dt[0];  // read now, its latency behind the network pass
     // the grid never exceeds the tile count: every workgroup has a first
     // tile, whose loads need not wait for the loop test
     int w = blockIdx.x;
@@ -2132,7 +2164,7 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_one_kernel(LSolve d, in
         }
         float *s_z = fused_tile<DIR ? TS + 2 : TS + 1, OUT_Z_LDS, 1, TS>(
             STAGE == 1 ? d.q : d.s1, P, pk, nrm, nullptr, d.ny, d.nx, ty * TS, tx * TS, pr, first, s_qf, &rd);
-        learned_epilogue<STAGE, BL, DIR, TS>(d, it, s_z, s_qf, pr, tx * TS, ty * TS, sig, PRE ? q0v : nullptr);
+        learned_epilogue<STAGE, BL, DIR, TS>(d, it, s_z, s_qf, pr, tx * TS, ty * TS, dt0, sig, PRE ? q0v : nullptr);
         w += gridDim.x;
     } while (w < total);
     // no writer of the previous step's slot in stage 1
