@@ -1790,13 +1790,16 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
     bool staged = false;  // this workgroup's weights are in LDS
     for (int tile = blockIdx.x; tile < total; tile += gridDim.x) {
         const int b = tile / (tx_n * ty_n);
-        if (a.fatal[b]) continue;  // frozen solve (wave-uniform)
+        // stage 1 with xprev: a solve whose previous step is flagged is redone
+        // on this workgroup's region first (no writer of that slot in stage
+        // 1); both flags read together, one wait
+        const int fz = a.fatal[b];
+        const int rf = a.flagbit == 1 && xprev ? a.flags[2 * b + (a.parity ^ 1)] : 0;
+        if (fz) continue;  // frozen solve (wave-uniform)
         if (staged) __syncthreads();  // the previous tile's LDS reads are done
         const int rt = tile - b * tx_n * ty_n;
         const int y0 = (rt / tx_n) * TS, x0 = (rt % tx_n) * TS;
-        // stage 1 with xprev: a solve whose previous step is flagged is redone
-        // on this workgroup's region first (no writer of that slot in stage 1)
-        const bool redo = a.flagbit == 1 && xprev && a.flags[2 * b + (a.parity ^ 1)] != 0;
+        const bool redo = rf != 0;
         // stage 2 (a0 != 0): the cell's q^n loaded now, its latency behind the network pass
         float q0v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (a.a0 != 0.0f && tid < TX * TY) {

@@ -254,6 +254,39 @@ def test_redo_inside_a_call_bitwise(fv, E, n):
         assert np.array_equal(res[0][0], res[1][0]) and res[0][1:] == res[1][1:]
 
 
+@pytest.mark.parametrize("n", [32, 64])
+def test_frozen_solve_leaves_the_batch_unchanged(fv, E, n):
+    """A solve whose state is inadmissible from the start (negative pressure
+    in a band) fails its plain redo and is frozen; the other solve of the
+    batch runs on, bit-identical to the same solve alone, in the two-launch
+    form whose workgroups skip a frozen solve's tiles (4 x 4 network tiles at
+    32^2, 8 x 8 at 64^2)."""
+    p = E.init_params(2, scale_last=0.05)
+    bad = I.random_smooth_euler(n, seed=6)
+    kin = 0.5 * (bad[1] ** 2 + bad[2] ** 2) / bad[0]
+    bad[3, n // 4:n // 2, :] = kin[n // 4:n // 2, :] - 0.05  # p < 0 in a band of rows
+    good = I.random_smooth_euler(n, seed=7)
+    q0 = np.stack([bad, good]).astype(np.float32)
+    dt, steps = 5e-4 * 32 / n, 4
+    net = gpu_net(fv, p, 2, n, dt)
+    q = torch.tensor(q0, device="cuda").contiguous()
+    net.step(q, steps)
+    fb, rd, fr, rc = net.stats()
+    both = q.cpu().numpy()
+    net.close()
+    one = gpu_net(fv, p, 1, n, dt)
+    q1 = torch.tensor(q0[1:2], device="cuda").contiguous()
+    one.step(q1, steps)
+    fb1, rd1, fr1, rc1 = one.stats()
+    alone = q1.cpu().numpy()
+    one.close()
+    print(f"[euler frozen {n}^2] frozen {fr.tolist()} rc {rc}, redone {rd.tolist()}, fallback {fb.tolist()}; "
+          f"alone frozen {fr1.tolist()} rc {rc1}", flush=True)
+    assert fr.tolist() == [1, 0] and rc == fv.FV_E_INADMISSIBLE
+    assert fr1.tolist() == [0] and rc1 == fv.FV_OK
+    assert np.array_equal(both[1], alone[0]) and (fb[1], rd[1]) == (fb1[0], rd1[0])
+
+
 def test_invalid_configurations_rejected(fv):
     vec = np.zeros(fv.lib.fv_euler_net_param_count(), dtype=np.float32)
     for kw in (dict(nx=40), dict(flux=fv.FV_FLUX_ROE), dict(dt=0.0)):
