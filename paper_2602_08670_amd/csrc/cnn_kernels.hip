@@ -1197,6 +1197,9 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     // the first LDS store.  qf (OUT_Z_LDS): the FP32 values of the
     // (TS + 6)^2 cells from (x0 - 3, y0 - 3), kept for the learned stage.
     constexpr int NIN = 3 * FRI_ * FRI_, TIN = (NIN + FNW * 64 - 1) / (FNW * 64);
+    // the redo flag's load first: the decision below then waits for it alone,
+    // not for the input's loads, and the weights' loads follow at once
+    const int rflag = OUT == OUT_Z_LDS && rd && rd->xprev ? *rd->flag : 0;
     float xin[TIN];
 #pragma unroll
     for (int k = 0; k < TIN; k++) {
@@ -1212,7 +1215,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
         // the redo decision after the loads have been issued (their values
         // are discarded on a redo); the activations' LDS is free until layer
         // 0's first store, which follows the staging barrier below
-        if (rd && rd->xprev && *rd->flag) {
+        if (rflag) {
             static_assert(3 * ((FRI_ + 8) * (FRI_ + 8) + (FRI_ + 4) * (FRI_ + 4) + FRI_ * FRI_) * 4 <= sizeof(s_act),
                           "the redo's three fields fit over the activations");
             const float *sr = redo_region<FRI_, TS>(rd->xprev, rd->xk, rd->dt, rd->rdx, rd->rdy, rd->ph.g, rd->ph.sqg,
