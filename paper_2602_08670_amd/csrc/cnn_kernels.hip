@@ -1901,16 +1901,22 @@ int fused_euler_grid()
     if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
     if (!cache[dev]) {
         int cus = 0, m = 0;
-        int m1 = 0, m2 = 0;
+        int m1 = 0, m2 = 0, m3 = 0, m4 = 0;
         if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&m, conv_fused_euler_kernel, FNW * 64, 0) != hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&m1, conv_learned_euler_kernel<fvk::HLLE>, FNW * 64, 0) !=
                 hipSuccess ||
             hipOccupancyMaxActiveBlocksPerMultiprocessor(&m2, conv_learned_euler_kernel<fvk::RUSANOV>, FNW * 64, 0) !=
+                hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&m3, conv_learned_euler_kernel<fvk::HLLE, 4>, FNW * 64, 0) !=
+                hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&m4, conv_learned_euler_kernel<fvk::RUSANOV, 4>, FNW * 64, 0) !=
                 hipSuccess)
             return 256;
         m = m < m1 ? m : m1;
         m = m < m2 ? m : m2;
+        m = m < m3 ? m : m3;
+        m = m < m4 ? m : m4;
         cache[dev] = (m > 0 ? m : 1) * (cus > 0 ? cus : 256);
     }
     return cache[dev];
@@ -2226,6 +2232,22 @@ int fused_max_grid()
             return 256;
         k4 = k4 < k5 ? k4 : k5;
         k4 = k4 < k6 ? k4 : k6;
+        // the single solve's 4 x 4 network tiles (launched with the same cap)
+        int t[6] = {0, 0, 0, 0, 0, 0};
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&t[0], conv_learned_one_kernel<1, false, false, 4>, FNW * 64,
+                                                         0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&t[1], conv_learned_one_kernel<2, false, false, 4>, FNW * 64,
+                                                         0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&t[2], conv_learned_one_kernel<1, true, false, 4>, FNW * 64,
+                                                         0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&t[3], conv_learned_one_kernel<2, true, false, 4>, FNW * 64,
+                                                         0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&t[4], conv_learned_one_kernel<1, false, true, 4>, FNW * 64,
+                                                         0) != hipSuccess ||
+            hipOccupancyMaxActiveBlocksPerMultiprocessor(&t[5], conv_learned_one_kernel<2, false, true, 4>, FNW * 64,
+                                                         0) != hipSuccess)
+            return 256;
+        for (int i = 0; i < 6; i++) k4 = k4 < t[i] ? k4 : t[i];
         int m = a < b ? a : b;
         m = m < k1 ? m : k1;
         m = m < k2 ? m : k2;
