@@ -1795,14 +1795,15 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
         const int b = tile / (tx_n * ty_n);
         // stage 1 with xprev: a solve whose previous step is flagged is redone
         // on this workgroup's region first (no writer of that slot in stage
-        // 1); both flags read together, one wait
+        // 1).  A frozen solve's tiles run the pass but write nothing (live
+        // false), so that neither flag is waited for before the input's
+        // loads are issued (an early exit makes the compiler wait for them)
         const int fz = a.fatal[b];
         const int rf = a.flagbit == 1 && xprev ? a.flags[2 * b + (a.parity ^ 1)] : 0;
-        if (fz) continue;  // frozen solve (wave-uniform)
         if (staged) __syncthreads();  // the previous tile's LDS reads are done
         const int rt = tile - b * tx_n * ty_n;
         const int y0 = (rt / tx_n) * TS, x0 = (rt % tx_n) * TS;
-        const bool redo = rf != 0;
+        const bool live = fz == 0, redo = rf != 0 && live;
         // stage 2 (a0 != 0): the cell's q^n loaded now, its latency behind the network pass
         float q0v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
         if (a.a0 != 0.0f && tid < TX * TY) {
@@ -1866,7 +1867,7 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
         }
         __syncthreads();
         bool bad = false;
-        if (tid < TX * TY) {
+        if (live && tid < TX * TY) {
             const int cy = tid / TX, cx = tid - cy * TX;
             const size_t idx = (size_t)b * 4 * plane + (size_t)(y0 + cy) * nx + x0 + cx;
             float qn[4];
@@ -1881,10 +1882,10 @@ __global__ __launch_bounds__(FNW * 64) void conv_learned_euler_kernel(eln::Stage
             }
             bad = !eln::admissible(qn, a.gamma);
         }
-        if (count && nfb) atomicAdd(&s_cnt, nfb);
+        if (live && count && nfb) atomicAdd(&s_cnt, nfb);
         if (bad) s_bad = 1;
         __syncthreads();
-        if (tid == 0) {
+        if (live && tid == 0) {
             if (s_cnt) atomicAdd(&a.nfb[b], (unsigned long long)s_cnt);
             if (s_bad) atomicOr(flag, a.flagbit);
             // stage 2: every reader of the previous step's slot has finished
