@@ -789,7 +789,6 @@ constexpr int FNW = 8;  // waves per workgroup of the fused pass
 // q * AS + g; AS = 5 octets per pixel (an odd stride: 16 consecutive pixels
 // fall in 16 different bank groups, and a tap's shift stays a constant
 // offset), AS = 4 (unpadded) where LDS has no room for the padding.
-__device__ __forceinline__ unsigned wfrag_slot(unsigned i) { return (i & ~63u) | ((i & 3u) << 4) | ((i >> 2) & 15u); }
 __device__ __forceinline__ int wfrag(int f, int row, int g) { return (f * 4 + g) * 16 + row; }
 template <int AS> __device__ __forceinline__ int act_slot(int q, int g) { return q * AS + g; }
 // bf16 offset of channels co0 .. co0 + 3 (co0 % 4 == 0) of pixel q
@@ -898,6 +897,30 @@ __device__ __forceinline__ void last_layer_by_tile(const bf16x8 *act, const bf16
     }
 }
 
+// A layer's packed weights (NB blocks of 64 octets) straight from global
+// memory into LDS, one global_load_lds_dwordx4 per 1 KB block, blocks
+// wave, wave + FNW, ...: lane l of a block writes the block's octet l; with
+// PERM that is octet (l & 15, l >> 4) of the packed row-major fragment
+// (the K-block-major order wfrag reads), else octet l.  These writes are
+// not tracked by the compiler's waits: barrier_after_weights() waits for
+// them before any LDS read.
+template <int NB, bool PERM = true>
+__device__ __forceinline__ void dma_weights(const char *g, bf16x8 *s, int wave, int lane)
+{
+    for (int b = wave; b < NB; b += FNW) {  // wave-uniform
+        const unsigned i = PERM ? ((unsigned)b * 64 | (unsigned)(lane & 15) << 2 | (unsigned)(lane >> 4))
+                                : (unsigned)b * 64 + lane;
+        __builtin_amdgcn_global_load_lds((const void *)(g + (size_t)i * 16), (void *)(s + b * 64), 16, 0, 0);
+    }
+}
+
+// Workgroup barrier after every global load of this wave (the weights'
+// loads into LDS included) and its LDS accesses are done.
+__device__ __forceinline__ void barrier_after_weights()
+{
+    __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // All five layers' biases in LDS ([4][32] hidden, then the last layer's
 // NL4), so that no layer waits on a global load for them: one float per
 // thread, loaded with the weights and stored with them.
@@ -915,37 +938,6 @@ template <int NL4, class PK> struct BiasChunk {
     __device__ __forceinline__ void store(float *s) const
     {
         if (threadIdx.x < 4 * 32 + NL4) s[threadIdx.x] = v;
-    }
-};
-
-// N chunks of 16 bytes, global -> registers (load) and registers -> LDS
-// (store), FNW * 64 threads striding; split so that every load of the
-// workgroup's staging can be issued before its first LDS store.
-template <int N> struct Chunks {
-    static constexpr int T = FNW * 64, IT = (N + T - 1) / T;
-    bf16x8 v[IT];
-    __device__ __forceinline__ void load(const char *P, size_t off)
-    {
-        const bf16x8 *g = (const bf16x8 *)(P + off);
-#pragma unroll
-        for (int k = 0; k < IT; k++) {
-            // an unsigned 32-bit index: the loads take the uniform base
-            // address plus a 32-bit per-lane offset, not a 64-bit address
-            // per load in registers
-            const unsigned i = threadIdx.x + k * T;
-            if (i < (unsigned)N) v[k] = g[i];
-        }
-    }
-    // PERM: each 64-octet fragment K-block-major (wfrag_slot; T is a
-    // multiple of 64, so octet i + k T goes to wfrag_slot(i) + k T)
-    template <bool PERM = true> __device__ __forceinline__ void store(bf16x8 *s) const
-    {
-        static_assert(T % 64 == 0, "whole fragments per stride");
-        const unsigned b = PERM ? wfrag_slot(threadIdx.x) : threadIdx.x;
-#pragma unroll
-        for (int k = 0; k < IT; k++) {
-            if (threadIdx.x + k * T < (unsigned)N) s[b + k * T] = v[k];
-        }
     }
 };
 
@@ -1227,17 +1219,16 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
             }
         }
     }
-    Chunks<W0> c0;
-    Chunks<WH> c1, c2, c3;
-    Chunks<W4> c4;
+    // all five layers' weights straight into LDS, waited for at the
+    // staging barrier (the waves issue no LDS writes for them)
     BiasChunk<80, Packed> cb;
     if (load_w) {
         cb.load(P, pk);
-        c0.load(P, pk.w[0]);
-        c1.load(P, pk.w[1]);
-        c2.load(P, pk.w[2]);
-        c3.load(P, pk.w[3]);
-        c4.load(P, pk.w[4]);
+        dma_weights<W0 / 64>(P + pk.w[0], s_wall, wave, lane);
+        dma_weights<WH / 64>(P + pk.w[1], s_wall + W0, wave, lane);
+        dma_weights<WH / 64>(P + pk.w[2], s_wall + W0 + WH, wave, lane);
+        dma_weights<WH / 64>(P + pk.w[3], s_wall + W0 + 2 * WH, wave, lane);
+        dma_weights<W4 / 64>(P + pk.w[4], s_wall + W0 + 3 * WH, wave, lane);
     }
 #pragma unroll
     for (int k = 0; k < TIN; k++) {
@@ -1253,13 +1244,8 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
             }
         }
     }
-    // layer 0's weights now; the others after layers 0 and 1, so that their
-    // loads complete behind layer 0's arithmetic
-    if (load_w) {
-        c0.store(s_wall);
-        cb.store(s_bias);
-    }
-    __syncthreads();
+    if (load_w) cb.store(s_bias);
+    barrier_after_weights();
 
     // layer 0 on the FR0_ x FR0_ region, 16 pixels per group
     {
@@ -1309,15 +1295,7 @@ __device__ __forceinline__ float *fused_tile(const float *qb, const char *P, con
     // hidden layers 1..3: s_a0 -> s_a1 -> s_a0 -> s_a1
 #pragma unroll
     for (int l = 1; l < 4; l++) {
-        if (load_w && l == 1) {
-            c1.store(s_wall + W0);
-            c2.store(s_wall + W0 + WH);
-        }
-        if (load_w && l == 2) {
-            c3.store(s_wall + W0 + 2 * WH);
-            c4.store(s_wall + W0 + 3 * WH);
-        }
-        __syncthreads();  // previous layer's output (and this layer's weights) written
+        __syncthreads();  // previous layer's output written
         const int rin = FR0_ - 2 * (l - 1);
         const bf16x8 *in = (l & 1) ? s_a0 : s_a1;
         bf16 *out = (bf16 *)((l & 1) ? s_a1 : s_a0);
@@ -1592,17 +1570,16 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
             }
         }
     }
-    Chunks<EW0> c0;
-    Chunks<EWH> c1, c2, c3;
-    Chunks<EW4> c4;
+    // all five layers' weights straight into LDS (layer 0's in the packed
+    // order: it reads its two K blocks so), waited for at the staging barrier
     BiasChunk<E_COUT, EPacked> cb;
     if (load_w) {
         cb.load(P, pk);
-        c0.load(P, pk.w[0]);
-        c1.load(P, pk.w[1]);
-        c2.load(P, pk.w[2]);
-        c3.load(P, pk.w[3]);
-        c4.load(P, pk.w[4]);
+        dma_weights<EW0 / 64, false>(P + pk.w[0], s_wall, wave, lane);
+        dma_weights<EWH / 64>(P + pk.w[1], s_wall + EW0, wave, lane);
+        dma_weights<EWH / 64>(P + pk.w[2], s_wall + EW0 + EWH, wave, lane);
+        dma_weights<EWH / 64>(P + pk.w[3], s_wall + EW0 + 2 * EWH, wave, lane);
+        dma_weights<EW4 / 64>(P + pk.w[4], s_wall + EW0 + 3 * EWH, wave, lane);
     }
 #pragma unroll
     for (int k = 0; k < TIN; k++) {
@@ -1618,15 +1595,8 @@ __device__ __forceinline__ float *fused_tile_euler(const float *qb, const char *
             }
         }
     }
-    if (load_w) {
-        cb.store(s_bias);
-        c0.store<false>(s_wall);  // layer 0 reads its two K blocks in the packed order
-        c1.store(s_wall + EW0);
-        c2.store(s_wall + EW0 + EWH);
-        c3.store(s_wall + EW0 + 2 * EWH);
-        c4.store(s_wall + EW0 + 3 * EWH);
-    }
-    __syncthreads();
+    if (load_w) cb.store(s_bias);
+    barrier_after_weights();
     // layer 0 on the FR0_ x FR0_ region: K = 36 (tap*4 + ci) in two blocks
     {
         const float *bias = s_bias;
