@@ -142,6 +142,14 @@ hipError_t launch_pack(const float *master, void *packed, hipStream_t st)
 // ----------------------------------------------------------------- forward
 __device__ __forceinline__ int wrap(int i, int n) { return i < 0 ? i + n : (i >= n ? i - n : i); }
 
+// Workgroup barrier after every global load of this wave (loads straight
+// into LDS, global_load_lds, included: the compiler's waits do not track
+// those) and its LDS accesses are done.
+__device__ __forceinline__ void barrier_after_weights()
+{
+    __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
+}
+
 // Constrained coefficients of one group of six (side 0: left state, 1: right
 // state), in place: alpha_k = base_k + sum_j P[k][j] z_j.
 __device__ __forceinline__ void alpha_group(float *zz, int side, const Proj &pr)
@@ -274,19 +282,29 @@ __device__ __forceinline__ void halo_conv(const bf16 *src, const bf16 *wp, int H
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int g = lane >> 4, px = lane & 15;
     {
+        // the weights and the halo straight from global memory into LDS
+        // (global_load_lds_dwordx4: a wave's 64 lanes fill one 1 KB block,
+        // lane l its octet l), waited for at the barrier below
+        static_assert(WEL / 8 % 64 == 0, "whole weight blocks");
+        const int wv = __builtin_amdgcn_readfirstlane(wave);
         const bf16x8 *gw = (const bf16x8 *)wp;
-        for (int i = tid; i < WEL / 8; i += 256) s_w[i] = gw[i];
-        for (int i = tid; i < HP * OCT; i += 256) {
-            const int hp = i / OCT, o = i - hp * OCT;
+        for (int b = wv; b < WEL / 512; b += 4)  // wave-uniform
+            __builtin_amdgcn_global_load_lds((const void *)(gw + b * 64 + lane), (void *)(s_w + b * 64), 16, 0, 0);
+        for (int b = wv; b * 64 < HP * OCT; b += 4) {
+            // LDS octet j of the halo holds pixel hp's octet o, o the
+            // swizzled position (an involution)
+            const int j = b * 64 + lane, hp = j / OCT, pos = j - hp * OCT;
             const int hr = hp / (HT + 2), hc = hp - hr * (HT + 2);
             int yy = y0 - 1 + hr;
             yy = yy < 0 ? yy + H : yy % H;
             const int xx = wrap(x0 - 1 + hc, W);
-            const int pos = (o & ~3) | ((o & 3) ^ ((hc >> 2) & 3));
-            s_a[hp * OCT + pos] = *(const bf16x8 *)(src + ((size_t)yy * W + xx) * CG + o * 8);
+            const int o = (pos & ~3) | ((pos & 3) ^ ((hc >> 2) & 3));
+            if (j < HP * OCT)
+                __builtin_amdgcn_global_load_lds((const void *)(src + ((size_t)yy * W + xx) * CG + o * 8),
+                                                 (void *)(s_a + b * 64), 16, 0, 0);
         }
     }
-    __syncthreads();
+    barrier_after_weights();
     static_assert(TR == 4 * R, "tile rows");
 #pragma unroll
     for (int r = 0; r < R; r++)
@@ -912,13 +930,6 @@ __device__ __forceinline__ void dma_weights(const char *g, bf16x8 *s, int wave, 
                                 : (unsigned)b * 64 + lane;
         __builtin_amdgcn_global_load_lds((const void *)(g + (size_t)i * 16), (void *)(s + b * 64), 16, 0, 0);
     }
-}
-
-// Workgroup barrier after every global load of this wave (the weights'
-// loads into LDS included) and its LDS accesses are done.
-__device__ __forceinline__ void barrier_after_weights()
-{
-    __asm__ volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory");
 }
 
 // All five layers' biases in LDS ([4][32] hidden, then the last layer's
